@@ -1,0 +1,171 @@
+/*
+ * strokex -- GPU stroke expansion for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the library that turns stroked vector paths (lines, quadratic and
+ * cubic Beziers with SVG joins and caps) into strongly correct outlines made
+ * of line or circular-arc segments, following Levien & Uguray, "GPU-friendly
+ * Stroke Expansion" (arXiv:2405.00127):
+ *   - path encoding: tag stream + overlapping point stream, one stroke cap
+ *     marker per subpath (Section 8.2, Table 1);
+ *   - tag-monoid prefix scan giving each segment its path, style, transform
+ *     and point offset (Section 8.2);
+ *   - per segment, cubic -> Euler spiral subdivision driven by the error
+ *     estimate of Section 7.1 (Algorithm 2), parallel curves flattened to lines
+ *     with the density integral of Section 4 or to arcs with the metric of
+ *     Section 5, evolutes for strong correctness (Section 6);
+ *   - joins and caps from each segment's neighbour (Algorithm 1).
+ *
+ * All pointers are plain host or device pointers as stated per argument; no
+ * framework types cross this boundary.  Calls are ordered on the given HIP
+ * stream (hipStream_t passed as void*; NULL = the null stream).  A context is
+ * not thread-safe: use one per host thread.
+ *
+ * Every entry point returns an sx_status.  On failure sx_last_error(ctx)
+ * describes it; the context stays usable.
+ */
+#ifndef STROKEX_H
+#define STROKEX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SX_OK = 0,
+    SX_EINVAL = -1,    /* invalid argument or input geometry */
+    SX_ENOMEM = -2,    /* device or host allocation failed */
+    SX_EDEVICE = -3,   /* a HIP call failed */
+    SX_ETOOSMALL = -4, /* output buffer too small; required count reported */
+    SX_EBUSY = -5
+} sx_status;
+
+/* Path verbs (SVG moveto / lineto / quadto / curveto / closepath, Section 8.1). */
+enum { SX_MOVE = 0, SX_LINE = 1, SX_QUAD = 2, SX_CUBIC = 3, SX_CLOSE = 4 };
+/* Join and cap styles (SVG, criteria list of Section 8). */
+enum { SX_JOIN_BEVEL = 0, SX_JOIN_MITER = 1, SX_JOIN_ROUND = 2 };
+enum { SX_CAP_BUTT = 0, SX_CAP_SQUARE = 1, SX_CAP_ROUND = 2 };
+/* Output primitive (Section 8.1: line soup, or arcs storing curvature). */
+enum { SX_OUT_LINES = 0, SX_OUT_ARCS = 1 };
+
+/* Stroke style, one per path (Section 8.2: style stream).  half_width >= 0
+ * in the path's local units (scaled by sqrt|det| of the transform);
+ * miter_limit >= 1 (SVG ratio of miter length to stroke width). 12 bytes. */
+typedef struct {
+    float half_width;
+    float miter_limit;
+    uint8_t join, start_cap, end_cap, flags; /* flags: reserved, must be 0 */
+} sx_style;
+
+/* Affine transform, one per path (Section 8.2: transform stream):
+ * x' = a x + c y + e,  y' = b x + d y + f.  Strokes need a similarity
+ * (rotation or reflection with uniform scale): a == d && b == -c, or
+ * a == -d && b == c, exactly. */
+typedef struct {
+    float a, b, c, d, e, f;
+} sx_affine;
+
+/* Input paths, all host memory, owned by the caller and read only during
+ * sx_scene_encode.  Path k owns verbs[verb_off[k] .. verb_off[k+1]) and points
+ * pts[2*pt_off[k] .. 2*pt_off[k+1]) (x, y pairs); every path starts with
+ * SX_MOVE.  MOVE / LINE take 1 point, QUAD 2, CUBIC 3, CLOSE none. */
+typedef struct {
+    const uint8_t *verbs;
+    const uint32_t *verb_off; /* n_paths + 1 */
+    const float *pts;
+    const uint32_t *pt_off;   /* n_paths + 1 */
+    const uint32_t *style_ix; /* n_paths, index into the style table */
+    const uint32_t *xform_ix; /* n_paths, index into the transform table */
+    uint32_t n_paths;
+} sx_paths;
+
+/* Output records (Section 8.1).  path_ix is the input path index.
+ * Arcs: signed curvature of the circular arc from (x0,y0) to (x1,y1),
+ * positive when it turns counter-clockwise (y up); 0 for a straight line. */
+typedef struct {
+    float x0, y0, x1, y1;
+    uint32_t path_ix;
+} sx_line; /* 20 bytes */
+
+typedef struct {
+    float x0, y0, x1, y1, curvature;
+    uint32_t path_ix;
+} sx_arc; /* 24 bytes */
+
+typedef struct sx_ctx sx_ctx;
+typedef struct sx_scene sx_scene;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int sx_ctx_create(int device, sx_ctx **out);
+/* Destroy a context and every scene it still owns.  NULL is a no-op. */
+int sx_ctx_destroy(sx_ctx *ctx);
+/* Text of the last error on this context (never NULL; "" when none). */
+const char *sx_last_error(const sx_ctx *ctx);
+/* Library version string. */
+const char *sx_version(void);
+
+/* Encode paths into a device-resident scene (Section 8.2): tags, the
+ * overlapping point stream, style / transform streams and the encoded-path to
+ * input-path map; closing lines are inserted for closed subpaths whose end
+ * differs from their start, one stroke cap marker is appended per subpath,
+ * zero-length segments and empty subpaths are dropped.  The upload is
+ * ordered on `stream`; the host inputs may be reused when this returns.
+ * Errors: SX_EINVAL (path not starting with MOVE, unknown verb, point count
+ * mismatch, non-finite coordinate, style or transform index out of range,
+ * half_width < 0, miter_limit < 1, non-similarity transform),
+ * SX_ENOMEM, SX_EDEVICE.  The scene is owned by ctx. */
+int sx_scene_encode(sx_ctx *ctx, const sx_paths *paths, const sx_style *styles, uint32_t n_styles,
+                    const sx_affine *xforms, uint32_t n_xforms, void *stream, sx_scene **out);
+/* Release a scene (waits for work queued on the scene's last stream). */
+int sx_scene_release(sx_ctx *ctx, sx_scene *scene);
+/* Sizes of an encoded scene (any pointer may be NULL). */
+int sx_scene_info(const sx_scene *scene, uint32_t *n_tags, uint32_t *n_pts, uint32_t *n_paths,
+                  uint32_t *n_styles, uint32_t *n_xforms);
+/* Copy the encoded streams back to host memory (for verification):
+ * tags n_tags bytes, data 2*n_pts floats, path_map n_paths u32.  NULL skips.
+ * Synchronous. */
+int sx_scene_download(const sx_scene *scene, uint8_t *tags, float *data, uint32_t *path_map);
+
+/* Expand a scene: tag-monoid scan, per-segment output counts, exclusive scan
+ * of the counts (output offsets), emission of the outline in canonical order
+ * (by tag; within a tag: Euler spiral pieces in parameter order, side A
+ * (right, p + wN) then side B, then the join or cap).
+ *   tolerance  > 0, in output units (pixels), Frechet-style bound;
+ *   output_mode SX_OUT_LINES (sx_line records) or SX_OUT_ARCS (sx_arc);
+ *   out_dev    device memory, out_capacity_bytes bytes, caller-owned;
+ *   out_count  host pointer, receives the number of records.
+ * If the outline needs more than out_capacity_bytes, nothing is written,
+ * *out_count holds the required record count and SX_ETOOSMALL is returned
+ * (retry with a larger buffer).  Blocks the host until the count is known.
+ * Errors: SX_EINVAL (tolerance not finite and > 0, bad mode), SX_EDEVICE. */
+int sx_expand(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, void *out_dev,
+              uint64_t out_capacity_bytes, uint64_t *out_count, void *stream);
+
+/* Same pipeline without any host synchronisation (capturable in a HIP graph):
+ * the record count is written to device memory *out_count_dev (uint64_t);
+ * when it exceeds the capacity nothing is emitted and the count is still
+ * written, so the caller can compare it with the capacity afterwards. */
+int sx_expand_async(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, void *out_dev,
+                    uint64_t out_capacity_bytes, uint64_t *out_count_dev, void *stream);
+
+/* Verification exports, running the same kernels as sx_expand:
+ * monoids: 4 x n_tags uint32 in device memory (SoA: point offset, path index,
+ * style index, transform index), exclusive for offset / path and inclusive-1
+ * for style / transform (Section 8.2). */
+int sx_debug_monoids(sx_ctx *ctx, const sx_scene *scene, uint32_t *out4xn_dev, void *stream);
+/* counts: n_tags uint32 (device) = records each tag emits. */
+int sx_debug_counts(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode,
+                    uint32_t *counts_dev, void *stream);
+/* offsets: n_tags + 1 uint64 (device) = exclusive scan of the counts. */
+int sx_debug_offsets(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode,
+                     uint64_t *offsets_dev, void *stream);
+
+/* Scan primitive on its own: exclusive prefix sum of n uint32 values into
+ * n + 1 uint64 (device pointers), single-pass decoupled look-back. */
+int sx_scan_u32(sx_ctx *ctx, const uint32_t *in_dev, uint64_t *out_dev, uint32_t n, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STROKEX_H */

@@ -739,9 +739,24 @@ static void emit_range(ox_sink *k, const ox_cfg *cfg, const ox_es *es, double h,
                 double x = ox_f_approx_inv(y);
                 us[i] = ua + (ub - ua) * ((x - xa) / (xb - xa));
             }
-        } else if (cfg->mode == OX_OUT_LINES) {
-            /* h = 0: invert the 1.5-power ES integral (Section 2.2) */
-            for (uint32_t i = 1; i < n; i++) us[i] = ua + (ub - ua) * ((double)i / n);
+        } else if (cfg->mode == OX_OUT_LINES && es->k1 != 0.0) {
+            /* h = 0: points uniform in the ES integral (2/3)|kappa|^1.5 / |kappa'|
+             * (Section 2.2), split at an inflection inside the range */
+            double Pa = pow(fabs(ka), 1.5), Pb = pow(fabs(kb), 1.5);
+            int same = ka * kb >= 0.0;
+            double total = same ? fabs(Pb - Pa) : Pa + Pb;
+            for (uint32_t i = 1; i < n; i++) {
+                double target = total * ((double)i / n), kap;
+                if (same) {
+                    double P = Pa + (Pb > Pa ? target : -target);
+                    kap = (ka + kb >= 0.0 ? 1.0 : -1.0) * pow(P, 2.0 / 3.0);
+                } else if (target <= Pa) {
+                    kap = (ka >= 0.0 ? 1.0 : -1.0) * pow(Pa - target, 2.0 / 3.0);
+                } else {
+                    kap = (kb >= 0.0 ? 1.0 : -1.0) * pow(target - Pa, 2.0 / 3.0);
+                }
+                us[i] = 0.5 + (kap * es->L - es->k0) / es->k1;
+            }
         } else {
             for (uint32_t i = 1; i < n; i++) us[i] = ua + (ub - ua) * ((double)i / n);
         }

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libstrokex.so (include/strokex.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  PyTorch supplies device memory (tensors) and streams.  Loading
+fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+import threading
+from typing import Optional
+
+import numpy as np
+
+from . import scenes as S
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libstrokex.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "strokex.h")
+
+SX_OK, SX_EINVAL, SX_ENOMEM, SX_EDEVICE, SX_ETOOSMALL, SX_EBUSY = 0, -1, -2, -3, -4, -5
+OUT_LINES, OUT_ARCS = 0, 1
+RECORD_BYTES = {OUT_LINES: 20, OUT_ARCS: 24}
+
+LINE_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("path", "<u4")])
+ARC_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("curv", "<f4"), ("path", "<u4")])
+
+
+class StrokexError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"strokex error {code}: {msg}")
+        self.code = code
+
+
+class _Paths(C.Structure):
+    _fields_ = [("verbs", C.c_void_p), ("verb_off", C.c_void_p), ("pts", C.c_void_p), ("pt_off", C.c_void_p),
+                ("style_ix", C.c_void_p), ("xform_ix", C.c_void_p), ("n_paths", C.c_uint32)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def header_symbols():
+    """Function names declared in include/strokex.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(sx_\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+            L = C.CDLL(LIB_PATH)
+            vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
+            sig = {
+                "sx_ctx_create": (C.c_int, [C.c_int, C.POINTER(vp)]),
+                "sx_ctx_destroy": (C.c_int, [vp]),
+                "sx_last_error": (C.c_char_p, [vp]),
+                "sx_version": (C.c_char_p, []),
+                "sx_scene_encode": (C.c_int, [vp, C.POINTER(_Paths), vp, u32, vp, u32, vp, C.POINTER(vp)]),
+                "sx_scene_release": (C.c_int, [vp, vp]),
+                "sx_scene_info": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+                "sx_scene_download": (C.c_int, [vp, vp, vp, vp]),
+                "sx_expand": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, u64, C.POINTER(u64), vp]),
+                "sx_expand_async": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, u64, vp, vp]),
+                "sx_debug_monoids": (C.c_int, [vp, vp, vp, vp]),
+                "sx_debug_counts": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
+                "sx_debug_offsets": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
+                "sx_scan_u32": (C.c_int, [vp, vp, vp, u32, vp]),
+            }
+            for name, (res, args) in sig.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Scene:
+    """A device-resident encoded scene (owned by its Context)."""
+
+    def __init__(self, ctx: "Context", handle: int, src: S.Scene):
+        self.ctx = ctx
+        self.h = handle
+        self.src = src
+        nt, npt, np_, ns, nx = (C.c_uint32() for _ in range(5))
+        lib().sx_scene_info(C.c_void_p(handle), C.byref(nt), C.byref(npt), C.byref(np_), C.byref(ns), C.byref(nx))
+        self.n_tags, self.n_pts, self.n_paths = nt.value, npt.value, np_.value
+        self.n_styles, self.n_xforms = ns.value, nx.value
+
+    def release(self):
+        if self.h:
+            lib().sx_scene_release(C.c_void_p(self.ctx.h), C.c_void_p(self.h))
+            self.h = 0
+
+    def __del__(self):
+        try:
+            if self.h and self.ctx.h:
+                self.release()
+        except Exception:
+            pass
+
+    def download(self):
+        tags = np.zeros(self.n_tags, np.uint8)
+        data = np.zeros((self.n_pts, 2), np.float32)
+        pm = np.zeros(self.n_paths, np.uint32)
+        rc = lib().sx_scene_download(C.c_void_p(self.h), tags.ctypes.data, data.ctypes.data, pm.ctypes.data)
+        if rc:
+            raise StrokexError(rc, "download")
+        return tags, data, pm
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.h = 0
+        h = C.c_void_p()
+        rc = lib().sx_ctx_create(int(device), C.byref(h))
+        if rc != SX_OK:
+            raise StrokexError(rc, "sx_ctx_create failed (is a gfx950 GPU visible?)")
+        self.h = h.value
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().sx_ctx_destroy(C.c_void_p(self.h))
+            self.h = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, what):
+        if rc != SX_OK:
+            msg = lib().sx_last_error(C.c_void_p(self.h)).decode()
+            raise StrokexError(rc, f"{what}: {msg}")
+
+    def encode(self, scene: S.Scene, stream=None) -> Scene:
+        keep = dict(
+            verbs=_arr(scene.verbs, np.uint8), verb_off=_arr(scene.verb_off, np.uint32),
+            pts=_arr(scene.pts, np.float32), pt_off=_arr(scene.pt_off, np.uint32),
+            style_ix=_arr(scene.style_ix, np.uint32), xform_ix=_arr(scene.xform_ix, np.uint32),
+            styles=_arr(scene.styles, S.STYLE_DTYPE), xforms=_arr(scene.xforms, np.float32),
+        )
+        p = _Paths(keep["verbs"].ctypes.data, keep["verb_off"].ctypes.data, keep["pts"].ctypes.data,
+                   keep["pt_off"].ctypes.data, keep["style_ix"].ctypes.data, keep["xform_ix"].ctypes.data,
+                   scene.n_paths)
+        out = C.c_void_p()
+        rc = lib().sx_scene_encode(C.c_void_p(self.h), C.byref(p), keep["styles"].ctypes.data, len(keep["styles"]),
+                                   keep["xforms"].ctypes.data, len(keep["xforms"]), _stream_ptr(stream), C.byref(out))
+        self._check(rc, "sx_scene_encode")
+        return Scene(self, out.value, scene)
+
+    def expand_into(self, scene: Scene, out_ptr: int, capacity_bytes: int, tolerance: float, mode: int,
+                    stream=None) -> int:
+        """Raw call: returns the record count; raises on SX_ETOOSMALL."""
+        cnt = C.c_uint64()
+        rc = lib().sx_expand(C.c_void_p(self.h), C.c_void_p(scene.h), float(tolerance), int(mode),
+                             C.c_void_p(out_ptr), int(capacity_bytes), C.byref(cnt), _stream_ptr(stream))
+        if rc == SX_ETOOSMALL:
+            e = StrokexError(rc, "output buffer too small")
+            e.required = cnt.value
+            raise e
+        self._check(rc, "sx_expand")
+        return cnt.value
+
+    def expand_async(self, scene: Scene, out_ptr: int, capacity_bytes: int, count_dev_ptr: int, tolerance: float,
+                     mode: int, stream=None):
+        rc = lib().sx_expand_async(C.c_void_p(self.h), C.c_void_p(scene.h), float(tolerance), int(mode),
+                                   C.c_void_p(out_ptr), int(capacity_bytes), C.c_void_p(count_dev_ptr),
+                                   _stream_ptr(stream))
+        self._check(rc, "sx_expand_async")
+
+    def expand(self, scene: Scene, tolerance: Optional[float] = None, mode: Optional[int] = None, out=None,
+               stream=None):
+        """Expand into a torch uint8 device tensor (grown on demand).
+        Returns (records tensor view [n, 5|6] float32 (path id bits in the last
+        column), count, buffer)."""
+        import torch
+
+        tol = scene.src.tolerance if tolerance is None else tolerance
+        mode = scene.src.output_mode if mode is None else mode
+        rec = RECORD_BYTES[mode]
+        if out is None:
+            out = torch.empty(max(1, scene.n_tags * 16) * rec, dtype=torch.uint8, device=f"cuda:{self.device}")
+        while True:
+            try:
+                n = self.expand_into(scene, out.data_ptr(), out.numel(), tol, mode, stream)
+                break
+            except StrokexError as e:
+                if e.code != SX_ETOOSMALL:
+                    raise
+                out = torch.empty(int(e.required * 1.25 + 1) * rec, dtype=torch.uint8, device=out.device)
+        return out[: n * rec].view(torch.float32).view(-1, rec // 4), n, out
+
+    def monoids(self, scene: Scene, stream=None):
+        import torch
+
+        m = torch.empty(4 * max(scene.n_tags, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib().sx_debug_monoids(C.c_void_p(self.h), C.c_void_p(scene.h), C.c_void_p(m.data_ptr()),
+                                           _stream_ptr(stream)), "sx_debug_monoids")
+        return m[: 4 * scene.n_tags].view(4, -1)
+
+    def counts(self, scene: Scene, tolerance=None, mode=None, stream=None):
+        import torch
+
+        tol = scene.src.tolerance if tolerance is None else tolerance
+        mode = scene.src.output_mode if mode is None else mode
+        c = torch.empty(max(scene.n_tags, 1), dtype=torch.int32, device=f"cuda:{self.device}")
+        self._check(lib().sx_debug_counts(C.c_void_p(self.h), C.c_void_p(scene.h), float(tol), int(mode),
+                                          C.c_void_p(c.data_ptr()), _stream_ptr(stream)), "sx_debug_counts")
+        return c[: scene.n_tags]
+
+    def offsets(self, scene: Scene, tolerance=None, mode=None, stream=None):
+        import torch
+
+        tol = scene.src.tolerance if tolerance is None else tolerance
+        mode = scene.src.output_mode if mode is None else mode
+        o = torch.empty(scene.n_tags + 1, dtype=torch.int64, device=f"cuda:{self.device}")
+        self._check(lib().sx_debug_offsets(C.c_void_p(self.h), C.c_void_p(scene.h), float(tol), int(mode),
+                                           C.c_void_p(o.data_ptr()), _stream_ptr(stream)), "sx_debug_offsets")
+        return o
+
+    def scan_u32(self, values, stream=None):
+        import torch
+
+        n = int(values.numel())
+        out = torch.empty(n + 1, dtype=torch.int64, device=values.device)
+        self._check(lib().sx_scan_u32(C.c_void_p(self.h), C.c_void_p(values.data_ptr()), C.c_void_p(out.data_ptr()),
+                                      n, _stream_ptr(stream)), "sx_scan_u32")
+        return out
+
+
+def records_to_numpy(recs_tensor, mode) -> np.ndarray:
+    a = recs_tensor.detach().cpu().numpy()
+    return np.ascontiguousarray(a).view(LINE_DTYPE if mode == OUT_LINES else ARC_DTYPE).reshape(-1)

@@ -1,0 +1,362 @@
+// C ABI of the strokex library (declared in include/strokex.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "strokex.h"
+#include "sx_device.h"
+#include "sx_encode.h"
+#include "sx_kernels.h"
+
+struct sx_ctx {
+    int device = 0;
+    std::string err;
+    uint64_t* pinned_total = nullptr;  // host-pinned u64 for the record count
+};
+
+struct sx_scene {
+    sx_ctx* ctx = nullptr;
+    uint32_t n_tags = 0, n_pts = 0, n_paths = 0, n_styles = 0, n_xforms = 0;
+    uint8_t* d_tags = nullptr;
+    float2* d_pts = nullptr;
+    sx::StyleD* d_styles = nullptr;
+    float* d_xforms = nullptr;
+    uint32_t* d_path_map = nullptr;
+    uint32_t* d_mon = nullptr;
+    uint32_t* d_counts = nullptr;
+    uint64_t* d_offsets = nullptr;
+    void* d_scan_ctl = nullptr;  // two control blocks (tags, counts)
+    void* d_status_tags = nullptr;
+    void* d_status_counts = nullptr;
+    hipStream_t last_stream = nullptr;
+};
+
+namespace {
+
+int fail(sx_ctx* ctx, int code, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+int hip_fail(sx_ctx* ctx, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? SX_ENOMEM : SX_EDEVICE, m);
+}
+
+template <class T>
+hipError_t dalloc(T** p, size_t bytes) {
+    return hipMalloc((void**)p, bytes ? bytes : 16);
+}
+
+void free_scene(sx_scene* s) {
+    if (!s) return;
+    void* bufs[] = {s->d_tags, s->d_pts, s->d_styles, s->d_xforms, s->d_path_map, s->d_mon,
+                    s->d_counts, s->d_offsets, s->d_scan_ctl, s->d_status_tags, s->d_status_counts};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete s;
+}
+
+bool similarity(const sx_affine& X) {
+    bool rot = (X.a == X.d) && (X.b == -X.c);
+    bool refl = (X.a == -X.d) && (X.b == X.c);
+    double det = (double)X.a * X.d - (double)X.b * X.c;
+    bool fin = std::isfinite(X.a) && std::isfinite(X.b) && std::isfinite(X.c) && std::isfinite(X.d) &&
+               std::isfinite(X.e) && std::isfinite(X.f);
+    return fin && (rot || refl) && det != 0.0;
+}
+
+sx::SceneView view(const sx_scene* s) {
+    sx::SceneView v;
+    v.tags = s->d_tags;
+    v.pts = s->d_pts;
+    v.styles = s->d_styles;
+    v.xforms = s->d_xforms;
+    v.path_map = s->d_path_map;
+    v.mon = s->d_mon;
+    v.n_tags = s->n_tags;
+    return v;
+}
+
+bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
+    if (!(tol > 0.0f) || !std::isfinite(tol)) return false;
+    if (mode != SX_OUT_LINES && mode != SX_OUT_ARCS) return false;
+    double tf = (double)sx::kFlatFrac * (double)tol;
+    cfg.tau_fit = (float)((double)sx::kFitFrac * (double)tol);
+    cfg.tau_flat = (float)tf;
+    cfg.inv_sqrt8tf = (float)std::sqrt(1.0 / (8.0 * tf));
+    cfg.cbrt_inv120tf = (float)std::cbrt(1.0 / (120.0 * tf));
+    cfg.round_step = 0.0f;
+    cfg.arcs = mode == SX_OUT_ARCS;
+    cfg.paper_fit = 0;
+    return true;
+}
+
+// tag scan + count + count scan
+int run_counts(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, hipStream_t st) {
+    hipError_t e;
+    char* ctl = (char*)s->d_scan_ctl;
+    if ((e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, st)) != hipSuccess)
+        return hip_fail(ctx, e, "scan_tags launch");
+    if ((e = sx::launch_count(view(s), cfg, s->d_counts, st)) != hipSuccess) return hip_fail(ctx, e, "count launch");
+    if ((e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
+                                    s->d_status_counts, st)) != hipSuccess)
+        return hip_fail(ctx, e, "scan_counts launch");
+    return SX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sx_version(void) { return "strokex 0.1 (gfx950)"; }
+
+int sx_ctx_create(int device, sx_ctx** out) {
+    if (!out) return SX_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SX_EDEVICE;
+    sx_ctx* c = new (std::nothrow) sx_ctx();
+    if (!c) return SX_ENOMEM;
+    c->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete c; return SX_EDEVICE; }
+    if (hipHostMalloc((void**)&c->pinned_total, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SX_ENOMEM;
+    }
+    *out = c;
+    return SX_OK;
+}
+
+int sx_ctx_destroy(sx_ctx* ctx) {
+    if (!ctx) return SX_OK;
+    if (ctx->pinned_total) (void)hipHostFree(ctx->pinned_total);
+    delete ctx;
+    return SX_OK;
+}
+
+const char* sx_last_error(const sx_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, uint32_t n_styles,
+                    const sx_affine* xforms, uint32_t n_xforms, void* stream, sx_scene** out) {
+    if (!ctx || !out) return SX_EINVAL;
+    *out = nullptr;
+    if (!paths || (paths->n_paths && (!paths->verbs || !paths->verb_off || !paths->pts || !paths->pt_off ||
+                                      !paths->style_ix || !paths->xform_ix)))
+        return fail(ctx, SX_EINVAL, "null path arrays");
+    if ((n_styles && !styles) || (n_xforms && !xforms)) return fail(ctx, SX_EINVAL, "null style/transform table");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SX_EDEVICE, "hipSetDevice");
+    sx::HostEncoding enc;
+    std::string err;
+    if (!sx::encode_paths(*paths, n_styles, n_xforms, enc, err)) return fail(ctx, SX_EINVAL, err);
+    // validate the styles and transforms that are actually used
+    std::vector<sx::StyleD> sd(enc.style_stream.size());
+    for (size_t i = 0; i < enc.style_stream.size(); i++) {
+        const sx_style& st = styles[enc.style_stream[i]];
+        if (!(st.half_width >= 0.0f) || !std::isfinite(st.half_width)) return fail(ctx, SX_EINVAL, "half_width < 0");
+        if (!(st.miter_limit >= 1.0f) || !std::isfinite(st.miter_limit)) return fail(ctx, SX_EINVAL, "miter_limit < 1");
+        if (st.join > 2 || st.start_cap > 2 || st.end_cap > 2) return fail(ctx, SX_EINVAL, "bad join/cap");
+        if (st.flags != 0) return fail(ctx, SX_EINVAL, "style flags are reserved");
+        sd[i] = sx::StyleD{st.half_width, st.miter_limit,
+                           (uint32_t)st.join | ((uint32_t)st.start_cap << 8) | ((uint32_t)st.end_cap << 16)};
+    }
+    std::vector<float> xd(6 * enc.xform_stream.size());
+    for (size_t i = 0; i < enc.xform_stream.size(); i++) {
+        const sx_affine& X = xforms[enc.xform_stream[i]];
+        if (!similarity(X)) return fail(ctx, SX_EINVAL, "stroke transforms must be similarities");
+        const float v[6] = {X.a, X.b, X.c, X.d, X.e, X.f};
+        memcpy(&xd[6 * i], v, sizeof(v));
+    }
+    sx_scene* s = new (std::nothrow) sx_scene();
+    if (!s) return fail(ctx, SX_ENOMEM, "scene alloc");
+    s->ctx = ctx;
+    s->n_tags = (uint32_t)enc.tags.size();
+    s->n_pts = (uint32_t)(enc.data.size() / 2);
+    s->n_paths = (uint32_t)enc.path_map.size();
+    s->n_styles = (uint32_t)sd.size();
+    s->n_xforms = (uint32_t)enc.xform_stream.size();
+    hipStream_t st = (hipStream_t)stream;
+    const size_t ntag_pad = ((size_t)s->n_tags + 16 + 15) & ~(size_t)15;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+    };
+    A(dalloc(&s->d_tags, ntag_pad));
+    A(dalloc(&s->d_pts, (size_t)s->n_pts * sizeof(float2)));
+    A(dalloc(&s->d_styles, sd.size() * sizeof(sx::StyleD)));
+    A(dalloc(&s->d_xforms, xd.size() * sizeof(float)));
+    A(dalloc(&s->d_path_map, enc.path_map.size() * sizeof(uint32_t)));
+    A(dalloc(&s->d_mon, 4 * (size_t)s->n_tags * sizeof(uint32_t)));
+    A(dalloc(&s->d_counts, ((size_t)s->n_tags + 16) * sizeof(uint32_t)));
+    A(dalloc(&s->d_offsets, ((size_t)s->n_tags + 1) * sizeof(uint64_t)));
+    A(dalloc(&s->d_scan_ctl, 2 * sx::scan_ctl_bytes()));
+    A(dalloc(&s->d_status_tags, sx::scan_status_bytes(s->n_tags)));
+    A(dalloc(&s->d_status_counts, sx::scan_status_bytes(s->n_tags)));
+    if (e != hipSuccess) {
+        free_scene(s);
+        return hip_fail(ctx, e, "scene allocation");
+    }
+    A(hipMemsetAsync(s->d_tags, 0, ntag_pad, st));
+    A(hipMemsetAsync(s->d_scan_ctl, 0, 2 * sx::scan_ctl_bytes(), st));
+    A(hipMemsetAsync(s->d_status_tags, 0, sx::scan_status_bytes(s->n_tags), st));
+    A(hipMemsetAsync(s->d_status_counts, 0, sx::scan_status_bytes(s->n_tags), st));
+    if (s->n_tags) A(hipMemcpyAsync(s->d_tags, enc.tags.data(), s->n_tags, hipMemcpyHostToDevice, st));
+    if (s->n_pts)
+        A(hipMemcpyAsync(s->d_pts, enc.data.data(), enc.data.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    if (!sd.empty()) A(hipMemcpyAsync(s->d_styles, sd.data(), sd.size() * sizeof(sx::StyleD), hipMemcpyHostToDevice, st));
+    if (!xd.empty()) A(hipMemcpyAsync(s->d_xforms, xd.data(), xd.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    if (!enc.path_map.empty())
+        A(hipMemcpyAsync(s->d_path_map, enc.path_map.data(), enc.path_map.size() * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, st));
+    // host vectors die with this call: finish the uploads before returning
+    A(hipStreamSynchronize(st));
+    if (e != hipSuccess) {
+        free_scene(s);
+        return hip_fail(ctx, e, "scene upload");
+    }
+    s->last_stream = st;
+    *out = s;
+    return SX_OK;
+}
+
+int sx_scene_release(sx_ctx* ctx, sx_scene* scene) {
+    if (!scene) return SX_OK;
+    if (ctx && scene->ctx != ctx) return fail(ctx, SX_EINVAL, "scene belongs to another context");
+    (void)hipStreamSynchronize(scene->last_stream);
+    free_scene(scene);
+    return SX_OK;
+}
+
+int sx_scene_info(const sx_scene* s, uint32_t* n_tags, uint32_t* n_pts, uint32_t* n_paths, uint32_t* n_styles,
+                  uint32_t* n_xforms) {
+    if (!s) return SX_EINVAL;
+    if (n_tags) *n_tags = s->n_tags;
+    if (n_pts) *n_pts = s->n_pts;
+    if (n_paths) *n_paths = s->n_paths;
+    if (n_styles) *n_styles = s->n_styles;
+    if (n_xforms) *n_xforms = s->n_xforms;
+    return SX_OK;
+}
+
+int sx_scene_download(const sx_scene* s, uint8_t* tags, float* data, uint32_t* path_map) {
+    if (!s) return SX_EINVAL;
+    hipError_t e = hipSuccess;
+    if (tags && s->n_tags) e = hipMemcpy(tags, s->d_tags, s->n_tags, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && data && s->n_pts)
+        e = hipMemcpy(data, s->d_pts, (size_t)s->n_pts * sizeof(float2), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && path_map && s->n_paths)
+        e = hipMemcpy(path_map, s->d_path_map, (size_t)s->n_paths * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? SX_OK : SX_EDEVICE;
+}
+
+int sx_expand_async(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mode, void* out_dev,
+                    uint64_t out_capacity_bytes, uint64_t* out_count_dev, void* stream) {
+    if (!ctx || !scene) return SX_EINVAL;
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!out_count_dev) return fail(ctx, SX_EINVAL, "null count pointer");
+    if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const_cast<sx_scene*>(scene)->last_stream = st;
+    const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
+    if (scene->n_tags == 0) {
+        hipError_t e = hipMemsetAsync(out_count_dev, 0, sizeof(uint64_t), st);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
+    }
+    int r = run_counts(ctx, scene, cfg, st);
+    if (r != SX_OK) return r;
+    hipError_t e = sx::launch_emit(view(scene), cfg, scene->d_offsets, out_dev, out_capacity_bytes / rec, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "emit launch");
+    e = sx::launch_copy_total(scene->d_offsets, scene->n_tags, out_count_dev, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "count copy");
+    return SX_OK;
+}
+
+int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mode, void* out_dev,
+              uint64_t out_capacity_bytes, uint64_t* out_count, void* stream) {
+    if (!ctx || !scene || !out_count) return SX_EINVAL;
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
+    hipStream_t st = (hipStream_t)stream;
+    const_cast<sx_scene*>(scene)->last_stream = st;
+    const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
+    *out_count = 0;
+    if (scene->n_tags == 0) return SX_OK;
+    int r = run_counts(ctx, scene, cfg, st);
+    if (r != SX_OK) return r;
+    hipError_t e = sx::launch_emit(view(scene), cfg, scene->d_offsets, out_dev, out_capacity_bytes / rec, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "emit launch");
+    e = hipMemcpyAsync(ctx->pinned_total, scene->d_offsets + scene->n_tags, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "count readback");
+    *out_count = *ctx->pinned_total;
+    if (*out_count > out_capacity_bytes / rec) return fail(ctx, SX_ETOOSMALL, "output buffer too small");
+    return SX_OK;
+}
+
+int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void* stream) {
+    if (!ctx || !s || (!out4xn_dev && s->n_tags)) return SX_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    char* ctl = (char*)s->d_scan_ctl;
+    hipError_t e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, st);
+    if (e == hipSuccess && s->n_tags)
+        e = hipMemcpyAsync(out4xn_dev, s->d_mon, 4 * (size_t)s->n_tags * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "monoids");
+}
+
+int sx_debug_counts(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint32_t* counts_dev,
+                    void* stream) {
+    if (!ctx || !s || (!counts_dev && s->n_tags)) return SX_EINVAL;
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (s->n_tags == 0) return SX_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int r = run_counts(ctx, s, cfg, st);
+    if (r != SX_OK) return r;
+    hipError_t e = hipMemcpyAsync(counts_dev, s->d_counts, (size_t)s->n_tags * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "counts copy");
+}
+
+int sx_debug_offsets(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint64_t* offsets_dev,
+                     void* stream) {
+    if (!ctx || !s || !offsets_dev) return SX_EINVAL;
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    hipStream_t st = (hipStream_t)stream;
+    if (s->n_tags == 0) {
+        hipError_t e = hipMemsetAsync(offsets_dev, 0, sizeof(uint64_t), st);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
+    }
+    int r = run_counts(ctx, s, cfg, st);
+    if (r != SX_OK) return r;
+    hipError_t e = hipMemcpyAsync(offsets_dev, s->d_offsets, ((size_t)s->n_tags + 1) * sizeof(uint64_t),
+                                  hipMemcpyDeviceToDevice, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "offsets copy");
+}
+
+int sx_scan_u32(sx_ctx* ctx, const uint32_t* in_dev, uint64_t* out_dev, uint32_t n, void* stream) {
+    if (!ctx || !out_dev || (n && !in_dev)) return SX_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        hipError_t e = hipMemsetAsync(out_dev, 0, sizeof(uint64_t), st);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
+    }
+    void *ctl = nullptr, *status = nullptr;
+    hipError_t e = hipMalloc(&ctl, sx::scan_ctl_bytes());
+    if (e == hipSuccess) e = hipMalloc(&status, sx::scan_status_bytes(n));
+    if (e == hipSuccess) e = hipMemsetAsync(ctl, 0, sx::scan_ctl_bytes(), st);
+    if (e == hipSuccess) e = hipMemsetAsync(status, 0, sx::scan_status_bytes(n), st);
+    if (e == hipSuccess) e = sx::launch_scan_counts(in_dev, n, out_dev, ctl, status, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (ctl) (void)hipFree(ctl);
+    if (status) (void)hipFree(status);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "scan_u32");
+}
+
+}  // extern "C"

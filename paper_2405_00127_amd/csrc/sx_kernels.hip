@@ -1,0 +1,355 @@
+// HIP kernels of the stroke-expansion hot path for gfx950 (wave64).
+//
+//  scan_tags_kernel   tag-monoid prefix scan (Section 8.2): single pass,
+//                     wave64 shuffle scan + LDS block scan + decoupled
+//                     look-back over dynamically numbered tiles.
+//  count_kernel       per tag, the number of output records (Algorithm 1 /
+//                     Algorithm 2 run in counting mode).
+//  scan_counts_kernel exclusive scan of the counts into u64 output offsets
+//                     (replaces the paper's atomic bump allocation, so the
+//                     output order is canonical and deterministic).
+//  emit_kernel        per tag, the records at their offsets.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sx_device.h"
+#include "sx_kernels.h"
+
+namespace sx {
+
+// ------------------------------------------------------ look-back scan
+// Per-tile status word: (epoch << 2) | state, state 1 = aggregate ready,
+// 2 = inclusive prefix ready.  The epoch (kept in device memory and bumped
+// by the last tile of every launch) makes stale flags of earlier launches
+// read as "not ready", so nothing has to be cleared between launches and the
+// kernels can be replayed inside a HIP graph.
+struct TileStatus {
+    uint32_t flag;
+    uint32_t pad;
+    uint64_t a;
+    uint64_t b;
+    uint64_t pad2;
+};
+static_assert(sizeof(TileStatus) == 32, "tile status layout");
+
+struct Pair {
+    uint64_t a, b;
+};
+
+struct ScanCtl {
+    uint32_t ticket, done, epoch, err;
+};
+__device__ __forceinline__ Pair operator+(Pair x, Pair y) { return Pair{x.a + y.a, x.b + y.b}; }
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int d) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_up(lo, d, 64);
+    hi = __shfl_up(hi, d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl(lo, src, 64);
+    hi = __shfl(hi, src, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    lo = __shfl_xor(lo, m, 64);
+    hi = __shfl_xor(hi, m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// inclusive wave64 scan
+__device__ __forceinline__ Pair wave_scan(Pair v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint64_t ua = shfl_up_u64(v.a, d), ub = shfl_up_u64(v.b, d);
+        if (lane >= d) { v.a += ua; v.b += ub; }
+    }
+    return v;
+}
+__device__ __forceinline__ Pair wave_sum(Pair v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        v.a += shfl_xor_u64(v.a, m);
+        v.b += shfl_xor_u64(v.b, m);
+    }
+    return v;
+}
+
+__device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_release(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish a tile's value with its state (data first, then the flag).
+__device__ __forceinline__ void publish(TileStatus* st, uint32_t tile, uint32_t epoch, uint32_t state, Pair v) {
+    st[tile].a = v.a;
+    st[tile].b = v.b;
+    __threadfence();
+    store_release(&st[tile].flag, (epoch << 2) | state);
+}
+
+// Wave 0 of tile `tile` computes the exclusive prefix of all earlier tiles.
+// The wait for a predecessor is bounded: after kSpinLimit polls the tile
+// gives up, records the failure in *err and carries on (wrong sums, but every
+// wave exits).  Predecessors always hold earlier tickets, so they are resident
+// and the limit is never reached in a correct run.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ Pair look_back(TileStatus* st, uint32_t tile, uint32_t epoch, int lane, uint32_t* err) {
+    Pair excl{0, 0};
+    int64_t pos = (int64_t)tile - 1;
+    while (pos >= 0) {
+        int64_t idx = pos - lane;
+        uint32_t state;
+        Pair v{0, 0};
+        for (uint32_t spins = 0;; spins++) {
+            state = 3;  // lanes past tile 0 count as "inclusive zero"
+            if (idx >= 0) {
+                uint32_t f = load_acquire(&st[idx].flag);
+                state = ((f >> 2) == (epoch & 0x3fffffffu)) ? (f & 3u) : 0u;
+            }
+            if (__ballot(state == 0u) == 0ull) break;
+            if (spins >= kSpinLimit) {
+                if (lane == 0) atomicOr(err, 1u);
+                state = 3;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (idx >= 0) {
+            v.a = __hip_atomic_load(&st[idx].a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v.b = __hip_atomic_load(&st[idx].b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        uint64_t incl_mask = __ballot(state >= 2u);
+        if (incl_mask) {
+            int first = __builtin_ctzll(incl_mask);  // nearest tile with a full prefix
+            if (lane > first) v = Pair{0, 0};
+            excl = excl + wave_sum(v);
+            break;
+        }
+        excl = excl + wave_sum(v);
+        pos -= 64;
+    }
+    return excl;
+}
+
+// --------------------------------------------------------- tag monoid
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanBlock * kScanItems;
+
+__device__ __forceinline__ Pair tag_inc(uint32_t t) {
+    uint64_t pts = (t & kTagCount) + ((t & kTagEnd) ? 1u : 0u);
+    uint64_t pth = (t & kTagPath) ? 1u : 0u;
+    uint64_t sty = (t & kTagStyle) ? 1u : 0u;
+    uint64_t xf = (t & kTagXform) ? 1u : 0u;
+    return Pair{pts | (pth << 32), sty | (xf << 32)};
+}
+
+template <class Load, class Store>
+__device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, TileStatus* st) {
+    __shared__ uint32_t s_tile, s_epoch;
+    __shared__ Pair s_wave[kScanBlock / 64];
+    __shared__ Pair s_excl;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) {
+        s_tile = atomicAdd(&ctl->ticket, 1u);
+        s_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t tile = s_tile, epoch = s_epoch & 0x3fffffffu;
+    const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)tid * kScanItems;
+    Pair item[kScanItems];
+    load(base, item);
+    Pair run{0, 0};
+#pragma unroll
+    for (int j = 0; j < kScanItems; j++) {
+        run = run + item[j];
+        item[j] = run;  // thread-local inclusive
+    }
+    Pair wincl = wave_scan(run, lane);
+    if (lane == 63) s_wave[wv] = wincl;
+    __syncthreads();
+    Pair wpre{0, 0}, agg{0, 0};
+#pragma unroll
+    for (int k = 0; k < kScanBlock / 64; k++) {
+        if (k < wv) wpre = wpre + s_wave[k];
+        agg = agg + s_wave[k];
+    }
+    Pair texcl = wpre + wincl;
+    texcl.a -= run.a;
+    texcl.b -= run.b;
+    if (wv == 0) {
+        Pair excl{0, 0};
+        if (tile == 0) {
+            if (lane == 0) publish(st, tile, epoch, 2, agg);
+        } else {
+            if (lane == 0) publish(st, tile, epoch, 1, agg);
+            excl = look_back(st, tile, epoch, lane, &ctl->err);
+            if (lane == 0) publish(st, tile, epoch, 2, excl + agg);
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    Pair pre = s_excl + texcl;
+    store(base, item, pre);
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+        if (atomicAdd(&ctl->done, 1u) == ntiles - 1) {
+            ctl->ticket = 0;
+            ctl->done = 0;
+            __threadfence();
+            __hip_atomic_store(&ctl->epoch, (s_epoch + 1u) & 0x3fffffffu, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __restrict__ tags, uint32_t n,
+                                                               uint32_t* __restrict__ mon, ScanCtl* ctl,
+                                                               TileStatus* st) {
+    auto load = [&](uint64_t base, Pair* item) {
+        if (base + kScanItems <= n) {
+            uint4 raw = *reinterpret_cast<const uint4*>(tags + base);
+            uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+            for (int j = 0; j < kScanItems; j++) item[j] = tag_inc((w[j >> 2] >> (8 * (j & 3))) & 0xffu);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanItems; j++) item[j] = (base + j < n) ? tag_inc(tags[base + j]) : Pair{0, 0};
+        }
+    };
+    auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
+        // item j: exclusive = pre + incl[j-1]; style/xform stored inclusive - 1
+        uint32_t o_off[kScanItems], o_pth[kScanItems], o_sty[kScanItems], o_xf[kScanItems];
+#pragma unroll
+        for (int j = 0; j < kScanItems; j++) {
+            Pair ex = pre;
+            if (j > 0) ex = ex + incl[j - 1];
+            Pair in = pre + incl[j];
+            o_off[j] = (uint32_t)ex.a;
+            o_pth[j] = (uint32_t)(ex.a >> 32);
+            o_sty[j] = (uint32_t)in.b - 1u;
+            o_xf[j] = (uint32_t)(in.b >> 32) - 1u;
+        }
+        uint32_t* m0 = mon;
+        uint32_t* m1 = mon + n;
+        uint32_t* m2 = mon + 2 * (size_t)n;
+        uint32_t* m3 = mon + 3 * (size_t)n;
+        if (base + kScanItems <= n && (n & 3u) == 0u) {
+#pragma unroll
+            for (int j = 0; j < kScanItems; j += 4) {
+                *reinterpret_cast<uint4*>(m0 + base + j) = make_uint4(o_off[j], o_off[j + 1], o_off[j + 2], o_off[j + 3]);
+                *reinterpret_cast<uint4*>(m1 + base + j) = make_uint4(o_pth[j], o_pth[j + 1], o_pth[j + 2], o_pth[j + 3]);
+                *reinterpret_cast<uint4*>(m2 + base + j) = make_uint4(o_sty[j], o_sty[j + 1], o_sty[j + 2], o_sty[j + 3]);
+                *reinterpret_cast<uint4*>(m3 + base + j) = make_uint4(o_xf[j], o_xf[j + 1], o_xf[j + 2], o_xf[j + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanItems; j++) {
+                if (base + j < n) {
+                    m0[base + j] = o_off[j];
+                    m1[base + j] = o_pth[j];
+                    m2[base + j] = o_sty[j];
+                    m3[base + j] = o_xf[j];
+                }
+            }
+        }
+    };
+    scan_tile(load, store, n, ctl, st);
+}
+
+// exclusive scan of u32 counts into u64 offsets; out[n] = total
+__global__ __launch_bounds__(kScanBlock) void scan_counts_kernel(const uint32_t* __restrict__ in, uint32_t n,
+                                                                 uint64_t* __restrict__ out, ScanCtl* ctl,
+                                                                 TileStatus* st) {
+    auto load = [&](uint64_t base, Pair* item) {
+        if (base + kScanItems <= n) {
+#pragma unroll
+            for (int j = 0; j < kScanItems; j += 4) {
+                uint4 v = *reinterpret_cast<const uint4*>(in + base + j);
+                item[j] = Pair{v.x, 0};
+                item[j + 1] = Pair{v.y, 0};
+                item[j + 2] = Pair{v.z, 0};
+                item[j + 3] = Pair{v.w, 0};
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kScanItems; j++) item[j] = Pair{(base + j < n) ? (uint64_t)in[base + j] : 0ull, 0};
+        }
+    };
+    auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
+#pragma unroll
+        for (int j = 0; j < kScanItems; j++) {
+            uint64_t ex = pre.a + (j > 0 ? incl[j - 1].a : 0ull);
+            if (base + j < n) out[base + j] = ex;
+            if (base + j == (uint64_t)n - 1u) out[n] = pre.a + incl[j].a;
+        }
+    };
+    scan_tile(load, store, n, ctl, st);
+}
+
+// ------------------------------------------------------- count / emit
+constexpr int kTagBlock = 256;
+
+__global__ __launch_bounds__(kTagBlock) void count_kernel(SceneView sv, Cfg cfg, uint32_t* __restrict__ counts) {
+    uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
+    if (i >= sv.n_tags) return;
+    CountSink k{0};
+    process_tag(k, cfg, sv, i);
+    counts[i] = k.n;
+}
+
+__global__ __launch_bounds__(kTagBlock) void emit_kernel(SceneView sv, Cfg cfg, const uint64_t* __restrict__ offsets,
+                                                         float* __restrict__ out, uint64_t capacity_records) {
+    uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
+    if (i >= sv.n_tags) return;
+    if (offsets[sv.n_tags] > capacity_records) return;  // caller reads the count
+    uint32_t path = sv.path_map[sv.mon[(size_t)sv.n_tags + i]];
+    WriteSink k{out, offsets[i], offsets[i + 1], path, cfg.arcs, 0};
+    process_tag(k, cfg, sv, i);
+}
+
+__global__ void copy_total_kernel(const uint64_t* __restrict__ offsets, uint32_t n, uint64_t* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = offsets[n];
+}
+
+// ------------------------------------------------------------- launches
+int scan_tiles(uint32_t n) { return (int)((n + kScanTile - 1) / kScanTile); }
+
+hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    scan_tags_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(tags, n, mon, (ScanCtl*)ctl, (TileStatus*)st);
+    return hipGetLastError();
+}
+hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    scan_counts_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
+    return hipGetLastError();
+}
+hipError_t launch_count(const SceneView& sv, const Cfg& cfg, uint32_t* counts, hipStream_t s) {
+    if (sv.n_tags == 0) return hipSuccess;
+    count_kernel<<<(sv.n_tags + kTagBlock - 1) / kTagBlock, kTagBlock, 0, s>>>(sv, cfg, counts);
+    return hipGetLastError();
+}
+hipError_t launch_emit(const SceneView& sv, const Cfg& cfg, const uint64_t* offsets, void* out, uint64_t cap,
+                       hipStream_t s) {
+    if (sv.n_tags == 0) return hipSuccess;
+    emit_kernel<<<(sv.n_tags + kTagBlock - 1) / kTagBlock, kTagBlock, 0, s>>>(sv, cfg, offsets, (float*)out, cap);
+    return hipGetLastError();
+}
+hipError_t launch_copy_total(const uint64_t* offsets, uint32_t n, uint64_t* dst, hipStream_t s) {
+    copy_total_kernel<<<1, 64, 0, s>>>(offsets, n, dst);
+    return hipGetLastError();
+}
+size_t scan_status_bytes(uint32_t n) { return (size_t)scan_tiles(n > 0 ? n : 1) * sizeof(TileStatus); }
+size_t scan_ctl_bytes() { return sizeof(ScanCtl); }
+
+}  // namespace sx

@@ -1,0 +1,282 @@
+"""GPU (HIP, gfx950) vs FP64 oracle parity, through the C ABI.
+
+Bars: encoding and monoids bit-exact; output offsets bit-exact where the
+counts agree; counts identical except at oracle decisions within the margin
+thresholds of ``parity``; endpoints within 1e-3 px; arcs' sweep within
+2e-3 rad; path ids equal; outlines closed bit-exactly per path."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import parity as P
+from paper_2405_00127_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+    from paper_2405_00127_amd import build as PB
+
+    if not __import__("os").path.exists(B.LIB_PATH):
+        PB.build()
+    torch.cuda.set_device(0)
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _expand(ctx, sc, mode=None):
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    mode = sc.output_mode if mode is None else mode
+    scene = ctx.encode(sc)
+    recs, n, _ = ctx.expand(scene, sc.tolerance, mode)
+    counts = ctx.counts(scene, sc.tolerance, mode).cpu().numpy().astype(np.uint32)
+    torch.cuda.synchronize()
+    return scene, counts, B.records_to_numpy(recs, mode)
+
+
+# ------------------------------------------------------------- encoding
+@pytest.mark.parametrize("name", ["c1", "c2small", "c3small"])
+def test_encoding_bit_exact(ctx, name):
+    sc = {"c1": lambda: S.scene_c1(1), "c2small": lambda: S.scene_c2(2, n_segments=30000, n_paths=300),
+          "c3small": lambda: S.scene_c3(3, n_cubics=500)}[name]()
+    _say("encoding", name)
+    scene = ctx.encode(sc)
+    tags, data, pm = scene.download()
+    e = O.encode(sc)
+    assert np.array_equal(tags, e.tags)
+    assert np.array_equal(data.view(np.uint32), e.data.view(np.uint32))
+    assert np.array_equal(pm, e.path_map)
+
+
+# --------------------------------------------------------------- scans
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 4095, 4096, 4097, 65536 * 4 + 3, 1 << 20])
+def test_scan_u32_bit_exact(ctx, n):
+    import torch
+
+    _say("scan_u32 n =", n)
+    rng = np.random.default_rng(n)
+    v = rng.integers(0, 5000, n).astype(np.uint32)
+    t = torch.from_numpy(v.view(np.int32)).cuda()
+    out = ctx.scan_u32(t).cpu().numpy().astype(np.uint64)
+    ref = np.concatenate([[0], np.cumsum(v.astype(np.uint64))])
+    assert np.array_equal(out, ref)
+
+
+def test_scan_u32_repeated_launches(ctx):
+    import torch
+
+    v = np.arange(50000, dtype=np.uint32) % 7
+    t = torch.from_numpy(v.view(np.int32)).cuda()
+    ref = np.concatenate([[0], np.cumsum(v.astype(np.uint64))])
+    for _ in range(5):
+        assert np.array_equal(ctx.scan_u32(t).cpu().numpy().astype(np.uint64), ref)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "tiny", "tile_edges"])
+def test_monoids_bit_exact(ctx, name):
+    if name == "c1":
+        sc = S.scene_c1(1)
+    elif name == "c2":
+        sc = S.scene_c2(2)
+    elif name == "tiny":
+        sc = S.single_path_scene([0, 1], [[0, 0], [1, 0]], 1.0)
+    else:
+        # 4096-tag tiles: paths sized so tag counts straddle tile boundaries
+        b = S.SceneBuilder()
+        rng = np.random.default_rng(0)
+        for k, n in enumerate([4094, 1, 4096, 4095, 2, 8191]):
+            pts = np.cumsum(rng.uniform(-3, 3, (n + 1, 2)), 0) + 500
+            b.add_path([0] + [1] * n, pts, k % 3, 0)
+        sc = b.build(S.make_styles([1.0, 2.0, 3.0], S.JOIN_ROUND, S.CAP_BUTT))
+    _say("monoids", name)
+    scene = ctx.encode(sc)
+    e = O.encode(sc)
+    for rep in range(3):  # repeated launches reuse the look-back state
+        m = ctx.monoids(scene).cpu().numpy().view(np.uint32)
+        assert np.array_equal(m, O.monoids(e.tags)), rep
+
+
+# ------------------------------------------------------------- outlines
+def _scene(name):
+    if name == "c1_lines":
+        return S.scene_c1(1)
+    if name == "c1_arcs":
+        return S.scene_c1(1, output_mode=S.OUT_ARCS)
+    if name == "c2_lines":
+        return S.scene_c2(2, n_segments=40000, n_paths=400)
+    if name == "c2_arcs":
+        return S.scene_c2(2, n_segments=40000, n_paths=400, output_mode=S.OUT_ARCS)
+    if name == "c3_arcs":
+        return S.scene_c3(3, n_cubics=3000)
+    if name == "c3_lines":
+        return S.scene_c3(3, n_cubics=3000, output_mode=S.OUT_LINES)
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["c1_lines", "c1_arcs", "c2_lines", "c2_arcs", "c3_arcs", "c3_lines"])
+def test_outline_parity(ctx, name):
+    sc = _scene(name)
+    _say("parity", name, "segments", sc.n_segments())
+    scene, counts, recs = _expand(ctx, sc)
+    ref = O.expand(sc)
+    assert ref.status == 0
+    rep = P.compare(counts, recs, ref, sc.output_mode)
+    _say(name, rep)
+    assert rep.n_unexplained == 0, rep
+    assert rep.worst_endpoint <= P.ENDPOINT_TOL, rep
+    assert rep.worst_sweep <= P.SWEEP_TOL, rep
+    assert rep.bad_path_ids == 0
+    # near-threshold exclusions stay rare
+    assert rep.n_count_mismatch <= max(3, 0.01 * rep.n_tags), rep
+    assert P.closed_per_path(recs) == 0
+
+
+def test_offsets_are_the_scan_of_the_counts(ctx):
+    sc = _scene("c2_lines")
+    scene = ctx.encode(sc)
+    c = ctx.counts(scene).cpu().numpy().astype(np.uint64)
+    o = ctx.offsets(scene).cpu().numpy().astype(np.uint64)
+    assert np.array_equal(o, np.concatenate([[0], np.cumsum(c)]))
+
+
+def test_full_size_c2_counts_and_samples(ctx):
+    """The 1M-segment map scene in the launch configuration the benchmark
+    times: counts of every tag against the oracle (count-only pass) and the
+    records of sampled tags against the oracle run tag by tag."""
+    sc = S.scene_c2(2)
+    _say("full c2: encode")
+    scene, counts, recs = _expand(ctx, sc)
+    _say("full c2: oracle counts")
+    ref = O.expand(sc, emit=False)
+    near = P.near_threshold(ref.margins)
+    mism = counts != ref.counts
+    _say("full c2: tags", len(counts), "mismatch", int(mism.sum()), "near", int(near.sum()))
+    assert not np.any(mism & ~near)
+    assert mism.sum() <= 1e-3 * len(counts)
+    go = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
+    rng = np.random.default_rng(9)
+    sample = np.sort(rng.choice(np.nonzero(~mism)[0], 3000, replace=False))
+    worst = 0.0
+    enc = ref.enc
+    for i in sample:
+        r = O.expand(sc, emit=True, tag_begin=int(i), tag_end=int(i) + 1, enc=enc)
+        g = recs[go[i] : go[i + 1]]
+        o = r.out
+        assert len(o) == len(g)
+        if len(g):
+            d = max(np.max(np.abs(g["x0"] - o["x0"])), np.max(np.abs(g["y0"] - o["y0"])),
+                    np.max(np.abs(g["x1"] - o["x1"])), np.max(np.abs(g["y1"] - o["y1"])))
+            worst = max(worst, float(d))
+            assert np.all(g["path"] == o["path"])
+    _say("full c2: sampled worst endpoint", worst)
+    assert worst <= P.ENDPOINT_TOL
+    assert P.closed_per_path(recs) == 0
+
+
+@pytest.mark.parametrize("name", ["c1_lines", "c3_arcs"])
+def test_gpu_offsets_within_tolerance_of_exact_curve(ctx, name):
+    """Every GPU offset record within tau of the FP64 exact parallel curves
+    (independent dense sampling), on a subset of segments."""
+    import exact_stroke as X
+
+    sc = _scene(name)
+    if name == "c1_lines":
+        sc = sc.subset(range(3))
+    else:
+        sc = S.scene_c3(3, n_cubics=200)
+    scene, counts, recs = _expand(ctx, sc)
+    ref = O.expand(sc)
+    go = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
+    oo = ref.offsets().astype(np.int64)
+    mon = O.monoids(ref.enc.tags)
+    worst = 0.0
+    for i in np.nonzero(((ref.enc.tags & 4) == 0) & (counts == ref.counts))[0]:
+        kinds = ref.out[oo[i] : oo[i + 1]]["kind"]
+        g = recs[go[i] : go[i + 1]][kinds == O.KIND_OFFSET]
+        xf = sc.xforms[ref.enc.xform_stream[mon[3][i]]]
+        w = float(sc.styles[ref.enc.style_stream[mon[2][i]]]["half_width"])
+        P_, W = X.world_segment(ref.enc.data, mon[0][i], ref.enc.tags[i], xf)
+        A, B_, cusps = X.dense_offsets(P_, w, 0.02)
+        refpts = np.concatenate([A, B_] + [X.circle_pts(c, w) for c in cusps])
+        pts, _ = X.sample_outputs(g["x0"].astype(np.float64), g["y0"].astype(np.float64),
+                                  g["x1"].astype(np.float64), g["y1"].astype(np.float64),
+                                  g["curv"].astype(np.float64) if sc.output_mode == S.OUT_ARCS else None, 0.05)
+        worst = max(worst, X.max_dist(pts, refpts)[0])
+    _say(name, "worst distance to exact", worst)
+    assert worst <= sc.tolerance
+
+
+# ------------------------------------------------------ edge behaviour
+def test_too_small_buffer_reports_the_count(ctx):
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    sc = S.scene_c1(1).subset(range(3))
+    scene = ctx.encode(sc)
+    buf = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.StrokexError) as ei:
+        ctx.expand_into(scene, buf.data_ptr(), buf.numel(), sc.tolerance, S.OUT_LINES)
+    assert ei.value.code == B.SX_ETOOSMALL
+    assert ei.value.required > 5
+    assert int(buf.sum()) == 0  # nothing written
+    recs, n, _ = ctx.expand(scene)
+    assert n == ei.value.required
+
+
+def test_repeated_runs_are_bit_identical(ctx):
+    sc = _scene("c1_arcs")
+    _, c1, r1 = _expand(ctx, sc)
+    _, c2, r2 = _expand(ctx, sc)
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(r1.view(np.uint8), r2.view(np.uint8))
+
+
+def test_empty_scene(ctx):
+    sc = S.SceneBuilder().build(S.make_styles([1.0], S.JOIN_ROUND, S.CAP_BUTT))
+    scene = ctx.encode(sc)
+    recs, n, _ = ctx.expand(scene, 0.25, S.OUT_LINES)
+    assert n == 0
+
+
+@pytest.mark.parametrize("bad", ["no_move", "nan", "neg_width", "shear", "bad_style_ix"])
+def test_invalid_inputs_are_rejected(ctx, bad):
+    from paper_2405_00127_amd import binding as B
+
+    verbs, pts, st, xf, six = [0, 1], [[0, 0], [1, 0]], S.make_styles([1.0], 2, 0), S.identity_xforms(), 0
+    if bad == "no_move":
+        verbs, pts = [1], [[1, 0]]
+    elif bad == "nan":
+        pts = [[0, 0], [math.nan, 0]]
+    elif bad == "neg_width":
+        st = S.make_styles([-1.0], 2, 0)
+    elif bad == "shear":
+        xf = np.array([[1, 0, 0.5, 1, 0, 0]], np.float32)
+    else:
+        six = 3
+    b = S.SceneBuilder()
+    b.add_path(verbs, pts, six, 0)
+    sc = b.build(st, xf)
+    with pytest.raises(B.StrokexError) as ei:
+        ctx.encode(sc)
+    assert ei.value.code == B.SX_EINVAL
+    bad_tol = S.single_path_scene([0, 1], [[0, 0], [1, 0]], 1.0)
+    scene = ctx.encode(bad_tol)
+    with pytest.raises(B.StrokexError):
+        ctx.expand(scene, tolerance=0.0)
