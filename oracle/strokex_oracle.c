@@ -102,6 +102,10 @@ typedef struct {
 #endif
 /* G28: lower clamp for the Appendix A chord/arc ratio (only reached by
  * pieces accepted at the depth cap with near-reversed tangents). */
+/* G31: nearly tangent-continuous joins */
+#ifndef OX_SMOOTH_JOIN
+#define OX_SMOOTH_JOIN 1e-5
+#endif
 #ifndef OX_C_MIN
 #define OX_C_MIN 0.1
 #endif
@@ -121,7 +125,7 @@ typedef struct {
     double rho;    /* min |rho| at piece ends                              */
     double q;      /* min ||q|/(eps L) - 1| perturbation decisions         */
     double len;    /* min |hodograph turning test| / scale (reading G29)   */
-    double join;   /* join classification margins                          */
+    double join;   /* join decisions: |cr| distance to its thresholds (abs.) */
     uint32_t n_pieces;
     uint32_t max_depth_hits;
 } ox_margin;
@@ -568,12 +572,27 @@ static uint32_t ceil_count(double n_est) {
     return (uint32_t)ceil(n_est);
 }
 
-/* Cubic point and q = B'/3 */
-static v2 cubic_point(const v2 *P, double t) {
+/* Cubic point B(t) - P0 (evaluated relative to the start point so that
+ * short chords far from the origin keep their precision) and q = B'/3 */
+static v2 cubic_rel(const v2 *P, double t) {
     double mt = 1.0 - t;
-    double a = mt * mt * mt, b = 3.0 * mt * mt * t, c = 3.0 * mt * t * t, d = t * t * t;
-    return v2m(a * P[0].x + b * P[1].x + c * P[2].x + d * P[3].x,
-               a * P[0].y + b * P[1].y + c * P[2].y + d * P[3].y);
+    double b = 3.0 * mt * mt * t, c = 3.0 * mt * t * t, d = t * t * t;
+    v2 d1 = vsub(P[1], P[0]), d2 = vsub(P[2], P[0]), d3 = vsub(P[3], P[0]);
+    return v2m(b * d1.x + c * d2.x + d * d3.x, b * d1.y + c * d2.y + d * d3.y);
+}
+/* B(t0 + dt) - B(t0): a cubic's Taylor expansion terminates, so
+ * B' dt + B'' dt^2 / 2 + B''' dt^3 / 6 is exact algebra; written with
+ * q = B'/3 it keeps the chord's relative precision however short it is. */
+static v2 cubic_chord(const v2 *P, double t0, double dt) {
+    double mt = 1.0 - t0;
+    v2 a = vsub(P[1], P[0]), b = vsub(P[2], P[1]), c = vsub(P[3], P[2]);
+    v2 q0 = v2m(mt * mt * a.x + 2.0 * t0 * mt * b.x + t0 * t0 * c.x,
+                mt * mt * a.y + 2.0 * t0 * mt * b.y + t0 * t0 * c.y);
+    v2 s0 = vsub(b, a), s1 = vsub(c, b); /* B''/6 = (1-t) s0 + t s1 */
+    v2 s2 = v2m(mt * s0.x + t0 * s1.x, mt * s0.y + t0 * s1.y);
+    v2 s3 = vsub(s1, s0);                /* third derivative / 6 */
+    return v2m(3.0 * dt * q0.x + 3.0 * dt * dt * s2.x + dt * dt * dt * s3.x,
+               3.0 * dt * q0.y + 3.0 * dt * dt * s2.y + dt * dt * dt * s3.y);
 }
 static v2 cubic_q(const v2 *P, double t) {
     double mt = 1.0 - t;
@@ -919,12 +938,20 @@ static void emit_cap(ox_sink *k, const ox_cfg *cfg, int cap, v2 p, v2 u, double 
 static void emit_join(ox_sink *k, const ox_cfg *cfg, const ox_style *st, v2 p, v2 ta, v2 tb,
                       double w, ox_margin *m) {
     v2 ua = vunit(ta), ub = vunit(tb);
-    if (veq(ua, ub)) return;
     double cr = vcross(ua, ub), dp = vdot(ua, ub);
-    /* near-reversal: which side is outer hinges on the sign of cr;
-     * near-tangent: whether a join is emitted at all hinges on rounding */
-    margin_min(&m->join, dp < 0.0 ? fabs(cr) : 1e3 * fabs(cr));
     v2 Na = vnormal(ua), Nb = vnormal(ub);
+    /* reading G31: tangents within OX_SMOOTH_JOIN rad of each other close
+     * each side with one straight line and no pivot lines; the wedge left out
+     * is thinner than w * 1e-5.  Which side would be "outer" is then moot. */
+    /* join margins are absolute distances of cr (unit vectors) to a threshold */
+    if (dp > 0.0) margin_min(&m->join, fabs(fabs(cr) - OX_SMOOTH_JOIN));
+    if (dp > 0.0 && fabs(cr) < OX_SMOOTH_JOIN) {
+        sink_line(k, vadd(p, vscale(Na, w)), vadd(p, vscale(Nb, w)), OX_K_JOIN_OUTER);
+        sink_line(k, vadd(p, vscale(Nb, -w)), vadd(p, vscale(Na, -w)), OX_K_JOIN_OUTER);
+        return;
+    }
+    /* near-reversal: which side is outer hinges on the sign of cr */
+    if (dp < 0.0) margin_min(&m->join, fabs(cr));
     /* reading G21: cr == 0 (reversal) counts as a left turn */
     int outerA = !(cr < 0.0);
     double h_out = outerA ? w : -w;
@@ -971,6 +998,7 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
     uint32_t t0_u = 0;
     double dt = 1.0;
     v2 last_p = s->P[0];
+    v2 last_rel = v2m(0.0, 0.0);
     ox_tan last_q = sample_q(s, 0.0, m);
     double hw = s->w;
     double tau_fit = cfg->tau_fit;
@@ -978,9 +1006,10 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
         double t0 = (double)t0_u * dt;
         if (t0 == 1.0) break;
         double t1 = t0 + dt;
-        v2 next_p = (t1 == 1.0) ? s->P[3] : cubic_point(s->P, t1);
+        v2 next_rel = (t1 == 1.0) ? vsub(s->P[3], s->P[0]) : cubic_rel(s->P, t1);
+        v2 next_p = (t1 == 1.0) ? s->P[3] : vadd(s->P[0], next_rel);
         ox_tan next_q = sample_q(s, t1, m);
-        v2 chord = vsub(next_p, last_p);
+        v2 chord = cubic_chord(s->P, t0, dt);
         double cl = vlen(chord);
         double th0 = atan2(vcross(last_q.dir, chord), vdot(last_q.dir, chord));
         double th1 = atan2(vcross(chord, next_q.dir), vdot(chord, next_q.dir));
@@ -1001,7 +1030,9 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
             double ma = last_q.mag * dt, mc = next_q.mag * dt;
             v2 a = vscale(vunit(last_q.dir), ma), c = vscale(vunit(next_q.dir), mc);
             v2 b = vsub(vsub(chord, a), c);
-            if (ma > 0.0 && mc > 0.0 && !vzero(b)) {
+            /* a middle vector that is zero up to rounding leaves only the
+             * turn from a to c, which is below pi: no test */
+            if (ma > 0.0 && mc > 0.0 && vlen(b) > 1e-9 * (ma + mc)) {
                 double hv = vdot(a, b) * mc + vdot(b, c) * ma;
                 double scale = vlen(b) * ma * mc;
                 if (scale > 0.0) margin_min(&m->len, fabs(hv) / scale);
@@ -1055,6 +1086,7 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
             t0_u >>= sh;
             dt *= (double)(1u << sh);
             last_p = next_p;
+            last_rel = next_rel;
             last_q = next_q;
         } else {
             t0_u *= 2;
