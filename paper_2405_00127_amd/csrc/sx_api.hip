@@ -79,18 +79,21 @@ sx::SceneView view(const sx_scene* s) {
     v.path_map = s->d_path_map;
     v.mon = s->d_mon;
     v.n_tags = s->n_tags;
+    v.n_pts = s->n_pts;
+    v.n_styles = s->n_styles;
+    v.n_xforms = s->n_xforms;
+    v.n_paths = s->n_paths;
     return v;
 }
 
 bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
     if (!(tol > 0.0f) || !std::isfinite(tol)) return false;
     if (mode != SX_OUT_LINES && mode != SX_OUT_ARCS) return false;
-    double tf = (double)sx::kFlatFrac * (double)tol;
-    cfg.tau_fit = (float)((double)sx::kFitFrac * (double)tol);
-    cfg.tau_flat = (float)tf;
-    cfg.inv_sqrt8tf = (float)std::sqrt(1.0 / (8.0 * tf));
-    cfg.cbrt_inv120tf = (float)std::cbrt(1.0 / (120.0 * tf));
-    cfg.round_step = 0.0f;
+    double tf = sx::kFlatFrac * (double)tol;
+    cfg.tau_fit = sx::kFitFrac * (double)tol;
+    cfg.tau_flat = tf;
+    cfg.inv_sqrt8tf = std::sqrt(1.0 / (8.0 * tf));
+    cfg.cbrt_inv120tf = std::cbrt(1.0 / (120.0 * tf));
     cfg.arcs = mode == SX_OUT_ARCS;
     cfg.paper_fit = 0;
     return true;

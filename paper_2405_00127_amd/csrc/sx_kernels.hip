@@ -23,14 +23,16 @@ namespace sx {
 // by the last tile of every launch) makes stale flags of earlier launches
 // read as "not ready", so nothing has to be cleared between launches and the
 // kernels can be replayed inside a HIP graph.
+// The aggregate and the inclusive prefix live in separate words: a reader
+// that saw "aggregate ready" must never pick up a later inclusive value.
 struct TileStatus {
     uint32_t flag;
     uint32_t pad;
-    uint64_t a;
-    uint64_t b;
-    uint64_t pad2;
+    uint64_t agg_a, agg_b;
+    uint64_t inc_a, inc_b;
+    uint64_t pad2[3];
 };
-static_assert(sizeof(TileStatus) == 32, "tile status layout");
+static_assert(sizeof(TileStatus) == 64, "tile status layout");
 
 struct Pair {
     uint64_t a, b;
@@ -87,8 +89,13 @@ __device__ __forceinline__ void store_release(uint32_t* p, uint32_t v) {
 
 // Publish a tile's value with its state (data first, then the flag).
 __device__ __forceinline__ void publish(TileStatus* st, uint32_t tile, uint32_t epoch, uint32_t state, Pair v) {
-    st[tile].a = v.a;
-    st[tile].b = v.b;
+    if (state == 1) {
+        st[tile].agg_a = v.a;
+        st[tile].agg_b = v.b;
+    } else {
+        st[tile].inc_a = v.a;
+        st[tile].inc_b = v.b;
+    }
     __threadfence();
     store_release(&st[tile].flag, (epoch << 2) | state);
 }
@@ -121,9 +128,12 @@ __device__ Pair look_back(TileStatus* st, uint32_t tile, uint32_t epoch, int lan
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (idx >= 0) {
-            v.a = __hip_atomic_load(&st[idx].a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v.b = __hip_atomic_load(&st[idx].b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (idx >= 0 && state == 1u) {
+            v.a = __hip_atomic_load(&st[idx].agg_a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v.b = __hip_atomic_load(&st[idx].agg_b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (idx >= 0 && state == 2u) {
+            v.a = __hip_atomic_load(&st[idx].inc_a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v.b = __hip_atomic_load(&st[idx].inc_b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         uint64_t incl_mask = __ballot(state >= 2u);
         if (incl_mask) {
@@ -312,8 +322,10 @@ __global__ __launch_bounds__(kTagBlock) void emit_kernel(SceneView sv, Cfg cfg, 
     uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
     if (i >= sv.n_tags) return;
     if (offsets[sv.n_tags] > capacity_records) return;  // caller reads the count
-    uint32_t path = sv.path_map[sv.mon[(size_t)sv.n_tags + i]];
-    WriteSink k{out, offsets[i], offsets[i + 1], path, cfg.arcs, 0};
+    uint32_t pi = sv.mon[(size_t)sv.n_tags + i];
+    uint32_t path = pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
+    uint64_t end = offsets[i + 1] < capacity_records ? offsets[i + 1] : capacity_records;
+    WriteSink k{out, offsets[i], end, path, cfg.arcs, 0};
     process_tag(k, cfg, sv, i);
 }
 

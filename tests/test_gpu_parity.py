@@ -2,8 +2,9 @@
 
 Bars: encoding and monoids bit-exact; output offsets bit-exact where the
 counts agree; counts identical except at oracle decisions within the margin
-thresholds of ``parity``; endpoints within 1e-3 px; arcs' sweep within
-2e-3 rad; path ids equal; outlines closed bit-exactly per path."""
+thresholds of ``parity`` (1e-9: both sides decide in FP64); endpoints within
+1e-3 px; arcs' bulge within 1e-3 px; path ids equal; outlines closed
+bit-exactly per path."""
 import math
 import sys
 
