@@ -161,6 +161,19 @@ int sx_debug_counts(sx_ctx *ctx, const sx_scene *scene, float tolerance, int out
 int sx_debug_offsets(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode,
                      uint64_t *offsets_dev, void *stream);
 
+/* The four phases of sx_expand_async, one kernel each, for per-kernel timing:
+ *   SX_PHASE_SCAN_TAGS   tag-monoid scan (Section 8.2)
+ *   SX_PHASE_COUNT       per-tag record counts (Algorithms 1-2, counting)
+ *   SX_PHASE_SCAN_COUNTS exclusive scan of the counts into output offsets
+ *   SX_PHASE_EMIT        records written at their offsets
+ * Run in this order on one stream they equal sx_expand_async without the
+ * final count copy.  out_dev / out_capacity_bytes are used by SX_PHASE_EMIT
+ * only (nothing is written when the total exceeds the capacity).
+ * Errors: SX_EINVAL (bad phase, tolerance or mode), SX_EDEVICE. */
+enum { SX_PHASE_SCAN_TAGS = 0, SX_PHASE_COUNT = 1, SX_PHASE_SCAN_COUNTS = 2, SX_PHASE_EMIT = 3 };
+int sx_run_phase(sx_ctx *ctx, const sx_scene *scene, int phase, float tolerance, int output_mode, void *out_dev,
+                 uint64_t out_capacity_bytes, void *stream);
+
 /* Scan primitive on its own: exclusive prefix sum of n uint32 values into
  * n + 1 uint64 (device pointers), single-pass decoupled look-back. */
 int sx_scan_u32(sx_ctx *ctx, const uint32_t *in_dev, uint64_t *out_dev, uint32_t n, void *stream);

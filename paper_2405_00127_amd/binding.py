@@ -22,6 +22,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "strokex.h")
 
 SX_OK, SX_EINVAL, SX_ENOMEM, SX_EDEVICE, SX_ETOOSMALL, SX_EBUSY = 0, -1, -2, -3, -4, -5
 OUT_LINES, OUT_ARCS = 0, 1
+PHASE_SCAN_TAGS, PHASE_COUNT, PHASE_SCAN_COUNTS, PHASE_EMIT = 0, 1, 2, 3
+PHASE_NAMES = ["scan_tags", "count", "scan_counts", "emit"]
 RECORD_BYTES = {OUT_LINES: 20, OUT_ARCS: 24}
 
 LINE_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("path", "<u4")])
@@ -72,6 +74,7 @@ def lib():
                 "sx_debug_counts": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
                 "sx_debug_offsets": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
                 "sx_scan_u32": (C.c_int, [vp, vp, vp, u32, vp]),
+                "sx_run_phase": (C.c_int, [vp, vp, C.c_int, C.c_float, C.c_int, vp, u64, vp]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -210,6 +213,12 @@ class Context:
                     raise
                 out = torch.empty(int(e.required * 1.25 + 1) * rec, dtype=torch.uint8, device=out.device)
         return out[: n * rec].view(torch.float32).view(-1, rec // 4), n, out
+
+    def run_phase(self, scene: Scene, phase: int, tolerance: float, mode: int, out_ptr: int = 0,
+                  capacity_bytes: int = 0, stream=None):
+        rc = lib().sx_run_phase(C.c_void_p(self.h), C.c_void_p(scene.h), int(phase), float(tolerance), int(mode),
+                                C.c_void_p(out_ptr), int(capacity_bytes), _stream_ptr(stream))
+        self._check(rc, "sx_run_phase")
 
     def monoids(self, scene: Scene, stream=None):
         import torch

@@ -302,6 +302,38 @@ int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mo
     return SX_OK;
 }
 
+int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int output_mode, void* out_dev,
+                 uint64_t out_capacity_bytes, void* stream) {
+    if (!ctx || !s) return SX_EINVAL;
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (s->n_tags == 0) return SX_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const_cast<sx_scene*>(s)->last_stream = st;
+    char* ctl = (char*)s->d_scan_ctl;
+    const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
+    hipError_t e;
+    switch (phase) {
+        case SX_PHASE_SCAN_TAGS:
+            e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, st);
+            break;
+        case SX_PHASE_COUNT:
+            e = sx::launch_count(view(s), cfg, s->d_counts, st);
+            break;
+        case SX_PHASE_SCAN_COUNTS:
+            e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
+                                       s->d_status_counts, st);
+            break;
+        case SX_PHASE_EMIT:
+            if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
+            e = sx::launch_emit(view(s), cfg, s->d_offsets, out_dev, out_capacity_bytes / rec, st);
+            break;
+        default:
+            return fail(ctx, SX_EINVAL, "bad phase");
+    }
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "phase launch");
+}
+
 int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void* stream) {
     if (!ctx || !s || (!out4xn_dev && s->n_tags)) return SX_EINVAL;
     hipStream_t st = (hipStream_t)stream;
