@@ -1095,6 +1095,33 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
     }
 }
 
+/* Reading G32: a line segment is exactly straight, so it is its own Euler
+ * spiral piece: k0 = k1 = 0, arc length equal to the chord, tangent angle of
+ * the chord.  The subdivision and fit test are skipped; on a line they would
+ * only measure rounding noise (angles of order 1e-16 that leave the counts
+ * unchanged but give arcs a curvature of that order). */
+static void straight_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_margin *m) {
+    ox_es es;
+    v2 chord = vsub(s->P[3], s->P[0]);
+    es.pivot = 0;
+    es.p0 = s->P[0];
+    es.p1 = s->P[3];
+    es.n0 = vnormal(vunit(s->t_start));
+    es.n1 = es.n0;
+    es.k0 = 0.0;
+    es.k1 = 0.0;
+    es.rot = chord;
+    es.base = atan2(chord.y, chord.x);
+    es.L = vlen(chord);
+    m->n_pieces++;
+    if (k->emit) {
+        ox_piece pc = {0.0, 1.0, 0.0, 0.0, es.L, es.L, 0.0, 0.0, s->tag, 0u};
+        piece_push(k->r, &pc);
+    }
+    emit_side(k, cfg, &es, +s->w, m);
+    emit_side(k, cfg, &es, -s->w, m);
+}
+
 /* ---- segment fetch (Section 8.1: degree elevation) --------------------- */
 
 static v2 xf_apply(const float *X, double x, double y) {
@@ -1201,7 +1228,8 @@ ox_res *ox_expand(const ox_enc *e, const ox_style *styles, uint32_t n_styles,
             s.t_start = first_nonzero(cs, (int)c);
             s.t_end = first_nonzero(ce, (int)c);
             s.lpoly = vlen(vsub(s.P[1], s.P[0])) + vlen(vsub(s.P[2], s.P[1])) + vlen(vsub(s.P[3], s.P[2]));
-            process_segment(&sk, &cfg, &s, m);
+            if (c == 1) straight_segment(&sk, &cfg, &s, m);
+            else process_segment(&sk, &cfg, &s, m);
             /* join or end cap with the neighbour at i + 1 (Algorithm 1) */
             uint8_t nt = e->tags[i + 1];
             v2 pend = raw[c];
