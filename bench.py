@@ -122,7 +122,7 @@ def main():
     tol = sc.tolerance
     # size the output once (not timed)
     recs, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)
-    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     log(f"bench: {n_seg} segments, {scene.n_tags} tags -> {n_rec} records")
 
@@ -137,7 +137,7 @@ def main():
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    assert int(cnt.item()) == n_rec
+    assert int(cnt[0].item()) == n_rec and int(cnt[1].item()) == 0
     ms = (t1 - t0) * 1e3 / args.steps
     log(f"bench: {ms:.3f} ms/step")
 
@@ -158,10 +158,10 @@ def main():
     log("bench: phases " + ", ".join(f"{names[p]} {phase_ms[p]:.3f} ms" for p in range(nph)))
 
     n_tags = scene.n_tags
-    if names[dom] == "emit":
+    if names[dom] == "records":
         flops = n_rec * FLOPS_PER_RECORD[mode]
         achieved = flops / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "emit", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+        roof = {"kernel": "records", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                 "units_per_launch": {"records": n_rec}, "flops_per_record": FLOPS_PER_RECORD[mode]}
     elif names[dom] in ("scan_tags", "scan_counts"):
@@ -174,7 +174,7 @@ def main():
         # the per-point work; its algorithmic work is charged per record too
         flops = n_rec * FLOPS_PER_RECORD[mode]
         achieved = flops / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "count", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+        roof = {"kernel": "pieces", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
     roof["phase_ms"] = {names[p]: phase_ms[p] for p in range(nph)}
     roof["emit_hbm_GBps"] = (n_rec * RECORD_BYTES[mode] + n_tags * 48) / (phase_ms[3] * 1e-3) / 1e9

@@ -127,25 +127,33 @@ int sx_scene_info(const sx_scene *scene, uint32_t *n_tags, uint32_t *n_pts, uint
  * Synchronous. */
 int sx_scene_download(const sx_scene *scene, uint8_t *tags, float *data, uint32_t *path_map);
 
-/* Expand a scene: tag-monoid scan, per-segment output counts, exclusive scan
- * of the counts (output offsets), emission of the outline in canonical order
- * (by tag; within a tag: Euler spiral pieces in parameter order, side A
- * (right, p + wN) then side B, then the join or cap).
+/* Expand a scene: tag-monoid scan, per-segment decisions writing emission
+ * items and per-tag record counts, exclusive scan of the counts (output
+ * offsets), records written at their offsets in canonical order (by tag;
+ * within a tag: Euler spiral pieces in parameter order, side A (right,
+ * p + wN) then side B, then the join or cap).
  *   tolerance  > 0, in output units (pixels), Frechet-style bound;
  *   output_mode SX_OUT_LINES (sx_line records) or SX_OUT_ARCS (sx_arc);
  *   out_dev    device memory, out_capacity_bytes bytes, caller-owned;
  *   out_count  host pointer, receives the number of records.
  * If the outline needs more than out_capacity_bytes, nothing is written,
  * *out_count holds the required record count and SX_ETOOSMALL is returned
- * (retry with a larger buffer).  Blocks the host until the count is known.
- * Errors: SX_EINVAL (tolerance not finite and > 0, bad mode), SX_EDEVICE. */
+ * (retry with a larger buffer).  The scene's item workspace (device memory
+ * owned by the scene) grows here when a scene needs more items than it
+ * holds.  Blocks the host until the count is known.
+ * Errors: SX_EINVAL (tolerance not finite and > 0, bad mode), SX_ENOMEM,
+ * SX_EDEVICE. */
 int sx_expand(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, void *out_dev,
               uint64_t out_capacity_bytes, uint64_t *out_count, void *stream);
 
-/* Same pipeline without any host synchronisation (capturable in a HIP graph):
- * the record count is written to device memory *out_count_dev (uint64_t);
- * when it exceeds the capacity nothing is emitted and the count is still
- * written, so the caller can compare it with the capacity afterwards. */
+/* Same pipeline without any host synchronisation or allocation (capturable
+ * in a HIP graph).  out_count_dev: device memory, two uint64_t:
+ *   [0] the record count (always written);
+ *   [1] 0 on success, else the number of items the scene's workspace must
+ *       hold: it was too small, nothing was emitted; one sx_expand call with
+ *       the same tolerance and mode resizes it.
+ * When [0] exceeds the capacity nothing is emitted either; the caller
+ * compares it with the capacity afterwards. */
 int sx_expand_async(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, void *out_dev,
                     uint64_t out_capacity_bytes, uint64_t *out_count_dev, void *stream);
 
@@ -163,14 +171,15 @@ int sx_debug_offsets(sx_ctx *ctx, const sx_scene *scene, float tolerance, int ou
 
 /* The four phases of sx_expand_async, one kernel each, for per-kernel timing:
  *   SX_PHASE_SCAN_TAGS   tag-monoid scan (Section 8.2)
- *   SX_PHASE_COUNT       per-tag record counts (Algorithms 1-2, counting)
+ *   SX_PHASE_PIECES      per-segment decisions (Algorithms 1-2) in FP64:
+ *                        emission items and per-tag record counts
  *   SX_PHASE_SCAN_COUNTS exclusive scan of the counts into output offsets
- *   SX_PHASE_EMIT        records written at their offsets
+ *   SX_PHASE_RECORDS     per item, records written at their offsets
  * Run in this order on one stream they equal sx_expand_async without the
- * final count copy.  out_dev / out_capacity_bytes are used by SX_PHASE_EMIT
- * only (nothing is written when the total exceeds the capacity).
- * Errors: SX_EINVAL (bad phase, tolerance or mode), SX_EDEVICE. */
-enum { SX_PHASE_SCAN_TAGS = 0, SX_PHASE_COUNT = 1, SX_PHASE_SCAN_COUNTS = 2, SX_PHASE_EMIT = 3 };
+ * final count copy.  out_dev / out_capacity_bytes are used by
+ * SX_PHASE_RECORDS only (nothing is written when the total exceeds the
+ * capacity).  Errors: SX_EINVAL (bad phase, tolerance or mode), SX_EDEVICE. */
+enum { SX_PHASE_SCAN_TAGS = 0, SX_PHASE_PIECES = 1, SX_PHASE_SCAN_COUNTS = 2, SX_PHASE_RECORDS = 3 };
 int sx_run_phase(sx_ctx *ctx, const sx_scene *scene, int phase, float tolerance, int output_mode, void *out_dev,
                  uint64_t out_capacity_bytes, void *stream);
 

@@ -22,8 +22,8 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "strokex.h")
 
 SX_OK, SX_EINVAL, SX_ENOMEM, SX_EDEVICE, SX_ETOOSMALL, SX_EBUSY = 0, -1, -2, -3, -4, -5
 OUT_LINES, OUT_ARCS = 0, 1
-PHASE_SCAN_TAGS, PHASE_COUNT, PHASE_SCAN_COUNTS, PHASE_EMIT = 0, 1, 2, 3
-PHASE_NAMES = ["scan_tags", "count", "scan_counts", "emit"]
+PHASE_SCAN_TAGS, PHASE_PIECES, PHASE_SCAN_COUNTS, PHASE_RECORDS = 0, 1, 2, 3
+PHASE_NAMES = ["scan_tags", "pieces", "scan_counts", "records"]
 RECORD_BYTES = {OUT_LINES: 20, OUT_ARCS: 24}
 
 LINE_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("path", "<u4")])
@@ -187,6 +187,7 @@ class Context:
 
     def expand_async(self, scene: Scene, out_ptr: int, capacity_bytes: int, count_dev_ptr: int, tolerance: float,
                      mode: int, stream=None):
+        """count_dev_ptr: two device uint64 (records; 0 or the item workspace needed)."""
         rc = lib().sx_expand_async(C.c_void_p(self.h), C.c_void_p(scene.h), float(tolerance), int(mode),
                                    C.c_void_p(out_ptr), int(capacity_bytes), C.c_void_p(count_dev_ptr),
                                    _stream_ptr(stream))

@@ -1,6 +1,7 @@
 // C ABI of the strokex library (declared in include/strokex.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -16,7 +17,7 @@
 struct sx_ctx {
     int device = 0;
     std::string err;
-    uint64_t* pinned_total = nullptr;  // host-pinned u64 for the record count
+    uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, items needed
 };
 
 struct sx_scene {
@@ -33,10 +34,20 @@ struct sx_scene {
     void* d_scan_ctl = nullptr;  // two control blocks (tags, counts)
     void* d_status_tags = nullptr;
     void* d_status_counts = nullptr;
+    // item workspace of the piece / record kernels
+    sx::Item* d_items = nullptr;
+    uint32_t* d_tile_n = nullptr;
+    sx::WsCtl* d_ws_ctl = nullptr;
+    uint32_t region_cap = 0;  // slots per piece tile
+    uint64_t ovf_cap = 0;     // shared overflow slots
+    uint32_t chunk_k = 16;    // records per item chunk
     hipStream_t last_stream = nullptr;
 };
 
 namespace {
+
+constexpr uint32_t kRegionPerTag = 8;      // initial item slots per tag
+constexpr uint64_t kMinOverflow = 65536;   // initial shared overflow slots (minimum)
 
 int fail(sx_ctx* ctx, int code, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -54,8 +65,9 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void free_scene(sx_scene* s) {
     if (!s) return;
-    void* bufs[] = {s->d_tags, s->d_pts, s->d_styles, s->d_xforms, s->d_path_map, s->d_mon,
-                    s->d_counts, s->d_offsets, s->d_scan_ctl, s->d_status_tags, s->d_status_counts};
+    void* bufs[] = {s->d_tags,     s->d_pts,           s->d_styles,        s->d_xforms, s->d_path_map,
+                    s->d_mon,      s->d_counts,        s->d_offsets,       s->d_scan_ctl, s->d_status_tags,
+                    s->d_status_counts, s->d_items,    s->d_tile_n,        s->d_ws_ctl};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete s;
@@ -86,6 +98,28 @@ sx::SceneView view(const sx_scene* s) {
     return v;
 }
 
+sx::ItemWs workspace(const sx_scene* s) {
+    sx::ItemWs w;
+    w.items = s->d_items;
+    w.tile_n = s->d_tile_n;
+    w.ctl = s->d_ws_ctl;
+    w.region_cap = s->region_cap;
+    w.ovf_base = (uint64_t)sx::piece_tiles(s->n_tags) * s->region_cap;
+    w.ovf_cap = s->ovf_cap;
+    return w;
+}
+
+// (Re)allocate the item workspace: region_per_tag slots per tag in each
+// piece tile's region plus ovf shared slots.  The caller has synchronised.
+hipError_t size_workspace(sx_scene* s, uint32_t region_per_tag, uint64_t ovf) {
+    if (s->d_items) (void)hipFree(s->d_items);
+    s->d_items = nullptr;
+    s->region_cap = region_per_tag * sx::tag_block();
+    s->ovf_cap = ovf;
+    const uint64_t slots = (uint64_t)sx::piece_tiles(s->n_tags) * s->region_cap + ovf;
+    return dalloc(&s->d_items, slots * sizeof(sx::Item));
+}
+
 bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
     if (!(tol > 0.0f) || !std::isfinite(tol)) return false;
     if (mode != SX_OUT_LINES && mode != SX_OUT_ARCS) return false;
@@ -96,19 +130,34 @@ bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
     cfg.cbrt_inv120tf = std::cbrt(1.0 / (120.0 * tf));
     cfg.arcs = mode == SX_OUT_ARCS;
     cfg.paper_fit = 0;
+    cfg.K = 16;
     return true;
 }
 
-// tag scan + count + count scan
+// tag scan + pieces + count scan
 int run_counts(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, hipStream_t st) {
     hipError_t e;
     char* ctl = (char*)s->d_scan_ctl;
-    if ((e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, st)) != hipSuccess)
+    if ((e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st)) !=
+        hipSuccess)
         return hip_fail(ctx, e, "scan_tags launch");
-    if ((e = sx::launch_count(view(s), cfg, s->d_counts, st)) != hipSuccess) return hip_fail(ctx, e, "count launch");
+    if ((e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, st)) != hipSuccess)
+        return hip_fail(ctx, e, "pieces launch");
     if ((e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
                                     s->d_status_counts, st)) != hipSuccess)
         return hip_fail(ctx, e, "scan_counts launch");
+    return SX_OK;
+}
+
+// the whole pipeline; dst (device) receives {records, items needed or 0}
+int run_all(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, void* out, uint64_t cap_records, uint64_t* dst,
+            hipStream_t st) {
+    int r = run_counts(ctx, s, cfg, st);
+    if (r != SX_OK) return r;
+    hipError_t e = sx::launch_records(view(s), workspace(s), cfg.arcs, s->d_offsets, out, cap_records, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "records launch");
+    e = sx::launch_finish(s->d_offsets, s->n_tags, workspace(s), dst, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "finish launch");
     return SX_OK;
 }
 
@@ -127,7 +176,7 @@ int sx_ctx_create(int device, sx_ctx** out) {
     if (!c) return SX_ENOMEM;
     c->device = device;
     if (hipSetDevice(device) != hipSuccess) { delete c; return SX_EDEVICE; }
-    if (hipHostMalloc((void**)&c->pinned_total, sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->pinned_total, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return SX_ENOMEM;
     }
@@ -199,6 +248,9 @@ int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, 
     A(dalloc(&s->d_scan_ctl, 2 * sx::scan_ctl_bytes()));
     A(dalloc(&s->d_status_tags, sx::scan_status_bytes(s->n_tags)));
     A(dalloc(&s->d_status_counts, sx::scan_status_bytes(s->n_tags)));
+    A(dalloc(&s->d_tile_n, (size_t)sx::piece_tiles(s->n_tags) * sizeof(uint32_t)));
+    A(dalloc(&s->d_ws_ctl, sizeof(sx::WsCtl)));
+    A(size_workspace(s, kRegionPerTag, std::max<uint64_t>(s->n_tags, kMinOverflow)));
     if (e != hipSuccess) {
         free_scene(s);
         return hip_fail(ctx, e, "scene allocation");
@@ -207,6 +259,7 @@ int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, 
     A(hipMemsetAsync(s->d_scan_ctl, 0, 2 * sx::scan_ctl_bytes(), st));
     A(hipMemsetAsync(s->d_status_tags, 0, sx::scan_status_bytes(s->n_tags), st));
     A(hipMemsetAsync(s->d_status_counts, 0, sx::scan_status_bytes(s->n_tags), st));
+    A(hipMemsetAsync(s->d_ws_ctl, 0, sizeof(sx::WsCtl), st));
     if (s->n_tags) A(hipMemcpyAsync(s->d_tags, enc.tags.data(), s->n_tags, hipMemcpyHostToDevice, st));
     if (s->n_pts)
         A(hipMemcpyAsync(s->d_pts, enc.data.data(), enc.data.size() * sizeof(float), hipMemcpyHostToDevice, st));
@@ -265,18 +318,13 @@ int sx_expand_async(sx_ctx* ctx, const sx_scene* scene, float tolerance, int out
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(scene)->last_stream = st;
+    cfg.K = scene->chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     if (scene->n_tags == 0) {
-        hipError_t e = hipMemsetAsync(out_count_dev, 0, sizeof(uint64_t), st);
+        hipError_t e = hipMemsetAsync(out_count_dev, 0, 2 * sizeof(uint64_t), st);
         return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
     }
-    int r = run_counts(ctx, scene, cfg, st);
-    if (r != SX_OK) return r;
-    hipError_t e = sx::launch_emit(view(scene), cfg, scene->d_offsets, out_dev, out_capacity_bytes / rec, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "emit launch");
-    e = sx::launch_copy_total(scene->d_offsets, scene->n_tags, out_count_dev, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "count copy");
-    return SX_OK;
+    return run_all(ctx, scene, cfg, out_dev, out_capacity_bytes / rec, out_count_dev, st);
 }
 
 int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mode, void* out_dev,
@@ -286,18 +334,31 @@ int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mo
     if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     hipStream_t st = (hipStream_t)stream;
-    const_cast<sx_scene*>(scene)->last_stream = st;
+    sx_scene* s = const_cast<sx_scene*>(scene);
+    s->last_stream = st;
+    cfg.K = s->chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     *out_count = 0;
-    if (scene->n_tags == 0) return SX_OK;
-    int r = run_counts(ctx, scene, cfg, st);
-    if (r != SX_OK) return r;
-    hipError_t e = sx::launch_emit(view(scene), cfg, scene->d_offsets, out_dev, out_capacity_bytes / rec, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "emit launch");
-    e = hipMemcpyAsync(ctx->pinned_total, scene->d_offsets + scene->n_tags, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "count readback");
-    *out_count = *ctx->pinned_total;
+    if (s->n_tags == 0) return SX_OK;
+    // the second attempt has a workspace sized from the first one's request
+    // and cannot overflow (the item count is a deterministic function of the
+    // scene, tolerance and mode)
+    for (int attempt = 0; attempt < 2; attempt++) {
+        uint64_t* dev2 = (uint64_t*)s->d_ws_ctl->result;
+        int r = run_all(ctx, s, cfg, out_dev, out_capacity_bytes / rec, dev2, st);
+        if (r != SX_OK) return r;
+        hipError_t e = hipMemcpyAsync(ctx->pinned_total, dev2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "count readback");
+        const uint64_t need = ctx->pinned_total[1];
+        *out_count = ctx->pinned_total[0];
+        if (need == 0) break;
+        if (attempt == 1) return fail(ctx, SX_EDEVICE, "item workspace overflow after resizing");
+        const uint64_t per_tag = (need * 5 / 4 + s->n_tags - 1) / s->n_tags;
+        const uint32_t region = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per_tag, kRegionPerTag), 256);
+        e = size_workspace(s, region, need);
+        if (e != hipSuccess) return hip_fail(ctx, e, "item workspace allocation");
+    }
     if (*out_count > out_capacity_bytes / rec) return fail(ctx, SX_ETOOSMALL, "output buffer too small");
     return SX_OK;
 }
@@ -308,6 +369,7 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
     sx::Cfg cfg;
     if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (s->n_tags == 0) return SX_OK;
+    cfg.K = s->chunk_k;
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(s)->last_stream = st;
     char* ctl = (char*)s->d_scan_ctl;
@@ -315,18 +377,19 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
     hipError_t e;
     switch (phase) {
         case SX_PHASE_SCAN_TAGS:
-            e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, st);
+            e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
             break;
-        case SX_PHASE_COUNT:
-            e = sx::launch_count(view(s), cfg, s->d_counts, st);
+        case SX_PHASE_PIECES:
+            e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, st);
             break;
         case SX_PHASE_SCAN_COUNTS:
             e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
                                        s->d_status_counts, st);
             break;
-        case SX_PHASE_EMIT:
+        case SX_PHASE_RECORDS:
             if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
-            e = sx::launch_emit(view(s), cfg, s->d_offsets, out_dev, out_capacity_bytes / rec, st);
+            e = sx::launch_records(view(s), workspace(s), cfg.arcs, s->d_offsets, out_dev, out_capacity_bytes / rec,
+                                   st);
             break;
         default:
             return fail(ctx, SX_EINVAL, "bad phase");
@@ -338,7 +401,7 @@ int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void*
     if (!ctx || !s || (!out4xn_dev && s->n_tags)) return SX_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     char* ctl = (char*)s->d_scan_ctl;
-    hipError_t e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, st);
+    hipError_t e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, nullptr, st);
     if (e == hipSuccess && s->n_tags)
         e = hipMemcpyAsync(out4xn_dev, s->d_mon, 4 * (size_t)s->n_tags * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "monoids");
@@ -350,6 +413,7 @@ int sx_debug_counts(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_
     sx::Cfg cfg;
     if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (s->n_tags == 0) return SX_OK;
+    cfg.K = s->chunk_k;
     hipStream_t st = (hipStream_t)stream;
     int r = run_counts(ctx, s, cfg, st);
     if (r != SX_OK) return r;
@@ -368,6 +432,7 @@ int sx_debug_offsets(sx_ctx* ctx, const sx_scene* s, float tolerance, int output
         hipError_t e = hipMemsetAsync(offsets_dev, 0, sizeof(uint64_t), st);
         return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
     }
+    cfg.K = s->chunk_k;
     int r = run_counts(ctx, s, cfg, st);
     if (r != SX_OK) return r;
     hipError_t e = hipMemcpyAsync(offsets_dev, s->d_offsets, ((size_t)s->n_tags + 1) * sizeof(uint64_t),

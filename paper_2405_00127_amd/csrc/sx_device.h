@@ -1,18 +1,20 @@
 // Device-side math of the stroke-expansion hot path (gfx950, wave64).
 //
-// One function template, process_tag<Sink>, runs the whole per-segment
-// computation; the count kernel instantiates it with a counting sink and
-// the emit kernel with a writing sink, so both passes take bit-identical
-// decisions (the library is built with -ffp-contract=off; every FMA here
-// is explicit).
+// Two stages share this header.  The piece stage, process_tag, runs the
+// per-segment decisions of one tag (Algorithm 1 / Algorithm 2) and writes
+// compact emission items: one per parallel-curve range, per evolute bundle
+// and per join or cap, each split into chunks of at most K records, with the
+// tag's record count.  The record stage, emit_item, expands one item chunk
+// into output records at their final positions.
 //
 // Precision split.  CDNA4 issues FP64 vector FMA at the FP32 (unpacked)
 // rate, so everything that *decides* -- the bisection and its fit estimate,
 // the Euler spiral parameters, parallel-curve cusp splits, every count,
 // join classification -- runs in FP64 from the exact FP32 inputs, once per
 // piece.  The per-output-point work (spiral position, normal, offset and
-// evolute points) runs in FP32 from the FP64 piece parameters; outputs are
-// FP32 records.
+// evolute points) runs in FP32 from the piece parameters; outputs are FP32
+// records.  The library is built with -ffp-contract=off; every FMA here is
+// explicit.
 //
 // Paper: Levien & Uguray, "GPU-friendly Stroke Expansion" (arXiv:2405.00127).
 #pragma once
@@ -208,6 +210,12 @@ SX_FN V2 evolute_end(const ES& es, bool at_end) {
     return f32(p - n * (es.L / kn));
 }
 
+// FP32 copies of an ES for the record pass: p0, chord/Z(1), p1 - p0, k0, k1, L, base
+SX_FN void set_es_f(const ES& es, float* d) {
+    d[0] = es.fp0.x; d[1] = es.fp0.y; d[2] = es.frot.x; d[3] = es.frot.y; d[4] = es.fd.x; d[5] = es.fd.y;
+    d[6] = es.fk0; d[7] = es.fk1; d[8] = es.fL; d[9] = es.fbase;
+}
+
 // ------------------------------------------- subdivision density integral
 // x = -1 - 2 h kappa maps the ES inflection to -1 and the parallel-curve
 // cusp to +1 (Section 4.1).  A point on this axis keeps x and, precisely,
@@ -286,6 +294,30 @@ SX_HD inline int split_x(XP xa, XP xb, double dx_total, XSeg* segs) {
     return n + 1;
 }
 
+// Total F increment over [xa, xb]: the sum of split_x's pieces, in the same
+// order and arithmetic, without storing them.
+SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total) {
+    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
+    double dF = 0.0;
+    int n = 0;
+    XP cur = xa;
+    bool up = xb.x > xa.x;
+    for (int kk = 0; kk < 6; kk++) {
+        int k = up ? kk : 5 - kk;
+        bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
+        if (inside) {
+            XP nb = bp_xp(bps[k]);
+            double l = bps[k] - cur.x;
+            dF += branch_dd(branch_of(fabs(cur.x + 0.5 * l)), cur, nb, l) * l;
+            cur = nb;
+            n++;
+        }
+    }
+    double l = (n == 0) ? dx_total : xb.x - cur.x;
+    int br = (n == 0) ? branch_of(fabs(0.5 * (xa.x + xb.x))) : branch_of(fabs(cur.x + 0.5 * l));
+    return dF + branch_dd(br, cur, xb, l) * l;
+}
+
 // Fraction of a branch segment at which F has risen by f * seg.dF
 // (local, cancellation-free inverse of f_approx; FP32 per output point).
 SX_HD inline float branch_inv_frac(const XSeg& s, float f) {
@@ -340,59 +372,120 @@ SX_FN uint32_t ceil_count(double n_est) {
     return (uint32_t)ceil(n_est);
 }
 
-// ------------------------------------------------------------- the sink
-// Counting sink: only counts.  Writing sink: writes records at base + n.
-struct CountSink {
-    uint32_t n;
-    SX_FN void line(V2, V2) { n++; }
-    SX_FN void arc(V2, V2, float) { n++; }
-    SX_FN void skip(uint32_t k) { n += k; }
-    static constexpr bool kEmit = false;
-};
+// ------------------------------------------------------------- items
+// The piece pass turns each tag into emission items in canonical order:
+// one per parallel-curve range (offset lines / arcs), one per reversed
+// range's evolute bundle (evolute twice + connecting lines), one per join or
+// cap.  Items longer than K records are split into chunks of K.  The record
+// pass then runs one thread per item: FP32 per-point work only, at most K
+// records each, so the load is balanced and the register footprint small.
+enum { kItemOffset = 1, kItemEvolute = 2, kItemJoin = 3 };
+// item header flags (bits 4..)
+constexpr uint32_t kIfDirNeg = 1u << 4;     // offset: records run backwards in u
+constexpr uint32_t kIfArcs = 1u << 5;       // arc records
+constexpr uint32_t kIfPivot = 1u << 6;      // ES is a pivot (straight position)
+constexpr uint32_t kIfPlaceF = 1u << 7;     // offset: place points by the density inverse (h != 0)
+constexpr uint32_t kIfPlaceES = 1u << 8;    // offset: place points uniform in |kappa|^1.5 (h == 0)
+constexpr uint32_t kIfEndA = 1u << 9;       // evolute: connecting lines at ua
+constexpr uint32_t kIfEndB = 1u << 10;      // evolute: connecting lines at ub
+constexpr uint32_t kIfDneg = 1u << 11;      // evolute: side traversed backwards
+constexpr uint32_t kIfInnerFirst = 1u << 12;  // join: inner part before the outer part
+constexpr uint32_t kIfKSame = 1u << 13;       // offset, h == 0: curvature keeps its sign over the range
+// join outer part kind (bits 16..19), inner part kind (bits 20..21)
+enum { kOutLine1 = 0, kOutLine2 = 1, kOutLine3 = 2, kOutRound = 3 };
+enum { kInNone = 0, kInPivot = 1, kInSmooth = 2 };
 
-struct WriteSink {
-    float* out;      // records base (float words)
-    uint64_t idx;    // next record index
-    uint64_t end;    // min(one past this tag's last record, capacity): never written beyond
-    uint32_t path;
-    int arcs;        // 0: 5-word lines, 1: 6-word arcs
-    uint32_t n;
-    SX_FN void put(V2 a, V2 b, float curv) {
-        if (idx >= end) { n++; return; }
-        if (arcs) {
-            float* r = out + idx * 6;
-            r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y; r[4] = curv;
-            reinterpret_cast<uint32_t*>(r)[5] = path;
-        } else {
-            float* r = out + idx * 5;
-            r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y;
-            reinterpret_cast<uint32_t*>(r)[4] = path;
-        }
-        idx++;
-        n++;
-    }
-    SX_FN void line(V2 a, V2 b) { put(a, b, 0.0f); }
-    SX_FN void arc(V2 a, V2 b, float turn) {
-        float c = len(b - a);
-        float curv = (c > 0.0f && turn != 0.0f) ? 2.0f * sinf(0.5f * turn) / c : 0.0f;
-        put(a, b, curv);
-    }
-    SX_FN void skip(uint32_t) {}
-    static constexpr bool kEmit = true;
+struct __align__(16) Item {
+    uint32_t hdr;    // kind | flags | outer kind << 16 | inner kind << 20
+    uint32_t tag;    // tag index
+    uint32_t local;  // record offset of this chunk within the tag
+    uint32_t n;      // records in this chunk
+    uint32_t k0;     // first record of the chunk within the whole item
+    uint32_t ntot;   // records of the whole item
+    uint32_t u[26];  // payload (floats / doubles by kind)
 };
+static_assert(sizeof(Item) == 128, "item layout");
+
+// offset-item payload
+struct OffsetP {
+    float fp0x, fp0y, frotx, froty, fdx, fdy, fk0, fk1, fL, fbase;  // ES
+    double hka, hkb, dx;                                              // density axis
+    float kna, knb;                                                   // normalised curvature at the range ends
+    float ua, du, ub, fh;
+    float Pax, Pay, Pbx, Pby;
+};
+// evolute-item payload
+struct EvoluteP {
+    float fp0x, fp0y, frotx, froty, fdx, fdy, fk0, fk1, fL, fbase;
+    float ua, du, alpha;
+    uint32_t ne;
+    float E0x, E0y, E1x, E1y, Pax, Pay, Pbx, Pby;
+};
+// join-item payload
+struct JoinP {
+    float fromx, fromy, tox, toy, ax, ay, bx, by;  // outer part points
+    float cx, cy, a0, sweep, w;                    // round part
+    float fx, fy, px, py, tx, ty;                  // inner part (pivot: f -> p -> t; smooth: f -> t)
+    uint32_t n_outer;
+};
+static_assert(sizeof(OffsetP) <= 26 * 4 && sizeof(EvoluteP) <= 26 * 4 && sizeof(JoinP) <= 26 * 4, "payload size");
+
+SX_FN uint32_t chunks(uint32_t n, uint32_t K) { return (n + K - 1) / K; }
+
+// 128-byte item copy as eight 16-byte moves
+SX_FN void store_item(Item* dst, const Item& src) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(&src);
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+    for (int j = 0; j < 8; j++) d4[j] = s4[j];
+}
+SX_FN void load_item(Item& dst, const Item* src) {
+    const uint4* s4 = reinterpret_cast<const uint4*>(src);
+    uint4* d4 = reinterpret_cast<uint4*>(&dst);
+#pragma unroll
+    for (int j = 0; j < 8; j++) d4[j] = s4[j];
+}
 
 struct Cfg {
     double tau_fit, tau_flat, inv_sqrt8tf;  // sqrt(1 / (8 tau_flat))
     double cbrt_inv120tf;                   // cbrt(1 / (120 tau_flat))
     int arcs;
     int paper_fit;
+    uint32_t K;                             // records per item chunk
+};
+
+// Item sink: writes a tag's items into slots handed out by the allocator and
+// counts the tag's records.  Alloc::alloc(nc) returns the first of nc
+// consecutive slots owned by the caller, or ~0 when the workspace is full
+// (the items are then dropped; the caller sees the overflow count).
+template <class Alloc>
+struct ItemSink {
+    Item* items;
+    Alloc al;
+    uint32_t tag;
+    uint32_t n;  // records of the tag so far
+    template <class P>
+    SX_HD void put(uint32_t hdr, uint32_t nrec, uint32_t K, const P& p) {
+        const uint32_t nc = chunks(nrec, K);
+        const uint64_t base = al.alloc(nc);
+        if (base != ~0ull) {
+            for (uint32_t c = 0; c < nc; c++) {
+                Item* dst = items + base + c;
+                const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
+                *reinterpret_cast<uint4*>(dst) = make_uint4(hdr, tag, n + c * K, nchunk);
+                *reinterpret_cast<uint2*>(&dst->k0) = make_uint2(c * K, nrec);
+                *reinterpret_cast<P*>(dst->u) = p;
+            }
+        }
+        n += nrec;
+    }
 };
 
 // ----------------------------------------------- one range of one side
 // Section 4 (lines), Section 5 (arcs) and Section 6 (evolute for rho < 0).
 // Pa, Pb: the range's end points (exact piece ends or the shared cusp point).
 template <class Sink>
-SX_HD void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua, double ub, bool reversed,
+SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua, double ub, bool reversed,
                       bool end_a_piece, bool end_b_piece, V2 Pa, V2 Pb) {
     const bool sideA = h >= 0.0;
     const int D = sideA ? 1 : -1;
@@ -400,26 +493,28 @@ SX_HD void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
     const double du = ub - ua;
     const double kna = es_kn(es, ua), knb = es_kn(es, ub);
     uint32_t n;
-    XSeg segs[kMaxXSeg];
-    int nseg = 0;
-    double dF = 0.0;
+    double hka = 0.0, hkb = 0.0, dx = 0.0;
+    uint32_t place = 0;
     if (!cfg.arcs) {
         double I;
         if (es.k1 == 0.0) {
             I = du * sqrt(fabs(es.k0) * fabs(es.L + h * es.k0));
         } else if (h == 0.0) {
+            place = kIfPlaceES;
             double aa = fabs(kna), ab = fabs(knb);
             if (kna * knb >= 0.0) {
+                place |= kIfKSame;
                 double den = pow15(aa) + pow15(ab);
                 I = den > 0.0 ? (2.0 / 3.0) * du * sqrt(es.L) * (aa * aa + aa * ab + ab * ab) / den : 0.0;
             } else {
                 I = (2.0 / 3.0) * du * sqrt(es.L) * (pow15(aa) + pow15(ab)) / (aa + ab);
             }
         } else {
-            XP xa = make_xp(h * kna / es.L), xb = make_xp(h * knb / es.L);
-            double dx = -2.0 * h * es.k1 * du / es.L;
-            nseg = split_x(xa, xb, dx, segs);
-            for (int j = 0; j < nseg; j++) dF += segs[j].dF;
+            place = kIfPlaceF;
+            hka = h * kna / es.L;
+            hkb = h * knb / es.L;
+            dx = -2.0 * h * es.k1 * du / es.L;
+            double dF = split_x_sum(make_xp(hka), make_xp(hkb), dx);
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
             double G = (dx != 0.0) ? dF / dx : 0.0;
             I = fabs(G) * du * es.L / (2.0 * sqrt(fabs(h)));
@@ -437,124 +532,62 @@ SX_HD void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
         uint32_t ns = ceil_count(sweep);
         n = ns > n ? ns : n;
     }
-
-    if (!Sink::kEmit) {
-        k.skip(n);
-    } else {
-        const float fh = (float)h, fua = (float)ua, fdu = (float)du;
-        float dx_total = 0.0f;
-        for (int j = 0; j < nseg; j++) dx_total += (float)segs[j].len;
-        V2 prev = Pa;
-        float uprev = fua;
-        for (uint32_t i = 1; i <= n; i++) {
-            float u;
-            V2 P;
-            if (i == n) {
-                u = (float)ub;
-                P = Pb;
-            } else {
-                float f = (float)i / (float)n;
-                float tau = f;
-                if (!cfg.arcs && es.k1 != 0.0) {
-                    if (h != 0.0) {
-                        // walk the branch pieces to the one holding f * dF
-                        double target = f * dF, cum = 0.0;
-                        float acc_len = 0.0f;
-                        int j = 0;
-                        for (; j < nseg - 1; j++) {
-                            if (fabs(cum + segs[j].dF) >= fabs(target)) break;
-                            cum += segs[j].dF;
-                            acc_len += (float)segs[j].len;
-                        }
-                        float fl = (segs[j].dF != 0.0) ? (float)((target - cum) / segs[j].dF) : 0.0f;
-                        fl = fminf(fmaxf(fl, 0.0f), 1.0f);
-                        float phi = (segs[j].len != 0.0) ? branch_inv_frac(segs[j], fl) : fl;
-                        tau = (nseg == 1) ? phi : (acc_len + phi * (float)segs[j].len) / dx_total;
-                    } else {
-                        // h = 0: uniform in |kappa|^1.5 (Section 2.2)
-                        float aa = fabsf((float)kna), ab = fabsf((float)knb);
-                        float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
-                        float kap;
-                        if (kna * knb >= 0.0) {
-                            float P15 = Pa15 + f * (Pb15 - Pa15);
-                            kap = cbrtf(P15 * P15);
-                            tau = (ab != aa) ? (kap - aa) / (ab - aa) : f;
-                        } else {
-                            float target = f * (Pa15 + Pb15);
-                            if (target <= Pa15) {
-                                float t15 = Pa15 - target;
-                                kap = cbrtf(t15 * t15);
-                                tau = (aa - kap) / (aa + ab);
-                            } else {
-                                float t15 = target - Pa15;
-                                kap = cbrtf(t15 * t15);
-                                tau = (aa + kap) / (aa + ab);
-                            }
-                        }
-                    }
-                }
-                tau = fminf(fmaxf(tau, 0.0f), 1.0f);
-                u = fua + fdu * tau;
-                P = offset_point_f(es, fh, u);
-            }
-            if (!cfg.arcs) {
-                if (dir > 0) k.line(prev, P); else k.line(P, prev);
-            } else {
-                float turn = es_phi_f(es.fk0, es.fk1, u) - es_phi_f(es.fk0, es.fk1, uprev);
-                if (dir > 0) k.arc(prev, P, turn); else k.arc(P, prev, -turn);
-            }
-            prev = P;
-            uprev = u;
-        }
+    uint32_t ne = 0, nconn = 0;
+    double ra = 0.0, rb = 0.0;
+    if (reversed) {
+        // evolute: density |s - s0|^-1/2 (Section 6); lines in both modes
+        ra = sqrt(fabs(kna));
+        rb = sqrt(fabs(knb));
+        double Iev = (es.k1 != 0.0 && ra + rb > 0.0) ? 2.0 * du * sqrt(fabs(es.k1) * es.L) / (ra + rb) : 0.0;
+        ne = ceil_count(Iev * cfg.inv_sqrt8tf);
+        nconn = (end_a_piece ? 1u : 0u) + (end_b_piece ? 1u : 0u);
     }
-    if (!reversed) return;
-
-    // ---- evolute: density |s - s0|^-1/2 (Section 6); lines in both modes
-    double aa = fabs(kna), ab = fabs(knb);
-    double ra = sqrt(aa), rb = sqrt(ab);
-    double Iev = (es.k1 != 0.0 && ra + rb > 0.0) ? 2.0 * du * sqrt(fabs(es.k1) * es.L) / (ra + rb) : 0.0;
-    uint32_t ne = ceil_count(Iev * cfg.inv_sqrt8tf);
-    uint32_t nconn = (end_a_piece ? 1u : 0u) + (end_b_piece ? 1u : 0u);
-    if (!Sink::kEmit) {
-        k.skip(2u * ne + 2u * nconn);
-        return;
+    {
+        OffsetP p;
+        set_es_f(es, &p.fp0x);
+        p.hka = hka; p.hkb = hkb; p.dx = dx;
+        p.kna = (float)kna; p.knb = (float)knb;
+        p.ua = (float)ua; p.du = (float)du; p.ub = (float)ub; p.fh = (float)h;
+        p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
+        uint32_t hdr = kItemOffset | (dir < 0 ? kIfDirNeg : 0u) | (cfg.arcs ? kIfArcs : 0u) |
+                       (es.pivot ? kIfPivot : 0u) | place;
+        k.put(hdr, n, cfg.K, p);
     }
-    const float alpha = (ra + rb > 0.0) ? (float)(ra / (ra + rb)) : 0.5f;
-    const float fua = (float)ua, fdu = (float)du;
-    V2 E0 = end_a_piece ? evolute_end(es, ua == 1.0) : Pa;
-    V2 E1 = end_b_piece ? evolute_end(es, ub == 1.0) : Pb;
-    for (int copy = 0; copy < 2; copy++) {
-        V2 prev = E0;
-        for (uint32_t i = 1; i <= ne; i++) {
-            V2 E;
-            if (i == ne) {
-                E = E1;
-            } else {
-                float f = (float)i / (float)ne;
-                float tau = f * (2.0f * alpha + f * (1.0f - 2.0f * alpha));
-                E = evolute_point_f(es, fua + fdu * tau);
-            }
-            if (D > 0) k.line(prev, E); else k.line(E, prev);
-            prev = E;
-        }
+    if (reversed) {
+        EvoluteP p;
+        set_es_f(es, &p.fp0x);
+        p.ua = (float)ua; p.du = (float)du;
+        p.alpha = (ra + rb > 0.0) ? (float)(ra / (ra + rb)) : 0.5f;
+        p.ne = ne;
+        V2 E0 = end_a_piece ? evolute_end(es, ua == 1.0) : Pa;
+        V2 E1 = end_b_piece ? evolute_end(es, ub == 1.0) : Pb;
+        p.E0x = E0.x; p.E0y = E0.y; p.E1x = E1.x; p.E1y = E1.y;
+        p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
+        uint32_t hdr = kItemEvolute | (D < 0 ? kIfDneg : 0u) | (es.pivot ? kIfPivot : 0u) |
+                       (end_a_piece ? kIfEndA : 0u) | (end_b_piece ? kIfEndB : 0u);
+        k.put(hdr, 2u * ne + 2u * nconn, cfg.K, p);
     }
-    if (end_a_piece)
-        for (int c = 0; c < 2; c++) { if (D > 0) k.line(Pa, E0); else k.line(E0, Pa); }
-    if (end_b_piece)
-        for (int c = 0; c < 2; c++) { if (D > 0) k.line(E1, Pb); else k.line(Pb, E1); }
 }
 
+// Both sides of one piece: side A (h = +w) then side B (h = -w); a side
+// whose rho changes sign inside the piece is split at the parallel-curve cusp
+// into two ranges (Section 6).  One emit_range call site keeps the code small.
 template <class Sink>
-SX_HD void emit_side(Sink& k, const Cfg& cfg, const ES& es, double h) {
-    double r0 = es_rhoL(es, h, 0.0), r1 = es_rhoL(es, h, 1.0);
-    V2 P0 = offs(es.p0, es.n0, h), P1 = offs(es.p1, es.n1, h);
-    if (r0 * r1 < 0.0) {
-        double tc = r0 / (r0 - r1);
-        V2 Pc = Sink::kEmit ? offset_point_f(es, (float)h, (float)tc) : v2(0.0f, 0.0f);
-        emit_range(k, cfg, es, h, 0.0, tc, r0 < 0.0, true, false, P0, Pc);
-        emit_range(k, cfg, es, h, tc, 1.0, r1 < 0.0, false, true, Pc, P1);
-    } else {
-        emit_range(k, cfg, es, h, 0.0, 1.0, (r0 < 0.0 || r1 < 0.0), true, true, P0, P1);
+SX_FN void emit_sides(Sink& k, const Cfg& cfg, const ES& es, double w) {
+    for (int side = 0; side < 2; side++) {
+        const double h = side == 0 ? w : -w;
+        const double r0 = es_rhoL(es, h, 0.0), r1 = es_rhoL(es, h, 1.0);
+        const V2 P0 = offs(es.p0, es.n0, h), P1 = offs(es.p1, es.n1, h);
+        const bool split = r0 * r1 < 0.0;
+        const double tc = split ? r0 / (r0 - r1) : 1.0;
+        const V2 Pc = split ? offset_point_f(es, (float)h, (float)tc) : P1;
+        for (int r = 0; r < (split ? 2 : 1); r++) {
+            const bool second = r == 1;
+            const double ua = second ? tc : 0.0, ub = second ? 1.0 : tc;
+            const bool rev = split ? (second ? r1 < 0.0 : r0 < 0.0) : (r0 < 0.0 || r1 < 0.0);
+            emit_range(k, cfg, es, h, ua, ub, rev, !second, !split || second, second ? Pc : P0,
+                       second ? P1 : Pc);
+        }
     }
 }
 
@@ -564,27 +597,20 @@ SX_FN double round_step(double w, double tau_flat) {
     c = fmin(fmax(c, -1.0), 1.0);
     return 2.0 * acos(c);
 }
+SX_FN uint32_t round_count(const Cfg& cfg, double w, double sweep) {
+    return cfg.arcs ? ceil_count(fabs(sweep) * (1.0 / kHalfPi)) : ceil_count(fabs(sweep) / round_step(w, cfg.tau_flat));
+}
+SX_FN uint32_t inner_count(uint32_t inner) { return inner == kInPivot ? 2u : (inner == kInSmooth ? 1u : 0u); }
+SX_FN uint32_t outer_count(uint32_t outer, uint32_t n_round) {
+    return outer == kOutLine1 ? 1u : (outer == kOutLine2 ? 2u : (outer == kOutLine3 ? 3u : n_round));
+}
 
 template <class Sink>
-SX_HD void emit_round(Sink& k, const Cfg& cfg, D2 c, double w, double a0, double sweep, V2 A, V2 B) {
-    uint32_t n = cfg.arcs ? ceil_count(fabs(sweep) * (1.0 / kHalfPi))
-                          : ceil_count(fabs(sweep) / round_step(w, cfg.tau_flat));
-    if (!Sink::kEmit) { k.skip(n); return; }
-    V2 prev = A;
-    const V2 fc = f32(c);
-    const float fw = (float)w, fa0 = (float)a0, fsw = (float)sweep;
-    for (uint32_t i = 1; i <= n; i++) {
-        V2 nx;
-        if (i == n) nx = B;
-        else {
-            float a = fa0 + fsw * ((float)i / (float)n);
-            float sn, cs;
-            sincosf(a, &sn, &cs);
-            nx = v2(fc.x + fw * cs, fc.y + fw * sn);
-        }
-        if (cfg.arcs) k.arc(prev, nx, fsw / (float)n); else k.line(prev, nx);
-        prev = nx;
-    }
+SX_FN void put_join(Sink& k, const Cfg& cfg, uint32_t outer, uint32_t inner, bool inner_first, const JoinP& p) {
+    uint32_t nrec = outer_count(outer, p.n_outer) + inner_count(inner);
+    uint32_t hdr = kItemJoin | (cfg.arcs ? kIfArcs : 0u) | (inner_first ? kIfInnerFirst : 0u) | (outer << 16) |
+                   (inner << 20);
+    k.put(hdr, nrec, cfg.K, p);
 }
 
 template <class Sink>
@@ -593,16 +619,21 @@ SX_HD void emit_cap(Sink& k, const Cfg& cfg, int cap, D2 p, D2 u, double w, bool
     D2 PA = p + N * w, PB = p + N * (-w);
     D2 from = start ? PB : PA, to = start ? PA : PB;
     D2 fwd = start ? d2(-u.x, -u.y) : u;
+    JoinP jp = {};
+    V2 f = f32(from), t = f32(to);
+    jp.fromx = f.x; jp.fromy = f.y; jp.tox = t.x; jp.toy = t.y;
     if (cap == kCapButt) {
-        k.line(f32(from), f32(to));
+        put_join(k, cfg, kOutLine1, kInNone, false, jp);
     } else if (cap == kCapSquare) {
-        D2 a = from + fwd * w, b = to + fwd * w;
-        k.line(f32(from), f32(a));
-        k.line(f32(a), f32(b));
-        k.line(f32(b), f32(to));
+        V2 a = f32(from + fwd * w), b = f32(to + fwd * w);
+        jp.ax = a.x; jp.ay = a.y; jp.bx = b.x; jp.by = b.y;
+        put_join(k, cfg, kOutLine3, kInNone, false, jp);
     } else {
         double a0 = atan2(from.y - p.y, from.x - p.x);
-        emit_round(k, cfg, p, w, a0, kPi, f32(from), f32(to));
+        V2 c = f32(p);
+        jp.cx = c.x; jp.cy = c.y; jp.a0 = (float)a0; jp.sweep = (float)kPi; jp.w = (float)w;
+        jp.n_outer = round_count(cfg, w, kPi);
+        put_join(k, cfg, kOutRound, kInNone, false, jp);
     }
 }
 
@@ -611,10 +642,13 @@ SX_HD void emit_join(Sink& k, const Cfg& cfg, int join, double miter_limit, D2 p
     D2 ua = unit(ta), ub = unit(tb);
     double cr = cross(ua, ub), dp = dot(ua, ub);
     D2 Na = rnormal(ua), Nb = rnormal(ub);
+    JoinP jp = {};
     // nearly tangent-continuous: one straight line per side, no pivot lines
     if (dp > 0.0 && fabs(cr) < kSmoothJoin) {
-        k.line(offs(p, Na, w), offs(p, Nb, w));
-        k.line(offs(p, Nb, -w), offs(p, Na, -w));
+        V2 a0 = offs(p, Na, w), a1 = offs(p, Nb, w), b0 = offs(p, Nb, -w), b1 = offs(p, Na, -w);
+        jp.fromx = a0.x; jp.fromy = a0.y; jp.tox = a1.x; jp.toy = a1.y;
+        jp.fx = b0.x; jp.fy = b0.y; jp.tx = b1.x; jp.ty = b1.y;
+        put_join(k, cfg, kOutLine1, kInSmooth, false, jp);
         return;
     }
     bool outerA = !(cr < 0.0);
@@ -622,30 +656,239 @@ SX_HD void emit_join(Sink& k, const Cfg& cfg, int join, double miter_limit, D2 p
     D2 Oa = p + Na * h_out, Ob = p + Nb * h_out;
     V2 Ia = offs(p, Na, h_in), Ib = offs(p, Nb, h_in);
     D2 from = outerA ? Oa : Ob, to = outerA ? Ob : Oa;
-    V2 fp = f32(p);
-    for (int side = 0; side < 2; side++) {
-        bool isA = side == 0;
-        if (isA == outerA) {
-            if (join == kJoinRound) {
-                double dphi = atan2(cr, dp);
-                double a0 = atan2(from.y - p.y, from.x - p.x);
-                emit_round(k, cfg, p, w, a0, fabs(dphi), f32(from), f32(to));
-            } else if (join == kJoinMiter) {
-                double crit = miter_limit * miter_limit * (1.0 + dp);
-                if (crit >= 2.0) {
-                    V2 M = offs(p, Na + Nb, h_out / (1.0 + dp));
-                    k.line(f32(from), M);
-                    k.line(M, f32(to));
-                } else {
-                    k.line(f32(from), f32(to));
-                }
+    V2 ff = f32(from), ft = f32(to), fp = f32(p);
+    jp.fromx = ff.x; jp.fromy = ff.y; jp.tox = ft.x; jp.toy = ft.y;
+    V2 fi = outerA ? Ib : Ia, ti = outerA ? Ia : Ib;
+    jp.fx = fi.x; jp.fy = fi.y; jp.px = fp.x; jp.py = fp.y; jp.tx = ti.x; jp.ty = ti.y;
+    uint32_t outer = kOutLine1;
+    if (join == kJoinRound) {
+        double dphi = atan2(cr, dp);
+        double a0 = atan2(from.y - p.y, from.x - p.x);
+        jp.cx = fp.x; jp.cy = fp.y; jp.a0 = (float)a0; jp.sweep = (float)fabs(dphi); jp.w = (float)w;
+        jp.n_outer = round_count(cfg, w, fabs(dphi));
+        outer = kOutRound;
+    } else if (join == kJoinMiter) {
+        double crit = miter_limit * miter_limit * (1.0 + dp);
+        if (crit >= 2.0) {
+            V2 M = offs(p, Na + Nb, h_out / (1.0 + dp));
+            jp.ax = M.x; jp.ay = M.y;
+            outer = kOutLine2;
+        }
+    }
+    // canonical order: side A's part first, then side B's
+    put_join(k, cfg, outer, kInPivot, !outerA, jp);
+}
+
+// ------------------------------------------------------ record emission
+// FP32 per-point work of one item chunk; records go to out at `dst`.
+struct RecOut {
+    float* out;
+    uint64_t idx, end;
+    uint32_t path;
+    int arcs;
+    SX_FN void put(V2 a, V2 b, float curv) {
+        if (idx < end) {
+            if (arcs) {
+                float* r = out + idx * 6;
+                r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y; r[4] = curv;
+                reinterpret_cast<uint32_t*>(r)[5] = path;
             } else {
-                k.line(f32(from), f32(to));
+                float* r = out + idx * 5;
+                r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y;
+                reinterpret_cast<uint32_t*>(r)[4] = path;
             }
+        }
+        idx++;
+    }
+    SX_FN void line(V2 a, V2 b) { put(a, b, 0.0f); }
+    SX_FN void arc(V2 a, V2 b, float turn) {
+        float c = len(b - a);
+        float curv = (c > 0.0f && turn != 0.0f) ? 2.0f * sinf(0.5f * turn) / c : 0.0f;
+        put(a, b, curv);
+    }
+};
+
+SX_FN ES es_from_f(const float* d, bool pivot) {
+    ES es;
+    es.fp0 = v2(d[0], d[1]);
+    es.frot = v2(d[2], d[3]);
+    es.fd = v2(d[4], d[5]);
+    es.fk0 = d[6]; es.fk1 = d[7]; es.fL = d[8]; es.fbase = d[9];
+    es.pivot = pivot;
+    return es;
+}
+
+// u of point i (0 < i < n) of an offset range
+SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, const XSeg* segs, int nseg,
+                            double dF, float dx_total) {
+    float f = (float)i / (float)n;
+    float tau = f;
+    if (hdr & kIfPlaceF) {
+        // walk the branch pieces to the one holding f * dF
+        double target = f * dF, cum = 0.0;
+        float acc_len = 0.0f;
+        int j = 0;
+        for (; j < nseg - 1; j++) {
+            if (fabs(cum + segs[j].dF) >= fabs(target)) break;
+            cum += segs[j].dF;
+            acc_len += (float)segs[j].len;
+        }
+        float fl = (segs[j].dF != 0.0) ? (float)((target - cum) / segs[j].dF) : 0.0f;
+        fl = fminf(fmaxf(fl, 0.0f), 1.0f);
+        float phi = (segs[j].len != 0.0) ? branch_inv_frac(segs[j], fl) : fl;
+        tau = (nseg == 1) ? phi : (acc_len + phi * (float)segs[j].len) / dx_total;
+    } else if (hdr & kIfPlaceES) {
+        // h = 0: uniform in |kappa|^1.5 (Section 2.2)
+        float aa = fabsf(p.kna), ab = fabsf(p.knb);
+        float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
+        float kap;
+        if (hdr & kIfKSame) {
+            float P15 = Pa15 + f * (Pb15 - Pa15);
+            kap = cbrtf(P15 * P15);
+            tau = (ab != aa) ? (kap - aa) / (ab - aa) : f;
         } else {
-            V2 f = outerA ? Ib : Ia, t = outerA ? Ia : Ib;
-            k.line(f, fp);
-            k.line(fp, t);
+            float target = f * (Pa15 + Pb15);
+            if (target <= Pa15) {
+                float t15 = Pa15 - target;
+                kap = cbrtf(t15 * t15);
+                tau = (aa - kap) / (aa + ab);
+            } else {
+                float t15 = target - Pa15;
+                kap = cbrtf(t15 * t15);
+                tau = (aa + kap) / (aa + ab);
+            }
+        }
+    }
+    tau = fminf(fmaxf(tau, 0.0f), 1.0f);
+    return p.ua + p.du * tau;
+}
+
+SX_HD inline void emit_item(const Item& it, RecOut& o) {
+    const uint32_t kind = it.hdr & 15u;
+    const uint32_t hdr = it.hdr;
+    const bool arcs = (hdr & kIfArcs) != 0;
+    if (kind == kItemOffset) {
+        OffsetP p;
+        memcpy(&p, it.u, sizeof(p));
+        ES es = es_from_f(&p.fp0x, (hdr & kIfPivot) != 0);
+        XSeg segs[kMaxXSeg];
+        int nseg = 0;
+        double dF = 0.0;
+        float dx_total = 0.0f;
+        if (hdr & kIfPlaceF) {
+            nseg = split_x(make_xp(p.hka), make_xp(p.hkb), p.dx, segs);
+            for (int j = 0; j < nseg; j++) {
+                dF += segs[j].dF;
+                dx_total += (float)segs[j].len;
+            }
+        }
+        const uint32_t n = it.ntot;
+        const bool neg = (hdr & kIfDirNeg) != 0;
+        // point k0 of the chunk
+        float uprev;
+        V2 prev;
+        if (it.k0 == 0) {
+            uprev = p.ua;
+            prev = v2(p.Pax, p.Pay);
+        } else {
+            uprev = offset_u(p, hdr, it.k0, n, segs, nseg, dF, dx_total);
+            prev = offset_point_f(es, p.fh, uprev);
+        }
+        for (uint32_t r = 0; r < it.n; r++) {
+            uint32_t i = it.k0 + r + 1;
+            float u;
+            V2 P;
+            if (i == n) {
+                u = p.ub;
+                P = v2(p.Pbx, p.Pby);
+            } else {
+                u = offset_u(p, hdr, i, n, segs, nseg, dF, dx_total);
+                P = offset_point_f(es, p.fh, u);
+            }
+            if (!arcs) {
+                if (!neg) o.line(prev, P); else o.line(P, prev);
+            } else {
+                float turn = es_phi_f(es.fk0, es.fk1, u) - es_phi_f(es.fk0, es.fk1, uprev);
+                if (!neg) o.arc(prev, P, turn); else o.arc(P, prev, -turn);
+            }
+            prev = P;
+            uprev = u;
+        }
+    } else if (kind == kItemEvolute) {
+        EvoluteP p;
+        memcpy(&p, it.u, sizeof(p));
+        ES es = es_from_f(&p.fp0x, (hdr & kIfPivot) != 0);
+        const uint32_t ne = p.ne;
+        const bool Dneg = (hdr & kIfDneg) != 0;
+        const V2 E0 = v2(p.E0x, p.E0y), E1 = v2(p.E1x, p.E1y), Pa = v2(p.Pax, p.Pay), Pb = v2(p.Pbx, p.Pby);
+        auto ev = [&](uint32_t i) -> V2 {
+            if (i == 0) return E0;
+            if (i == ne) return E1;
+            float f = (float)i / (float)ne;
+            float tau = f * (2.0f * p.alpha + f * (1.0f - 2.0f * p.alpha));
+            return evolute_point_f(es, p.ua + p.du * tau);
+        };
+        const bool ca = (hdr & kIfEndA) != 0, cb = (hdr & kIfEndB) != 0;
+        V2 cache_a = v2(0.0f, 0.0f);
+        uint32_t cache_i = 0xffffffffu;
+        for (uint32_t r = 0; r < it.n; r++) {
+            uint32_t k = it.k0 + r;
+            if (k < 2u * ne) {
+                uint32_t s = k % ne;  // segment s of copy k / ne
+                V2 A = (cache_i == s) ? cache_a : ev(s);
+                V2 B = ev(s + 1);
+                cache_a = B;
+                cache_i = s + 1;
+                if (!Dneg) o.line(A, B); else o.line(B, A);
+            } else {
+                uint32_t c = k - 2u * ne;  // connecting lines: 2 at ua (if any), then 2 at ub
+                bool at_a = ca && c < 2u;
+                if (at_a) {
+                    if (!Dneg) o.line(Pa, E0); else o.line(E0, Pa);
+                } else {
+                    if (!Dneg) o.line(E1, Pb); else o.line(Pb, E1);
+                }
+            }
+        }
+        (void)cb;
+    } else {
+        JoinP p;
+        memcpy(&p, it.u, sizeof(p));
+        const uint32_t outer = (hdr >> 16) & 15u, inner = (hdr >> 20) & 3u;
+        const bool inner_first = (hdr & kIfInnerFirst) != 0;
+        const uint32_t no = outer_count(outer, p.n_outer), ni = inner_count(inner);
+        const V2 from = v2(p.fromx, p.fromy), to = v2(p.tox, p.toy), A = v2(p.ax, p.ay), B = v2(p.bx, p.by);
+        const V2 F = v2(p.fx, p.fy), Pp = v2(p.px, p.py), T = v2(p.tx, p.ty);
+        for (uint32_t r = 0; r < it.n; r++) {
+            uint32_t k = it.k0 + r;
+            bool is_inner = inner_first ? (k < ni) : (k >= no);
+            if (is_inner) {
+                uint32_t j = inner_first ? k : k - no;
+                if (inner == kInSmooth) o.line(F, T);
+                else if (j == 0) o.line(F, Pp);
+                else o.line(Pp, T);
+                continue;
+            }
+            uint32_t j = inner_first ? k - ni : k;
+            if (outer == kOutLine1) {
+                o.line(from, to);
+            } else if (outer == kOutLine2) {
+                if (j == 0) o.line(from, A); else o.line(A, to);
+            } else if (outer == kOutLine3) {
+                if (j == 0) o.line(from, A); else if (j == 1) o.line(A, B); else o.line(B, to);
+            } else {
+                const uint32_t nr = p.n_outer;
+                auto rp = [&](uint32_t q) -> V2 {
+                    if (q == 0) return from;
+                    if (q == nr) return to;
+                    float a = p.a0 + p.sweep * ((float)q / (float)nr);
+                    float sn, cs;
+                    sincosf(a, &sn, &cs);
+                    return v2(p.cx + p.w * cs, p.cy + p.w * sn);
+                };
+                V2 a = rp(j), b = rp(j + 1);
+                if (arcs) o.arc(a, b, p.sweep / (float)nr); else o.line(a, b);
+            }
         }
     }
 }
@@ -707,8 +950,10 @@ SX_FN Tan sample_q(const Seg& s, double t) {
 
 // Algorithm 2: adaptive bisection of the cubic into Euler spiral pieces with
 // the two-word stack (t0_u, dt), then the parallel curves of each piece.
+// A line is its own Euler spiral piece (k0 = k1 = 0, arc length equal to the
+// chord, tangent angle of the chord) and skips the fit.
 template <class Sink>
-SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s) {
+SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s, bool line) {
     uint32_t t0_u = 0;
     double dt = 1.0;
     D2 last_p = s.P0w;
@@ -721,25 +966,34 @@ SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s) {
         if (t0 == 1.0) break;
         double t1 = t0 + dt;
         D2 next_p = cubic_world(s, t1);
-        Tan next_q = sample_q(s, t1);
-        D2 chord = cubic_chord(s, t0, dt, last_qtrue);
-        double cl = len(chord);
-        double th0 = atan2(cross(last_q.dir, chord), dot(last_q.dir, chord));
-        double th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
-        double d0 = last_q.mag * dt / cl, d1 = next_q.mag * dt / cl;
-        double est = fit_estimate(th0, th1, d0, d1);
-        double err = cfg.paper_fit ? est * cl : est * (cl + kFitK * hw) * kFitS;
-        bool len_ok = cl > 0.0;
-        bool hodo_ok = true;
-        {
-            double ma = last_q.mag * dt, mc = next_q.mag * dt;
-            D2 a = unit(last_q.dir) * ma, c = unit(next_q.dir) * mc;
-            D2 b = chord - a - c;
-            // a middle vector that is zero up to rounding leaves only the turn from a to c (< pi)
-            if (ma > 0.0 && mc > 0.0 && len(b) > 1e-9 * (ma + mc)) hodo_ok = (dot(a, b) * mc + dot(b, c) * ma) > 0.0;
+        Tan next_q = line ? last_q : sample_q(s, t1);
+        D2 chord;
+        double cl, th0 = 0.0, th1 = 0.0;
+        bool ok = true;
+        if (line) {
+            chord = s.D3;
+            cl = len(chord);
+        } else {
+            chord = cubic_chord(s, t0, dt, last_qtrue);
+            cl = len(chord);
+            th0 = atan2(cross(last_q.dir, chord), dot(last_q.dir, chord));
+            th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
+            double d0 = last_q.mag * dt / cl, d1 = next_q.mag * dt / cl;
+            double est = fit_estimate(th0, th1, d0, d1);
+            double err = cfg.paper_fit ? est * cl : est * (cl + kFitK * hw) * kFitS;
+            bool len_ok = cl > 0.0;
+            bool hodo_ok = true;
+            {
+                double ma = last_q.mag * dt, mc = next_q.mag * dt;
+                D2 a = unit(last_q.dir) * ma, c = unit(next_q.dir) * mc;
+                D2 b = chord - a - c;
+                // a middle vector that is zero up to rounding leaves only the turn from a to c (< pi)
+                if (ma > 0.0 && mc > 0.0 && len(b) > 1e-9 * (ma + mc))
+                    hodo_ok = (dot(a, b) * mc + dot(b, c) * ma) > 0.0;
+            }
+            ok = len_ok && hodo_ok && (err <= cfg.tau_fit);
         }
         bool forced = dt <= min_dt;
-        bool ok = len_ok && hodo_ok && (err <= cfg.tau_fit);
         if (ok || forced) {
             bool pivot = !ok;
             ES es;
@@ -750,7 +1004,13 @@ SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s) {
             es.n1 = rnormal(unit(next_q.dir));
             double c, base;
             D2 rot = d2(0.0, 0.0);
-            if (pivot) {
+            if (line) {
+                es.k0 = 0.0;
+                es.k1 = 0.0;
+                c = 1.0;
+                rot = chord;
+                base = atan2(rot.y, rot.x);
+            } else if (pivot) {
                 es.k0 = atan2(cross(last_q.dir, next_q.dir), dot(last_q.dir, next_q.dir));
                 es.k1 = 0.0;
                 c = es_chord(0.5 * es.k0, 0.5 * es.k0);
@@ -766,17 +1026,14 @@ SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s) {
             }
             if (!(c > kCMin)) c = kCMin;
             es.L = cl / c;
-            if (Sink::kEmit) {
-                es.fp0 = f32(es.p0);
-                es.fd = f32(es.p1 - es.p0);
-                es.frot = f32(rot);
-                es.fk0 = (float)es.k0;
-                es.fk1 = (float)es.k1;
-                es.fL = (float)es.L;
-                es.fbase = (float)base;
-            }
-            emit_side(k, cfg, es, hw);
-            emit_side(k, cfg, es, -hw);
+            es.fp0 = f32(es.p0);
+            es.fd = f32(es.p1 - es.p0);
+            es.frot = f32(rot);
+            es.fk0 = (float)es.k0;
+            es.fk1 = (float)es.k1;
+            es.fL = (float)es.L;
+            es.fbase = (float)base;
+            emit_sides(k, cfg, es, hw);
             // pop: count trailing zeros
             t0_u += 1;
             uint32_t sh = __builtin_ctz(t0_u);
@@ -880,7 +1137,7 @@ SX_HD void process_tag(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i)
     s.ts = first_nonzero(e, c);
     s.te = first_nonzero(ce, c);
     s.lpoly = len(s.D1) + len(s.D2_ - s.D1) + len(s.D3 - s.D2_);
-    process_segment(k, cfg, s);
+    process_segment(k, cfg, s, c == 1);
 
     // join with tag i + 1 or end cap (Algorithm 1)
     uint32_t nt = sv.tags[i + 1];

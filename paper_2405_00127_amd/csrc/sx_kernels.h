@@ -7,15 +7,33 @@
 
 namespace sx {
 
+// Item workspace of the piece / record kernels: one region of region_cap
+// slots per piece tile, then ovf_cap shared overflow slots at ovf_base.
+struct WsCtl {
+    unsigned long long ovf_n;        // overflow slots requested
+    unsigned long long items_total;  // items requested by all tiles
+    unsigned long long result[2];    // records and items needed, for synchronous readback
+};
+struct ItemWs {
+    Item* items;
+    uint32_t* tile_n;  // per piece tile: slots requested (clamp to region_cap)
+    WsCtl* ctl;
+    uint32_t region_cap;
+    uint64_t ovf_base, ovf_cap;
+};
+
 int scan_tiles(uint32_t n);
+uint32_t piece_tiles(uint32_t n);
+uint32_t tag_block();
 size_t scan_status_bytes(uint32_t n);
 size_t scan_ctl_bytes();
 
-hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, hipStream_t s);
+hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
+                            hipStream_t s);
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s);
-hipError_t launch_count(const SceneView& sv, const Cfg& cfg, uint32_t* counts, hipStream_t s);
-hipError_t launch_emit(const SceneView& sv, const Cfg& cfg, const uint64_t* offsets, void* out, uint64_t cap_records,
-                       hipStream_t s);
-hipError_t launch_copy_total(const uint64_t* offsets, uint32_t n, uint64_t* dst, hipStream_t s);
+hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, hipStream_t s);
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
+                          uint64_t cap, hipStream_t s);
+hipError_t launch_finish(const uint64_t* offsets, uint32_t n, const ItemWs& ws, uint64_t* dst, hipStream_t s);
 
 }  // namespace sx

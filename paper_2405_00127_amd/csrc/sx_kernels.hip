@@ -3,12 +3,16 @@
 //  scan_tags_kernel   tag-monoid prefix scan (Section 8.2): single pass,
 //                     wave64 shuffle scan + LDS block scan + decoupled
 //                     look-back over dynamically numbered tiles.
-//  count_kernel       per tag, the number of output records (Algorithm 1 /
-//                     Algorithm 2 run in counting mode).
+//  piece_kernel       per tag, the per-segment decisions (Algorithm 1 /
+//                     Algorithm 2) in FP64; writes emission items into the
+//                     workspace (slots handed out per tile by LDS atomics,
+//                     overflow through one global counter) and the tag's
+//                     record count.
 //  scan_counts_kernel exclusive scan of the counts into u64 output offsets
 //                     (replaces the paper's atomic bump allocation, so the
 //                     output order is canonical and deterministic).
-//  emit_kernel        per tag, the records at their offsets.
+//  record_kernel      per item chunk, the FP32 per-point work: records at
+//                     offsets[tag] + the chunk's position within the tag.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -224,7 +228,12 @@ __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, Tile
 
 __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __restrict__ tags, uint32_t n,
                                                                uint32_t* __restrict__ mon, ScanCtl* ctl,
-                                                               TileStatus* st) {
+                                                               TileStatus* st, WsCtl* ws_reset) {
+    // the workspace counters of the piece kernel that follows start at zero
+    if (ws_reset && blockIdx.x == 0 && threadIdx.x == 0) {
+        ws_reset->ovf_n = 0;
+        ws_reset->items_total = 0;
+    }
     auto load = [&](uint64_t base, Pair* item) {
         if (base + kScanItems <= n) {
             uint4 raw = *reinterpret_cast<const uint4*>(tags + base);
@@ -306,39 +315,102 @@ __global__ __launch_bounds__(kScanBlock) void scan_counts_kernel(const uint32_t*
     scan_tile(load, store, n, ctl, st);
 }
 
-// ------------------------------------------------------- count / emit
+// ------------------------------------------------------ pieces / records
 constexpr int kTagBlock = 256;
+constexpr int kRecBlock = 256;
+constexpr int kOvfBlocks = 512;  // record-kernel blocks striding over the overflow slots
 
-__global__ __launch_bounds__(kTagBlock) void count_kernel(SceneView sv, Cfg cfg, uint32_t* __restrict__ counts) {
-    uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
-    if (i >= sv.n_tags) return;
-    CountSink k{0};
-    process_tag(k, cfg, sv, i);
-    counts[i] = k.n;
+// Slot allocator of one piece-kernel tile: the tile's own region first (LDS
+// counter), then the shared overflow region (global counter).
+struct TileAlloc {
+    Item* items;
+    uint32_t* lds_n;
+    uint64_t region;
+    uint32_t region_cap;
+    unsigned long long* ovf_n;
+    uint64_t ovf_base, ovf_cap;
+    __device__ uint64_t alloc(uint32_t nc) {
+        uint32_t s = atomicAdd(lds_n, nc);
+        if (s + nc <= region_cap) return region + s;
+        // the part of the request inside the region is left empty
+        for (uint32_t j = s; j < region_cap; j++) items[region + j].hdr = 0u;
+        unsigned long long o = atomicAdd(ovf_n, (unsigned long long)nc);
+        if (o + nc <= ovf_cap) return ovf_base + o;
+        return ~0ull;
+    }
+};
+
+__global__ __launch_bounds__(kTagBlock) void piece_kernel(SceneView sv, Cfg cfg, ItemWs ws,
+                                                          uint32_t* __restrict__ counts) {
+    __shared__ uint32_t s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
+    if (i < sv.n_tags) {
+        TileAlloc al{ws.items, &s_n, (uint64_t)blockIdx.x * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
+                     ws.ovf_base, ws.ovf_cap};
+        ItemSink<TileAlloc> k{ws.items, al, i, 0};
+        process_tag(k, cfg, sv, i);
+        counts[i] = k.n;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ws.tile_n[blockIdx.x] = s_n;
+        atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
+    }
 }
 
-__global__ __launch_bounds__(kTagBlock) void emit_kernel(SceneView sv, Cfg cfg, const uint64_t* __restrict__ offsets,
-                                                         float* __restrict__ out, uint64_t capacity_records) {
-    uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
-    if (i >= sv.n_tags) return;
-    if (offsets[sv.n_tags] > capacity_records) return;  // caller reads the count
-    uint32_t pi = sv.mon[(size_t)sv.n_tags + i];
-    uint32_t path = pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
-    uint64_t end = offsets[i + 1] < capacity_records ? offsets[i + 1] : capacity_records;
-    WriteSink k{out, offsets[i], end, path, cfg.arcs, 0};
-    process_tag(k, cfg, sv, i);
+__device__ __forceinline__ void record_item(const SceneView& sv, const Item* slot, const uint64_t* offsets,
+                                            float* out, uint64_t cap, int arcs) {
+    Item it;
+    load_item(it, slot);
+    if ((it.hdr & 15u) == 0u || it.tag >= sv.n_tags) return;
+    const uint32_t pi = sv.mon[(size_t)sv.n_tags + it.tag];
+    const uint32_t path = pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
+    const uint64_t end = offsets[it.tag + 1] < cap ? offsets[it.tag + 1] : cap;
+    RecOut o{out, offsets[it.tag] + it.local, end, path, arcs};
+    emit_item(it, o);
 }
 
-__global__ void copy_total_kernel(const uint64_t* __restrict__ offsets, uint32_t n, uint64_t* __restrict__ dst) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = offsets[n];
+__global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs ws, int arcs,
+                                                           const uint64_t* __restrict__ offsets,
+                                                           float* __restrict__ out, uint64_t cap_records,
+                                                           uint32_t n_tiles) {
+    // nothing is written when the records exceed the capacity or items were dropped
+    if (offsets[sv.n_tags] > cap_records || ws.ctl->ovf_n > ws.ovf_cap) return;
+    const uint32_t b = blockIdx.x;
+    if (b < n_tiles) {
+        const uint32_t cnt = ws.tile_n[b] < ws.region_cap ? ws.tile_n[b] : ws.region_cap;
+        const Item* base = ws.items + (uint64_t)b * ws.region_cap;
+        for (uint32_t s = threadIdx.x; s < cnt; s += kRecBlock) record_item(sv, base + s, offsets, out, cap_records, arcs);
+    } else {
+        const uint64_t cnt = ws.ctl->ovf_n;
+        const Item* base = ws.items + ws.ovf_base;
+        for (uint64_t s = (uint64_t)(b - n_tiles) * kRecBlock + threadIdx.x; s < cnt; s += (uint64_t)kOvfBlocks * kRecBlock)
+            record_item(sv, base + s, offsets, out, cap_records, arcs);
+    }
+}
+
+// out[0] = records, out[1] = 0, or the item count the workspace must hold
+// when items were dropped
+__global__ void finish_kernel(const uint64_t* __restrict__ offsets, uint32_t n, const ItemWs ws,
+                              uint64_t* __restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        dst[0] = offsets[n];
+        dst[1] = ws.ctl->ovf_n > ws.ovf_cap ? ws.ctl->items_total : 0ull;
+    }
 }
 
 // ------------------------------------------------------------- launches
 int scan_tiles(uint32_t n) { return (int)((n + kScanTile - 1) / kScanTile); }
 
-hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, hipStream_t s) {
+uint32_t piece_tiles(uint32_t n) { return (n + kTagBlock - 1) / kTagBlock; }
+uint32_t tag_block() { return kTagBlock; }
+
+hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
+                            hipStream_t s) {
     if (n == 0) return hipSuccess;
-    scan_tags_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(tags, n, mon, (ScanCtl*)ctl, (TileStatus*)st);
+    scan_tags_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(tags, n, mon, (ScanCtl*)ctl, (TileStatus*)st, ws_reset);
     return hipGetLastError();
 }
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s) {
@@ -346,19 +418,20 @@ hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, voi
     scan_counts_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
     return hipGetLastError();
 }
-hipError_t launch_count(const SceneView& sv, const Cfg& cfg, uint32_t* counts, hipStream_t s) {
+hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    count_kernel<<<(sv.n_tags + kTagBlock - 1) / kTagBlock, kTagBlock, 0, s>>>(sv, cfg, counts);
+    piece_kernel<<<piece_tiles(sv.n_tags), kTagBlock, 0, s>>>(sv, cfg, ws, counts);
     return hipGetLastError();
 }
-hipError_t launch_emit(const SceneView& sv, const Cfg& cfg, const uint64_t* offsets, void* out, uint64_t cap,
-                       hipStream_t s) {
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
+                          uint64_t cap, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    emit_kernel<<<(sv.n_tags + kTagBlock - 1) / kTagBlock, kTagBlock, 0, s>>>(sv, cfg, offsets, (float*)out, cap);
+    const uint32_t nt = piece_tiles(sv.n_tags);
+    record_kernel<<<nt + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, arcs, offsets, (float*)out, cap, nt);
     return hipGetLastError();
 }
-hipError_t launch_copy_total(const uint64_t* offsets, uint32_t n, uint64_t* dst, hipStream_t s) {
-    copy_total_kernel<<<1, 64, 0, s>>>(offsets, n, dst);
+hipError_t launch_finish(const uint64_t* offsets, uint32_t n, const ItemWs& ws, uint64_t* dst, hipStream_t s) {
+    finish_kernel<<<1, 64, 0, s>>>(offsets, n, ws, dst);
     return hipGetLastError();
 }
 size_t scan_status_bytes(uint32_t n) { return (size_t)scan_tiles(n > 0 ? n : 1) * sizeof(TileStatus); }

@@ -241,6 +241,38 @@ def test_too_small_buffer_reports_the_count(ctx):
     assert n == ei.value.required
 
 
+def test_async_workspace_overflow_is_reported_then_resized(ctx):
+    """A scene needing more emission items than its initial workspace: the
+    asynchronous call reports the need and emits nothing; one synchronous call
+    resizes the workspace; the asynchronous call then matches it bit for bit."""
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    sc = S.scene_c3(3, n_cubics=500)
+    mode = sc.output_mode
+    _say("async overflow", sc.name)
+    scene = ctx.encode(sc)
+    rec = B.RECORD_BYTES[mode]
+    buf = torch.zeros(4_000_000 * rec, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+    ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), sc.tolerance, mode)
+    torch.cuda.synchronize()
+    n0, need = int(cnt[0]), int(cnt[1])
+    assert need > 0 and n0 > 0
+    assert int(buf[: n0 * rec].count_nonzero()) == 0  # nothing emitted
+    recs, n, _ = ctx.expand(scene, sc.tolerance, mode)
+    assert n == n0
+    ref = B.records_to_numpy(recs, mode).copy()
+    buf.zero_()
+    cnt.zero_()
+    ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), sc.tolerance, mode)
+    torch.cuda.synchronize()
+    assert int(cnt[0]) == n and int(cnt[1]) == 0
+    got = B.records_to_numpy(buf[: n * rec].view(torch.float32).view(-1, rec // 4), mode)
+    assert np.array_equal(got.view(np.uint8), ref.view(np.uint8))
+
+
 def test_repeated_runs_are_bit_identical(ctx):
     sc = _scene("c1_arcs")
     _, c1, r1 = _expand(ctx, sc)
