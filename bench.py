@@ -1,13 +1,20 @@
 #!/usr/bin/env python
 """Benchmark of GPU stroke expansion on one MI355X.
 
-Headline: input path segments expanded per second at 0.25 px tolerance on
-the map/CAD-shaped scene (10,000 paths, 1,000,000 segments: 60% lines, 15%
-quads, 25% cubics, mixed joins/caps, lognormal half-widths), line output.
-One step = the whole hot path over the scene already resident in HBM: tag
-monoid scan, per-segment counts, count scan, emission.
+Headline (``value``): input path segments expanded per second at 0.25 px
+tolerance on the map/CAD-shaped scene (10,000 paths, 1,000,000 segments: 60%
+lines, 15% quads, 25% cubics, mixed joins/caps, lognormal half-widths), line
+output, plain per-scene expansion.  One step = the whole hot path over the
+scene already resident in HBM: tag-monoid scan, piece kernel (per-segment
+decisions, emission items, record counts), count scan, record kernel.
 
-Prints one JSON line (see the design doc for the roofline model).
+Beside it, in the same JSON line:
+  * ``batched``: 256 map-shaped scenes (log-uniform 100..200k segments) in one
+    graph-captured batched pipeline vs a loop of per-scene launches;
+  * ``served``: Poisson arrivals into the continuous-batching server vs serial
+    FIFO plain expansion, p50/p99 latency and throughput;
+  * ``roofline`` of the dominant kernel and ``cpu_baseline`` (the FP64 oracle
+    on the host cores, bounded sample).
 """
 from __future__ import annotations
 
@@ -24,13 +31,27 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
-# Algorithmic FP32 work per output record of the emit kernel (one new
-# outline point per record):
-#   spiral position: 4-node Gauss-Legendre, 4 x (phase 4 + sincos 36 + 2 FMA 4) = 176
-#   normal: phase 4 + sincos 36 = 40; offset + rotation 10; record write 0
-#   point placement (inverse of the density integral, lines): ~24 + asin 30 = 54
-#   arc mode replaces placement by the sweep: 2 phases 8 + sin 18 + chord 6 = 32
-FLOPS_PER_RECORD = {0: 280.0, 1: 258.0}
+PEAK_FP64_TFLOPS = 78.6
+
+# Algorithmic FP64 work of the piece kernel per unit, counted from its
+# definition (transcendentals at the FMA count of their polynomial
+# evaluation: sin/cos 25, sincos 40, atan2 40, acos 40, cbrt 30, sqrt 10,
+# divide 10):
+#   fit trial: sub-cubic end point, tangent and chord 70, two end angles 92,
+#     arms 24, the Section 7.1 estimate 180, hodograph test 91      = 460
+#   accepted cubic piece: end normals 66, Appendix A polynomials 50, Z(1) by
+#     8-node quadrature 386, rotation and base angle 66, L 10       = 580
+#   line piece: normal 33, length 13, angle 40                     = 90
+#   parallel-curve range: curvatures, density split and its F increment
+#     (Section 4.2 branches) or the arc count (Section 5), count     = 130
+#   evolute bundle: Section 6 count and exact end points            = 90
+#   join or cap: tangents, normals, offsets, round-join angles      = 150
+PIECE_FLOPS = {"trial": 460.0, "piece": 580.0, "line": 90.0, "range": 130.0, "evolute": 90.0, "join": 150.0}
+# Algorithmic FP32 work of the record kernel per output record (one new
+# outline point per record): spiral position by 4-node quadrature 118,
+# normal 24, offset 4, point placement (inverse of the density integral) 54
+# for lines; arcs replace placement by the sweep and curvature 32.
+FLOPS_PER_RECORD = {0: 200.0, 1: 178.0}
 RECORD_BYTES = {0: 20, 1: 24}
 
 
@@ -38,9 +59,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sc, mode, budget_s=12.0):
     """The FP64 oracle (single thread, as it stands) on a bounded prefix of the
-    same scene: whole paths, grown until ~budget_s of CPU time."""
+    same scene: whole tag ranges, grown until ~budget_s of CPU time."""
     import numpy as np
 
     import oracle as O
@@ -74,57 +105,34 @@ def cpu_baseline(sc, mode, budget_s=12.0):
     }
 
 
-def _cpu_model():
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
-        pass
-    return "unknown"
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", choices=["lines", "arcs"], default="lines")
-    ap.add_argument("--segments", type=int, default=1_000_000)
-    ap.add_argument("--paths", type=int, default=10_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "stroke expansion of independent scenes would shard by scene, see DESIGN.md", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-
-    from paper_2405_00127_amd import binding as B
-    from paper_2405_00127_amd import build as PB
-    from paper_2405_00127_amd import scenes as S
-
-    if not os.path.exists(B.LIB_PATH):
-        PB.build()
+# ------------------------------------------------------------------ plain
+def plain(args, ctx, B, S, torch, np):
     mode = S.OUT_LINES if args.mode == "lines" else S.OUT_ARCS
-    torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    log("bench: generating scene")
+    log("bench: generating the map scene")
     sc = S.scene_map(2, args.segments, args.paths, 0.25, mode)
     n_seg = sc.n_segments()
-    ctx = B.Context(0)
-    log("bench: encoding")
     scene = ctx.encode(sc, stream=stream)
     tol = sc.tolerance
-    # size the output once (not timed)
-    recs, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)
+    recs, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)  # sizes output and workspace
     cnt = torch.zeros(2, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     log(f"bench: {n_seg} segments, {scene.n_tags} tags -> {n_rec} records")
+
+    tune_info = {}
+    if args.piece_waves or args.chunk_k:
+        cur = ctx.get_tuning()
+        ctx.set_tuning(args.piece_waves or cur["piece_waves"], args.chunk_k or cur["chunk_k"])
+    elif not args.no_tune:
+        from paper_2405_00127_amd import autotune as AT
+
+        log("bench: autotuning launch parameters")
+        _, times = AT.tune(ctx, scene, tol, mode, buf.data_ptr(), buf.numel(), cnt.data_ptr(), stream,
+                           use_cache=False)
+        tune_info = {"candidates_ms": times}
+    tune_info["chosen"] = ctx.get_tuning()
+    log(f"bench: tuning {tune_info['chosen']}")
 
     def step():
         ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=stream)
@@ -139,7 +147,7 @@ def main():
     t1 = time.perf_counter()
     assert int(cnt[0].item()) == n_rec and int(cnt[1].item()) == 0
     ms = (t1 - t0) * 1e3 / args.steps
-    log(f"bench: {ms:.3f} ms/step")
+    log(f"bench: plain {ms:.3f} ms/step")
 
     # per-kernel times: HIP events on the launching stream around each phase
     nph = 4
@@ -154,31 +162,37 @@ def main():
     phase_ms = [sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
                 for p in range(nph)]
     names = B.PHASE_NAMES
-    dom = int(np.argmax(phase_ms))
     log("bench: phases " + ", ".join(f"{names[p]} {phase_ms[p]:.3f} ms" for p in range(nph)))
+    stats = ctx.piece_stats(scene, tol, mode, stream=stream)
+    log(f"bench: piece work {stats}")
 
     n_tags = scene.n_tags
-    if names[dom] == "records":
+    dom = int(np.argmax(phase_ms))
+    pieces_nonline = stats["pieces"] - stats["lines"]
+    piece_flops = (stats["trials"] * PIECE_FLOPS["trial"] + pieces_nonline * PIECE_FLOPS["piece"]
+                   + stats["lines"] * PIECE_FLOPS["line"] + stats["ranges"] * PIECE_FLOPS["range"]
+                   + stats["evolutes"] * PIECE_FLOPS["evolute"] + stats["joins"] * PIECE_FLOPS["join"])
+    if names[dom] == "pieces":
+        achieved = piece_flops / (phase_ms[dom] * 1e-3) / 1e12
+        roof = {"kernel": "piece_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": piece_flops, "work": stats, "flops_per_unit": PIECE_FLOPS,
+                "precision": "fp64 (decisions)"}
+    elif names[dom] == "records":
         flops = n_rec * FLOPS_PER_RECORD[mode]
         achieved = flops / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "records", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+        roof = {"kernel": "record_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
                 "units_per_launch": {"records": n_rec}, "flops_per_record": FLOPS_PER_RECORD[mode]}
-    elif names[dom] in ("scan_tags", "scan_counts"):
+    else:
         per = 17 if names[dom] == "scan_tags" else 12
         gbs = n_tags * per / (phase_ms[dom] * 1e-3) / 1e9
         roof = {"kernel": names[dom], "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": gbs / PEAK_HBM_GBS, "traffic": None}
-    else:
-        # the count kernel does the emit kernel's per-piece decisions without
-        # the per-point work; its algorithmic work is charged per record too
-        flops = n_rec * FLOPS_PER_RECORD[mode]
-        achieved = flops / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "pieces", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
     roof["phase_ms"] = {names[p]: phase_ms[p] for p in range(nph)}
-    roof["emit_hbm_GBps"] = (n_rec * RECORD_BYTES[mode] + n_tags * 48) / (phase_ms[3] * 1e-3) / 1e9
-
+    roof["scan_tags_GBps"] = n_tags * 17 / (phase_ms[0] * 1e-3) / 1e9
+    roof["scan_counts_GBps"] = n_tags * 12 / (phase_ms[2] * 1e-3) / 1e9
+    roof["records_fp32_TFLOPs"] = n_rec * FLOPS_PER_RECORD[mode] / (phase_ms[3] * 1e-3) / 1e12
     out = {
         "metric": "path segs/s expanded at 0.25px tol (batched vs plain); p50/p99 request latency",
         "value": n_seg / (ms * 1e-3),
@@ -199,7 +213,184 @@ def main():
         },
         "output_records_per_s": n_rec / (ms * 1e-3),
         "roofline": roof,
+        "tuning": tune_info,
     }
+    return out, sc, mode
+
+
+# ---------------------------------------------------------------- batched
+def batched(args, ctx, B, S, torch, np):
+    """256 map-shaped scenes: one graph-captured batched pipeline vs a loop of
+    one launch sequence per scene, same GPU, same stream, same outputs."""
+    mode = S.OUT_LINES if args.mode == "lines" else S.OUT_ARCS
+    tol = 0.25
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    log("bench: generating the batch scenes")
+    scs = S.scene_batch(4, args.batch_scenes, 100, 200_000, mode)
+    sizes = [s.n_segments() for s in scs]
+    total_seg = int(sum(sizes))
+    scenes = [ctx.encode(s, stream=stream) for s in scs]
+    # plain loop: each scene into its own slice of one buffer
+    rec = B.RECORD_BYTES[mode]
+    probe = torch.empty(16, dtype=torch.uint8, device=dev)
+    counts = []
+    for s in scenes:  # one synchronous call per scene sizes its item workspace and tells its record count
+        try:
+            counts.append(ctx.expand_into(s, probe.data_ptr(), 0, tol, mode, stream))
+        except B.StrokexError as e:
+            if e.code != B.SX_ETOOSMALL:
+                raise
+            counts.append(e.required)
+    starts = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    total_rec = int(starts[-1])
+    buf = torch.empty(max(1, total_rec) * rec, dtype=torch.uint8, device=dev)
+    cnts = torch.zeros(2 * len(scenes), dtype=torch.int64, device=dev)
+
+    def loop_step():
+        for i, s in enumerate(scenes):
+            ctx.expand_async(s, buf.data_ptr() + int(starts[i]) * rec, int(counts[i]) * rec,
+                             cnts.data_ptr() + 16 * i, tol, mode, stream=stream)
+
+    # batched: one arena, one pipeline, captured in a graph
+    batch = B.Batch(ctx)
+    batch.set(scenes, stream=stream)
+    bout, boffs, bstatus = batch.prepare(tol, mode, stream=stream)
+
+    def batch_step():
+        batch.expand_async(tol, mode, bout.data_ptr(), bout.numel(), boffs.data_ptr(), bstatus.data_ptr(),
+                           stream=stream)
+
+    with torch.cuda.stream(stream):
+        loop_step()
+        batch_step()
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        batch_step()
+    stream.synchronize()
+
+    def timed(fn, k):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        with torch.cuda.stream(stream):
+            for _ in range(k):
+                fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k, e0.elapsed_time(e1) / k
+
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            loop_step()
+            g.replay()
+    loop_ms, loop_dev = timed(loop_step, args.batch_steps)
+    graph_ms, graph_dev = timed(lambda: g.replay(), args.batch_steps)
+    # same outputs: every scene's records, bit for bit
+    o = boffs.cpu().numpy()
+    same = bool(np.array_equal(o, starts) and int(bstatus[1]) == 0
+                and torch.equal(bout[: total_rec * rec], buf[: total_rec * rec]))
+    del g
+    batch.destroy()
+    return {
+        "workload": f"{len(scs)} map/CAD scenes, log-uniform 100..200k segments, {total_seg} segments, "
+                    f"{args.mode}, tol 0.25 px",
+        "segments": total_seg,
+        "records": total_rec,
+        "min_scene": int(min(sizes)),
+        "max_scene": int(max(sizes)),
+        "batched_graph_ms": graph_ms,
+        "batched_segs_per_s": total_seg / (graph_ms * 1e-3),
+        "plain_loop_ms": loop_ms,
+        "plain_loop_segs_per_s": total_seg / (loop_ms * 1e-3),
+        "speedup": loop_ms / graph_ms,
+        "device_ms": {"batched": graph_dev, "plain_loop": loop_dev},
+        "outputs_identical": same,
+    }
+
+
+# ----------------------------------------------------------------- served
+def served(args, ctx, B, S, torch, np):
+    from paper_2405_00127_amd import serve as V
+
+    mode = S.OUT_LINES if args.mode == "lines" else S.OUT_ARCS
+    tol = 0.25
+    log("bench: generating the request pool")
+    rng = np.random.Generator(np.random.PCG64(55))
+    sizes = np.floor(np.exp(rng.uniform(math.log(1000), math.log(1_000_000), args.pool))).astype(int)
+    scs = [S.scene_map(500 + i, int(n), max(1, int(n) // 100), tol, mode) for i, n in enumerate(sizes)]
+    segs = [s.n_segments() for s in scs]
+    pool = [ctx.encode(s) for s in scs]
+    probe = torch.empty(16, dtype=torch.uint8, device="cuda:0")
+    for s in pool:  # size each scene's item workspace (the serial baseline runs them alone)
+        try:
+            ctx.expand_into(s, probe.data_ptr(), 0, tol, mode)
+        except B.StrokexError as e:
+            if e.code != B.SX_ETOOSMALL:
+                raise
+    # warm the server's slots (arena and workspace growth happen here, untimed)
+    V.run_load(ctx, pool, segs, 1e6, len(pool), tol, mode, seed=1, max_seconds=30.0)
+    points = []
+    for qps in args.qps:
+        n = int(max(50, min(2000, qps * args.serve_seconds)))
+        log(f"bench: serving at {qps} req/s ({n} requests)")
+        srv = V.run_load(ctx, pool, segs, qps, n, tol, mode, seed=7, max_seconds=args.serve_seconds)
+        ser = V.run_serial(ctx, pool, segs, qps, n, tol, mode, seed=7, max_seconds=args.serve_seconds)
+        points.append({"qps": qps, "served": srv, "serial_fifo": ser})
+        log(f"bench:   served {srv}")
+        log(f"bench:   serial {ser}")
+    return {
+        "workload": f"Poisson arrivals, requests log-uniform 1k..1M segments from a pool of {len(pool)} "
+                    f"encoded map scenes (mean {np.mean(segs):.0f} segments), {args.mode}, tol 0.25 px",
+        "points": points,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", choices=["lines", "arcs"], default="lines")
+    ap.add_argument("--segments", type=int, default=1_000_000)
+    ap.add_argument("--paths", type=int, default=10_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
+    ap.add_argument("--piece-waves", type=int, default=None)
+    ap.add_argument("--chunk-k", type=int, default=None)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-scenes", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--qps", type=float, nargs="*", default=[100.0, 1000.0, 5000.0])
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "stroke expansion of independent scenes would shard by scene, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+    from paper_2405_00127_amd import build as PB
+    from paper_2405_00127_amd import scenes as S
+
+    if not os.path.exists(B.LIB_PATH):
+        PB.build()
+    torch.cuda.set_device(0)
+    ctx = B.Context(0)
+    out, sc, mode = plain(args, ctx, B, S, torch, np)
+    if not args.no_batched:
+        out["batched"] = batched(args, ctx, B, S, torch, np)
+        log(f"bench: batched {out['batched']}")
+    if not args.no_served:
+        out["served"] = served(args, ctx, B, S, torch, np)
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc, mode, args.cpu_budget)

@@ -169,6 +169,18 @@ int sx_debug_counts(sx_ctx *ctx, const sx_scene *scene, float tolerance, int out
 int sx_debug_offsets(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode,
                      uint64_t *offsets_dev, void *stream);
 
+/* Work done by the piece phase (Algorithms 1-2) on a scene, counted by an
+ * instrumented run of the same computation (synchronous; host output):
+ *   stats6[0] fit trials of the cubic bisection (Algorithm 2; lines excluded)
+ *   stats6[1] accepted Euler spiral pieces (lines included)
+ *   stats6[2] parallel-curve ranges (Sections 4-5)
+ *   stats6[3] evolute bundles (Section 6)
+ *   stats6[4] joins and caps (Algorithm 1)
+ *   stats6[5] line segments (straight pieces)
+ * Errors: SX_EINVAL, SX_EDEVICE. */
+int sx_debug_piece_stats(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, uint64_t *stats6,
+                         void *stream);
+
 /* The four phases of sx_expand_async, one kernel each, for per-kernel timing:
  *   SX_PHASE_SCAN_TAGS   tag-monoid scan (Section 8.2)
  *   SX_PHASE_PIECES      per-segment decisions (Algorithms 1-2) in FP64:
@@ -182,6 +194,60 @@ int sx_debug_offsets(sx_ctx *ctx, const sx_scene *scene, float tolerance, int ou
 enum { SX_PHASE_SCAN_TAGS = 0, SX_PHASE_PIECES = 1, SX_PHASE_SCAN_COUNTS = 2, SX_PHASE_RECORDS = 3 };
 int sx_run_phase(sx_ctx *ctx, const sx_scene *scene, int phase, float tolerance, int output_mode, void *out_dev,
                  uint64_t out_capacity_bytes, void *stream);
+
+/* ---- Batches: many scenes in one pipeline launch -------------------------
+ * A batch owns a device arena into which sx_batch_set concatenates the
+ * streams of n already encoded scenes (tags, points, styles, transforms, path
+ * maps; Section 8.2).  Every scene starts a new path, style and transform, so
+ * the tag-monoid scan of the concatenation gives each segment the same path,
+ * style, transform and neighbours it has in its own scene: the outline of a
+ * scene is the same alone and in a batch, bit for bit, and its records keep
+ * the scene's own input path indices. */
+typedef struct sx_batch sx_batch;
+int sx_batch_create(sx_ctx *ctx, sx_batch **out);
+/* Waits for the batch's streams, then frees it and its arena. */
+int sx_batch_destroy(sx_ctx *ctx, sx_batch *batch);
+/* Gather scenes[0..n) (n <= 65535, all of ctx) into the arena, ordered on
+ * `stream`: one descriptor upload and one gather kernel.  The arena grows
+ * (synchronous allocation) when the scenes need more room than it has; it
+ * never shrinks.  The scenes must stay alive until the gather has run on
+ * `stream`; after that the batch does not read them.
+ * Errors: SX_EINVAL (null or foreign scene, n too large, sizes over 2^32),
+ * SX_ENOMEM, SX_EDEVICE. */
+int sx_batch_set(sx_ctx *ctx, sx_batch *batch, const sx_scene *const *scenes, uint32_t n, void *stream);
+/* Number of scenes set and the arena as a scene (owned by the batch: it may
+ * be passed to sx_expand, e.g. to size the output and the item workspace,
+ * but not to sx_scene_release or sx_batch_set). */
+int sx_batch_info(const sx_batch *batch, uint32_t *n_scenes, sx_scene **arena);
+/* Expand every scene of the batch in one pipeline (the kernels of
+ * sx_expand_async over the arena, then one kernel for the per-scene
+ * offsets); no host synchronisation or allocation, capturable in a HIP graph.
+ *   out_dev / out_capacity_bytes  device output, records of scene s at
+ *                                 [scene_offsets[s], scene_offsets[s+1]);
+ *   scene_offsets_dev             device, n_scenes + 1 uint64_t;
+ *   status_dev                    device, 2 uint64_t as out_count_dev of
+ *                                 sx_expand_async (total records; 0 or the
+ *                                 item workspace needed).
+ * Nothing is emitted when the total exceeds the capacity or the workspace is
+ * too small (one sx_expand on the arena resizes it).
+ * Errors: SX_EINVAL (bad tolerance or mode, null pointers), SX_EDEVICE. */
+int sx_batch_expand(sx_ctx *ctx, sx_batch *batch, float tolerance, int output_mode, void *out_dev,
+                    uint64_t out_capacity_bytes, uint64_t *scene_offsets_dev, uint64_t *status_dev, void *stream);
+
+/* Launch parameters of a context (used by every later call on it; the
+ * outline does not depend on them):
+ *   piece_waves  1..3: waves per SIMD the piece kernel's register allocation
+ *                allows (more waves hide more latency but spill more);
+ *   chunk_k      1..255: records per emission item chunk (work per thread of
+ *                the record kernel).
+ * Defaults {2, 16}.  Errors: SX_EINVAL (out of range, reserved fields != 0). */
+typedef struct {
+    uint32_t piece_waves;
+    uint32_t chunk_k;
+    uint32_t reserved0, reserved1; /* must be 0 */
+} sx_tuning;
+int sx_set_tuning(sx_ctx *ctx, const sx_tuning *tuning);
+int sx_get_tuning(const sx_ctx *ctx, sx_tuning *tuning);
 
 /* Scan primitive on its own: exclusive prefix sum of n uint32 values into
  * n + 1 uint64 (device pointers), single-pass decoupled look-back. */

@@ -41,6 +41,11 @@ class _Paths(C.Structure):
                 ("style_ix", C.c_void_p), ("xform_ix", C.c_void_p), ("n_paths", C.c_uint32)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("reserved0", C.c_uint32),
+                ("reserved1", C.c_uint32)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -75,6 +80,14 @@ def lib():
                 "sx_debug_offsets": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
                 "sx_scan_u32": (C.c_int, [vp, vp, vp, u32, vp]),
                 "sx_run_phase": (C.c_int, [vp, vp, C.c_int, C.c_float, C.c_int, vp, u64, vp]),
+                "sx_set_tuning": (C.c_int, [vp, C.POINTER(_Tuning)]),
+                "sx_batch_create": (C.c_int, [vp, C.POINTER(vp)]),
+                "sx_debug_piece_stats": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
+                "sx_batch_destroy": (C.c_int, [vp, vp]),
+                "sx_batch_set": (C.c_int, [vp, vp, vp, u32, vp]),
+                "sx_batch_info": (C.c_int, [vp, vp, C.POINTER(vp)]),
+                "sx_batch_expand": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, u64, vp, vp, vp]),
+                "sx_get_tuning": (C.c_int, [vp, C.POINTER(_Tuning)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -215,6 +228,25 @@ class Context:
                 out = torch.empty(int(e.required * 1.25 + 1) * rec, dtype=torch.uint8, device=out.device)
         return out[: n * rec].view(torch.float32).view(-1, rec // 4), n, out
 
+    def set_tuning(self, piece_waves: int, chunk_k: int):
+        t = _Tuning(int(piece_waves), int(chunk_k), 0, 0)
+        self._check(lib().sx_set_tuning(C.c_void_p(self.h), C.byref(t)), "sx_set_tuning")
+
+    def get_tuning(self):
+        t = _Tuning()
+        self._check(lib().sx_get_tuning(C.c_void_p(self.h), C.byref(t)), "sx_get_tuning")
+        return {"piece_waves": t.piece_waves, "chunk_k": t.chunk_k}
+
+    def piece_stats(self, scene: Scene, tolerance=None, mode=None, stream=None) -> dict:
+        """Work counts of the piece phase (instrumented run; synchronous)."""
+        tol = scene.src.tolerance if tolerance is None else tolerance
+        mode = scene.src.output_mode if mode is None else mode
+        st = (C.c_uint64 * 6)()
+        self._check(lib().sx_debug_piece_stats(C.c_void_p(self.h), C.c_void_p(scene.h), float(tol), int(mode), st,
+                                               _stream_ptr(stream)), "sx_debug_piece_stats")
+        keys = ["trials", "pieces", "ranges", "evolutes", "joins", "lines"]
+        return {k: int(v) for k, v in zip(keys, st)}
+
     def run_phase(self, scene: Scene, phase: int, tolerance: float, mode: int, out_ptr: int = 0,
                   capacity_bytes: int = 0, stream=None):
         rc = lib().sx_run_phase(C.c_void_p(self.h), C.c_void_p(scene.h), int(phase), float(tolerance), int(mode),
@@ -257,6 +289,86 @@ class Context:
         self._check(lib().sx_scan_u32(C.c_void_p(self.h), C.c_void_p(values.data_ptr()), C.c_void_p(out.data_ptr()),
                                       n, _stream_ptr(stream)), "sx_scan_u32")
         return out
+
+
+class Batch:
+    """Many encoded scenes concatenated in one device arena and expanded by
+    one pipeline (``sx_batch_*``).  Keeps the member scenes alive."""
+
+    def __init__(self, ctx: "Context"):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._check(lib().sx_batch_create(C.c_void_p(ctx.h), C.byref(h)), "sx_batch_create")
+        self.h = h.value
+        self.scenes = []
+
+    def set(self, scenes, stream=None):
+        arr = (C.c_void_p * max(1, len(scenes)))(*[sc.h for sc in scenes])
+        self.ctx._check(lib().sx_batch_set(C.c_void_p(self.ctx.h), C.c_void_p(self.h), arr, len(scenes),
+                                           _stream_ptr(stream)), "sx_batch_set")
+        self.scenes = list(scenes)
+
+    @property
+    def n_scenes(self) -> int:
+        return len(self.scenes)
+
+    def arena(self) -> "Scene":
+        """The arena as a scene handle (owned by the batch: never released)."""
+        a = C.c_void_p()
+        n = C.c_uint32()
+        self.ctx._check(lib().sx_batch_info(C.c_void_p(self.h), C.byref(n), C.byref(a)), "sx_batch_info")
+        return _ArenaScene(self.ctx, a.value)
+
+    def expand_async(self, tolerance: float, mode: int, out_ptr: int, capacity_bytes: int, scene_offsets_ptr: int,
+                     status_ptr: int, stream=None):
+        rc = lib().sx_batch_expand(C.c_void_p(self.ctx.h), C.c_void_p(self.h), float(tolerance), int(mode),
+                                   C.c_void_p(out_ptr), int(capacity_bytes), C.c_void_p(scene_offsets_ptr),
+                                   C.c_void_p(status_ptr), _stream_ptr(stream))
+        self.ctx._check(rc, "sx_batch_expand")
+
+    def prepare(self, tolerance: float, mode: int, stream=None, headroom: float = 1.0):
+        """Size the output and the arena's item workspace with one synchronous
+        expansion; returns (output uint8 tensor, scene offsets tensor (n+1),
+        status tensor (2)), all device int64 / uint8 torch tensors."""
+        import torch
+
+        dev = f"cuda:{self.ctx.device}"
+        arena = self.arena()
+        rec = RECORD_BYTES[mode]
+        probe = torch.empty(16, dtype=torch.uint8, device=dev)
+        try:
+            n = self.ctx.expand_into(arena, probe.data_ptr(), 0, tolerance, mode, stream)
+        except StrokexError as e:
+            if e.code != SX_ETOOSMALL:
+                raise
+            n = e.required
+        out = torch.empty(max(1, int(n * headroom)) * rec, dtype=torch.uint8, device=dev)
+        offs = torch.zeros(self.n_scenes + 1, dtype=torch.int64, device=dev)
+        status = torch.zeros(2, dtype=torch.int64, device=dev)
+        return out, offs, status
+
+    def destroy(self):
+        if self.h:
+            lib().sx_batch_destroy(C.c_void_p(self.ctx.h), C.c_void_p(self.h))
+            self.h = None
+            self.scenes = []
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class _ArenaScene:
+    """Scene-shaped view of a batch arena (for sx_expand sizing)."""
+
+    def __init__(self, ctx, h):
+        self.ctx = ctx
+        self.h = h
+        n = C.c_uint32()
+        lib().sx_scene_info(C.c_void_p(h), C.byref(n), None, None, None, None)
+        self.n_tags = n.value
 
 
 def records_to_numpy(recs_tensor, mode) -> np.ndarray:

@@ -17,6 +17,7 @@
 struct sx_ctx {
     int device = 0;
     std::string err;
+    sx_tuning tune = {2u, 16u, 0u, 0u};
     uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, items needed
 };
 
@@ -40,12 +41,25 @@ struct sx_scene {
     sx::WsCtl* d_ws_ctl = nullptr;
     uint32_t region_cap = 0;  // slots per piece tile
     uint64_t ovf_cap = 0;     // shared overflow slots
-    uint32_t chunk_k = 16;    // records per item chunk
+    // allocated capacities (a batch arena is reused for smaller contents)
+    uint32_t cap_tags = 0, cap_pts = 0, cap_styles = 0, cap_xforms = 0, cap_paths = 0;
+    bool allocated = false;
+    bool batch_arena = false;  // owned by a batch, released with it
     hipStream_t last_stream = nullptr;
+};
+
+struct sx_batch {
+    sx_ctx* ctx = nullptr;
+    sx_scene* arena = nullptr;
+    uint32_t n_scenes = 0, cap_scenes = 0;
+    sx::GatherDesc* d_desc = nullptr;  // device copy of the descriptors
+    sx::GatherDesc* h_desc = nullptr;  // pinned staging
+    hipEvent_t staged = nullptr;       // recorded after the last staging upload
 };
 
 namespace {
 
+constexpr uint32_t kMaxBatchScenes = 65535;
 constexpr uint32_t kRegionPerTag = 8;      // initial item slots per tag
 constexpr uint64_t kMinOverflow = 65536;   // initial shared overflow slots (minimum)
 
@@ -116,8 +130,68 @@ hipError_t size_workspace(sx_scene* s, uint32_t region_per_tag, uint64_t ovf) {
     s->d_items = nullptr;
     s->region_cap = region_per_tag * sx::tag_block();
     s->ovf_cap = ovf;
-    const uint64_t slots = (uint64_t)sx::piece_tiles(s->n_tags) * s->region_cap + ovf;
+    const uint64_t slots = (uint64_t)sx::piece_tiles(s->cap_tags) * s->region_cap + ovf;
     return dalloc(&s->d_items, slots * sizeof(sx::Item));
+}
+
+// Grow the scene's device buffers to hold at least the given sizes (the
+// contents are rewritten by the caller).  Scan status words and control
+// blocks are zeroed whenever they are (re)allocated; the item workspace keeps
+// its slots per tag.  Ordered on st; allocation is synchronous.
+hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t n_styles, uint32_t n_xforms,
+                         uint32_t n_paths, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+    };
+    auto regrow = [&](auto** p, size_t bytes) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+        A(dalloc(p, bytes));
+    };
+    const bool first = !s->allocated;
+    if (first || n_tags > s->cap_tags) {
+        const uint32_t c = n_tags;
+        const size_t ntag_pad = ((size_t)c + 16 + 15) & ~(size_t)15;
+        regrow(&s->d_tags, ntag_pad);
+        regrow(&s->d_mon, 4 * (size_t)c * sizeof(uint32_t));
+        regrow(&s->d_counts, ((size_t)c + 16) * sizeof(uint32_t));
+        regrow(&s->d_offsets, ((size_t)c + 1) * sizeof(uint64_t));
+        regrow(&s->d_status_tags, sx::scan_status_bytes(c));
+        regrow(&s->d_status_counts, sx::scan_status_bytes(c));
+        regrow(&s->d_tile_n, (size_t)sx::piece_tiles(c) * sizeof(uint32_t));
+        if (e != hipSuccess) return e;
+        s->cap_tags = c;
+        const uint32_t per_tag = s->region_cap ? s->region_cap / sx::tag_block() : kRegionPerTag;
+        A(size_workspace(s, per_tag, std::max<uint64_t>(std::max<uint64_t>(c, s->ovf_cap), kMinOverflow)));
+        A(hipMemsetAsync(s->d_tags, 0, ntag_pad, st));
+        A(hipMemsetAsync(s->d_status_tags, 0, sx::scan_status_bytes(c), st));
+        A(hipMemsetAsync(s->d_status_counts, 0, sx::scan_status_bytes(c), st));
+    }
+    if (first || n_pts > s->cap_pts) {
+        regrow(&s->d_pts, (size_t)n_pts * sizeof(float2));
+        s->cap_pts = n_pts;
+    }
+    if (first || n_styles > s->cap_styles) {
+        regrow(&s->d_styles, (size_t)n_styles * sizeof(sx::StyleD));
+        s->cap_styles = n_styles;
+    }
+    if (first || n_xforms > s->cap_xforms) {
+        regrow(&s->d_xforms, (size_t)n_xforms * 6 * sizeof(float));
+        s->cap_xforms = n_xforms;
+    }
+    if (first || n_paths > s->cap_paths) {
+        regrow(&s->d_path_map, (size_t)n_paths * sizeof(uint32_t));
+        s->cap_paths = n_paths;
+    }
+    if (first) {
+        A(dalloc(&s->d_scan_ctl, 2 * sx::scan_ctl_bytes()));
+        A(dalloc(&s->d_ws_ctl, sizeof(sx::WsCtl)));
+        A(hipMemsetAsync(s->d_scan_ctl, 0, 2 * sx::scan_ctl_bytes(), st));
+        A(hipMemsetAsync(s->d_ws_ctl, 0, sizeof(sx::WsCtl), st));
+    }
+    if (e == hipSuccess) s->allocated = true;
+    return e;
 }
 
 bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
@@ -141,7 +215,8 @@ int run_counts(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, hipStream_t s
     if ((e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st)) !=
         hipSuccess)
         return hip_fail(ctx, e, "scan_tags launch");
-    if ((e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, st)) != hipSuccess)
+    if ((e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, (int)ctx->tune.piece_waves, st)) !=
+        hipSuccess)
         return hip_fail(ctx, e, "pieces launch");
     if ((e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
                                     s->d_status_counts, st)) != hipSuccess)
@@ -191,6 +266,21 @@ int sx_ctx_destroy(sx_ctx* ctx) {
     return SX_OK;
 }
 
+int sx_set_tuning(sx_ctx* ctx, const sx_tuning* t) {
+    if (!ctx || !t) return SX_EINVAL;
+    if (t->piece_waves < 1 || t->piece_waves > 3) return fail(ctx, SX_EINVAL, "piece_waves must be 1, 2 or 3");
+    if (t->chunk_k < 1 || t->chunk_k > 255) return fail(ctx, SX_EINVAL, "chunk_k must be in [1, 255]");
+    if (t->reserved0 || t->reserved1) return fail(ctx, SX_EINVAL, "reserved tuning fields must be 0");
+    ctx->tune = *t;
+    return SX_OK;
+}
+
+int sx_get_tuning(const sx_ctx* ctx, sx_tuning* t) {
+    if (!ctx || !t) return SX_EINVAL;
+    *t = ctx->tune;
+    return SX_OK;
+}
+
 const char* sx_last_error(const sx_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, uint32_t n_styles,
@@ -232,34 +322,14 @@ int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, 
     s->n_styles = (uint32_t)sd.size();
     s->n_xforms = (uint32_t)enc.xform_stream.size();
     hipStream_t st = (hipStream_t)stream;
-    const size_t ntag_pad = ((size_t)s->n_tags + 16 + 15) & ~(size_t)15;
-    hipError_t e = hipSuccess;
-    auto A = [&](hipError_t r) {
-        if (e == hipSuccess) e = r;
-    };
-    A(dalloc(&s->d_tags, ntag_pad));
-    A(dalloc(&s->d_pts, (size_t)s->n_pts * sizeof(float2)));
-    A(dalloc(&s->d_styles, sd.size() * sizeof(sx::StyleD)));
-    A(dalloc(&s->d_xforms, xd.size() * sizeof(float)));
-    A(dalloc(&s->d_path_map, enc.path_map.size() * sizeof(uint32_t)));
-    A(dalloc(&s->d_mon, 4 * (size_t)s->n_tags * sizeof(uint32_t)));
-    A(dalloc(&s->d_counts, ((size_t)s->n_tags + 16) * sizeof(uint32_t)));
-    A(dalloc(&s->d_offsets, ((size_t)s->n_tags + 1) * sizeof(uint64_t)));
-    A(dalloc(&s->d_scan_ctl, 2 * sx::scan_ctl_bytes()));
-    A(dalloc(&s->d_status_tags, sx::scan_status_bytes(s->n_tags)));
-    A(dalloc(&s->d_status_counts, sx::scan_status_bytes(s->n_tags)));
-    A(dalloc(&s->d_tile_n, (size_t)sx::piece_tiles(s->n_tags) * sizeof(uint32_t)));
-    A(dalloc(&s->d_ws_ctl, sizeof(sx::WsCtl)));
-    A(size_workspace(s, kRegionPerTag, std::max<uint64_t>(s->n_tags, kMinOverflow)));
+    hipError_t e = reserve_scene(s, s->n_tags, s->n_pts, s->n_styles, s->n_xforms, s->n_paths, st);
     if (e != hipSuccess) {
         free_scene(s);
         return hip_fail(ctx, e, "scene allocation");
     }
-    A(hipMemsetAsync(s->d_tags, 0, ntag_pad, st));
-    A(hipMemsetAsync(s->d_scan_ctl, 0, 2 * sx::scan_ctl_bytes(), st));
-    A(hipMemsetAsync(s->d_status_tags, 0, sx::scan_status_bytes(s->n_tags), st));
-    A(hipMemsetAsync(s->d_status_counts, 0, sx::scan_status_bytes(s->n_tags), st));
-    A(hipMemsetAsync(s->d_ws_ctl, 0, sizeof(sx::WsCtl), st));
+    auto A = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+    };
     if (s->n_tags) A(hipMemcpyAsync(s->d_tags, enc.tags.data(), s->n_tags, hipMemcpyHostToDevice, st));
     if (s->n_pts)
         A(hipMemcpyAsync(s->d_pts, enc.data.data(), enc.data.size() * sizeof(float), hipMemcpyHostToDevice, st));
@@ -282,6 +352,7 @@ int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, 
 int sx_scene_release(sx_ctx* ctx, sx_scene* scene) {
     if (!scene) return SX_OK;
     if (ctx && scene->ctx != ctx) return fail(ctx, SX_EINVAL, "scene belongs to another context");
+    if (scene->batch_arena) return fail(ctx, SX_EINVAL, "a batch arena is released with its batch");
     (void)hipStreamSynchronize(scene->last_stream);
     free_scene(scene);
     return SX_OK;
@@ -318,7 +389,7 @@ int sx_expand_async(sx_ctx* ctx, const sx_scene* scene, float tolerance, int out
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(scene)->last_stream = st;
-    cfg.K = scene->chunk_k;
+    cfg.K = ctx->tune.chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     if (scene->n_tags == 0) {
         hipError_t e = hipMemsetAsync(out_count_dev, 0, 2 * sizeof(uint64_t), st);
@@ -336,7 +407,7 @@ int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mo
     hipStream_t st = (hipStream_t)stream;
     sx_scene* s = const_cast<sx_scene*>(scene);
     s->last_stream = st;
-    cfg.K = s->chunk_k;
+    cfg.K = ctx->tune.chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     *out_count = 0;
     if (s->n_tags == 0) return SX_OK;
@@ -369,7 +440,7 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
     sx::Cfg cfg;
     if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (s->n_tags == 0) return SX_OK;
-    cfg.K = s->chunk_k;
+    cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(s)->last_stream = st;
     char* ctl = (char*)s->d_scan_ctl;
@@ -380,7 +451,7 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
             e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
             break;
         case SX_PHASE_PIECES:
-            e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, st);
+            e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, (int)ctx->tune.piece_waves, st);
             break;
         case SX_PHASE_SCAN_COUNTS:
             e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
@@ -395,6 +466,174 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
             return fail(ctx, SX_EINVAL, "bad phase");
     }
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "phase launch");
+}
+
+int sx_batch_create(sx_ctx* ctx, sx_batch** out) {
+    if (!ctx || !out) return SX_EINVAL;
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SX_EDEVICE, "hipSetDevice");
+    sx_batch* b = new (std::nothrow) sx_batch();
+    if (!b) return fail(ctx, SX_ENOMEM, "batch alloc");
+    b->ctx = ctx;
+    b->arena = new (std::nothrow) sx_scene();
+    if (!b->arena) {
+        delete b;
+        return fail(ctx, SX_ENOMEM, "batch alloc");
+    }
+    b->arena->ctx = ctx;
+    b->arena->batch_arena = true;
+    hipError_t e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+    if (e == hipSuccess) e = reserve_scene(b->arena, 0, 0, 0, 0, 0, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+        if (b->staged) (void)hipEventDestroy(b->staged);
+        free_scene(b->arena);
+        delete b;
+        return hip_fail(ctx, e, "batch creation");
+    }
+    *out = b;
+    return SX_OK;
+}
+
+int sx_batch_destroy(sx_ctx* ctx, sx_batch* b) {
+    if (!b) return SX_OK;
+    if (ctx && b->ctx != ctx) return fail(ctx, SX_EINVAL, "batch belongs to another context");
+    (void)hipStreamSynchronize(b->arena->last_stream);
+    (void)hipEventSynchronize(b->staged);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->h_desc) (void)hipHostFree(b->h_desc);
+    (void)hipEventDestroy(b->staged);
+    free_scene(b->arena);
+    delete b;
+    return SX_OK;
+}
+
+int sx_batch_set(sx_ctx* ctx, sx_batch* b, const sx_scene* const* scenes, uint32_t n, void* stream) {
+    if (!ctx || !b || (n && !scenes)) return SX_EINVAL;
+    if (b->ctx != ctx) return fail(ctx, SX_EINVAL, "batch belongs to another context");
+    if (n > kMaxBatchScenes) return fail(ctx, SX_EINVAL, "too many scenes in one batch");
+    uint64_t nt = 0, np = 0, ns = 0, nx = 0, npa = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        const sx_scene* sc = scenes[i];
+        if (!sc || sc->ctx != ctx) return fail(ctx, SX_EINVAL, "null scene or scene of another context");
+        if (sc->batch_arena) return fail(ctx, SX_EINVAL, "a batch arena cannot be batched");
+        nt += sc->n_tags;
+        np += sc->n_pts;
+        ns += sc->n_styles;
+        nx += sc->n_xforms;
+        npa += sc->n_paths;
+    }
+    if (nt > UINT32_MAX - 64 || np > UINT32_MAX || ns > UINT32_MAX || nx > UINT32_MAX / 6 || npa > UINT32_MAX)
+        return fail(ctx, SX_EINVAL, "batch exceeds 32-bit stream sizes");
+    hipStream_t st = (hipStream_t)stream;
+    // the staging buffer is reused: wait until its previous upload is done
+    hipError_t e = hipEventSynchronize(b->staged);
+    if (e == hipSuccess && n > b->cap_scenes) {
+        if (b->d_desc) (void)hipFree(b->d_desc);
+        if (b->h_desc) (void)hipHostFree(b->h_desc);
+        b->d_desc = nullptr;
+        b->h_desc = nullptr;
+        b->cap_scenes = 0;
+        e = hipMalloc((void**)&b->d_desc, (size_t)n * sizeof(sx::GatherDesc));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&b->h_desc, (size_t)n * sizeof(sx::GatherDesc), hipHostMallocDefault);
+        if (e == hipSuccess) b->cap_scenes = n;
+    }
+    if (e == hipSuccess)
+        e = reserve_scene(b->arena, (uint32_t)nt, (uint32_t)np, (uint32_t)ns, (uint32_t)nx, (uint32_t)npa, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "batch allocation");
+    uint32_t tb = 0, pb = 0, sb = 0, xb = 0, ab = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        const sx_scene* sc = scenes[i];
+        sx::GatherDesc& d = b->h_desc[i];
+        d.tags = sc->d_tags;
+        d.pts = sc->d_pts;
+        d.styles = sc->d_styles;
+        d.xforms = sc->d_xforms;
+        d.path_map = sc->d_path_map;
+        d.n_tags = sc->n_tags;
+        d.n_pts = sc->n_pts;
+        d.n_styles = sc->n_styles;
+        d.n_xforms = sc->n_xforms;
+        d.n_paths = sc->n_paths;
+        d.tag_base = tb;
+        d.pt_base = pb;
+        d.style_base = sb;
+        d.xform_base = xb;
+        d.path_base = ab;
+        d.pad = 0;
+        tb += sc->n_tags;
+        pb += sc->n_pts;
+        sb += sc->n_styles;
+        xb += sc->n_xforms;
+        ab += sc->n_paths;
+    }
+    sx_scene* a = b->arena;
+    a->n_tags = tb;
+    a->n_pts = pb;
+    a->n_styles = sb;
+    a->n_xforms = xb;
+    a->n_paths = ab;
+    b->n_scenes = n;
+    a->last_stream = st;
+    if (n) {
+        e = hipMemcpyAsync(b->d_desc, b->h_desc, (size_t)n * sizeof(sx::GatherDesc), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(b->staged, st);
+        if (e == hipSuccess)
+            e = sx::launch_gather(b->d_desc, n, a->d_tags, a->d_pts, a->d_styles, a->d_xforms, a->d_path_map, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "batch gather");
+    }
+    return SX_OK;
+}
+
+int sx_batch_info(const sx_batch* b, uint32_t* n_scenes, sx_scene** arena) {
+    if (!b) return SX_EINVAL;
+    if (n_scenes) *n_scenes = b->n_scenes;
+    if (arena) *arena = b->arena;
+    return SX_OK;
+}
+
+int sx_batch_expand(sx_ctx* ctx, sx_batch* b, float tolerance, int output_mode, void* out_dev,
+                    uint64_t out_capacity_bytes, uint64_t* scene_offsets_dev, uint64_t* status_dev, void* stream) {
+    if (!ctx || !b || !scene_offsets_dev || !status_dev) return SX_EINVAL;
+    if (b->ctx != ctx) return fail(ctx, SX_EINVAL, "batch belongs to another context");
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
+    cfg.K = ctx->tune.chunk_k;
+    hipStream_t st = (hipStream_t)stream;
+    sx_scene* a = b->arena;
+    a->last_stream = st;
+    const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
+    if (a->n_tags) {
+        int r = run_all(ctx, a, cfg, out_dev, out_capacity_bytes / rec, status_dev, st);
+        if (r != SX_OK) return r;
+    } else {
+        hipError_t e = sx::launch_finish(a->d_offsets, 0, workspace(a), status_dev, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "finish launch");
+    }
+    hipError_t e = sx::launch_scene_offsets(a->d_offsets, b->d_desc, b->n_scenes, a->n_tags, scene_offsets_dev, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "scene offsets");
+}
+
+int sx_debug_piece_stats(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint64_t* stats6,
+                         void* stream) {
+    if (!ctx || !s || !stats6) return SX_EINVAL;
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    for (int j = 0; j < 6; j++) stats6[j] = 0;
+    if (s->n_tags == 0) return SX_OK;
+    cfg.K = ctx->tune.chunk_k;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long* d = nullptr;
+    char* ctl = (char*)s->d_scan_ctl;
+    hipError_t e = hipMalloc((void**)&d, 6 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemsetAsync(d, 0, 6 * sizeof(unsigned long long), st);
+    if (e == hipSuccess) e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
+    if (e == hipSuccess) e = sx::launch_piece_stats(view(s), cfg, workspace(s), s->d_counts, d, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(stats6, d, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (d) (void)hipFree(d);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "piece stats");
 }
 
 int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void* stream) {
@@ -413,7 +652,7 @@ int sx_debug_counts(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_
     sx::Cfg cfg;
     if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (s->n_tags == 0) return SX_OK;
-    cfg.K = s->chunk_k;
+    cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     int r = run_counts(ctx, s, cfg, st);
     if (r != SX_OK) return r;
@@ -432,7 +671,7 @@ int sx_debug_offsets(sx_ctx* ctx, const sx_scene* s, float tolerance, int output
         hipError_t e = hipMemsetAsync(offsets_dev, 0, sizeof(uint64_t), st);
         return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
     }
-    cfg.K = s->chunk_k;
+    cfg.K = ctx->tune.chunk_k;
     int r = run_counts(ctx, s, cfg, st);
     if (r != SX_OK) return r;
     hipError_t e = hipMemcpyAsync(offsets_dev, s->d_offsets, ((size_t)s->n_tags + 1) * sizeof(uint64_t),

@@ -210,10 +210,12 @@ SX_FN V2 evolute_end(const ES& es, bool at_end) {
     return f32(p - n * (es.L / kn));
 }
 
-// FP32 copies of an ES for the record pass: p0, chord/Z(1), p1 - p0, k0, k1, L, base
+// FP32 copies of an ES for the record pass: p0, chord / Z(1) (or p1 - p0 for
+// a pivot), k0, k1, L, base angle
 SX_FN void set_es_f(const ES& es, float* d) {
-    d[0] = es.fp0.x; d[1] = es.fp0.y; d[2] = es.frot.x; d[3] = es.frot.y; d[4] = es.fd.x; d[5] = es.fd.y;
-    d[6] = es.fk0; d[7] = es.fk1; d[8] = es.fL; d[9] = es.fbase;
+    V2 r = es.pivot ? es.fd : es.frot;
+    d[0] = es.fp0.x; d[1] = es.fp0.y; d[2] = r.x; d[3] = r.y;
+    d[4] = es.fk0; d[5] = es.fk1; d[6] = es.fL; d[7] = es.fbase;
 }
 
 // ------------------------------------------- subdivision density integral
@@ -266,39 +268,13 @@ struct XSeg {
     double dF;   // F increment over the piece
     int br;
 };
-constexpr int kMaxXSeg = 7;
-SX_HD inline int split_x(XP xa, XP xb, double dx_total, XSeg* segs) {
-    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
-    int n = 0;
-    XP cur = xa;
-    bool up = xb.x > xa.x;
-    for (int kk = 0; kk < 6; kk++) {
-        int k = up ? kk : 5 - kk;
-        bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
-        if (inside) {
-            XP nb = bp_xp(bps[k]);
-            double l = bps[k] - cur.x;
-            segs[n].a = cur;
-            segs[n].len = l;
-            segs[n].br = branch_of(fabs(cur.x + 0.5 * l));
-            segs[n].dF = branch_dd(segs[n].br, cur, nb, l) * l;
-            cur = nb;
-            n++;
-        }
-    }
-    double l = (n == 0) ? dx_total : xb.x - cur.x;
-    segs[n].a = cur;
-    segs[n].len = l;
-    segs[n].br = (n == 0) ? branch_of(fabs(0.5 * (xa.x + xb.x))) : branch_of(fabs(cur.x + 0.5 * l));
-    segs[n].dF = branch_dd(segs[n].br, cur, xb, l) * l;
-    return n + 1;
-}
-
-// Total F increment over [xa, xb]: the sum of split_x's pieces, in the same
-// order and arithmetic, without storing them.
-SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total) {
+// Total F increment over [xa, xb], split at the branch breaks of f_approx
+// (the pieces in order of x from xa); *dxs receives the FP32 sum of
+// the pieces' lengths.
+SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs) {
     const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
     double dF = 0.0;
+    float ls = 0.0f;
     int n = 0;
     XP cur = xa;
     bool up = xb.x > xa.x;
@@ -309,13 +285,55 @@ SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total) {
             XP nb = bp_xp(bps[k]);
             double l = bps[k] - cur.x;
             dF += branch_dd(branch_of(fabs(cur.x + 0.5 * l)), cur, nb, l) * l;
+            ls += (float)l;
             cur = nb;
             n++;
         }
     }
     double l = (n == 0) ? dx_total : xb.x - cur.x;
     int br = (n == 0) ? branch_of(fabs(0.5 * (xa.x + xb.x))) : branch_of(fabs(cur.x + 0.5 * l));
+    *dxs = ls + (float)l;
     return dF + branch_dd(br, cur, xb, l) * l;
+}
+
+// Piece j of that split on its own (the same values and order), and the
+// number of pieces.
+SX_HD inline int xseg_count(XP xa, XP xb) {
+    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
+    bool up = xb.x > xa.x;
+    int n = 1;
+    for (int k = 0; k < 6; k++) n += (up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x)) ? 1 : 0;
+    return n;
+}
+SX_HD inline XSeg xseg_at(XP xa, XP xb, double dx_total, int j) {
+    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
+    int n = 0;
+    XP cur = xa;
+    bool up = xb.x > xa.x;
+    XSeg sg;
+    for (int kk = 0; kk < 6; kk++) {
+        int k = up ? kk : 5 - kk;
+        bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
+        if (inside) {
+            if (n == j) {
+                XP nb = bp_xp(bps[k]);
+                double l = bps[k] - cur.x;
+                sg.a = cur;
+                sg.len = l;
+                sg.br = branch_of(fabs(cur.x + 0.5 * l));
+                sg.dF = branch_dd(sg.br, cur, nb, l) * l;
+                return sg;
+            }
+            cur = bp_xp(bps[k]);
+            n++;
+        }
+    }
+    double l = (n == 0) ? dx_total : xb.x - cur.x;
+    sg.a = cur;
+    sg.len = l;
+    sg.br = (n == 0) ? branch_of(fabs(0.5 * (xa.x + xb.x))) : branch_of(fabs(cur.x + 0.5 * l));
+    sg.dF = branch_dd(sg.br, cur, xb, l) * l;
+    return sg;
 }
 
 // Fraction of a branch segment at which F has risen by f * seg.dF
@@ -406,17 +424,23 @@ struct __align__(16) Item {
 };
 static_assert(sizeof(Item) == 128, "item layout");
 
-// offset-item payload
+// offset-item payload.  es: p0, (chord / Z(1)) or (p1 - p0) for a pivot,
+// k0, k1, L, base angle.
 struct OffsetP {
-    float fp0x, fp0y, frotx, froty, fdx, fdy, fk0, fk1, fL, fbase;  // ES
-    double hka, hkb, dx;                                              // density axis
-    float kna, knb;                                                   // normalised curvature at the range ends
+    float es[8];
     float ua, du, ub, fh;
     float Pax, Pay, Pbx, Pby;
+    float dxs;                  // FP32 sum of the branch piece lengths (density placement)
+    uint32_t pad;
+    double hka, hkb, dx, dF;    // density axis: h kappa at the ends, x length, F increment
+};
+// h = 0 placement keeps the normalised end curvatures in the hka slot
+struct KnPair {
+    float kna, knb;
 };
 // evolute-item payload
 struct EvoluteP {
-    float fp0x, fp0y, frotx, froty, fdx, fdy, fk0, fk1, fL, fbase;
+    float es[8];
     float ua, du, alpha;
     uint32_t ne;
     float E0x, E0y, E1x, E1y, Pax, Pay, Pbx, Pby;
@@ -458,14 +482,23 @@ struct Cfg {
 // counts the tag's records.  Alloc::alloc(nc) returns the first of nc
 // consecutive slots owned by the caller, or ~0 when the workspace is full
 // (the items are then dropped; the caller sees the overflow count).
-template <class Alloc>
+// With Stats, the sink also counts the work done (fit trials, accepted
+// pieces, items by kind) for the algorithmic-work figures of the roofline.
+enum { kStTrials = 0, kStPieces = 1, kStRanges = 2, kStEvolutes = 3, kStJoins = 4, kStLines = 5, kStN = 6 };
+template <class Alloc, bool Stats = false>
 struct ItemSink {
     Item* items;
     Alloc al;
     uint32_t tag;
     uint32_t n;  // records of the tag so far
+    uint32_t st[Stats ? kStN : 1];
+    static constexpr bool kStats = Stats;
     template <class P>
     SX_HD void put(uint32_t hdr, uint32_t nrec, uint32_t K, const P& p) {
+        if constexpr (Stats) {
+            const uint32_t kind = hdr & 15u;
+            st[kind == kItemOffset ? kStRanges : (kind == kItemEvolute ? kStEvolutes : kStJoins)]++;
+        }
         const uint32_t nc = chunks(nrec, K);
         const uint64_t base = al.alloc(nc);
         if (base != ~0ull) {
@@ -493,7 +526,8 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
     const double du = ub - ua;
     const double kna = es_kn(es, ua), knb = es_kn(es, ub);
     uint32_t n;
-    double hka = 0.0, hkb = 0.0, dx = 0.0;
+    double hka = 0.0, hkb = 0.0, dx = 0.0, dF = 0.0;
+    float dxs = 0.0f;
     uint32_t place = 0;
     if (!cfg.arcs) {
         double I;
@@ -514,7 +548,7 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
             hka = h * kna / es.L;
             hkb = h * knb / es.L;
             dx = -2.0 * h * es.k1 * du / es.L;
-            double dF = split_x_sum(make_xp(hka), make_xp(hkb), dx);
+            dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, &dxs);
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
             double G = (dx != 0.0) ? dF / dx : 0.0;
             I = fabs(G) * du * es.L / (2.0 * sqrt(fabs(h)));
@@ -544,9 +578,14 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
     }
     {
         OffsetP p;
-        set_es_f(es, &p.fp0x);
-        p.hka = hka; p.hkb = hkb; p.dx = dx;
-        p.kna = (float)kna; p.knb = (float)knb;
+        set_es_f(es, p.es);
+        p.hka = hka; p.hkb = hkb; p.dx = dx; p.dF = dF;
+        p.dxs = dxs;
+        p.pad = 0u;
+        if (place & kIfPlaceES) {
+            KnPair kp{(float)kna, (float)knb};
+            memcpy(&p.hka, &kp, sizeof(kp));
+        }
         p.ua = (float)ua; p.du = (float)du; p.ub = (float)ub; p.fh = (float)h;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
         uint32_t hdr = kItemOffset | (dir < 0 ? kIfDirNeg : 0u) | (cfg.arcs ? kIfArcs : 0u) |
@@ -555,7 +594,7 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
     }
     if (reversed) {
         EvoluteP p;
-        set_es_f(es, &p.fp0x);
+        set_es_f(es, p.es);
         p.ua = (float)ua; p.du = (float)du;
         p.alpha = (ra + rb > 0.0) ? (float)(ra / (ra + rb)) : 0.5f;
         p.ne = ne;
@@ -712,34 +751,45 @@ SX_FN ES es_from_f(const float* d, bool pivot) {
     ES es;
     es.fp0 = v2(d[0], d[1]);
     es.frot = v2(d[2], d[3]);
-    es.fd = v2(d[4], d[5]);
-    es.fk0 = d[6]; es.fk1 = d[7]; es.fL = d[8]; es.fbase = d[9];
+    es.fd = es.frot;
+    es.fk0 = d[4]; es.fk1 = d[5]; es.fL = d[6]; es.fbase = d[7];
     es.pivot = pivot;
     return es;
 }
 
+// Walk state over the branch pieces of an offset range's density axis.
+// Points are placed in increasing order, so the piece holding each point's
+// share of F only moves forward; the pieces are produced one at a time.
+struct XWalk {
+    XP xa, xb;
+    double dx, cum;
+    XSeg seg;
+    int j, nseg;
+    float acc_len;
+};
+
 // u of point i (0 < i < n) of an offset range
-SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, const XSeg* segs, int nseg,
-                            double dF, float dx_total) {
+SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, XWalk& w) {
     float f = (float)i / (float)n;
     float tau = f;
     if (hdr & kIfPlaceF) {
-        // walk the branch pieces to the one holding f * dF
-        double target = f * dF, cum = 0.0;
-        float acc_len = 0.0f;
-        int j = 0;
-        for (; j < nseg - 1; j++) {
-            if (fabs(cum + segs[j].dF) >= fabs(target)) break;
-            cum += segs[j].dF;
-            acc_len += (float)segs[j].len;
+        // advance to the branch piece holding f * dF
+        double target = f * p.dF;
+        while (w.j < w.nseg - 1 && !(fabs(w.cum + w.seg.dF) >= fabs(target))) {
+            w.cum += w.seg.dF;
+            w.acc_len += (float)w.seg.len;
+            w.j++;
+            w.seg = xseg_at(w.xa, w.xb, w.dx, w.j);
         }
-        float fl = (segs[j].dF != 0.0) ? (float)((target - cum) / segs[j].dF) : 0.0f;
+        float fl = (w.seg.dF != 0.0) ? (float)((target - w.cum) / w.seg.dF) : 0.0f;
         fl = fminf(fmaxf(fl, 0.0f), 1.0f);
-        float phi = (segs[j].len != 0.0) ? branch_inv_frac(segs[j], fl) : fl;
-        tau = (nseg == 1) ? phi : (acc_len + phi * (float)segs[j].len) / dx_total;
+        float phi = (w.seg.len != 0.0) ? branch_inv_frac(w.seg, fl) : fl;
+        tau = (w.nseg == 1) ? phi : (w.acc_len + phi * (float)w.seg.len) / p.dxs;
     } else if (hdr & kIfPlaceES) {
         // h = 0: uniform in |kappa|^1.5 (Section 2.2)
-        float aa = fabsf(p.kna), ab = fabsf(p.knb);
+        KnPair kp;
+        memcpy(&kp, &p.hka, sizeof(kp));
+        float aa = fabsf(kp.kna), ab = fabsf(kp.knb);
         float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
         float kap;
         if (hdr & kIfKSame) {
@@ -770,17 +820,18 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
     if (kind == kItemOffset) {
         OffsetP p;
         memcpy(&p, it.u, sizeof(p));
-        ES es = es_from_f(&p.fp0x, (hdr & kIfPivot) != 0);
-        XSeg segs[kMaxXSeg];
-        int nseg = 0;
-        double dF = 0.0;
-        float dx_total = 0.0f;
+        ES es = es_from_f(p.es, (hdr & kIfPivot) != 0);
+        XWalk w;
+        w.j = 0;
+        w.nseg = 1;
+        w.cum = 0.0;
+        w.acc_len = 0.0f;
         if (hdr & kIfPlaceF) {
-            nseg = split_x(make_xp(p.hka), make_xp(p.hkb), p.dx, segs);
-            for (int j = 0; j < nseg; j++) {
-                dF += segs[j].dF;
-                dx_total += (float)segs[j].len;
-            }
+            w.xa = make_xp(p.hka);
+            w.xb = make_xp(p.hkb);
+            w.dx = p.dx;
+            w.nseg = xseg_count(w.xa, w.xb);
+            w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
         }
         const uint32_t n = it.ntot;
         const bool neg = (hdr & kIfDirNeg) != 0;
@@ -791,7 +842,7 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
             uprev = p.ua;
             prev = v2(p.Pax, p.Pay);
         } else {
-            uprev = offset_u(p, hdr, it.k0, n, segs, nseg, dF, dx_total);
+            uprev = offset_u(p, hdr, it.k0, n, w);
             prev = offset_point_f(es, p.fh, uprev);
         }
         for (uint32_t r = 0; r < it.n; r++) {
@@ -802,7 +853,7 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
                 u = p.ub;
                 P = v2(p.Pbx, p.Pby);
             } else {
-                u = offset_u(p, hdr, i, n, segs, nseg, dF, dx_total);
+                u = offset_u(p, hdr, i, n, w);
                 P = offset_point_f(es, p.fh, u);
             }
             if (!arcs) {
@@ -817,7 +868,7 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
     } else if (kind == kItemEvolute) {
         EvoluteP p;
         memcpy(&p, it.u, sizeof(p));
-        ES es = es_from_f(&p.fp0x, (hdr & kIfPivot) != 0);
+        ES es = es_from_f(p.es, (hdr & kIfPivot) != 0);
         const uint32_t ne = p.ne;
         const bool Dneg = (hdr & kIfDneg) != 0;
         const V2 E0 = v2(p.E0x, p.E0y), E1 = v2(p.E1x, p.E1y), Pa = v2(p.Pax, p.Pay), Pb = v2(p.Pbx, p.Pby);
@@ -994,7 +1045,12 @@ SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s, bool line) {
             ok = len_ok && hodo_ok && (err <= cfg.tau_fit);
         }
         bool forced = dt <= min_dt;
+        if constexpr (Sink::kStats) {
+            if (line) k.st[kStLines]++;
+            else k.st[kStTrials]++;
+        }
         if (ok || forced) {
+            if constexpr (Sink::kStats) k.st[kStPieces]++;
             bool pivot = !ok;
             ES es;
             es.pivot = pivot;

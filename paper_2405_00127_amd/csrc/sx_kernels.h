@@ -22,6 +22,18 @@ struct ItemWs {
     uint64_t ovf_base, ovf_cap;
 };
 
+// One scene's streams and where they go in a batch arena.
+struct GatherDesc {
+    const uint8_t* tags;
+    const float2* pts;
+    const StyleD* styles;
+    const float* xforms;
+    const uint32_t* path_map;
+    uint32_t n_tags, n_pts, n_styles, n_xforms, n_paths;
+    uint32_t tag_base, pt_base, style_base, xform_base, path_base;
+    uint32_t pad;
+};
+
 int scan_tiles(uint32_t n);
 uint32_t piece_tiles(uint32_t n);
 uint32_t tag_block();
@@ -31,9 +43,16 @@ size_t scan_ctl_bytes();
 hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
                             hipStream_t s);
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s);
-hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, hipStream_t s);
+hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, int waves,
+                         hipStream_t s);
+hipError_t launch_piece_stats(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts,
+                              unsigned long long* stats, hipStream_t s);
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
                           uint64_t cap, hipStream_t s);
+hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
+                         float* xforms, uint32_t* path_map, hipStream_t s);
+hipError_t launch_scene_offsets(const uint64_t* offsets, const GatherDesc* descs, uint32_t n_scenes, uint32_t n_tags,
+                                uint64_t* scene_offsets, hipStream_t s);
 hipError_t launch_finish(const uint64_t* offsets, uint32_t n, const ItemWs& ws, uint64_t* dst, hipStream_t s);
 
 }  // namespace sx

@@ -340,8 +340,11 @@ struct TileAlloc {
     }
 };
 
-__global__ __launch_bounds__(kTagBlock) void piece_kernel(SceneView sv, Cfg cfg, ItemWs ws,
-                                                          uint32_t* __restrict__ counts) {
+// MinWaves: waves per SIMD the register allocation must allow (1, 2 or 3):
+// more waves hide more latency, at the price of spills to scratch.
+template <int MinWaves>
+__global__ __launch_bounds__(kTagBlock, MinWaves) void piece_kernel(SceneView sv, Cfg cfg, ItemWs ws,
+                                                                     uint32_t* __restrict__ counts) {
     __shared__ uint32_t s_n;
     if (threadIdx.x == 0) s_n = 0;
     __syncthreads();
@@ -358,6 +361,35 @@ __global__ __launch_bounds__(kTagBlock) void piece_kernel(SceneView sv, Cfg cfg,
         ws.tile_n[blockIdx.x] = s_n;
         atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
     }
+}
+
+// The piece kernel with work counters (one configuration; not timed):
+// stats[j] += per-tag counts j (fit trials, pieces, ranges, evolutes,
+// joins and caps, lines).  Items and counts are written as by piece_kernel.
+__global__ __launch_bounds__(kTagBlock) void piece_stats_kernel(SceneView sv, Cfg cfg, ItemWs ws,
+                                                                uint32_t* __restrict__ counts,
+                                                                unsigned long long* __restrict__ stats) {
+    __shared__ uint32_t s_n;
+    __shared__ unsigned long long s_st[kStN];
+    if (threadIdx.x == 0) s_n = 0;
+    if (threadIdx.x < kStN) s_st[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
+    if (i < sv.n_tags) {
+        TileAlloc al{ws.items, &s_n, (uint64_t)blockIdx.x * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
+                     ws.ovf_base, ws.ovf_cap};
+        ItemSink<TileAlloc, true> k{ws.items, al, i, 0, {0, 0, 0, 0, 0, 0}};
+        process_tag(k, cfg, sv, i);
+        counts[i] = k.n;
+        for (int j = 0; j < kStN; j++)
+            if (k.st[j]) atomicAdd(&s_st[j], (unsigned long long)k.st[j]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ws.tile_n[blockIdx.x] = s_n;
+        atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
+    }
+    if (threadIdx.x < kStN) atomicAdd(&stats[threadIdx.x], s_st[threadIdx.x]);
 }
 
 __device__ __forceinline__ void record_item(const SceneView& sv, const Item* slot, const uint64_t* offsets,
@@ -396,9 +428,40 @@ __global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs 
 __global__ void finish_kernel(const uint64_t* __restrict__ offsets, uint32_t n, const ItemWs ws,
                               uint64_t* __restrict__ dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        dst[0] = offsets[n];
-        dst[1] = ws.ctl->ovf_n > ws.ovf_cap ? ws.ctl->items_total : 0ull;
+        dst[0] = n ? offsets[n] : 0ull;
+        dst[1] = (n && ws.ctl->ovf_n > ws.ovf_cap) ? ws.ctl->items_total : 0ull;
     }
+}
+
+// ------------------------------------------------------------- batches
+// Concatenate scenes into one arena: block (x, s) copies a strided share of
+// scene s's streams.  Concatenation needs no index fix-ups: every scene
+// starts a path, a style and a transform, so the tag-monoid scan of the
+// arena gives global stream indices, and the path map keeps each scene's own
+// input path numbers.
+constexpr int kGatherBlock = 256;
+constexpr int kGatherBlocksPerScene = 32;
+
+__global__ __launch_bounds__(kGatherBlock) void gather_kernel(const GatherDesc* __restrict__ descs,
+                                                              uint8_t* __restrict__ tags, float2* __restrict__ pts,
+                                                              StyleD* __restrict__ styles, float* __restrict__ xforms,
+                                                              uint32_t* __restrict__ path_map) {
+    const GatherDesc d = descs[blockIdx.y];
+    const uint32_t stride = kGatherBlock * kGatherBlocksPerScene;
+    const uint32_t t0 = blockIdx.x * kGatherBlock + threadIdx.x;
+    for (uint32_t i = t0; i < d.n_tags; i += stride) tags[d.tag_base + i] = d.tags[i];
+    for (uint32_t i = t0; i < d.n_pts; i += stride) pts[d.pt_base + i] = d.pts[i];
+    for (uint32_t i = t0; i < d.n_styles; i += stride) styles[d.style_base + i] = d.styles[i];
+    for (uint32_t i = t0; i < 6 * d.n_xforms; i += stride) xforms[6 * (size_t)d.xform_base + i] = d.xforms[i];
+    for (uint32_t i = t0; i < d.n_paths; i += stride) path_map[d.path_base + i] = d.path_map[i];
+}
+
+// scene_offsets[s] = first record of scene s; scene_offsets[n] = total
+__global__ void scene_offsets_kernel(const uint64_t* __restrict__ offsets, const GatherDesc* __restrict__ descs,
+                                     uint32_t n_scenes, uint32_t n_tags, uint64_t* __restrict__ out) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n_scenes) out[s] = n_tags ? offsets[descs[s].tag_base] : 0ull;
+    if (s == n_scenes) out[s] = n_tags ? offsets[n_tags] : 0ull;
 }
 
 // ------------------------------------------------------------- launches
@@ -418,9 +481,19 @@ hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, voi
     scan_counts_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
     return hipGetLastError();
 }
-hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, hipStream_t s) {
+hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, int waves,
+                         hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    piece_kernel<<<piece_tiles(sv.n_tags), kTagBlock, 0, s>>>(sv, cfg, ws, counts);
+    const uint32_t g = piece_tiles(sv.n_tags);
+    if (waves <= 1) piece_kernel<1><<<g, kTagBlock, 0, s>>>(sv, cfg, ws, counts);
+    else if (waves == 2) piece_kernel<2><<<g, kTagBlock, 0, s>>>(sv, cfg, ws, counts);
+    else piece_kernel<3><<<g, kTagBlock, 0, s>>>(sv, cfg, ws, counts);
+    return hipGetLastError();
+}
+hipError_t launch_piece_stats(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts,
+                              unsigned long long* stats, hipStream_t s) {
+    if (sv.n_tags == 0) return hipSuccess;
+    piece_stats_kernel<<<piece_tiles(sv.n_tags), kTagBlock, 0, s>>>(sv, cfg, ws, counts, stats);
     return hipGetLastError();
 }
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
@@ -428,6 +501,18 @@ hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const
     if (sv.n_tags == 0) return hipSuccess;
     const uint32_t nt = piece_tiles(sv.n_tags);
     record_kernel<<<nt + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, arcs, offsets, (float*)out, cap, nt);
+    return hipGetLastError();
+}
+hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
+                         float* xforms, uint32_t* path_map, hipStream_t s) {
+    if (n_scenes == 0) return hipSuccess;
+    gather_kernel<<<dim3(kGatherBlocksPerScene, n_scenes), kGatherBlock, 0, s>>>(descs, tags, pts, styles, xforms,
+                                                                                 path_map);
+    return hipGetLastError();
+}
+hipError_t launch_scene_offsets(const uint64_t* offsets, const GatherDesc* descs, uint32_t n_scenes, uint32_t n_tags,
+                                uint64_t* scene_offsets, hipStream_t s) {
+    scene_offsets_kernel<<<(n_scenes + 1 + 255) / 256, 256, 0, s>>>(offsets, descs, n_scenes, n_tags, scene_offsets);
     return hipGetLastError();
 }
 hipError_t launch_finish(const uint64_t* offsets, uint32_t n, const ItemWs& ws, uint64_t* dst, hipStream_t s) {

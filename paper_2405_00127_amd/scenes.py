@@ -284,74 +284,82 @@ def scene_map(seed: int = 2, n_segments: int = 1_000_000, n_paths: Optional[int]
     starts = np.stack([rng.uniform(0, W, n_paths), rng.uniform(0, H, n_paths)], 1)
     heads = rng.uniform(-math.pi, math.pi, n_paths)
 
-    verbs_all = np.empty(total + 2 * n_paths, dtype=np.uint8)
-    pts_all = np.empty((total * 3 + n_paths, 2), dtype=np.float64)
-    verb_off = np.zeros(n_paths + 1, dtype=np.uint32)
-    pt_off = np.zeros(n_paths + 1, dtype=np.uint32)
-    vi = 0
-    pi = 0
-    si = 0
-    for k in range(n_paths):
-        verb_off[k] = vi
-        pt_off[k] = pi
-        cur = starts[k].copy()
-        tan = heads[k]
-        verbs_all[vi] = MOVE
-        vi += 1
-        pts_all[pi] = cur
-        pi += 1
-        for j in range(int(lens[k])):
-            s = si + j
-            st = tan if (g1[s] and j > 0) else tan + dturn[s]
-            kind = kinds[s]
-            L = chord[s]
-            if kind == LINE:
-                cdir = st
-            elif kind == QUAD:
-                cdir = st - th_a[s]
-            else:
-                cdir = st - th_a[s]
-            end = cur + L * _dir(cdir)
-            # reflect the walk at the canvas borders
-            if not (0.0 <= end[0] <= W):
-                cdir = math.pi - cdir
-                st = math.pi - st
-            if not (0.0 <= end[1] <= H):
-                cdir = -cdir
-                st = -st
-            end = cur + L * _dir(cdir)
-            end = np.clip(end, 0.0, [W, H])
-            verbs_all[vi] = kind
-            vi += 1
-            if kind == LINE:
-                pts_all[pi] = end
-                pi += 1
-                tan = cdir
-            elif kind == QUAD:
-                # control point where the start tangent meets a ray from the end
-                # point; keep it simple: arm along the start tangent
-                c1 = cur + arm_a[s] * L * _dir(st) * 1.5
-                pts_all[pi] = c1
-                pts_all[pi + 1] = end
-                pi += 2
-                d = end - c1
-                tan = math.atan2(d[1], d[0]) if (d[0] or d[1]) else cdir
-            else:
-                et = cdir + th_b[s]
-                c1 = cur + arm_a[s] * L * _dir(st)
-                c2 = end - arm_b[s] * L * _dir(et)
-                pts_all[pi] = c1
-                pts_all[pi + 1] = c2
-                pts_all[pi + 2] = end
-                pi += 3
-                tan = et
-            cur = end
-        si += int(lens[k])
-        if closed[k]:
-            verbs_all[vi] = CLOSE
-            vi += 1
-    verb_off[n_paths] = vi
-    pt_off[n_paths] = pi
+    # layout: path k = MOVE, its segments, CLOSE if closed; a segment of kind
+    # LINE / QUAD / CUBIC carries 1 / 2 / 3 points (the verb codes)
+    seg_start = np.zeros(n_paths + 1, dtype=np.int64)
+    np.cumsum(lens, out=seg_start[1:])
+    pc = kinds.astype(np.int64)
+    path_of_seg = np.repeat(np.arange(n_paths), lens)
+    cum_pc = np.zeros(total + 1, dtype=np.int64)
+    np.cumsum(pc, out=cum_pc[1:])
+    pts_per_path = 1 + (cum_pc[seg_start[1:]] - cum_pc[seg_start[:-1]])
+    verbs_per_path = 1 + lens + closed.astype(np.int64)
+    pt_off = np.zeros(n_paths + 1, dtype=np.int64)
+    np.cumsum(pts_per_path, out=pt_off[1:])
+    verb_off = np.zeros(n_paths + 1, dtype=np.int64)
+    np.cumsum(verbs_per_path, out=verb_off[1:])
+    # first point of each segment in the point stream, its verb slot
+    seg_pt = pt_off[path_of_seg] + 1 + (cum_pc[:-1] - cum_pc[seg_start[path_of_seg]])
+    seg_verb = verb_off[path_of_seg] + 1 + (np.arange(total) - seg_start[path_of_seg])
+    verbs_all = np.empty(int(verb_off[-1]), dtype=np.uint8)
+    pts_all = np.empty((int(pt_off[-1]), 2), dtype=np.float64)
+    verbs_all[verb_off[:-1]] = MOVE
+    verbs_all[seg_verb] = kinds
+    verbs_all[verb_off[1:][closed] - 1] = CLOSE
+    pts_all[pt_off[:-1]] = starts
+
+    def unit(a):
+        return np.stack([np.cos(a), np.sin(a)], 1)
+
+    # the walks of all paths advance together, one segment per step
+    cur = starts.copy()
+    tan = heads.copy()
+    for j in range(int(lens.max()) if n_paths else 0):
+        K = np.nonzero(lens > j)[0]
+        si = seg_start[K] + j
+        st = np.where(g1[si] & (j > 0), tan[K], tan[K] + dturn[si])
+        kind = kinds[si]
+        L = chord[si]
+        cdir = np.where(kind == LINE, st, st - th_a[si])
+        c0 = cur[K]
+        end = c0 + L[:, None] * unit(cdir)
+        # reflect the walk at the canvas borders
+        rx = ~((end[:, 0] >= 0.0) & (end[:, 0] <= W))
+        cdir = np.where(rx, math.pi - cdir, cdir)
+        st = np.where(rx, math.pi - st, st)
+        ry = ~((end[:, 1] >= 0.0) & (end[:, 1] <= H))
+        cdir = np.where(ry, -cdir, cdir)
+        st = np.where(ry, -st, st)
+        end = c0 + L[:, None] * unit(cdir)
+        end = np.clip(end, 0.0, [W, H])
+        base = seg_pt[si]
+        new_tan = cdir.copy()
+        m = kind == LINE
+        pts_all[base[m]] = end[m]
+        m = kind == QUAD
+        if m.any():
+            # control point along the start tangent
+            c1 = c0[m] + (arm_a[si[m]] * L[m])[:, None] * unit(st[m]) * 1.5
+            pts_all[base[m]] = c1
+            pts_all[base[m] + 1] = end[m]
+            d = end[m] - c1
+            nz = (d[:, 0] != 0.0) | (d[:, 1] != 0.0)
+            new_tan[m] = np.where(nz, np.arctan2(d[:, 1], d[:, 0]), cdir[m])
+        m = kind == CUBIC
+        if m.any():
+            et = cdir[m] + th_b[si[m]]
+            c1 = c0[m] + (arm_a[si[m]] * L[m])[:, None] * unit(st[m])
+            c2 = end[m] - (arm_b[si[m]] * L[m])[:, None] * unit(et)
+            pts_all[base[m]] = c1
+            pts_all[base[m] + 1] = c2
+            pts_all[base[m] + 2] = end[m]
+            new_tan[m] = et
+        tan[K] = new_tan
+        cur[K] = end
+    vi = int(verb_off[-1])
+    pi = int(pt_off[-1])
+    verb_off = verb_off.astype(np.uint32)
+    pt_off = pt_off.astype(np.uint32)
     xf = np.array([[scale, 0, 0, scale, 0, 0]], dtype=np.float32)
     return Scene(
         verbs=verbs_all[:vi].copy(),

@@ -1,0 +1,154 @@
+"""Batched expansion (many scenes, one pipeline) through the C ABI.
+
+A scene's outline must be the same alone and in a batch, bit for bit (the
+arena is a concatenation; every per-segment computation sees the same
+inputs), with the scene's own path indices; the batched launch must survive
+HIP graph capture and replay."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2405_00127_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+    from paper_2405_00127_amd import build as PB
+
+    if not __import__("os").path.exists(B.LIB_PATH):
+        PB.build()
+    torch.cuda.set_device(0)
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_scenes(mode):
+    empty = S.SceneBuilder().build(S.make_styles([1.0], S.JOIN_ROUND, S.CAP_BUTT))
+    return [
+        S.scene_c1(1).subset(range(7)),
+        S.scene_map(11, 5000, 40, 0.25, mode),
+        empty,
+        S.scene_c3(3, n_cubics=120),
+        S.scene_map(12, 300, 3, 0.25, mode),
+        S.single_path_scene([S.MOVE, S.LINE], [(10.0, 10.0), (40.0, 12.0)], 3.0, S.JOIN_MITER, S.CAP_SQUARE,
+                            output_mode=mode),
+        S.scene_map(14, 20000, 150, 0.25, mode),
+    ]
+
+
+def _alone(ctx, scene, tol, mode):
+    from paper_2405_00127_amd import binding as B
+
+    recs, n, _ = ctx.expand(scene, tol, mode)
+    return B.records_to_numpy(recs, mode).copy() if n else np.zeros(0, B.LINE_DTYPE if mode == 0 else B.ARC_DTYPE)
+
+
+def _slices(buf, offs, mode):
+    from paper_2405_00127_amd import binding as B
+
+    rec = B.RECORD_BYTES[mode]
+    total = int(offs[-1])
+    allr = B.records_to_numpy(buf[: total * rec].view(__import__("torch").float32).view(-1, rec // 4), mode) \
+        if total else np.zeros(0, B.LINE_DTYPE if mode == 0 else B.ARC_DTYPE)
+    return [allr[int(offs[i]):int(offs[i + 1])] for i in range(len(offs) - 1)]
+
+
+@pytest.mark.parametrize("mode", [S.OUT_LINES, S.OUT_ARCS])
+def test_batch_equals_scenes_alone(ctx, mode):
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    tol = 0.25
+    scs = _mixed_scenes(mode)
+    _say("batch vs alone, mode", mode, [s.name for s in scs])
+    scenes = [ctx.encode(sc) for sc in scs]
+    alone = [_alone(ctx, s, tol, mode) for s in scenes]
+    batch = B.Batch(ctx)
+    batch.set(scenes)
+    out, offs, status = batch.prepare(tol, mode)
+    batch.expand_async(tol, mode, out.data_ptr(), out.numel(), offs.data_ptr(), status.data_ptr())
+    torch.cuda.synchronize()
+    o = offs.cpu().numpy()
+    assert int(status[1]) == 0 and int(status[0]) == o[-1] == sum(len(a) for a in alone)
+    for i, (got, ref) in enumerate(zip(_slices(out, o, mode), alone)):
+        assert len(got) == len(ref), i
+        assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), i
+    batch.destroy()
+
+
+def test_batch_graph_replay_and_reuse(ctx):
+    """Capture the batched launch in a graph, replay it three times with eager
+    work in between, then reuse the batch for a smaller set of scenes."""
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    tol, mode = 0.25, S.OUT_LINES
+    scs = [S.scene_map(20 + i, n, max(1, n // 100), tol, mode) for i, n in enumerate([150, 9000, 40, 30000, 2500])]
+    _say("batch graph replay", [s.n_segments() for s in scs])
+    scenes = [ctx.encode(sc) for sc in scs]
+    alone = [_alone(ctx, s, tol, mode) for s in scenes]
+    batch = B.Batch(ctx)
+    batch.set(scenes)
+    out, offs, status = batch.prepare(tol, mode)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        # warm up on the capture stream, then capture
+        batch.expand_async(tol, mode, out.data_ptr(), out.numel(), offs.data_ptr(), status.data_ptr(), stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        batch.expand_async(tol, mode, out.data_ptr(), out.numel(), offs.data_ptr(), status.data_ptr(), stream=side)
+    for rep in range(3):
+        out.zero_()
+        offs.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o = offs.cpu().numpy()
+        assert int(status[1]) == 0, rep
+        for i, (got, ref) in enumerate(zip(_slices(out, o, mode), alone)):
+            assert np.array_equal(got.view(np.uint8), ref.view(np.uint8)), (rep, i)
+        del junk
+    del g
+    # reuse the arena for fewer, smaller scenes (stale contents must not leak)
+    batch.set([scenes[2], scenes[0]])
+    out2, offs2, status2 = batch.prepare(tol, mode)
+    batch.expand_async(tol, mode, out2.data_ptr(), out2.numel(), offs2.data_ptr(), status2.data_ptr())
+    torch.cuda.synchronize()
+    o = offs2.cpu().numpy()
+    got = _slices(out2, o, mode)
+    assert np.array_equal(got[0].view(np.uint8), alone[2].view(np.uint8))
+    assert np.array_equal(got[1].view(np.uint8), alone[0].view(np.uint8))
+    batch.destroy()
+
+
+def test_empty_batch(ctx):
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    batch = B.Batch(ctx)
+    batch.set([])
+    offs = torch.full((1,), 7, dtype=torch.int64, device="cuda")
+    status = torch.full((2,), 7, dtype=torch.int64, device="cuda")
+    batch.expand_async(0.25, S.OUT_LINES, 0, 0, offs.data_ptr(), status.data_ptr())
+    torch.cuda.synchronize()
+    assert int(offs[0]) == 0 and int(status[0]) == 0 and int(status[1]) == 0
+    batch.destroy()
