@@ -121,9 +121,10 @@ def plain(args, ctx, B, S, torch, np):
     log(f"bench: {n_seg} segments, {scene.n_tags} tags -> {n_rec} records")
 
     tune_info = {}
-    if args.piece_waves or args.chunk_k:
+    if args.piece_waves or args.chunk_k or args.piece_block:
         cur = ctx.get_tuning()
-        ctx.set_tuning(args.piece_waves or cur["piece_waves"], args.chunk_k or cur["chunk_k"])
+        ctx.set_tuning(args.piece_waves or cur["piece_waves"], args.chunk_k or cur["chunk_k"],
+                       args.piece_block or cur["piece_block"])
     elif not args.no_tune:
         from paper_2405_00127_amd import autotune as AT
 
@@ -361,6 +362,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
     ap.add_argument("--piece-waves", type=int, default=None)
     ap.add_argument("--chunk-k", type=int, default=None)
+    ap.add_argument("--piece-block", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)

@@ -239,12 +239,14 @@ int sx_batch_expand(sx_ctx *ctx, sx_batch *batch, float tolerance, int output_mo
  *   piece_waves  1..3: waves per SIMD the piece kernel's register allocation
  *                allows (more waves hide more latency but spill more);
  *   chunk_k      1..255: records per emission item chunk (work per thread of
- *                the record kernel).
- * Defaults {2, 16}.  Errors: SX_EINVAL (out of range, reserved fields != 0). */
+ *                the record kernel);
+ *   piece_block  64 or 256 (0 = 256): tags per piece-kernel workgroup.
+ * Defaults {2, 16, 256}.  Errors: SX_EINVAL (out of range, reserved != 0). */
 typedef struct {
     uint32_t piece_waves;
     uint32_t chunk_k;
-    uint32_t reserved0, reserved1; /* must be 0 */
+    uint32_t piece_block;
+    uint32_t reserved1; /* must be 0 */
 } sx_tuning;
 int sx_set_tuning(sx_ctx *ctx, const sx_tuning *tuning);
 int sx_get_tuning(const sx_ctx *ctx, sx_tuning *tuning);

@@ -2,7 +2,8 @@
 
 The outline does not depend on the launch parameters (``sx_set_tuning``), only
 the speed does: the piece kernel's register budget (waves per SIMD it must
-allow; more waves hide more FP64 latency but spill more) and the number of
+allow; more waves hide more FP64 latency but spill more), its workgroup size
+(one wave per group frees a SIMD as soon as its wave ends) and the number of
 records per emission item chunk (work per record-kernel thread; longer chunks
 amortise the item read, shorter ones balance the load).  The tuner times each
 candidate on the caller's own scene with HIP events on the caller's stream and
@@ -18,6 +19,7 @@ import threading
 from typing import Dict, Iterable, Optional, Tuple
 
 PIECE_WAVES = (1, 2, 3)
+PIECE_BLOCK = (64, 256)
 CHUNK_K = (4, 8, 16, 32, 64)
 
 _lock = threading.Lock()
@@ -75,12 +77,15 @@ def time_config(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity:
 
 
 def tune(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, count_ptr: int, stream=None,
-         waves: Iterable[int] = PIECE_WAVES, chunks: Iterable[int] = CHUNK_K, reps: int = 5,
-         cache_path: Optional[str] = None, use_cache: bool = True) -> Tuple[dict, Dict[str, float]]:
-    """Pick the fastest (piece_waves, chunk_k) for this scene and set it on
-    ``ctx``.  The output buffer must already be large enough (size it with one
-    ``ctx.expand``).  Returns (chosen tuning, {"w{W}k{K}": ms} of every
-    candidate timed; empty when the cache answered)."""
+         waves: Iterable[int] = PIECE_WAVES, blocks: Iterable[int] = PIECE_BLOCK, chunks: Iterable[int] = CHUNK_K,
+         reps: int = 5, cache_path: Optional[str] = None, use_cache: bool = True) -> Tuple[dict, Dict[str, float]]:
+    """Pick the fastest (piece_waves, piece_block, chunk_k) for this scene and
+    set it on ``ctx``.  The output buffer must already be large enough (size
+    it with one ``ctx.expand``).  The piece-kernel knobs are searched first
+    with the current chunk size, then the chunk size with the best of those
+    (the two stages do not interact: chunk_k only changes the record kernel).
+    Returns (chosen tuning, {"w{W}b{B}k{K}": ms} of every candidate timed;
+    empty when the cache answered)."""
     import torch
 
     stream = stream if stream is not None else torch.cuda.current_stream()
@@ -89,22 +94,26 @@ def tune(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, c
     if use_cache:
         with _lock:
             hit = _load(path).get(key)
-        if hit and hit.get("piece_waves") in PIECE_WAVES and 1 <= int(hit.get("chunk_k", 0)) <= 255:
-            ctx.set_tuning(int(hit["piece_waves"]), int(hit["chunk_k"]))
+        if (hit and hit.get("piece_waves") in PIECE_WAVES and hit.get("piece_block") in PIECE_BLOCK
+                and 1 <= int(hit.get("chunk_k", 0)) <= 255):
+            ctx.set_tuning(int(hit["piece_waves"]), int(hit["chunk_k"]), int(hit["piece_block"]))
             return ctx.get_tuning(), {}
     times: Dict[str, float] = {}
-    best = None
-    for w in waves:
-        for k in chunks:
-            ctx.set_tuning(w, k)
-            ms = time_config(ctx, scene, tolerance, mode, out_ptr, capacity, count_ptr, stream, reps)
-            times[f"w{w}k{k}"] = ms
-            if best is None or ms < best[0]:
-                best = (ms, w, k)
-    ctx.set_tuning(best[1], best[2])
+    k0 = ctx.get_tuning()["chunk_k"]
+
+    def run(w, b, k):
+        ctx.set_tuning(w, k, b)
+        ms = time_config(ctx, scene, tolerance, mode, out_ptr, capacity, count_ptr, stream, reps)
+        times[f"w{w}b{b}k{k}"] = ms
+        return ms
+
+    best = min(((run(w, b, k0), w, b) for w in waves for b in blocks), key=lambda t: t[0])
+    _, bw, bb = best
+    bestk = min(((times.get(f"w{bw}b{bb}k{k}") or run(bw, bb, k), k) for k in chunks), key=lambda t: t[0])
+    ctx.set_tuning(bw, bestk[1], bb)
     chosen = ctx.get_tuning()
     with _lock:
         data = _load(path)
-        data[key] = dict(chosen, ms=best[0])
+        data[key] = dict(chosen, ms=bestk[0])
         _store(path, data)
     return chosen, times

@@ -42,7 +42,7 @@ class _Paths(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("reserved0", C.c_uint32),
+    _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("piece_block", C.c_uint32),
                 ("reserved1", C.c_uint32)]
 
 
@@ -228,14 +228,14 @@ class Context:
                 out = torch.empty(int(e.required * 1.25 + 1) * rec, dtype=torch.uint8, device=out.device)
         return out[: n * rec].view(torch.float32).view(-1, rec // 4), n, out
 
-    def set_tuning(self, piece_waves: int, chunk_k: int):
-        t = _Tuning(int(piece_waves), int(chunk_k), 0, 0)
+    def set_tuning(self, piece_waves: int, chunk_k: int, piece_block: int = 256):
+        t = _Tuning(int(piece_waves), int(chunk_k), int(piece_block), 0)
         self._check(lib().sx_set_tuning(C.c_void_p(self.h), C.byref(t)), "sx_set_tuning")
 
     def get_tuning(self):
         t = _Tuning()
         self._check(lib().sx_get_tuning(C.c_void_p(self.h), C.byref(t)), "sx_get_tuning")
-        return {"piece_waves": t.piece_waves, "chunk_k": t.chunk_k}
+        return {"piece_waves": t.piece_waves, "chunk_k": t.chunk_k, "piece_block": t.piece_block}
 
     def piece_stats(self, scene: Scene, tolerance=None, mode=None, stream=None) -> dict:
         """Work counts of the piece phase (instrumented run; synchronous)."""

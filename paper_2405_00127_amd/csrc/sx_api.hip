@@ -17,7 +17,7 @@
 struct sx_ctx {
     int device = 0;
     std::string err;
-    sx_tuning tune = {2u, 16u, 0u, 0u};
+    sx_tuning tune = {2u, 16u, 256u, 0u};
     uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, items needed
 };
 
@@ -39,8 +39,8 @@ struct sx_scene {
     sx::Item* d_items = nullptr;
     uint32_t* d_tile_n = nullptr;
     sx::WsCtl* d_ws_ctl = nullptr;
-    uint32_t region_cap = 0;  // slots per piece tile
-    uint64_t ovf_cap = 0;     // shared overflow slots
+    uint32_t region_per_tag = 0;  // item slots per tag in the per-tile regions
+    uint64_t ovf_cap = 0;         // shared overflow slots
     // allocated capacities (a batch arena is reused for smaller contents)
     uint32_t cap_tags = 0, cap_pts = 0, cap_styles = 0, cap_xforms = 0, cap_paths = 0;
     bool allocated = false;
@@ -60,6 +60,7 @@ struct sx_batch {
 namespace {
 
 constexpr uint32_t kMaxBatchScenes = 65535;
+constexpr uint32_t kMinTile = 64, kMaxTile = 256;  // piece kernel block sizes
 constexpr uint32_t kRegionPerTag = 8;      // initial item slots per tag
 constexpr uint64_t kMinOverflow = 65536;   // initial shared overflow slots (minimum)
 
@@ -112,25 +113,29 @@ sx::SceneView view(const sx_scene* s) {
     return v;
 }
 
-sx::ItemWs workspace(const sx_scene* s) {
+sx::ItemWs workspace(const sx_scene* s, uint32_t tile) {
     sx::ItemWs w;
     w.items = s->d_items;
     w.tile_n = s->d_tile_n;
     w.ctl = s->d_ws_ctl;
-    w.region_cap = s->region_cap;
-    w.ovf_base = (uint64_t)sx::piece_tiles(s->n_tags) * s->region_cap;
+    w.tile = tile;
+    w.region_cap = s->region_per_tag * tile;
+    w.ovf_base = (uint64_t)sx::piece_tiles(s->n_tags, tile) * w.region_cap;
     w.ovf_cap = s->ovf_cap;
     return w;
 }
+sx::ItemWs workspace(const sx_scene* s, const sx_ctx* ctx) { return workspace(s, ctx->tune.piece_block); }
 
 // (Re)allocate the item workspace: region_per_tag slots per tag in each
-// piece tile's region plus ovf shared slots.  The caller has synchronised.
+// piece tile's region (room for either tile size) plus ovf shared slots.
+// The caller has synchronised.
 hipError_t size_workspace(sx_scene* s, uint32_t region_per_tag, uint64_t ovf) {
     if (s->d_items) (void)hipFree(s->d_items);
     s->d_items = nullptr;
-    s->region_cap = region_per_tag * sx::tag_block();
+    s->region_per_tag = region_per_tag;
     s->ovf_cap = ovf;
-    const uint64_t slots = (uint64_t)sx::piece_tiles(s->cap_tags) * s->region_cap + ovf;
+    const uint64_t tags = ((uint64_t)s->cap_tags + kMaxTile - 1) / kMaxTile * kMaxTile;
+    const uint64_t slots = tags * region_per_tag + ovf;
     return dalloc(&s->d_items, slots * sizeof(sx::Item));
 }
 
@@ -159,10 +164,10 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         regrow(&s->d_offsets, ((size_t)c + 1) * sizeof(uint64_t));
         regrow(&s->d_status_tags, sx::scan_status_bytes(c));
         regrow(&s->d_status_counts, sx::scan_status_bytes(c));
-        regrow(&s->d_tile_n, (size_t)sx::piece_tiles(c) * sizeof(uint32_t));
+        regrow(&s->d_tile_n, (size_t)sx::piece_tiles(c, kMinTile) * sizeof(uint32_t));
         if (e != hipSuccess) return e;
         s->cap_tags = c;
-        const uint32_t per_tag = s->region_cap ? s->region_cap / sx::tag_block() : kRegionPerTag;
+        const uint32_t per_tag = s->region_per_tag ? s->region_per_tag : kRegionPerTag;
         A(size_workspace(s, per_tag, std::max<uint64_t>(std::max<uint64_t>(c, s->ovf_cap), kMinOverflow)));
         A(hipMemsetAsync(s->d_tags, 0, ntag_pad, st));
         A(hipMemsetAsync(s->d_status_tags, 0, sx::scan_status_bytes(c), st));
@@ -215,7 +220,7 @@ int run_counts(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, hipStream_t s
     if ((e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st)) !=
         hipSuccess)
         return hip_fail(ctx, e, "scan_tags launch");
-    if ((e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, (int)ctx->tune.piece_waves, st)) !=
+    if ((e = sx::launch_pieces(view(s), cfg, workspace(s, ctx), s->d_counts, (int)ctx->tune.piece_waves, st)) !=
         hipSuccess)
         return hip_fail(ctx, e, "pieces launch");
     if ((e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
@@ -229,9 +234,9 @@ int run_all(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, void* out, uint6
             hipStream_t st) {
     int r = run_counts(ctx, s, cfg, st);
     if (r != SX_OK) return r;
-    hipError_t e = sx::launch_records(view(s), workspace(s), cfg.arcs, s->d_offsets, out, cap_records, st);
+    hipError_t e = sx::launch_records(view(s), workspace(s, ctx), cfg.arcs, s->d_offsets, out, cap_records, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "records launch");
-    e = sx::launch_finish(s->d_offsets, s->n_tags, workspace(s), dst, st);
+    e = sx::launch_finish(s->d_offsets, s->n_tags, workspace(s, ctx), dst, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "finish launch");
     return SX_OK;
 }
@@ -270,8 +275,11 @@ int sx_set_tuning(sx_ctx* ctx, const sx_tuning* t) {
     if (!ctx || !t) return SX_EINVAL;
     if (t->piece_waves < 1 || t->piece_waves > 3) return fail(ctx, SX_EINVAL, "piece_waves must be 1, 2 or 3");
     if (t->chunk_k < 1 || t->chunk_k > 255) return fail(ctx, SX_EINVAL, "chunk_k must be in [1, 255]");
-    if (t->reserved0 || t->reserved1) return fail(ctx, SX_EINVAL, "reserved tuning fields must be 0");
+    if (t->piece_block != 0 && t->piece_block != 64 && t->piece_block != 256)
+        return fail(ctx, SX_EINVAL, "piece_block must be 64 or 256 (0: 256)");
+    if (t->reserved1) return fail(ctx, SX_EINVAL, "reserved tuning fields must be 0");
     ctx->tune = *t;
+    if (ctx->tune.piece_block == 0) ctx->tune.piece_block = 256;
     return SX_OK;
 }
 
@@ -451,7 +459,7 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
             e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
             break;
         case SX_PHASE_PIECES:
-            e = sx::launch_pieces(view(s), cfg, workspace(s), s->d_counts, (int)ctx->tune.piece_waves, st);
+            e = sx::launch_pieces(view(s), cfg, workspace(s, ctx), s->d_counts, (int)ctx->tune.piece_waves, st);
             break;
         case SX_PHASE_SCAN_COUNTS:
             e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
@@ -459,7 +467,7 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
             break;
         case SX_PHASE_RECORDS:
             if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
-            e = sx::launch_records(view(s), workspace(s), cfg.arcs, s->d_offsets, out_dev, out_capacity_bytes / rec,
+            e = sx::launch_records(view(s), workspace(s, ctx), cfg.arcs, s->d_offsets, out_dev, out_capacity_bytes / rec,
                                    st);
             break;
         default:
@@ -608,7 +616,7 @@ int sx_batch_expand(sx_ctx* ctx, sx_batch* b, float tolerance, int output_mode, 
         int r = run_all(ctx, a, cfg, out_dev, out_capacity_bytes / rec, status_dev, st);
         if (r != SX_OK) return r;
     } else {
-        hipError_t e = sx::launch_finish(a->d_offsets, 0, workspace(a), status_dev, st);
+        hipError_t e = sx::launch_finish(a->d_offsets, 0, workspace(a, ctx), status_dev, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "finish launch");
     }
     hipError_t e = sx::launch_scene_offsets(a->d_offsets, b->d_desc, b->n_scenes, a->n_tags, scene_offsets_dev, st);
@@ -629,7 +637,7 @@ int sx_debug_piece_stats(sx_ctx* ctx, const sx_scene* s, float tolerance, int ou
     hipError_t e = hipMalloc((void**)&d, 6 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemsetAsync(d, 0, 6 * sizeof(unsigned long long), st);
     if (e == hipSuccess) e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
-    if (e == hipSuccess) e = sx::launch_piece_stats(view(s), cfg, workspace(s), s->d_counts, d, st);
+    if (e == hipSuccess) e = sx::launch_piece_stats(view(s), cfg, workspace(s, kMaxTile), s->d_counts, d, st);
     if (e == hipSuccess) e = hipMemcpyAsync(stats6, d, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (d) (void)hipFree(d);

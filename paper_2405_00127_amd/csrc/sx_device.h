@@ -156,21 +156,22 @@ SX_FN V2 es_integral_f(float k0, float k1, float u) {
     }
     return v2(sx * hu, sy * hu);
 }
-// Z(1) in FP64 (once per piece): 8-point Gauss-Legendre
+// Z(1) in FP64 (once per piece): 8-point Gauss-Legendre on v = u - 1/2.
+// The nodes come in pairs +-v, and exp(i phi(v)) + exp(i phi(-v)) =
+// 2 cos(k0 v) exp(i k1 v^2 / 2), so each pair costs one sincos and one cos.
 SX_FN D2 es_integral1(double k0, double k1) {
     const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
     const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
     double sx = 0.0, sy = 0.0;
     for (int i = 0; i < 4; i++) {
-        for (int sgn = -1; sgn <= 1; sgn += 2) {
-            double v = 0.5 * (sgn * gx[i] + 1.0);
-            double sn, cs;
-            sincos(es_phi(k0, k1, v), &sn, &cs);
-            sx += gw[i] * cs;
-            sy += gw[i] * sn;
-        }
+        const double v = 0.5 * gx[i];
+        double sn, cs;
+        sincos(0.5 * k1 * v * v, &sn, &cs);
+        const double c = gw[i] * cos(k0 * v);
+        sx += c * cs;
+        sy += c * sn;
     }
-    return d2(0.5 * sx, 0.5 * sy);
+    return d2(sx, sy);
 }
 
 struct ES {

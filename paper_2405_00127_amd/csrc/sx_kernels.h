@@ -18,7 +18,8 @@ struct ItemWs {
     Item* items;
     uint32_t* tile_n;  // per piece tile: slots requested (clamp to region_cap)
     WsCtl* ctl;
-    uint32_t region_cap;
+    uint32_t tile;        // tags per piece tile (the piece kernel's block size: 64 or 256)
+    uint32_t region_cap;  // slots per tile
     uint64_t ovf_base, ovf_cap;
 };
 
@@ -35,8 +36,7 @@ struct GatherDesc {
 };
 
 int scan_tiles(uint32_t n);
-uint32_t piece_tiles(uint32_t n);
-uint32_t tag_block();
+uint32_t piece_tiles(uint32_t n, uint32_t tile);
 size_t scan_status_bytes(uint32_t n);
 size_t scan_ctl_bytes();
 

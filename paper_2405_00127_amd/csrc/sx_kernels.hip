@@ -340,15 +340,58 @@ struct TileAlloc {
     }
 };
 
+// Work class of a tag for the in-block ordering: cubics (longest bisection),
+// quadratics, then lines and stroke cap markers (no bisection).
+__device__ __forceinline__ uint32_t work_class(uint32_t tag) {
+    if (tag & kTagEnd) return 2u;
+    const uint32_t c = tag & kTagCount;
+    return c == 3u ? 0u : (c == 2u ? 1u : 2u);
+}
+
 // MinWaves: waves per SIMD the register allocation must allow (1, 2 or 3):
 // more waves hide more latency, at the price of spills to scratch.
-template <int MinWaves>
-__global__ __launch_bounds__(kTagBlock, MinWaves) void piece_kernel(SceneView sv, Cfg cfg, ItemWs ws,
-                                                                     uint32_t* __restrict__ counts) {
+// Block: tags per workgroup and per workspace tile (64 or 256).  With one
+// wave per block a SIMD takes new work as soon as its own wave finishes;
+// with several, the block first orders its tags by work class (a stable
+// counting sort in LDS) so that each wave runs tags of one kind: a wave of
+// lines no longer waits for one lane's cubic bisection.
+template <int MinWaves, int Block>
+__global__ __launch_bounds__(Block, MinWaves) void piece_kernel(SceneView sv, Cfg cfg, ItemWs ws,
+                                                                uint32_t* __restrict__ counts) {
     __shared__ uint32_t s_n;
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    const uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
+    __shared__ uint32_t s_order[Block];
+    __shared__ uint32_t s_hist[Block / 64][3];
+    const uint32_t t = threadIdx.x;
+    const uint32_t first = blockIdx.x * Block;
+    if (t == 0) s_n = 0;
+    uint32_t i = first + t;
+    if constexpr (Block > 64) {
+        const uint32_t lane = t & 63u, wv = t >> 6;
+        const uint32_t cls = i < sv.n_tags ? work_class(sv.tags[i]) : 2u;
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        uint64_t m[3];
+        uint32_t rank = 0;
+#pragma unroll
+        for (uint32_t c = 0; c < 3; c++) {
+            m[c] = __ballot(cls == c);
+            if (cls == c) rank = (uint32_t)__popcll(m[c] & below);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (uint32_t c = 0; c < 3; c++) s_hist[wv][c] = (uint32_t)__popcll(m[c]);
+        }
+        __syncthreads();
+        // destination = tags of lower classes + same class in earlier waves + rank
+        uint32_t pos = rank;
+        for (uint32_t c = 0; c < 3; c++)
+            for (uint32_t w = 0; w < Block / 64; w++)
+                if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
+        s_order[pos] = t;
+        __syncthreads();
+        i = first + s_order[t];
+    } else {
+        __syncthreads();
+    }
     if (i < sv.n_tags) {
         TileAlloc al{ws.items, &s_n, (uint64_t)blockIdx.x * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
                      ws.ovf_base, ws.ovf_cap};
@@ -357,7 +400,7 @@ __global__ __launch_bounds__(kTagBlock, MinWaves) void piece_kernel(SceneView sv
         counts[i] = k.n;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         ws.tile_n[blockIdx.x] = s_n;
         atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
     }
@@ -392,6 +435,15 @@ __global__ __launch_bounds__(kTagBlock) void piece_stats_kernel(SceneView sv, Cf
     if (threadIdx.x < kStN) atomicAdd(&stats[threadIdx.x], s_st[threadIdx.x]);
 }
 
+// Record-kernel item classes: offset ranges placed by the density inverse,
+// other offset ranges, evolute bundles, joins and caps (and empty slots).
+constexpr uint32_t kItemClasses = 4;
+__device__ __forceinline__ uint32_t item_class(uint32_t hdr) {
+    const uint32_t kind = hdr & 15u;
+    if (kind == kItemOffset) return (hdr & kIfPlaceF) ? 0u : 1u;
+    return kind == kItemEvolute ? 2u : 3u;
+}
+
 __device__ __forceinline__ void record_item(const SceneView& sv, const Item* slot, const uint64_t* offsets,
                                             float* out, uint64_t cap, int arcs) {
     Item it;
@@ -412,9 +464,34 @@ __global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs 
     if (offsets[sv.n_tags] > cap_records || ws.ctl->ovf_n > ws.ovf_cap) return;
     const uint32_t b = blockIdx.x;
     if (b < n_tiles) {
+        // a tile's items, kRecBlock at a time, each round ordered by item
+        // class so that a wave runs items of one kind
+        __shared__ uint32_t s_order[kRecBlock];
+        __shared__ uint32_t s_hist[kRecBlock / 64][kItemClasses];
+        const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
         const uint32_t cnt = ws.tile_n[b] < ws.region_cap ? ws.tile_n[b] : ws.region_cap;
         const Item* base = ws.items + (uint64_t)b * ws.region_cap;
-        for (uint32_t s = threadIdx.x; s < cnt; s += kRecBlock) record_item(sv, base + s, offsets, out, cap_records, arcs);
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        for (uint32_t r0 = 0; r0 < cnt; r0 += kRecBlock) {
+            const uint32_t cls = (r0 + t < cnt) ? item_class(base[r0 + t].hdr) : kItemClasses - 1;
+            uint32_t rank = 0;
+#pragma unroll
+            for (uint32_t c = 0; c < kItemClasses; c++) {
+                const uint64_t m = __ballot(cls == c);
+                if (cls == c) rank = (uint32_t)__popcll(m & below);
+                if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
+            }
+            __syncthreads();
+            uint32_t pos = rank;
+            for (uint32_t c = 0; c < kItemClasses; c++)
+                for (uint32_t w = 0; w < kRecBlock / 64; w++)
+                    if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
+            s_order[pos] = t;
+            __syncthreads();
+            const uint32_t s2 = r0 + s_order[t];
+            if (s2 < cnt) record_item(sv, base + s2, offsets, out, cap_records, arcs);
+            __syncthreads();
+        }
     } else {
         const uint64_t cnt = ws.ctl->ovf_n;
         const Item* base = ws.items + ws.ovf_base;
@@ -467,8 +544,7 @@ __global__ void scene_offsets_kernel(const uint64_t* __restrict__ offsets, const
 // ------------------------------------------------------------- launches
 int scan_tiles(uint32_t n) { return (int)((n + kScanTile - 1) / kScanTile); }
 
-uint32_t piece_tiles(uint32_t n) { return (n + kTagBlock - 1) / kTagBlock; }
-uint32_t tag_block() { return kTagBlock; }
+uint32_t piece_tiles(uint32_t n, uint32_t tile) { return (n + tile - 1) / tile; }
 
 hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
                             hipStream_t s) {
@@ -484,22 +560,29 @@ hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, voi
 hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, int waves,
                          hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    const uint32_t g = piece_tiles(sv.n_tags);
-    if (waves <= 1) piece_kernel<1><<<g, kTagBlock, 0, s>>>(sv, cfg, ws, counts);
-    else if (waves == 2) piece_kernel<2><<<g, kTagBlock, 0, s>>>(sv, cfg, ws, counts);
-    else piece_kernel<3><<<g, kTagBlock, 0, s>>>(sv, cfg, ws, counts);
+    const uint32_t g = piece_tiles(sv.n_tags, ws.tile);
+    if (ws.tile == 64) {
+        if (waves <= 1) piece_kernel<1, 64><<<g, 64, 0, s>>>(sv, cfg, ws, counts);
+        else if (waves == 2) piece_kernel<2, 64><<<g, 64, 0, s>>>(sv, cfg, ws, counts);
+        else piece_kernel<3, 64><<<g, 64, 0, s>>>(sv, cfg, ws, counts);
+    } else {
+        if (waves <= 1) piece_kernel<1, 256><<<g, 256, 0, s>>>(sv, cfg, ws, counts);
+        else if (waves == 2) piece_kernel<2, 256><<<g, 256, 0, s>>>(sv, cfg, ws, counts);
+        else piece_kernel<3, 256><<<g, 256, 0, s>>>(sv, cfg, ws, counts);
+    }
     return hipGetLastError();
 }
 hipError_t launch_piece_stats(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts,
                               unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    piece_stats_kernel<<<piece_tiles(sv.n_tags), kTagBlock, 0, s>>>(sv, cfg, ws, counts, stats);
+    if (ws.tile != (uint32_t)kTagBlock) return hipErrorInvalidValue;
+    piece_stats_kernel<<<piece_tiles(sv.n_tags, kTagBlock), kTagBlock, 0, s>>>(sv, cfg, ws, counts, stats);
     return hipGetLastError();
 }
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
                           uint64_t cap, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    const uint32_t nt = piece_tiles(sv.n_tags);
+    const uint32_t nt = piece_tiles(sv.n_tags, ws.tile);
     record_kernel<<<nt + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, arcs, offsets, (float*)out, cap, nt);
     return hipGetLastError();
 }
