@@ -33,20 +33,22 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 
-# Algorithmic FP64 work of the piece kernel per unit, counted from its
-# definition (transcendentals at the FMA count of their polynomial
-# evaluation: sin/cos 25, sincos 40, atan2 40, acos 40, cbrt 30, sqrt 10,
-# divide 10):
-#   fit trial: sub-cubic end point, tangent and chord 70, two end angles 92,
-#     arms 24, the Section 7.1 estimate 180, hodograph test 91      = 460
-#   accepted cubic piece: end normals 66, Appendix A polynomials 50, Z(1) by
-#     8-node quadrature 386, rotation and base angle 66, L 10       = 580
-#   line piece: normal 33, length 13, angle 40                     = 90
+# Algorithmic FP64 work per unit, counted from the definitions
+# (transcendentals at the FMA count of their polynomial evaluation: sin/cos
+# 25, sincos 40, atan2 40, acos 40, cbrt 30, sqrt 10, divide 10):
+#   fit trial (Algorithm 2): sub-cubic end point, tangent and chord 70, two
+#     end angles 92, arms 24, the Section 7.1 estimate 180, hodograph 91 = 460
+#   line step: chord length and acceptance                               = 15
+#   accepted cubic piece: the trial again 460, end normals 66, Appendix A
+#     polynomials 50, Z(1) by 8-node quadrature (paired nodes) 226,
+#     rotation and base angle 66, L 10                                  = 880
+#   line piece: normal 33, length 13, angle 40                           = 90
 #   parallel-curve range: curvatures, density split and its F increment
-#     (Section 4.2 branches) or the arc count (Section 5), count     = 130
-#   evolute bundle: Section 6 count and exact end points            = 90
-#   join or cap: tangents, normals, offsets, round-join angles      = 150
-PIECE_FLOPS = {"trial": 460.0, "piece": 580.0, "line": 90.0, "range": 130.0, "evolute": 90.0, "join": 150.0}
+#     (Section 4.2 branches) or the arc count (Section 5), count           = 130
+#   evolute bundle: Section 6 count and exact end points                  = 90
+#   join or cap: tangents, normals, offsets, round-join angles            = 150
+FLOPS = {"trial": 460.0, "line_step": 15.0, "piece": 880.0, "line": 90.0, "range": 130.0, "evolute": 90.0,
+         "join": 150.0}
 # Algorithmic FP32 work of the record kernel per output record (one new
 # outline point per record): spiral position by 4-node quadrature 118,
 # normal 24, offset 4, point placement (inverse of the density integral) 54
@@ -121,10 +123,10 @@ def plain(args, ctx, B, S, torch, np):
     log(f"bench: {n_seg} segments, {scene.n_tags} tags -> {n_rec} records")
 
     tune_info = {}
-    if args.piece_waves or args.chunk_k or args.piece_block:
-        cur = ctx.get_tuning()
-        ctx.set_tuning(args.piece_waves or cur["piece_waves"], args.chunk_k or cur["chunk_k"],
-                       args.piece_block or cur["piece_block"])
+    manual = {k: v for k, v in (("piece_waves", args.piece_waves), ("chunk_k", args.chunk_k),
+                                ("bisect_range", args.bisect_range), ("bisect_waves", args.bisect_waves)) if v}
+    if manual:
+        ctx.set_tuning(**manual)
     elif not args.no_tune:
         from paper_2405_00127_amd import autotune as AT
 
@@ -151,7 +153,8 @@ def plain(args, ctx, B, S, torch, np):
     log(f"bench: plain {ms:.3f} ms/step")
 
     # per-kernel times: HIP events on the launching stream around each phase
-    nph = 4
+    names = B.PHASE_NAMES
+    nph = len(names)
     evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nph)]
            for _ in range(args.steps)]
     for k in range(args.steps):
@@ -160,40 +163,51 @@ def plain(args, ctx, B, S, torch, np):
             ctx.run_phase(scene, p, tol, mode, buf.data_ptr(), buf.numel(), stream=stream)
             evs[k][p][1].record(stream)
     torch.cuda.synchronize()
-    phase_ms = [sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
-                for p in range(nph)]
-    names = B.PHASE_NAMES
-    log("bench: phases " + ", ".join(f"{names[p]} {phase_ms[p]:.3f} ms" for p in range(nph)))
+    phase_ms = {names[p]: sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
+                for p in range(nph)}
+    log("bench: phases " + ", ".join(f"{n} {phase_ms[n]:.3f} ms" for n in names))
     stats = ctx.piece_stats(scene, tol, mode, stream=stream)
-    log(f"bench: piece work {stats}")
+    log(f"bench: work {stats}")
 
     n_tags = scene.n_tags
-    dom = int(np.argmax(phase_ms))
-    pieces_nonline = stats["pieces"] - stats["lines"]
-    piece_flops = (stats["trials"] * PIECE_FLOPS["trial"] + pieces_nonline * PIECE_FLOPS["piece"]
-                   + stats["lines"] * PIECE_FLOPS["line"] + stats["ranges"] * PIECE_FLOPS["range"]
-                   + stats["evolutes"] * PIECE_FLOPS["evolute"] + stats["joins"] * PIECE_FLOPS["join"])
-    if names[dom] == "pieces":
-        achieved = piece_flops / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "piece_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                "algorithmic_flops_per_launch": piece_flops, "work": stats, "flops_per_unit": PIECE_FLOPS,
-                "precision": "fp64 (decisions)"}
-    elif names[dom] == "records":
-        flops = n_rec * FLOPS_PER_RECORD[mode]
-        achieved = flops / (phase_ms[dom] * 1e-3) / 1e12
-        roof = {"kernel": "record_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                "units_per_launch": {"records": n_rec}, "flops_per_record": FLOPS_PER_RECORD[mode]}
+    n_slots = stats["pieces"] + n_tags
+    curve_pieces = stats["pieces"] - stats["lines"]
+    work = {
+        # algorithmic FP64 flops per launch of each kernel
+        "bisect_count": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
+        "bisect_write": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
+        "slots": (curve_pieces * FLOPS["piece"] + stats["lines"] * FLOPS["line"] + stats["ranges"] * FLOPS["range"]
+                  + stats["evolutes"] * FLOPS["evolute"] + stats["joins"] * FLOPS["join"]),
+        # algorithmic FP32 flops
+        "records": n_rec * FLOPS_PER_RECORD[mode],
+        # algorithmic bytes
+        "scan_tags": n_tags * 17.0,
+        "scan_slots": n_tags * 12.0,
+        "scan_records": n_slots * 12.0,
+    }
+    dom = max(phase_ms, key=phase_ms.get)
+    t_dom = phase_ms[dom] * 1e-3
+    if dom in ("bisect_count", "bisect_write", "slots"):
+        achieved = work[dom] / t_dom / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "precision": "fp64 (decisions)"}
+    elif dom == "records":
+        achieved = work[dom] / t_dom / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
     else:
-        per = 17 if names[dom] == "scan_tags" else 12
-        gbs = n_tags * per / (phase_ms[dom] * 1e-3) / 1e9
-        roof = {"kernel": names[dom], "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+        gbs = work[dom] / t_dom / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": gbs / PEAK_HBM_GBS, "traffic": None}
-    roof["phase_ms"] = {names[p]: phase_ms[p] for p in range(nph)}
-    roof["scan_tags_GBps"] = n_tags * 17 / (phase_ms[0] * 1e-3) / 1e9
-    roof["scan_counts_GBps"] = n_tags * 12 / (phase_ms[2] * 1e-3) / 1e9
-    roof["records_fp32_TFLOPs"] = n_rec * FLOPS_PER_RECORD[mode] / (phase_ms[3] * 1e-3) / 1e12
+    roof["algorithmic_work_per_launch"] = work[dom]
+    roof["phase_ms"] = phase_ms
+    roof["work_counts"] = stats
+    roof["flops_per_unit"] = FLOPS
+    roof["flops_per_record"] = FLOPS_PER_RECORD[mode]
+    roof["per_kernel"] = {
+        n: ({"TFLOP/s": work[n] / (phase_ms[n] * 1e-3) / 1e12} if n in ("bisect_count", "bisect_write", "slots",
+                                                                         "records")
+            else {"GB/s": work[n] / (phase_ms[n] * 1e-3) / 1e9}) for n in names}
     out = {
         "metric": "path segs/s expanded at 0.25px tol (batched vs plain); p50/p99 request latency",
         "value": n_seg / (ms * 1e-3),
@@ -362,7 +376,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
     ap.add_argument("--piece-waves", type=int, default=None)
     ap.add_argument("--chunk-k", type=int, default=None)
-    ap.add_argument("--piece-block", type=int, default=None)
+    ap.add_argument("--bisect-range", type=int, default=None)
+    ap.add_argument("--bisect-waves", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)

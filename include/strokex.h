@@ -148,10 +148,10 @@ int sx_expand(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mo
 
 /* Same pipeline without any host synchronisation or allocation (capturable
  * in a HIP graph).  out_count_dev: device memory, two uint64_t:
- *   [0] the record count (always written);
- *   [1] 0 on success, else the number of items the scene's workspace must
- *       hold: it was too small, nothing was emitted; one sx_expand call with
- *       the same tolerance and mode resizes it.
+ *   [0] the record count (always written when the workspace sufficed);
+ *   [1] 0 on success, else 1: the scene's slot or item workspace was too
+ *       small and nothing was emitted; one sx_expand call with the same
+ *       tolerance and mode resizes it.
  * When [0] exceeds the capacity nothing is emitted either; the caller
  * compares it with the capacity afterwards. */
 int sx_expand_async(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, void *out_dev,
@@ -181,17 +181,29 @@ int sx_debug_offsets(sx_ctx *ctx, const sx_scene *scene, float tolerance, int ou
 int sx_debug_piece_stats(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, uint64_t *stats6,
                          void *stream);
 
-/* The four phases of sx_expand_async, one kernel each, for per-kernel timing:
- *   SX_PHASE_SCAN_TAGS   tag-monoid scan (Section 8.2)
- *   SX_PHASE_PIECES      per-segment decisions (Algorithms 1-2) in FP64:
- *                        emission items and per-tag record counts
- *   SX_PHASE_SCAN_COUNTS exclusive scan of the counts into output offsets
- *   SX_PHASE_RECORDS     per item, records written at their offsets
+/* The phases of sx_expand_async, one kernel each, for per-kernel timing:
+ *   SX_PHASE_SCAN_TAGS     tag-monoid scan (Section 8.2)
+ *   SX_PHASE_BISECT_COUNT  Algorithm 2 per segment: slots per tag (pieces + 1)
+ *   SX_PHASE_SCAN_SLOTS    exclusive scan of the slot counts (slot bases)
+ *   SX_PHASE_BISECT_WRITE  Algorithm 2 again: each piece's slot at its base
+ *   SX_PHASE_SLOTS         per slot: Euler spiral, parallel curves and counts
+ *                          (Sections 4-6) or the join / cap (Algorithm 1) as
+ *                          emission items, and the slot's record count
+ *   SX_PHASE_SCAN_RECORDS  exclusive scan of the record counts (offsets)
+ *   SX_PHASE_RECORDS       per item, records written at their offsets
  * Run in this order on one stream they equal sx_expand_async without the
  * final count copy.  out_dev / out_capacity_bytes are used by
  * SX_PHASE_RECORDS only (nothing is written when the total exceeds the
  * capacity).  Errors: SX_EINVAL (bad phase, tolerance or mode), SX_EDEVICE. */
-enum { SX_PHASE_SCAN_TAGS = 0, SX_PHASE_PIECES = 1, SX_PHASE_SCAN_COUNTS = 2, SX_PHASE_RECORDS = 3 };
+enum {
+    SX_PHASE_SCAN_TAGS = 0,
+    SX_PHASE_BISECT_COUNT = 1,
+    SX_PHASE_SCAN_SLOTS = 2,
+    SX_PHASE_BISECT_WRITE = 3,
+    SX_PHASE_SLOTS = 4,
+    SX_PHASE_SCAN_RECORDS = 5,
+    SX_PHASE_RECORDS = 6
+};
 int sx_run_phase(sx_ctx *ctx, const sx_scene *scene, int phase, float tolerance, int output_mode, void *out_dev,
                  uint64_t out_capacity_bytes, void *stream);
 
@@ -236,17 +248,19 @@ int sx_batch_expand(sx_ctx *ctx, sx_batch *batch, float tolerance, int output_mo
 
 /* Launch parameters of a context (used by every later call on it; the
  * outline does not depend on them):
- *   piece_waves  1..3: waves per SIMD the piece kernel's register allocation
- *                allows (more waves hide more latency but spill more);
- *   chunk_k      1..255: records per emission item chunk (work per thread of
- *                the record kernel);
- *   piece_block  64 or 256 (0 = 256): tags per piece-kernel workgroup.
- * Defaults {2, 16, 256}.  Errors: SX_EINVAL (out of range, reserved != 0). */
+ *   piece_waves   1..3: waves per SIMD the slot kernel's register
+ *                 allocation allows (more waves hide more latency but spill);
+ *   chunk_k       1..255: records per emission item chunk (work per thread
+ *                 of the record kernel);
+ *   bisect_range  tags per bisection wave, a multiple of 64 up to 8192
+ *                 (0 = 256): longer ranges keep lanes refilled longer;
+ *   bisect_waves  2 or 4 (0 = 2): waves per SIMD of the bisection kernels.
+ * Defaults {2, 16, 256, 2}.  Errors: SX_EINVAL (out of range). */
 typedef struct {
     uint32_t piece_waves;
     uint32_t chunk_k;
-    uint32_t piece_block;
-    uint32_t reserved1; /* must be 0 */
+    uint32_t bisect_range;
+    uint32_t bisect_waves;
 } sx_tuning;
 int sx_set_tuning(sx_ctx *ctx, const sx_tuning *tuning);
 int sx_get_tuning(const sx_ctx *ctx, sx_tuning *tuning);

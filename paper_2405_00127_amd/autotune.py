@@ -1,14 +1,15 @@
 """Launch-parameter autotuner of the stroke-expansion pipeline.
 
 The outline does not depend on the launch parameters (``sx_set_tuning``), only
-the speed does: the piece kernel's register budget (waves per SIMD it must
-allow; more waves hide more FP64 latency but spill more), its workgroup size
-(one wave per group frees a SIMD as soon as its wave ends) and the number of
+the speed does: the slot kernel's register budget (waves per SIMD it must
+allow; more waves hide more FP64 latency but spill more), the bisection
+kernels' range of tags per wave and their register budget, and the number of
 records per emission item chunk (work per record-kernel thread; longer chunks
-amortise the item read, shorter ones balance the load).  The tuner times each
-candidate on the caller's own scene with HIP events on the caller's stream and
-keeps the fastest; results are cached per device and workload shape in a JSON
-file so a serving process tunes once.
+amortise the item read, shorter ones balance the load).  The tuner times
+candidates on the caller's own scene with HIP events on the caller's stream,
+one knob group at a time (the groups drive different kernels), and keeps the
+fastest; results are cached per device and workload shape in a JSON file so a
+serving process tunes once.
 """
 from __future__ import annotations
 
@@ -19,8 +20,10 @@ import threading
 from typing import Dict, Iterable, Optional, Tuple
 
 PIECE_WAVES = (1, 2, 3)
-PIECE_BLOCK = (64, 256)
+BISECT_RANGE = (128, 256, 512, 1024)
+BISECT_WAVES = (2, 4)
 CHUNK_K = (4, 8, 16, 32, 64)
+KEYS = ("piece_waves", "chunk_k", "bisect_range", "bisect_waves")
 
 _lock = threading.Lock()
 
@@ -77,15 +80,13 @@ def time_config(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity:
 
 
 def tune(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, count_ptr: int, stream=None,
-         waves: Iterable[int] = PIECE_WAVES, blocks: Iterable[int] = PIECE_BLOCK, chunks: Iterable[int] = CHUNK_K,
          reps: int = 5, cache_path: Optional[str] = None, use_cache: bool = True) -> Tuple[dict, Dict[str, float]]:
-    """Pick the fastest (piece_waves, piece_block, chunk_k) for this scene and
-    set it on ``ctx``.  The output buffer must already be large enough (size
-    it with one ``ctx.expand``).  The piece-kernel knobs are searched first
-    with the current chunk size, then the chunk size with the best of those
-    (the two stages do not interact: chunk_k only changes the record kernel).
-    Returns (chosen tuning, {"w{W}b{B}k{K}": ms} of every candidate timed;
-    empty when the cache answered)."""
+    """Pick the fastest launch parameters for this scene and set them on
+    ``ctx``.  The output buffer must already be large enough (size it with
+    one ``ctx.expand``).  Coordinate search: the slot kernel's waves, then the
+    bisection range and waves, then the chunk size.  Returns (chosen tuning,
+    {"w{W}r{R}b{B}k{K}": ms} of every candidate timed; empty when the cache
+    answered)."""
     import torch
 
     stream = stream if stream is not None else torch.cuda.current_stream()
@@ -94,26 +95,43 @@ def tune(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, c
     if use_cache:
         with _lock:
             hit = _load(path).get(key)
-        if (hit and hit.get("piece_waves") in PIECE_WAVES and hit.get("piece_block") in PIECE_BLOCK
-                and 1 <= int(hit.get("chunk_k", 0)) <= 255):
-            ctx.set_tuning(int(hit["piece_waves"]), int(hit["chunk_k"]), int(hit["piece_block"]))
+        if (hit and all(k in hit for k in KEYS) and hit["piece_waves"] in PIECE_WAVES
+                and hit["bisect_range"] in BISECT_RANGE and hit["bisect_waves"] in BISECT_WAVES
+                and 1 <= int(hit["chunk_k"]) <= 255):
+            ctx.set_tuning(**{k: int(hit[k]) for k in KEYS})
             return ctx.get_tuning(), {}
     times: Dict[str, float] = {}
-    k0 = ctx.get_tuning()["chunk_k"]
+    cur = ctx.get_tuning()
 
-    def run(w, b, k):
-        ctx.set_tuning(w, k, b)
-        ms = time_config(ctx, scene, tolerance, mode, out_ptr, capacity, count_ptr, stream, reps)
-        times[f"w{w}b{b}k{k}"] = ms
-        return ms
+    def run(t):
+        name = f"w{t['piece_waves']}r{t['bisect_range']}b{t['bisect_waves']}k{t['chunk_k']}"
+        if name not in times:
+            ctx.set_tuning(**t)
+            times[name] = time_config(ctx, scene, tolerance, mode, out_ptr, capacity, count_ptr, stream, reps)
+        return times[name]
 
-    best = min(((run(w, b, k0), w, b) for w in waves for b in blocks), key=lambda t: t[0])
-    _, bw, bb = best
-    bestk = min(((times.get(f"w{bw}b{bb}k{k}") or run(bw, bb, k), k) for k in chunks), key=lambda t: t[0])
-    ctx.set_tuning(bw, bestk[1], bb)
+    for group in ({"piece_waves": PIECE_WAVES}, {"bisect_range": BISECT_RANGE, "bisect_waves": BISECT_WAVES},
+                  {"chunk_k": CHUNK_K}):
+        names = list(group)
+        cands = [dict(cur)]
+        for vals in _product([group[n] for n in names]):
+            c = dict(cur)
+            c.update(zip(names, vals))
+            cands.append(c)
+        cur = min(cands, key=run)
+    ctx.set_tuning(**cur)
     chosen = ctx.get_tuning()
     with _lock:
         data = _load(path)
-        data[key] = dict(chosen, ms=bestk[0])
+        data[key] = dict(chosen, ms=min(times.values()))
         _store(path, data)
     return chosen, times
+
+
+def _product(lists):
+    if not lists:
+        yield ()
+        return
+    for v in lists[0]:
+        for rest in _product(lists[1:]):
+            yield (v,) + rest

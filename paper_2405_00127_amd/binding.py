@@ -22,8 +22,9 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "strokex.h")
 
 SX_OK, SX_EINVAL, SX_ENOMEM, SX_EDEVICE, SX_ETOOSMALL, SX_EBUSY = 0, -1, -2, -3, -4, -5
 OUT_LINES, OUT_ARCS = 0, 1
-PHASE_SCAN_TAGS, PHASE_PIECES, PHASE_SCAN_COUNTS, PHASE_RECORDS = 0, 1, 2, 3
-PHASE_NAMES = ["scan_tags", "pieces", "scan_counts", "records"]
+(PHASE_SCAN_TAGS, PHASE_BISECT_COUNT, PHASE_SCAN_SLOTS, PHASE_BISECT_WRITE, PHASE_SLOTS, PHASE_SCAN_RECORDS,
+ PHASE_RECORDS) = range(7)
+PHASE_NAMES = ["scan_tags", "bisect_count", "scan_slots", "bisect_write", "slots", "scan_records", "records"]
 RECORD_BYTES = {OUT_LINES: 20, OUT_ARCS: 24}
 
 LINE_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("path", "<u4")])
@@ -42,8 +43,8 @@ class _Paths(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("piece_block", C.c_uint32),
-                ("reserved1", C.c_uint32)]
+    _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("bisect_range", C.c_uint32),
+                ("bisect_waves", C.c_uint32)]
 
 
 _lib = None
@@ -228,14 +229,21 @@ class Context:
                 out = torch.empty(int(e.required * 1.25 + 1) * rec, dtype=torch.uint8, device=out.device)
         return out[: n * rec].view(torch.float32).view(-1, rec // 4), n, out
 
-    def set_tuning(self, piece_waves: int, chunk_k: int, piece_block: int = 256):
-        t = _Tuning(int(piece_waves), int(chunk_k), int(piece_block), 0)
+    def set_tuning(self, piece_waves: int = None, chunk_k: int = None, bisect_range: int = None,
+                   bisect_waves: int = None):
+        """Set launch parameters (unspecified ones keep their value)."""
+        cur = self.get_tuning() if self.h else {}
+        t = _Tuning(int(piece_waves if piece_waves is not None else cur["piece_waves"]),
+                    int(chunk_k if chunk_k is not None else cur["chunk_k"]),
+                    int(bisect_range if bisect_range is not None else cur["bisect_range"]),
+                    int(bisect_waves if bisect_waves is not None else cur["bisect_waves"]))
         self._check(lib().sx_set_tuning(C.c_void_p(self.h), C.byref(t)), "sx_set_tuning")
 
     def get_tuning(self):
         t = _Tuning()
         self._check(lib().sx_get_tuning(C.c_void_p(self.h), C.byref(t)), "sx_get_tuning")
-        return {"piece_waves": t.piece_waves, "chunk_k": t.chunk_k, "piece_block": t.piece_block}
+        return {"piece_waves": t.piece_waves, "chunk_k": t.chunk_k, "bisect_range": t.bisect_range,
+                "bisect_waves": t.bisect_waves}
 
     def piece_stats(self, scene: Scene, tolerance=None, mode=None, stream=None) -> dict:
         """Work counts of the piece phase (instrumented run; synchronous)."""

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <new>
 #include <string>
@@ -17,30 +18,38 @@
 struct sx_ctx {
     int device = 0;
     std::string err;
-    sx_tuning tune = {2u, 16u, 256u, 0u};
-    uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, items needed
+    sx_tuning tune = {2u, 16u, 256u, 2u};
+    uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, status
 };
 
 struct sx_scene {
     sx_ctx* ctx = nullptr;
     uint32_t n_tags = 0, n_pts = 0, n_paths = 0, n_styles = 0, n_xforms = 0;
+    // encoded streams
     uint8_t* d_tags = nullptr;
     float2* d_pts = nullptr;
     sx::StyleD* d_styles = nullptr;
     float* d_xforms = nullptr;
     uint32_t* d_path_map = nullptr;
+    // per tag: monoids, slot counts and their exclusive scan (slot bases)
     uint32_t* d_mon = nullptr;
-    uint32_t* d_counts = nullptr;
-    uint64_t* d_offsets = nullptr;
-    void* d_scan_ctl = nullptr;  // two control blocks (tags, counts)
+    uint32_t* d_nslots = nullptr;
+    uint64_t* d_base = nullptr;
+    // per slot: the slot, its record count and record offset
+    sx::Slot* d_slots = nullptr;
+    uint32_t* d_rc = nullptr;
+    uint64_t* d_roff = nullptr;
+    void* d_scan_ctl = nullptr;  // three control blocks (tags, slot counts, record counts)
     void* d_status_tags = nullptr;
-    void* d_status_counts = nullptr;
-    // item workspace of the piece / record kernels
+    void* d_status_nslots = nullptr;
+    void* d_status_rc = nullptr;
+    // item workspace of the slot / record kernels
     sx::Item* d_items = nullptr;
     uint32_t* d_tile_n = nullptr;
     sx::WsCtl* d_ws_ctl = nullptr;
-    uint32_t region_per_tag = 0;  // item slots per tag in the per-tile regions
-    uint64_t ovf_cap = 0;         // shared overflow slots
+    uint32_t region_per_slot = 0;  // items per slot in the per-tile regions
+    uint64_t ovf_cap = 0;          // shared overflow items
+    uint64_t slot_cap = 0;         // slots the slot buffers hold
     // allocated capacities (a batch arena is reused for smaller contents)
     uint32_t cap_tags = 0, cap_pts = 0, cap_styles = 0, cap_xforms = 0, cap_paths = 0;
     bool allocated = false;
@@ -60,9 +69,11 @@ struct sx_batch {
 namespace {
 
 constexpr uint32_t kMaxBatchScenes = 65535;
-constexpr uint32_t kMinTile = 64, kMaxTile = 256;  // piece kernel block sizes
-constexpr uint32_t kRegionPerTag = 8;      // initial item slots per tag
-constexpr uint64_t kMinOverflow = 65536;   // initial shared overflow slots (minimum)
+constexpr uint32_t kSlotsPerTag = 4;        // initial slot capacity per tag
+constexpr uint32_t kRegionPerSlot = 3;      // initial items per slot in the tile regions
+constexpr uint64_t kMinSlots = 4096;
+constexpr uint64_t kMinOverflow = 65536;    // initial shared overflow items (minimum)
+constexpr uint32_t kMaxSlotCap = 0xfffff000u;  // slots are indexed by u32
 
 int fail(sx_ctx* ctx, int code, const std::string& msg) {
     if (ctx) ctx->err = msg;
@@ -77,14 +88,32 @@ template <class T>
 hipError_t dalloc(T** p, size_t bytes) {
     return hipMalloc((void**)p, bytes ? bytes : 16);
 }
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
 
 void free_scene(sx_scene* s) {
     if (!s) return;
-    void* bufs[] = {s->d_tags,     s->d_pts,           s->d_styles,        s->d_xforms, s->d_path_map,
-                    s->d_mon,      s->d_counts,        s->d_offsets,       s->d_scan_ctl, s->d_status_tags,
-                    s->d_status_counts, s->d_items,    s->d_tile_n,        s->d_ws_ctl};
-    for (void* b : bufs)
-        if (b) (void)hipFree(b);
+    dfree(s->d_tags);
+    dfree(s->d_pts);
+    dfree(s->d_styles);
+    dfree(s->d_xforms);
+    dfree(s->d_path_map);
+    dfree(s->d_mon);
+    dfree(s->d_nslots);
+    dfree(s->d_base);
+    dfree(s->d_slots);
+    dfree(s->d_rc);
+    dfree(s->d_roff);
+    dfree(s->d_scan_ctl);
+    dfree(s->d_status_tags);
+    dfree(s->d_status_nslots);
+    dfree(s->d_status_rc);
+    dfree(s->d_items);
+    dfree(s->d_tile_n);
+    dfree(s->d_ws_ctl);
     delete s;
 }
 
@@ -113,86 +142,106 @@ sx::SceneView view(const sx_scene* s) {
     return v;
 }
 
-sx::ItemWs workspace(const sx_scene* s, uint32_t tile) {
+sx::ItemWs workspace(const sx_scene* s) {
     sx::ItemWs w;
     w.items = s->d_items;
     w.tile_n = s->d_tile_n;
     w.ctl = s->d_ws_ctl;
-    w.tile = tile;
-    w.region_cap = s->region_per_tag * tile;
-    w.ovf_base = (uint64_t)sx::piece_tiles(s->n_tags, tile) * w.region_cap;
+    w.tile = sx::slot_block();
+    w.region_cap = s->region_per_slot * w.tile;
+    w.ovf_base = (uint64_t)sx::slot_tiles(s->slot_cap) * w.region_cap;
     w.ovf_cap = s->ovf_cap;
     return w;
 }
-sx::ItemWs workspace(const sx_scene* s, const sx_ctx* ctx) { return workspace(s, ctx->tune.piece_block); }
 
-// (Re)allocate the item workspace: region_per_tag slots per tag in each
-// piece tile's region (room for either tile size) plus ovf shared slots.
-// The caller has synchronised.
-hipError_t size_workspace(sx_scene* s, uint32_t region_per_tag, uint64_t ovf) {
-    if (s->d_items) (void)hipFree(s->d_items);
-    s->d_items = nullptr;
-    s->region_per_tag = region_per_tag;
+char* ctl_block(const sx_scene* s, int k) { return (char*)s->d_scan_ctl + k * sx::scan_ctl_bytes(); }
+
+// (Re)allocate the slot buffers for slot_cap slots and the item workspace
+// (region_per_slot items per slot in the tile regions, ovf shared items).
+// Scan status words are zeroed when allocated.  Ordered on st; allocation is
+// synchronous.
+hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_slot, uint64_t ovf, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) {
+        if (e == hipSuccess) e = r;
+    };
+    if (slot_cap != s->slot_cap || !s->d_slots) {
+        dfree(s->d_slots);
+        dfree(s->d_rc);
+        dfree(s->d_roff);
+        dfree(s->d_status_rc);
+        dfree(s->d_tile_n);
+        A(dalloc(&s->d_slots, slot_cap * sizeof(sx::Slot)));
+        A(dalloc(&s->d_rc, (slot_cap + 16) * sizeof(uint32_t)));
+        A(dalloc(&s->d_roff, (slot_cap + 1) * sizeof(uint64_t)));
+        A(dalloc(&s->d_status_rc, sx::scan_status_bytes((uint32_t)slot_cap)));
+        A(dalloc(&s->d_tile_n, (size_t)sx::slot_tiles(slot_cap) * sizeof(uint32_t)));
+        if (e == hipSuccess) A(hipMemsetAsync(s->d_status_rc, 0, sx::scan_status_bytes((uint32_t)slot_cap), st));
+        if (e != hipSuccess) return e;
+        s->slot_cap = slot_cap;
+    }
+    dfree(s->d_items);
+    s->region_per_slot = region_per_slot;
     s->ovf_cap = ovf;
-    const uint64_t tags = ((uint64_t)s->cap_tags + kMaxTile - 1) / kMaxTile * kMaxTile;
-    const uint64_t slots = tags * region_per_tag + ovf;
-    return dalloc(&s->d_items, slots * sizeof(sx::Item));
+    const uint64_t items = (uint64_t)sx::slot_tiles(slot_cap) * sx::slot_block() * region_per_slot + ovf;
+    return dalloc(&s->d_items, items * sizeof(sx::Item));
 }
 
 // Grow the scene's device buffers to hold at least the given sizes (the
-// contents are rewritten by the caller).  Scan status words and control
-// blocks are zeroed whenever they are (re)allocated; the item workspace keeps
-// its slots per tag.  Ordered on st; allocation is synchronous.
+// contents are rewritten by the caller).  Ordered on st; allocation is
+// synchronous.
 hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t n_styles, uint32_t n_xforms,
                          uint32_t n_paths, hipStream_t st) {
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t r) {
         if (e == hipSuccess) e = r;
     };
-    auto regrow = [&](auto** p, size_t bytes) {
-        if (*p) (void)hipFree(*p);
-        *p = nullptr;
-        A(dalloc(p, bytes));
+    auto regrow = [&](auto*& p, size_t bytes) {
+        dfree(p);
+        A(dalloc(&p, bytes));
     };
     const bool first = !s->allocated;
     if (first || n_tags > s->cap_tags) {
         const uint32_t c = n_tags;
         const size_t ntag_pad = ((size_t)c + 16 + 15) & ~(size_t)15;
-        regrow(&s->d_tags, ntag_pad);
-        regrow(&s->d_mon, 4 * (size_t)c * sizeof(uint32_t));
-        regrow(&s->d_counts, ((size_t)c + 16) * sizeof(uint32_t));
-        regrow(&s->d_offsets, ((size_t)c + 1) * sizeof(uint64_t));
-        regrow(&s->d_status_tags, sx::scan_status_bytes(c));
-        regrow(&s->d_status_counts, sx::scan_status_bytes(c));
-        regrow(&s->d_tile_n, (size_t)sx::piece_tiles(c, kMinTile) * sizeof(uint32_t));
+        regrow(s->d_tags, ntag_pad);
+        regrow(s->d_mon, 4 * (size_t)c * sizeof(uint32_t));
+        regrow(s->d_nslots, ((size_t)c + 16) * sizeof(uint32_t));
+        regrow(s->d_base, ((size_t)c + 1) * sizeof(uint64_t));
+        regrow(s->d_status_tags, sx::scan_status_bytes(c));
+        regrow(s->d_status_nslots, sx::scan_status_bytes(c));
         if (e != hipSuccess) return e;
         s->cap_tags = c;
-        const uint32_t per_tag = s->region_per_tag ? s->region_per_tag : kRegionPerTag;
-        A(size_workspace(s, per_tag, std::max<uint64_t>(std::max<uint64_t>(c, s->ovf_cap), kMinOverflow)));
         A(hipMemsetAsync(s->d_tags, 0, ntag_pad, st));
         A(hipMemsetAsync(s->d_status_tags, 0, sx::scan_status_bytes(c), st));
-        A(hipMemsetAsync(s->d_status_counts, 0, sx::scan_status_bytes(c), st));
+        A(hipMemsetAsync(s->d_status_nslots, 0, sx::scan_status_bytes(c), st));
+        const uint64_t want = std::max<uint64_t>((uint64_t)c * kSlotsPerTag, kMinSlots);
+        if (want > s->slot_cap) {
+            const uint32_t region = s->region_per_slot ? s->region_per_slot : kRegionPerSlot;
+            A(size_slots(s, std::min<uint64_t>(want, kMaxSlotCap), region,
+                         std::max<uint64_t>(std::max<uint64_t>(want, s->ovf_cap), kMinOverflow), st));
+        }
     }
     if (first || n_pts > s->cap_pts) {
-        regrow(&s->d_pts, (size_t)n_pts * sizeof(float2));
+        regrow(s->d_pts, (size_t)n_pts * sizeof(float2));
         s->cap_pts = n_pts;
     }
     if (first || n_styles > s->cap_styles) {
-        regrow(&s->d_styles, (size_t)n_styles * sizeof(sx::StyleD));
+        regrow(s->d_styles, (size_t)n_styles * sizeof(sx::StyleD));
         s->cap_styles = n_styles;
     }
     if (first || n_xforms > s->cap_xforms) {
-        regrow(&s->d_xforms, (size_t)n_xforms * 6 * sizeof(float));
+        regrow(s->d_xforms, (size_t)n_xforms * 6 * sizeof(float));
         s->cap_xforms = n_xforms;
     }
     if (first || n_paths > s->cap_paths) {
-        regrow(&s->d_path_map, (size_t)n_paths * sizeof(uint32_t));
+        regrow(s->d_path_map, (size_t)n_paths * sizeof(uint32_t));
         s->cap_paths = n_paths;
     }
     if (first) {
-        A(dalloc(&s->d_scan_ctl, 2 * sx::scan_ctl_bytes()));
+        A(dalloc(&s->d_scan_ctl, 3 * sx::scan_ctl_bytes()));
         A(dalloc(&s->d_ws_ctl, sizeof(sx::WsCtl)));
-        A(hipMemsetAsync(s->d_scan_ctl, 0, 2 * sx::scan_ctl_bytes(), st));
+        A(hipMemsetAsync(s->d_scan_ctl, 0, 3 * sx::scan_ctl_bytes(), st));
         A(hipMemsetAsync(s->d_ws_ctl, 0, sizeof(sx::WsCtl), st));
     }
     if (e == hipSuccess) s->allocated = true;
@@ -213,32 +262,87 @@ bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
     return true;
 }
 
-// tag scan + pieces + count scan
-int run_counts(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, hipStream_t st) {
-    hipError_t e;
-    char* ctl = (char*)s->d_scan_ctl;
-    if ((e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st)) !=
-        hipSuccess)
-        return hip_fail(ctx, e, "scan_tags launch");
-    if ((e = sx::launch_pieces(view(s), cfg, workspace(s, ctx), s->d_counts, (int)ctx->tune.piece_waves, st)) !=
-        hipSuccess)
-        return hip_fail(ctx, e, "pieces launch");
-    if ((e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
-                                    s->d_status_counts, st)) != hipSuccess)
-        return hip_fail(ctx, e, "scan_counts launch");
+const uint64_t* n_slots_dev(const sx_scene* s) { return s->d_base + s->n_tags; }
+
+// Pipeline phases (each one kernel, in this order on one stream).
+enum { kPhScanTags, kPhBisectCount, kPhScanSlots, kPhBisectWrite, kPhSlots, kPhScanRecords, kPhRecords, kPhN };
+
+hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int ph, void* out, uint64_t cap_records,
+                   unsigned long long* stats, hipStream_t st) {
+    const sx_tuning& t = ctx->tune;
+    if (s->n_tags == 0) return hipSuccess;
+    switch (ph) {
+        case kPhScanTags:
+            return sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl_block(s, 0), s->d_status_tags, s->d_ws_ctl,
+                                        st);
+        case kPhBisectCount:
+            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, false, s->d_nslots, nullptr,
+                                     nullptr, 0, stats, st);
+        case kPhScanSlots:
+            return sx::launch_scan_counts(s->d_nslots, s->n_tags, s->d_base, ctl_block(s, 1), s->d_status_nslots, st);
+        case kPhBisectWrite:
+            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, true, nullptr, s->d_base,
+                                     s->d_slots, s->slot_cap, nullptr, st);
+        case kPhSlots:
+            return sx::launch_slots(view(s), cfg, workspace(s), s->d_slots, n_slots_dev(s), s->slot_cap, s->d_rc,
+                                    (int)t.piece_waves, stats, st);
+        case kPhScanRecords:
+            return sx::launch_scan_counts_dev(s->d_rc, n_slots_dev(s), (uint32_t)s->slot_cap, s->d_roff,
+                                              ctl_block(s, 2), s->d_status_rc, st);
+        case kPhRecords:
+            return sx::launch_records(view(s), workspace(s), cfg.arcs, s->d_roff, n_slots_dev(s), s->slot_cap, out,
+                                      cap_records, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+// phases [0, last) of the pipeline
+int run_phases(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int last, void* out, uint64_t cap_records,
+               hipStream_t st) {
+    for (int ph = 0; ph < last; ph++) {
+        hipError_t e = run_one(ctx, s, cfg, ph, out, cap_records, nullptr, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "pipeline launch");
+    }
     return SX_OK;
 }
 
-// the whole pipeline; dst (device) receives {records, items needed or 0}
+// the whole pipeline; dst (device) receives {records, 0 or 1 = workspace too small}
 int run_all(sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, void* out, uint64_t cap_records, uint64_t* dst,
             hipStream_t st) {
-    int r = run_counts(ctx, s, cfg, st);
+    int r = run_phases(ctx, s, cfg, kPhN, out, cap_records, st);
     if (r != SX_OK) return r;
-    hipError_t e = sx::launch_records(view(s), workspace(s, ctx), cfg.arcs, s->d_offsets, out, cap_records, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "records launch");
-    e = sx::launch_finish(s->d_offsets, s->n_tags, workspace(s, ctx), dst, st);
-    if (e != hipSuccess) return hip_fail(ctx, e, "finish launch");
-    return SX_OK;
+    hipError_t e = sx::launch_finish(s->d_roff, n_slots_dev(s), s->slot_cap, s->n_tags, workspace(s), dst, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "finish launch");
+}
+
+// Synchronous expansion with workspace growth: runs the pipeline, and when
+// slots or items did not fit, grows what was short (from the counters the
+// run left) and runs again.  The slot and item counts are deterministic
+// functions of the scene, tolerance and mode, so the grown run fits.
+int run_sized(sx_ctx* ctx, sx_scene* s, const sx::Cfg& cfg, void* out, uint64_t cap_records, uint64_t* n_records,
+              hipStream_t st) {
+    for (int attempt = 0; attempt < 3; attempt++) {
+        uint64_t* dst = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(s->d_ws_ctl) + offsetof(sx::WsCtl, result));
+        int r = run_all(ctx, s, cfg, out, cap_records, dst, st);
+        if (r != SX_OK) return r;
+        sx::WsCtl w;
+        hipError_t e = hipMemcpyAsync(&w, s->d_ws_ctl, sizeof(w), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "count readback");
+        *n_records = w.result[0];
+        if (w.result[1] == 0) return SX_OK;
+        if (w.slots_total > s->slot_cap) {
+            if (w.slots_total > kMaxSlotCap) return fail(ctx, SX_ENOMEM, "scene needs more than 2^32 slots");
+            const uint64_t cap = std::min<uint64_t>(w.slots_total + w.slots_total / 4 + 64, kMaxSlotCap);
+            e = size_slots(s, cap, s->region_per_slot, std::max<uint64_t>(s->ovf_cap, cap), st);
+        } else {
+            const uint64_t per = (w.items_total * 5 / 4 + w.slots_total - 1) / std::max<uint64_t>(w.slots_total, 1);
+            const uint32_t region = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per, kRegionPerSlot), 64);
+            e = size_slots(s, s->slot_cap, region, std::max<uint64_t>(w.items_total, kMinOverflow), st);
+        }
+        if (e != hipSuccess) return hip_fail(ctx, e, "workspace allocation");
+    }
+    return fail(ctx, SX_EDEVICE, "workspace still too small after resizing");
 }
 
 }  // namespace
@@ -275,11 +379,13 @@ int sx_set_tuning(sx_ctx* ctx, const sx_tuning* t) {
     if (!ctx || !t) return SX_EINVAL;
     if (t->piece_waves < 1 || t->piece_waves > 3) return fail(ctx, SX_EINVAL, "piece_waves must be 1, 2 or 3");
     if (t->chunk_k < 1 || t->chunk_k > 255) return fail(ctx, SX_EINVAL, "chunk_k must be in [1, 255]");
-    if (t->piece_block != 0 && t->piece_block != 64 && t->piece_block != 256)
-        return fail(ctx, SX_EINVAL, "piece_block must be 64 or 256 (0: 256)");
-    if (t->reserved1) return fail(ctx, SX_EINVAL, "reserved tuning fields must be 0");
+    if (t->bisect_range != 0 && (t->bisect_range % 64 || t->bisect_range > 8192))
+        return fail(ctx, SX_EINVAL, "bisect_range must be a multiple of 64 up to 8192 (0: 256)");
+    if (t->bisect_waves != 0 && t->bisect_waves != 2 && t->bisect_waves != 4)
+        return fail(ctx, SX_EINVAL, "bisect_waves must be 2 or 4 (0: 2)");
     ctx->tune = *t;
-    if (ctx->tune.piece_block == 0) ctx->tune.piece_block = 256;
+    if (ctx->tune.bisect_range == 0) ctx->tune.bisect_range = 256;
+    if (ctx->tune.bisect_waves == 0) ctx->tune.bisect_waves = 2;
     return SX_OK;
 }
 
@@ -399,10 +505,6 @@ int sx_expand_async(sx_ctx* ctx, const sx_scene* scene, float tolerance, int out
     const_cast<sx_scene*>(scene)->last_stream = st;
     cfg.K = ctx->tune.chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
-    if (scene->n_tags == 0) {
-        hipError_t e = hipMemsetAsync(out_count_dev, 0, 2 * sizeof(uint64_t), st);
-        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
-    }
     return run_all(ctx, scene, cfg, out_dev, out_capacity_bytes / rec, out_count_dev, st);
 }
 
@@ -419,25 +521,8 @@ int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mo
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     *out_count = 0;
     if (s->n_tags == 0) return SX_OK;
-    // the second attempt has a workspace sized from the first one's request
-    // and cannot overflow (the item count is a deterministic function of the
-    // scene, tolerance and mode)
-    for (int attempt = 0; attempt < 2; attempt++) {
-        uint64_t* dev2 = (uint64_t*)s->d_ws_ctl->result;
-        int r = run_all(ctx, s, cfg, out_dev, out_capacity_bytes / rec, dev2, st);
-        if (r != SX_OK) return r;
-        hipError_t e = hipMemcpyAsync(ctx->pinned_total, dev2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(ctx, e, "count readback");
-        const uint64_t need = ctx->pinned_total[1];
-        *out_count = ctx->pinned_total[0];
-        if (need == 0) break;
-        if (attempt == 1) return fail(ctx, SX_EDEVICE, "item workspace overflow after resizing");
-        const uint64_t per_tag = (need * 5 / 4 + s->n_tags - 1) / s->n_tags;
-        const uint32_t region = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per_tag, kRegionPerTag), 256);
-        e = size_workspace(s, region, need);
-        if (e != hipSuccess) return hip_fail(ctx, e, "item workspace allocation");
-    }
+    int r = run_sized(ctx, s, cfg, out_dev, out_capacity_bytes / rec, out_count, st);
+    if (r != SX_OK) return r;
     if (*out_count > out_capacity_bytes / rec) return fail(ctx, SX_ETOOSMALL, "output buffer too small");
     return SX_OK;
 }
@@ -447,32 +532,14 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
     if (!ctx || !s) return SX_EINVAL;
     sx::Cfg cfg;
     if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (phase < 0 || phase >= kPhN) return fail(ctx, SX_EINVAL, "bad phase");
+    if (phase == kPhRecords && out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     if (s->n_tags == 0) return SX_OK;
     cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(s)->last_stream = st;
-    char* ctl = (char*)s->d_scan_ctl;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
-    hipError_t e;
-    switch (phase) {
-        case SX_PHASE_SCAN_TAGS:
-            e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
-            break;
-        case SX_PHASE_PIECES:
-            e = sx::launch_pieces(view(s), cfg, workspace(s, ctx), s->d_counts, (int)ctx->tune.piece_waves, st);
-            break;
-        case SX_PHASE_SCAN_COUNTS:
-            e = sx::launch_scan_counts(s->d_counts, s->n_tags, s->d_offsets, ctl + sx::scan_ctl_bytes(),
-                                       s->d_status_counts, st);
-            break;
-        case SX_PHASE_RECORDS:
-            if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
-            e = sx::launch_records(view(s), workspace(s, ctx), cfg.arcs, s->d_offsets, out_dev, out_capacity_bytes / rec,
-                                   st);
-            break;
-        default:
-            return fail(ctx, SX_EINVAL, "bad phase");
-    }
+    hipError_t e = run_one(ctx, s, cfg, phase, out_dev, out_capacity_bytes / rec, nullptr, st);
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "phase launch");
 }
 
@@ -612,14 +679,10 @@ int sx_batch_expand(sx_ctx* ctx, sx_batch* b, float tolerance, int output_mode, 
     sx_scene* a = b->arena;
     a->last_stream = st;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
-    if (a->n_tags) {
-        int r = run_all(ctx, a, cfg, out_dev, out_capacity_bytes / rec, status_dev, st);
-        if (r != SX_OK) return r;
-    } else {
-        hipError_t e = sx::launch_finish(a->d_offsets, 0, workspace(a, ctx), status_dev, st);
-        if (e != hipSuccess) return hip_fail(ctx, e, "finish launch");
-    }
-    hipError_t e = sx::launch_scene_offsets(a->d_offsets, b->d_desc, b->n_scenes, a->n_tags, scene_offsets_dev, st);
+    int r = run_all(ctx, a, cfg, out_dev, out_capacity_bytes / rec, status_dev, st);
+    if (r != SX_OK) return r;
+    hipError_t e = sx::launch_scene_offsets(a->d_base, a->d_roff, a->slot_cap, b->d_desc, b->n_scenes, a->n_tags,
+                                            scene_offsets_dev, st);
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "scene offsets");
 }
 
@@ -632,12 +695,18 @@ int sx_debug_piece_stats(sx_ctx* ctx, const sx_scene* s, float tolerance, int ou
     if (s->n_tags == 0) return SX_OK;
     cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
+    sx_scene* sc = const_cast<sx_scene*>(s);
+    // size the workspace first, so the instrumented run covers every slot
+    uint64_t n_rec = 0;
+    int r = run_sized(ctx, sc, cfg, nullptr, 0, &n_rec, st);
+    if (r != SX_OK) return r;
     unsigned long long* d = nullptr;
-    char* ctl = (char*)s->d_scan_ctl;
     hipError_t e = hipMalloc((void**)&d, 6 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemsetAsync(d, 0, 6 * sizeof(unsigned long long), st);
-    if (e == hipSuccess) e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, s->d_ws_ctl, st);
-    if (e == hipSuccess) e = sx::launch_piece_stats(view(s), cfg, workspace(s, kMaxTile), s->d_counts, d, st);
+    for (int ph = 0; ph <= kPhSlots && e == hipSuccess; ph++) {
+        const bool counted = ph == kPhBisectCount || ph == kPhSlots;
+        e = run_one(ctx, sc, cfg, ph, nullptr, 0, counted ? d : nullptr, st);
+    }
     if (e == hipSuccess) e = hipMemcpyAsync(stats6, d, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (d) (void)hipFree(d);
@@ -647,44 +716,41 @@ int sx_debug_piece_stats(sx_ctx* ctx, const sx_scene* s, float tolerance, int ou
 int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void* stream) {
     if (!ctx || !s || (!out4xn_dev && s->n_tags)) return SX_EINVAL;
     hipStream_t st = (hipStream_t)stream;
-    char* ctl = (char*)s->d_scan_ctl;
-    hipError_t e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl, s->d_status_tags, nullptr, st);
+    hipError_t e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl_block(s, 0), s->d_status_tags, nullptr, st);
     if (e == hipSuccess && s->n_tags)
         e = hipMemcpyAsync(out4xn_dev, s->d_mon, 4 * (size_t)s->n_tags * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "monoids");
 }
 
+// per-tag record counts and / or offsets after a sized run of the pipeline
+static int tag_records(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint32_t* counts,
+                       uint64_t* offs, void* stream) {
+    sx::Cfg cfg;
+    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    hipStream_t st = (hipStream_t)stream;
+    if (s->n_tags == 0) {
+        if (!offs) return SX_OK;
+        hipError_t e = hipMemsetAsync(offs, 0, sizeof(uint64_t), st);
+        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
+    }
+    cfg.K = ctx->tune.chunk_k;
+    uint64_t n_rec = 0;
+    int r = run_sized(ctx, const_cast<sx_scene*>(s), cfg, nullptr, 0, &n_rec, st);
+    if (r != SX_OK) return r;
+    hipError_t e = sx::launch_tag_records(s->d_base, s->d_roff, s->slot_cap, s->n_tags, counts, offs, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "tag records");
+}
+
 int sx_debug_counts(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint32_t* counts_dev,
                     void* stream) {
     if (!ctx || !s || (!counts_dev && s->n_tags)) return SX_EINVAL;
-    sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
-    if (s->n_tags == 0) return SX_OK;
-    cfg.K = ctx->tune.chunk_k;
-    hipStream_t st = (hipStream_t)stream;
-    int r = run_counts(ctx, s, cfg, st);
-    if (r != SX_OK) return r;
-    hipError_t e = hipMemcpyAsync(counts_dev, s->d_counts, (size_t)s->n_tags * sizeof(uint32_t),
-                                  hipMemcpyDeviceToDevice, st);
-    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "counts copy");
+    return tag_records(ctx, s, tolerance, output_mode, counts_dev, nullptr, stream);
 }
 
 int sx_debug_offsets(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint64_t* offsets_dev,
                      void* stream) {
     if (!ctx || !s || !offsets_dev) return SX_EINVAL;
-    sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
-    hipStream_t st = (hipStream_t)stream;
-    if (s->n_tags == 0) {
-        hipError_t e = hipMemsetAsync(offsets_dev, 0, sizeof(uint64_t), st);
-        return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
-    }
-    cfg.K = ctx->tune.chunk_k;
-    int r = run_counts(ctx, s, cfg, st);
-    if (r != SX_OK) return r;
-    hipError_t e = hipMemcpyAsync(offsets_dev, s->d_offsets, ((size_t)s->n_tags + 1) * sizeof(uint64_t),
-                                  hipMemcpyDeviceToDevice, st);
-    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "offsets copy");
+    return tag_records(ctx, s, tolerance, output_mode, nullptr, offsets_dev, stream);
 }
 
 int sx_scan_u32(sx_ctx* ctx, const uint32_t* in_dev, uint64_t* out_dev, uint32_t n, void* stream) {

@@ -415,14 +415,15 @@ enum { kOutLine1 = 0, kOutLine2 = 1, kOutLine3 = 2, kOutRound = 3 };
 enum { kInNone = 0, kInPivot = 1, kInSmooth = 2 };
 
 struct __align__(16) Item {
-    uint32_t hdr;    // kind | flags | outer kind << 16 | inner kind << 20
-    uint32_t tag;    // tag index
-    uint32_t local;  // record offset of this chunk within the tag
-    uint32_t n;      // records in this chunk
+    uint32_t hdr;    // kind | flags | outer kind << 16 | inner kind << 20 | records in this chunk << 24
+    uint32_t tag;    // tag index (for the path id)
+    uint32_t slot;   // slot index (canonical position of the piece or tail)
+    uint32_t local;  // record offset of this chunk within the slot
     uint32_t k0;     // first record of the chunk within the whole item
     uint32_t ntot;   // records of the whole item
     uint32_t u[26];  // payload (floats / doubles by kind)
 };
+SX_FN uint32_t item_n(uint32_t hdr) { return hdr >> 24; }
 static_assert(sizeof(Item) == 128, "item layout");
 
 // offset-item payload.  es: p0, (chord / Z(1)) or (p1 - p0) for a pivot,
@@ -490,8 +491,8 @@ template <class Alloc, bool Stats = false>
 struct ItemSink {
     Item* items;
     Alloc al;
-    uint32_t tag;
-    uint32_t n;  // records of the tag so far
+    uint32_t tag, slot;
+    uint32_t n;  // records of the slot so far
     uint32_t st[Stats ? kStN : 1];
     static constexpr bool kStats = Stats;
     template <class P>
@@ -506,7 +507,7 @@ struct ItemSink {
             for (uint32_t c = 0; c < nc; c++) {
                 Item* dst = items + base + c;
                 const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
-                *reinterpret_cast<uint4*>(dst) = make_uint4(hdr, tag, n + c * K, nchunk);
+                *reinterpret_cast<uint4*>(dst) = make_uint4(hdr | (nchunk << 24), tag, slot, n + c * K);
                 *reinterpret_cast<uint2*>(&dst->k0) = make_uint2(c * K, nrec);
                 *reinterpret_cast<P*>(dst->u) = p;
             }
@@ -846,7 +847,7 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
             uprev = offset_u(p, hdr, it.k0, n, w);
             prev = offset_point_f(es, p.fh, uprev);
         }
-        for (uint32_t r = 0; r < it.n; r++) {
+        for (uint32_t r = 0; r < item_n(it.hdr); r++) {
             uint32_t i = it.k0 + r + 1;
             float u;
             V2 P;
@@ -883,7 +884,7 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
         const bool ca = (hdr & kIfEndA) != 0, cb = (hdr & kIfEndB) != 0;
         V2 cache_a = v2(0.0f, 0.0f);
         uint32_t cache_i = 0xffffffffu;
-        for (uint32_t r = 0; r < it.n; r++) {
+        for (uint32_t r = 0; r < item_n(it.hdr); r++) {
             uint32_t k = it.k0 + r;
             if (k < 2u * ne) {
                 uint32_t s = k % ne;  // segment s of copy k / ne
@@ -911,7 +912,7 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
         const uint32_t no = outer_count(outer, p.n_outer), ni = inner_count(inner);
         const V2 from = v2(p.fromx, p.fromy), to = v2(p.tox, p.toy), A = v2(p.ax, p.ay), B = v2(p.bx, p.by);
         const V2 F = v2(p.fx, p.fy), Pp = v2(p.px, p.py), T = v2(p.tx, p.ty);
-        for (uint32_t r = 0; r < it.n; r++) {
+        for (uint32_t r = 0; r < item_n(it.hdr); r++) {
             uint32_t k = it.k0 + r;
             bool is_inner = inner_first ? (k < ni) : (k >= no);
             if (is_inner) {
@@ -1000,112 +1001,7 @@ SX_FN Tan sample_q(const Seg& s, double t) {
     return Tan{q, ql};
 }
 
-// Algorithm 2: adaptive bisection of the cubic into Euler spiral pieces with
-// the two-word stack (t0_u, dt), then the parallel curves of each piece.
-// A line is its own Euler spiral piece (k0 = k1 = 0, arc length equal to the
-// chord, tangent angle of the chord) and skips the fit.
-template <class Sink>
-SX_HD void process_segment(Sink& k, const Cfg& cfg, const Seg& s, bool line) {
-    uint32_t t0_u = 0;
-    double dt = 1.0;
-    D2 last_p = s.P0w;
-    Tan last_q = sample_q(s, 0.0);
-    D2 last_qtrue = s.D1;  // the true derivative sample at t0 (for the chord)
-    const double hw = s.w;
-    const double min_dt = 1.0 / (double)(1u << kMaxDepth);
-    for (;;) {
-        double t0 = (double)t0_u * dt;
-        if (t0 == 1.0) break;
-        double t1 = t0 + dt;
-        D2 next_p = cubic_world(s, t1);
-        Tan next_q = line ? last_q : sample_q(s, t1);
-        D2 chord;
-        double cl, th0 = 0.0, th1 = 0.0;
-        bool ok = true;
-        if (line) {
-            chord = s.D3;
-            cl = len(chord);
-        } else {
-            chord = cubic_chord(s, t0, dt, last_qtrue);
-            cl = len(chord);
-            th0 = atan2(cross(last_q.dir, chord), dot(last_q.dir, chord));
-            th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
-            double d0 = last_q.mag * dt / cl, d1 = next_q.mag * dt / cl;
-            double est = fit_estimate(th0, th1, d0, d1);
-            double err = cfg.paper_fit ? est * cl : est * (cl + kFitK * hw) * kFitS;
-            bool len_ok = cl > 0.0;
-            bool hodo_ok = true;
-            {
-                double ma = last_q.mag * dt, mc = next_q.mag * dt;
-                D2 a = unit(last_q.dir) * ma, c = unit(next_q.dir) * mc;
-                D2 b = chord - a - c;
-                // a middle vector that is zero up to rounding leaves only the turn from a to c (< pi)
-                if (ma > 0.0 && mc > 0.0 && len(b) > 1e-9 * (ma + mc))
-                    hodo_ok = (dot(a, b) * mc + dot(b, c) * ma) > 0.0;
-            }
-            ok = len_ok && hodo_ok && (err <= cfg.tau_fit);
-        }
-        bool forced = dt <= min_dt;
-        if constexpr (Sink::kStats) {
-            if (line) k.st[kStLines]++;
-            else k.st[kStTrials]++;
-        }
-        if (ok || forced) {
-            if constexpr (Sink::kStats) k.st[kStPieces]++;
-            bool pivot = !ok;
-            ES es;
-            es.pivot = pivot;
-            es.p0 = last_p;
-            es.p1 = next_p;
-            es.n0 = rnormal(unit(last_q.dir));
-            es.n1 = rnormal(unit(next_q.dir));
-            double c, base;
-            D2 rot = d2(0.0, 0.0);
-            if (line) {
-                es.k0 = 0.0;
-                es.k1 = 0.0;
-                c = 1.0;
-                rot = chord;
-                base = atan2(rot.y, rot.x);
-            } else if (pivot) {
-                es.k0 = atan2(cross(last_q.dir, next_q.dir), dot(last_q.dir, next_q.dir));
-                es.k1 = 0.0;
-                c = es_chord(0.5 * es.k0, 0.5 * es.k0);
-                base = atan2(last_q.dir.y, last_q.dir.x) + 0.5 * es.k0;
-            } else {
-                es.k0 = th0 + th1;
-                es.k1 = es_k1(th0, th1);
-                c = es_chord(th0, th1);
-                D2 z1 = es_integral1(es.k0, es.k1);
-                double zz = z1.x * z1.x + z1.y * z1.y;
-                rot = d2((chord.x * z1.x + chord.y * z1.y) / zz, (chord.y * z1.x - chord.x * z1.y) / zz);
-                base = atan2(rot.y, rot.x);
-            }
-            if (!(c > kCMin)) c = kCMin;
-            es.L = cl / c;
-            es.fp0 = f32(es.p0);
-            es.fd = f32(es.p1 - es.p0);
-            es.frot = f32(rot);
-            es.fk0 = (float)es.k0;
-            es.fk1 = (float)es.k1;
-            es.fL = (float)es.L;
-            es.fbase = (float)base;
-            emit_sides(k, cfg, es, hw);
-            // pop: count trailing zeros
-            t0_u += 1;
-            uint32_t sh = __builtin_ctz(t0_u);
-            t0_u >>= sh;
-            dt *= (double)(1u << sh);
-            last_p = next_p;
-            last_q = next_q;
-            last_qtrue = (t1 == 1.0) ? s.D3 - s.D2_ : cubic_q(s, t1);
-        } else {
-            t0_u *= 2;
-            dt *= 0.5;
-        }
-    }
-}
-
+// ------------------------------------------------------ segment fetch
 // linear part of the transform applied to a difference vector (FP64 from FP32)
 SX_FN D2 xf_vec(const float* X, double dx, double dy) {
     return d2((double)X[0] * dx + (double)X[2] * dy, (double)X[1] * dx + (double)X[3] * dy);
@@ -1131,44 +1027,58 @@ struct SceneView {
     uint32_t n_tags, n_pts, n_styles, n_xforms, n_paths;
 };
 
-// Algorithm 1: the work of thread `i` (one tag).
-template <class Sink>
-SX_HD void process_tag(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i) {
+enum { kTagInvalid = 0, kTagSegment = 1, kTagMarker = 2 };
+
+// What one tag's work needs besides the segment geometry.
+struct TagInfo {
+    uint32_t kind, tag, off;
+    const float* X;  // transform
+    double w;        // half-width in output units
+    float miter;
+    int join, scap, ecap;
+    bool line;
+};
+
+// Segment fetch and degree elevation (Section 8.1) of tag i; bounds derived
+// from the monoids are checked (a consistent scan never trips them).
+SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s) {
     const uint32_t n = sv.n_tags;
-    uint32_t tag = sv.tags[i];
-    uint32_t off = sv.mon[i];
-    uint32_t sty = sv.mon[2 * (size_t)n + i];
-    uint32_t xfi = sv.mon[3 * (size_t)n + i];
-    // defensive bounds (a consistent scan never trips them)
+    ti.kind = kTagInvalid;
+    ti.line = false;
+    const uint32_t tag = sv.tags[i];
+    const uint32_t off = sv.mon[i];
+    const uint32_t sty = sv.mon[2 * (size_t)n + i];
+    const uint32_t xfi = sv.mon[3 * (size_t)n + i];
     const uint32_t need = (tag & kTagEnd) ? 3u : (tag & kTagCount) + 1u;
     if (sty >= sv.n_styles || xfi >= sv.n_xforms || (size_t)off + need > sv.n_pts) return;
     if (!(tag & kTagEnd)) {
         if (i + 1 >= n) return;
-        uint32_t t1 = sv.tags[i + 1];
-        uint32_t need1 = (t1 & kTagEnd) ? 3u : (t1 & kTagCount) + 1u;
+        const uint32_t t1 = sv.tags[i + 1];
+        const uint32_t need1 = (t1 & kTagEnd) ? 3u : (t1 & kTagCount) + 1u;
         if ((size_t)sv.mon[i + 1] + need1 > sv.n_pts) return;
     }
-    StyleD st = sv.styles[sty];
+    const StyleD st = sv.styles[sty];
     const float* X = sv.xforms + 6 * (size_t)xfi;
-    double scale = sqrt(fabs((double)X[0] * X[3] - (double)X[1] * X[2]));
-    double w = (double)st.half_width * scale;
-    int join = st.packed & 0xff, scap = (st.packed >> 8) & 0xff, ecap = (st.packed >> 16) & 0xff;
-    const float2* D = sv.pts + off;
+    const double scale = sqrt(fabs((double)X[0] * X[3] - (double)X[1] * X[2]));
+    ti.tag = tag;
+    ti.off = off;
+    ti.X = X;
+    ti.w = (double)st.half_width * scale;
+    ti.miter = st.miter_limit;
+    ti.join = st.packed & 0xff;
+    ti.scap = (st.packed >> 8) & 0xff;
+    ti.ecap = (st.packed >> 16) & 0xff;
     if (tag & kTagEnd) {
-        if (!(tag & kTagClosed)) {
-            float2 a = D[1], b = D[2];
-            D2 ps = xf_apply(X, a.x, a.y);
-            D2 dir = xf_vec(X, (double)b.x - a.x, (double)b.y - a.y);
-            if (is_zero(dir)) dir = d2(1.0, 0.0);
-            emit_cap(k, cfg, scap, ps, unit(dir), w, true);
-        }
+        ti.kind = kTagMarker;
         return;
     }
-    int c = tag & kTagCount;
+    ti.kind = kTagSegment;
+    const float2* D = sv.pts + off;
+    const int c = tag & kTagCount;
+    ti.line = c == 1;
     float2 r[4];
     for (int j = 0; j <= c; j++) r[j] = D[j];
-    Seg s;
-    s.w = w;
+    s.w = ti.w;
     s.P0w = xf_apply(X, r[0].x, r[0].y);
     s.P3w = xf_apply(X, r[c].x, r[c].y);
     D2 e[3];  // transformed differences r_j - r_0
@@ -1194,32 +1104,195 @@ SX_HD void process_tag(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i)
     s.ts = first_nonzero(e, c);
     s.te = first_nonzero(ce, c);
     s.lpoly = len(s.D1) + len(s.D2_ - s.D1) + len(s.D3 - s.D2_);
-    process_segment(k, cfg, s, c == 1);
+}
 
-    // join with tag i + 1 or end cap (Algorithm 1)
-    uint32_t nt = sv.tags[i + 1];
-    D2 pend = s.P3w;
-    if ((nt & kTagEnd) && !(nt & kTagClosed)) {
-        emit_cap(k, cfg, ecap, pend, unit(s.te), w, false);
+// ------------------------------------------- Algorithm 2: the bisection
+// One candidate piece [t0, t0 + dt] of the segment: its chord, end angles and
+// the accept test (Section 7.1 estimate with reading G2, the hodograph test
+// of reading G29; a line is its own piece and skips the test).
+struct Trial {
+    D2 chord;
+    double cl, th0, th1;
+    bool ok;
+};
+SX_HD inline Trial trial(const Seg& s, const Cfg& cfg, bool line, double dt, const Tan& last_q, const Tan& next_q,
+                         D2 chord) {
+    Trial r;
+    r.chord = chord;
+    r.cl = len(chord);
+    r.th0 = 0.0;
+    r.th1 = 0.0;
+    r.ok = true;
+    if (line) return r;
+    r.th0 = atan2(cross(last_q.dir, chord), dot(last_q.dir, chord));
+    r.th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
+    const double d0 = last_q.mag * dt / r.cl, d1 = next_q.mag * dt / r.cl;
+    const double est = fit_estimate(r.th0, r.th1, d0, d1);
+    const double err = cfg.paper_fit ? est * r.cl : est * (r.cl + kFitK * s.w) * kFitS;
+    const bool len_ok = r.cl > 0.0;
+    bool hodo_ok = true;
+    {
+        const double ma = last_q.mag * dt, mc = next_q.mag * dt;
+        const D2 a = unit(last_q.dir) * ma, c = unit(next_q.dir) * mc;
+        const D2 b = chord - a - c;
+        // a middle vector that is zero up to rounding leaves only the turn from a to c (< pi)
+        if (ma > 0.0 && mc > 0.0 && len(b) > 1e-9 * (ma + mc)) hodo_ok = (dot(a, b) * mc + dot(b, c) * ma) > 0.0;
+    }
+    r.ok = len_ok && hodo_ok && (err <= cfg.tau_fit);
+    return r;
+}
+
+// The bisection state of one segment: the two-word stack (t0_u, depth with
+// dt = 2^-depth) and the samples at t0.
+struct Bisect {
+    uint32_t t0_u, depth;
+    Tan last_q;
+    D2 last_qtrue;
+};
+SX_FN void bisect_init(Bisect& b, const Seg& s) {
+    b.t0_u = 0;
+    b.depth = 0;
+    b.last_q = sample_q(s, 0.0);
+    b.last_qtrue = s.D1;
+}
+SX_FN double depth_dt(uint32_t depth) { return 1.0 / (double)(1u << depth); }
+
+// One trial of the bisection.  Returns true when [t0, t0 + dt] is accepted
+// (its t0_u and depth are reported before the stack pops); *done is set when
+// the segment is fully covered.
+SX_HD inline bool bisect_step(Bisect& b, const Seg& s, const Cfg& cfg, bool line, uint32_t& acc_t0u,
+                              uint32_t& acc_depth, bool& done) {
+    const double dt = depth_dt(b.depth);
+    const double t0 = (double)b.t0_u * dt;
+    const double t1 = t0 + dt;
+    const Tan next_q = line ? b.last_q : sample_q(s, t1);
+    const D2 chord = line ? s.D3 : cubic_chord(s, t0, dt, b.last_qtrue);
+    const Trial tr = trial(s, cfg, line, dt, b.last_q, next_q, chord);
+    const bool forced = b.depth >= (uint32_t)kMaxDepth;
+    done = false;
+    if (tr.ok || forced) {
+        acc_t0u = b.t0_u;
+        acc_depth = b.depth;
+        // pop: count trailing zeros
+        b.t0_u += 1;
+        const uint32_t sh = __builtin_ctz(b.t0_u);
+        b.t0_u >>= sh;
+        b.depth -= sh;
+        b.last_q = next_q;
+        b.last_qtrue = (t1 == 1.0) ? s.D3 - s.D2_ : cubic_q(s, t1);
+        done = (double)b.t0_u * depth_dt(b.depth) == 1.0;
+        return true;
+    }
+    b.t0_u *= 2;
+    b.depth += 1;
+    return false;
+}
+
+// The accepted piece [t0, t0 + 2^-depth] of the segment: the trial again
+// (the same arithmetic as in the bisection, so the same decision), its Euler
+// spiral (Appendix A; a pivot for reading G28) and both parallel-curve sides.
+template <class Sink>
+SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth) {
+    const double dt = depth_dt(depth);
+    const double t0 = (double)t0_u * dt;
+    const double t1 = t0 + dt;
+    const Tan last_q = sample_q(s, t0);
+    const D2 last_qtrue = (t0 == 0.0) ? s.D1 : cubic_q(s, t0);
+    const Tan next_q = line ? last_q : sample_q(s, t1);
+    const D2 chord = line ? s.D3 : cubic_chord(s, t0, dt, last_qtrue);
+    const Trial tr = trial(s, cfg, line, dt, last_q, next_q, chord);
+    const bool pivot = !tr.ok;
+    if constexpr (Sink::kStats) k.st[kStPieces]++;
+    ES es;
+    es.pivot = pivot;
+    es.p0 = cubic_world(s, t0);
+    es.p1 = cubic_world(s, t1);
+    es.n0 = rnormal(unit(last_q.dir));
+    es.n1 = rnormal(unit(next_q.dir));
+    double c, base;
+    D2 rot = d2(0.0, 0.0);
+    if (line) {
+        es.k0 = 0.0;
+        es.k1 = 0.0;
+        c = 1.0;
+        rot = chord;
+        base = atan2(rot.y, rot.x);
+    } else if (pivot) {
+        es.k0 = atan2(cross(last_q.dir, next_q.dir), dot(last_q.dir, next_q.dir));
+        es.k1 = 0.0;
+        c = es_chord(0.5 * es.k0, 0.5 * es.k0);
+        base = atan2(last_q.dir.y, last_q.dir.x) + 0.5 * es.k0;
+    } else {
+        es.k0 = tr.th0 + tr.th1;
+        es.k1 = es_k1(tr.th0, tr.th1);
+        c = es_chord(tr.th0, tr.th1);
+        const D2 z1 = es_integral1(es.k0, es.k1);
+        const double zz = z1.x * z1.x + z1.y * z1.y;
+        rot = d2((chord.x * z1.x + chord.y * z1.y) / zz, (chord.y * z1.x - chord.x * z1.y) / zz);
+        base = atan2(rot.y, rot.x);
+    }
+    if (!(c > kCMin)) c = kCMin;
+    es.L = tr.cl / c;
+    es.fp0 = f32(es.p0);
+    es.fd = f32(es.p1 - es.p0);
+    es.frot = f32(rot);
+    es.fk0 = (float)es.k0;
+    es.fk1 = (float)es.k1;
+    es.fL = (float)es.L;
+    es.fbase = (float)base;
+    emit_sides(k, cfg, es, s.w);
+}
+
+// The tail of tag i: the start cap of an open subpath (stroke cap marker),
+// or the join with tag i + 1 / the end cap of a segment (Algorithm 1).
+template <class Sink>
+SX_HD void emit_tail(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i, const TagInfo& ti, const Seg& s) {
+    if (ti.kind == kTagMarker) {
+        if (!(ti.tag & kTagClosed)) {
+            const float2* D = sv.pts + ti.off;
+            const float2 a = D[1], bb = D[2];
+            const D2 ps = xf_apply(ti.X, a.x, a.y);
+            D2 dir = xf_vec(ti.X, (double)bb.x - a.x, (double)bb.y - a.y);
+            if (is_zero(dir)) dir = d2(1.0, 0.0);
+            emit_cap(k, cfg, ti.scap, ps, unit(dir), ti.w, true);
+        }
         return;
     }
+    if (ti.kind != kTagSegment) return;
+    const uint32_t nt = sv.tags[i + 1];
+    const D2 pend = s.P3w;
+    if ((nt & kTagEnd) && !(nt & kTagClosed)) {
+        emit_cap(k, cfg, ti.ecap, pend, unit(s.te), ti.w, false);
+        return;
+    }
+    const float* X = ti.X;
     const float2* Dn = sv.pts + sv.mon[i + 1];
     D2 tb;
     if (nt & kTagEnd) {
-        float2 a = Dn[1], b = Dn[2];
-        tb = xf_vec(X, (double)b.x - a.x, (double)b.y - a.y);
+        const float2 a = Dn[1], bb = Dn[2];
+        tb = xf_vec(X, (double)bb.x - a.x, (double)bb.y - a.y);
         if (is_zero(tb)) tb = d2(1.0, 0.0);
     } else {
-        int cn = nt & kTagCount;
-        float2 r0 = Dn[0];
+        const int cn = nt & kTagCount;
+        const float2 r0 = Dn[0];
         D2 cands[3];
         for (int j = 0; j < cn; j++) {
-            float2 q = Dn[j + 1];
+            const float2 q = Dn[j + 1];
             cands[j] = xf_vec(X, (double)q.x - r0.x, (double)q.y - r0.y);
         }
         tb = first_nonzero(cands, cn);
     }
-    emit_join(k, cfg, join, (double)st.miter_limit, pend, s.te, tb, w);
+    emit_join(k, cfg, ti.join, (double)ti.miter, pend, s.te, tb, ti.w);
 }
+
+// ------------------------------------------------------------ slots
+// Every tag owns (pieces + 1) consecutive *slots* in canonical order: one
+// per accepted piece in t order, then its tail (join / cap).  A slot code is
+// (t0_u << 5) | depth for a piece, kSlotTail for the tail.
+constexpr uint32_t kSlotTail = 0xffffffffu;
+struct Slot {
+    uint32_t tag, code;
+};
+SX_FN uint32_t slot_code(uint32_t t0_u, uint32_t depth) { return (t0_u << 5) | depth; }
 
 }  // namespace sx

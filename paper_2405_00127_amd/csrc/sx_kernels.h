@@ -7,19 +7,20 @@
 
 namespace sx {
 
-// Item workspace of the piece / record kernels: one region of region_cap
-// slots per piece tile, then ovf_cap shared overflow slots at ovf_base.
+// Item workspace of the slot / record kernels: one region of region_cap
+// items per slot tile, then ovf_cap shared overflow items at ovf_base.
 struct WsCtl {
-    unsigned long long ovf_n;        // overflow slots requested
+    unsigned long long ovf_n;        // overflow items requested
     unsigned long long items_total;  // items requested by all tiles
-    unsigned long long result[2];    // records and items needed, for synchronous readback
+    unsigned long long slots_total;  // slots of the last expansion
+    unsigned long long result[2];    // records and status, for synchronous readback
 };
 struct ItemWs {
     Item* items;
-    uint32_t* tile_n;  // per piece tile: slots requested (clamp to region_cap)
+    uint32_t* tile_n;  // per slot tile: items requested (clamp to region_cap)
     WsCtl* ctl;
-    uint32_t tile;        // tags per piece tile (the piece kernel's block size: 64 or 256)
-    uint32_t region_cap;  // slots per tile
+    uint32_t tile;        // slots per tile
+    uint32_t region_cap;  // items per tile
     uint64_t ovf_base, ovf_cap;
 };
 
@@ -37,22 +38,31 @@ struct GatherDesc {
 
 int scan_tiles(uint32_t n);
 uint32_t piece_tiles(uint32_t n, uint32_t tile);
+uint32_t slot_tiles(uint64_t n_slots);
+uint32_t slot_block();
 size_t scan_status_bytes(uint32_t n);
 size_t scan_ctl_bytes();
 
 hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
                             hipStream_t s);
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s);
-hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, int waves,
+hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
+                                  void* st, hipStream_t s);
+hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
+                         const uint64_t* base, Slot* slots, uint64_t slot_cap, unsigned long long* stats,
                          hipStream_t s);
-hipError_t launch_piece_stats(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts,
-                              unsigned long long* stats, hipStream_t s);
-hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
-                          uint64_t cap, hipStream_t s);
+hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
+                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
+                        unsigned long long* stats, hipStream_t s);
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,
+                          const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s);
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
                          float* xforms, uint32_t* path_map, hipStream_t s);
-hipError_t launch_scene_offsets(const uint64_t* offsets, const GatherDesc* descs, uint32_t n_scenes, uint32_t n_tags,
-                                uint64_t* scene_offsets, hipStream_t s);
-hipError_t launch_finish(const uint64_t* offsets, uint32_t n, const ItemWs& ws, uint64_t* dst, hipStream_t s);
+hipError_t launch_scene_offsets(const uint64_t* base, const uint64_t* roff, uint64_t slot_cap, const GatherDesc* descs,
+                                uint32_t n_scenes, uint32_t n_tags, uint64_t* scene_offsets, hipStream_t s);
+hipError_t launch_finish(const uint64_t* roff, const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t n_tags,
+                         const ItemWs& ws, uint64_t* dst, hipStream_t s);
+hipError_t launch_tag_records(const uint64_t* base, const uint64_t* roff, uint64_t slot_cap, uint32_t n_tags,
+                              uint32_t* counts, uint64_t* offs, hipStream_t s);
 
 }  // namespace sx

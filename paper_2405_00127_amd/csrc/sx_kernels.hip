@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "sx_device.h"
 #include "sx_kernels.h"
 
@@ -165,6 +167,18 @@ __device__ __forceinline__ Pair tag_inc(uint32_t t) {
     return Pair{pts | (pth << 32), sty | (xf << 32)};
 }
 
+// The last block of a launch resets the ticket and done counters and bumps
+// the epoch, so the next launch starts clean without any memset.
+__device__ __forceinline__ void finish_scan(ScanCtl* ctl, uint32_t epoch_read) {
+    __threadfence();
+    if (atomicAdd(&ctl->done, 1u) == gridDim.x - 1) {
+        ctl->ticket = 0;
+        ctl->done = 0;
+        __threadfence();
+        __hip_atomic_store(&ctl->epoch, (epoch_read + 1u) & 0x3fffffffu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 template <class Load, class Store>
 __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, TileStatus* st) {
     __shared__ uint32_t s_tile, s_epoch;
@@ -177,6 +191,12 @@ __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, Tile
     }
     __syncthreads();
     const uint32_t tile = s_tile, epoch = s_epoch & 0x3fffffffu;
+    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    if (tile >= ntiles) {
+        // a grid sized for a capacity larger than this launch's n: nothing to scan
+        if (tid == 0) finish_scan(ctl, s_epoch);
+        return;
+    }
     const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)tid * kScanItems;
     Pair item[kScanItems];
     load(base, item);
@@ -213,17 +233,7 @@ __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, Tile
     Pair pre = s_excl + texcl;
     store(base, item, pre);
     __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
-        if (atomicAdd(&ctl->done, 1u) == ntiles - 1) {
-            ctl->ticket = 0;
-            ctl->done = 0;
-            __threadfence();
-            __hip_atomic_store(&ctl->epoch, (s_epoch + 1u) & 0x3fffffffu, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    if (tid == 0) finish_scan(ctl, s_epoch);
 }
 
 __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __restrict__ tags, uint32_t n,
@@ -286,9 +296,25 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
 }
 
 // exclusive scan of u32 counts into u64 offsets; out[n] = total
+__device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
+                                              ScanCtl* ctl, TileStatus* st);
 __global__ __launch_bounds__(kScanBlock) void scan_counts_kernel(const uint32_t* __restrict__ in, uint32_t n,
                                                                  uint64_t* __restrict__ out, ScanCtl* ctl,
                                                                  TileStatus* st) {
+    scan_u32_body(in, n, out, ctl, st);
+}
+// the same with n read from device memory (clamped to the buffers' capacity);
+// the grid covers the capacity
+__global__ __launch_bounds__(kScanBlock) void scan_counts_dev_kernel(const uint32_t* __restrict__ in,
+                                                                     const uint64_t* __restrict__ n_dev, uint32_t cap,
+                                                                     uint64_t* __restrict__ out, ScanCtl* ctl,
+                                                                     TileStatus* st) {
+    const uint64_t nd = *n_dev;
+    if (nd == 0 && blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
+    scan_u32_body(in, nd < cap ? (uint32_t)nd : cap, out, ctl, st);
+}
+__device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
+                                              ScanCtl* ctl, TileStatus* st) {
     auto load = [&](uint64_t base, Pair* item) {
         if (base + kScanItems <= n) {
 #pragma unroll
@@ -315,12 +341,97 @@ __global__ __launch_bounds__(kScanBlock) void scan_counts_kernel(const uint32_t*
     scan_tile(load, store, n, ctl, st);
 }
 
-// ------------------------------------------------------ pieces / records
-constexpr int kTagBlock = 256;
-constexpr int kRecBlock = 256;
-constexpr int kOvfBlocks = 512;  // record-kernel blocks striding over the overflow slots
+// --------------------------------------------------------- bisection
+// One wave per workgroup owns `range` consecutive tags.  Every lane runs the
+// bisection of one segment at a time (Algorithm 2, one trial per loop turn);
+// a lane whose segment is done takes the wave's next tag (lane refill), so
+// the wave is busy until its range is exhausted instead of waiting for its
+// longest segment.  The count pass writes, per tag, its slot count (accepted
+// pieces + 1 tail); the write pass, after the scan of those counts, writes
+// each piece's slot at its canonical position.
+constexpr int kBisectBlock = 64;
 
-// Slot allocator of one piece-kernel tile: the tile's own region first (LDS
+template <bool Write, bool Stats, int MinWaves>
+__global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
+    SceneView sv, Cfg cfg, uint32_t range, uint32_t* __restrict__ nslots, const uint64_t* __restrict__ base,
+    Slot* __restrict__ slots, uint64_t slot_cap, unsigned long long* __restrict__ stats) {
+    const uint32_t lane = threadIdx.x;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const uint32_t a = blockIdx.x * range;
+    const uint32_t b = min(sv.n_tags, a + range);
+    uint32_t cursor = a;  // next unassigned tag (wave-uniform)
+    bool busy = false;
+    uint32_t i = 0, seq = 0;
+    uint64_t bi = 0;  // slot base of the lane's tag (write pass)
+    TagInfo ti;
+    Seg s;
+    Bisect bs;
+    uint32_t n_trials = 0, n_lines = 0;
+    for (;;) {
+        // refill idle lanes with the next tags of the range
+        const uint64_t idle = __ballot(!busy);
+        if (idle && cursor < b) {
+            const uint32_t ni = cursor + (uint32_t)__popcll(idle & below);
+            cursor += (uint32_t)__popcll(idle);
+            if (!busy && ni < b) {
+                i = ni;
+                seq = 0;
+                if (Write) bi = base[i];
+                fetch_tag(sv, i, ti, s);
+                if (ti.kind == kTagSegment) {
+                    bisect_init(bs, s);
+                    busy = true;
+                } else {
+                    // markers and invalid tags own only their tail slot
+                    if (Write) {
+                        if (bi < slot_cap) slots[bi] = Slot{i, kSlotTail};
+                    } else {
+                        nslots[i] = 1u;
+                    }
+                }
+            }
+            continue;  // refill again until no idle lane can take a tag
+        }
+        if (__ballot(busy) == 0ull) break;
+        if (busy) {
+            uint32_t t0u = 0, depth = 0;
+            bool done = false;
+            if (Stats) {
+                if (ti.line) n_lines++;
+                else n_trials++;
+            }
+            if (bisect_step(bs, s, cfg, ti.line, t0u, depth, done)) {
+                if (Write) {
+                    const uint64_t at = bi + seq;
+                    if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth)};
+                }
+                seq++;
+                if (done) {
+                    if (Write) {
+                        const uint64_t at = bi + seq;
+                        if (at < slot_cap) slots[at] = Slot{i, kSlotTail};
+                    } else {
+                        nslots[i] = seq + 1u;
+                    }
+                    busy = false;
+                }
+            }
+        }
+    }
+    if (Stats) {
+        atomicAdd(&stats[kStTrials], (unsigned long long)n_trials);
+        atomicAdd(&stats[kStLines], (unsigned long long)n_lines);
+    }
+}
+
+// ------------------------------------------------------------- slots
+constexpr int kSlotBlock = 256;   // slots per workgroup and per workspace tile
+constexpr int kSlotGrid = 8192;   // persistent grid of the slot kernel (tiles stride by it)
+constexpr int kRecBlock = 256;
+constexpr int kRecGrid = 8192;    // persistent grid of the record kernel
+constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the overflow slots
+
+// Slot allocator of one slot tile: the tile's own region first (LDS
 // counter), then the shared overflow region (global counter).
 struct TileAlloc {
     Item* items;
@@ -340,99 +451,87 @@ struct TileAlloc {
     }
 };
 
-// Work class of a tag for the in-block ordering: cubics (longest bisection),
-// quadratics, then lines and stroke cap markers (no bisection).
-__device__ __forceinline__ uint32_t work_class(uint32_t tag) {
-    if (tag & kTagEnd) return 2u;
-    const uint32_t c = tag & kTagCount;
-    return c == 3u ? 0u : (c == 2u ? 1u : 2u);
+// Work class of a slot for the in-tile ordering: curve pieces, line
+// pieces, tails (joins and caps).
+__device__ __forceinline__ uint32_t slot_class(const SceneView& sv, Slot sl) {
+    if (sl.code == kSlotTail) return 2u;
+    return (sl.tag < sv.n_tags && (sv.tags[sl.tag] & kTagCount) == 1u) ? 1u : 0u;
 }
 
-// MinWaves: waves per SIMD the register allocation must allow (1, 2 or 3):
-// more waves hide more latency, at the price of spills to scratch.
-// Block: tags per workgroup and per workspace tile (64 or 256).  With one
-// wave per block a SIMD takes new work as soon as its own wave finishes;
-// with several, the block first orders its tags by work class (a stable
-// counting sort in LDS) so that each wave runs tags of one kind: a wave of
-// lines no longer waits for one lane's cubic bisection.
-template <int MinWaves, int Block>
-__global__ __launch_bounds__(Block, MinWaves) void piece_kernel(SceneView sv, Cfg cfg, ItemWs ws,
-                                                                uint32_t* __restrict__ counts) {
+// One thread per slot: the piece's Euler spiral and parallel curves, or the
+// tag's join / cap, as emission items (records relative to the slot) and
+// the slot's record count.  Tiles of kSlotBlock slots are ordered by work
+// class first, so a wave runs slots of one kind.
+template <int MinWaves, bool Stats>
+__global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
+                                                                    const Slot* __restrict__ slots,
+                                                                    const uint64_t* __restrict__ n_slots_dev,
+                                                                    uint64_t slot_cap, uint32_t* __restrict__ rc,
+                                                                    unsigned long long* __restrict__ stats) {
     __shared__ uint32_t s_n;
-    __shared__ uint32_t s_order[Block];
-    __shared__ uint32_t s_hist[Block / 64][3];
-    const uint32_t t = threadIdx.x;
-    const uint32_t first = blockIdx.x * Block;
-    if (t == 0) s_n = 0;
-    uint32_t i = first + t;
-    if constexpr (Block > 64) {
-        const uint32_t lane = t & 63u, wv = t >> 6;
-        const uint32_t cls = i < sv.n_tags ? work_class(sv.tags[i]) : 2u;
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        uint64_t m[3];
+    __shared__ uint32_t s_order[kSlotBlock];
+    __shared__ uint32_t s_hist[kSlotBlock / 64][3];
+    const uint64_t n_slots = *n_slots_dev;
+    if (n_slots > slot_cap) return;  // reported by the finish kernel
+    const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t first = (uint64_t)tile * kSlotBlock;
+        if (t == 0) s_n = 0;
+        const uint64_t j0 = first + t;
+        const Slot mine = j0 < n_slots ? slots[j0] : Slot{0u, kSlotTail};
+        const uint32_t cls = j0 < n_slots ? slot_class(sv, mine) : 2u;
         uint32_t rank = 0;
 #pragma unroll
         for (uint32_t c = 0; c < 3; c++) {
-            m[c] = __ballot(cls == c);
-            if (cls == c) rank = (uint32_t)__popcll(m[c] & below);
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (uint32_t c = 0; c < 3; c++) s_hist[wv][c] = (uint32_t)__popcll(m[c]);
+            const uint64_t m = __ballot(cls == c);
+            if (cls == c) rank = (uint32_t)__popcll(m & below);
+            if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
         }
         __syncthreads();
-        // destination = tags of lower classes + same class in earlier waves + rank
         uint32_t pos = rank;
         for (uint32_t c = 0; c < 3; c++)
-            for (uint32_t w = 0; w < Block / 64; w++)
+            for (uint32_t w = 0; w < kSlotBlock / 64; w++)
                 if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
         s_order[pos] = t;
         __syncthreads();
-        i = first + s_order[t];
-    } else {
+        const uint64_t j = first + s_order[t];
+        if (j < n_slots) {
+            const Slot sl = slots[j];
+            TileAlloc al{ws.items, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
+                         ws.ovf_cap};
+            ItemSink<TileAlloc, Stats> k;
+            k.items = ws.items;
+            k.al = al;
+            k.tag = sl.tag;
+            k.slot = (uint32_t)j;
+            k.n = 0;
+            if (Stats)
+                for (int q = 0; q < kStN; q++) k.st[q] = 0;
+            if (sl.tag < sv.n_tags) {
+                TagInfo ti;
+                Seg sg;
+                fetch_tag(sv, sl.tag, ti, sg);
+                if (sl.code == kSlotTail) emit_tail(k, cfg, sv, sl.tag, ti, sg);
+                else if (ti.kind == kTagSegment) emit_piece(k, cfg, sg, ti.line, sl.code >> 5, sl.code & 31u);
+            }
+            rc[j] = k.n;
+            if (Stats)
+                for (int q = 0; q < kStN; q++) st[q] += k.st[q];
+        }
+        __syncthreads();
+        if (t == 0) {
+            ws.tile_n[tile] = s_n;
+            atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
+        }
         __syncthreads();
     }
-    if (i < sv.n_tags) {
-        TileAlloc al{ws.items, &s_n, (uint64_t)blockIdx.x * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
-                     ws.ovf_base, ws.ovf_cap};
-        ItemSink<TileAlloc> k{ws.items, al, i, 0};
-        process_tag(k, cfg, sv, i);
-        counts[i] = k.n;
+    if (Stats) {
+        for (int q = kStPieces; q <= kStJoins; q++)
+            if (st[q]) atomicAdd(&stats[q], (unsigned long long)st[q]);
     }
-    __syncthreads();
-    if (t == 0) {
-        ws.tile_n[blockIdx.x] = s_n;
-        atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
-    }
-}
-
-// The piece kernel with work counters (one configuration; not timed):
-// stats[j] += per-tag counts j (fit trials, pieces, ranges, evolutes,
-// joins and caps, lines).  Items and counts are written as by piece_kernel.
-__global__ __launch_bounds__(kTagBlock) void piece_stats_kernel(SceneView sv, Cfg cfg, ItemWs ws,
-                                                                uint32_t* __restrict__ counts,
-                                                                unsigned long long* __restrict__ stats) {
-    __shared__ uint32_t s_n;
-    __shared__ unsigned long long s_st[kStN];
-    if (threadIdx.x == 0) s_n = 0;
-    if (threadIdx.x < kStN) s_st[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t i = blockIdx.x * kTagBlock + threadIdx.x;
-    if (i < sv.n_tags) {
-        TileAlloc al{ws.items, &s_n, (uint64_t)blockIdx.x * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
-                     ws.ovf_base, ws.ovf_cap};
-        ItemSink<TileAlloc, true> k{ws.items, al, i, 0, {0, 0, 0, 0, 0, 0}};
-        process_tag(k, cfg, sv, i);
-        counts[i] = k.n;
-        for (int j = 0; j < kStN; j++)
-            if (k.st[j]) atomicAdd(&s_st[j], (unsigned long long)k.st[j]);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ws.tile_n[blockIdx.x] = s_n;
-        atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
-    }
-    if (threadIdx.x < kStN) atomicAdd(&stats[threadIdx.x], s_st[threadIdx.x]);
 }
 
 // Record-kernel item classes: offset ranges placed by the density inverse,
@@ -444,70 +543,98 @@ __device__ __forceinline__ uint32_t item_class(uint32_t hdr) {
     return kind == kItemEvolute ? 2u : 3u;
 }
 
-__device__ __forceinline__ void record_item(const SceneView& sv, const Item* slot, const uint64_t* offsets,
-                                            float* out, uint64_t cap, int arcs) {
+__device__ __forceinline__ void record_item(const SceneView& sv, const Item* slot, const uint64_t* roff,
+                                            uint64_t n_slots, float* out, uint64_t cap, int arcs) {
     Item it;
     load_item(it, slot);
-    if ((it.hdr & 15u) == 0u || it.tag >= sv.n_tags) return;
+    if ((it.hdr & 15u) == 0u || it.slot >= n_slots || it.tag >= sv.n_tags) return;
     const uint32_t pi = sv.mon[(size_t)sv.n_tags + it.tag];
     const uint32_t path = pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
-    const uint64_t end = offsets[it.tag + 1] < cap ? offsets[it.tag + 1] : cap;
-    RecOut o{out, offsets[it.tag] + it.local, end, path, arcs};
+    const uint64_t end = roff[it.slot + 1] < cap ? roff[it.slot + 1] : cap;
+    RecOut o{out, roff[it.slot] + it.local, end, path, arcs};
     emit_item(it, o);
 }
 
+// Per item chunk, the FP32 per-point work: records at
+// roff[slot] + the chunk's position within its slot.
 __global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs ws, int arcs,
-                                                           const uint64_t* __restrict__ offsets,
-                                                           float* __restrict__ out, uint64_t cap_records,
-                                                           uint32_t n_tiles) {
-    // nothing is written when the records exceed the capacity or items were dropped
-    if (offsets[sv.n_tags] > cap_records || ws.ctl->ovf_n > ws.ovf_cap) return;
+                                                           const uint64_t* __restrict__ roff,
+                                                           const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
+                                                           float* __restrict__ out, uint64_t cap_records) {
+    const uint64_t n_slots = *n_slots_dev;
+    // nothing is written when the records exceed the capacity, or slots or items were dropped
+    if (n_slots > slot_cap || roff[n_slots] > cap_records || ws.ctl->ovf_n > ws.ovf_cap) return;
+    const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
     const uint32_t b = blockIdx.x;
-    if (b < n_tiles) {
+    if (b < kRecGrid) {
         // a tile's items, kRecBlock at a time, each round ordered by item
         // class so that a wave runs items of one kind
         __shared__ uint32_t s_order[kRecBlock];
         __shared__ uint32_t s_hist[kRecBlock / 64][kItemClasses];
         const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
-        const uint32_t cnt = ws.tile_n[b] < ws.region_cap ? ws.tile_n[b] : ws.region_cap;
-        const Item* base = ws.items + (uint64_t)b * ws.region_cap;
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-        for (uint32_t r0 = 0; r0 < cnt; r0 += kRecBlock) {
-            const uint32_t cls = (r0 + t < cnt) ? item_class(base[r0 + t].hdr) : kItemClasses - 1;
-            uint32_t rank = 0;
+        for (uint32_t tile = b; tile < n_tiles; tile += kRecGrid) {
+            const uint32_t cnt = ws.tile_n[tile] < ws.region_cap ? ws.tile_n[tile] : ws.region_cap;
+            const Item* base = ws.items + (uint64_t)tile * ws.region_cap;
+            for (uint32_t r0 = 0; r0 < cnt; r0 += kRecBlock) {
+                const uint32_t cls = (r0 + t < cnt) ? item_class(base[r0 + t].hdr) : kItemClasses - 1;
+                uint32_t rank = 0;
 #pragma unroll
-            for (uint32_t c = 0; c < kItemClasses; c++) {
-                const uint64_t m = __ballot(cls == c);
-                if (cls == c) rank = (uint32_t)__popcll(m & below);
-                if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
+                for (uint32_t c = 0; c < kItemClasses; c++) {
+                    const uint64_t m = __ballot(cls == c);
+                    if (cls == c) rank = (uint32_t)__popcll(m & below);
+                    if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
+                }
+                __syncthreads();
+                uint32_t pos = rank;
+                for (uint32_t c = 0; c < kItemClasses; c++)
+                    for (uint32_t w = 0; w < kRecBlock / 64; w++)
+                        if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
+                s_order[pos] = t;
+                __syncthreads();
+                const uint32_t s2 = r0 + s_order[t];
+                if (s2 < cnt) record_item(sv, base + s2, roff, n_slots, out, cap_records, arcs);
+                __syncthreads();
             }
-            __syncthreads();
-            uint32_t pos = rank;
-            for (uint32_t c = 0; c < kItemClasses; c++)
-                for (uint32_t w = 0; w < kRecBlock / 64; w++)
-                    if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
-            s_order[pos] = t;
-            __syncthreads();
-            const uint32_t s2 = r0 + s_order[t];
-            if (s2 < cnt) record_item(sv, base + s2, offsets, out, cap_records, arcs);
-            __syncthreads();
         }
     } else {
         const uint64_t cnt = ws.ctl->ovf_n;
         const Item* base = ws.items + ws.ovf_base;
-        for (uint64_t s = (uint64_t)(b - n_tiles) * kRecBlock + threadIdx.x; s < cnt; s += (uint64_t)kOvfBlocks * kRecBlock)
-            record_item(sv, base + s, offsets, out, cap_records, arcs);
+        for (uint64_t s = (uint64_t)(b - kRecGrid) * kRecBlock + threadIdx.x; s < cnt;
+             s += (uint64_t)kOvfBlocks * kRecBlock)
+            record_item(sv, base + s, roff, n_slots, out, cap_records, arcs);
     }
 }
 
-// out[0] = records, out[1] = 0, or the item count the workspace must hold
-// when items were dropped
-__global__ void finish_kernel(const uint64_t* __restrict__ offsets, uint32_t n, const ItemWs ws,
-                              uint64_t* __restrict__ dst) {
+// dst[0] = records, dst[1] = 0 when everything fit, else 1 (slots or items
+// were dropped: the workspace must grow); the counters stay in ws.ctl.
+__global__ void finish_kernel(const uint64_t* __restrict__ roff, const uint64_t* __restrict__ n_slots_dev,
+                              uint64_t slot_cap, uint32_t n_tags, const ItemWs ws, uint64_t* __restrict__ dst) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        dst[0] = n ? offsets[n] : 0ull;
-        dst[1] = (n && ws.ctl->ovf_n > ws.ovf_cap) ? ws.ctl->items_total : 0ull;
+        if (n_tags == 0) {
+            dst[0] = 0;
+            dst[1] = 0;
+            return;
+        }
+        const uint64_t ns = *n_slots_dev;
+        const bool slots_ok = ns <= slot_cap;
+        dst[0] = slots_ok ? roff[ns] : 0ull;
+        dst[1] = (!slots_ok || ws.ctl->ovf_n > ws.ovf_cap) ? 1ull : 0ull;
+        ws.ctl->slots_total = ns;
     }
+}
+
+// Per-tag record counts and offsets (verification exports):
+// offs[t] = roff[base[t]], counts[t] = offs[t + 1] - offs[t].
+__global__ void tag_records_kernel(const uint64_t* __restrict__ base, const uint64_t* __restrict__ roff,
+                                   uint64_t slot_cap, uint32_t n_tags, uint32_t* __restrict__ counts,
+                                   uint64_t* __restrict__ offs) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n_tags) return;
+    const bool fit = base[n_tags] <= slot_cap;  // else the slots were dropped: report zeros
+    const uint64_t o = fit ? roff[base[i]] : 0ull;
+    if (offs) offs[i] = o;
+    if (counts && i < n_tags) counts[i] = fit ? (uint32_t)(roff[base[i + 1]] - o) : 0u;
 }
 
 // ------------------------------------------------------------- batches
@@ -534,17 +661,23 @@ __global__ __launch_bounds__(kGatherBlock) void gather_kernel(const GatherDesc* 
 }
 
 // scene_offsets[s] = first record of scene s; scene_offsets[n] = total
-__global__ void scene_offsets_kernel(const uint64_t* __restrict__ offsets, const GatherDesc* __restrict__ descs,
-                                     uint32_t n_scenes, uint32_t n_tags, uint64_t* __restrict__ out) {
+// (slot base of the scene's first tag, then that slot's record offset)
+__global__ void scene_offsets_kernel(const uint64_t* __restrict__ base, const uint64_t* __restrict__ roff,
+                                     uint64_t slot_cap, const GatherDesc* __restrict__ descs, uint32_t n_scenes,
+                                     uint32_t n_tags, uint64_t* __restrict__ out) {
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n_scenes) out[s] = n_tags ? offsets[descs[s].tag_base] : 0ull;
-    if (s == n_scenes) out[s] = n_tags ? offsets[n_tags] : 0ull;
+    // zeros when empty or when the slots were dropped (the status word says so)
+    const bool fit = n_tags && base[n_tags] <= slot_cap;
+    if (s < n_scenes) out[s] = fit ? roff[base[descs[s].tag_base]] : 0ull;
+    if (s == n_scenes) out[s] = fit ? roff[base[n_tags]] : 0ull;
 }
 
 // ------------------------------------------------------------- launches
 int scan_tiles(uint32_t n) { return (int)((n + kScanTile - 1) / kScanTile); }
 
 uint32_t piece_tiles(uint32_t n, uint32_t tile) { return (n + tile - 1) / tile; }
+uint32_t slot_tiles(uint64_t n_slots) { return (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock); }
+uint32_t slot_block() { return kSlotBlock; }
 
 hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
                             hipStream_t s) {
@@ -557,33 +690,47 @@ hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, voi
     scan_counts_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
     return hipGetLastError();
 }
-hipError_t launch_pieces(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts, int waves,
+hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
+                                  void* st, hipStream_t s) {
+    scan_counts_dev_kernel<<<scan_tiles(cap > 0 ? cap : 1), kScanBlock, 0, s>>>(in, n_dev, cap, out, (ScanCtl*)ctl,
+                                                                              (TileStatus*)st);
+    return hipGetLastError();
+}
+
+template <bool Write, bool Stats>
+static void bisect_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, uint32_t range,
+                          uint32_t* nslots, const uint64_t* base, Slot* slots, uint64_t cap,
+                          unsigned long long* stats) {
+    if (waves <= 2) bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, base, slots, cap, stats);
+    else bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, base, slots, cap, stats);
+}
+hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
+                         const uint64_t* base, Slot* slots, uint64_t slot_cap, unsigned long long* stats,
                          hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    const uint32_t g = piece_tiles(sv.n_tags, ws.tile);
-    if (ws.tile == 64) {
-        if (waves <= 1) piece_kernel<1, 64><<<g, 64, 0, s>>>(sv, cfg, ws, counts);
-        else if (waves == 2) piece_kernel<2, 64><<<g, 64, 0, s>>>(sv, cfg, ws, counts);
-        else piece_kernel<3, 64><<<g, 64, 0, s>>>(sv, cfg, ws, counts);
-    } else {
-        if (waves <= 1) piece_kernel<1, 256><<<g, 256, 0, s>>>(sv, cfg, ws, counts);
-        else if (waves == 2) piece_kernel<2, 256><<<g, 256, 0, s>>>(sv, cfg, ws, counts);
-        else piece_kernel<3, 256><<<g, 256, 0, s>>>(sv, cfg, ws, counts);
-    }
+    if (range == 0 || range % 64u) return hipErrorInvalidValue;
+    const uint32_t g = (sv.n_tags + range - 1) / range;
+    if (write) bisect_launch<true, false>(g, s, waves, sv, cfg, range, nslots, base, slots, slot_cap, stats);
+    else if (stats) bisect_launch<false, true>(g, s, waves, sv, cfg, range, nslots, base, slots, slot_cap, stats);
+    else bisect_launch<false, false>(g, s, waves, sv, cfg, range, nslots, base, slots, slot_cap, stats);
     return hipGetLastError();
 }
-hipError_t launch_piece_stats(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, uint32_t* counts,
-                              unsigned long long* stats, hipStream_t s) {
+hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
+                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
+                        unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    if (ws.tile != (uint32_t)kTagBlock) return hipErrorInvalidValue;
-    piece_stats_kernel<<<piece_tiles(sv.n_tags, kTagBlock), kTagBlock, 0, s>>>(sv, cfg, ws, counts, stats);
+    const uint32_t g = std::min<uint32_t>(kSlotGrid, std::max<uint32_t>(1u, slot_tiles(slot_cap)));
+    if (stats) slot_kernel<1, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else if (waves <= 1) slot_kernel<1, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else if (waves == 2) slot_kernel<2, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else slot_kernel<3, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
     return hipGetLastError();
 }
-hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* offsets, void* out,
-                          uint64_t cap, hipStream_t s) {
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,
+                          const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    const uint32_t nt = piece_tiles(sv.n_tags, ws.tile);
-    record_kernel<<<nt + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, arcs, offsets, (float*)out, cap, nt);
+    record_kernel<<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, arcs, roff, n_slots_dev, slot_cap, (float*)out,
+                                                              cap);
     return hipGetLastError();
 }
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
@@ -593,13 +740,20 @@ hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* ta
                                                                                  path_map);
     return hipGetLastError();
 }
-hipError_t launch_scene_offsets(const uint64_t* offsets, const GatherDesc* descs, uint32_t n_scenes, uint32_t n_tags,
-                                uint64_t* scene_offsets, hipStream_t s) {
-    scene_offsets_kernel<<<(n_scenes + 1 + 255) / 256, 256, 0, s>>>(offsets, descs, n_scenes, n_tags, scene_offsets);
+hipError_t launch_scene_offsets(const uint64_t* base, const uint64_t* roff, uint64_t slot_cap, const GatherDesc* descs,
+                                uint32_t n_scenes, uint32_t n_tags, uint64_t* scene_offsets, hipStream_t s) {
+    scene_offsets_kernel<<<(n_scenes + 1 + 255) / 256, 256, 0, s>>>(base, roff, slot_cap, descs, n_scenes, n_tags,
+                                                                    scene_offsets);
     return hipGetLastError();
 }
-hipError_t launch_finish(const uint64_t* offsets, uint32_t n, const ItemWs& ws, uint64_t* dst, hipStream_t s) {
-    finish_kernel<<<1, 64, 0, s>>>(offsets, n, ws, dst);
+hipError_t launch_finish(const uint64_t* roff, const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t n_tags,
+                         const ItemWs& ws, uint64_t* dst, hipStream_t s) {
+    finish_kernel<<<1, 64, 0, s>>>(roff, n_slots_dev, slot_cap, n_tags, ws, dst);
+    return hipGetLastError();
+}
+hipError_t launch_tag_records(const uint64_t* base, const uint64_t* roff, uint64_t slot_cap, uint32_t n_tags,
+                              uint32_t* counts, uint64_t* offs, hipStream_t s) {
+    tag_records_kernel<<<(n_tags + 1 + 255) / 256, 256, 0, s>>>(base, roff, slot_cap, n_tags, counts, offs);
     return hipGetLastError();
 }
 size_t scan_status_bytes(uint32_t n) { return (size_t)scan_tiles(n > 0 ? n : 1) * sizeof(TileStatus); }

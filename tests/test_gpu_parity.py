@@ -242,9 +242,10 @@ def test_too_small_buffer_reports_the_count(ctx):
 
 
 def test_async_workspace_overflow_is_reported_then_resized(ctx):
-    """A scene needing more emission items than its initial workspace: the
-    asynchronous call reports the need and emits nothing; one synchronous call
-    resizes the workspace; the asynchronous call then matches it bit for bit."""
+    """A scene needing more slots and emission items than its initial
+    workspace: the asynchronous call reports it and emits nothing; one
+    synchronous call resizes the workspace; the asynchronous call then
+    matches it bit for bit."""
     import torch
 
     from paper_2405_00127_amd import binding as B
@@ -258,11 +259,10 @@ def test_async_workspace_overflow_is_reported_then_resized(ctx):
     cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
     ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), sc.tolerance, mode)
     torch.cuda.synchronize()
-    n0, need = int(cnt[0]), int(cnt[1])
-    assert need > 0 and n0 > 0
-    assert int(buf[: n0 * rec].count_nonzero()) == 0  # nothing emitted
+    need = int(cnt[1])
+    assert need != 0
     recs, n, _ = ctx.expand(scene, sc.tolerance, mode)
-    assert n == n0
+    assert int(buf[: n * rec].count_nonzero()) == 0  # nothing was emitted
     ref = B.records_to_numpy(recs, mode).copy()
     buf.zero_()
     cnt.zero_()

@@ -24,7 +24,7 @@ def test_workload_key_buckets_sizes_by_power_of_two():
 def test_tuning_cache_roundtrip(tmp_path):
     path = str(tmp_path / "sub" / "tuning.json")
     assert AT._load(path) == {}
-    AT._store(path, {"a": {"piece_waves": 2, "chunk_k": 16, "piece_block": 64}})
+    AT._store(path, {"a": {"piece_waves": 2, "chunk_k": 16, "bisect_range": 256, "bisect_waves": 2}})
     assert AT._load(path)["a"]["chunk_k"] == 16
     with open(path, "w") as f:
         f.write("not json")
@@ -32,29 +32,32 @@ def test_tuning_cache_roundtrip(tmp_path):
 
 
 class _FakeCtx:
-    """Records tuning calls; times come from a table (no GPU)."""
+    """Records tuning calls; times come from a cost function (no GPU)."""
 
     device = 0
 
     def __init__(self, cost):
-        self.t = {"piece_waves": 2, "chunk_k": 16, "piece_block": 256}
+        self.t = {"piece_waves": 2, "chunk_k": 16, "bisect_range": 256, "bisect_waves": 2}
         self.cost = cost
 
-    def set_tuning(self, w, k, b=256):
-        self.t = {"piece_waves": w, "chunk_k": k, "piece_block": b}
+    def set_tuning(self, **kw):
+        self.t.update(kw)
 
     def get_tuning(self):
         return dict(self.t)
 
 
 def test_tuner_picks_the_fastest_candidate(monkeypatch, tmp_path):
-    cost = {(w, b, k): 10.0 + w + (0 if b == 64 else 3) + abs(k - 32) / 8
-            for w in AT.PIECE_WAVES for b in AT.PIECE_BLOCK for k in AT.CHUNK_K}
+    def cost(t):  # separable: each group has one best value
+        return (10.0 + abs(t["piece_waves"] - 1) + abs(t["bisect_range"] - 512) / 256 + (t["bisect_waves"] == 2)
+                + abs(t["chunk_k"] - 32) / 8)
+
     ctx = _FakeCtx(cost)
+    calls = []
 
     def fake_time(c, *a, **kw):
-        t = c.get_tuning()
-        return c.cost[(t["piece_waves"], t["piece_block"], t["chunk_k"])]
+        calls.append(c.get_tuning())
+        return c.cost(c.get_tuning())
 
     monkeypatch.setattr(AT, "time_config", fake_time)
 
@@ -73,14 +76,12 @@ def test_tuner_picks_the_fastest_candidate(monkeypatch, tmp_path):
     class _Scene:
         n_tags = 1000
 
-    chosen, times = AT.tune(ctx, _Scene(), 0.25, 0, 0, 0, 0, stream=object(),
-                            cache_path=str(tmp_path / "t.json"))
-    assert chosen == {"piece_waves": 1, "chunk_k": 32, "piece_block": 64}
-    assert len(times) == len(AT.PIECE_WAVES) * len(AT.PIECE_BLOCK) + len(AT.CHUNK_K) - 1
+    chosen, times = AT.tune(ctx, _Scene(), 0.25, 0, 0, 0, 0, stream=object(), cache_path=str(tmp_path / "t.json"))
+    assert chosen == {"piece_waves": 1, "chunk_k": 32, "bisect_range": 512, "bisect_waves": 4}
+    assert len(calls) == len(times)  # every candidate timed once
     # second call answers from the cache without timing anything
-    ctx2 = _FakeCtx({})
-    chosen2, times2 = AT.tune(ctx2, _Scene(), 0.25, 0, 0, 0, 0, stream=object(),
-                              cache_path=str(tmp_path / "t.json"))
+    ctx2 = _FakeCtx(cost)
+    chosen2, times2 = AT.tune(ctx2, _Scene(), 0.25, 0, 0, 0, 0, stream=object(), cache_path=str(tmp_path / "t.json"))
     assert times2 == {} and chosen2 == chosen
 
 
