@@ -156,9 +156,26 @@ SX_FN V2 es_integral_f(float k0, float k1, float u) {
     }
     return v2(sx * hu, sy * hu);
 }
-// Z(1) in FP64 (once per piece): 8-point Gauss-Legendre on v = u - 1/2.
-// The nodes come in pairs +-v, and exp(i phi(v)) + exp(i phi(-v)) =
-// 2 cos(k0 v) exp(i k1 v^2 / 2), so each pair costs one sincos and one cos.
+// Z(1) (once per piece): 8-point Gauss-Legendre on v = u - 1/2.  The nodes
+// come in pairs +-v, and exp(i phi(v)) + exp(i phi(-v)) = 2 cos(k0 v)
+// exp(i k1 v^2 / 2), so each pair costs one sincos and one cos.  Z(1) only
+// places the piece for the per-point work (p0 + chord / Z(1) * Z(u)), so the
+// pipeline takes it in FP32; the FP64 form serves host checks.
+SX_FN V2 es_integral1_f(float k0, float k1) {
+    const float gx[4] = {0.1834346424956498f, 0.5255324099163290f, 0.7966664774136267f, 0.9602898564975363f};
+    const float gw[4] = {0.3626837833783620f, 0.3137066458778873f, 0.2223810344533745f, 0.1012285362903763f};
+    float sx = 0.0f, sy = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const float v = 0.5f * gx[i];
+        float sn, cs;
+        sincosf(0.5f * k1 * v * v, &sn, &cs);
+        const float c = gw[i] * cosf(k0 * v);
+        sx += c * cs;
+        sy += c * sn;
+    }
+    return v2(sx, sy);
+}
 SX_FN D2 es_integral1(double k0, double k1) {
     const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
     const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
@@ -223,52 +240,64 @@ SX_FN void set_es_f(const ES& es, float* d) {
 // x = -1 - 2 h kappa maps the ES inflection to -1 and the parallel-curve
 // cusp to +1 (Section 4.1).  A point on this axis keeps x and, precisely,
 // e = |x| - 1 (2 h kappa when x <= 0, -2 rho when x > 0).
-struct XP {
-    double x, e;
+// The helpers are templates: FP64 where they decide counts (piece stage),
+// FP32 where they only place points (record stage).
+template <class T>
+SX_FN T absT(T v) { return v < T(0) ? -v : v; }
+template <class T>
+struct XPT {
+    T x, e;
 };
-SX_FN XP make_xp(double hk) {
-    double x = -1.0 - 2.0 * hk;
-    double e = (x <= 0.0) ? 2.0 * hk : -2.0 * (1.0 + hk);
-    return XP{x, e};
+using XP = XPT<double>;
+template <class T>
+SX_FN XPT<T> make_xp(T hk) {
+    const T x = T(-1) - T(2) * hk;
+    const T e = (x <= T(0)) ? T(2) * hk : T(-2) * (T(1) + hk);
+    return XPT<T>{x, e};
 }
-SX_FN XP bp_xp(double x) { return XP{x, fabs(x) - 1.0}; }
+template <class T>
+SX_FN XPT<T> bp_xp(T x) { return XPT<T>{x, absT(x) - T(1)}; }
 
 // branch of f_approx by |x|: 0 [0,0.8) sin, 1 [0.8,1.25) 1.5-power, 2 [1.25,2.1) and 3 quadratics
-SX_FN int branch_of(double ax) { return ax < 0.8 ? 0 : (ax < 1.25 ? 1 : (ax < 2.1 ? 2 : 3)); }
+template <class T>
+SX_FN int branch_of(T ax) { return ax < T(0.8) ? 0 : (ax < T(1.25) ? 1 : (ax < T(2.1) ? 2 : 3)); }
 SX_FN double pow15(double a) { return a * sqrt(a); }
 SX_FN float pow15f(float a) { return a * sqrtf(a); }
 
 // Divided difference (F(b) - F(a)) / (b - a) of f_approx over one branch,
 // in a cancellation-free form; dx = b - a given precisely.
-SX_HD inline double branch_dd(int br, XP a, XP b, double dx) {
+template <class T>
+SX_HD inline T branch_dd(int br, XPT<T> a, XPT<T> b, T dx) {
     if (br == 0) {
-        double m = 0.5 * (a.x + b.x);
-        double hz = 0.5 * kC1 * dx;
-        double sc = (fabs(hz) < 1e-6) ? 1.0 - hz * hz * (1.0 / 6.0) : sin(hz) / hz;
-        return cos(kC1 * m) * sc;
+        const T m = T(0.5) * (a.x + b.x);
+        const T hz = T(0.5) * T(kC1) * dx;
+        const T sc = (absT(hz) < T(1e-6)) ? T(1) - hz * hz * T(1.0 / 6.0) : sin(hz) / hz;
+        return cos(T(kC1) * m) * sc;
     }
     if (br == 1) {
-        double ea = fabs(a.e), eb = fabs(b.e);
-        if (a.e * b.e >= 0.0) {
-            double ra = sqrt(ea), rb = sqrt(eb);
-            double den = ra + rb;
-            if (den == 0.0) return 0.0;
-            return kA2 * (ea + ra * rb + eb) / den;
+        const T ea = absT(a.e), eb = absT(b.e);
+        if (a.e * b.e >= T(0)) {
+            const T ra = sqrt(ea), rb = sqrt(eb);
+            const T den = ra + rb;
+            if (den == T(0)) return T(0);
+            return T(kA2) * (ea + ra * rb + eb) / den;
         }
-        return kA2 * (pow15(ea) + pow15(eb)) / (ea + eb);
+        return T(kA2) * (ea * sqrt(ea) + eb * sqrt(eb)) / (ea + eb);
     }
-    double aa = fabs(a.x), ab = fabs(b.x);
-    if (br == 2) return 0.6406 * (aa + ab) - 0.81;
-    return 0.5 * (aa + ab) - 0.156;
+    const T aa = absT(a.x), ab = absT(b.x);
+    if (br == 2) return T(0.6406) * (aa + ab) - T(0.81);
+    return T(0.5) * (aa + ab) - T(0.156);
 }
 
 // Range of the x axis split at the branch breaks of f_approx.
-struct XSeg {
-    XP a;
-    double len;  // signed x length
-    double dF;   // F increment over the piece
+template <class T>
+struct XSegT {
+    XPT<T> a;
+    T len;  // signed x length
+    T dF;   // F increment over the piece
     int br;
 };
+using XSeg = XSegT<double>;
 // Total F increment over [xa, xb], split at the branch breaks of f_approx
 // (the pieces in order of x from xa); *dxs receives the FP32 sum of
 // the pieces' lengths.
@@ -299,29 +328,31 @@ SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs) {
 
 // Piece j of that split on its own (the same values and order), and the
 // number of pieces.
-SX_HD inline int xseg_count(XP xa, XP xb) {
-    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
-    bool up = xb.x > xa.x;
+template <class T>
+SX_HD inline int xseg_count(XPT<T> xa, XPT<T> xb) {
+    const T bps[6] = {T(-2.1), T(-1.25), T(-0.8), T(0.8), T(1.25), T(2.1)};
+    const bool up = xb.x > xa.x;
     int n = 1;
     for (int k = 0; k < 6; k++) n += (up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x)) ? 1 : 0;
     return n;
 }
-SX_HD inline XSeg xseg_at(XP xa, XP xb, double dx_total, int j) {
-    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
+template <class T>
+SX_HD inline XSegT<T> xseg_at(XPT<T> xa, XPT<T> xb, T dx_total, int j) {
+    const T bps[6] = {T(-2.1), T(-1.25), T(-0.8), T(0.8), T(1.25), T(2.1)};
     int n = 0;
-    XP cur = xa;
-    bool up = xb.x > xa.x;
-    XSeg sg;
+    XPT<T> cur = xa;
+    const bool up = xb.x > xa.x;
+    XSegT<T> sg;
     for (int kk = 0; kk < 6; kk++) {
-        int k = up ? kk : 5 - kk;
-        bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
+        const int k = up ? kk : 5 - kk;
+        const bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
         if (inside) {
             if (n == j) {
-                XP nb = bp_xp(bps[k]);
-                double l = bps[k] - cur.x;
+                const XPT<T> nb = bp_xp(bps[k]);
+                const T l = bps[k] - cur.x;
                 sg.a = cur;
                 sg.len = l;
-                sg.br = branch_of(fabs(cur.x + 0.5 * l));
+                sg.br = branch_of(absT(cur.x + T(0.5) * l));
                 sg.dF = branch_dd(sg.br, cur, nb, l) * l;
                 return sg;
             }
@@ -329,19 +360,19 @@ SX_HD inline XSeg xseg_at(XP xa, XP xb, double dx_total, int j) {
             n++;
         }
     }
-    double l = (n == 0) ? dx_total : xb.x - cur.x;
+    const T l = (n == 0) ? dx_total : xb.x - cur.x;
     sg.a = cur;
     sg.len = l;
-    sg.br = (n == 0) ? branch_of(fabs(0.5 * (xa.x + xb.x))) : branch_of(fabs(cur.x + 0.5 * l));
+    sg.br = (n == 0) ? branch_of(absT(T(0.5) * (xa.x + xb.x))) : branch_of(absT(cur.x + T(0.5) * l));
     sg.dF = branch_dd(sg.br, cur, xb, l) * l;
     return sg;
 }
 
 // Fraction of a branch segment at which F has risen by f * seg.dF
 // (local, cancellation-free inverse of f_approx; FP32 per output point).
-SX_HD inline float branch_inv_frac(const XSeg& s, float f) {
-    float G = (float)(s.dF / s.len);  // divided difference (len != 0 here)
-    float ax = (float)s.a.x, ae = (float)s.a.e, dF = (float)s.dF, ln = (float)s.len;
+SX_HD inline float branch_inv_frac(const XSegT<float>& s, float f) {
+    const float G = s.dF / s.len;  // divided difference (len != 0 here)
+    const float ax = s.a.x, ae = s.a.e, dF = s.dF, ln = s.len;
     if (s.br == 0) {
         const float c1 = (float)kC1;
         float th = c1 * ax;
@@ -763,9 +794,9 @@ SX_FN ES es_from_f(const float* d, bool pivot) {
 // Points are placed in increasing order, so the piece holding each point's
 // share of F only moves forward; the pieces are produced one at a time.
 struct XWalk {
-    XP xa, xb;
-    double dx, cum;
-    XSeg seg;
+    XPT<float> xa, xb;
+    float dx, cum;
+    XSegT<float> seg;
     int j, nseg;
     float acc_len;
 };
@@ -776,17 +807,17 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
     float tau = f;
     if (hdr & kIfPlaceF) {
         // advance to the branch piece holding f * dF
-        double target = f * p.dF;
-        while (w.j < w.nseg - 1 && !(fabs(w.cum + w.seg.dF) >= fabs(target))) {
+        const float target = f * (float)p.dF;
+        while (w.j < w.nseg - 1 && !(fabsf(w.cum + w.seg.dF) >= fabsf(target))) {
             w.cum += w.seg.dF;
-            w.acc_len += (float)w.seg.len;
+            w.acc_len += w.seg.len;
             w.j++;
             w.seg = xseg_at(w.xa, w.xb, w.dx, w.j);
         }
-        float fl = (w.seg.dF != 0.0) ? (float)((target - w.cum) / w.seg.dF) : 0.0f;
+        float fl = (w.seg.dF != 0.0f) ? (target - w.cum) / w.seg.dF : 0.0f;
         fl = fminf(fmaxf(fl, 0.0f), 1.0f);
-        float phi = (w.seg.len != 0.0) ? branch_inv_frac(w.seg, fl) : fl;
-        tau = (w.nseg == 1) ? phi : (w.acc_len + phi * (float)w.seg.len) / p.dxs;
+        const float phi = (w.seg.len != 0.0f) ? branch_inv_frac(w.seg, fl) : fl;
+        tau = (w.nseg == 1) ? phi : (w.acc_len + phi * w.seg.len) / p.dxs;
     } else if (hdr & kIfPlaceES) {
         // h = 0: uniform in |kappa|^1.5 (Section 2.2)
         KnPair kp;
@@ -826,12 +857,14 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
         XWalk w;
         w.j = 0;
         w.nseg = 1;
-        w.cum = 0.0;
+        w.cum = 0.0f;
         w.acc_len = 0.0f;
         if (hdr & kIfPlaceF) {
-            w.xa = make_xp(p.hka);
-            w.xb = make_xp(p.hkb);
-            w.dx = p.dx;
+            // x and e from FP64 (e keeps its relative precision next to the cusp)
+            const XP xa = make_xp(p.hka), xb = make_xp(p.hkb);
+            w.xa = XPT<float>{(float)xa.x, (float)xa.e};
+            w.xb = XPT<float>{(float)xb.x, (float)xb.e};
+            w.dx = (float)p.dx;
             w.nseg = xseg_count(w.xa, w.xb);
             w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
         }
@@ -1226,10 +1259,13 @@ SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t
         es.k0 = tr.th0 + tr.th1;
         es.k1 = es_k1(tr.th0, tr.th1);
         c = es_chord(tr.th0, tr.th1);
-        const D2 z1 = es_integral1(es.k0, es.k1);
-        const double zz = z1.x * z1.x + z1.y * z1.y;
-        rot = d2((chord.x * z1.x + chord.y * z1.y) / zz, (chord.y * z1.x - chord.x * z1.y) / zz);
-        base = atan2(rot.y, rot.x);
+        // rotation chord / Z(1) in FP32: it only places the per-point work
+        const V2 z1 = es_integral1_f((float)es.k0, (float)es.k1);
+        const V2 ch = f32(chord);
+        const float zz = z1.x * z1.x + z1.y * z1.y;
+        const V2 fr = v2((ch.x * z1.x + ch.y * z1.y) / zz, (ch.y * z1.x - ch.x * z1.y) / zz);
+        rot = d2(fr.x, fr.y);
+        base = (double)atan2f(fr.y, fr.x);
     }
     if (!(c > kCMin)) c = kCMin;
     es.L = tr.cl / c;

@@ -24,19 +24,21 @@
 namespace sx {
 
 // ------------------------------------------------------ look-back scan
-// Per-tile status word: (epoch << 2) | state, state 1 = aggregate ready,
-// 2 = inclusive prefix ready.  The epoch (kept in device memory and bumped
-// by the last tile of every launch) makes stale flags of earlier launches
-// read as "not ready", so nothing has to be cleared between launches and the
-// kernels can be replayed inside a HIP graph.
-// The aggregate and the inclusive prefix live in separate words: a reader
-// that saw "aggregate ready" must never pick up a later inclusive value.
+// A tile publishes its aggregate, then its inclusive prefix, as four 32-bit
+// parts each (the pair (a, b) split in halves), every part in its own 64-bit
+// word next to the launch's epoch: (epoch << 32) | part.  A word is read and
+// written with single relaxed device-scope atomics, so a reader sees a part
+// only together with its epoch and no fences are needed (on this GPU a
+// release or acquire at device scope writes back or invalidates the whole L2
+// of the XCD).  A part is ready once its word carries the current epoch; the
+// epoch (kept in device memory, advanced by the last tile of every launch,
+// never 0) makes stale words of earlier launches read as "not ready", so
+// nothing is cleared between launches and the kernels can be replayed inside
+// a HIP graph.  Aggregate and inclusive words are separate, so a reader that
+// takes a tile's aggregate never mixes in its inclusive prefix.
 struct TileStatus {
-    uint32_t flag;
-    uint32_t pad;
-    uint64_t agg_a, agg_b;
-    uint64_t inc_a, inc_b;
-    uint64_t pad2[3];
+    unsigned long long agg[4];
+    unsigned long long inc[4];
 };
 static_assert(sizeof(TileStatus) == 64, "tile status layout");
 
@@ -86,24 +88,33 @@ __device__ __forceinline__ Pair wave_sum(Pair v) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_release(uint32_t* p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t pair_part(Pair v, int k) {
+    const uint64_t w = (k < 2) ? v.a : v.b;
+    return (k & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
 }
 
-// Publish a tile's value with its state (data first, then the flag).
-__device__ __forceinline__ void publish(TileStatus* st, uint32_t tile, uint32_t epoch, uint32_t state, Pair v) {
-    if (state == 1) {
-        st[tile].agg_a = v.a;
-        st[tile].agg_b = v.b;
-    } else {
-        st[tile].inc_a = v.a;
-        st[tile].inc_b = v.b;
+// Lanes 0..3 of the calling wave publish the four parts of v.
+__device__ __forceinline__ void publish(TileStatus* st, uint32_t tile, uint32_t epoch, bool inclusive, Pair v,
+                                       int lane) {
+    if (lane < 4) {
+        const unsigned long long w = ((unsigned long long)epoch << 32) | pair_part(v, lane);
+        unsigned long long* p = inclusive ? &st[tile].inc[lane] : &st[tile].agg[lane];
+        __hip_atomic_store(p, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __threadfence();
-    store_release(&st[tile].flag, (epoch << 2) | state);
+}
+
+__device__ __forceinline__ unsigned long long rd(const unsigned long long* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The four words of a status record as a pair, if all carry `epoch`.
+__device__ __forceinline__ bool read4(const unsigned long long* w, uint32_t epoch, Pair& v) {
+    const unsigned long long w0 = rd(w), w1 = rd(w + 1), w2 = rd(w + 2), w3 = rd(w + 3);
+    const bool ok = (uint32_t)(w0 >> 32) == epoch && (uint32_t)(w1 >> 32) == epoch && (uint32_t)(w2 >> 32) == epoch &&
+                    (uint32_t)(w3 >> 32) == epoch;
+    v.a = (uint64_t)(uint32_t)w0 | ((uint64_t)(uint32_t)w1 << 32);
+    v.b = (uint64_t)(uint32_t)w2 | ((uint64_t)(uint32_t)w3 << 32);
+    return ok;
 }
 
 // Wave 0 of tile `tile` computes the exclusive prefix of all earlier tiles.
@@ -117,33 +128,29 @@ __device__ Pair look_back(TileStatus* st, uint32_t tile, uint32_t epoch, int lan
     Pair excl{0, 0};
     int64_t pos = (int64_t)tile - 1;
     while (pos >= 0) {
-        int64_t idx = pos - lane;
-        uint32_t state;
+        const int64_t idx = pos - lane;
+        uint32_t state;  // 0 not ready, 1 aggregate, 2 inclusive, 3 before tile 0 (inclusive zero)
         Pair v{0, 0};
         for (uint32_t spins = 0;; spins++) {
-            state = 3;  // lanes past tile 0 count as "inclusive zero"
+            state = 3;
+            v = Pair{0, 0};
             if (idx >= 0) {
-                uint32_t f = load_acquire(&st[idx].flag);
-                state = ((f >> 2) == (epoch & 0x3fffffffu)) ? (f & 3u) : 0u;
+                if (read4(st[idx].inc, epoch, v)) state = 2;
+                else if (read4(st[idx].agg, epoch, v)) state = 1;
+                else state = 0;
             }
             if (__ballot(state == 0u) == 0ull) break;
             if (spins >= kSpinLimit) {
                 if (lane == 0) atomicOr(err, 1u);
                 state = 3;
+                v = Pair{0, 0};
                 break;
             }
             __builtin_amdgcn_s_sleep(1);
         }
-        if (idx >= 0 && state == 1u) {
-            v.a = __hip_atomic_load(&st[idx].agg_a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v.b = __hip_atomic_load(&st[idx].agg_b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else if (idx >= 0 && state == 2u) {
-            v.a = __hip_atomic_load(&st[idx].inc_a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v.b = __hip_atomic_load(&st[idx].inc_b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        uint64_t incl_mask = __ballot(state >= 2u);
+        const uint64_t incl_mask = __ballot(state >= 2u);
         if (incl_mask) {
-            int first = __builtin_ctzll(incl_mask);  // nearest tile with a full prefix
+            const int first = __builtin_ctzll(incl_mask);  // nearest tile with a full prefix
             if (lane > first) v = Pair{0, 0};
             excl = excl + wave_sum(v);
             break;
@@ -167,15 +174,16 @@ __device__ __forceinline__ Pair tag_inc(uint32_t t) {
     return Pair{pts | (pth << 32), sty | (xf << 32)};
 }
 
-// The last block of a launch resets the ticket and done counters and bumps
-// the epoch, so the next launch starts clean without any memset.
-__device__ __forceinline__ void finish_scan(ScanCtl* ctl, uint32_t epoch_read) {
-    __threadfence();
+// The last block of a launch resets the ticket and done counters and
+// records the epoch it used, so the next launch starts clean without any
+// memset.
+// (The next launch reads these words after the kernel boundary, which
+// makes them visible; no fence is needed here.)
+__device__ __forceinline__ void finish_scan(ScanCtl* ctl, uint32_t epoch_used) {
     if (atomicAdd(&ctl->done, 1u) == gridDim.x - 1) {
         ctl->ticket = 0;
         ctl->done = 0;
-        __threadfence();
-        __hip_atomic_store(&ctl->epoch, (epoch_read + 1u) & 0x3fffffffu, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ctl->epoch = epoch_used;
     }
 }
 
@@ -187,10 +195,12 @@ __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, Tile
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) {
         s_tile = atomicAdd(&ctl->ticket, 1u);
-        s_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        // this launch's epoch: one past the last launch's, never 0 (zeroed words)
+        const uint32_t e = ctl->epoch + 1u;
+        s_epoch = e ? e : 1u;
     }
     __syncthreads();
-    const uint32_t tile = s_tile, epoch = s_epoch & 0x3fffffffu;
+    const uint32_t tile = s_tile, epoch = s_epoch;
     const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
     if (tile >= ntiles) {
         // a grid sized for a capacity larger than this launch's n: nothing to scan
@@ -221,11 +231,11 @@ __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, Tile
     if (wv == 0) {
         Pair excl{0, 0};
         if (tile == 0) {
-            if (lane == 0) publish(st, tile, epoch, 2, agg);
+            publish(st, tile, epoch, true, agg, lane);
         } else {
-            if (lane == 0) publish(st, tile, epoch, 1, agg);
+            publish(st, tile, epoch, false, agg, lane);
             excl = look_back(st, tile, epoch, lane, &ctl->err);
-            if (lane == 0) publish(st, tile, epoch, 2, excl + agg);
+            publish(st, tile, epoch, true, excl + agg, lane);
         }
         if (lane == 0) s_excl = excl;
     }
