@@ -34,6 +34,7 @@ struct sx_scene {
     // per tag: monoids, slot counts and their exclusive scan (slot bases)
     uint32_t* d_mon = nullptr;
     uint32_t* d_nslots = nullptr;
+    uint32_t* d_codes = nullptr;  // the first piece codes of each tag (count pass)
     uint64_t* d_base = nullptr;
     // per slot: the slot, its record count and record offset
     sx::Slot* d_slots = nullptr;
@@ -103,6 +104,7 @@ void free_scene(sx_scene* s) {
     dfree(s->d_path_map);
     dfree(s->d_mon);
     dfree(s->d_nslots);
+    dfree(s->d_codes);
     dfree(s->d_base);
     dfree(s->d_slots);
     dfree(s->d_rc);
@@ -207,6 +209,7 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         regrow(s->d_tags, ntag_pad);
         regrow(s->d_mon, 4 * (size_t)c * sizeof(uint32_t));
         regrow(s->d_nslots, ((size_t)c + 16) * sizeof(uint32_t));
+        regrow(s->d_codes, ((size_t)c + 1) * sx::kKeepCodes * sizeof(uint32_t));
         regrow(s->d_base, ((size_t)c + 1) * sizeof(uint64_t));
         regrow(s->d_status_tags, sx::scan_status_bytes(c));
         regrow(s->d_status_nslots, sx::scan_status_bytes(c));
@@ -276,13 +279,13 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
             return sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl_block(s, 0), s->d_status_tags, s->d_ws_ctl,
                                         st);
         case kPhBisectCount:
-            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, false, s->d_nslots, nullptr,
-                                     nullptr, 0, stats, st);
+            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, false, s->d_nslots,
+                                     s->d_codes, nullptr, nullptr, 0, stats, st);
         case kPhScanSlots:
             return sx::launch_scan_counts(s->d_nslots, s->n_tags, s->d_base, ctl_block(s, 1), s->d_status_nslots, st);
         case kPhBisectWrite:
-            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, true, nullptr, s->d_base,
-                                     s->d_slots, s->slot_cap, nullptr, st);
+            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, true, s->d_nslots,
+                                     s->d_codes, s->d_base, s->d_slots, s->slot_cap, nullptr, st);
         case kPhSlots:
             return sx::launch_slots(view(s), cfg, workspace(s), s->d_slots, n_slots_dev(s), s->slot_cap, s->d_rc,
                                     (int)t.piece_waves, stats, st);

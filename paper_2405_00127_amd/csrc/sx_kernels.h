@@ -48,9 +48,11 @@ hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s);
 hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
                                   void* st, hipStream_t s);
+// piece codes kept per tag by the counting bisection pass
+constexpr int kKeepCodes = 32;
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
-                         const uint64_t* base, Slot* slots, uint64_t slot_cap, unsigned long long* stats,
-                         hipStream_t s);
+                         uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
+                         unsigned long long* stats, hipStream_t s);
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
                         const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
                         unsigned long long* stats, hipStream_t s);

@@ -357,14 +357,17 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // a lane whose segment is done takes the wave's next tag (lane refill), so
 // the wave is busy until its range is exhausted instead of waiting for its
 // longest segment.  The count pass writes, per tag, its slot count (accepted
-// pieces + 1 tail); the write pass, after the scan of those counts, writes
-// each piece's slot at its canonical position.
+// pieces + 1 tail) and keeps the codes of its first kKeepCodes pieces; the
+// write pass, after the scan of those counts, writes each tag's slots at
+// their canonical positions: copied from the kept codes, or, for the few
+// segments with more pieces, from a second run of the bisection.
 constexpr int kBisectBlock = 64;
 
 template <bool Write, bool Stats, int MinWaves>
 __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
-    SceneView sv, Cfg cfg, uint32_t range, uint32_t* __restrict__ nslots, const uint64_t* __restrict__ base,
-    Slot* __restrict__ slots, uint64_t slot_cap, unsigned long long* __restrict__ stats) {
+    SceneView sv, Cfg cfg, uint32_t range, uint32_t* __restrict__ nslots, uint32_t* __restrict__ codes,
+    const uint64_t* __restrict__ base, Slot* __restrict__ slots, uint64_t slot_cap,
+    unsigned long long* __restrict__ stats) {
     const uint32_t lane = threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t a = blockIdx.x * range;
@@ -386,9 +389,23 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
             if (!busy && ni < b) {
                 i = ni;
                 seq = 0;
-                if (Write) bi = base[i];
-                fetch_tag(sv, i, ti, s);
-                if (ti.kind == kTagSegment) {
+                bool copied = false;
+                if (Write) {
+                    bi = base[i];
+                    const uint32_t np = nslots[i] - 1u;
+                    if (np <= (uint32_t)kKeepCodes) {
+                        // pieces known from the count pass: copy them and the tail
+                        const uint32_t* c = codes + (size_t)i * kKeepCodes;
+                        for (uint32_t q = 0; q < np; q++)
+                            if (bi + q < slot_cap) slots[bi + q] = Slot{i, c[q]};
+                        if (bi + np < slot_cap) slots[bi + np] = Slot{i, kSlotTail};
+                        copied = true;
+                    }
+                }
+                if (!copied) fetch_tag(sv, i, ti, s);
+                if (copied) {
+                    // done with this tag
+                } else if (ti.kind == kTagSegment) {
                     bisect_init(bs, s);
                     busy = true;
                 } else {
@@ -414,6 +431,8 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 if (Write) {
                     const uint64_t at = bi + seq;
                     if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth)};
+                } else if (seq < (uint32_t)kKeepCodes) {
+                    codes[(size_t)i * kKeepCodes + seq] = slot_code(t0u, depth);
                 }
                 seq++;
                 if (done) {
@@ -709,20 +728,22 @@ hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uin
 
 template <bool Write, bool Stats>
 static void bisect_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, uint32_t range,
-                          uint32_t* nslots, const uint64_t* base, Slot* slots, uint64_t cap,
+                          uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t cap,
                           unsigned long long* stats) {
-    if (waves <= 2) bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, base, slots, cap, stats);
-    else bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, base, slots, cap, stats);
+    if (waves <= 2)
+        bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
+    else
+        bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
 }
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
-                         const uint64_t* base, Slot* slots, uint64_t slot_cap, unsigned long long* stats,
-                         hipStream_t s) {
+                         uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
+                         unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     if (range == 0 || range % 64u) return hipErrorInvalidValue;
     const uint32_t g = (sv.n_tags + range - 1) / range;
-    if (write) bisect_launch<true, false>(g, s, waves, sv, cfg, range, nslots, base, slots, slot_cap, stats);
-    else if (stats) bisect_launch<false, true>(g, s, waves, sv, cfg, range, nslots, base, slots, slot_cap, stats);
-    else bisect_launch<false, false>(g, s, waves, sv, cfg, range, nslots, base, slots, slot_cap, stats);
+    if (write) bisect_launch<true, false>(g, s, waves, sv, cfg, range, nslots, codes, base, slots, slot_cap, stats);
+    else if (stats) bisect_launch<false, true>(g, s, waves, sv, cfg, range, nslots, codes, base, slots, slot_cap, stats);
+    else bisect_launch<false, false>(g, s, waves, sv, cfg, range, nslots, codes, base, slots, slot_cap, stats);
     return hipGetLastError();
 }
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
