@@ -254,7 +254,7 @@ int sx_batch_expand(sx_ctx *ctx, sx_batch *batch, float tolerance, int output_mo
  *                 of the record kernel);
  *   bisect_range  tags per bisection wave, a multiple of 64 up to 8192
  *                 (0 = 256): longer ranges keep lanes refilled longer;
- *   bisect_waves  2 or 4 (0 = 2): waves per SIMD of the bisection kernels.
+ *   bisect_waves  2, 3 or 4 (0 = 2): waves per SIMD of the bisection kernels.
  * Defaults {2, 16, 256, 2}.  Errors: SX_EINVAL (out of range). */
 typedef struct {
     uint32_t piece_waves;

@@ -384,8 +384,8 @@ int sx_set_tuning(sx_ctx* ctx, const sx_tuning* t) {
     if (t->chunk_k < 1 || t->chunk_k > 255) return fail(ctx, SX_EINVAL, "chunk_k must be in [1, 255]");
     if (t->bisect_range != 0 && (t->bisect_range % 64 || t->bisect_range > 8192))
         return fail(ctx, SX_EINVAL, "bisect_range must be a multiple of 64 up to 8192 (0: 256)");
-    if (t->bisect_waves != 0 && t->bisect_waves != 2 && t->bisect_waves != 4)
-        return fail(ctx, SX_EINVAL, "bisect_waves must be 2 or 4 (0: 2)");
+    if (t->bisect_waves != 0 && (t->bisect_waves < 2 || t->bisect_waves > 4))
+        return fail(ctx, SX_EINVAL, "bisect_waves must be 2, 3 or 4 (0: 2)");
     ctx->tune = *t;
     if (ctx->tune.bisect_range == 0) ctx->tune.bisect_range = 256;
     if (ctx->tune.bisect_waves == 0) ctx->tune.bisect_waves = 2;

@@ -162,17 +162,32 @@ SX_FN V2 es_integral_f(float k0, float k1, float u) {
 // places the piece for the per-point work (p0 + chord / Z(1) * Z(u)), so the
 // pipeline takes it in FP32; the FP64 form serves host checks.
 SX_FN V2 es_integral1_f(float k0, float k1) {
-    const float gx[4] = {0.1834346424956498f, 0.5255324099163290f, 0.7966664774136267f, 0.9602898564975363f};
-    const float gw[4] = {0.3626837833783620f, 0.3137066458778873f, 0.2223810344533745f, 0.1012285362903763f};
     float sx = 0.0f, sy = 0.0f;
+    if (fabsf(k0) + fabsf(k1) < 1.5f) {
+        // 4 nodes (2 pairs) integrate the smooth phase to FP32 accuracy here
+        const float gx[2] = {0.3399810435848563f, 0.8611363115940526f};
+        const float gw[2] = {0.6521451548625461f, 0.3478548451374538f};
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const float v = 0.5f * gx[i];
-        float sn, cs;
-        sincosf(0.5f * k1 * v * v, &sn, &cs);
-        const float c = gw[i] * cosf(k0 * v);
-        sx += c * cs;
-        sy += c * sn;
+        for (int i = 0; i < 2; i++) {
+            const float v = 0.5f * gx[i];
+            float sn, cs;
+            sincosf(0.5f * k1 * v * v, &sn, &cs);
+            const float c = gw[i] * cosf(k0 * v);
+            sx += c * cs;
+            sy += c * sn;
+        }
+    } else {
+        const float gx[4] = {0.1834346424956498f, 0.5255324099163290f, 0.7966664774136267f, 0.9602898564975363f};
+        const float gw[4] = {0.3626837833783620f, 0.3137066458778873f, 0.2223810344533745f, 0.1012285362903763f};
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const float v = 0.5f * gx[i];
+            float sn, cs;
+            sincosf(0.5f * k1 * v * v, &sn, &cs);
+            const float c = gw[i] * cosf(k0 * v);
+            sx += c * cs;
+            sy += c * sn;
+        }
     }
     return v2(sx, sy);
 }
@@ -269,10 +284,26 @@ SX_FN float pow15f(float a) { return a * sqrtf(a); }
 template <class T>
 SX_HD inline T branch_dd(int br, XPT<T> a, XPT<T> b, T dx) {
     if (br == 0) {
+        // cos(c1 m) sin(hz) / hz; on this branch |c1 m| < 0.88, and hz is
+        // small for all but very long pieces: both by their Taylor series
+        // (truncation below 1e-17 relative), else by the library functions.
         const T m = T(0.5) * (a.x + b.x);
         const T hz = T(0.5) * T(kC1) * dx;
-        const T sc = (absT(hz) < T(1e-6)) ? T(1) - hz * hz * T(1.0 / 6.0) : sin(hz) / hz;
-        return cos(T(kC1) * m) * sc;
+        const T z = T(kC1) * m;
+        T sc;
+        if (absT(hz) < T(0.25)) {
+            const T h2 = hz * hz;
+            sc = T(1) + h2 * (T(-1.0 / 6) + h2 * (T(1.0 / 120) + h2 * (T(-1.0 / 5040) + h2 * (T(1.0 / 362880) +
+                 h2 * (T(-1.0 / 39916800) + h2 * (T(1.0 / 6227020800.0) + h2 * T(-1.0 / 1307674368000.0)))))));
+        } else {
+            sc = sin(hz) / hz;
+        }
+        const T z2 = z * z;
+        const T cz = T(1) + z2 * (T(-1.0 / 2) + z2 * (T(1.0 / 24) + z2 * (T(-1.0 / 720) + z2 * (T(1.0 / 40320) +
+                     z2 * (T(-1.0 / 3628800) + z2 * (T(1.0 / 479001600.0) + z2 * (T(-1.0 / 87178291200.0) +
+                     z2 * (T(1.0 / 20922789888000.0) + z2 * (T(-1.0 / 6402373705728000.0) +
+                     z2 * T(1.0 / 2432902008176640000.0))))))))));
+        return cz * sc;
     }
     if (br == 1) {
         const T ea = absT(a.e), eb = absT(b.e);
@@ -1044,11 +1075,6 @@ SX_FN D2 xf_apply(const float* X, float x, float y) {
     return d2((double)X[0] * x + (double)X[2] * y + (double)X[4], (double)X[1] * x + (double)X[3] * y + (double)X[5]);
 }
 
-SX_FN D2 first_nonzero(const D2* c, int n) {
-    for (int i = 0; i < n; i++)
-        if (!is_zero(c[i])) return c[i];
-    return d2(1.0, 0.0);
-}
 
 struct SceneView {
     const uint8_t* tags;
@@ -1109,33 +1135,42 @@ SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s
     const float2* D = sv.pts + off;
     const int c = tag & kTagCount;
     ti.line = c == 1;
-    float2 r[4];
-    for (int j = 0; j <= c; j++) r[j] = D[j];
+    // the segment's c + 1 points, loaded without a runtime-indexed array
+    // (indices clamped to the segment, so every load stays in it)
+    const float2 r0 = D[0], r1 = D[1], r2 = D[c >= 2 ? 2 : 1], r3 = D[c >= 3 ? 3 : c];
+    const float2 rc = (c == 1) ? r1 : ((c == 2) ? r2 : r3);
     s.w = ti.w;
-    s.P0w = xf_apply(X, r[0].x, r[0].y);
-    s.P3w = xf_apply(X, r[c].x, r[c].y);
-    D2 e[3];  // transformed differences r_j - r_0
-    for (int j = 0; j < c; j++) e[j] = xf_vec(X, (double)r[j + 1].x - r[0].x, (double)r[j + 1].y - r[0].y);
+    s.P0w = xf_apply(X, r0.x, r0.y);
+    s.P3w = xf_apply(X, rc.x, rc.y);
+    // transformed differences r_j - r_0
+    const D2 e0 = xf_vec(X, (double)r1.x - r0.x, (double)r1.y - r0.y);
+    const D2 e1 = xf_vec(X, (double)r2.x - r0.x, (double)r2.y - r0.y);
+    const D2 e2 = xf_vec(X, (double)r3.x - r0.x, (double)r3.y - r0.y);
     if (c == 1) {
-        s.D1 = e[0] * (1.0 / 3.0);
-        s.D2_ = e[0] * (2.0 / 3.0);
-        s.D3 = e[0];
+        s.D1 = e0 * (1.0 / 3.0);
+        s.D2_ = e0 * (2.0 / 3.0);
+        s.D3 = e0;
     } else if (c == 2) {
-        s.D1 = e[0] * (2.0 / 3.0);
-        s.D2_ = e[1] + (e[0] - e[1]) * (2.0 / 3.0);
-        s.D3 = e[1];
+        s.D1 = e0 * (2.0 / 3.0);
+        s.D2_ = e1 + (e0 - e1) * (2.0 / 3.0);
+        s.D3 = e1;
     } else {
-        s.D1 = e[0];
-        s.D2_ = e[1];
-        s.D3 = e[2];
+        s.D1 = e0;
+        s.D2_ = e1;
+        s.D3 = e2;
     }
     s.A2 = s.D2_ - s.D1 * 2.0;
     s.B2 = s.D3 - s.D2_ * 2.0 + s.D1;
     s.C3 = s.D3 - s.D2_ * 3.0 + s.D1 * 3.0;
-    D2 ce[3];
-    for (int j = 0; j < c; j++) ce[j] = xf_vec(X, (double)r[c].x - r[c - 1 - j].x, (double)r[c].y - r[c - 1 - j].y);
-    s.ts = first_nonzero(e, c);
-    s.te = first_nonzero(ce, c);
+    // end tangents: the first nonzero difference from each end (r_c - r_{c-1-j})
+    const float2 q0 = (c == 1) ? r0 : ((c == 2) ? r1 : r2);  // r_{c-1}
+    const float2 q1 = (c == 2) ? r0 : r1;                    // r_{c-2}
+    const D2 ce0 = xf_vec(X, (double)rc.x - q0.x, (double)rc.y - q0.y);
+    const D2 ce1 = xf_vec(X, (double)rc.x - q1.x, (double)rc.y - q1.y);
+    const D2 ce2 = xf_vec(X, (double)rc.x - r0.x, (double)rc.y - r0.y);
+    const D2 one = d2(1.0, 0.0);
+    s.ts = !is_zero(e0) ? e0 : (c >= 2 && !is_zero(e1)) ? e1 : (c >= 3 && !is_zero(e2)) ? e2 : one;
+    s.te = !is_zero(ce0) ? ce0 : (c >= 2 && !is_zero(ce1)) ? ce1 : (c >= 3 && !is_zero(ce2)) ? ce2 : one;
     s.lpoly = len(s.D1) + len(s.D2_ - s.D1) + len(s.D3 - s.D2_);
 }
 
@@ -1309,14 +1344,13 @@ SX_HD void emit_tail(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i, c
         tb = xf_vec(X, (double)bb.x - a.x, (double)bb.y - a.y);
         if (is_zero(tb)) tb = d2(1.0, 0.0);
     } else {
+        // the next segment's start tangent: its first nonzero difference
         const int cn = nt & kTagCount;
-        const float2 r0 = Dn[0];
-        D2 cands[3];
-        for (int j = 0; j < cn; j++) {
-            const float2 q = Dn[j + 1];
-            cands[j] = xf_vec(X, (double)q.x - r0.x, (double)q.y - r0.y);
-        }
-        tb = first_nonzero(cands, cn);
+        const float2 r0 = Dn[0], r1 = Dn[1], r2 = Dn[cn >= 2 ? 2 : 1], r3 = Dn[cn >= 3 ? 3 : cn];
+        const D2 c0 = xf_vec(X, (double)r1.x - r0.x, (double)r1.y - r0.y);
+        const D2 c1 = xf_vec(X, (double)r2.x - r0.x, (double)r2.y - r0.y);
+        const D2 c2 = xf_vec(X, (double)r3.x - r0.x, (double)r3.y - r0.y);
+        tb = !is_zero(c0) ? c0 : (cn >= 2 && !is_zero(c1)) ? c1 : (cn >= 3 && !is_zero(c2)) ? c2 : d2(1.0, 0.0);
     }
     emit_join(k, cfg, ti.join, (double)ti.miter, pend, s.te, tb, ti.w);
 }

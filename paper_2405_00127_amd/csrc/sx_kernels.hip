@@ -732,6 +732,8 @@ static void bisect_launch(uint32_t g, hipStream_t s, int waves, const SceneView&
                           unsigned long long* stats) {
     if (waves <= 2)
         bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
+    else if (waves == 3)
+        bisect_kernel<Write, Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
     else
         bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
 }
