@@ -45,11 +45,12 @@ struct sx_scene {
     void* d_status_nslots = nullptr;
     void* d_status_rc = nullptr;
     // item workspace of the slot / record kernels
-    sx::Item* d_items = nullptr;
+    sx::Unit* d_items = nullptr;
+    float* d_es = nullptr;  // per-slot spiral records
     uint32_t* d_tile_n = nullptr;
     sx::WsCtl* d_ws_ctl = nullptr;
-    uint32_t region_per_slot = 0;  // items per slot in the per-tile regions
-    uint64_t ovf_cap = 0;          // shared overflow items
+    uint32_t region_per_slot = 0;  // item units per slot in the per-tile regions
+    uint64_t ovf_cap = 0;          // shared overflow units
     uint64_t slot_cap = 0;         // slots the slot buffers hold
     // allocated capacities (a batch arena is reused for smaller contents)
     uint32_t cap_tags = 0, cap_pts = 0, cap_styles = 0, cap_xforms = 0, cap_paths = 0;
@@ -71,9 +72,9 @@ namespace {
 
 constexpr uint32_t kMaxBatchScenes = 65535;
 constexpr uint32_t kSlotsPerTag = 4;        // initial slot capacity per tag
-constexpr uint32_t kRegionPerSlot = 3;      // initial items per slot in the tile regions
+constexpr uint32_t kRegionPerSlot = 3;      // initial item units per slot in the tile regions
 constexpr uint64_t kMinSlots = 4096;
-constexpr uint64_t kMinOverflow = 65536;    // initial shared overflow items (minimum)
+constexpr uint64_t kMinOverflow = 65536;    // initial shared overflow units (minimum)
 constexpr uint32_t kMaxSlotCap = 0xfffff000u;  // slots are indexed by u32
 
 int fail(sx_ctx* ctx, int code, const std::string& msg) {
@@ -114,6 +115,7 @@ void free_scene(sx_scene* s) {
     dfree(s->d_status_nslots);
     dfree(s->d_status_rc);
     dfree(s->d_items);
+    dfree(s->d_es);
     dfree(s->d_tile_n);
     dfree(s->d_ws_ctl);
     delete s;
@@ -146,7 +148,8 @@ sx::SceneView view(const sx_scene* s) {
 
 sx::ItemWs workspace(const sx_scene* s) {
     sx::ItemWs w;
-    w.items = s->d_items;
+    w.units = s->d_items;
+    w.es_tab = s->d_es;
     w.tile_n = s->d_tile_n;
     w.ctl = s->d_ws_ctl;
     w.tile = sx::slot_block();
@@ -159,7 +162,8 @@ sx::ItemWs workspace(const sx_scene* s) {
 char* ctl_block(const sx_scene* s, int k) { return (char*)s->d_scan_ctl + k * sx::scan_ctl_bytes(); }
 
 // (Re)allocate the slot buffers for slot_cap slots and the item workspace
-// (region_per_slot items per slot in the tile regions, ovf shared items).
+// (region_per_slot 64-byte units per slot in the tile regions, ovf shared
+// units).
 // Scan status words are zeroed when allocated.  Ordered on st; allocation is
 // synchronous.
 hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_slot, uint64_t ovf, hipStream_t st) {
@@ -173,7 +177,9 @@ hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_slot, 
         dfree(s->d_roff);
         dfree(s->d_status_rc);
         dfree(s->d_tile_n);
+        dfree(s->d_es);
         A(dalloc(&s->d_slots, slot_cap * sizeof(sx::Slot)));
+        A(dalloc(&s->d_es, slot_cap * 8 * sizeof(float)));
         A(dalloc(&s->d_rc, (slot_cap + 16) * sizeof(uint32_t)));
         A(dalloc(&s->d_roff, (slot_cap + 1) * sizeof(uint64_t)));
         A(dalloc(&s->d_status_rc, sx::scan_status_bytes((uint32_t)slot_cap)));
@@ -186,7 +192,7 @@ hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_slot, 
     s->region_per_slot = region_per_slot;
     s->ovf_cap = ovf;
     const uint64_t items = (uint64_t)sx::slot_tiles(slot_cap) * sx::slot_block() * region_per_slot + ovf;
-    return dalloc(&s->d_items, items * sizeof(sx::Item));
+    return dalloc(&s->d_items, items * sizeof(sx::Unit));
 }
 
 // Grow the scene's device buffers to hold at least the given sizes (the

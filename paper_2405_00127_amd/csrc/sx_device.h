@@ -476,63 +476,64 @@ constexpr uint32_t kIfKSame = 1u << 13;       // offset, h == 0: curvature keeps
 enum { kOutLine1 = 0, kOutLine2 = 1, kOutLine3 = 2, kOutRound = 3 };
 enum { kInNone = 0, kInPivot = 1, kInSmooth = 2 };
 
-struct __align__(16) Item {
+// Items live in 64-byte units.  Offset items take one unit; evolute, join
+// and cap items two (their payload keeps word 16 at zero, so a scan over
+// units reads the second unit as an empty slot).  The Euler spiral of a
+// piece is stored once per slot (the slot's ES record), not per item.
+constexpr uint32_t kUnitWords = 16;
+struct __align__(16) Unit {
+    uint32_t w[kUnitWords];
+};
+struct ItemHdr {
     uint32_t hdr;    // kind | flags | outer kind << 16 | inner kind << 20 | records in this chunk << 24
     uint32_t tag;    // tag index (for the path id)
     uint32_t slot;   // slot index (canonical position of the piece or tail)
     uint32_t local;  // record offset of this chunk within the slot
     uint32_t k0;     // first record of the chunk within the whole item
     uint32_t ntot;   // records of the whole item
-    uint32_t u[26];  // payload (floats / doubles by kind)
 };
+constexpr uint32_t kHdrWords = 6;
 SX_FN uint32_t item_n(uint32_t hdr) { return hdr >> 24; }
-static_assert(sizeof(Item) == 128, "item layout");
 
-// offset-item payload.  es: p0, (chord / Z(1)) or (p1 - p0) for a pivot,
-// k0, k1, L, base angle.
+// offset-item payload: the range [ua, ub] of side h, its exact end points,
+// and for density placement the F increment over the range and the FP32 sum
+// of its branch pieces' x lengths (from the FP64 count)
 struct OffsetP {
-    float es[8];
     float ua, du, ub, fh;
     float Pax, Pay, Pbx, Pby;
-    float dxs;                  // FP32 sum of the branch piece lengths (density placement)
-    uint32_t pad;
-    double hka, hkb, dx, dF;    // density axis: h kappa at the ends, x length, F increment
+    float dF, dxs;
 };
-// h = 0 placement keeps the normalised end curvatures in the hka slot
-struct KnPair {
-    float kna, knb;
-};
-// evolute-item payload
+// evolute-item payload: the range, its density split alpha and evolute
+// count, the exact offset and evolute end points
 struct EvoluteP {
-    float es[8];
     float ua, du, alpha;
     uint32_t ne;
-    float E0x, E0y, E1x, E1y, Pax, Pay, Pbx, Pby;
+    float Pax, Pay, Pbx, Pby;
+    float E0x, E0y;
+    uint32_t zero;  // word 16 of the item
+    float E1x, E1y;
 };
-// join-item payload
+// join- and cap-item payload: the outer part's end points (exact offsets,
+// shared with the adjacent sides), the inner part, the join point and the
+// round or miter / square geometry
 struct JoinP {
-    float fromx, fromy, tox, toy, ax, ay, bx, by;  // outer part points
-    float cx, cy, a0, sweep, w;                    // round part
-    float fx, fy, px, py, tx, ty;                  // inner part (pivot: f -> p -> t; smooth: f -> t)
+    float fromx, fromy, tox, toy;
+    float fx, fy, tx, ty;  // inner part (pivot: f -> p -> t; smooth: f -> t)
+    float px, py;          // join / cap point (round centre)
+    uint32_t zero;         // word 16 of the item
+    float a0, sweep, w;    // round part
+    float ax, ay, bx, by;  // miter point / square corners
     uint32_t n_outer;
 };
-static_assert(sizeof(OffsetP) <= 26 * 4 && sizeof(EvoluteP) <= 26 * 4 && sizeof(JoinP) <= 26 * 4, "payload size");
+template <class P>
+struct Units {
+    static constexpr uint32_t n = (kHdrWords + (uint32_t)(sizeof(P) / 4) + kUnitWords - 1) / kUnitWords;
+};
+static_assert(Units<OffsetP>::n == 1 && Units<EvoluteP>::n == 2 && Units<JoinP>::n == 2, "item units");
+static_assert(offsetof(EvoluteP, zero) == (kUnitWords - kHdrWords) * 4 && offsetof(JoinP, zero) == (kUnitWords - kHdrWords) * 4,
+              "second unit starts with a zero word");
 
 SX_FN uint32_t chunks(uint32_t n, uint32_t K) { return (n + K - 1) / K; }
-
-// 128-byte item copy as eight 16-byte moves
-SX_FN void store_item(Item* dst, const Item& src) {
-    const uint4* s4 = reinterpret_cast<const uint4*>(&src);
-    uint4* d4 = reinterpret_cast<uint4*>(dst);
-#pragma unroll
-    for (int j = 0; j < 8; j++) d4[j] = s4[j];
-}
-SX_FN void load_item(Item& dst, const Item* src) {
-    const uint4* s4 = reinterpret_cast<const uint4*>(src);
-    uint4* d4 = reinterpret_cast<uint4*>(&dst);
-#pragma unroll
-    for (int j = 0; j < 8; j++) d4[j] = s4[j];
-}
 
 struct Cfg {
     double tau_fit, tau_flat, inv_sqrt8tf;  // sqrt(1 / (8 tau_flat))
@@ -551,7 +552,8 @@ struct Cfg {
 enum { kStTrials = 0, kStPieces = 1, kStRanges = 2, kStEvolutes = 3, kStJoins = 4, kStLines = 5, kStN = 6 };
 template <class Alloc, bool Stats = false>
 struct ItemSink {
-    Item* items;
+    Unit* units;
+    float* es_tab;  // 8 floats per slot
     Alloc al;
     uint32_t tag, slot;
     uint32_t n;  // records of the slot so far
@@ -563,15 +565,16 @@ struct ItemSink {
             const uint32_t kind = hdr & 15u;
             st[kind == kItemOffset ? kStRanges : (kind == kItemEvolute ? kStEvolutes : kStJoins)]++;
         }
+        constexpr uint32_t U = Units<P>::n;
         const uint32_t nc = chunks(nrec, K);
-        const uint64_t base = al.alloc(nc);
+        const uint64_t base = al.alloc(nc * U);
         if (base != ~0ull) {
             for (uint32_t c = 0; c < nc; c++) {
-                Item* dst = items + base + c;
+                uint32_t* dst = units[base + (uint64_t)c * U].w;
                 const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
                 *reinterpret_cast<uint4*>(dst) = make_uint4(hdr | (nchunk << 24), tag, slot, n + c * K);
-                *reinterpret_cast<uint2*>(&dst->k0) = make_uint2(c * K, nrec);
-                *reinterpret_cast<P*>(dst->u) = p;
+                *reinterpret_cast<uint2*>(dst + 4) = make_uint2(c * K, nrec);
+                *reinterpret_cast<P*>(dst + kHdrWords) = p;
             }
         }
         n += nrec;
@@ -642,15 +645,8 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
     }
     {
         OffsetP p;
-        set_es_f(es, p.es);
-        p.hka = hka; p.hkb = hkb; p.dx = dx; p.dF = dF;
-        p.dxs = dxs;
-        p.pad = 0u;
-        if (place & kIfPlaceES) {
-            KnPair kp{(float)kna, (float)knb};
-            memcpy(&p.hka, &kp, sizeof(kp));
-        }
         p.ua = (float)ua; p.du = (float)du; p.ub = (float)ub; p.fh = (float)h;
+        p.dF = (float)dF; p.dxs = dxs;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
         uint32_t hdr = kItemOffset | (dir < 0 ? kIfDirNeg : 0u) | (cfg.arcs ? kIfArcs : 0u) |
                        (es.pivot ? kIfPivot : 0u) | place;
@@ -658,23 +654,20 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
     }
     if (reversed) {
         EvoluteP p;
-        set_es_f(es, p.es);
         p.ua = (float)ua; p.du = (float)du;
         p.alpha = (ra + rb > 0.0) ? (float)(ra / (ra + rb)) : 0.5f;
         p.ne = ne;
-        V2 E0 = end_a_piece ? evolute_end(es, ua == 1.0) : Pa;
-        V2 E1 = end_b_piece ? evolute_end(es, ub == 1.0) : Pb;
+        const V2 E0 = end_a_piece ? evolute_end(es, ua == 1.0) : Pa;
+        const V2 E1 = end_b_piece ? evolute_end(es, ub == 1.0) : Pb;
         p.E0x = E0.x; p.E0y = E0.y; p.E1x = E1.x; p.E1y = E1.y;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
+        p.zero = 0u;
         uint32_t hdr = kItemEvolute | (D < 0 ? kIfDneg : 0u) | (es.pivot ? kIfPivot : 0u) |
                        (end_a_piece ? kIfEndA : 0u) | (end_b_piece ? kIfEndB : 0u);
         k.put(hdr, 2u * ne + 2u * nconn, cfg.K, p);
     }
 }
 
-// Both sides of one piece: side A (h = +w) then side B (h = -w); a side
-// whose rho changes sign inside the piece is split at the parallel-curve cusp
-// into two ranges (Section 6).  One emit_range call site keeps the code small.
 template <class Sink>
 SX_FN void emit_sides(Sink& k, const Cfg& cfg, const ES& es, double w) {
     for (int side = 0; side < 2; side++) {
@@ -725,6 +718,8 @@ SX_HD void emit_cap(Sink& k, const Cfg& cfg, int cap, D2 p, D2 u, double w, bool
     JoinP jp = {};
     V2 f = f32(from), t = f32(to);
     jp.fromx = f.x; jp.fromy = f.y; jp.tox = t.x; jp.toy = t.y;
+    const V2 fpc = f32(p);
+    jp.px = fpc.x; jp.py = fpc.y;
     if (cap == kCapButt) {
         put_join(k, cfg, kOutLine1, kInNone, false, jp);
     } else if (cap == kCapSquare) {
@@ -733,8 +728,7 @@ SX_HD void emit_cap(Sink& k, const Cfg& cfg, int cap, D2 p, D2 u, double w, bool
         put_join(k, cfg, kOutLine3, kInNone, false, jp);
     } else {
         double a0 = atan2(from.y - p.y, from.x - p.x);
-        V2 c = f32(p);
-        jp.cx = c.x; jp.cy = c.y; jp.a0 = (float)a0; jp.sweep = (float)kPi; jp.w = (float)w;
+        jp.a0 = (float)a0; jp.sweep = (float)kPi; jp.w = (float)w;
         jp.n_outer = round_count(cfg, w, kPi);
         put_join(k, cfg, kOutRound, kInNone, false, jp);
     }
@@ -767,7 +761,7 @@ SX_HD void emit_join(Sink& k, const Cfg& cfg, int join, double miter_limit, D2 p
     if (join == kJoinRound) {
         double dphi = atan2(cr, dp);
         double a0 = atan2(from.y - p.y, from.x - p.x);
-        jp.cx = fp.x; jp.cy = fp.y; jp.a0 = (float)a0; jp.sweep = (float)fabs(dphi); jp.w = (float)w;
+        jp.a0 = (float)a0; jp.sweep = (float)fabs(dphi); jp.w = (float)w;
         jp.n_outer = round_count(cfg, w, fabs(dphi));
         outer = kOutRound;
     } else if (join == kJoinMiter) {
@@ -826,19 +820,48 @@ SX_FN ES es_from_f(const float* d, bool pivot) {
 // share of F only moves forward; the pieces are produced one at a time.
 struct XWalk {
     XPT<float> xa, xb;
-    float dx, cum;
+    float dx, cum, dF, dxs;
     XSegT<float> seg;
     int j, nseg;
     float acc_len;
 };
 
+// Point placement data of an offset range, from the piece's FP32 spiral:
+// the density axis of side h (the counts were decided in FP64; here the
+// points only have to follow the same density), or the h = 0 curvatures.
+struct Place {
+    XWalk w;
+    float kna, knb;
+};
+SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t hdr) {
+    pl.kna = es.fk0 + es.fk1 * (p.ua - 0.5f);
+    pl.knb = es.fk0 + es.fk1 * (p.ub - 0.5f);
+    XWalk& w = pl.w;
+    w.j = 0;
+    w.nseg = 1;
+    w.cum = 0.0f;
+    w.acc_len = 0.0f;
+    w.dF = 0.0f;
+    w.dxs = 0.0f;
+    if (hdr & kIfPlaceF) {
+        w.xa = make_xp(p.fh * pl.kna / es.fL);
+        w.xb = make_xp(p.fh * pl.knb / es.fL);
+        w.dx = -2.0f * p.fh * es.fk1 * p.du / es.fL;
+        w.dF = p.dF;
+        w.dxs = p.dxs;
+        w.nseg = xseg_count(w.xa, w.xb);
+        w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
+    }
+}
+
 // u of point i (0 < i < n) of an offset range
-SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, XWalk& w) {
-    float f = (float)i / (float)n;
+SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, Place& pl) {
+    const float f = (float)i / (float)n;
     float tau = f;
     if (hdr & kIfPlaceF) {
         // advance to the branch piece holding f * dF
-        const float target = f * (float)p.dF;
+        XWalk& w = pl.w;
+        const float target = f * w.dF;
         while (w.j < w.nseg - 1 && !(fabsf(w.cum + w.seg.dF) >= fabsf(target))) {
             w.cum += w.seg.dF;
             w.acc_len += w.seg.len;
@@ -848,26 +871,24 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
         float fl = (w.seg.dF != 0.0f) ? (target - w.cum) / w.seg.dF : 0.0f;
         fl = fminf(fmaxf(fl, 0.0f), 1.0f);
         const float phi = (w.seg.len != 0.0f) ? branch_inv_frac(w.seg, fl) : fl;
-        tau = (w.nseg == 1) ? phi : (w.acc_len + phi * w.seg.len) / p.dxs;
+        tau = (w.nseg == 1) ? phi : (w.acc_len + phi * w.seg.len) / w.dxs;
     } else if (hdr & kIfPlaceES) {
         // h = 0: uniform in |kappa|^1.5 (Section 2.2)
-        KnPair kp;
-        memcpy(&kp, &p.hka, sizeof(kp));
-        float aa = fabsf(kp.kna), ab = fabsf(kp.knb);
-        float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
+        const float aa = fabsf(pl.kna), ab = fabsf(pl.knb);
+        const float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
         float kap;
         if (hdr & kIfKSame) {
-            float P15 = Pa15 + f * (Pb15 - Pa15);
+            const float P15 = Pa15 + f * (Pb15 - Pa15);
             kap = cbrtf(P15 * P15);
             tau = (ab != aa) ? (kap - aa) / (ab - aa) : f;
         } else {
-            float target = f * (Pa15 + Pb15);
+            const float target = f * (Pa15 + Pb15);
             if (target <= Pa15) {
-                float t15 = Pa15 - target;
+                const float t15 = Pa15 - target;
                 kap = cbrtf(t15 * t15);
                 tau = (aa - kap) / (aa + ab);
             } else {
-                float t15 = target - Pa15;
+                const float t15 = target - Pa15;
                 kap = cbrtf(t15 * t15);
                 tau = (aa + kap) / (aa + ab);
             }
@@ -877,116 +898,104 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
     return p.ua + p.du * tau;
 }
 
-SX_HD inline void emit_item(const Item& it, RecOut& o) {
-    const uint32_t kind = it.hdr & 15u;
-    const uint32_t hdr = it.hdr;
+// One item chunk (header + payload words) into records; es: the slot's
+// spiral (8 floats) for offset and evolute items.
+SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) {
+    const ItemHdr h = *reinterpret_cast<const ItemHdr*>(it);
+    const uint32_t* pw = it + kHdrWords;
+    const uint32_t hdr = h.hdr;
+    const uint32_t kind = hdr & 15u;
+    const uint32_t nrec = item_n(hdr);
     const bool arcs = (hdr & kIfArcs) != 0;
     if (kind == kItemOffset) {
-        OffsetP p;
-        memcpy(&p, it.u, sizeof(p));
-        ES es = es_from_f(p.es, (hdr & kIfPivot) != 0);
-        XWalk w;
-        w.j = 0;
-        w.nseg = 1;
-        w.cum = 0.0f;
-        w.acc_len = 0.0f;
-        if (hdr & kIfPlaceF) {
-            // x and e from FP64 (e keeps its relative precision next to the cusp)
-            const XP xa = make_xp(p.hka), xb = make_xp(p.hkb);
-            w.xa = XPT<float>{(float)xa.x, (float)xa.e};
-            w.xb = XPT<float>{(float)xb.x, (float)xb.e};
-            w.dx = (float)p.dx;
-            w.nseg = xseg_count(w.xa, w.xb);
-            w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
-        }
-        const uint32_t n = it.ntot;
+        const OffsetP p = *reinterpret_cast<const OffsetP*>(pw);
+        const ES es = es_from_f(es_rec, (hdr & kIfPivot) != 0);
+        Place pl;
+        place_init(pl, es, p, hdr);
+        const uint32_t n = h.ntot;
         const bool neg = (hdr & kIfDirNeg) != 0;
         // point k0 of the chunk
         float uprev;
         V2 prev;
-        if (it.k0 == 0) {
+        if (h.k0 == 0) {
             uprev = p.ua;
             prev = v2(p.Pax, p.Pay);
         } else {
-            uprev = offset_u(p, hdr, it.k0, n, w);
+            uprev = offset_u(p, hdr, h.k0, n, pl);
             prev = offset_point_f(es, p.fh, uprev);
         }
-        for (uint32_t r = 0; r < item_n(it.hdr); r++) {
-            uint32_t i = it.k0 + r + 1;
+        for (uint32_t r = 0; r < nrec; r++) {
+            const uint32_t i = h.k0 + r + 1;
             float u;
             V2 P;
             if (i == n) {
                 u = p.ub;
                 P = v2(p.Pbx, p.Pby);
             } else {
-                u = offset_u(p, hdr, i, n, w);
+                u = offset_u(p, hdr, i, n, pl);
                 P = offset_point_f(es, p.fh, u);
             }
             if (!arcs) {
                 if (!neg) o.line(prev, P); else o.line(P, prev);
             } else {
-                float turn = es_phi_f(es.fk0, es.fk1, u) - es_phi_f(es.fk0, es.fk1, uprev);
+                const float turn = es_phi_f(es.fk0, es.fk1, u) - es_phi_f(es.fk0, es.fk1, uprev);
                 if (!neg) o.arc(prev, P, turn); else o.arc(P, prev, -turn);
             }
             prev = P;
             uprev = u;
         }
     } else if (kind == kItemEvolute) {
-        EvoluteP p;
-        memcpy(&p, it.u, sizeof(p));
-        ES es = es_from_f(p.es, (hdr & kIfPivot) != 0);
+        const EvoluteP p = *reinterpret_cast<const EvoluteP*>(pw);
+        const ES es = es_from_f(es_rec, (hdr & kIfPivot) != 0);
         const uint32_t ne = p.ne;
         const bool Dneg = (hdr & kIfDneg) != 0;
         const V2 E0 = v2(p.E0x, p.E0y), E1 = v2(p.E1x, p.E1y), Pa = v2(p.Pax, p.Pay), Pb = v2(p.Pbx, p.Pby);
         auto ev = [&](uint32_t i) -> V2 {
             if (i == 0) return E0;
             if (i == ne) return E1;
-            float f = (float)i / (float)ne;
-            float tau = f * (2.0f * p.alpha + f * (1.0f - 2.0f * p.alpha));
+            const float f = (float)i / (float)ne;
+            const float tau = f * (2.0f * p.alpha + f * (1.0f - 2.0f * p.alpha));
             return evolute_point_f(es, p.ua + p.du * tau);
         };
-        const bool ca = (hdr & kIfEndA) != 0, cb = (hdr & kIfEndB) != 0;
+        const bool ca = (hdr & kIfEndA) != 0;
         V2 cache_a = v2(0.0f, 0.0f);
         uint32_t cache_i = 0xffffffffu;
-        for (uint32_t r = 0; r < item_n(it.hdr); r++) {
-            uint32_t k = it.k0 + r;
+        for (uint32_t r = 0; r < nrec; r++) {
+            const uint32_t k = h.k0 + r;
             if (k < 2u * ne) {
-                uint32_t s = k % ne;  // segment s of copy k / ne
-                V2 A = (cache_i == s) ? cache_a : ev(s);
-                V2 B = ev(s + 1);
+                const uint32_t s = k % ne;  // segment s of copy k / ne
+                const V2 A = (cache_i == s) ? cache_a : ev(s);
+                const V2 B = ev(s + 1);
                 cache_a = B;
                 cache_i = s + 1;
                 if (!Dneg) o.line(A, B); else o.line(B, A);
             } else {
-                uint32_t c = k - 2u * ne;  // connecting lines: 2 at ua (if any), then 2 at ub
-                bool at_a = ca && c < 2u;
-                if (at_a) {
+                const uint32_t c = k - 2u * ne;  // connecting lines: 2 at ua (if any), then 2 at ub
+                if (ca && c < 2u) {
                     if (!Dneg) o.line(Pa, E0); else o.line(E0, Pa);
                 } else {
                     if (!Dneg) o.line(E1, Pb); else o.line(Pb, E1);
                 }
             }
         }
-        (void)cb;
     } else {
-        JoinP p;
-        memcpy(&p, it.u, sizeof(p));
+        const JoinP p = *reinterpret_cast<const JoinP*>(pw);
         const uint32_t outer = (hdr >> 16) & 15u, inner = (hdr >> 20) & 3u;
         const bool inner_first = (hdr & kIfInnerFirst) != 0;
         const uint32_t no = outer_count(outer, p.n_outer), ni = inner_count(inner);
         const V2 from = v2(p.fromx, p.fromy), to = v2(p.tox, p.toy), A = v2(p.ax, p.ay), B = v2(p.bx, p.by);
         const V2 F = v2(p.fx, p.fy), Pp = v2(p.px, p.py), T = v2(p.tx, p.ty);
-        for (uint32_t r = 0; r < item_n(it.hdr); r++) {
-            uint32_t k = it.k0 + r;
-            bool is_inner = inner_first ? (k < ni) : (k >= no);
+        for (uint32_t r = 0; r < nrec; r++) {
+            const uint32_t k = h.k0 + r;
+            const bool is_inner = inner_first ? (k < ni) : (k >= no);
             if (is_inner) {
-                uint32_t j = inner_first ? k : k - no;
+                const uint32_t j = inner_first ? k : k - no;
                 if (inner == kInSmooth) o.line(F, T);
                 else if (j == 0) o.line(F, Pp);
                 else o.line(Pp, T);
                 continue;
             }
-            uint32_t j = inner_first ? k - ni : k;
+            const uint32_t j = inner_first ? k - ni : k;
             if (outer == kOutLine1) {
                 o.line(from, to);
             } else if (outer == kOutLine2) {
@@ -998,12 +1007,12 @@ SX_HD inline void emit_item(const Item& it, RecOut& o) {
                 auto rp = [&](uint32_t q) -> V2 {
                     if (q == 0) return from;
                     if (q == nr) return to;
-                    float a = p.a0 + p.sweep * ((float)q / (float)nr);
+                    const float a = p.a0 + p.sweep * ((float)q / (float)nr);
                     float sn, cs;
                     sincosf(a, &sn, &cs);
-                    return v2(p.cx + p.w * cs, p.cy + p.w * sn);
+                    return v2(p.px + p.w * cs, p.py + p.w * sn);
                 };
-                V2 a = rp(j), b = rp(j + 1);
+                const V2 a = rp(j), b = rp(j + 1);
                 if (arcs) o.arc(a, b, p.sweep / (float)nr); else o.line(a, b);
             }
         }
@@ -1229,7 +1238,7 @@ SX_FN double depth_dt(uint32_t depth) { return 1.0 / (double)(1u << depth); }
 // (its t0_u and depth are reported before the stack pops); *done is set when
 // the segment is fully covered.
 SX_HD inline bool bisect_step(Bisect& b, const Seg& s, const Cfg& cfg, bool line, uint32_t& acc_t0u,
-                              uint32_t& acc_depth, bool& done) {
+                              uint32_t& acc_depth, bool& acc_pivot, bool& done) {
     const double dt = depth_dt(b.depth);
     const double t0 = (double)b.t0_u * dt;
     const double t1 = t0 + dt;
@@ -1241,6 +1250,7 @@ SX_HD inline bool bisect_step(Bisect& b, const Seg& s, const Cfg& cfg, bool line
     if (tr.ok || forced) {
         acc_t0u = b.t0_u;
         acc_depth = b.depth;
+        acc_pivot = !tr.ok;
         // pop: count trailing zeros
         b.t0_u += 1;
         const uint32_t sh = __builtin_ctz(b.t0_u);
@@ -1256,11 +1266,12 @@ SX_HD inline bool bisect_step(Bisect& b, const Seg& s, const Cfg& cfg, bool line
     return false;
 }
 
-// The accepted piece [t0, t0 + 2^-depth] of the segment: the trial again
-// (the same arithmetic as in the bisection, so the same decision), its Euler
-// spiral (Appendix A; a pivot for reading G28) and both parallel-curve sides.
+// The accepted piece [t0, t0 + 2^-depth] of the segment (accepted by the
+// fit, or only at the depth cap: a pivot): the same chord and end angles as
+// in the bisection, its Euler spiral (Appendix A; a pivot for reading G28)
+// and both parallel-curve sides.
 template <class Sink>
-SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth) {
+SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth, bool pivot) {
     const double dt = depth_dt(depth);
     const double t0 = (double)t0_u * dt;
     const double t1 = t0 + dt;
@@ -1268,8 +1279,15 @@ SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t
     const D2 last_qtrue = (t0 == 0.0) ? s.D1 : cubic_q(s, t0);
     const Tan next_q = line ? last_q : sample_q(s, t1);
     const D2 chord = line ? s.D3 : cubic_chord(s, t0, dt, last_qtrue);
-    const Trial tr = trial(s, cfg, line, dt, last_q, next_q, chord);
-    const bool pivot = !tr.ok;
+    Trial tr;
+    tr.chord = chord;
+    tr.cl = len(chord);
+    tr.th0 = 0.0;
+    tr.th1 = 0.0;
+    if (!line && !pivot) {
+        tr.th0 = atan2(cross(last_q.dir, chord), dot(last_q.dir, chord));
+        tr.th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
+    }
     if constexpr (Sink::kStats) k.st[kStPieces]++;
     ES es;
     es.pivot = pivot;
@@ -1311,6 +1329,7 @@ SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t
     es.fk1 = (float)es.k1;
     es.fL = (float)es.L;
     es.fbase = (float)base;
+    set_es_f(es, k.es_tab + 8 * (size_t)k.slot);
     emit_sides(k, cfg, es, s.w);
 }
 
@@ -1358,11 +1377,16 @@ SX_HD void emit_tail(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i, c
 // ------------------------------------------------------------ slots
 // Every tag owns (pieces + 1) consecutive *slots* in canonical order: one
 // per accepted piece in t order, then its tail (join / cap).  A slot code is
-// (t0_u << 5) | depth for a piece, kSlotTail for the tail.
+// (t0_u << 6) | pivot << 5 | depth for a piece, kSlotTail for the tail.
 constexpr uint32_t kSlotTail = 0xffffffffu;
 struct Slot {
     uint32_t tag, code;
 };
-SX_FN uint32_t slot_code(uint32_t t0_u, uint32_t depth) { return (t0_u << 5) | depth; }
+SX_FN uint32_t slot_code(uint32_t t0_u, uint32_t depth, bool pivot) {
+    return (t0_u << 6) | (pivot ? 32u : 0u) | depth;
+}
+SX_FN uint32_t code_t0u(uint32_t code) { return code >> 6; }
+SX_FN uint32_t code_depth(uint32_t code) { return code & 31u; }
+SX_FN bool code_pivot(uint32_t code) { return (code & 32u) != 0u; }
 
 }  // namespace sx

@@ -8,19 +8,21 @@
 namespace sx {
 
 // Item workspace of the slot / record kernels: one region of region_cap
-// items per slot tile, then ovf_cap shared overflow items at ovf_base.
+// 64-byte units per slot tile, then ovf_cap shared overflow units at
+// ovf_base; and the per-slot spiral records (8 floats per slot).
 struct WsCtl {
-    unsigned long long ovf_n;        // overflow items requested
-    unsigned long long items_total;  // items requested by all tiles
+    unsigned long long ovf_n;        // overflow units requested
+    unsigned long long items_total;  // units requested by all tiles
     unsigned long long slots_total;  // slots of the last expansion
     unsigned long long result[2];    // records and status, for synchronous readback
 };
 struct ItemWs {
-    Item* items;
-    uint32_t* tile_n;  // per slot tile: items requested (clamp to region_cap)
+    Unit* units;
+    float* es_tab;
+    uint32_t* tile_n;  // per slot tile: units requested (clamp to region_cap)
     WsCtl* ctl;
     uint32_t tile;        // slots per tile
-    uint32_t region_cap;  // items per tile
+    uint32_t region_cap;  // units per tile
     uint64_t ovf_base, ovf_cap;
 };
 

@@ -422,17 +422,17 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
         if (__ballot(busy) == 0ull) break;
         if (busy) {
             uint32_t t0u = 0, depth = 0;
-            bool done = false;
+            bool done = false, pivot = false;
             if (Stats) {
                 if (ti.line) n_lines++;
                 else n_trials++;
             }
-            if (bisect_step(bs, s, cfg, ti.line, t0u, depth, done)) {
+            if (bisect_step(bs, s, cfg, ti.line, t0u, depth, pivot, done)) {
                 if (Write) {
                     const uint64_t at = bi + seq;
-                    if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth)};
+                    if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth, pivot)};
                 } else if (seq < (uint32_t)kKeepCodes) {
-                    codes[(size_t)i * kKeepCodes + seq] = slot_code(t0u, depth);
+                    codes[(size_t)i * kKeepCodes + seq] = slot_code(t0u, depth, pivot);
                 }
                 seq++;
                 if (done) {
@@ -463,7 +463,7 @@ constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the over
 // Slot allocator of one slot tile: the tile's own region first (LDS
 // counter), then the shared overflow region (global counter).
 struct TileAlloc {
-    Item* items;
+    Unit* units;
     uint32_t* lds_n;
     uint64_t region;
     uint32_t region_cap;
@@ -473,7 +473,7 @@ struct TileAlloc {
         uint32_t s = atomicAdd(lds_n, nc);
         if (s + nc <= region_cap) return region + s;
         // the part of the request inside the region is left empty
-        for (uint32_t j = s; j < region_cap; j++) items[region + j].hdr = 0u;
+        for (uint32_t j = s; j < region_cap; j++) units[region + j].w[0] = 0u;
         unsigned long long o = atomicAdd(ovf_n, (unsigned long long)nc);
         if (o + nc <= ovf_cap) return ovf_base + o;
         return ~0ull;
@@ -529,10 +529,11 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         const uint64_t j = first + s_order[t];
         if (j < n_slots) {
             const Slot sl = slots[j];
-            TileAlloc al{ws.items, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
+            TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
                          ws.ovf_cap};
             ItemSink<TileAlloc, Stats> k;
-            k.items = ws.items;
+            k.units = ws.units;
+            k.es_tab = ws.es_tab;
             k.al = al;
             k.tag = sl.tag;
             k.slot = (uint32_t)j;
@@ -544,7 +545,8 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                 Seg sg;
                 fetch_tag(sv, sl.tag, ti, sg);
                 if (sl.code == kSlotTail) emit_tail(k, cfg, sv, sl.tag, ti, sg);
-                else if (ti.kind == kTagSegment) emit_piece(k, cfg, sg, ti.line, sl.code >> 5, sl.code & 31u);
+                else if (ti.kind == kTagSegment)
+                    emit_piece(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code));
             }
             rc[j] = k.n;
             if (Stats)
@@ -564,24 +566,38 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
 }
 
 // Record-kernel item classes: offset ranges placed by the density inverse,
-// other offset ranges, evolute bundles, joins and caps (and empty slots).
-constexpr uint32_t kItemClasses = 4;
+// other offset ranges, evolute bundles, joins and caps, empty units (second
+// units of two-unit items, holes).
+constexpr uint32_t kItemClasses = 5;
 __device__ __forceinline__ uint32_t item_class(uint32_t hdr) {
     const uint32_t kind = hdr & 15u;
+    if (kind == 0u) return 4u;
     if (kind == kItemOffset) return (hdr & kIfPlaceF) ? 0u : 1u;
     return kind == kItemEvolute ? 2u : 3u;
 }
 
-__device__ __forceinline__ void record_item(const SceneView& sv, const Item* slot, const uint64_t* roff,
-                                            uint64_t n_slots, float* out, uint64_t cap, int arcs) {
-    Item it;
-    load_item(it, slot);
-    if ((it.hdr & 15u) == 0u || it.slot >= n_slots || it.tag >= sv.n_tags) return;
-    const uint32_t pi = sv.mon[(size_t)sv.n_tags + it.tag];
+// One item chunk starting at unit u: loads its one or two units and writes
+// its records.
+__device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& ws, const Unit* u,
+                                            const uint64_t* roff, uint64_t n_slots, float* out, uint64_t cap,
+                                            int arcs) {
+    uint32_t w[2 * kUnitWords];
+    const uint4* src = reinterpret_cast<const uint4*>(u);
+#pragma unroll
+    for (int j = 0; j < 4; j++) reinterpret_cast<uint4*>(w)[j] = src[j];
+    const uint32_t kind = w[0] & 15u;
+    if (kind == 0u) return;
+    if (kind != kItemOffset) {
+#pragma unroll
+        for (int j = 4; j < 8; j++) reinterpret_cast<uint4*>(w)[j] = src[j];
+    }
+    const uint32_t tag = w[1], slot = w[2];
+    if (slot >= n_slots || tag >= sv.n_tags) return;
+    const uint32_t pi = sv.mon[(size_t)sv.n_tags + tag];
     const uint32_t path = pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
-    const uint64_t end = roff[it.slot + 1] < cap ? roff[it.slot + 1] : cap;
-    RecOut o{out, roff[it.slot] + it.local, end, path, arcs};
-    emit_item(it, o);
+    const uint64_t end = roff[slot + 1] < cap ? roff[slot + 1] : cap;
+    RecOut o{out, roff[slot] + w[3], end, path, arcs};
+    emit_item(w, ws.es_tab + 8 * (size_t)slot, o);
 }
 
 // Per item chunk, the FP32 per-point work: records at
@@ -604,9 +620,9 @@ __global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs 
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
         for (uint32_t tile = b; tile < n_tiles; tile += kRecGrid) {
             const uint32_t cnt = ws.tile_n[tile] < ws.region_cap ? ws.tile_n[tile] : ws.region_cap;
-            const Item* base = ws.items + (uint64_t)tile * ws.region_cap;
+            const Unit* base = ws.units + (uint64_t)tile * ws.region_cap;
             for (uint32_t r0 = 0; r0 < cnt; r0 += kRecBlock) {
-                const uint32_t cls = (r0 + t < cnt) ? item_class(base[r0 + t].hdr) : kItemClasses - 1;
+                const uint32_t cls = (r0 + t < cnt) ? item_class(base[r0 + t].w[0]) : kItemClasses - 1;
                 uint32_t rank = 0;
 #pragma unroll
                 for (uint32_t c = 0; c < kItemClasses; c++) {
@@ -622,16 +638,16 @@ __global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs 
                 s_order[pos] = t;
                 __syncthreads();
                 const uint32_t s2 = r0 + s_order[t];
-                if (s2 < cnt) record_item(sv, base + s2, roff, n_slots, out, cap_records, arcs);
+                if (s2 < cnt) record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs);
                 __syncthreads();
             }
         }
     } else {
         const uint64_t cnt = ws.ctl->ovf_n;
-        const Item* base = ws.items + ws.ovf_base;
+        const Unit* base = ws.units + ws.ovf_base;
         for (uint64_t s = (uint64_t)(b - kRecGrid) * kRecBlock + threadIdx.x; s < cnt;
              s += (uint64_t)kOvfBlocks * kRecBlock)
-            record_item(sv, base + s, roff, n_slots, out, cap_records, arcs);
+            record_item(sv, ws, base + s, roff, n_slots, out, cap_records, arcs);
     }
 }
 
