@@ -5,8 +5,10 @@ Headline (``value``): input path segments expanded per second at 0.25 px
 tolerance on the map/CAD-shaped scene (10,000 paths, 1,000,000 segments: 60%
 lines, 15% quads, 25% cubics, mixed joins/caps, lognormal half-widths), line
 output, plain per-scene expansion.  One step = the whole hot path over the
-scene already resident in HBM: tag-monoid scan, piece kernel (per-segment
-decisions, emission items, record counts), count scan, record kernel.
+scene already resident in HBM: tag-monoid scan, bisection count pass, slot
+scan, bisection write pass, piece and tail slot kernels (Euler spirals,
+parallel curves, evolutes, joins and caps as emission items with record
+counts), record-count scan, record kernel.
 
 Beside it, in the same JSON line:
   * ``batched``: 256 map-shaped scenes (log-uniform 100..200k segments) in one
@@ -176,8 +178,9 @@ def plain(args, ctx, B, S, torch, np):
         # algorithmic FP64 flops per launch of each kernel
         "bisect_count": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
         "bisect_write": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
-        "slots": (curve_pieces * FLOPS["piece"] + stats["lines"] * FLOPS["line"] + stats["ranges"] * FLOPS["range"]
-                  + stats["evolutes"] * FLOPS["evolute"] + stats["joins"] * FLOPS["join"]),
+        "pieces": (curve_pieces * FLOPS["piece"] + stats["lines"] * FLOPS["line"] + stats["ranges"] * FLOPS["range"]
+                   + stats["evolutes"] * FLOPS["evolute"]),
+        "tails": stats["joins"] * FLOPS["join"],
         # algorithmic FP32 flops
         "records": n_rec * FLOPS_PER_RECORD[mode],
         # algorithmic bytes
@@ -187,7 +190,7 @@ def plain(args, ctx, B, S, torch, np):
     }
     dom = max(phase_ms, key=phase_ms.get)
     t_dom = phase_ms[dom] * 1e-3
-    if dom in ("bisect_count", "bisect_write", "slots"):
+    if dom in ("bisect_count", "bisect_write", "pieces", "tails"):
         achieved = work[dom] / t_dom / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "precision": "fp64 (decisions)"}
@@ -205,8 +208,8 @@ def plain(args, ctx, B, S, torch, np):
     roof["flops_per_unit"] = FLOPS
     roof["flops_per_record"] = FLOPS_PER_RECORD[mode]
     roof["per_kernel"] = {
-        n: ({"TFLOP/s": work[n] / (phase_ms[n] * 1e-3) / 1e12} if n in ("bisect_count", "bisect_write", "slots",
-                                                                         "records")
+        n: ({"TFLOP/s": work[n] / (phase_ms[n] * 1e-3) / 1e12} if n in ("bisect_count", "bisect_write", "pieces",
+                                                                         "tails", "records")
             else {"GB/s": work[n] / (phase_ms[n] * 1e-3) / 1e9}) for n in names}
     out = {
         "metric": "path segs/s expanded at 0.25px tol (batched vs plain); p50/p99 request latency",
@@ -363,7 +366,99 @@ def served(args, ctx, B, S, torch, np):
     }
 
 
+def kernel_source_hash() -> str:
+    """Hash of the HIP sources: counter readings are tied to the kernels they
+    were taken on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2405_00127_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, mode: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
+    None when the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_map1M_{mode}.json")
+    try:
+        with open(path, "r", encoding="utf-8") as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if data.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def phase_of_kernel(name: str):
+    """Pipeline phase of a rocprofv3 kernel name (None for other kernels and
+    for the launch variants with work counters, which run only to count)."""
+    import re
+
+    simple = (("scan_tags_kernel", "scan_tags"), ("scan_counts_kernel", "scan_slots"),
+              ("scan_counts_dev_kernel", "scan_records"), ("record_kernel", "records"), ("finish_kernel", "finish"))
+    for key, phase in simple:
+        if f"sx::{key}(" in name:
+            return phase
+    m = re.search(r"sx::bisect_kernel<(true|false), (true|false), \d+>", name)
+    if m:
+        return None if m.group(2) == "true" else ("bisect_write" if m.group(1) == "true" else "bisect_count")
+    m = re.search(r"sx::slot_kernel<\d+, (true|false), (true|false)>", name)
+    if m:
+        return None if m.group(1) == "true" else ("tails" if m.group(2) == "true" else "pieces")
+    return None
+
+
+def summarize_counters(fetch_db: str, write_db: str, probe_mb: int, mode: str, commands) -> dict:
+    """Per-launch HBM bytes of each phase from two rocprofv3 --pmc databases
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
+    counter reads for the plain copy of probe_mb MiB that --copy-probe runs
+    (the largest runtime copy kernel of the run)."""
+    import sqlite3
+
+    probe = float(probe_mb << 20)
+    out = {"kernel_source_hash": kernel_source_hash(), "workload": f"map1M_{mode}", "commands": list(commands),
+           "calibration": {"probe_bytes": probe}, "kernels": {}}
+    per = {}
+    for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        con = sqlite3.connect(db)
+        rows = con.execute("select kernel_name, dispatch_id, value from counters_collection where counter_name = ?",
+                           (counter,)).fetchall()
+        con.close()
+        copies = [v for k, _, v in rows if "copyBuffer" in k]
+        if not copies:
+            raise SystemExit(f"{db}: no copy kernel to calibrate {counter} against (run with --copy-probe)")
+        factor = probe / (max(copies) * 1024.0)
+        out["calibration"][counter] = {"copy_kib": max(copies), "factor": factor}
+        for k, d, v in rows:
+            ph = phase_of_kernel(k)
+            if ph is not None:
+                per.setdefault(ph, {}).setdefault(counter, {})[d] = v * 1024.0 * factor
+    for ph, c in per.items():
+        if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
+            f = sum(c["FETCH_SIZE"].values()) / len(c["FETCH_SIZE"])
+            w = sum(c["WRITE_SIZE"].values()) / len(c["WRITE_SIZE"])
+            out["kernels"][ph] = {"fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,
+                                  "dispatches": [len(c["FETCH_SIZE"]), len(c["WRITE_SIZE"])]}
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
+        # offline: bench.py --summarize-counters FETCH_DB WRITE_DB PROBE_MB MODE [COMMAND ...]
+        fetch_db, write_db, probe_mb, mode = sys.argv[2:6]
+        res = summarize_counters(fetch_db, write_db, int(probe_mb), mode, sys.argv[6:])
+        path = os.path.join(ROOT, "profiles", f"traffic_map1M_{mode}.json")
+        with open(path, "w", encoding="utf-8") as f:
+            json.dump(res, f, indent=1)
+        print(json.dumps(res["kernels"], indent=1))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -385,6 +480,9 @@ def main():
     ap.add_argument("--pool", type=int, default=64)
     ap.add_argument("--qps", type=float, nargs="*", default=[100.0, 1000.0, 5000.0])
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="also run one plain device copy of this many MB (a known-size reference for "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -402,7 +500,18 @@ def main():
         PB.build()
     torch.cuda.set_device(0)
     ctx = B.Context(0)
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     out, sc, mode = plain(args, ctx, B, S, torch, np)
+    traffic = measured_traffic(out["roofline"]["kernel"], args.mode)
+    if traffic is not None:
+        out["roofline"]["traffic"] = traffic
     if not args.no_batched:
         out["batched"] = batched(args, ctx, B, S, torch, np)
         log(f"bench: batched {out['batched']}")

@@ -186,9 +186,10 @@ int sx_debug_piece_stats(sx_ctx *ctx, const sx_scene *scene, float tolerance, in
  *   SX_PHASE_BISECT_COUNT  Algorithm 2 per segment: slots per tag (pieces + 1)
  *   SX_PHASE_SCAN_SLOTS    exclusive scan of the slot counts (slot bases)
  *   SX_PHASE_BISECT_WRITE  Algorithm 2 again: each piece's slot at its base
- *   SX_PHASE_SLOTS         per slot: Euler spiral, parallel curves and counts
- *                          (Sections 4-6) or the join / cap (Algorithm 1) as
- *                          emission items, and the slot's record count
+ *   SX_PHASE_PIECES        per piece slot: Euler spiral, parallel curves and
+ *                          counts (Sections 4-6) as emission items, and the
+ *                          slot's record count
+ *   SX_PHASE_TAILS         per tail slot: the join or cap (Algorithm 1)
  *   SX_PHASE_SCAN_RECORDS  exclusive scan of the record counts (offsets)
  *   SX_PHASE_RECORDS       per item, records written at their offsets
  * Run in this order on one stream they equal sx_expand_async without the
@@ -200,9 +201,10 @@ enum {
     SX_PHASE_BISECT_COUNT = 1,
     SX_PHASE_SCAN_SLOTS = 2,
     SX_PHASE_BISECT_WRITE = 3,
-    SX_PHASE_SLOTS = 4,
-    SX_PHASE_SCAN_RECORDS = 5,
-    SX_PHASE_RECORDS = 6
+    SX_PHASE_PIECES = 4,
+    SX_PHASE_TAILS = 5,
+    SX_PHASE_SCAN_RECORDS = 6,
+    SX_PHASE_RECORDS = 7
 };
 int sx_run_phase(sx_ctx *ctx, const sx_scene *scene, int phase, float tolerance, int output_mode, void *out_dev,
                  uint64_t out_capacity_bytes, void *stream);

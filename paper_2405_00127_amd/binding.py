@@ -22,9 +22,10 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "strokex.h")
 
 SX_OK, SX_EINVAL, SX_ENOMEM, SX_EDEVICE, SX_ETOOSMALL, SX_EBUSY = 0, -1, -2, -3, -4, -5
 OUT_LINES, OUT_ARCS = 0, 1
-(PHASE_SCAN_TAGS, PHASE_BISECT_COUNT, PHASE_SCAN_SLOTS, PHASE_BISECT_WRITE, PHASE_SLOTS, PHASE_SCAN_RECORDS,
- PHASE_RECORDS) = range(7)
-PHASE_NAMES = ["scan_tags", "bisect_count", "scan_slots", "bisect_write", "slots", "scan_records", "records"]
+(PHASE_SCAN_TAGS, PHASE_BISECT_COUNT, PHASE_SCAN_SLOTS, PHASE_BISECT_WRITE, PHASE_PIECES, PHASE_TAILS,
+ PHASE_SCAN_RECORDS, PHASE_RECORDS) = range(8)
+PHASE_NAMES = ["scan_tags", "bisect_count", "scan_slots", "bisect_write", "pieces", "tails", "scan_records",
+               "records"]
 RECORD_BYTES = {OUT_LINES: 20, OUT_ARCS: 24}
 
 LINE_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("path", "<u4")])

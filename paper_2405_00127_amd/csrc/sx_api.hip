@@ -274,7 +274,8 @@ bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
 const uint64_t* n_slots_dev(const sx_scene* s) { return s->d_base + s->n_tags; }
 
 // Pipeline phases (each one kernel, in this order on one stream).
-enum { kPhScanTags, kPhBisectCount, kPhScanSlots, kPhBisectWrite, kPhSlots, kPhScanRecords, kPhRecords, kPhN };
+enum { kPhScanTags, kPhBisectCount, kPhScanSlots, kPhBisectWrite, kPhPieces, kPhTails, kPhScanRecords, kPhRecords,
+       kPhN };
 
 hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int ph, void* out, uint64_t cap_records,
                    unsigned long long* stats, hipStream_t st) {
@@ -292,9 +293,10 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
         case kPhBisectWrite:
             return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, true, s->d_nslots,
                                      s->d_codes, s->d_base, s->d_slots, s->slot_cap, nullptr, st);
-        case kPhSlots:
+        case kPhPieces:
+        case kPhTails:
             return sx::launch_slots(view(s), cfg, workspace(s), s->d_slots, n_slots_dev(s), s->slot_cap, s->d_rc,
-                                    (int)t.piece_waves, stats, st);
+                                    (int)t.piece_waves, ph == kPhTails, stats, st);
         case kPhScanRecords:
             return sx::launch_scan_counts_dev(s->d_rc, n_slots_dev(s), (uint32_t)s->slot_cap, s->d_roff,
                                               ctl_block(s, 2), s->d_status_rc, st);
@@ -712,8 +714,8 @@ int sx_debug_piece_stats(sx_ctx* ctx, const sx_scene* s, float tolerance, int ou
     unsigned long long* d = nullptr;
     hipError_t e = hipMalloc((void**)&d, 6 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemsetAsync(d, 0, 6 * sizeof(unsigned long long), st);
-    for (int ph = 0; ph <= kPhSlots && e == hipSuccess; ph++) {
-        const bool counted = ph == kPhBisectCount || ph == kPhSlots;
+    for (int ph = 0; ph <= kPhTails && e == hipSuccess; ph++) {
+        const bool counted = ph == kPhBisectCount || ph == kPhPieces || ph == kPhTails;
         e = run_one(ctx, sc, cfg, ph, nullptr, 0, counted ? d : nullptr, st);
     }
     if (e == hipSuccess) e = hipMemcpyAsync(stats6, d, 6 * sizeof(uint64_t), hipMemcpyDeviceToHost, st);

@@ -210,6 +210,9 @@ struct ES {
     D2 p0, p1, n0, n1;  // exact end points and end normals
     double k0, k1, L;   // curvature params and arc length (px)
     bool pivot;
+    // from the exact ends, rounded once: offset end points of sides A / B
+    // and the evolute's end points (p - N / kappa at u = 0 and 1)
+    V2 P0A, P1A, P0B, P1B, E0, E1;
     // FP32 copies for the per-point work
     V2 fp0, frot, fd;   // world p0, chord / Z(1), p1 - p0 (pivot)
     float fk0, fk1, fL, fbase;
@@ -237,10 +240,20 @@ SX_FN V2 evolute_point_f(const ES& es, float u) {
     return es_point_f(es, u) - es_normal_f(es, u) * (es.fL / kn);
 }
 SX_FN V2 evolute_end(const ES& es, bool at_end) {
-    // exact end points and normals, FP64
+    // exact end points and normals, FP64 (infinite where kappa = 0: only
+    // read on reversed ranges, where kappa is not 0)
     D2 p = at_end ? es.p1 : es.p0, n = at_end ? es.n1 : es.n0;
     double kn = es_kn(es, at_end ? 1.0 : 0.0);
     return f32(p - n * (es.L / kn));
+}
+// the rounded end points of the spiral's sides and evolute (see ES)
+SX_FN void es_ends(ES& es, double w) {
+    es.P0A = offs(es.p0, es.n0, w);
+    es.P1A = offs(es.p1, es.n1, w);
+    es.P0B = offs(es.p0, es.n0, -w);
+    es.P1B = offs(es.p1, es.n1, -w);
+    es.E0 = evolute_end(es, false);
+    es.E1 = evolute_end(es, true);
 }
 
 // FP32 copies of an ES for the record pass: p0, chord / Z(1) (or p1 - p0 for
@@ -657,8 +670,8 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
         p.ua = (float)ua; p.du = (float)du;
         p.alpha = (ra + rb > 0.0) ? (float)(ra / (ra + rb)) : 0.5f;
         p.ne = ne;
-        const V2 E0 = end_a_piece ? evolute_end(es, ua == 1.0) : Pa;
-        const V2 E1 = end_b_piece ? evolute_end(es, ub == 1.0) : Pb;
+        const V2 E0 = end_a_piece ? es.E0 : Pa;  // a range ending at a piece end: ua = 0, ub = 1
+        const V2 E1 = end_b_piece ? es.E1 : Pb;
         p.E0x = E0.x; p.E0y = E0.y; p.E1x = E1.x; p.E1y = E1.y;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
         p.zero = 0u;
@@ -673,7 +686,7 @@ SX_FN void emit_sides(Sink& k, const Cfg& cfg, const ES& es, double w) {
     for (int side = 0; side < 2; side++) {
         const double h = side == 0 ? w : -w;
         const double r0 = es_rhoL(es, h, 0.0), r1 = es_rhoL(es, h, 1.0);
-        const V2 P0 = offs(es.p0, es.n0, h), P1 = offs(es.p1, es.n1, h);
+        const V2 P0 = side == 0 ? es.P0A : es.P0B, P1 = side == 0 ? es.P1A : es.P1B;
         const bool split = r0 * r1 < 0.0;
         const double tc = split ? r0 / (r0 - r1) : 1.0;
         const V2 Pc = split ? offset_point_f(es, (float)h, (float)tc) : P1;
@@ -727,8 +740,9 @@ SX_HD void emit_cap(Sink& k, const Cfg& cfg, int cap, D2 p, D2 u, double w, bool
         jp.ax = a.x; jp.ay = a.y; jp.bx = b.x; jp.by = b.y;
         put_join(k, cfg, kOutLine3, kInNone, false, jp);
     } else {
-        double a0 = atan2(from.y - p.y, from.x - p.x);
-        jp.a0 = (float)a0; jp.sweep = (float)kPi; jp.w = (float)w;
+        // the start angle only places FP32 points: FP32 is enough
+        jp.a0 = atan2f((float)(from.y - p.y), (float)(from.x - p.x));
+        jp.sweep = (float)kPi; jp.w = (float)w;
         jp.n_outer = round_count(cfg, w, kPi);
         put_join(k, cfg, kOutRound, kInNone, false, jp);
     }
@@ -759,9 +773,9 @@ SX_HD void emit_join(Sink& k, const Cfg& cfg, int join, double miter_limit, D2 p
     jp.fx = fi.x; jp.fy = fi.y; jp.px = fp.x; jp.py = fp.y; jp.tx = ti.x; jp.ty = ti.y;
     uint32_t outer = kOutLine1;
     if (join == kJoinRound) {
-        double dphi = atan2(cr, dp);
-        double a0 = atan2(from.y - p.y, from.x - p.x);
-        jp.a0 = (float)a0; jp.sweep = (float)fabs(dphi); jp.w = (float)w;
+        double dphi = atan2(cr, dp);  // FP64: it decides the count
+        jp.a0 = atan2f((float)(from.y - p.y), (float)(from.x - p.x));
+        jp.sweep = (float)fabs(dphi); jp.w = (float)w;
         jp.n_outer = round_count(cfg, w, fabs(dphi));
         outer = kOutRound;
     } else if (join == kJoinMiter) {
@@ -1329,6 +1343,7 @@ SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t
     es.fk1 = (float)es.k1;
     es.fL = (float)es.L;
     es.fbase = (float)base;
+    es_ends(es, s.w);
     set_es_f(es, k.es_tab + 8 * (size_t)k.slot);
     emit_sides(k, cfg, es, s.w);
 }

@@ -487,11 +487,14 @@ __device__ __forceinline__ uint32_t slot_class(const SceneView& sv, Slot sl) {
     return (sl.tag < sv.n_tags && (sv.tags[sl.tag] & kTagCount) == 1u) ? 1u : 0u;
 }
 
-// One thread per slot: the piece's Euler spiral and parallel curves, or the
-// tag's join / cap, as emission items (records relative to the slot) and
-// the slot's record count.  Tiles of kSlotBlock slots are ordered by work
+// One thread per slot: the piece's Euler spiral and parallel curves
+// (Tails = false), or the tag's join / cap (Tails = true), as emission items
+// (records relative to the slot) and the slot's record count.  The two kinds
+// run as two launches with their own register budgets; a tile's items
+// continue in the same region (the tail launch starts its tile counter where
+// the piece launch left it).  Tiles of kSlotBlock slots are ordered by work
 // class first, so a wave runs slots of one kind.
-template <int MinWaves, bool Stats>
+template <int MinWaves, bool Stats, bool Tails>
 __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
                                                                     const Slot* __restrict__ slots,
                                                                     const uint64_t* __restrict__ n_slots_dev,
@@ -508,10 +511,10 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t first = (uint64_t)tile * kSlotBlock;
-        if (t == 0) s_n = 0;
+        if (t == 0) s_n = Tails ? ws.tile_n[tile] : 0u;
         const uint64_t j0 = first + t;
         const Slot mine = j0 < n_slots ? slots[j0] : Slot{0u, kSlotTail};
-        const uint32_t cls = j0 < n_slots ? slot_class(sv, mine) : 2u;
+        const uint32_t cls = j0 < n_slots ? slot_class(sv, mine) : 3u;
         uint32_t rank = 0;
 #pragma unroll
         for (uint32_t c = 0; c < 3; c++) {
@@ -524,38 +527,44 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         for (uint32_t c = 0; c < 3; c++)
             for (uint32_t w = 0; w < kSlotBlock / 64; w++)
                 if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
-        s_order[pos] = t;
+        if (cls < 3u) s_order[pos] = t;
+        uint32_t n_valid = 0;  // slots of this tile (the rest of s_order is unused)
+        for (uint32_t w = 0; w < kSlotBlock / 64; w++) n_valid += s_hist[w][0] + s_hist[w][1] + s_hist[w][2];
         __syncthreads();
-        const uint64_t j = first + s_order[t];
-        if (j < n_slots) {
+        if (t < n_valid) {
+            const uint64_t j = first + s_order[t];
             const Slot sl = slots[j];
-            TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
-                         ws.ovf_cap};
-            ItemSink<TileAlloc, Stats> k;
-            k.units = ws.units;
-            k.es_tab = ws.es_tab;
-            k.al = al;
-            k.tag = sl.tag;
-            k.slot = (uint32_t)j;
-            k.n = 0;
-            if (Stats)
-                for (int q = 0; q < kStN; q++) k.st[q] = 0;
-            if (sl.tag < sv.n_tags) {
-                TagInfo ti;
-                Seg sg;
-                fetch_tag(sv, sl.tag, ti, sg);
-                if (sl.code == kSlotTail) emit_tail(k, cfg, sv, sl.tag, ti, sg);
-                else if (ti.kind == kTagSegment)
-                    emit_piece(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code));
+            const bool tail = sl.code == kSlotTail;
+            if (tail == Tails) {
+                TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
+                             ws.ovf_base, ws.ovf_cap};
+                ItemSink<TileAlloc, Stats> k;
+                k.units = ws.units;
+                k.es_tab = ws.es_tab;
+                k.al = al;
+                k.tag = sl.tag;
+                k.slot = (uint32_t)j;
+                k.n = 0;
+                if (Stats)
+                    for (int q = 0; q < kStN; q++) k.st[q] = 0;
+                if (sl.tag < sv.n_tags) {
+                    TagInfo ti;
+                    Seg sg;
+                    fetch_tag(sv, sl.tag, ti, sg);
+                    if (Tails) emit_tail(k, cfg, sv, sl.tag, ti, sg);
+                    else if (ti.kind == kTagSegment)
+                        emit_piece(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code));
+                }
+                rc[j] = k.n;
+                if (Stats)
+                    for (int q = 0; q < kStN; q++) st[q] += k.st[q];
             }
-            rc[j] = k.n;
-            if (Stats)
-                for (int q = 0; q < kStN; q++) st[q] += k.st[q];
         }
         __syncthreads();
         if (t == 0) {
+            const uint32_t before = Tails ? ws.tile_n[tile] : 0u;
             ws.tile_n[tile] = s_n;
-            atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
+            atomicAdd(&ws.ctl->items_total, (unsigned long long)(s_n - before));
         }
         __syncthreads();
     }
@@ -765,14 +774,22 @@ hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, in
     return hipGetLastError();
 }
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
-                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
+                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves, bool tails,
                         unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     const uint32_t g = std::min<uint32_t>(kSlotGrid, std::max<uint32_t>(1u, slot_tiles(slot_cap)));
-    if (stats) slot_kernel<1, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    else if (waves <= 1) slot_kernel<1, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    else if (waves == 2) slot_kernel<2, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    else slot_kernel<3, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    if (tails) {
+        if (stats) slot_kernel<3, true, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        else slot_kernel<3, false, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    } else if (stats) {
+        slot_kernel<1, true, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    } else if (waves <= 1) {
+        slot_kernel<1, false, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    } else if (waves == 2) {
+        slot_kernel<2, false, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    } else {
+        slot_kernel<3, false, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    }
     return hipGetLastError();
 }
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,

@@ -49,7 +49,7 @@ class _FakeCtx:
 
 def test_tuner_picks_the_fastest_candidate(monkeypatch, tmp_path):
     def cost(t):  # separable: each group has one best value
-        return (10.0 + abs(t["piece_waves"] - 1) + abs(t["bisect_range"] - 512) / 256 + (t["bisect_waves"] == 2)
+        return (10.0 + abs(t["piece_waves"] - 1) + abs(t["bisect_range"] - 512) / 256 + abs(t["bisect_waves"] - 4)
                 + abs(t["chunk_k"] - 32) / 8)
 
     ctx = _FakeCtx(cost)
