@@ -1,18 +1,24 @@
 // HIP kernels of the stroke-expansion hot path for gfx950 (wave64).
 //
-//  scan_tags_kernel   tag-monoid prefix scan (Section 8.2): single pass,
-//                     wave64 shuffle scan + LDS block scan + decoupled
-//                     look-back over dynamically numbered tiles.
-//  piece_kernel       per tag, the per-segment decisions (Algorithm 1 /
-//                     Algorithm 2) in FP64; writes emission items into the
-//                     workspace (slots handed out per tile by LDS atomics,
-//                     overflow through one global counter) and the tag's
-//                     record count.
-//  scan_counts_kernel exclusive scan of the counts into u64 output offsets
-//                     (replaces the paper's atomic bump allocation, so the
-//                     output order is canonical and deterministic).
-//  record_kernel      per item chunk, the FP32 per-point work: records at
-//                     offsets[tag] + the chunk's position within the tag.
+//  scan_tags_kernel       tag-monoid prefix scan (Section 8.2): single pass,
+//                         wave64 shuffle scan + LDS block scan + decoupled
+//                         look-back over dynamically numbered tiles.
+//  bisect_kernel          Algorithm 2 in FP64 with lane refill (a wave owns a
+//                         range of tags; a lane whose tag is done takes the
+//                         next).  Count pass: slots per tag (pieces + 1 tail)
+//                         and the codes of the first pieces; write pass: every
+//                         slot {tag, code} at its canonical position.
+//  scan_counts_kernel     exclusive scan of u32 counts into u64 offsets (slot
+//  scan_counts_dev_kernel bases; record offsets, with the count read on the
+//                         device).  Replaces the paper's atomic bump
+//                         allocation: the output order is canonical.
+//  slot_kernel            per piece slot, the Euler spiral, parallel curves,
+//                         cusp split, evolutes and counts (Sections 4-6); per
+//                         tail slot, the join or cap (Algorithm 1).  Writes
+//                         emission items into per-tile workspace regions and
+//                         the slot's record count.
+//  record_kernel          per item chunk, the FP32 per-point work: records
+//                         at roff[slot] + the chunk's position in its slot.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
