@@ -294,9 +294,10 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
             return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, true, s->d_nslots,
                                      s->d_codes, s->d_base, s->d_slots, s->slot_cap, nullptr, st);
         case kPhPieces:
-        case kPhTails:
             return sx::launch_slots(view(s), cfg, workspace(s), s->d_slots, n_slots_dev(s), s->slot_cap, s->d_rc,
-                                    (int)t.piece_waves, ph == kPhTails, stats, st);
+                                    (int)t.piece_waves, stats, st);
+        case kPhTails:
+            return sx::launch_tails(view(s), cfg, workspace(s), s->d_base, s->slot_cap, s->d_rc, stats, st);
         case kPhScanRecords:
             return sx::launch_scan_counts_dev(s->d_rc, n_slots_dev(s), (uint32_t)s->slot_cap, s->d_roff,
                                               ctl_block(s, 2), s->d_status_rc, st);

@@ -563,6 +563,24 @@ struct Cfg {
 // With Stats, the sink also counts the work done (fit trials, accepted
 // pieces, items by kind) for the algorithmic-work figures of the roofline.
 enum { kStTrials = 0, kStPieces = 1, kStRanges = 2, kStEvolutes = 3, kStJoins = 4, kStLines = 5, kStN = 6 };
+
+// An item of nrec records as chunks of at most K records, each chunk a copy
+// of the header (with its own count and position) and the payload, at unit
+// `base` of the workspace; n0 = the item's first record within its slot.
+template <class P>
+SX_HD void write_item(Unit* units, uint64_t base, uint32_t hdr, uint32_t tag, uint32_t slot, uint32_t n0,
+                      uint32_t nrec, uint32_t K, const P& p) {
+    constexpr uint32_t U = Units<P>::n;
+    const uint32_t nc = chunks(nrec, K);
+    for (uint32_t c = 0; c < nc; c++) {
+        uint32_t* dst = units[base + (uint64_t)c * U].w;
+        const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
+        *reinterpret_cast<uint4*>(dst) = make_uint4(hdr | (nchunk << 24), tag, slot, n0 + c * K);
+        *reinterpret_cast<uint2*>(dst + 4) = make_uint2(c * K, nrec);
+        *reinterpret_cast<P*>(dst + kHdrWords) = p;
+    }
+}
+
 template <class Alloc, bool Stats = false>
 struct ItemSink {
     Unit* units;
@@ -578,18 +596,8 @@ struct ItemSink {
             const uint32_t kind = hdr & 15u;
             st[kind == kItemOffset ? kStRanges : (kind == kItemEvolute ? kStEvolutes : kStJoins)]++;
         }
-        constexpr uint32_t U = Units<P>::n;
-        const uint32_t nc = chunks(nrec, K);
-        const uint64_t base = al.alloc(nc * U);
-        if (base != ~0ull) {
-            for (uint32_t c = 0; c < nc; c++) {
-                uint32_t* dst = units[base + (uint64_t)c * U].w;
-                const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
-                *reinterpret_cast<uint4*>(dst) = make_uint4(hdr | (nchunk << 24), tag, slot, n + c * K);
-                *reinterpret_cast<uint2*>(dst + 4) = make_uint2(c * K, nrec);
-                *reinterpret_cast<P*>(dst + kHdrWords) = p;
-            }
-        }
+        const uint64_t base = al.alloc(chunks(nrec, K) * Units<P>::n);
+        if (base != ~0ull) write_item(units, base, hdr, tag, slot, n, nrec, K, p);
         n += nrec;
     }
 };

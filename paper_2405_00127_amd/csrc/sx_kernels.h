@@ -55,10 +55,13 @@ constexpr int kKeepCodes = 32;
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
                          uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
                          unsigned long long* stats, hipStream_t s);
-// pieces (tails = false) then tails (tails = true), two launches
+// piece slots (one thread per slot)
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
-                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves, bool tails,
+                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
                         unsigned long long* stats, hipStream_t s);
+// tail slots (one thread per tag), after launch_slots
+hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const uint64_t* base,
+                        uint64_t slot_cap, uint32_t* rc, unsigned long long* stats, hipStream_t s);
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,
                           const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s);
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,

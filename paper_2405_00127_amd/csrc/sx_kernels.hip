@@ -462,6 +462,9 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
 // ------------------------------------------------------------- slots
 constexpr int kSlotBlock = 256;   // slots per workgroup and per workspace tile
 constexpr int kSlotGrid = 8192;   // persistent grid of the slot kernel (tiles stride by it)
+constexpr int kTailBlock = 256;   // tags per tail-kernel workgroup
+constexpr int kTailGrid = 8192;   // grid cap of the tail kernel (tags stride by it)
+constexpr int kTailWin = 64;      // slot tiles a tail-kernel block counts in LDS
 constexpr int kRecBlock = 256;
 constexpr int kRecGrid = 8192;    // persistent grid of the record kernel
 constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the overflow slots
@@ -493,14 +496,12 @@ __device__ __forceinline__ uint32_t slot_class(const SceneView& sv, Slot sl) {
     return (sl.tag < sv.n_tags && (sv.tags[sl.tag] & kTagCount) == 1u) ? 1u : 0u;
 }
 
-// One thread per slot: the piece's Euler spiral and parallel curves
-// (Tails = false), or the tag's join / cap (Tails = true), as emission items
-// (records relative to the slot) and the slot's record count.  The two kinds
-// run as two launches with their own register budgets; a tile's items
-// continue in the same region (the tail launch starts its tile counter where
-// the piece launch left it).  Tiles of kSlotBlock slots are ordered by work
-// class first, so a wave runs slots of one kind.
-template <int MinWaves, bool Stats, bool Tails>
+// One thread per piece slot: the piece's Euler spiral and parallel curves
+// as emission items (records relative to the slot) and the slot's record
+// count.  Tiles of kSlotBlock slots are ordered by work class first (curve
+// pieces, line pieces), so a wave runs slots of one kind; tail slots are left
+// to tail_kernel.
+template <int MinWaves, bool Stats>
 __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
                                                                     const Slot* __restrict__ slots,
                                                                     const uint64_t* __restrict__ n_slots_dev,
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t first = (uint64_t)tile * kSlotBlock;
-        if (t == 0) s_n = Tails ? ws.tile_n[tile] : 0u;
+        if (t == 0) s_n = 0u;
         const uint64_t j0 = first + t;
         const Slot mine = j0 < n_slots ? slots[j0] : Slot{0u, kSlotTail};
         const uint32_t cls = j0 < n_slots ? slot_class(sv, mine) : 3u;
@@ -540,8 +541,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         if (t < n_valid) {
             const uint64_t j = first + s_order[t];
             const Slot sl = slots[j];
-            const bool tail = sl.code == kSlotTail;
-            if (tail == Tails) {
+            if (sl.code != kSlotTail) {
                 TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
                              ws.ovf_base, ws.ovf_cap};
                 ItemSink<TileAlloc, Stats> k;
@@ -557,8 +557,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                     TagInfo ti;
                     Seg sg;
                     fetch_tag(sv, sl.tag, ti, sg);
-                    if (Tails) emit_tail(k, cfg, sv, sl.tag, ti, sg);
-                    else if (ti.kind == kTagSegment)
+                    if (ti.kind == kTagSegment)
                         emit_piece(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code));
                 }
                 rc[j] = k.n;
@@ -568,16 +567,103 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         }
         __syncthreads();
         if (t == 0) {
-            const uint32_t before = Tails ? ws.tile_n[tile] : 0u;
             ws.tile_n[tile] = s_n;
-            atomicAdd(&ws.ctl->items_total, (unsigned long long)(s_n - before));
+            atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
         }
         __syncthreads();
     }
     if (Stats) {
-        for (int q = kStPieces; q <= kStJoins; q++)
+        for (int q = kStPieces; q <= kStEvolutes; q++)
             if (st[q]) atomicAdd(&stats[q], (unsigned long long)st[q]);
     }
+}
+
+// Sink of a tail: a join or cap is one item (or none), held in registers
+// until the block has placed it.
+template <bool Stats>
+struct TailSink {
+    static constexpr bool kStats = Stats;
+    uint32_t hdr, nrec, n;
+    JoinP p;
+    uint32_t st[Stats ? kStN : 1];
+    __device__ void put(uint32_t h, uint32_t nr, uint32_t, const JoinP& q) {
+        if constexpr (Stats) st[kStJoins]++;
+        hdr = h;
+        nrec = nr;
+        p = q;
+        n += nr;
+    }
+};
+
+// One thread per tag: its tail slot (the last of its slots, at
+// base[tag + 1] - 1) holds the join with the next segment or the cap
+// (Algorithm 1).  The items continue the regions of the tails' slot tiles
+// after the piece launch's items: a block's consecutive tags have increasing
+// tail slots spanning a few tiles, so it counts its units per tile in LDS and
+// takes them from each tile's counter with one global atomic (per lane only
+// when the block spans more than kTailWin tiles).
+template <bool Stats>
+__global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg cfg, ItemWs ws,
+                                                            const uint64_t* __restrict__ base, uint64_t slot_cap,
+                                                            uint32_t* __restrict__ rc,
+                                                            unsigned long long* __restrict__ stats) {
+    __shared__ uint32_t s_cnt[kTailWin];
+    __shared__ uint32_t s_at[kTailWin];
+    __shared__ uint32_t s_asked;
+    const uint32_t n = sv.n_tags;
+    if (base[n] > slot_cap) return;  // reported by the finish kernel
+    const uint32_t t = threadIdx.x;
+    if (t == 0) s_asked = 0u;
+    uint32_t asked = 0, joins = 0;
+    for (uint32_t i0 = blockIdx.x * kTailBlock; i0 < n; i0 += gridDim.x * kTailBlock) {
+        const uint32_t i = i0 + t;
+        const uint32_t ilast = min(n, i0 + kTailBlock) - 1u;
+        const uint64_t tile_lo = (base[i0 + 1] - 1u) / kSlotBlock;
+        const uint64_t span = (base[ilast + 1] - 1u) / kSlotBlock - tile_lo + 1u;
+        const bool win = span <= (uint64_t)kTailWin;
+        if (t < kTailWin) s_cnt[t] = 0u;
+        __syncthreads();
+        TailSink<Stats> k;
+        k.nrec = 0;
+        k.n = 0;
+        if (Stats) k.st[kStJoins] = 0;
+        uint64_t slot = 0, tile = 0;
+        uint32_t need = 0, local = 0;
+        if (i < n) {
+            slot = base[i + 1] - 1u;
+            tile = slot / kSlotBlock;
+            TagInfo ti;
+            Seg sg;
+            fetch_tag(sv, i, ti, sg);
+            emit_tail(k, cfg, sv, i, ti, sg);
+            need = k.nrec ? chunks(k.nrec, cfg.K) * Units<JoinP>::n : 0u;
+            if (win && need) local = atomicAdd(&s_cnt[tile - tile_lo], need);
+        }
+        __syncthreads();
+        if (win && t < span && s_cnt[t]) s_at[t] = atomicAdd(&ws.tile_n[tile_lo + t], s_cnt[t]);
+        __syncthreads();
+        if (i < n) {
+            if (need) {
+                const uint32_t at = win ? s_at[tile - tile_lo] + local : atomicAdd(&ws.tile_n[tile], need);
+                uint64_t u = tile * ws.region_cap + at;
+                if (at + need > ws.region_cap) {
+                    // the part inside the region is left empty; the item goes to the overflow area
+                    for (uint32_t j = at; j < ws.region_cap; j++) ws.units[tile * ws.region_cap + j].w[0] = 0u;
+                    const unsigned long long o = atomicAdd(&ws.ctl->ovf_n, (unsigned long long)need);
+                    u = (o + need <= ws.ovf_cap) ? ws.ovf_base + o : ~0ull;
+                }
+                if (u != ~0ull) write_item(ws.units, u, k.hdr, i, (uint32_t)slot, 0u, k.nrec, cfg.K, k.p);
+            }
+            rc[slot] = k.n;
+            asked += need;
+            if (Stats) joins += k.st[kStJoins];
+        }
+        __syncthreads();  // s_cnt and s_at are reused
+    }
+    atomicAdd(&s_asked, asked);
+    __syncthreads();
+    if (t == 0 && s_asked) atomicAdd(&ws.ctl->items_total, (unsigned long long)s_asked);
+    if (Stats && joins) atomicAdd(&stats[kStJoins], (unsigned long long)joins);
 }
 
 // Record-kernel item classes: offset ranges placed by the density inverse,
@@ -780,22 +866,27 @@ hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, in
     return hipGetLastError();
 }
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
-                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves, bool tails,
+                        const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
                         unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     const uint32_t g = std::min<uint32_t>(kSlotGrid, std::max<uint32_t>(1u, slot_tiles(slot_cap)));
-    if (tails) {
-        if (stats) slot_kernel<3, true, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-        else slot_kernel<3, false, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    } else if (stats) {
-        slot_kernel<1, true, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    if (stats) {
+        slot_kernel<1, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
     } else if (waves <= 1) {
-        slot_kernel<1, false, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<1, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
     } else if (waves == 2) {
-        slot_kernel<2, false, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<2, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
     } else {
-        slot_kernel<3, false, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<3, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
     }
+    return hipGetLastError();
+}
+hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const uint64_t* base,
+                        uint64_t slot_cap, uint32_t* rc, unsigned long long* stats, hipStream_t s) {
+    if (sv.n_tags == 0) return hipSuccess;
+    const uint32_t g = std::min<uint32_t>(kTailGrid, (sv.n_tags + kTailBlock - 1) / kTailBlock);
+    if (stats) tail_kernel<true><<<g, kTailBlock, 0, s>>>(sv, cfg, ws, base, slot_cap, rc, stats);
+    else tail_kernel<false><<<g, kTailBlock, 0, s>>>(sv, cfg, ws, base, slot_cap, rc, stats);
     return hipGetLastError();
 }
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,
