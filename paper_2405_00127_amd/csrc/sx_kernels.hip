@@ -677,6 +677,10 @@ __device__ __forceinline__ uint32_t item_class(uint32_t hdr) {
     return kind == kItemEvolute ? 2u : 3u;
 }
 
+// Record-kernel ordering key (the item class).
+constexpr uint32_t kSortKeys = kItemClasses;
+__device__ __forceinline__ uint32_t sort_key(uint32_t hdr) { return item_class(hdr); }
+
 // One item chunk starting at unit u: loads its one or two units and writes
 // its records.
 __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& ws, const Unit* u,
@@ -703,7 +707,7 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
 
 // Per item chunk, the FP32 per-point work: records at
 // roff[slot] + the chunk's position within its slot.
-__global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs ws, int arcs,
+__global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, ItemWs ws, int arcs,
                                                            const uint64_t* __restrict__ roff,
                                                            const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
                                                            float* __restrict__ out, uint64_t cap_records) {
@@ -716,26 +720,21 @@ __global__ __launch_bounds__(kRecBlock) void record_kernel(SceneView sv, ItemWs 
         // a tile's items, kRecBlock at a time, each round ordered by item
         // class so that a wave runs items of one kind
         __shared__ uint32_t s_order[kRecBlock];
-        __shared__ uint32_t s_hist[kRecBlock / 64][kItemClasses];
-        const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        __shared__ uint32_t s_cnt[kSortKeys];
+        const uint32_t t = threadIdx.x;
         for (uint32_t tile = b; tile < n_tiles; tile += kRecGrid) {
             const uint32_t cnt = ws.tile_n[tile] < ws.region_cap ? ws.tile_n[tile] : ws.region_cap;
             const Unit* base = ws.units + (uint64_t)tile * ws.region_cap;
             for (uint32_t r0 = 0; r0 < cnt; r0 += kRecBlock) {
-                const uint32_t cls = (r0 + t < cnt) ? item_class(base[r0 + t].w[0]) : kItemClasses - 1;
-                uint32_t rank = 0;
-#pragma unroll
-                for (uint32_t c = 0; c < kItemClasses; c++) {
-                    const uint64_t m = __ballot(cls == c);
-                    if (cls == c) rank = (uint32_t)__popcll(m & below);
-                    if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
-                }
+                // counting sort by key through LDS atomics (the order within
+                // a key is free: every record's position comes from the scans)
+                if (t < kSortKeys) s_cnt[t] = 0u;
+                __syncthreads();
+                const uint32_t key = (r0 + t < cnt) ? sort_key(base[r0 + t].w[0]) : kSortKeys - 1;
+                const uint32_t rank = atomicAdd(&s_cnt[key], 1u);
                 __syncthreads();
                 uint32_t pos = rank;
-                for (uint32_t c = 0; c < kItemClasses; c++)
-                    for (uint32_t w = 0; w < kRecBlock / 64; w++)
-                        if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
+                for (uint32_t c = 0; c < kSortKeys; c++) pos += (c < key) ? s_cnt[c] : 0u;
                 s_order[pos] = t;
                 __syncthreads();
                 const uint32_t s2 = r0 + s_order[t];
