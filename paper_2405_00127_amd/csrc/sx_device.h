@@ -530,7 +530,7 @@ struct __align__(16) Unit {
 };
 struct ItemHdr {
     uint32_t hdr;    // kind | flags | outer kind << 16 | inner kind << 20 | records in this chunk << 24
-    uint32_t tag;    // tag index (for the path id)
+    uint32_t path;   // output path id of the records
     uint32_t slot;   // slot index (canonical position of the piece or tail)
     uint32_t local;  // record offset of this chunk within the slot
     uint32_t k0;     // first record of the chunk within the whole item
@@ -599,14 +599,14 @@ enum { kStTrials = 0, kStPieces = 1, kStRanges = 2, kStEvolutes = 3, kStJoins = 
 // of the header (with its own count and position) and the payload, at unit
 // `base` of the workspace; n0 = the item's first record within its slot.
 template <class P>
-SX_HD void write_item(Unit* units, uint64_t base, uint32_t hdr, uint32_t tag, uint32_t slot, uint32_t n0,
+SX_HD void write_item(Unit* units, uint64_t base, uint32_t hdr, uint32_t path, uint32_t slot, uint32_t n0,
                       uint32_t nrec, uint32_t K, const P& p) {
     constexpr uint32_t U = Units<P>::n;
     const uint32_t nc = chunks(nrec, K);
     for (uint32_t c = 0; c < nc; c++) {
         uint32_t* dst = units[base + (uint64_t)c * U].w;
         const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
-        *reinterpret_cast<uint4*>(dst) = make_uint4(hdr | (nchunk << 24), tag, slot, n0 + c * K);
+        *reinterpret_cast<uint4*>(dst) = make_uint4(hdr | (nchunk << 24), path, slot, n0 + c * K);
         *reinterpret_cast<uint2*>(dst + 4) = make_uint2(c * K, nrec);
         *reinterpret_cast<P*>(dst + kHdrWords) = p;
     }
@@ -617,8 +617,8 @@ struct ItemSink {
     Unit* units;
     float* es_tab;  // 8 floats per slot
     Alloc al;
-    uint32_t tag, slot;
-    uint32_t n;  // records of the slot so far
+    uint32_t path, slot;  // output path id, slot index
+    uint32_t n;           // records of the slot so far
     uint32_t st[Stats ? kStN : 1];
     static constexpr bool kStats = Stats;
     template <class P>
@@ -628,87 +628,102 @@ struct ItemSink {
             st[kind == kItemOffset ? kStRanges : (kind == kItemEvolute ? kStEvolutes : kStJoins)]++;
         }
         const uint64_t base = al.alloc(chunks(nrec, K) * Units<P>::n);
-        if (base != ~0ull) write_item(units, base, hdr, tag, slot, n, nrec, K, p);
+        if (base != ~0ull) write_item(units, base, hdr, path, slot, n, nrec, K, p);
         n += nrec;
     }
 };
 
 // ----------------------------------------------- one range of one side
 // Section 4 (lines), Section 5 (arcs) and Section 6 (evolute for rho < 0).
-// Pa, Pb: the range's end points (exact piece ends or the shared cusp point).
-template <class Sink>
-SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua, double ub, bool reversed,
-                      bool end_a_piece, bool end_b_piece, V2 Pa, V2 Pb) {
-    const bool sideA = h >= 0.0;
-    const int D = sideA ? 1 : -1;
-    const int dir = reversed ? -D : D;
+// The decisions of a range (its counts and the density increment that places
+// its points) depend only on the spiral's k0, k1, L, the side h and the u
+// range; writing its items needs the rest.
+struct RangeRes {
+    double dF;          // F increment over the range (density placement)
+    float dxs, alpha;   // FP32 sum of the x pieces' lengths; evolute point split
+    uint32_t n, ne, place;
+};
+SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, double h, double ua, double ub,
+                           bool reversed) {
+    RangeRes r;
     const double du = ub - ua;
-    const double kna = es_kn(es, ua), knb = es_kn(es, ub);
-    uint32_t n;
-    double hka = 0.0, hkb = 0.0, dx = 0.0, dF = 0.0;
-    float dxs = 0.0f;
-    uint32_t place = 0;
+    const double kna = k0 + k1 * (ua - 0.5), knb = k0 + k1 * (ub - 0.5);
+    r.dF = 0.0;
+    r.dxs = 0.0f;
+    r.place = 0;
     if (!cfg.arcs) {
         double I;
-        if (es.k1 == 0.0) {
-            I = du * sqrt(fabs(es.k0) * fabs(es.L + h * es.k0));
+        if (k1 == 0.0) {
+            I = du * sqrt(fabs(k0) * fabs(L + h * k0));
         } else if (h == 0.0) {
-            place = kIfPlaceES;
+            r.place = kIfPlaceES;
             double aa = fabs(kna), ab = fabs(knb);
             if (kna * knb >= 0.0) {
-                place |= kIfKSame;
+                r.place |= kIfKSame;
                 double den = pow15(aa) + pow15(ab);
-                I = den > 0.0 ? (2.0 / 3.0) * du * sqrt(es.L) * (aa * aa + aa * ab + ab * ab) / den : 0.0;
+                I = den > 0.0 ? (2.0 / 3.0) * du * sqrt(L) * (aa * aa + aa * ab + ab * ab) / den : 0.0;
             } else {
-                I = (2.0 / 3.0) * du * sqrt(es.L) * (pow15(aa) + pow15(ab)) / (aa + ab);
+                I = (2.0 / 3.0) * du * sqrt(L) * (pow15(aa) + pow15(ab)) / (aa + ab);
             }
         } else {
-            place = kIfPlaceF;
-            hka = h * kna / es.L;
-            hkb = h * knb / es.L;
-            dx = -2.0 * h * es.k1 * du / es.L;
-            dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, &dxs);
+            r.place = kIfPlaceF;
+            const double hka = h * kna / L, hkb = h * knb / L;
+            const double dx = -2.0 * h * k1 * du / L;
+            r.dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, &r.dxs);
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
-            double G = (dx != 0.0) ? dF / dx : 0.0;
-            I = fabs(G) * du * es.L / (2.0 * sqrt(fabs(h)));
+            double G = (dx != 0.0) ? r.dF / dx : 0.0;
+            I = fabs(G) * du * L / (2.0 * sqrt(fabs(h)));
         }
-        n = ceil_count(I * cfg.inv_sqrt8tf);
+        r.n = ceil_count(I * cfg.inv_sqrt8tf);
     } else {
         double n_est = 0.0;
-        if (es.k1 != 0.0) {
-            double Lr = du * es.L;
-            double kp = es.k1 / (es.L * es.L);
+        if (k1 != 0.0) {
+            double Lr = du * L;
+            double kp = k1 / (L * L);
             n_est = Lr * cbrt(fabs(kp) * (1.0 + 0.4 * fabs(h * Lr * kp))) * cfg.cbrt_inv120tf;
         }
-        n = ceil_count(n_est);
+        r.n = ceil_count(n_est);
         double sweep = fmax(fabs(kna), fabs(knb)) * du * (1.0 / kHalfPi);
         uint32_t ns = ceil_count(sweep);
-        n = ns > n ? ns : n;
+        r.n = ns > r.n ? ns : r.n;
     }
-    uint32_t ne = 0, nconn = 0;
-    double ra = 0.0, rb = 0.0;
+    r.ne = 0;
+    r.alpha = 0.5f;
     if (reversed) {
         // evolute: density |s - s0|^-1/2 (Section 6); lines in both modes
-        ra = sqrt(fabs(kna));
-        rb = sqrt(fabs(knb));
-        double Iev = (es.k1 != 0.0 && ra + rb > 0.0) ? 2.0 * du * sqrt(fabs(es.k1) * es.L) / (ra + rb) : 0.0;
-        ne = ceil_count(Iev * cfg.inv_sqrt8tf);
-        nconn = (end_a_piece ? 1u : 0u) + (end_b_piece ? 1u : 0u);
+        const double ra = sqrt(fabs(kna)), rb = sqrt(fabs(knb));
+        double Iev = (k1 != 0.0 && ra + rb > 0.0) ? 2.0 * du * sqrt(fabs(k1) * L) / (ra + rb) : 0.0;
+        r.ne = ceil_count(Iev * cfg.inv_sqrt8tf);
+        if (ra + rb > 0.0) r.alpha = (float)(ra / (ra + rb));
     }
+    return r;
+}
+
+// The range's items: the offset (or reversed offset) range, then for a
+// reversed range its evolute bundle (the evolute twice and the connecting
+// lines at ends that are piece ends).  Pa, Pb: the range's end points (exact
+// piece ends or the shared cusp point).
+template <class Sink>
+SX_FN void range_put(Sink& k, const Cfg& cfg, const ES& es, double h, double ua, double ub, bool reversed,
+                     bool end_a_piece, bool end_b_piece, V2 Pa, V2 Pb, const RangeRes& r) {
+    const int D = h >= 0.0 ? 1 : -1;
+    const int dir = reversed ? -D : D;
+    const double du = ub - ua;
     {
         OffsetP p;
         p.ua = (float)ua; p.du = (float)du; p.ub = (float)ub; p.fh = (float)h;
-        p.dF = (float)dF; p.dxs = dxs;
+        p.dF = (float)r.dF; p.dxs = r.dxs;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
         uint32_t hdr = kItemOffset | (dir < 0 ? kIfDirNeg : 0u) | (cfg.arcs ? kIfArcs : 0u) |
-                       (es.pivot ? kIfPivot : 0u) | place;
-        k.put(hdr, n, cfg.K, p);
+                       (es.pivot ? kIfPivot : 0u) | r.place;
+        k.put(hdr, r.n, cfg.K, p);
     }
     if (reversed) {
+        const uint32_t nconn = (end_a_piece ? 1u : 0u) + (end_b_piece ? 1u : 0u);
         EvoluteP p;
         p.ua = (float)ua; p.du = (float)du;
-        p.alpha = (ra + rb > 0.0) ? (float)(ra / (ra + rb)) : 0.5f;
-        p.ne = ne;
+        p.alpha = r.alpha;
+        p.ne = r.ne;
         const V2 E0 = end_a_piece ? es.E0 : Pa;  // a range ending at a piece end: ua = 0, ub = 1
         const V2 E1 = end_b_piece ? es.E1 : Pb;
         p.E0x = E0.x; p.E0y = E0.y; p.E1x = E1.x; p.E1y = E1.y;
@@ -716,26 +731,45 @@ SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua
         p.zero = 0u;
         uint32_t hdr = kItemEvolute | (D < 0 ? kIfDneg : 0u) | (es.pivot ? kIfPivot : 0u) |
                        (end_a_piece ? kIfEndA : 0u) | (end_b_piece ? kIfEndB : 0u);
-        k.put(hdr, 2u * ne + 2u * nconn, cfg.K, p);
+        k.put(hdr, 2u * r.ne + 2u * nconn, cfg.K, p);
     }
+}
+
+template <class Sink>
+SX_FN void emit_range(Sink& k, const Cfg& cfg, const ES& es, double h, double ua, double ub, bool reversed,
+                      bool end_a_piece, bool end_b_piece, V2 Pa, V2 Pb) {
+    range_put(k, cfg, es, h, ua, ub, reversed, end_a_piece, end_b_piece, Pa, Pb,
+              range_count(cfg, es.k0, es.k1, es.L, h, ua, ub, reversed));
+}
+
+// One side (h = +w for side 0, -w for side 1) of a piece: rho = 1 + h kappa
+// changes sign at most once along it (kappa is linear in u), splitting the
+// side at the parallel-curve cusp tc into two ranges (reading G9).
+struct SideGeo {
+    double h, tc;
+    bool split, rev1, rev2;  // two ranges; first / second range reversed (rho < 0)
+    V2 P0, P1, Pc;           // side end points and the cusp point
+};
+SX_FN SideGeo side_geo(const ES& es, double w, int side) {
+    SideGeo g;
+    g.h = side == 0 ? w : -w;
+    const double r0 = es_rhoL(es, g.h, 0.0), r1 = es_rhoL(es, g.h, 1.0);
+    g.P0 = side == 0 ? es.P0A : es.P0B;
+    g.P1 = side == 0 ? es.P1A : es.P1B;
+    g.split = r0 * r1 < 0.0;
+    g.tc = g.split ? r0 / (r0 - r1) : 1.0;
+    g.Pc = g.split ? offset_point_f(es, (float)g.h, (float)g.tc) : g.P1;
+    g.rev1 = g.split ? r0 < 0.0 : (r0 < 0.0 || r1 < 0.0);
+    g.rev2 = r1 < 0.0;
+    return g;
 }
 
 template <class Sink>
 SX_FN void emit_sides(Sink& k, const Cfg& cfg, const ES& es, double w) {
     for (int side = 0; side < 2; side++) {
-        const double h = side == 0 ? w : -w;
-        const double r0 = es_rhoL(es, h, 0.0), r1 = es_rhoL(es, h, 1.0);
-        const V2 P0 = side == 0 ? es.P0A : es.P0B, P1 = side == 0 ? es.P1A : es.P1B;
-        const bool split = r0 * r1 < 0.0;
-        const double tc = split ? r0 / (r0 - r1) : 1.0;
-        const V2 Pc = split ? offset_point_f(es, (float)h, (float)tc) : P1;
-        for (int r = 0; r < (split ? 2 : 1); r++) {
-            const bool second = r == 1;
-            const double ua = second ? tc : 0.0, ub = second ? 1.0 : tc;
-            const bool rev = split ? (second ? r1 < 0.0 : r0 < 0.0) : (r0 < 0.0 || r1 < 0.0);
-            emit_range(k, cfg, es, h, ua, ub, rev, !second, !split || second, second ? Pc : P0,
-                       second ? P1 : Pc);
-        }
+        const SideGeo g = side_geo(es, w, side);
+        emit_range(k, cfg, es, g.h, 0.0, g.tc, g.rev1, true, !g.split, g.P0, g.Pc);
+        if (g.split) emit_range(k, cfg, es, g.h, g.tc, 1.0, g.rev2, false, true, g.Pc, g.P1);
     }
 }
 
@@ -1162,6 +1196,12 @@ struct TagInfo {
     bool line;
 };
 
+// Input path id of tag i (all ones for a tag outside every path).
+SX_FN uint32_t path_of(const SceneView& sv, uint32_t i) {
+    const uint32_t pi = sv.mon[(size_t)sv.n_tags + i];
+    return pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
+}
+
 // Segment fetch and degree elevation (Section 8.1) of tag i; bounds derived
 // from the monoids are checked (a consistent scan never trips them).
 SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s) {
@@ -1323,10 +1363,12 @@ SX_HD inline bool bisect_step(Bisect& b, const Seg& s, const Cfg& cfg, bool line
 
 // The accepted piece [t0, t0 + 2^-depth] of the segment (accepted by the
 // fit, or only at the depth cap: a pivot): the same chord and end angles as
-// in the bisection, its Euler spiral (Appendix A; a pivot for reading G28)
-// and both parallel-curve sides.
+// in the bisection and its Euler spiral (Appendix A; a pivot for reading
+// G28), whose FP32 record goes to the slot's row of the spiral table;
+// emit_piece adds both parallel-curve sides.
 template <class Sink>
-SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth, bool pivot) {
+SX_HD void piece_es(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth, bool pivot,
+                    ES& es) {
     const double dt = depth_dt(depth);
     const double t0 = (double)t0_u * dt;
     const double t1 = t0 + dt;
@@ -1344,7 +1386,6 @@ SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t
         tr.th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
     }
     if constexpr (Sink::kStats) k.st[kStPieces]++;
-    ES es;
     es.pivot = pivot;
     es.p0 = cubic_world(s, t0);
     es.p1 = cubic_world(s, t1);
@@ -1386,6 +1427,11 @@ SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t
     es.fbase = (float)base;
     es_ends(es, s.w);
     set_es_f(es, k.es_tab + 8 * (size_t)k.slot);
+}
+template <class Sink>
+SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth, bool pivot) {
+    ES es;
+    piece_es(k, cfg, s, line, t0_u, depth, pivot, es);
     emit_sides(k, cfg, es, s.w);
 }
 

@@ -500,16 +500,24 @@ __device__ __forceinline__ uint32_t slot_class(const SceneView& sv, Slot sl) {
 // as emission items (records relative to the slot) and the slot's record
 // count.  Tiles of kSlotBlock slots are ordered by work class first (curve
 // pieces, line pieces), so a wave runs slots of one kind; tail slots are left
-// to tail_kernel.
+// to tail_kernel.  Every side has one range, a few have a second one past a
+// parallel-curve cusp: the counts of the first ranges run on the slot's own
+// thread, the second ranges of the whole block are packed onto its first
+// threads (the piece's k0, k1, L, width and cusp go through LDS), and then
+// each thread writes its piece's items in canonical order.
 template <int MinWaves, bool Stats>
 __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
                                                                     const Slot* __restrict__ slots,
                                                                     const uint64_t* __restrict__ n_slots_dev,
                                                                     uint64_t slot_cap, uint32_t* __restrict__ rc,
                                                                     unsigned long long* __restrict__ stats) {
-    __shared__ uint32_t s_n;
+    __shared__ uint32_t s_n, s_ntask;
     __shared__ uint32_t s_order[kSlotBlock];
     __shared__ uint32_t s_hist[kSlotBlock / 64][3];
+    __shared__ uint32_t s_task[2 * kSlotBlock];     // owner thread << 2 | side << 1 | reversed
+    __shared__ double s_own[kSlotBlock][4];        // k0, k1, L, w of the owner's piece
+    __shared__ double s_tc[kSlotBlock][2];         // cusp u of each side
+    __shared__ RangeRes s_res[2 * kSlotBlock];
     const uint64_t n_slots = *n_slots_dev;
     if (n_slots > slot_cap) return;  // reported by the finish kernel
     const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
@@ -518,7 +526,10 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t first = (uint64_t)tile * kSlotBlock;
-        if (t == 0) s_n = 0u;
+        if (t == 0) {
+            s_n = 0u;
+            s_ntask = 0u;
+        }
         const uint64_t j0 = first + t;
         const Slot mine = j0 < n_slots ? slots[j0] : Slot{0u, kSlotTail};
         const uint32_t cls = j0 < n_slots ? slot_class(sv, mine) : 3u;
@@ -538,32 +549,81 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         uint32_t n_valid = 0;  // slots of this tile (the rest of s_order is unused)
         for (uint32_t w = 0; w < kSlotBlock / 64; w++) n_valid += s_hist[w][0] + s_hist[w][1] + s_hist[w][2];
         __syncthreads();
+        // phase 1: the piece's spiral, its sides and the first range of each
+        uint64_t j = 0;
+        Slot sl{0u, kSlotTail};
         if (t < n_valid) {
-            const uint64_t j = first + s_order[t];
-            const Slot sl = slots[j];
-            if (sl.code != kSlotTail) {
-                TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n,
-                             ws.ovf_base, ws.ovf_cap};
-                ItemSink<TileAlloc, Stats> k;
-                k.units = ws.units;
-                k.es_tab = ws.es_tab;
-                k.al = al;
-                k.tag = sl.tag;
-                k.slot = (uint32_t)j;
-                k.n = 0;
-                if (Stats)
-                    for (int q = 0; q < kStN; q++) k.st[q] = 0;
-                if (sl.tag < sv.n_tags) {
-                    TagInfo ti;
-                    Seg sg;
-                    fetch_tag(sv, sl.tag, ti, sg);
-                    if (ti.kind == kTagSegment)
-                        emit_piece(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code));
+            j = first + s_order[t];
+            sl = slots[j];
+        }
+        const bool act = t < n_valid && sl.code != kSlotTail;
+        TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
+                     ws.ovf_cap};
+        ItemSink<TileAlloc, Stats> k;
+        k.units = ws.units;
+        k.es_tab = ws.es_tab;
+        k.al = al;
+        k.path = 0xffffffffu;
+        k.slot = (uint32_t)j;
+        k.n = 0;
+        if (Stats)
+            for (int q = 0; q < kStN; q++) k.st[q] = 0;
+        bool have = false;
+        ES es;
+        SideGeo g0, g1;
+        RangeRes a1, b1;
+        uint32_t qa = 0, qb = 0;
+        if (act && sl.tag < sv.n_tags) {
+            k.path = path_of(sv, sl.tag);
+            TagInfo ti;
+            Seg sg;
+            fetch_tag(sv, sl.tag, ti, sg);
+            if (ti.kind == kTagSegment) {
+                have = true;
+                piece_es(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code), es);
+                g0 = side_geo(es, sg.w, 0);
+                g1 = side_geo(es, sg.w, 1);
+                a1 = range_count(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
+                b1 = range_count(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
+                if (g0.split || g1.split) {
+                    s_own[t][0] = es.k0;
+                    s_own[t][1] = es.k1;
+                    s_own[t][2] = es.L;
+                    s_own[t][3] = sg.w;
+                    s_tc[t][0] = g0.tc;
+                    s_tc[t][1] = g1.tc;
                 }
-                rc[j] = k.n;
-                if (Stats)
-                    for (int q = 0; q < kStN; q++) st[q] += k.st[q];
+                if (g0.split) {
+                    qa = atomicAdd(&s_ntask, 1u);
+                    s_task[qa] = (t << 2) | (g0.rev2 ? 1u : 0u);
+                }
+                if (g1.split) {
+                    qb = atomicAdd(&s_ntask, 1u);
+                    s_task[qb] = (t << 2) | 2u | (g1.rev2 ? 1u : 0u);
+                }
             }
+        }
+        __syncthreads();
+        // phase 2: the second ranges of the block, packed
+        const uint32_t n_task = s_ntask;
+        for (uint32_t q = t; q < n_task; q += kSlotBlock) {
+            const uint32_t task = s_task[q], own = task >> 2, side = (task >> 1) & 1u;
+            const double w = s_own[own][3];
+            s_res[q] = range_count(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w, s_tc[own][side],
+                                   1.0, (task & 1u) != 0u);
+        }
+        __syncthreads();
+        // phase 3: the items of each piece in canonical order
+        if (have) {
+            range_put(k, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, a1);
+            if (g0.split) range_put(k, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, s_res[qa]);
+            range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, b1);
+            if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, s_res[qb]);
+        }
+        if (act) {
+            rc[j] = k.n;
+            if (Stats)
+                for (int q = 0; q < kStN; q++) st[q] += k.st[q];
         }
         __syncthreads();
         if (t == 0) {
@@ -652,7 +712,7 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
                     const unsigned long long o = atomicAdd(&ws.ctl->ovf_n, (unsigned long long)need);
                     u = (o + need <= ws.ovf_cap) ? ws.ovf_base + o : ~0ull;
                 }
-                if (u != ~0ull) write_item(ws.units, u, k.hdr, i, (uint32_t)slot, 0u, k.nrec, cfg.K, k.p);
+                if (u != ~0ull) write_item(ws.units, u, k.hdr, path_of(sv, i), (uint32_t)slot, 0u, k.nrec, cfg.K, k.p);
             }
             rc[slot] = k.n;
             asked += need;
@@ -696,10 +756,8 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
 #pragma unroll
         for (int j = 4; j < 8; j++) reinterpret_cast<uint4*>(w)[j] = src[j];
     }
-    const uint32_t tag = w[1], slot = w[2];
-    if (slot >= n_slots || tag >= sv.n_tags) return;
-    const uint32_t pi = sv.mon[(size_t)sv.n_tags + tag];
-    const uint32_t path = pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
+    const uint32_t path = w[1], slot = w[2];
+    if (slot >= n_slots) return;
     const uint64_t end = roff[slot + 1] < cap ? roff[slot + 1] : cap;
     RecOut o{out, roff[slot] + w[3], end, path, arcs};
     emit_item(w, ws.es_tab + 8 * (size_t)slot, o);

@@ -398,38 +398,63 @@ def _cusp_p2(p0, p1, p3, tc):
     return rhs / (tc * (2 - 3 * tc))
 
 
+_PAIRS = {}
+
+
+def _pair_block(m, i0):
+    """Index pairs (i, j) with i in [i0, i0 + 64) and j >= i + 2, j < m."""
+    key = (m, i0)
+    if key not in _PAIRS:
+        i, j = np.nonzero(np.arange(m)[None, :] >= np.arange(i0, min(i0 + 64, m - 2))[:, None] + 2)
+        _PAIRS[key] = (i + i0, j)
+    return _PAIRS[key]
+
+
 def _self_intersects(p, n=257):
     t = np.linspace(0, 1, n)[:, None]
     mt = 1 - t
     q = mt**3 * p[0] + 3 * mt * mt * t * p[1] + 3 * mt * t * t * p[2] + t**3 * p[3]
     a = q[:-1]
     b = q[1:]
-    # brute force: non-adjacent segment pairs
-    for i in range(len(a) - 2):
-        d1 = b[i] - a[i]
-        o = a[i + 2 :]
-        e = b[i + 2 :] - o
-        den = d1[0] * e[:, 1] - d1[1] * e[:, 0]
+    d1 = b - a
+    m = len(a)
+    # brute force over the non-adjacent segment pairs (i, j >= i + 2), a
+    # block of rows i at a time, middle rows first (a loop's crossing pairs an
+    # early segment with a late one); stops at the first block with a crossing
+    for i0 in (64, 0, 128, 192):
+        if i0 >= m - 2:
+            continue
+        i, j = _pair_block(m, i0)
+        o = a[j]
+        e = b[j] - o
+        den = d1[i, 0] * e[:, 1] - d1[i, 1] * e[:, 0]
         w = o - a[i]
         with np.errstate(divide="ignore", invalid="ignore"):
             s = (w[:, 0] * e[:, 1] - w[:, 1] * e[:, 0]) / den
-            u = (w[:, 0] * d1[1] - w[:, 1] * d1[0]) / den
+            u = (w[:, 0] * d1[i, 1] - w[:, 1] * d1[i, 0]) / den
         if np.any((den != 0) & (s >= 0) & (s <= 1) & (u >= 0) & (u <= 1)):
             return True
     return False
 
 
-def _max_curv_fp64(p, n=4097):
-    t = np.linspace(0, 1, n)
+_CURV_T = np.linspace(0, 1, 4097)
+
+
+def _max_curv_fp64(cubics):
+    """FP64 maximum curvature of each cubic (array [n, 4, 2]) over 4097
+    parameter samples."""
+    t = _CURV_T[None, :, None]
     mt = 1 - t
-    d1 = 3 * (np.outer(mt * mt, p[1] - p[0]) + np.outer(2 * t * mt, p[2] - p[1]) + np.outer(t * t, p[3] - p[2]))
-    d2 = 6 * (np.outer(mt, p[2] - 2 * p[1] + p[0]) + np.outer(t, p[3] - 2 * p[2] + p[1]))
-    cr = d1[:, 0] * d2[:, 1] - d1[:, 1] * d2[:, 0]
-    sp = np.hypot(d1[:, 0], d1[:, 1])
+    p = cubics[:, None, :, :]
+    d1 = 3 * (mt * mt * (p[:, :, 1] - p[:, :, 0]) + 2 * t * mt * (p[:, :, 2] - p[:, :, 1])
+              + t * t * (p[:, :, 3] - p[:, :, 2]))
+    d2 = 6 * (mt * (p[:, :, 2] - 2 * p[:, :, 1] + p[:, :, 0]) + t * (p[:, :, 3] - 2 * p[:, :, 2] + p[:, :, 1]))
+    cr = d1[..., 0] * d2[..., 1] - d1[..., 1] * d2[..., 0]
+    sp = np.hypot(d1[..., 0], d1[..., 1])
     with np.errstate(divide="ignore", invalid="ignore"):
         k = np.abs(cr) / sp**3
     k[~np.isfinite(k)] = np.inf
-    return float(np.max(k))
+    return np.max(k, axis=1)
 
 
 def stress_cubic(rng, kind: int) -> np.ndarray:
@@ -483,7 +508,7 @@ def scene_c3(seed: int = 3, n_cubics: int = 100_000, per_path: int = 10,
     for attempt in range(20):
         widths = rng.uniform(5.0, 50.0, n_paths)
         b = SceneBuilder()
-        over = 0
+        all_c32 = []
         for k in range(n_paths):
             cur = np.array([rng.uniform(0, CANVAS_W), rng.uniform(0, CANVAS_H)])
             verbs = [MOVE]
@@ -494,14 +519,22 @@ def scene_c3(seed: int = 3, n_cubics: int = 100_000, per_path: int = 10,
                 ang = rng.uniform(-math.pi, math.pi)
                 R = np.array([[math.cos(ang), -math.sin(ang)], [math.sin(ang), math.cos(ang)]])
                 c = c @ R.T + cur
-                c32 = c.astype(np.float32).astype(np.float64)
-                if _max_curv_fp64(c32) * widths[k] > 1.0:
-                    over += 1
+                all_c32.append(c.astype(np.float32).astype(np.float64))
                 verbs.append(CUBIC)
                 pts += [c[1], c[2], c[3]]
                 cur = c[3]
             b.add_path(verbs, np.array(pts), k, 0)
-        if over >= min_frac_over * n_paths * per_path:
+        # count segments with max curvature x half-width > 1 (stops once
+        # enough are found)
+        cubics = np.array(all_c32)
+        wseg = np.repeat(widths, per_path)
+        need = min_frac_over * n_paths * per_path
+        over = 0
+        for c in range(0, len(cubics), 256):
+            over += int(np.count_nonzero(_max_curv_fp64(cubics[c:c + 256]) * wseg[c:c + 256] > 1.0))
+            if over >= need:
+                break
+        if over >= need:
             break
     styles = make_styles(widths.astype(np.float32), JOIN_ROUND, CAP_ROUND)
     return b.build(styles, name=f"c3-seed{seed}", tolerance=tolerance, output_mode=output_mode)

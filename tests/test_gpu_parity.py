@@ -190,6 +190,68 @@ def test_full_size_c2_counts_and_samples(ctx):
     assert P.closed_per_path(recs) == 0
 
 
+def test_full_size_c3_counts_and_samples(ctx):
+    """The 100,000-cubic stress scene (cusps, near-cusps, loops, degenerate
+    control points; half-widths 5-50 px; tolerance 0.1 px; arcs) in one
+    launch: counts of every tag against the oracle, the records of sampled
+    windows of tags against the oracle run on those tags (endpoints, arc
+    bulge, path ids), the outlines closed per path, and the offset records of
+    sampled tags within tolerance of the exact FP64 parallel curves."""
+    import exact_stroke as X
+
+    _say("full c3: generate")
+    sc = S.scene_c3(3)
+    _say("full c3: expand", sc.n_segments(), "segments")
+    scene, counts, recs = _expand(ctx, sc)
+    _say("full c3: oracle counts")
+    ref = O.expand(sc, emit=False)
+    near = P.near_threshold(ref.margins)
+    mism = counts != ref.counts
+    _say("full c3: tags", len(counts), "records", int(counts.sum()), "mismatch", int(mism.sum()), "near",
+         int(near.sum()))
+    assert not np.any(mism & ~near)
+    assert mism.sum() <= 1e-3 * len(counts)
+    go = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
+    rng = np.random.default_rng(33)
+    enc = ref.enc
+    mon = O.monoids(enc.tags)
+    worst = worst_b = worst_x = 0.0
+    for a in np.sort(rng.choice(len(counts) - 40, 40, replace=False)):
+        a = int(a)
+        r = O.expand(sc, emit=True, tag_begin=a, tag_end=a + 40, enc=enc)
+        ro = np.concatenate([[0], np.cumsum(r.counts[a:a + 40].astype(np.int64))])
+        for i in range(a, a + 40):
+            if mism[i] or near[i]:
+                continue
+            g = recs[go[i]:go[i + 1]]
+            o = r.out[ro[i - a]:ro[i - a + 1]]
+            assert len(o) == len(g)
+            if not len(g):
+                continue
+            d = max(np.max(np.abs(g["x0"] - o["x0"])), np.max(np.abs(g["y0"] - o["y0"])),
+                    np.max(np.abs(g["x1"] - o["x1"])), np.max(np.abs(g["y1"] - o["y1"])))
+            worst = max(worst, float(d))
+            worst_b = max(worst_b, float(np.max(np.abs(P.arc_bulge(g) - P.arc_bulge(o)))))
+            assert np.all(g["path"] == o["path"])
+            if (enc.tags[i] & 4) == 0 and i % 8 == 0:
+                # offsets of this segment against the exact parallel curves
+                off = g[o["kind"] == O.KIND_OFFSET]
+                xf = sc.xforms[enc.xform_stream[mon[3][i]]]
+                w = float(sc.styles[enc.style_stream[mon[2][i]]]["half_width"])
+                P_, W = X.world_segment(enc.data, mon[0][i], enc.tags[i], xf)
+                A, B_, cusps = X.dense_offsets(P_, w, 0.02)
+                refpts = np.concatenate([A, B_] + [X.circle_pts(c, w) for c in cusps])
+                pts, _ = X.sample_outputs(off["x0"].astype(np.float64), off["y0"].astype(np.float64),
+                                          off["x1"].astype(np.float64), off["y1"].astype(np.float64),
+                                          off["curv"].astype(np.float64), 0.05)
+                worst_x = max(worst_x, X.max_dist(pts, refpts)[0])
+    _say("full c3: sampled worst endpoint", worst, "bulge", worst_b, "distance to exact", worst_x)
+    assert worst <= P.ENDPOINT_TOL
+    assert worst_b <= P.SWEEP_TOL
+    assert worst_x <= sc.tolerance
+    assert P.closed_per_path(recs) == 0
+
+
 @pytest.mark.parametrize("name", ["c1_lines", "c3_arcs"])
 def test_gpu_offsets_within_tolerance_of_exact_curve(ctx, name):
     """Every GPU offset record within tau of the FP64 exact parallel curves
