@@ -350,17 +350,21 @@ def served(args, ctx, B, S, torch, np):
         except B.StrokexError as e:
             if e.code != B.SX_ETOOSMALL:
                 raise
-    # warm the server's slots (arena and workspace growth happen here, untimed)
-    V.run_load(ctx, pool, segs, 1e6, len(pool), tol, mode, seed=1, max_seconds=30.0)
+    # one server for every load point; its slots are warmed first (arena and
+    # workspace growth happen here, untimed)
+    server = V.Server(ctx, tol, mode)
+    V.run_load(ctx, pool, segs, 1e6, 4 * len(pool), tol, mode, seed=1, max_seconds=30.0, server=server)
     points = []
     for qps in args.qps:
         n = int(max(50, min(2000, qps * args.serve_seconds)))
         log(f"bench: serving at {qps} req/s ({n} requests)")
-        srv = V.run_load(ctx, pool, segs, qps, n, tol, mode, seed=7, max_seconds=args.serve_seconds)
+        srv = V.run_load(ctx, pool, segs, qps, n, tol, mode, seed=7, max_seconds=args.serve_seconds,
+                         server=server)
         ser = V.run_serial(ctx, pool, segs, qps, n, tol, mode, seed=7, max_seconds=args.serve_seconds)
         points.append({"qps": qps, "served": srv, "serial_fifo": ser})
         log(f"bench:   served {srv}")
         log(f"bench:   serial {ser}")
+    server.close()
     return {
         "workload": f"Poisson arrivals, requests log-uniform 1k..1M segments from a pool of {len(pool)} "
                     f"encoded map scenes (mean {np.mean(segs):.0f} segments), {args.mode}, tol 0.25 px",

@@ -411,6 +411,11 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 if (!copied) fetch_tag(sv, i, ti, s);
                 if (copied) {
                     // done with this tag
+                } else if (!Write && ti.kind == kTagSegment && ti.line) {
+                    // a line is one straight piece (reading G32): no bisection
+                    nslots[i] = 2u;
+                    codes[(size_t)i * kKeepCodes] = slot_code(0u, 0u, false);
+                    if (Stats) n_lines++;
                 } else if (ti.kind == kTagSegment) {
                     bisect_init(bs, s);
                     busy = true;
@@ -726,21 +731,6 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
     if (Stats && joins) atomicAdd(&stats[kStJoins], (unsigned long long)joins);
 }
 
-// Record-kernel item classes: offset ranges placed by the density inverse,
-// other offset ranges, evolute bundles, joins and caps, empty units (second
-// units of two-unit items, holes).
-constexpr uint32_t kItemClasses = 5;
-__device__ __forceinline__ uint32_t item_class(uint32_t hdr) {
-    const uint32_t kind = hdr & 15u;
-    if (kind == 0u) return 4u;
-    if (kind == kItemOffset) return (hdr & kIfPlaceF) ? 0u : 1u;
-    return kind == kItemEvolute ? 2u : 3u;
-}
-
-// Record-kernel ordering key (the item class).
-constexpr uint32_t kSortKeys = kItemClasses;
-__device__ __forceinline__ uint32_t sort_key(uint32_t hdr) { return item_class(hdr); }
-
 // One item chunk starting at unit u: loads its one or two units and writes
 // its records.
 __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& ws, const Unit* u,
@@ -775,30 +765,13 @@ __global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, Item
     const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
     const uint32_t b = blockIdx.x;
     if (b < kRecGrid) {
-        // a tile's items, kRecBlock at a time, each round ordered by item
-        // class so that a wave runs items of one kind
-        __shared__ uint32_t s_order[kRecBlock];
-        __shared__ uint32_t s_cnt[kSortKeys];
-        const uint32_t t = threadIdx.x;
+        // a tile's units, one per thread (units in any order: every record's
+        // position comes from the scans)
         for (uint32_t tile = b; tile < n_tiles; tile += kRecGrid) {
             const uint32_t cnt = ws.tile_n[tile] < ws.region_cap ? ws.tile_n[tile] : ws.region_cap;
             const Unit* base = ws.units + (uint64_t)tile * ws.region_cap;
-            for (uint32_t r0 = 0; r0 < cnt; r0 += kRecBlock) {
-                // counting sort by key through LDS atomics (the order within
-                // a key is free: every record's position comes from the scans)
-                if (t < kSortKeys) s_cnt[t] = 0u;
-                __syncthreads();
-                const uint32_t key = (r0 + t < cnt) ? sort_key(base[r0 + t].w[0]) : kSortKeys - 1;
-                const uint32_t rank = atomicAdd(&s_cnt[key], 1u);
-                __syncthreads();
-                uint32_t pos = rank;
-                for (uint32_t c = 0; c < kSortKeys; c++) pos += (c < key) ? s_cnt[c] : 0u;
-                s_order[pos] = t;
-                __syncthreads();
-                const uint32_t s2 = r0 + s_order[t];
-                if (s2 < cnt) record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs);
-                __syncthreads();
-            }
+            for (uint32_t s2 = threadIdx.x; s2 < cnt; s2 += kRecBlock)
+                record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs);
         }
     } else {
         const uint64_t cnt = ws.ctl->ovf_n;

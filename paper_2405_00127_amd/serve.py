@@ -70,6 +70,7 @@ class _Slot:
         self.host = torch.zeros(2, dtype=torch.int64).pin_memory()
         self.host_offs = torch.zeros(1, dtype=torch.int64).pin_memory()
         self.reqs: List[Request] = []
+        self.single = None  # the scene of a one-request batch (run as a plain expansion)
         self.busy = False
         self.reruns = 0
 
@@ -82,17 +83,26 @@ class _Slot:
         if self.offs.numel() < n + 1:
             self.offs = torch.zeros(n + 1, dtype=torch.int64, device=dev)
             self.host_offs = torch.zeros(n + 1, dtype=torch.int64).pin_memory()
-        self.batch.set([r.scene for r in reqs], stream=self.stream)
+        # a request alone runs as a plain expansion of its own scene (no
+        # gather into the arena, no per-scene offsets)
+        self.single = reqs[0].scene if n == 1 else None
+        if self.single is None:
+            self.batch.set([r.scene for r in reqs], stream=self.stream)
         self._run()
         self.busy = True
 
     def _run(self):
         n = len(self.reqs)
-        self.batch.expand_async(self.tol, self.mode, self.out.data_ptr(), self.out.numel(), self.offs.data_ptr(),
-                                self.status.data_ptr(), stream=self.stream)
+        if self.single is not None:
+            self.ctx.expand_async(self.single, self.out.data_ptr(), self.out.numel(), self.status.data_ptr(),
+                                  self.tol, self.mode, stream=self.stream)
+        else:
+            self.batch.expand_async(self.tol, self.mode, self.out.data_ptr(), self.out.numel(),
+                                    self.offs.data_ptr(), self.status.data_ptr(), stream=self.stream)
         with __import__("torch").cuda.stream(self.stream):
             self.host.copy_(self.status, non_blocking=True)
-            self.host_offs[: n + 1].copy_(self.offs[: n + 1], non_blocking=True)
+            if self.single is None:
+                self.host_offs[: n + 1].copy_(self.offs[: n + 1], non_blocking=True)
         self.event.record(self.stream)
 
     def poll(self) -> bool:
@@ -109,11 +119,11 @@ class _Slot:
             if need:
                 from . import binding as B
 
-                # a synchronous expansion of the arena resizes its item workspace
-                arena = self.batch.arena()
+                # a synchronous expansion resizes the item workspace
+                scene = self.single if self.single is not None else self.batch.arena()
                 probe = torch.empty(16, dtype=torch.uint8, device=self.out.device)
                 try:
-                    total = self.ctx.expand_into(arena, probe.data_ptr(), 0, self.tol, self.mode, self.stream)
+                    total = self.ctx.expand_into(scene, probe.data_ptr(), 0, self.tol, self.mode, self.stream)
                 except B.StrokexError as e:
                     if e.code != B.SX_ETOOSMALL:
                         raise
@@ -123,7 +133,10 @@ class _Slot:
                 self.out = torch.empty(self.rec_budget * self.rec, dtype=torch.uint8, device=self.out.device)
             self._run()
             return False
-        offs = self.host_offs[: len(self.reqs) + 1].numpy()
+        if self.single is not None:
+            offs = np.array([0, total], dtype=np.int64)
+        else:
+            offs = self.host_offs[: len(self.reqs) + 1].numpy()
         for i, r in enumerate(self.reqs):
             r.first = int(offs[i])
             r.count = int(offs[i + 1] - offs[i])
@@ -227,14 +240,25 @@ def poisson_arrivals(seed: int, qps: float, n: int) -> np.ndarray:
 
 
 def run_load(ctx, pool, pool_segments, qps: float, n_requests: int, tolerance: float, mode: int, seed: int = 5,
-             max_seconds: float = 10.0, server_kwargs: Optional[dict] = None) -> Dict[str, float]:
-    """Drive the server with Poisson arrivals at ``qps`` over requests drawn
-    uniformly from ``pool`` (encoded scenes).  Returns throughput and latency
-    percentiles (ms)."""
+             max_seconds: float = 10.0, server_kwargs: Optional[dict] = None,
+             server: Optional["Server"] = None) -> Dict[str, float]:
+    """Drive a server with Poisson arrivals at ``qps`` over requests drawn
+    uniformly from ``pool`` (encoded scenes).  ``server``: an existing idle
+    server to reuse (its slots keep the arenas and workspaces earlier loads
+    grew; it is left open), else a new one is made and closed.  Returns
+    throughput and latency percentiles (ms)."""
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     arr = poisson_arrivals(seed, qps, n_requests)
     picks = rng.integers(0, len(pool), n_requests)
-    srv = Server(ctx, tolerance, mode, **(server_kwargs or {}))
+    own = server is None
+    srv = Server(ctx, tolerance, mode, **(server_kwargs or {})) if own else server
+    if not own:
+        if srv.busy():
+            raise ValueError("run_load needs an idle server")
+        srv.done = []
+        srv.batches = 0
+        for sl in srv.slots:
+            sl.reruns = 0
     t0 = time.perf_counter()
     i = 0
     while True:
@@ -261,7 +285,8 @@ def run_load(ctx, pool, pool_segments, qps: float, n_requests: int, tolerance: f
         "batches": srv.batches,
         "reruns": sum(sl.reruns for sl in srv.slots),
     }
-    srv.close()
+    if own:
+        srv.close()
     return out
 
 

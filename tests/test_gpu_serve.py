@@ -82,3 +82,31 @@ def test_server_results_equal_alone(ctx, mode, budget):
     if budget < 10_000:
         assert sum(sl.reruns for sl in srv.slots) > 0
     srv.close()
+
+
+def test_server_lone_request_on_a_fresh_scene(ctx):
+    """A request taken alone runs as a plain expansion of its scene; on a
+    scene never expanded before, its item workspace starts small, so the slot
+    sizes it and re-runs; the records equal the scene expanded alone."""
+    import time
+
+    from paper_2405_00127_amd import binding as B
+    from paper_2405_00127_amd import serve as V
+
+    tol, mode = 0.25, S.OUT_LINES
+    sc = S.scene_map(77, 30000, 300, tol, mode)
+    got = {}
+
+    def on_done(r, recs):
+        got[r.rid] = B.records_to_numpy(recs, mode).copy()
+
+    srv = V.Server(ctx, tol, mode, n_slots=1, rec_budget=1_000, on_done=on_done)
+    srv.submit(V.Request(0, ctx.encode(sc), sc.n_segments(), 0.0))
+    t0 = time.perf_counter()
+    while srv.busy() and time.perf_counter() < t0 + 60.0:
+        srv.step(0.0)
+    assert not srv.busy()
+    assert srv.batches == 1 and srv.slots[0].reruns >= 1
+    ref = _alone(ctx, ctx.encode(sc), tol, mode)
+    assert np.array_equal(got[0].view(np.uint8), ref.view(np.uint8))
+    srv.close()
