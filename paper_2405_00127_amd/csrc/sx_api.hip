@@ -268,6 +268,7 @@ bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
     cfg.arcs = mode == SX_OUT_ARCS;
     cfg.paper_fit = 0;
     cfg.K = 16;
+    sx::set_break_increments(cfg.xinc);
     return true;
 }
 

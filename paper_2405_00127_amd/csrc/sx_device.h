@@ -373,31 +373,55 @@ struct XSegT {
 };
 using XSeg = XSegT<double>;
 // Total F increment over [xa, xb], split at the branch breaks of f_approx
-// (the pieces in order of x from xa); *dxs receives the FP32 sum of
-// the pieces' lengths.
-SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs) {
-    const double bps[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
-    double dF = 0.0;
-    float ls = 0.0f;
+// (each piece within one branch, by its divided difference); *dxs receives
+// the FP32 sum of the pieces' lengths.  Pieces between two breaks have
+// fixed increments (xinc, see set_break_increments), so at most the two end
+// pieces are evaluated.
+constexpr double kXBreak[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
+SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs, const double* xinc) {
+    const bool up = xb.x > xa.x;
+    // the breaks strictly between xa and xb are consecutive ones: walk them
+    // from xa, summing the fixed increments between them
     int n = 0;
-    XP cur = xa;
-    bool up = xb.x > xa.x;
+    double bf = 0.0, bl = 0.0, mid = 0.0;
+    float lmid = 0.0f;
+#pragma unroll
     for (int kk = 0; kk < 6; kk++) {
-        int k = up ? kk : 5 - kk;
-        bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
-        if (inside) {
-            XP nb = bp_xp(bps[k]);
-            double l = bps[k] - cur.x;
-            dF += branch_dd(branch_of(fabs(cur.x + 0.5 * l)), cur, nb, l) * l;
-            ls += (float)l;
-            cur = nb;
+        const double b = up ? kXBreak[kk] : kXBreak[5 - kk];
+        const bool in = up ? (b > xa.x && b < xb.x) : (b < xa.x && b > xb.x);
+        if (in) {
+            if (n == 0) {
+                bf = b;
+            } else if (kk > 0) {
+                mid += up ? xinc[kk - 1] : -xinc[5 - kk];
+                lmid += (float)(b - bl);
+            }
+            bl = b;
             n++;
         }
     }
-    double l = (n == 0) ? dx_total : xb.x - cur.x;
-    int br = (n == 0) ? branch_of(fabs(0.5 * (xa.x + xb.x))) : branch_of(fabs(cur.x + 0.5 * l));
-    *dxs = ls + (float)l;
-    return dF + branch_dd(br, cur, xb, l) * l;
+    const bool cross = n > 0;
+    const double l1 = cross ? bf - xa.x : dx_total;
+    const int br1 = cross ? branch_of(fabs(xa.x + 0.5 * l1)) : branch_of(fabs(0.5 * (xa.x + xb.x)));
+    double dF = branch_dd(br1, xa, cross ? bp_xp(bf) : xb, l1) * l1;
+    float ls = (float)l1;
+    if (cross) {
+        const double l2 = xb.x - bl;
+        dF += mid;
+        dF += branch_dd(branch_of(fabs(bl + 0.5 * l2)), bp_xp(bl), xb, l2) * l2;
+        ls += lmid;
+        ls += (float)l2;
+    }
+    *dxs = ls;
+    return dF;
+}
+// F increments of the pieces between consecutive branch breaks (break k to
+// break k + 1), by the same divided differences.
+SX_HD inline void set_break_increments(double* xinc) {
+    for (int k = 0; k < 5; k++) {
+        const double a = kXBreak[k], b = kXBreak[k + 1], l = b - a;
+        xinc[k] = branch_dd(branch_of(fabs(a + 0.5 * l)), bp_xp(a), bp_xp(b), l) * l;
+    }
 }
 
 // Piece j of that split on its own (the same values and order), and the
@@ -585,6 +609,7 @@ struct Cfg {
     int arcs;
     int paper_fit;
     uint32_t K;                             // records per item chunk
+    double xinc[5];                         // F increments between the branch breaks
 };
 
 // Item sink: writes a tag's items into slots handed out by the allocator and
@@ -669,7 +694,7 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
             r.place = kIfPlaceF;
             const double hka = h * kna / L, hkb = h * knb / L;
             const double dx = -2.0 * h * k1 * du / L;
-            r.dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, &r.dxs);
+            r.dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, &r.dxs, cfg.xinc);
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
             double G = (dx != 0.0) ? r.dF / dx : 0.0;
             I = fabs(G) * du * L / (2.0 * sqrt(fabs(h)));
