@@ -327,20 +327,17 @@ SX_FN float pow15f(float a) { return a * sqrtf(a); }
 template <class T>
 SX_HD inline T branch_dd(int br, XPT<T> a, XPT<T> b, T dx) {
     if (br == 0) {
-        // cos(c1 m) sin(hz) / hz; on this branch |c1 m| < 0.88, and hz is
-        // small for all but very long pieces: both by their Taylor series
-        // (truncation below 1e-17 relative), else by the library functions.
+        // cos(c1 m) sin(hz) / hz.  A piece of this branch lies in
+        // [-0.8, 0.8], so |c1 m| < 0.88 and |hz| <= 0.8 c1 < 0.88: both by
+        // their Taylor series (truncation below 1e-18 relative for |hz| < 1).
         const T m = T(0.5) * (a.x + b.x);
         const T hz = T(0.5) * T(kC1) * dx;
         const T z = T(kC1) * m;
-        T sc;
-        if (absT(hz) < T(0.25)) {
-            const T h2 = hz * hz;
-            sc = T(1) + h2 * (T(-1.0 / 6) + h2 * (T(1.0 / 120) + h2 * (T(-1.0 / 5040) + h2 * (T(1.0 / 362880) +
-                 h2 * (T(-1.0 / 39916800) + h2 * (T(1.0 / 6227020800.0) + h2 * T(-1.0 / 1307674368000.0)))))));
-        } else {
-            sc = sin(hz) / hz;
-        }
+        const T h2 = hz * hz;
+        const T sc = T(1) + h2 * (T(-1.0 / 6) + h2 * (T(1.0 / 120) + h2 * (T(-1.0 / 5040) + h2 * (T(1.0 / 362880) +
+                     h2 * (T(-1.0 / 39916800) + h2 * (T(1.0 / 6227020800.0) + h2 * (T(-1.0 / 1307674368000.0) +
+                     h2 * (T(1.0 / 355687428096000.0) + h2 * (T(-1.0 / 121645100408832000.0) +
+                     h2 * T(1.0 / 51090942171709440000.0))))))))));
         const T z2 = z * z;
         const T cz = T(1) + z2 * (T(-1.0 / 2) + z2 * (T(1.0 / 24) + z2 * (T(-1.0 / 720) + z2 * (T(1.0 / 40320) +
                      z2 * (T(-1.0 / 3628800) + z2 * (T(1.0 / 479001600.0) + z2 * (T(-1.0 / 87178291200.0) +
