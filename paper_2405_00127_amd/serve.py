@@ -11,7 +11,10 @@ completion event.  The loop
      predicted record count into the output arena), gathers them into the
      slot's arena and launches the batched pipeline on the slot's stream --
      so requests that arrive while other batches run on the GPU join the next
-     free slot and their work overlaps on the device;
+     free slot and their work overlaps on the device.  A request taken alone
+     runs as a plain expansion of its own scene (no gather), unless another
+     slot is expanding that scene: a scene's own workspace serves one
+     expansion at a time;
   3. polls in-flight slots; a finished slot reports each request's record
      range and frees its memory.
 
@@ -74,7 +77,11 @@ class _Slot:
         self.busy = False
         self.reruns = 0
 
-    def launch(self, reqs: List[Request]):
+    def launch(self, reqs: List[Request], alone_ok: bool = True):
+        """Run ``reqs`` on the slot's stream.  ``alone_ok``: a single request
+        may run as a plain expansion of its own scene, which uses the scene's
+        own workspace -- only allowed when no other slot is expanding that
+        scene."""
         import torch
 
         self.reqs = reqs
@@ -85,7 +92,7 @@ class _Slot:
             self.host_offs = torch.zeros(n + 1, dtype=torch.int64).pin_memory()
         # a request alone runs as a plain expansion of its own scene (no
         # gather into the arena, no per-scene offsets)
-        self.single = reqs[0].scene if n == 1 else None
+        self.single = reqs[0].scene if (n == 1 and alone_ok) else None
         if self.single is None:
             self.batch.set([r.scene for r in reqs], stream=self.stream)
         self._run()
@@ -222,7 +229,10 @@ class Server:
                 take.append(r)
                 segs += r.n_segments
                 recs += p
-            sl.launch(take)
+            # a scene's own workspace serves one plain expansion at a time
+            alone_ok = len(take) == 1 and not any(
+                o is not sl and o.busy and o.single is take[0].scene for o in self.slots)
+            sl.launch(take, alone_ok)
             self.batches += 1
         return finished
 
