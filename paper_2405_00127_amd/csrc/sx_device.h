@@ -926,8 +926,19 @@ struct RecOut {
     uint64_t idx, end;
     uint32_t path;
     int arcs;
+    float* stage;        // staging copy of records [lo, hi) (LDS), or null
+    uint64_t lo, hi;
     SX_FN void put(V2 a, V2 b, float curv) {
-        if (idx < end) {
+        if (idx >= lo && idx < hi) {
+            float* r = stage + (idx - lo) * (arcs ? 6 : 5);
+            r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y;
+            if (arcs) {
+                r[4] = curv;
+                reinterpret_cast<uint32_t*>(r)[5] = path;
+            } else {
+                reinterpret_cast<uint32_t*>(r)[4] = path;
+            }
+        } else if (idx < end) {
             if (arcs) {
                 float* r = out + idx * 6;
                 r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y; r[4] = curv;

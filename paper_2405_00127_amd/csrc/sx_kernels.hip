@@ -472,6 +472,7 @@ constexpr int kTailGrid = 8192;   // grid cap of the tail kernel (tags stride by
 constexpr int kTailWin = 64;      // slot tiles a tail-kernel block counts in LDS
 constexpr int kRecBlock = 256;
 constexpr int kRecGrid = 8192;    // persistent grid of the record kernel
+constexpr uint32_t kStageWords = 7680;  // LDS words staging a tile's records (30 KB)
 constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the overflow slots
 
 // Slot allocator of one slot tile: the tile's own region first (LDS
@@ -735,7 +736,7 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
 // its records.
 __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& ws, const Unit* u,
                                             const uint64_t* roff, uint64_t n_slots, float* out, uint64_t cap,
-                                            int arcs) {
+                                            int arcs, float* stage = nullptr, uint64_t lo = 0, uint64_t hi = 0) {
     uint32_t w[2 * kUnitWords];
     const uint4* src = reinterpret_cast<const uint4*>(u);
 #pragma unroll
@@ -749,7 +750,7 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
     const uint32_t path = w[1], slot = w[2];
     if (slot >= n_slots) return;
     const uint64_t end = roff[slot + 1] < cap ? roff[slot + 1] : cap;
-    RecOut o{out, roff[slot] + w[3], end, path, arcs};
+    RecOut o{out, roff[slot] + w[3], end, path, arcs, stage, lo, hi};
     emit_item(w, ws.es_tab + 8 * (size_t)slot, o);
 }
 
@@ -767,11 +768,29 @@ __global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, Item
     if (b < kRecGrid) {
         // a tile's units, one per thread (units in any order: every record's
         // position comes from the scans)
+        // the tile's slots own one contiguous output range: records in its
+        // first kStageWords words are staged in LDS and copied out with
+        // coalesced stores once the tile is done
+        __shared__ float s_stage[kStageWords];
+        const uint32_t words = arcs ? 6u : 5u;
         for (uint32_t tile = b; tile < n_tiles; tile += kRecGrid) {
             const uint32_t cnt = ws.tile_n[tile] < ws.region_cap ? ws.tile_n[tile] : ws.region_cap;
             const Unit* base = ws.units + (uint64_t)tile * ws.region_cap;
+            const uint64_t s_lo = (uint64_t)tile * kSlotBlock;
+            const uint64_t s_hi = s_lo + kSlotBlock < n_slots ? s_lo + kSlotBlock : n_slots;
+            const uint64_t lo = roff[s_lo];
+            const uint64_t n_rec = roff[s_hi] - lo;
+            // (a tile whose items spilled into the overflow area is not
+            // staged: those records are written by the overflow blocks)
+            const uint64_t n_st = ws.tile_n[tile] > ws.region_cap ? 0u
+                                  : (n_rec < kStageWords / words ? n_rec : kStageWords / words);
             for (uint32_t s2 = threadIdx.x; s2 < cnt; s2 += kRecBlock)
-                record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs);
+                record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs, s_stage, lo, lo + n_st);
+            __syncthreads();
+            uint32_t* dst = reinterpret_cast<uint32_t*>(out) + lo * words;
+            const uint32_t* src = reinterpret_cast<const uint32_t*>(s_stage);
+            for (uint32_t d = threadIdx.x; d < (uint32_t)n_st * words; d += kRecBlock) dst[d] = src[d];
+            __syncthreads();
         }
     } else {
         const uint64_t cnt = ws.ctl->ovf_n;
