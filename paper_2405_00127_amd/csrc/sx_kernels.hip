@@ -141,9 +141,12 @@ __device__ Pair look_back(TileStatus* st, uint32_t tile, uint32_t epoch, int lan
             state = 3;
             v = Pair{0, 0};
             if (idx >= 0) {
-                if (read4(st[idx].inc, epoch, v)) state = 2;
-                else if (read4(st[idx].agg, epoch, v)) state = 1;
-                else state = 0;
+                // both records in one round trip, the inclusive one preferred
+                Pair vi, va;
+                const bool ri = read4(st[idx].inc, epoch, vi);
+                const bool ra = read4(st[idx].agg, epoch, va);
+                state = ri ? 2u : (ra ? 1u : 0u);
+                v = ri ? vi : va;
             }
             if (__ballot(state == 0u) == 0ull) break;
             if (spins >= kSpinLimit) {
@@ -346,12 +349,22 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
             for (int j = 0; j < kScanItems; j++) item[j] = Pair{(base + j < n) ? (uint64_t)in[base + j] : 0ull, 0};
         }
     };
+    // the exclusive sums go out through LDS, so that consecutive threads
+    // store consecutive words (a thread's own items are kScanItems apart)
+    __shared__ uint64_t s_out[kScanTile];
     auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
+        const uint32_t t0 = threadIdx.x * kScanItems;
 #pragma unroll
         for (int j = 0; j < kScanItems; j++) {
-            uint64_t ex = pre.a + (j > 0 ? incl[j - 1].a : 0ull);
-            if (base + j < n) out[base + j] = ex;
+            s_out[t0 + j] = pre.a + (j > 0 ? incl[j - 1].a : 0ull);
             if (base + j == (uint64_t)n - 1u) out[n] = pre.a + incl[j].a;
+        }
+        __syncthreads();
+        const uint64_t tile_base = base - t0;
+#pragma unroll
+        for (int j = 0; j < kScanItems; j++) {
+            const uint32_t k = j * kScanBlock + threadIdx.x;
+            if (tile_base + k < n) out[tile_base + k] = s_out[k];
         }
     };
     scan_tile(load, store, n, ctl, st);
