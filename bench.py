@@ -420,9 +420,12 @@ def phase_of_kernel(name: str):
     m = re.search(r"sx::bisect_kernel<(true|false), (true|false), \d+>", name)
     if m:
         return None if m.group(2) == "true" else ("bisect_write" if m.group(1) == "true" else "bisect_count")
-    m = re.search(r"sx::slot_kernel<\d+, (true|false), (true|false)>", name)
+    m = re.search(r"sx::slot_kernel<\d+, (true|false)>", name)
     if m:
-        return None if m.group(1) == "true" else ("tails" if m.group(2) == "true" else "pieces")
+        return None if m.group(1) == "true" else "pieces"
+    m = re.search(r"sx::tail_kernel<(true|false)>", name)
+    if m:
+        return None if m.group(1) == "true" else "tails"
     return None
 
 
@@ -460,7 +463,44 @@ def summarize_counters(fetch_db: str, write_db: str, probe_mb: int, mode: str, c
     return out
 
 
+def summarize_valu(db: str, n_cu: int = 256, n_xcd: int = 8):
+    """Per phase, from one rocprofv3 --pmc database with SQ_INSTS_VALU,
+    SQ_ACTIVE_INST_VALU, SQ_THREAD_CYCLES_VALU, SQ_INSTS_SALU,
+    SQ_INSTS_VALU_TRANS_F64 and GRBM_GUI_ACTIVE: VALU busy (share of the CUs'
+    cycles issuing VALU work: ACTIVE_INST_VALU / (CUs x GUI cycles), GUI
+    cycles = GRBM_GUI_ACTIVE summed over the XCDs / XCDs) and VALU lane
+    utilisation (THREAD_CYCLES_VALU / (64 x ACTIVE_INST_VALU)), averaged over
+    dispatches."""
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, dispatch_id, counter_name, value from counters_collection").fetchall()
+    con.close()
+    per = {}
+    for k, d, c, v in rows:
+        ph = phase_of_kernel(k)
+        if ph is not None:
+            per.setdefault(ph, {}).setdefault(d, {})[c] = per.get(ph, {}).get(d, {}).get(c, 0.0) + v
+    out = {}
+    for ph, ds in per.items():
+        def avg(c):
+            return sum(x.get(c, 0.0) for x in ds.values()) / len(ds)
+
+        gui = avg("GRBM_GUI_ACTIVE") / n_xcd
+        act = avg("SQ_ACTIVE_INST_VALU")
+        out[ph] = {"dispatches": len(ds), "gui_cycles": gui,
+                   "valu_busy_pct": 100.0 * act / (n_cu * gui) if gui else None,
+                   "valu_lane_util_pct": 100.0 * avg("SQ_THREAD_CYCLES_VALU") / (64.0 * act) if act else None,
+                   "valu_insts": avg("SQ_INSTS_VALU"), "salu_insts": avg("SQ_INSTS_SALU"),
+                   "valu_trans_f64_insts": avg("SQ_INSTS_VALU_TRANS_F64")}
+    return out
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-valu":
+        # offline: bench.py --summarize-valu DB
+        print(json.dumps(summarize_valu(sys.argv[2]), indent=1))
+        return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
         # offline: bench.py --summarize-counters FETCH_DB WRITE_DB PROBE_MB MODE [COMMAND ...]
         fetch_db, write_db, probe_mb, mode = sys.argv[2:6]
