@@ -13,12 +13,14 @@
 //                         device).  Replaces the paper's atomic bump
 //                         allocation: the output order is canonical.
 //  slot_kernel            per piece slot, the Euler spiral, parallel curves,
-//                         cusp split, evolutes and counts (Sections 4-6); per
-//                         tail slot, the join or cap (Algorithm 1).  Writes
-//                         emission items into per-tile workspace regions and
-//                         the slot's record count.
+//                         cusp split, evolutes and counts (Sections 4-6).
+//                         Writes emission items into per-tile workspace
+//                         regions and the slot's record count.
+//  tail_kernel            per tag, its tail slot: the join or cap
+//                         (Algorithm 1), items into the same regions.
 //  record_kernel          per item chunk, the FP32 per-point work: records
-//                         at roff[slot] + the chunk's position in its slot.
+//                         at roff[slot] + the chunk's position in its slot,
+//                         staged per tile in LDS and written coalesced.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
