@@ -152,3 +152,67 @@ def test_empty_batch(ctx):
     torch.cuda.synchronize()
     assert int(offs[0]) == 0 and int(status[0]) == 0 and int(status[1]) == 0
     batch.destroy()
+
+
+def test_full_size_batch_of_256_scenes(ctx):
+    """The 256-scene batch the benchmark times (log-uniform 100..200k
+    segments, 8.4 M in total), captured in a graph and replayed: every
+    scene's records bit-identical to the scene expanded alone, and sampled
+    tags of sampled scenes against the oracle (counts, endpoints, path ids)."""
+    import torch
+
+    import oracle as O
+    from paper_2405_00127_amd import binding as B
+
+    tol, mode = 0.25, S.OUT_LINES
+    _say("full batch: generate")
+    scs = S.scene_batch(4, 256, 100, 200_000, mode)
+    _say("full batch: segments", sum(s.n_segments() for s in scs))
+    stream = torch.cuda.Stream()
+    scenes = [ctx.encode(s, stream=stream) for s in scs]
+    stream.synchronize()
+    alone = [_alone(ctx, s, tol, mode) for s in scenes]
+    batch = B.Batch(ctx)
+    batch.set(scenes, stream=stream)
+    out, offs, status = batch.prepare(tol, mode, stream=stream)
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        batch.expand_async(tol, mode, out.data_ptr(), out.numel(), offs.data_ptr(), status.data_ptr(),
+                           stream=stream)
+    for rep in range(2):
+        out.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o = offs.cpu().numpy()
+        assert int(status[1]) == 0 and int(status[0]) == o[-1] == sum(len(a) for a in alone)
+        got = _slices(out, o, mode)
+        bad = [i for i in range(len(scs)) if not np.array_equal(got[i].view(np.uint8), alone[i].view(np.uint8))]
+        assert not bad, bad
+        _say("full batch: replay", rep, "records", int(o[-1]), "all scenes identical to alone")
+    # sampled tags of sampled scenes against the oracle
+    rng = np.random.default_rng(44)
+    worst = 0.0
+    import parity as P
+
+    for k in rng.choice(len(scs), 6, replace=False):
+        sc = scs[int(k)]
+        counts = ctx.counts(scenes[int(k)], tol, mode).cpu().numpy().astype(np.uint32)
+        ref = O.expand(sc, emit=False)
+        near = P.near_threshold(ref.margins)
+        mism = counts != ref.counts
+        assert not np.any(mism & ~near)
+        go = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
+        for i in np.sort(rng.choice(np.nonzero(~mism)[0], min(50, int((~mism).sum())), replace=False)):
+            r = O.expand(sc, emit=True, tag_begin=int(i), tag_end=int(i) + 1, enc=ref.enc)
+            gg = got[int(k)][go[i]:go[i + 1]]
+            assert len(gg) == len(r.out)
+            if len(gg):
+                d = max(np.max(np.abs(gg["x0"] - r.out["x0"])), np.max(np.abs(gg["y0"] - r.out["y0"])),
+                        np.max(np.abs(gg["x1"] - r.out["x1"])), np.max(np.abs(gg["y1"] - r.out["y1"])))
+                worst = max(worst, float(d))
+                assert np.all(gg["path"] == r.out["path"])
+    _say("full batch: sampled worst endpoint", worst)
+    assert worst <= P.ENDPOINT_TOL
+    batch.destroy()
