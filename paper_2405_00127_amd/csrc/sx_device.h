@@ -1006,7 +1006,15 @@ SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t
         w.dF = p.dF;
         w.dxs = p.dxs;
         w.nseg = xseg_count(w.xa, w.xb);
-        w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
+        if (w.nseg == 1) {
+            // one branch piece: its increment is the range's (decided in FP64)
+            w.seg.a = w.xa;
+            w.seg.len = w.dx;
+            w.seg.br = branch_of(absT(0.5f * (w.xa.x + w.xb.x)));
+            w.seg.dF = w.dF;
+        } else {
+            w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
+        }
     }
 }
 
@@ -1024,7 +1032,7 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
             w.j++;
             w.seg = xseg_at(w.xa, w.xb, w.dx, w.j);
         }
-        float fl = (w.seg.dF != 0.0f) ? (target - w.cum) / w.seg.dF : 0.0f;
+        float fl = (w.nseg == 1) ? f : ((w.seg.dF != 0.0f) ? (target - w.cum) / w.seg.dF : 0.0f);
         fl = fminf(fmaxf(fl, 0.0f), 1.0f);
         const float phi = (w.seg.len != 0.0f) ? branch_inv_frac(w.seg, fl) : fl;
         tau = (w.nseg == 1) ? phi : (w.acc_len + phi * w.seg.len) / w.dxs;
