@@ -400,6 +400,7 @@ struct XSegT {
     XPT<T> a;
     T len;  // signed x length
     T dF;   // F increment over the piece
+    T G;    // dF / len (the piece's divided difference)
     int br;
 };
 using XSeg = XSegT<double>;
@@ -482,7 +483,8 @@ SX_HD inline XSegT<T> xseg_at(XPT<T> xa, XPT<T> xb, T dx_total, int j) {
                 sg.a = cur;
                 sg.len = l;
                 sg.br = branch_of(absT(cur.x + T(0.5) * l));
-                sg.dF = branch_dd(sg.br, cur, nb, l) * l;
+                sg.G = branch_dd(sg.br, cur, nb, l);
+                sg.dF = sg.G * l;
                 return sg;
             }
             cur = bp_xp(bps[k]);
@@ -493,14 +495,15 @@ SX_HD inline XSegT<T> xseg_at(XPT<T> xa, XPT<T> xb, T dx_total, int j) {
     sg.a = cur;
     sg.len = l;
     sg.br = (n == 0) ? branch_of(absT(T(0.5) * (xa.x + xb.x))) : branch_of(absT(cur.x + T(0.5) * l));
-    sg.dF = branch_dd(sg.br, cur, xb, l) * l;
+    sg.G = branch_dd(sg.br, cur, xb, l);
+    sg.dF = sg.G * l;
     return sg;
 }
 
 // Fraction of a branch segment at which F has risen by f * seg.dF
 // (local, cancellation-free inverse of f_approx; FP32 per output point).
 SX_HD inline float branch_inv_frac(const XSegT<float>& s, float f) {
-    const float G = s.dF / s.len;  // divided difference (len != 0 here)
+    const float G = s.G;  // divided difference (len != 0 here)
     const float ax = s.a.x, ae = s.a.e, dF = s.dF, ln = s.len;
     if (s.br == 0) {
         const float c1 = (float)kC1;
@@ -988,6 +991,7 @@ struct XWalk {
 struct Place {
     XWalk w;
     float kna, knb;
+    float inv_n;  // 1 / (records of the range)
 };
 SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t hdr) {
     pl.kna = es.fk0 + es.fk1 * (p.ua - 0.5f);
@@ -1012,6 +1016,7 @@ SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t
             w.seg.len = w.dx;
             w.seg.br = branch_of(absT(0.5f * (w.xa.x + w.xb.x)));
             w.seg.dF = w.dF;
+            w.seg.G = (w.dx != 0.0f) ? w.dF / w.dx : 0.0f;
         } else {
             w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
         }
@@ -1020,7 +1025,7 @@ SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t
 
 // u of point i (0 < i < n) of an offset range
 SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, Place& pl) {
-    const float f = (float)i / (float)n;
+    const float f = (float)i * pl.inv_n;
     float tau = f;
     if (hdr & kIfPlaceF) {
         // advance to the branch piece holding f * dF
@@ -1077,6 +1082,7 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) 
         Place pl;
         place_init(pl, es, p, hdr);
         const uint32_t n = h.ntot;
+        pl.inv_n = 1.0f / (float)n;
         const bool neg = (hdr & kIfDirNeg) != 0;
         // point k0 of the chunk
         float uprev;
@@ -1114,10 +1120,11 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) 
         const uint32_t ne = p.ne;
         const bool Dneg = (hdr & kIfDneg) != 0;
         const V2 E0 = v2(p.E0x, p.E0y), E1 = v2(p.E1x, p.E1y), Pa = v2(p.Pax, p.Pay), Pb = v2(p.Pbx, p.Pby);
+        const float inv_ne = 1.0f / (float)ne;
         auto ev = [&](uint32_t i) -> V2 {
             if (i == 0) return E0;
             if (i == ne) return E1;
-            const float f = (float)i / (float)ne;
+            const float f = (float)i * inv_ne;
             const float tau = f * (2.0f * p.alpha + f * (1.0f - 2.0f * p.alpha));
             return evolute_point_f(es, p.ua + p.du * tau);
         };
@@ -1168,10 +1175,11 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) 
                 if (j == 0) o.line(from, A); else if (j == 1) o.line(A, B); else o.line(B, to);
             } else {
                 const uint32_t nr = p.n_outer;
+                const float inv_nr = 1.0f / (float)nr;
                 auto rp = [&](uint32_t q) -> V2 {
                     if (q == 0) return from;
                     if (q == nr) return to;
-                    const float a = p.a0 + p.sweep * ((float)q / (float)nr);
+                    const float a = p.a0 + p.sweep * ((float)q * inv_nr);
                     float sn, cs;
                     sincos_r(a, &sn, &cs);
                     return v2(p.px + p.w * cs, p.py + p.w * sn);
