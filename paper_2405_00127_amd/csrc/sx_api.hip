@@ -303,7 +303,7 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
             return sx::launch_scan_counts_dev(s->d_rc, n_slots_dev(s), (uint32_t)s->slot_cap, s->d_roff,
                                               ctl_block(s, 2), s->d_status_rc, st);
         case kPhRecords:
-            return sx::launch_records(view(s), workspace(s), cfg.arcs, s->d_roff, n_slots_dev(s), s->slot_cap, out,
+            return sx::launch_records(view(s), workspace(s), cfg, s->d_roff, n_slots_dev(s), s->slot_cap, out,
                                       cap_records, st);
     }
     return hipErrorInvalidValue;

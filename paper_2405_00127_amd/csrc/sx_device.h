@@ -405,18 +405,20 @@ struct XSegT {
 };
 using XSeg = XSegT<double>;
 // Total F increment over [xa, xb], split at the branch breaks of f_approx
-// (each piece within one branch, by its divided difference); *dxs receives
-// the FP32 sum of the pieces' lengths.  Pieces between two breaks have
-// fixed increments (xinc, see set_break_increments), so at most the two end
-// pieces are evaluated.
+// (each piece within one branch, by its divided difference).  Pieces
+// between two breaks have fixed increments (xinc, see set_break_increments),
+// so at most the two end pieces are evaluated.  *dF0 and *len0 receive the
+// first piece's increment and x length, *xbits the split: breaks crossed
+// (bits 0-2), index of the first one crossed (bits 3-5), walking up the x
+// axis (bit 6).
 constexpr double kXBreak[6] = {-2.1, -1.25, -0.8, 0.8, 1.25, 2.1};
-SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs, const double* xinc) {
+SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, const double* xinc, double* dF0, double* len0,
+                                uint32_t* xbits) {
     const bool up = xb.x > xa.x;
     // the breaks strictly between xa and xb are consecutive ones: walk them
     // from xa, summing the fixed increments between them
-    int n = 0;
+    int n = 0, kf = 0;
     double bf = 0.0, bl = 0.0, mid = 0.0;
-    float lmid = 0.0f;
 #pragma unroll
     for (int kk = 0; kk < 6; kk++) {
         const double b = up ? kXBreak[kk] : kXBreak[5 - kk];
@@ -424,9 +426,9 @@ SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs, const
         if (in) {
             if (n == 0) {
                 bf = b;
+                kf = up ? kk : 5 - kk;
             } else if (kk > 0) {
                 mid += up ? xinc[kk - 1] : -xinc[5 - kk];
-                lmid += (float)(b - bl);
             }
             bl = b;
             n++;
@@ -436,15 +438,14 @@ SX_HD inline double split_x_sum(XP xa, XP xb, double dx_total, float* dxs, const
     const double l1 = cross ? bf - xa.x : dx_total;
     const int br1 = cross ? branch_of(fabs(xa.x + 0.5 * l1)) : branch_of(fabs(0.5 * (xa.x + xb.x)));
     double dF = branch_dd(br1, xa, cross ? bp_xp(bf) : xb, l1) * l1;
-    float ls = (float)l1;
+    *dF0 = dF;
+    *len0 = l1;
     if (cross) {
         const double l2 = xb.x - bl;
         dF += mid;
         dF += branch_dd(branch_of(fabs(bl + 0.5 * l2)), bp_xp(bl), xb, l2) * l2;
-        ls += lmid;
-        ls += (float)l2;
     }
-    *dxs = ls;
+    *xbits = (uint32_t)n | ((uint32_t)kf << 3) | (up ? 64u : 0u);
     return dF;
 }
 // F increments of the pieces between consecutive branch breaks (break k to
@@ -454,50 +455,6 @@ SX_HD inline void set_break_increments(double* xinc) {
         const double a = kXBreak[k], b = kXBreak[k + 1], l = b - a;
         xinc[k] = branch_dd(branch_of(fabs(a + 0.5 * l)), bp_xp(a), bp_xp(b), l) * l;
     }
-}
-
-// Piece j of that split on its own (the same values and order), and the
-// number of pieces.
-template <class T>
-SX_HD inline int xseg_count(XPT<T> xa, XPT<T> xb) {
-    const T bps[6] = {T(-2.1), T(-1.25), T(-0.8), T(0.8), T(1.25), T(2.1)};
-    const bool up = xb.x > xa.x;
-    int n = 1;
-    for (int k = 0; k < 6; k++) n += (up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x)) ? 1 : 0;
-    return n;
-}
-template <class T>
-SX_HD inline XSegT<T> xseg_at(XPT<T> xa, XPT<T> xb, T dx_total, int j) {
-    const T bps[6] = {T(-2.1), T(-1.25), T(-0.8), T(0.8), T(1.25), T(2.1)};
-    int n = 0;
-    XPT<T> cur = xa;
-    const bool up = xb.x > xa.x;
-    XSegT<T> sg;
-    for (int kk = 0; kk < 6; kk++) {
-        const int k = up ? kk : 5 - kk;
-        const bool inside = up ? (bps[k] > xa.x && bps[k] < xb.x) : (bps[k] < xa.x && bps[k] > xb.x);
-        if (inside) {
-            if (n == j) {
-                const XPT<T> nb = bp_xp(bps[k]);
-                const T l = bps[k] - cur.x;
-                sg.a = cur;
-                sg.len = l;
-                sg.br = branch_of(absT(cur.x + T(0.5) * l));
-                sg.G = branch_dd(sg.br, cur, nb, l);
-                sg.dF = sg.G * l;
-                return sg;
-            }
-            cur = bp_xp(bps[k]);
-            n++;
-        }
-    }
-    const T l = (n == 0) ? dx_total : xb.x - cur.x;
-    sg.a = cur;
-    sg.len = l;
-    sg.br = (n == 0) ? branch_of(absT(T(0.5) * (xa.x + xb.x))) : branch_of(absT(cur.x + T(0.5) * l));
-    sg.G = branch_dd(sg.br, cur, xb, l);
-    sg.dF = sg.G * l;
-    return sg;
 }
 
 // Fraction of a branch segment at which F has risen by f * seg.dF
@@ -574,6 +531,7 @@ constexpr uint32_t kIfEndB = 1u << 10;      // evolute: connecting lines at ub
 constexpr uint32_t kIfDneg = 1u << 11;      // evolute: side traversed backwards
 constexpr uint32_t kIfInnerFirst = 1u << 12;  // join: inner part before the outer part
 constexpr uint32_t kIfKSame = 1u << 13;       // offset, h == 0: curvature keeps its sign over the range
+constexpr uint32_t kXBitsShift = 16;          // offset: the split at the branch breaks (bits 16-22)
 // join outer part kind (bits 16..19), inner part kind (bits 20..21)
 enum { kOutLine1 = 0, kOutLine2 = 1, kOutLine3 = 2, kOutRound = 3 };
 enum { kInNone = 0, kInPivot = 1, kInSmooth = 2 };
@@ -601,9 +559,9 @@ SX_FN uint32_t item_n(uint32_t hdr) { return hdr >> 24; }
 // and for density placement the F increment over the range and the FP32 sum
 // of its branch pieces' x lengths (from the FP64 count)
 struct OffsetP {
-    float ua, du, ub, fh;
+    float ua, du, len0, fh;  // u range, x length of its first branch piece, side h
     float Pax, Pay, Pbx, Pby;
-    float dF, dxs;
+    float dF, dF0;  // F increment of the range and of its first branch piece
 };
 // evolute-item payload: the range, its density split alpha and evolute
 // count, the exact offset and evolute end points
@@ -699,8 +657,8 @@ struct ItemSink {
 // range; writing its items needs the rest.
 struct RangeRes {
     double dF;          // F increment over the range (density placement)
-    float dxs, alpha;   // FP32 sum of the x pieces' lengths; evolute point split
-    uint32_t n, ne, place;
+    float dF0, len0, alpha;  // increment and x length of its first branch piece; evolute point split
+    uint32_t n, ne, place, xbits;  // xbits: the split at the branch breaks (split_x_sum)
 };
 SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, double h, double ua, double ub,
                            bool reversed) {
@@ -708,8 +666,10 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
     const double du = ub - ua;
     const double kna = k0 + k1 * (ua - 0.5), knb = k0 + k1 * (ub - 0.5);
     r.dF = 0.0;
-    r.dxs = 0.0f;
+    r.dF0 = 0.0f;
+    r.len0 = 0.0f;
     r.place = 0;
+    r.xbits = 0;
     if (!cfg.arcs) {
         double I;
         if (k1 == 0.0) {
@@ -728,7 +688,10 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
             r.place = kIfPlaceF;
             const double hka = h * kna / L, hkb = h * knb / L;
             const double dx = -2.0 * h * k1 * du / L;
-            r.dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, &r.dxs, cfg.xinc);
+            double d0, l0;
+            r.dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, cfg.xinc, &d0, &l0, &r.xbits);
+            r.dF0 = (float)d0;
+            r.len0 = (float)l0;
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
             double G = (dx != 0.0) ? r.dF / dx : 0.0;
             I = fabs(G) * du * L / (2.0 * sqrt(fabs(h)));
@@ -770,11 +733,11 @@ SX_FN void range_put(Sink& k, const Cfg& cfg, const ES& es, double h, double ua,
     const double du = ub - ua;
     {
         OffsetP p;
-        p.ua = (float)ua; p.du = (float)du; p.ub = (float)ub; p.fh = (float)h;
-        p.dF = (float)r.dF; p.dxs = r.dxs;
+        p.ua = (float)ua; p.du = (float)du; p.len0 = r.len0; p.fh = (float)h;
+        p.dF = (float)r.dF; p.dF0 = r.dF0;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
         uint32_t hdr = kItemOffset | (dir < 0 ? kIfDirNeg : 0u) | (cfg.arcs ? kIfArcs : 0u) |
-                       (es.pivot ? kIfPivot : 0u) | r.place;
+                       (es.pivot ? kIfPivot : 0u) | r.place | (r.xbits << kXBitsShift);
         k.put(hdr, r.n, cfg.K, p);
     }
     if (reversed) {
@@ -979,11 +942,45 @@ SX_FN ES es_from_f(const float* d, bool pivot) {
 // share of F only moves forward; the pieces are produced one at a time.
 struct XWalk {
     XPT<float> xa, xb;
-    float dx, cum, dF, dxs;
+    float dx;  // xb.x - xa.x, cancellation-free
+    float cum, dF, dF0, len0;
     XSegT<float> seg;
-    int j, nseg;
+    int j, nseg, kf;
+    bool up;
     float acc_len;
 };
+
+// the branch breaks of f_approx and the increments between them, as floats
+SX_FN float xbreak_f(int k) {
+    return k == 0 ? -2.1f : (k == 1 ? -1.25f : (k == 2 ? -0.8f : (k == 3 ? 0.8f : (k == 4 ? 1.25f : 2.1f))));
+}
+struct XIncF {
+    float v[5];
+};
+SX_FN float xinc_f(const XIncF& t, int k) {
+    return k == 0 ? t.v[0] : (k == 1 ? t.v[1] : (k == 2 ? t.v[2] : (k == 3 ? t.v[3] : t.v[4])));
+}
+
+// Branch piece j of an offset range's density axis (the split the piece
+// stage decided): from xa or the (j-1)-th break crossed to the j-th break
+// or xb.  Increments: the first piece's and the total come from the FP64
+// decisions, the pieces between breaks from the fixed increments, the last
+// one is the rest.
+SX_FN void walk_piece(XWalk& w, const XIncF& xi, int j) {
+    const int nc = w.nseg - 1;
+    const int kprev = w.up ? w.kf + j - 1 : w.kf - j + 1;
+    const int knext = w.up ? w.kf + j : w.kf - j;
+    const float a = (j == 0) ? w.xa.x : xbreak_f(kprev);
+    const float e = (j < nc) ? xbreak_f(knext) : w.xb.x;
+    w.seg.a = (j == 0) ? w.xa : bp_xp(a);
+    // lengths from the decided first piece and the exact breaks; the last
+    // piece is the rest of the cancellation-free total
+    w.seg.len = (j == 0) ? w.len0 : ((j < nc) ? e - a : w.dx - w.acc_len);
+    w.seg.dF = (j == 0) ? (nc ? w.dF0 : w.dF)
+                        : ((j < nc) ? (w.up ? xinc_f(xi, kprev) : -xinc_f(xi, knext)) : w.dF - w.cum);
+    w.seg.G = (w.seg.len != 0.0f) ? w.seg.dF / w.seg.len : 0.0f;
+    w.seg.br = branch_of(absT(a + 0.5f * w.seg.len));
+}
 
 // Point placement data of an offset range, from the piece's FP32 spiral:
 // the density axis of side h (the counts were decided in FP64; here the
@@ -993,38 +990,32 @@ struct Place {
     float kna, knb;
     float inv_n;  // 1 / (records of the range)
 };
-SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t hdr) {
+SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t hdr, const XIncF& xi) {
     pl.kna = es.fk0 + es.fk1 * (p.ua - 0.5f);
-    pl.knb = es.fk0 + es.fk1 * (p.ub - 0.5f);
+    pl.knb = es.fk0 + es.fk1 * (p.ua + p.du - 0.5f);
     XWalk& w = pl.w;
     w.j = 0;
     w.nseg = 1;
     w.cum = 0.0f;
     w.acc_len = 0.0f;
     w.dF = 0.0f;
-    w.dxs = 0.0f;
     if (hdr & kIfPlaceF) {
         w.xa = make_xp(p.fh * pl.kna / es.fL);
         w.xb = make_xp(p.fh * pl.knb / es.fL);
         w.dx = -2.0f * p.fh * es.fk1 * p.du / es.fL;
         w.dF = p.dF;
-        w.dxs = p.dxs;
-        w.nseg = xseg_count(w.xa, w.xb);
-        if (w.nseg == 1) {
-            // one branch piece: its increment is the range's (decided in FP64)
-            w.seg.a = w.xa;
-            w.seg.len = w.dx;
-            w.seg.br = branch_of(absT(0.5f * (w.xa.x + w.xb.x)));
-            w.seg.dF = w.dF;
-            w.seg.G = (w.dx != 0.0f) ? w.dF / w.dx : 0.0f;
-        } else {
-            w.seg = xseg_at(w.xa, w.xb, w.dx, 0);
-        }
+        w.dF0 = p.dF0;
+        w.len0 = p.len0;
+        const uint32_t xbits = (hdr >> kXBitsShift) & 127u;
+        w.nseg = 1 + (int)(xbits & 7u);
+        w.kf = (int)((xbits >> 3) & 7u);
+        w.up = (xbits & 64u) != 0u;
+        walk_piece(w, xi, 0);
     }
 }
 
 // u of point i (0 < i < n) of an offset range
-SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, Place& pl) {
+SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t n, Place& pl, const XIncF& xi) {
     const float f = (float)i * pl.inv_n;
     float tau = f;
     if (hdr & kIfPlaceF) {
@@ -1035,12 +1026,12 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
             w.cum += w.seg.dF;
             w.acc_len += w.seg.len;
             w.j++;
-            w.seg = xseg_at(w.xa, w.xb, w.dx, w.j);
+            walk_piece(w, xi, w.j);
         }
         float fl = (w.nseg == 1) ? f : ((w.seg.dF != 0.0f) ? (target - w.cum) / w.seg.dF : 0.0f);
         fl = fminf(fmaxf(fl, 0.0f), 1.0f);
         const float phi = (w.seg.len != 0.0f) ? branch_inv_frac(w.seg, fl) : fl;
-        tau = (w.nseg == 1) ? phi : (w.acc_len + phi * w.seg.len) / w.dxs;
+        tau = (w.nseg == 1 || w.dx == 0.0f) ? phi : (w.acc_len + phi * w.seg.len) / w.dx;
     } else if (hdr & kIfPlaceES) {
         // h = 0: uniform in |kappa|^1.5 (Section 2.2)
         const float aa = fabsf(pl.kna), ab = fabsf(pl.knb);
@@ -1069,7 +1060,7 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
 
 // One item chunk (header + payload words) into records; es: the slot's
 // spiral (8 floats) for offset and evolute items.
-SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) {
+SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, const XIncF& xi, RecOut& o) {
     const ItemHdr h = *reinterpret_cast<const ItemHdr*>(it);
     const uint32_t* pw = it + kHdrWords;
     const uint32_t hdr = h.hdr;
@@ -1080,7 +1071,7 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) 
         const OffsetP p = *reinterpret_cast<const OffsetP*>(pw);
         const ES es = es_from_f(es_rec, (hdr & kIfPivot) != 0);
         Place pl;
-        place_init(pl, es, p, hdr);
+        place_init(pl, es, p, hdr, xi);
         const uint32_t n = h.ntot;
         pl.inv_n = 1.0f / (float)n;
         const bool neg = (hdr & kIfDirNeg) != 0;
@@ -1091,7 +1082,7 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) 
             uprev = p.ua;
             prev = v2(p.Pax, p.Pay);
         } else {
-            uprev = offset_u(p, hdr, h.k0, n, pl);
+            uprev = offset_u(p, hdr, h.k0, n, pl, xi);
             prev = offset_point_f(es, p.fh, uprev);
         }
         for (uint32_t r = 0; r < nrec; r++) {
@@ -1099,10 +1090,10 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, RecOut& o) 
             float u;
             V2 P;
             if (i == n) {
-                u = p.ub;
+                u = p.ua + p.du;
                 P = v2(p.Pbx, p.Pby);
             } else {
-                u = offset_u(p, hdr, i, n, pl);
+                u = offset_u(p, hdr, i, n, pl, xi);
                 P = offset_point_f(es, p.fh, u);
             }
             if (!arcs) {

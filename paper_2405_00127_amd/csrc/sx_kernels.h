@@ -62,7 +62,7 @@ hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, c
 // tail slots (one thread per tag), after launch_slots
 hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const uint64_t* base,
                         uint64_t slot_cap, uint32_t* rc, unsigned long long* stats, hipStream_t s);
-hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff,
                           const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s);
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
                          float* xforms, uint32_t* path_map, hipStream_t s);

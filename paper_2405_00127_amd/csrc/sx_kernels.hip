@@ -751,7 +751,8 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
 // its records.
 __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& ws, const Unit* u,
                                             const uint64_t* roff, uint64_t n_slots, float* out, uint64_t cap,
-                                            int arcs, float* stage = nullptr, uint64_t lo = 0, uint64_t hi = 0) {
+                                            int arcs, const XIncF& xi, float* stage = nullptr, uint64_t lo = 0,
+                                            uint64_t hi = 0) {
     uint32_t w[2 * kUnitWords];
     const uint4* src = reinterpret_cast<const uint4*>(u);
 #pragma unroll
@@ -766,7 +767,7 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
     if (slot >= n_slots) return;
     const uint64_t end = roff[slot + 1] < cap ? roff[slot + 1] : cap;
     RecOut o{out, roff[slot] + w[3], end, path, arcs, stage, lo, hi};
-    emit_item(w, ws.es_tab + 8 * (size_t)slot, o);
+    emit_item(w, ws.es_tab + 8 * (size_t)slot, xi, o);
 }
 
 // Per item chunk, the FP32 per-point work: records at
@@ -774,7 +775,7 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
 __global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, ItemWs ws, int arcs,
                                                            const uint64_t* __restrict__ roff,
                                                            const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
-                                                           float* __restrict__ out, uint64_t cap_records) {
+                                                           float* __restrict__ out, uint64_t cap_records, XIncF xi) {
     const uint64_t n_slots = *n_slots_dev;
     // nothing is written when the records exceed the capacity, or slots or items were dropped
     if (n_slots > slot_cap || roff[n_slots] > cap_records || ws.ctl->ovf_n > ws.ovf_cap) return;
@@ -800,7 +801,7 @@ __global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, Item
             const uint64_t n_st = ws.tile_n[tile] > ws.region_cap ? 0u
                                   : (n_rec < kStageWords / words ? n_rec : kStageWords / words);
             for (uint32_t s2 = threadIdx.x; s2 < cnt; s2 += kRecBlock)
-                record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs, s_stage, lo, lo + n_st);
+                record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs, xi, s_stage, lo, lo + n_st);
             __syncthreads();
             uint32_t* dst = reinterpret_cast<uint32_t*>(out) + lo * words;
             const uint32_t* src = reinterpret_cast<const uint32_t*>(s_stage);
@@ -812,7 +813,7 @@ __global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, Item
         const Unit* base = ws.units + ws.ovf_base;
         for (uint64_t s = (uint64_t)(b - kRecGrid) * kRecBlock + threadIdx.x; s < cnt;
              s += (uint64_t)kOvfBlocks * kRecBlock)
-            record_item(sv, ws, base + s, roff, n_slots, out, cap_records, arcs);
+            record_item(sv, ws, base + s, roff, n_slots, out, cap_records, arcs, xi);
     }
 }
 
@@ -953,11 +954,13 @@ hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, c
     else tail_kernel<false><<<g, kTailBlock, 0, s>>>(sv, cfg, ws, base, slot_cap, rc, stats);
     return hipGetLastError();
 }
-hipError_t launch_records(const SceneView& sv, const ItemWs& ws, int arcs, const uint64_t* roff,
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff,
                           const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    record_kernel<<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, arcs, roff, n_slots_dev, slot_cap, (float*)out,
-                                                              cap);
+    XIncF xi;
+    for (int k = 0; k < 5; k++) xi.v[k] = (float)cfg.xinc[k];
+    record_kernel<<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, n_slots_dev, slot_cap,
+                                                              (float*)out, cap, xi);
     return hipGetLastError();
 }
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
