@@ -487,7 +487,7 @@ constexpr int kTailGrid = 8192;   // grid cap of the tail kernel (tags stride by
 constexpr int kTailWin = 64;      // slot tiles a tail-kernel block counts in LDS
 constexpr int kRecBlock = 256;
 constexpr int kRecGrid = 8192;    // persistent grid of the record kernel
-constexpr uint32_t kStageWords = 7680;  // LDS words staging a tile's records (30 KB)
+constexpr uint32_t kStageWords = 6400;  // LDS words staging a tile's records (25 KB)
 constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the overflow slots
 
 // Slot allocator of one slot tile: the tile's own region first (LDS
@@ -772,7 +772,7 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
 
 // Per item chunk, the FP32 per-point work: records at
 // roff[slot] + the chunk's position within its slot.
-__global__ __launch_bounds__(kRecBlock, 5) void record_kernel(SceneView sv, ItemWs ws, int arcs,
+__global__ __launch_bounds__(kRecBlock, 6) void record_kernel(SceneView sv, ItemWs ws, int arcs,
                                                            const uint64_t* __restrict__ roff,
                                                            const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
                                                            float* __restrict__ out, uint64_t cap_records, XIncF xi) {
