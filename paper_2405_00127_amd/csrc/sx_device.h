@@ -656,7 +656,7 @@ struct ItemSink {
 // its points) depend only on the spiral's k0, k1, L, the side h and the u
 // range; writing its items needs the rest.
 struct RangeRes {
-    double dF;          // F increment over the range (density placement)
+    float dF;           // F increment over the range (density placement)
     float dF0, len0, alpha;  // increment and x length of its first branch piece; evolute point split
     uint32_t n, ne, place, xbits;  // xbits: the split at the branch breaks (split_x_sum)
 };
@@ -665,7 +665,7 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
     RangeRes r;
     const double du = ub - ua;
     const double kna = k0 + k1 * (ua - 0.5), knb = k0 + k1 * (ub - 0.5);
-    r.dF = 0.0;
+    r.dF = 0.0f;
     r.dF0 = 0.0f;
     r.len0 = 0.0f;
     r.place = 0;
@@ -689,11 +689,12 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
             const double hka = h * kna / L, hkb = h * knb / L;
             const double dx = -2.0 * h * k1 * du / L;
             double d0, l0;
-            r.dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, cfg.xinc, &d0, &l0, &r.xbits);
+            const double dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, cfg.xinc, &d0, &l0, &r.xbits);
+            r.dF = (float)dF;
             r.dF0 = (float)d0;
             r.len0 = (float)l0;
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
-            double G = (dx != 0.0) ? r.dF / dx : 0.0;
+            double G = (dx != 0.0) ? dF / dx : 0.0;
             I = fabs(G) * du * L / (2.0 * sqrt(fabs(h)));
         }
         r.n = ceil_count(I * cfg.inv_sqrt8tf);
@@ -734,7 +735,7 @@ SX_FN void range_put(Sink& k, const Cfg& cfg, const ES& es, double h, double ua,
     {
         OffsetP p;
         p.ua = (float)ua; p.du = (float)du; p.len0 = r.len0; p.fh = (float)h;
-        p.dF = (float)r.dF; p.dF0 = r.dF0;
+        p.dF = r.dF; p.dF0 = r.dF0;
         p.Pax = Pa.x; p.Pay = Pa.y; p.Pbx = Pb.x; p.Pby = Pb.y;
         uint32_t hdr = kItemOffset | (dir < 0 ? kIfDirNeg : 0u) | (cfg.arcs ? kIfArcs : 0u) |
                        (es.pivot ? kIfPivot : 0u) | r.place | (r.xbits << kXBitsShift);

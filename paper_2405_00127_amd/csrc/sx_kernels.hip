@@ -539,6 +539,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     __shared__ double s_own[kSlotBlock][4];        // k0, k1, L, w of the owner's piece
     __shared__ double s_tc[kSlotBlock][2];         // cusp u of each side
     __shared__ RangeRes s_res[2 * kSlotBlock];
+    __shared__ RangeRes s_first[2][kSlotBlock];    // each side's first range
     const uint64_t n_slots = *n_slots_dev;
     if (n_slots > slot_cap) return;  // reported by the finish kernel
     const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
@@ -592,7 +593,6 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         bool have = false;
         ES es;
         SideGeo g0, g1;
-        RangeRes a1, b1;
         uint32_t qa = 0, qb = 0;
         if (act && sl.tag < sv.n_tags) {
             k.path = path_of(sv, sl.tag);
@@ -604,8 +604,8 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                 piece_es(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code), es);
                 g0 = side_geo(es, sg.w, 0);
                 g1 = side_geo(es, sg.w, 1);
-                a1 = range_count(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
-                b1 = range_count(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
+                s_first[0][t] = range_count(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
+                s_first[1][t] = range_count(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
                 if (g0.split || g1.split) {
                     s_own[t][0] = es.k0;
                     s_own[t][1] = es.k1;
@@ -636,9 +636,9 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         __syncthreads();
         // phase 3: the items of each piece in canonical order
         if (have) {
-            range_put(k, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, a1);
+            range_put(k, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
             if (g0.split) range_put(k, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, s_res[qa]);
-            range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, b1);
+            range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
             if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, s_res[qb]);
         }
         if (act) {
