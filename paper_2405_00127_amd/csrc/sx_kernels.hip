@@ -402,9 +402,11 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
     Bisect bs;
     uint32_t n_trials = 0, n_lines = 0;
     for (;;) {
-        // refill idle lanes with the next tags of the range
+        // refill idle lanes with the next tags of the range, once a quarter
+        // of the wave is idle (a refill fetches segments: its latency is
+        // shared by the lanes it serves) or the wave has nothing left to run
         const uint64_t idle = __ballot(!busy);
-        if (idle && cursor < b) {
+        if (idle && cursor < b && (__popcll(idle) >= 16 || __ballot(busy) == 0ull)) {
             const uint32_t ni = cursor + (uint32_t)__popcll(idle & below);
             cursor += (uint32_t)__popcll(idle);
             if (!busy && ni < b) {
