@@ -111,48 +111,14 @@ SX_FN double es_chord(double th0, double th1) {
 
 // Section 7.1: chord-normalised distance estimate between a cubic with end
 // angles th0, th1 and arms d0, d1 and the Euler spiral with those angles.
-// sin and cos in FP64 of an angle of a few turns (the fit estimate's end
-// angles and their sum, |x| <= 2 pi): quadrant k = rint(2x / pi), r = x -
-// k pi/2 by Cody-Waite reduction with pi/2 split in three doubles (products
-// inside FMAs), then the Taylor series on |r| <= pi/4 to the 17th / 18th
-// power (truncation below 1e-19).
-SX_FN void sincos_rd(double x, double* sn, double* cs) {
-    const double k = rint(x * 0.6366197723675814);
-    double r = fma(-k, 1.5707963267948966, x);
-    r = fma(-k, 6.123233995736766e-17, r);
-    r = fma(-k, -1.4973849048591698e-33, r);
-    const double r2 = r * r;
-    double ps = fma(r2, 1.0 / 355687428096000.0, -1.0 / 1307674368000.0);
-    ps = fma(r2, ps, 1.0 / 6227020800.0);
-    ps = fma(r2, ps, -1.0 / 39916800.0);
-    ps = fma(r2, ps, 1.0 / 362880.0);
-    ps = fma(r2, ps, -1.0 / 5040.0);
-    ps = fma(r2, ps, 1.0 / 120.0);
-    ps = fma(r2, ps, -1.0 / 6.0);
-    const double sr = fma(r * r2, ps, r);
-    double pc = fma(r2, 1.0 / 6402373705728000.0, -1.0 / 20922789888000.0);
-    pc = fma(r2, pc, 1.0 / 87178291200.0);
-    pc = fma(r2, pc, -1.0 / 479001600.0);
-    pc = fma(r2, pc, 1.0 / 3628800.0);
-    pc = fma(r2, pc, -1.0 / 40320.0);
-    pc = fma(r2, pc, 1.0 / 720.0);
-    pc = fma(r2, pc, -1.0 / 24.0);
-    pc = fma(r2, pc, 0.5);
-    const double cr = fma(-r2, pc, 1.0);
-    const int q = (int)k & 3;
-    const double a = (q & 1) ? cr : sr, b = (q & 1) ? sr : cr;
-    *sn = (q & 2) ? -a : a;
-    *cs = ((q + 1) & 2) ? -b : b;
-}
-
-SX_FN double fit_estimate(double th0, double th1, double d0, double d1) {
+// The estimate of Section 7.1 from the end angles th0, th1 (and their sines
+// and cosines, when the caller has them) and the normalised arm lengths.
+SX_FN double fit_estimate_sc(double th0, double th1, double sn0, double c0, double sn1, double c1, double d0,
+                             double d1) {
     double s = fabs(th0 + th1), df = fabs(th0 - th1);
     double s2 = s * s;
     double e0 = 4.6255e-6 * (s2 * s2 * s) + 7.5e-3 * s2 * df;
-    double sn0, c0, sn1, c1, sn01, c01;
-    sincos_rd(th0, &sn0, &c0);
-    sincos_rd(th1, &sn1, &c1);
-    sincos_rd(th0 + th1, &sn01, &c01);
+    const double sn01 = sn0 * c1 + c0 * sn1;
     double db0 = 2.0 / (3.0 * (1.0 + c0)), db1 = 2.0 / (3.0 * (1.0 + c1));
     // area(d0,d1) - area(db0,db1), area = 3/20 (2 d0 sin th0 + 2 d1 sin th1 - d0 d1 sin(th0+th1))
     double a_src = 2.0 * d0 * sn0 + 2.0 * d1 * sn1 - d0 * d1 * sn01;
@@ -1371,10 +1337,17 @@ SX_HD inline Trial trial(const Seg& s, const Cfg& cfg, bool line, double dt, con
     r.th1 = 0.0;
     r.ok = true;
     if (line) return r;
-    r.th0 = atan2(cross(last_q.dir, chord), dot(last_q.dir, chord));
-    r.th1 = atan2(cross(chord, next_q.dir), dot(chord, next_q.dir));
+    // the end angles, and their sines and cosines from the same cross and
+    // dot products (a zero vector gives angle 0)
+    const double x0 = cross(last_q.dir, chord), y0 = dot(last_q.dir, chord);
+    const double x1 = cross(chord, next_q.dir), y1 = dot(chord, next_q.dir);
+    r.th0 = atan2(x0, y0);
+    r.th1 = atan2(x1, y1);
+    const double h0 = sqrt(x0 * x0 + y0 * y0), h1 = sqrt(x1 * x1 + y1 * y1);
+    const double sn0 = h0 > 0.0 ? x0 / h0 : 0.0, c0 = h0 > 0.0 ? y0 / h0 : 1.0;
+    const double sn1 = h1 > 0.0 ? x1 / h1 : 0.0, c1 = h1 > 0.0 ? y1 / h1 : 1.0;
     const double d0 = last_q.mag * dt / r.cl, d1 = next_q.mag * dt / r.cl;
-    const double est = fit_estimate(r.th0, r.th1, d0, d1);
+    const double est = fit_estimate_sc(r.th0, r.th1, sn0, c0, sn1, c1, d0, d1);
     const double err = cfg.paper_fit ? est * r.cl : est * (r.cl + kFitK * s.w) * kFitS;
     const bool len_ok = r.cl > 0.0;
     bool hodo_ok = true;
