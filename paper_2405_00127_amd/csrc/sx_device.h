@@ -78,8 +78,8 @@ SX_FN double cross(D2 a, D2 b) { return a.x * b.y - a.y * b.x; }
 SX_FN double len(D2 a) { return sqrt(a.x * a.x + a.y * a.y); }
 SX_FN bool is_zero(D2 a) { return a.x == 0.0 && a.y == 0.0; }
 SX_FN D2 unit(D2 a) {
-    double l = len(a);
-    return d2(a.x / l, a.y / l);
+    const double r = 1.0 / len(a);
+    return d2(a.x * r, a.y * r);
 }
 // right normal N = (T_y, -T_x); N' = kappa T
 SX_FN D2 rnormal(D2 t) { return d2(t.y, -t.x); }
@@ -1344,9 +1344,10 @@ SX_HD inline Trial trial(const Seg& s, const Cfg& cfg, bool line, double dt, con
     r.th0 = atan2(x0, y0);
     r.th1 = atan2(x1, y1);
     const double h0 = sqrt(x0 * x0 + y0 * y0), h1 = sqrt(x1 * x1 + y1 * y1);
-    const double sn0 = h0 > 0.0 ? x0 / h0 : 0.0, c0 = h0 > 0.0 ? y0 / h0 : 1.0;
-    const double sn1 = h1 > 0.0 ? x1 / h1 : 0.0, c1 = h1 > 0.0 ? y1 / h1 : 1.0;
-    const double d0 = last_q.mag * dt / r.cl, d1 = next_q.mag * dt / r.cl;
+    const double r0 = 1.0 / h0, r1 = 1.0 / h1, rcl = dt / r.cl;
+    const double sn0 = h0 > 0.0 ? x0 * r0 : 0.0, c0 = h0 > 0.0 ? y0 * r0 : 1.0;
+    const double sn1 = h1 > 0.0 ? x1 * r1 : 0.0, c1 = h1 > 0.0 ? y1 * r1 : 1.0;
+    const double d0 = last_q.mag * rcl, d1 = next_q.mag * rcl;
     const double est = fit_estimate_sc(r.th0, r.th1, sn0, c0, sn1, c1, d0, d1);
     const double err = cfg.paper_fit ? est * r.cl : est * (r.cl + kFitK * s.w) * kFitS;
     const bool len_ok = r.cl > 0.0;
@@ -1375,7 +1376,7 @@ SX_FN void bisect_init(Bisect& b, const Seg& s) {
     b.last_q = sample_q(s, 0.0);
     b.last_qtrue = s.D1;
 }
-SX_FN double depth_dt(uint32_t depth) { return 1.0 / (double)(1u << depth); }
+SX_FN double depth_dt(uint32_t depth) { return ldexp(1.0, -(int)depth); }  // 2^-depth, exact
 
 // One trial of the bisection.  Returns true when [t0, t0 + dt] is accepted
 // (its t0_u and depth are reported before the stack pops); *done is set when
