@@ -652,16 +652,17 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
             }
         } else {
             r.place = kIfPlaceF;
-            const double hka = h * kna / L, hkb = h * knb / L;
-            const double dx = -2.0 * h * k1 * du / L;
+            const double hL = h / L;
+            const double hka = hL * kna, hkb = hL * knb;
+            const double dx = -2.0 * hL * k1 * du;
             double d0, l0;
             const double dF = split_x_sum(make_xp(hka), make_xp(hkb), dx, cfg.xinc, &d0, &l0, &r.xbits);
             r.dF = (float)dF;
             r.dF0 = (float)d0;
             r.len0 = (float)l0;
             // I = |dF| / (4 |kappa'| |h|^1.5) = |dF/dx| L_r / (2 sqrt|h|)
-            double G = (dx != 0.0) ? dF / dx : 0.0;
-            I = fabs(G) * du * L / (2.0 * sqrt(fabs(h)));
+            // (dx = -2 h k1 du / L, so |dF/dx| du L = |dF| L^2 / (2 |h k1|))
+            I = (dx != 0.0) ? fabs(dF) * L * L / (4.0 * fabs(h * k1) * sqrt(fabs(h))) : 0.0;
         }
         r.n = ceil_count(I * cfg.inv_sqrt8tf);
     } else {
@@ -1460,8 +1461,8 @@ SX_HD void piece_es(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t
         // rotation chord / Z(1) in FP32: it only places the per-point work
         const V2 z1 = es_integral1_f((float)es.k0, (float)es.k1);
         const V2 ch = f32(chord);
-        const float zz = z1.x * z1.x + z1.y * z1.y;
-        const V2 fr = v2((ch.x * z1.x + ch.y * z1.y) / zz, (ch.y * z1.x - ch.x * z1.y) / zz);
+        const float rzz = 1.0f / (z1.x * z1.x + z1.y * z1.y);
+        const V2 fr = v2((ch.x * z1.x + ch.y * z1.y) * rzz, (ch.y * z1.x - ch.x * z1.y) * rzz);
         rot = d2(fr.x, fr.y);
         base = (double)atan2f(fr.y, fr.x);
     }
