@@ -110,9 +110,8 @@ SX_FN double es_chord(double th0, double th1) {
 }
 
 // Section 7.1: chord-normalised distance estimate between a cubic with end
-// angles th0, th1 and arms d0, d1 and the Euler spiral with those angles.
-// The estimate of Section 7.1 from the end angles th0, th1 (and their sines
-// and cosines, when the caller has them) and the normalised arm lengths.
+// angles th0, th1 and arms d0, d1 and the Euler spiral with those angles
+// (sn0, c0, sn1, c1: the sines and cosines of th0 and th1).
 SX_FN double fit_estimate_sc(double th0, double th1, double sn0, double c0, double sn1, double c1, double d0,
                              double d1) {
     double s = fabs(th0 + th1), df = fabs(th0 - th1);
