@@ -174,8 +174,8 @@ __device__ Pair look_back(TileStatus* st, uint32_t tile, uint32_t epoch, int lan
 
 // --------------------------------------------------------- tag monoid
 constexpr int kScanBlock = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kScanBlock * kScanItems;
+constexpr int kTagItems = 16;    // tags per thread of the tag-monoid scan
+constexpr int kCountItems = 32;  // counts per thread of the count scans
 
 __device__ __forceinline__ Pair tag_inc(uint32_t t) {
     uint64_t pts = (t & kTagCount) + ((t & kTagEnd) ? 1u : 0u);
@@ -198,8 +198,9 @@ __device__ __forceinline__ void finish_scan(ScanCtl* ctl, uint32_t epoch_used) {
     }
 }
 
-template <class Load, class Store>
+template <int Items, class Load, class Store>
 __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, TileStatus* st) {
+    constexpr uint32_t kTile = kScanBlock * Items;
     __shared__ uint32_t s_tile, s_epoch;
     __shared__ Pair s_wave[kScanBlock / 64];
     __shared__ Pair s_excl;
@@ -212,18 +213,18 @@ __device__ void scan_tile(Load load, Store store, uint32_t n, ScanCtl* ctl, Tile
     }
     __syncthreads();
     const uint32_t tile = s_tile, epoch = s_epoch;
-    const uint32_t ntiles = (n + kScanTile - 1) / kScanTile;
+    const uint32_t ntiles = (n + kTile - 1) / kTile;
     if (tile >= ntiles) {
         // a grid sized for a capacity larger than this launch's n: nothing to scan
         if (tid == 0) finish_scan(ctl, s_epoch);
         return;
     }
-    const uint64_t base = (uint64_t)tile * kScanTile + (uint64_t)tid * kScanItems;
-    Pair item[kScanItems];
+    const uint64_t base = (uint64_t)tile * kTile + (uint64_t)tid * Items;
+    Pair item[Items];
     load(base, item);
     Pair run{0, 0};
 #pragma unroll
-    for (int j = 0; j < kScanItems; j++) {
+    for (int j = 0; j < Items; j++) {
         run = run + item[j];
         item[j] = run;  // thread-local inclusive
     }
@@ -266,21 +267,21 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
         ws_reset->items_total = 0;
     }
     auto load = [&](uint64_t base, Pair* item) {
-        if (base + kScanItems <= n) {
+        if (base + kTagItems <= n) {
             uint4 raw = *reinterpret_cast<const uint4*>(tags + base);
             uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
 #pragma unroll
-            for (int j = 0; j < kScanItems; j++) item[j] = tag_inc((w[j >> 2] >> (8 * (j & 3))) & 0xffu);
+            for (int j = 0; j < kTagItems; j++) item[j] = tag_inc((w[j >> 2] >> (8 * (j & 3))) & 0xffu);
         } else {
 #pragma unroll
-            for (int j = 0; j < kScanItems; j++) item[j] = (base + j < n) ? tag_inc(tags[base + j]) : Pair{0, 0};
+            for (int j = 0; j < kTagItems; j++) item[j] = (base + j < n) ? tag_inc(tags[base + j]) : Pair{0, 0};
         }
     };
     auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
         // item j: exclusive = pre + incl[j-1]; style/xform stored inclusive - 1
-        uint32_t o_off[kScanItems], o_pth[kScanItems], o_sty[kScanItems], o_xf[kScanItems];
+        uint32_t o_off[kTagItems], o_pth[kTagItems], o_sty[kTagItems], o_xf[kTagItems];
 #pragma unroll
-        for (int j = 0; j < kScanItems; j++) {
+        for (int j = 0; j < kTagItems; j++) {
             Pair ex = pre;
             if (j > 0) ex = ex + incl[j - 1];
             Pair in = pre + incl[j];
@@ -293,9 +294,9 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
         uint32_t* m1 = mon + n;
         uint32_t* m2 = mon + 2 * (size_t)n;
         uint32_t* m3 = mon + 3 * (size_t)n;
-        if (base + kScanItems <= n && (n & 3u) == 0u) {
+        if (base + kTagItems <= n && (n & 3u) == 0u) {
 #pragma unroll
-            for (int j = 0; j < kScanItems; j += 4) {
+            for (int j = 0; j < kTagItems; j += 4) {
                 *reinterpret_cast<uint4*>(m0 + base + j) = make_uint4(o_off[j], o_off[j + 1], o_off[j + 2], o_off[j + 3]);
                 *reinterpret_cast<uint4*>(m1 + base + j) = make_uint4(o_pth[j], o_pth[j + 1], o_pth[j + 2], o_pth[j + 3]);
                 *reinterpret_cast<uint4*>(m2 + base + j) = make_uint4(o_sty[j], o_sty[j + 1], o_sty[j + 2], o_sty[j + 3]);
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < kScanItems; j++) {
+            for (int j = 0; j < kTagItems; j++) {
                 if (base + j < n) {
                     m0[base + j] = o_off[j];
                     m1[base + j] = o_pth[j];
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
             }
         }
     };
-    scan_tile(load, store, n, ctl, st);
+    scan_tile<kTagItems>(load, store, n, ctl, st);
 }
 
 // exclusive scan of u32 counts into u64 offsets; out[n] = total
@@ -337,9 +338,9 @@ __global__ __launch_bounds__(kScanBlock) void scan_counts_dev_kernel(const uint3
 __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
                                               ScanCtl* ctl, TileStatus* st) {
     auto load = [&](uint64_t base, Pair* item) {
-        if (base + kScanItems <= n) {
+        if (base + kCountItems <= n) {
 #pragma unroll
-            for (int j = 0; j < kScanItems; j += 4) {
+            for (int j = 0; j < kCountItems; j += 4) {
                 uint4 v = *reinterpret_cast<const uint4*>(in + base + j);
                 item[j] = Pair{v.x, 0};
                 item[j + 1] = Pair{v.y, 0};
@@ -348,28 +349,18 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < kScanItems; j++) item[j] = Pair{(base + j < n) ? (uint64_t)in[base + j] : 0ull, 0};
+            for (int j = 0; j < kCountItems; j++) item[j] = Pair{(base + j < n) ? (uint64_t)in[base + j] : 0ull, 0};
         }
     };
-    // the exclusive sums go out through LDS, so that consecutive threads
-    // store consecutive words (a thread's own items are kScanItems apart)
-    __shared__ uint64_t s_out[kScanTile];
     auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
-        const uint32_t t0 = threadIdx.x * kScanItems;
 #pragma unroll
-        for (int j = 0; j < kScanItems; j++) {
-            s_out[t0 + j] = pre.a + (j > 0 ? incl[j - 1].a : 0ull);
+        for (int j = 0; j < kCountItems; j++) {
+            const uint64_t ex = pre.a + (j > 0 ? incl[j - 1].a : 0ull);
+            if (base + j < n) out[base + j] = ex;
             if (base + j == (uint64_t)n - 1u) out[n] = pre.a + incl[j].a;
         }
-        __syncthreads();
-        const uint64_t tile_base = base - t0;
-#pragma unroll
-        for (int j = 0; j < kScanItems; j++) {
-            const uint32_t k = j * kScanBlock + threadIdx.x;
-            if (tile_base + k < n) out[tile_base + k] = s_out[k];
-        }
     };
-    scan_tile(load, store, n, ctl, st);
+    scan_tile<kCountItems>(load, store, n, ctl, st);
 }
 
 // --------------------------------------------------------- bisection
@@ -886,7 +877,10 @@ __global__ void scene_offsets_kernel(const uint64_t* __restrict__ base, const ui
 }
 
 // ------------------------------------------------------------- launches
-int scan_tiles(uint32_t n) { return (int)((n + kScanTile - 1) / kScanTile); }
+int scan_tiles(uint32_t n) { return (int)((n + kScanBlock * kTagItems - 1) / (kScanBlock * kTagItems)); }
+static int count_scan_tiles(uint32_t n) {
+    return (int)((n + kScanBlock * kCountItems - 1) / (kScanBlock * kCountItems));
+}
 
 uint32_t piece_tiles(uint32_t n, uint32_t tile) { return (n + tile - 1) / tile; }
 uint32_t slot_tiles(uint64_t n_slots) { return (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock); }
@@ -900,12 +894,12 @@ hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void
 }
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    scan_counts_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
+    scan_counts_kernel<<<count_scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
     return hipGetLastError();
 }
 hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
                                   void* st, hipStream_t s) {
-    scan_counts_dev_kernel<<<scan_tiles(cap > 0 ? cap : 1), kScanBlock, 0, s>>>(in, n_dev, cap, out, (ScanCtl*)ctl,
+    scan_counts_dev_kernel<<<count_scan_tiles(cap > 0 ? cap : 1), kScanBlock, 0, s>>>(in, n_dev, cap, out, (ScanCtl*)ctl,
                                                                               (TileStatus*)st);
     return hipGetLastError();
 }
