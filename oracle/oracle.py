@@ -37,6 +37,9 @@ PIECE_DTYPE = np.dtype(
     align=True,
 )
 
+# style flag bit 0: the path is filled (flattened at offset 0), not stroked
+STYLE_FILL = 1
+
 _lock = threading.Lock()
 _lib = None
 
@@ -61,7 +64,7 @@ def lib():
             vp = C.c_void_p
             u32 = C.c_uint32
             L.ox_encode.restype = vp
-            L.ox_encode.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, u32]
+            L.ox_encode.argtypes = [vp, vp, vp, vp, vp, vp, u32, u32, u32, vp]
             for name, rt in [("ox_enc_status", C.c_int), ("ox_enc_ntags", u32), ("ox_enc_npts", u32),
                              ("ox_enc_nstyles", u32), ("ox_enc_nxforms", u32), ("ox_enc_npaths", u32),
                              ("ox_enc_tags", vp), ("ox_enc_data", vp), ("ox_enc_style_stream", vp),
@@ -91,6 +94,8 @@ def lib():
             L.ox_gl_nodes.argtypes = [vp, vp]
             L.ox_xform_ok.restype = C.c_int
             L.ox_xform_ok.argtypes = [vp]
+            L.ox_affine_ok.restype = C.c_int
+            L.ox_affine_ok.argtypes = [vp]
             assert L.ox_sizeof_out() == OUT_DTYPE.itemsize
             assert L.ox_sizeof_margin() == MARGIN_DTYPE.itemsize
             assert L.ox_sizeof_piece() == PIECE_DTYPE.itemsize
@@ -160,6 +165,11 @@ def xform_ok(xf):
     return bool(lib().ox_xform_ok(_ptr(a)))
 
 
+def affine_ok(xf):
+    a = np.ascontiguousarray(xf, dtype=np.float32)
+    return bool(lib().ox_affine_ok(_ptr(a)))
+
+
 # ----------------------------------------------------------------- encoding
 @dataclasses.dataclass
 class Encoded:
@@ -185,8 +195,15 @@ def encode(scene) -> Encoded:
     po = np.ascontiguousarray(scene.pt_off, np.uint32)
     si = np.ascontiguousarray(scene.style_ix, np.uint32)
     xi = np.ascontiguousarray(scene.xform_ix, np.uint32)
+    # paths drawn as fills (style flag bit 0); an out-of-range style index
+    # is left to the encoder, which rejects it
+    flags = np.asarray(scene.styles["flags"], np.uint8)
+    ok = si < len(flags)
+    fill = np.zeros(len(si), np.uint8)
+    fill[ok] = flags[si[ok]] & STYLE_FILL
+    fill = np.ascontiguousarray(fill)
     h = L.ox_encode(_ptr(verbs), _ptr(vo), _ptr(pts), _ptr(po), _ptr(si), _ptr(xi),
-                    scene.n_paths, len(scene.styles), len(scene.xforms))
+                    scene.n_paths, len(scene.styles), len(scene.xforms), _ptr(fill))
     if not h:
         raise MemoryError("oracle encode failed")
     hv = C.c_void_p(h)

@@ -57,6 +57,8 @@
 enum { OX_MOVE = 0, OX_LINE = 1, OX_QUAD = 2, OX_CUBIC = 3, OX_CLOSE = 4 };
 enum { OX_JOIN_BEVEL = 0, OX_JOIN_MITER = 1, OX_JOIN_ROUND = 2 };
 enum { OX_CAP_BUTT = 0, OX_CAP_SQUARE = 1, OX_CAP_ROUND = 2 };
+/* style flag: the path is filled, not stroked (reading G33) */
+#define OX_STYLE_FILL 0x01u
 enum { OX_OUT_LINES = 0, OX_OUT_ARCS = 1 };
 enum { OX_FIT_OFFSET = 0, OX_FIT_PAPER = 1 };
 
@@ -109,6 +111,11 @@ typedef struct {
 #ifndef OX_C_MIN
 #define OX_C_MIN 0.1
 #endif
+/* G33: fill flattening is the same expansion at offset 0 (Section 4, the
+ * h = 0 regime): the fit error without the width term, one side (the path
+ * itself, forward in u), no joins or caps, and every subpath closed by a
+ * line back to its start.  Pieces accepted at the depth cap draw their
+ * chord.  Without a width, any invertible affine transform is allowed. */
 
 /* ----------------------------------------------------- result records -- */
 typedef struct {
@@ -224,10 +231,23 @@ static void enc_pt(ox_enc *e, float x, float y) {
     e->n_pts++;
 }
 
-/* Status codes match the public ABI's meaning: 0 ok, -1 invalid input. */
+/* closing line from the current point back to the subpath's start point
+ * (none when the current point is already there) */
+static int enc_closing_line(ox_enc *e, float sx, float sy, float *cx, float *cy) {
+    if (*cx == sx && *cy == sy) return 0;
+    if (enc_reserve(e, 1, 1)) return -2;
+    e->tags[e->n_tags++] = (uint8_t)(1u | OX_TAG_F32);
+    enc_pt(e, sx, sy);
+    *cx = sx; *cy = sy;
+    return 0;
+}
+
+/* Status codes match the public ABI's meaning: 0 ok, -1 invalid input.
+ * path_fill (may be NULL: all strokes) marks the paths drawn as fills, whose
+ * subpaths are all closed (reading G33). */
 ox_enc *ox_encode(const uint8_t *verbs, const uint32_t *verb_off, const float *pts,
                   const uint32_t *pt_off, const uint32_t *style_ix, const uint32_t *xform_ix,
-                  uint32_t n_paths, uint32_t n_styles, uint32_t n_xforms) {
+                  uint32_t n_paths, uint32_t n_styles, uint32_t n_xforms, const uint8_t *path_fill) {
     ox_enc *e = (ox_enc *)calloc(1, sizeof(ox_enc));
     if (!e) return NULL;
     int32_t prev_style = -1, prev_xf = -1;
@@ -238,6 +258,7 @@ ox_enc *ox_encode(const uint8_t *verbs, const uint32_t *verb_off, const float *p
         uint32_t np = pt_off[k + 1] - pt_off[k];
         uint32_t pi = 0;
         int in_sub = 0, sub_nseg = 0, closed = 0;
+        const int fill = path_fill ? (path_fill[k] != 0) : 0;
         float sx = 0, sy = 0, cx = 0, cy = 0;      /* subpath start / current */
         float dirx = 0, diry = 0; int have_dir = 0; /* G14 tangent point */
         for (uint32_t vi = verb_off[k]; vi < verb_off[k + 1]; vi++) {
@@ -245,13 +266,11 @@ ox_enc *ox_encode(const uint8_t *verbs, const uint32_t *verb_off, const float *p
             if (v == OX_MOVE || v == OX_CLOSE) {
                 if (v == OX_CLOSE) {
                     if (!in_sub) continue;
-                    if (sub_nseg > 0 && !(cx == sx && cy == sy)) {
-                        /* closing line back to the start point */
-                        if (enc_reserve(e, 1, 1)) { e->status = -2; return e; }
-                        e->tags[e->n_tags++] = (uint8_t)(1u | OX_TAG_F32);
-                        enc_pt(e, sx, sy);
-                        cx = sx; cy = sy;
-                    }
+                    if (sub_nseg > 0 && enc_closing_line(e, sx, sy, &cx, &cy)) { e->status = -2; return e; }
+                    closed = 1;
+                } else if (fill && in_sub && sub_nseg > 0 && !closed) {
+                    /* a fill's subpath ends closed */
+                    if (enc_closing_line(e, sx, sy, &cx, &cy)) { e->status = -2; return e; }
                     closed = 1;
                 }
                 if (in_sub && sub_nseg > 0) {
@@ -301,6 +320,10 @@ ox_enc *ox_encode(const uint8_t *verbs, const uint32_t *verb_off, const float *p
             cx = P[2 * (pi + c - 1)]; cy = P[2 * (pi + c - 1) + 1];
             pi += c;
             sub_nseg++;
+        }
+        if (fill && in_sub && sub_nseg > 0 && !closed) {
+            if (enc_closing_line(e, sx, sy, &cx, &cy)) { e->status = -2; return e; }
+            closed = 1;
         }
         if (in_sub && sub_nseg > 0) {
             if (enc_reserve(e, 1, 2)) { e->status = -2; return e; }
@@ -528,10 +551,11 @@ typedef struct {
 typedef struct {
     v2 P[4];        /* elevated cubic, world space */
     v2 t_start, t_end; /* raw end tangent vectors (first nonzero difference) */
-    double w;       /* world half-width */
+    double w;       /* world half-width (0 for a fill) */
     double lpoly;
     uint32_t path;
     uint32_t tag;
+    int fill;       /* one side at offset 0, no joins or caps (reading G33) */
 } ox_seg;
 
 static void res_push(ox_res *r, v2 a, v2 b, double curv, uint32_t path, uint32_t kind, uint32_t tag) {
@@ -1078,7 +1102,7 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
                 piece_push(k->r, &pc);
             }
             emit_side(k, cfg, &es, +hw, m);
-            emit_side(k, cfg, &es, -hw, m);
+            if (!s->fill) emit_side(k, cfg, &es, -hw, m);
             /* pop the two-word stack: count trailing zeros */
             t0_u += 1;
             uint32_t sh = 0;
@@ -1119,7 +1143,7 @@ static void straight_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_
         piece_push(k->r, &pc);
     }
     emit_side(k, cfg, &es, +s->w, m);
-    emit_side(k, cfg, &es, -s->w, m);
+    if (!s->fill) emit_side(k, cfg, &es, -s->w, m);
 }
 
 /* ---- segment fetch (Section 8.1: degree elevation) --------------------- */
@@ -1133,6 +1157,12 @@ static v2 xf_apply(const float *X, double x, double y) {
 static v2 first_nonzero(const v2 *cands, int n) {
     for (int i = 0; i < n; i++) if (!vzero(cands[i])) return cands[i];
     return v2m(1.0, 0.0);
+}
+
+int ox_affine_ok(const float *X) {
+    for (int j = 0; j < 6; j++) if (!isfinite(X[j])) return 0;
+    double det = (double)X[0] * X[3] - (double)X[1] * X[2];
+    return det != 0.0 && isfinite(det);
 }
 
 int ox_xform_ok(const float *X) {
@@ -1171,18 +1201,26 @@ ox_res *ox_expand(const ox_enc *e, const ox_style *styles, uint32_t n_styles,
     cfg.mode = mode;
     cfg.fit_mode = fit_mode;
     for (uint32_t i = 0; i < e->n_xforms; i++) {
-        if (e->xform_stream[i] >= n_xforms || !ox_xform_ok(xforms + 6 * (size_t)e->xform_stream[i])) {
-            r->status = -1;
-            goto done;
-        }
+        if (e->xform_stream[i] >= n_xforms) { r->status = -1; goto done; }
     }
     for (uint32_t i = 0; i < e->n_styles; i++) {
         if (e->style_stream[i] >= n_styles) { r->status = -1; goto done; }
         const ox_style *st = &styles[e->style_stream[i]];
-        if (!(st->half_width >= 0.0f) || !isfinite(st->half_width) || !(st->miter_limit >= 1.0f)) {
+        if (st->flags & ~OX_STYLE_FILL) { r->status = -1; goto done; }
+        /* a fill ignores width, miter limit, join and caps */
+        if (!(st->flags & OX_STYLE_FILL) &&
+            (!(st->half_width >= 0.0f) || !isfinite(st->half_width) || !(st->miter_limit >= 1.0f))) {
             r->status = -1;
             goto done;
         }
+    }
+    /* a transform drawn with a stroke must be a similarity (reading G16), one
+     * drawn with a fill any invertible affine map (reading G33) */
+    for (uint32_t i = 0; i < n; i++) {
+        const ox_style *st = &styles[e->style_stream[sty[i]]];
+        const float *X = xforms + 6 * (size_t)e->xform_stream[xfi[i]];
+        int ok = (st->flags & OX_STYLE_FILL) ? ox_affine_ok(X) : ox_xform_ok(X);
+        if (!ok) { r->status = -1; goto done; }
     }
     for (uint32_t i = tag_begin; i < tag_end; i++) {
         uint8_t tag = e->tags[i];
@@ -1190,14 +1228,15 @@ ox_res *ox_expand(const ox_enc *e, const ox_style *styles, uint32_t n_styles,
         m->fit = m->count = m->rho = m->q = m->len = m->join = INFINITY;
         const ox_style *st = &styles[e->style_stream[sty[i]]];
         const float *X = xforms + 6 * (size_t)e->xform_stream[xfi[i]];
+        const int fill = (st->flags & OX_STYLE_FILL) != 0;
         double scale = sqrt(fabs((double)X[0] * X[3] - (double)X[1] * X[2]));
-        double w = (double)st->half_width * scale;
+        double w = fill ? 0.0 : (double)st->half_width * scale;
         ox_sink sk;
         sk.r = r; sk.path = e->path_map[pth[i]]; sk.tag = i; sk.emit = emit; sk.count = 0; sk.mode = mode;
         const float *D = e->data + 2 * (size_t)off[i];
         if (tag & OX_TAG_SUBPATH_END) {
             /* stroke cap marker: start cap if the subpath is open */
-            if (!(tag & OX_TAG_CLOSED)) {
+            if (!fill && !(tag & OX_TAG_CLOSED)) {
                 v2 ps = xf_apply(X, D[2], D[3]);
                 v2 pd = xf_apply(X, D[4], D[5]);
                 v2 dir = vsub(pd, ps);
@@ -1209,7 +1248,7 @@ ox_res *ox_expand(const ox_enc *e, const ox_style *styles, uint32_t n_styles,
             v2 raw[4];
             for (uint32_t j = 0; j <= c; j++) raw[j] = xf_apply(X, D[2 * j], D[2 * j + 1]);
             ox_seg s;
-            s.w = w; s.path = sk.path; s.tag = i;
+            s.w = w; s.path = sk.path; s.tag = i; s.fill = fill;
             if (c == 1) {
                 s.P[0] = raw[0]; s.P[3] = raw[1];
                 v2 d = vsub(raw[1], raw[0]);
@@ -1233,7 +1272,9 @@ ox_res *ox_expand(const ox_enc *e, const ox_style *styles, uint32_t n_styles,
             /* join or end cap with the neighbour at i + 1 (Algorithm 1) */
             uint8_t nt = e->tags[i + 1];
             v2 pend = raw[c];
-            if ((nt & OX_TAG_SUBPATH_END) && !(nt & OX_TAG_CLOSED)) {
+            if (fill) {
+                /* a fill has no joins or caps */
+            } else if ((nt & OX_TAG_SUBPATH_END) && !(nt & OX_TAG_CLOSED)) {
                 emit_cap(&sk, &cfg, st->end_cap, pend, vunit(s.t_end), w, 0);
             } else {
                 v2 tb;

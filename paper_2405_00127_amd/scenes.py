@@ -43,6 +43,9 @@ assert STYLE_DTYPE.itemsize == 12
 
 CANVAS_W, CANVAS_H = 2088.0, 1600.0
 
+# Style flag bit 0: the path is filled (flattened at offset 0), not stroked.
+STYLE_FILL = 1
+
 
 @dataclasses.dataclass
 class Scene:
@@ -374,6 +377,27 @@ def scene_map(seed: int = 2, n_segments: int = 1_000_000, n_paths: Optional[int]
         tolerance=tolerance,
         output_mode=output_mode,
     )
+
+
+def with_fills(scene: Scene, frac: float = 1.0, seed: int = 0, xform=None) -> Scene:
+    """A copy of ``scene`` in which a seeded fraction ``frac`` of the styles
+    are fills (every path drawn with such a style is flattened at offset 0
+    and closed).  With ``xform`` (six floats, any invertible affine map), the
+    fill paths are drawn with that transform appended to the table."""
+    rng = np.random.default_rng(seed)
+    styles = scene.styles.copy()
+    n = len(styles)
+    pick = rng.random(n) < frac if frac < 1.0 else np.ones(n, bool)
+    styles["flags"] = np.where(pick, styles["flags"] | STYLE_FILL, styles["flags"])
+    xforms = scene.xforms
+    xform_ix = scene.xform_ix
+    if xform is not None:
+        xforms = np.concatenate([xforms, np.asarray(xform, np.float32).reshape(1, 6)])
+        fill_path = pick[scene.style_ix]
+        xform_ix = np.where(fill_path, len(xforms) - 1, scene.xform_ix).astype(np.uint32)
+    return dataclasses.replace(scene, styles=styles, xforms=np.ascontiguousarray(xforms, np.float32),
+                               xform_ix=np.ascontiguousarray(xform_ix, np.uint32),
+                               name=scene.name + f"-fill{frac:g}")
 
 
 def scene_c2(seed: int = 2, output_mode: int = OUT_LINES, n_segments: int = 1_000_000,
