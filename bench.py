@@ -238,6 +238,59 @@ def plain(args, ctx, B, S, torch, np):
     return out, sc, mode
 
 
+# ------------------------------------------------------------------- fill
+def fill(args, ctx, B, S, torch, np):
+    """The same map scene with every path filled (flattened at offset 0, one
+    run per piece, subpaths closed, no joins or caps), launched with the
+    tuning the plain leg chose."""
+    mode = S.OUT_LINES if args.mode == "lines" else S.OUT_ARCS
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sc = S.with_fills(S.scene_map(2, args.segments, args.paths, 0.25, mode))
+    n_seg = sc.n_segments()
+    scene = ctx.encode(sc, stream=stream)
+    tol = sc.tolerance
+    recs, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert int(cnt[0].item()) == n_rec and int(cnt[1].item()) == 0
+    ms = (t1 - t0) * 1e3 / args.steps
+    names = B.PHASE_NAMES
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in names]
+           for _ in range(args.steps)]
+    for k in range(args.steps):
+        for p in range(len(names)):
+            evs[k][p][0].record(stream)
+            ctx.run_phase(scene, p, tol, mode, buf.data_ptr(), buf.numel(), stream=stream)
+            evs[k][p][1].record(stream)
+    torch.cuda.synchronize()
+    phase_ms = {names[p]: sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
+                for p in range(len(names))}
+    res = {
+        "workload": f"map/CAD scene, {args.paths} paths, {n_seg} segments, every path filled, {args.mode}, "
+                    f"tol 0.25 px",
+        "segments": n_seg, "tags": scene.n_tags, "records": n_rec,
+        "ms_per_step": ms, "segs_per_s": n_seg / (ms * 1e-3), "records_per_s": n_rec / (ms * 1e-3),
+        "phase_ms": phase_ms,
+    }
+    log(f"bench: fill {ms:.3f} ms/step, {n_rec} records; phases "
+        + ", ".join(f"{n} {phase_ms[n]:.3f}" for n in names))
+    del buf
+    return res, sc
+
+
 # ---------------------------------------------------------------- batched
 def batched(args, ctx, B, S, torch, np):
     """256 map-shaped scenes: one graph-captured batched pipeline vs a loop of
@@ -525,6 +578,7 @@ def main():
     ap.add_argument("--bisect-range", type=int, default=None)
     ap.add_argument("--bisect-waves", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fill", action="store_true", help="skip the fill leg (the map scene filled)")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true")
@@ -563,6 +617,9 @@ def main():
     traffic = measured_traffic(out["roofline"]["kernel"], args.mode)
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
+    fill_sc = None
+    if not args.no_fill:
+        out["fill"], fill_sc = fill(args, ctx, B, S, torch, np)
     if not args.no_batched:
         out["batched"] = batched(args, ctx, B, S, torch, np)
         log(f"bench: batched {out['batched']}")
@@ -571,6 +628,8 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc, mode, args.cpu_budget)
+        if fill_sc is not None:
+            out["fill"]["cpu_baseline"] = cpu_baseline(fill_sc, mode, min(args.cpu_budget, 6.0))
     print(json.dumps(out), flush=True)
 
 

@@ -49,13 +49,20 @@ enum { SX_CAP_BUTT = 0, SX_CAP_SQUARE = 1, SX_CAP_ROUND = 2 };
 /* Output primitive (Section 8.1: line soup, or arcs storing curvature). */
 enum { SX_OUT_LINES = 0, SX_OUT_ARCS = 1 };
 
+/* Style flags.  SX_STYLE_FILL: the path is filled, not stroked: it is
+ * flattened at offset 0 (the h = 0 regime of Section 4), one output run per
+ * Euler spiral piece along the path itself, every subpath closed by a line
+ * back to its start, no joins or caps; half_width, miter_limit, join and
+ * caps are ignored. */
+enum { SX_STYLE_FILL = 1 };
+
 /* Stroke style, one per path (Section 8.2: style stream).  half_width >= 0
  * in the path's local units (scaled by sqrt|det| of the transform);
  * miter_limit >= 1 (SVG ratio of miter length to stroke width). 12 bytes. */
 typedef struct {
     float half_width;
     float miter_limit;
-    uint8_t join, start_cap, end_cap, flags; /* flags: reserved, must be 0 */
+    uint8_t join, start_cap, end_cap, flags; /* flags: 0 (stroke) or SX_STYLE_FILL; other bits reserved */
 } sx_style;
 
 /* Affine transform, one per path (Section 8.2: transform stream):
@@ -108,12 +115,15 @@ const char *sx_version(void);
 /* Encode paths into a device-resident scene (Section 8.2): tags, the
  * overlapping point stream, style / transform streams and the encoded-path to
  * input-path map; closing lines are inserted for closed subpaths whose end
- * differs from their start, one stroke cap marker is appended per subpath,
- * zero-length segments and empty subpaths are dropped.  The upload is
- * ordered on `stream`; the host inputs may be reused when this returns.
+ * differs from their start (every subpath of a fill is closed), one stroke
+ * cap marker is appended per subpath, zero-length segments and empty
+ * subpaths are dropped.  The upload is ordered on `stream`; the host inputs
+ * may be reused when this returns.
  * Errors: SX_EINVAL (path not starting with MOVE, unknown verb, point count
  * mismatch, non-finite coordinate, style or transform index out of range,
- * half_width < 0, miter_limit < 1, non-similarity transform),
+ * reserved style flags, for strokes half_width < 0, miter_limit < 1, bad
+ * join or cap, or a transform that is not a similarity; for fills a
+ * transform that is not an invertible finite affine map),
  * SX_ENOMEM, SX_EDEVICE.  The scene is owned by ctx. */
 int sx_scene_encode(sx_ctx *ctx, const sx_paths *paths, const sx_style *styles, uint32_t n_styles,
                     const sx_affine *xforms, uint32_t n_xforms, void *stream, sx_scene **out);
@@ -131,7 +141,8 @@ int sx_scene_download(const sx_scene *scene, uint8_t *tags, float *data, uint32_
  * items and per-tag record counts, exclusive scan of the counts (output
  * offsets), records written at their offsets in canonical order (by tag;
  * within a tag: Euler spiral pieces in parameter order, side A (right,
- * p + wN) then side B, then the join or cap).
+ * p + wN) then side B, then the join or cap; a fill's piece has one run along
+ * the path and its tags no join or cap).
  *   tolerance  > 0, in output units (pixels), Frechet-style bound;
  *   output_mode SX_OUT_LINES (sx_line records) or SX_OUT_ARCS (sx_arc);
  *   out_dev    device memory, out_capacity_bytes bytes, caller-owned;

@@ -121,6 +121,12 @@ void free_scene(sx_scene* s) {
     delete s;
 }
 
+bool invertible(const sx_affine& X) {
+    const double det = (double)X.a * X.d - (double)X.b * X.c;
+    return std::isfinite(X.a) && std::isfinite(X.b) && std::isfinite(X.c) && std::isfinite(X.d) &&
+           std::isfinite(X.e) && std::isfinite(X.f) && det != 0.0;
+}
+
 bool similarity(const sx_affine& X) {
     bool rot = (X.a == X.d) && (X.b == -X.c);
     bool refl = (X.a == -X.d) && (X.b == X.c);
@@ -421,22 +427,37 @@ int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, 
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SX_EDEVICE, "hipSetDevice");
     sx::HostEncoding enc;
     std::string err;
-    if (!sx::encode_paths(*paths, n_styles, n_xforms, enc, err)) return fail(ctx, SX_EINVAL, err);
+    if (!sx::encode_paths(*paths, styles, n_styles, n_xforms, enc, err)) return fail(ctx, SX_EINVAL, err);
     // validate the styles and transforms that are actually used
     std::vector<sx::StyleD> sd(enc.style_stream.size());
     for (size_t i = 0; i < enc.style_stream.size(); i++) {
         const sx_style& st = styles[enc.style_stream[i]];
+        if (st.flags & ~(uint32_t)SX_STYLE_FILL) return fail(ctx, SX_EINVAL, "reserved style flags");
+        if (st.flags & SX_STYLE_FILL) {
+            // a fill: offset 0, no joins or caps (width and join/cap fields ignored)
+            sd[i] = sx::StyleD{0.0f, 1.0f, sx::kStyleFill};
+            continue;
+        }
         if (!(st.half_width >= 0.0f) || !std::isfinite(st.half_width)) return fail(ctx, SX_EINVAL, "half_width < 0");
         if (!(st.miter_limit >= 1.0f) || !std::isfinite(st.miter_limit)) return fail(ctx, SX_EINVAL, "miter_limit < 1");
         if (st.join > 2 || st.start_cap > 2 || st.end_cap > 2) return fail(ctx, SX_EINVAL, "bad join/cap");
-        if (st.flags != 0) return fail(ctx, SX_EINVAL, "style flags are reserved");
         sd[i] = sx::StyleD{st.half_width, st.miter_limit,
                            (uint32_t)st.join | ((uint32_t)st.start_cap << 8) | ((uint32_t)st.end_cap << 16)};
+    }
+    // a transform drawn with a stroke must be a similarity, one drawn with a
+    // fill an invertible finite affine map (checked per encoded path)
+    for (uint32_t p = 0; p < (uint32_t)enc.path_map.size(); p++) {
+        const uint32_t k = enc.path_map[p];
+        const sx_affine& X = xforms[paths->xform_ix[k]];
+        if (styles[paths->style_ix[k]].flags & SX_STYLE_FILL) {
+            if (!invertible(X)) return fail(ctx, SX_EINVAL, "fill transforms must be invertible");
+        } else if (!similarity(X)) {
+            return fail(ctx, SX_EINVAL, "stroke transforms must be similarities");
+        }
     }
     std::vector<float> xd(6 * enc.xform_stream.size());
     for (size_t i = 0; i < enc.xform_stream.size(); i++) {
         const sx_affine& X = xforms[enc.xform_stream[i]];
-        if (!similarity(X)) return fail(ctx, SX_EINVAL, "stroke transforms must be similarities");
         const float v[6] = {X.a, X.b, X.c, X.d, X.e, X.f};
         memcpy(&xd[6 * i], v, sizeof(v));
     }

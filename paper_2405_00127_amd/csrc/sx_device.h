@@ -55,6 +55,8 @@ struct StyleD {
     float half_width, miter_limit;
     uint32_t packed;  // join | start_cap << 8 | end_cap << 16 | flags << 24
 };
+// a fill: flattened at offset 0 (half_width 0), one side, no joins or caps
+constexpr uint32_t kStyleFill = 1u << 24;
 
 // ---------------------------------------------------------- small vectors
 struct V2 {  // FP32 (per-point work, outputs)
@@ -754,8 +756,8 @@ SX_FN SideGeo side_geo(const ES& es, double w, int side) {
 }
 
 template <class Sink>
-SX_FN void emit_sides(Sink& k, const Cfg& cfg, const ES& es, double w) {
-    for (int side = 0; side < 2; side++) {
+SX_FN void emit_sides(Sink& k, const Cfg& cfg, const ES& es, double w, bool fill) {
+    for (int side = 0; side < (fill ? 1 : 2); side++) {
         const SideGeo g = side_geo(es, w, side);
         emit_range(k, cfg, es, g.h, 0.0, g.tc, g.rev1, true, !g.split, g.P0, g.Pc);
         if (g.split) emit_range(k, cfg, es, g.h, g.tc, 1.0, g.rev2, false, true, g.Pc, g.P1);
@@ -1005,9 +1007,15 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
         const float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
         float kap;
         if (hdr & kIfKSame) {
-            const float P15 = Pa15 + f * (Pb15 - Pa15);
-            kap = cbrtf(P15 * P15);
-            tau = (ab != aa) ? (kap - aa) / (ab - aa) : f;
+            // with a = sqrt|kappa_a|, b = sqrt|kappa_b| and p^3 = a^3 +
+            // f (b^3 - a^3), tau = (p^2 - a^2) / (b^2 - a^2); dividing
+            // p^3 - a^3 by b^3 - a^3 gives it without cancellation (nearly
+            // constant curvature): tau = f (a^2 + ab + b^2)(p + a) /
+            // ((a^2 + ap + p^2)(a + b))
+            const float a = sqrtf(aa), b = sqrtf(ab);
+            const float p = cbrtf(Pa15 + f * (Pb15 - Pa15));
+            const float den = (aa + a * p + p * p) * (a + b);
+            tau = (den > 0.0f) ? f * (aa + a * b + ab) * (p + a) / den : f;
         } else {
             const float target = f * (Pa15 + Pb15);
             if (target <= Pa15) {
@@ -1160,6 +1168,7 @@ struct Seg {
     D2 A2, B2, C3;    // D2 - 2 D1, D3 - 2 D2 + D1, D3 - 3 D2 + 3 D1
     D2 ts, te;        // end tangents (transformed raw differences)
     double w, lpoly;
+    bool fill;        // one side at offset 0 (the path itself)
 };
 
 struct Tan {
@@ -1235,6 +1244,7 @@ struct TagInfo {
     float miter;
     int join, scap, ecap;
     bool line;
+    bool fill;       // one side at offset 0, no join or cap
 };
 
 // Input path id of tag i (all ones for a tag outside every path).
@@ -1249,6 +1259,7 @@ SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s
     const uint32_t n = sv.n_tags;
     ti.kind = kTagInvalid;
     ti.line = false;
+    ti.fill = false;
     const uint32_t tag = sv.tags[i];
     const uint32_t off = sv.mon[i];
     const uint32_t sty = sv.mon[2 * (size_t)n + i];
@@ -1272,6 +1283,7 @@ SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s
     ti.join = st.packed & 0xff;
     ti.scap = (st.packed >> 8) & 0xff;
     ti.ecap = (st.packed >> 16) & 0xff;
+    ti.fill = (st.packed & kStyleFill) != 0u;
     if (tag & kTagEnd) {
         ti.kind = kTagMarker;
         return;
@@ -1285,6 +1297,7 @@ SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s
     const float2 r0 = D[0], r1 = D[1], r2 = D[c >= 2 ? 2 : 1], r3 = D[c >= 3 ? 3 : c];
     const float2 rc = (c == 1) ? r1 : ((c == 2) ? r2 : r3);
     s.w = ti.w;
+    s.fill = ti.fill;
     s.P0w = xf_apply(X, r0.x, r0.y);
     s.P3w = xf_apply(X, rc.x, rc.y);
     // transformed differences r_j - r_0
@@ -1481,13 +1494,15 @@ template <class Sink>
 SX_HD void emit_piece(Sink& k, const Cfg& cfg, const Seg& s, bool line, uint32_t t0_u, uint32_t depth, bool pivot) {
     ES es;
     piece_es(k, cfg, s, line, t0_u, depth, pivot, es);
-    emit_sides(k, cfg, es, s.w);
+    emit_sides(k, cfg, es, s.w, s.fill);
 }
 
 // The tail of tag i: the start cap of an open subpath (stroke cap marker),
-// or the join with tag i + 1 / the end cap of a segment (Algorithm 1).
+// or the join with tag i + 1 / the end cap of a segment (Algorithm 1);
+// nothing for a fill.
 template <class Sink>
 SX_HD void emit_tail(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i, const TagInfo& ti, const Seg& s) {
+    if (ti.fill) return;  // a fill has no joins or caps
     if (ti.kind == kTagMarker) {
         if (!(ti.tag & kTagClosed)) {
             const float2* D = sv.pts + ti.off;

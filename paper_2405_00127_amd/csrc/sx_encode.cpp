@@ -5,7 +5,8 @@
 // the previous segment's last, except at subpath starts), the style and
 // transform streams (one entry per change between consecutive paths, the
 // tag's style / transform bit marking the change) and the encoded-path ->
-// input-path map.
+// input-path map.  A fill's subpaths all end closed: a line back to the start
+// point is added where a subpath ends elsewhere without a closepath.
 #include "sx_encode.h"
 
 #include <cmath>
@@ -30,7 +31,8 @@ struct SubpathState {
 inline bool same(float ax, float ay, float bx, float by) { return ax == bx && ay == by; }
 }  // namespace
 
-bool encode_paths(const sx_paths& in, uint32_t n_styles, uint32_t n_xforms, HostEncoding& out, std::string& err) {
+bool encode_paths(const sx_paths& in, const sx_style* styles, uint32_t n_styles, uint32_t n_xforms,
+                  HostEncoding& out, std::string& err) {
     out = HostEncoding{};
     out.tags.reserve(in.verb_off ? in.verb_off[in.n_paths] + in.n_paths : 0);
     int64_t prev_style = -1, prev_xf = -1;
@@ -46,12 +48,25 @@ bool encode_paths(const sx_paths& in, uint32_t n_styles, uint32_t n_xforms, Host
             return false;
         }
         const size_t first_tag = out.tags.size();
+        const bool fill = (styles[in.style_ix[k]].flags & SX_STYLE_FILL) != 0;
         const float* P = in.pts + 2 * (size_t)in.pt_off[k];
         const uint32_t np = in.pt_off[k + 1] - in.pt_off[k];
         uint32_t pi = 0;
         SubpathState sp;
+        auto close_line = [&]() {
+            if (!same(sp.cx, sp.cy, sp.sx, sp.sy)) {
+                out.tags.push_back((uint8_t)(1u | kF32));
+                put_pt(sp.sx, sp.sy);
+                sp.cx = sp.sx;
+                sp.cy = sp.sy;
+            }
+        };
         auto finish = [&]() {
             if (sp.open && sp.nseg > 0) {
+                if (fill && !sp.closed) {
+                    close_line();
+                    sp.closed = true;
+                }
                 out.tags.push_back((uint8_t)(2u | kEnd | kF32 | (sp.closed ? kClosedBit : 0u)));
                 if (!sp.has_dir) { sp.dx = sp.sx + 1.0f; sp.dy = sp.sy; }
                 put_pt(sp.sx, sp.sy);
@@ -72,12 +87,7 @@ bool encode_paths(const sx_paths& in, uint32_t n_styles, uint32_t n_xforms, Host
                 pi++;
             } else if (v == SX_CLOSE) {
                 if (!sp.open) continue;
-                if (sp.nseg > 0 && !same(sp.cx, sp.cy, sp.sx, sp.sy)) {
-                    out.tags.push_back((uint8_t)(1u | kF32));
-                    put_pt(sp.sx, sp.sy);
-                    sp.cx = sp.sx;
-                    sp.cy = sp.sy;
-                }
+                if (sp.nseg > 0) close_line();
                 sp.closed = true;
                 finish();
                 // the current point returns to the start; a following drawing

@@ -17,6 +17,9 @@ struct HostEncoding {
     std::vector<uint32_t> path_map;      // encoded path -> input path
 };
 
-bool encode_paths(const sx_paths& in, uint32_t n_styles, uint32_t n_xforms, HostEncoding& out, std::string& err);
+// styles: the caller's style table (n_styles entries); a path whose style
+// has SX_STYLE_FILL gets every subpath closed.
+bool encode_paths(const sx_paths& in, const sx_style* styles, uint32_t n_styles, uint32_t n_xforms,
+                  HostEncoding& out, std::string& err);
 
 }  // namespace sx

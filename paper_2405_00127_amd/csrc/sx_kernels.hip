@@ -587,6 +587,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         ES es;
         SideGeo g0, g1;
         uint32_t qa = 0, qb = 0;
+        bool side1 = false;  // a stroke's second side (a fill has one)
         if (act && sl.tag < sv.n_tags) {
             k.path = path_of(sv, sl.tag);
             TagInfo ti;
@@ -595,10 +596,12 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
             if (ti.kind == kTagSegment) {
                 have = true;
                 piece_es(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code), es);
+                side1 = !sg.fill;
                 g0 = side_geo(es, sg.w, 0);
                 g1 = side_geo(es, sg.w, 1);
+                g1.split = g1.split && side1;
                 s_first[0][t] = range_count(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
-                s_first[1][t] = range_count(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
+                if (side1) s_first[1][t] = range_count(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
                 if (g0.split || g1.split) {
                     s_own[t][0] = es.k0;
                     s_own[t][1] = es.k1;
@@ -631,8 +634,10 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         if (have) {
             range_put(k, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
             if (g0.split) range_put(k, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, s_res[qa]);
-            range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
-            if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, s_res[qb]);
+            if (side1) {
+                range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
+                if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, s_res[qb]);
+            }
         }
         if (act) {
             rc[j] = k.n;
