@@ -116,6 +116,8 @@ def plain(args, ctx, B, S, torch, np):
     stream = torch.cuda.current_stream()
     log("bench: generating the map scene")
     sc = S.scene_map(2, args.segments, args.paths, 0.25, mode)
+    if args.fill_scene:
+        sc = S.with_fills(sc)
     n_seg = sc.n_segments()
     scene = ctx.encode(sc, stream=stream)
     tol = sc.tolerance
@@ -228,7 +230,8 @@ def plain(args, ctx, B, S, torch, np):
         "data": "synthetic (seeded map/CAD-shaped scene; the paper's datasets are not available)",
         "config": {
             "workload": f"map/CAD scene, {args.paths} paths, {n_seg} segments (60% lines, 15% quads, 25% cubics), "
-                        f"plain per-scene expansion, {args.mode}, tol 0.25 px",
+                        + ("every path filled, " if args.fill_scene else "")
+                        + f"plain per-scene expansion, {args.mode}, tol 0.25 px",
             "segments": n_seg, "tags": n_tags, "records": n_rec, "output": args.mode, "tolerance": tol,
         },
         "output_records_per_s": n_rec / (ms * 1e-3),
@@ -579,6 +582,8 @@ def main():
     ap.add_argument("--bisect-waves", type=int, default=None)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fill", action="store_true", help="skip the fill leg (the map scene filled)")
+    ap.add_argument("--fill-scene", action="store_true",
+                    help="time the map scene with every path filled in the main leg (for profiling the fill)")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true")
@@ -614,7 +619,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     out, sc, mode = plain(args, ctx, B, S, torch, np)
-    traffic = measured_traffic(out["roofline"]["kernel"], args.mode)
+    # the stored counters are those of the stroked map scene
+    traffic = None if args.fill_scene else measured_traffic(out["roofline"]["kernel"], args.mode)
     if traffic is not None:
         out["roofline"]["traffic"] = traffic
     fill_sc = None
