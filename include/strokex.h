@@ -157,6 +157,35 @@ int sx_scene_download(const sx_scene *scene, uint8_t *tags, float *data, uint32_
 int sx_expand(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mode, void *out_dev,
               uint64_t out_capacity_bytes, uint64_t *out_count, void *stream);
 
+/* Single-pass expansion, the paper's own organisation (Section 8.1), kept as
+ * an ablation of the count / scan / write pipeline: after the tag-monoid
+ * scan, one thread per tag runs its bisection, its pieces' parallel curves
+ * and its join or cap, reserving each range's (or join's) records with an
+ * atomic add on one counter.  The records are the same as sx_expand's but in
+ * no defined order across ranges (a line soup; within a range they keep
+ * their order).  out_dev: device memory of out_capacity_bytes, caller-owned;
+ * *out_count (host) receives the number of records the scene needs.  If it
+ * exceeds the capacity, the records past it are dropped (those before it are
+ * written, in no defined selection) and SX_ETOOSMALL is returned: size the
+ * buffer with *out_count and call again.  Blocks the host until the count is
+ * known.  Errors: SX_EINVAL (tolerance, mode, null pointers), SX_ETOOSMALL,
+ * SX_EDEVICE.  Currently switched off: returns SX_EDEVICE without launching
+ * anything for a non-empty scene (its kernel did not finish on its first GPU
+ * run and the cause is not yet known). */
+int sx_expand_soup(sx_ctx *ctx, sx_scene *scene, float tolerance, int output_mode, void *out_dev,
+                   uint64_t out_capacity_bytes, uint64_t *out_count, void *stream);
+
+/* Host-side estimate of the records a scene needs, for sizing the
+ * single-pass output before any GPU work (Section 8.1 sizes its buffer with
+ * Wang's formula): per curve, Wang's count sqrt(d (d - 1) M / (8 t)) at the
+ * flattening tolerance t (M the largest second difference of the world
+ * control polygon), times sqrt(1 + w d (d - 1) M / chord^2) per stroke side,
+ * plus evolute room, plus a bound per join or cap.  A heuristic, not a bound
+ * (parallel curves near cusps can need more): sx_expand_soup reports the
+ * exact need when it is short.  Scenes from sx_scene_encode only (0 for a
+ * batch arena).  Errors: SX_EINVAL. */
+int sx_scene_estimate(const sx_scene *scene, float tolerance, int output_mode, uint64_t *out_records);
+
 /* Same pipeline without any host synchronisation or allocation (capturable
  * in a HIP graph).  out_count_dev: device memory, two uint64_t:
  *   [0] the record count (always written when the workspace sufficed);

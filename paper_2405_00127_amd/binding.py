@@ -90,6 +90,8 @@ def lib():
                 "sx_batch_info": (C.c_int, [vp, vp, C.POINTER(vp)]),
                 "sx_batch_expand": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, u64, vp, vp, vp]),
                 "sx_get_tuning": (C.c_int, [vp, C.POINTER(_Tuning)]),
+                "sx_expand_soup": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, u64, C.POINTER(u64), vp]),
+                "sx_scene_estimate": (C.c_int, [vp, C.c_float, C.c_int, C.POINTER(u64)]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -199,6 +201,52 @@ class Context:
             raise e
         self._check(rc, "sx_expand")
         return cnt.value
+
+    def expand_soup_into(self, scene: Scene, out_ptr: int, capacity_bytes: int, tolerance: float, mode: int,
+                         stream=None) -> int:
+        """Single-pass expansion (unordered line soup); returns the record count,
+        raises on SX_ETOOSMALL with .required set."""
+        cnt = C.c_uint64()
+        rc = lib().sx_expand_soup(C.c_void_p(self.h), C.c_void_p(scene.h), float(tolerance), int(mode),
+                                  C.c_void_p(out_ptr), int(capacity_bytes), C.byref(cnt), _stream_ptr(stream))
+        if rc == SX_ETOOSMALL:
+            e = StrokexError(rc, "output buffer too small")
+            e.required = cnt.value
+            raise e
+        self._check(rc, "sx_expand_soup")
+        return cnt.value
+
+    def estimate(self, scene: Scene, tolerance: Optional[float] = None, mode: Optional[int] = None) -> int:
+        """Host-side estimate of the records the scene needs (Wang's formula)."""
+        tol = scene.src.tolerance if tolerance is None else tolerance
+        mode = scene.src.output_mode if mode is None else mode
+        n = C.c_uint64()
+        self._check(lib().sx_scene_estimate(C.c_void_p(scene.h), float(tol), int(mode), C.byref(n)),
+                    "sx_scene_estimate")
+        return n.value
+
+    def expand_soup(self, scene: Scene, tolerance: Optional[float] = None, mode: Optional[int] = None,
+                    stream=None):
+        """Single-pass expansion into a buffer sized by the estimate; a short
+        buffer is regrown to the reported need and the call repeated once.
+        Returns (records view [n, 5|6] float32, count, buffer, retried)."""
+        import torch
+
+        tol = scene.src.tolerance if tolerance is None else tolerance
+        mode = scene.src.output_mode if mode is None else mode
+        rec = RECORD_BYTES[mode]
+        cap = max(1, self.estimate(scene, tol, mode))
+        out = torch.empty(cap * rec, dtype=torch.uint8, device=f"cuda:{self.device}")
+        retried = False
+        try:
+            n = self.expand_soup_into(scene, out.data_ptr(), out.numel(), tol, mode, stream)
+        except StrokexError as e:
+            if e.code != SX_ETOOSMALL:
+                raise
+            retried = True
+            out = torch.empty(max(1, e.required) * rec, dtype=torch.uint8, device=out.device)
+            n = self.expand_soup_into(scene, out.data_ptr(), out.numel(), tol, mode, stream)
+        return out[: n * rec].view(torch.float32).view(-1, rec // 4), n, out, retried
 
     def expand_async(self, scene: Scene, out_ptr: int, capacity_bytes: int, count_dev_ptr: int, tolerance: float,
                      mode: int, stream=None):

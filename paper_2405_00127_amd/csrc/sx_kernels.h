@@ -64,6 +64,11 @@ hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, c
                         uint64_t slot_cap, uint32_t* rc, unsigned long long* stats, hipStream_t s);
 hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff,
                           const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s);
+// Single-pass expansion into an unordered line soup (one thread per tag;
+// records reserved with atomic adds on *counter, which ends at the total the
+// scene needs even when it exceeds cap_records).
+hipError_t launch_soup(const SceneView& sv, const Cfg& cfg, void* out, uint64_t cap_records,
+                       unsigned long long* counter, hipStream_t s);
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,
                          float* xforms, uint32_t* path_map, hipStream_t s);
 hipError_t launch_scene_offsets(const uint64_t* base, const uint64_t* roff, uint64_t slot_cap, const GatherDesc* descs,

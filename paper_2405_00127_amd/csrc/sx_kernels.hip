@@ -815,6 +815,79 @@ __global__ __launch_bounds__(kRecBlock, 6) void record_kernel(SceneView sv, Item
     }
 }
 
+// ----------------------------------------------------- single pass
+// The paper's own organisation (Section 8.1), kept as an ablation of the
+// count / scan / write pipeline: one thread per tag runs its bisection, its
+// pieces' sides and its join or cap in sequence, and every item's records
+// are reserved with one atomic add on a global counter and written at once
+// (a line soup: records of a range stay together, ranges land in any order).
+struct SoupSink {
+    static constexpr bool kStats = false;
+    float* out;
+    uint64_t cap;
+    unsigned long long* counter;
+    float* es_tab;  // the current piece's FP32 spiral (8 floats, slot 0)
+    XIncF xi;
+    uint32_t path, slot, n, arcs;
+    uint32_t st[1];
+    template <class P>
+    __device__ void put(uint32_t hdr, uint32_t nrec, uint32_t K, const P& p) {
+        n += nrec;
+        if (nrec == 0u) return;
+        const uint64_t base = atomicAdd(counter, (unsigned long long)nrec);
+        if (base + nrec > cap) return;  // counted only: the caller sees the total
+        uint32_t w[2 * kUnitWords];
+        *reinterpret_cast<P*>(w + kHdrWords) = p;
+        const uint32_t nc = chunks(nrec, K);
+        for (uint32_t c = 0; c < nc; c++) {
+            const uint32_t nchunk = (c + 1 < nc) ? K : nrec - c * K;
+            w[0] = hdr | (nchunk << 24);
+            w[1] = path;
+            w[2] = 0u;
+            w[3] = c * K;
+            w[4] = c * K;
+            w[5] = nrec;
+            RecOut o{out, base + (uint64_t)c * K, base + nrec, path, (int)arcs, nullptr, 0, 0};
+            emit_item(w, es_tab, xi, o);
+        }
+    }
+};
+
+__global__ __launch_bounds__(256) void soup_kernel(SceneView sv, Cfg cfg, XIncF xi, float* __restrict__ out,
+                                                   uint64_t cap, unsigned long long* __restrict__ counter) {
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sv.n_tags; i += stride) {
+        float es_loc[8];
+        SoupSink k{out, cap, counter, es_loc, xi, path_of(sv, i), 0u, 0u, (uint32_t)cfg.arcs, {0u}};
+        TagInfo ti;
+        Seg sg;
+        fetch_tag(sv, i, ti, sg);
+        if (ti.kind == kTagSegment) {
+            Bisect bs;
+            bisect_init(bs, sg);
+            for (;;) {
+                uint32_t t0u = 0, depth = 0;
+                bool done = false, pivot = false;
+                if (bisect_step(bs, sg, cfg, ti.line, t0u, depth, pivot, done)) {
+                    emit_piece(k, cfg, sg, ti.line, t0u, depth, pivot);
+                    if (done) break;
+                }
+            }
+        }
+        emit_tail(k, cfg, sv, i, ti, sg);
+    }
+}
+
+hipError_t launch_soup(const SceneView& sv, const Cfg& cfg, void* out, uint64_t cap_records,
+                       unsigned long long* counter, hipStream_t s) {
+    if (sv.n_tags == 0) return hipSuccess;
+    XIncF xi;
+    for (int k = 0; k < 5; k++) xi.v[k] = (float)cfg.xinc[k];
+    const uint32_t blocks = (sv.n_tags + 255u) / 256u;
+    soup_kernel<<<blocks < 16384u ? blocks : 16384u, 256, 0, s>>>(sv, cfg, xi, (float*)out, cap_records, counter);
+    return hipGetLastError();
+}
+
 // dst[0] = records, dst[1] = 0 when everything fit, else 1 (slots or items
 // were dropped: the workspace must grow); the counters stay in ws.ctl.
 __global__ void finish_kernel(const uint64_t* __restrict__ roff, const uint64_t* __restrict__ n_slots_dev,

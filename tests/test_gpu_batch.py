@@ -45,6 +45,10 @@ def _mixed_scenes(mode):
         S.single_path_scene([S.MOVE, S.LINE], [(10.0, 10.0), (40.0, 12.0)], 3.0, S.JOIN_MITER, S.CAP_SQUARE,
                             output_mode=mode),
         S.scene_map(14, 20000, 150, 0.25, mode),
+        # fills: a filled map scene, and half fills under a shear
+        S.with_fills(S.scene_map(15, 4000, 30, 0.25, mode)),
+        S.with_fills(S.scene_c1(1, output_mode=mode).subset(range(5)), 0.5, seed=2,
+                     xform=[1.0, 0.2, 0.5, 0.9, 10.0, -5.0]),
     ]
 
 

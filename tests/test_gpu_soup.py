@@ -1,0 +1,139 @@
+"""Single-pass expansion (the paper's own organisation, an ablation of the
+count / scan / write pipeline), through the C ABI.
+
+Its output is a line soup: the same records in no defined order across
+ranges.  Bars: per path, the soup and the oracle's records match as
+multisets (same number; every record within 1e-3 px of one of the other
+side's, both ways); the soup and the ordered pipeline's records are the same
+multiset bit for bit; the total equals the ordered count; a short buffer is
+reported with the exact need."""
+import sys
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle as O
+import parity as P
+from paper_2405_00127_amd import scenes as S
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="single-pass kernel switched off: its first GPU run did not finish and the cause "
+                            "is not yet known; sx_expand_soup returns SX_EDEVICE without launching"),
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+    from paper_2405_00127_amd import build as PB
+
+    if not __import__("os").path.exists(B.LIB_PATH):
+        PB.build()
+    torch.cuda.set_device(0)
+    c = B.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _scene(name):
+    return {
+        "c1_lines": lambda: S.scene_c1(1),
+        "c1_arcs": lambda: S.scene_c1(1, output_mode=S.OUT_ARCS),
+        "c2_lines": lambda: S.scene_c2(2, n_segments=40000, n_paths=400),
+        "c3_arcs": lambda: S.scene_c3(3, n_cubics=3000),
+        "c1_fill_shear": lambda: S.with_fills(S.scene_c1(1), 0.5, seed=3, xform=[1.0, 0.2, 0.5, 0.9, 10.0, -5.0]),
+    }[name]()
+
+
+def _soup(ctx, sc):
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    scene = ctx.encode(sc)
+    recs, n, _, retried = ctx.expand_soup(scene, sc.tolerance, sc.output_mode)
+    torch.cuda.synchronize()
+    return scene, B.records_to_numpy(recs, sc.output_mode).copy(), n, retried
+
+
+def _sorted_bytes(r):
+    v = np.ascontiguousarray(r).view(np.dtype((np.void, r.dtype.itemsize)))
+    return np.sort(v)
+
+
+@pytest.mark.parametrize("name", ["c1_lines", "c1_arcs", "c2_lines", "c3_arcs", "c1_fill_shear"])
+def test_soup_matches_the_oracle_as_multisets(ctx, name):
+    from paper_2405_00127_amd import binding as B
+
+    sc = _scene(name)
+    _say("soup", name, "segments", sc.n_segments())
+    scene, soup, n, retried = _soup(ctx, sc)
+    est = ctx.estimate(scene)
+    _say(name, "records", n, "estimate", est, "retried", retried)
+    ref = O.expand(sc)
+    assert ref.status == 0
+    assert n == len(ref.out) == int(ref.counts.sum())
+    # the ordered pipeline's records, the same multiset bit for bit
+    recs, n2, _ = ctx.expand(scene, sc.tolerance, sc.output_mode)
+    ordered = B.records_to_numpy(recs, sc.output_mode)
+    assert n2 == n
+    assert np.array_equal(_sorted_bytes(soup), _sorted_bytes(ordered))
+    # against the oracle, per path
+    worst = 0.0
+    o = ref.out
+    for p in np.unique(o["path"]):
+        a = soup[soup["path"] == p]
+        b = o[o["path"] == p]
+        assert len(a) == len(b), p
+        A = np.stack([a["x0"], a["y0"], a["x1"], a["y1"]], 1).astype(np.float64)
+        Bq = np.stack([b["x0"], b["y0"], b["x1"], b["y1"]], 1)
+        d1 = cKDTree(Bq).query(A, p=np.inf)[0]
+        d2 = cKDTree(A).query(Bq, p=np.inf)[0]
+        worst = max(worst, float(d1.max()), float(d2.max()))
+    _say(name, "worst record distance", worst)
+    assert worst <= P.ENDPOINT_TOL
+    assert P.closed_per_path(soup) == 0
+
+
+def test_short_buffer_reports_the_exact_need(ctx):
+    import torch
+
+    from paper_2405_00127_amd import binding as B
+
+    sc = _scene("c1_lines")
+    scene = ctx.encode(sc)
+    n_ref = int(O.expand(sc, emit=False).counts.sum())
+    buf = torch.empty(100 * B.RECORD_BYTES[0], dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(B.StrokexError) as ei:
+        ctx.expand_soup_into(scene, buf.data_ptr(), buf.numel(), sc.tolerance, 0)
+    assert ei.value.code == B.SX_ETOOSMALL and ei.value.required == n_ref
+    # a repeated call after the failure starts from a cleared counter
+    with pytest.raises(B.StrokexError) as ei:
+        ctx.expand_soup_into(scene, buf.data_ptr(), buf.numel(), sc.tolerance, 0)
+    assert ei.value.required == n_ref
+
+
+def test_full_size_map_scene_soup(ctx):
+    """The 1M-segment map scene: the soup is the ordered pipeline's output as a
+    multiset, bit for bit, and the host estimate covers it."""
+    from paper_2405_00127_amd import binding as B
+
+    sc = S.scene_c2(2)
+    _say("full soup: encode")
+    scene, soup, n, retried = _soup(ctx, sc)
+    est = ctx.estimate(scene)
+    _say("full soup: records", n, "estimate", est, "retried", retried)
+    recs, n2, _ = ctx.expand(scene, sc.tolerance, sc.output_mode)
+    assert n2 == n
+    assert not retried and est >= n
+    ordered = B.records_to_numpy(recs, sc.output_mode)
+    assert np.array_equal(_sorted_bytes(soup), _sorted_bytes(ordered))
