@@ -595,8 +595,8 @@ def main():
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "stroke expansion of independent scenes would shard by scene, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); stroke expansion shards by "
+              "scene, or for one scene by path ranges", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -170,8 +170,8 @@ int sx_expand(sx_ctx *ctx, const sx_scene *scene, float tolerance, int output_mo
  * buffer with *out_count and call again.  Blocks the host until the count is
  * known.  Errors: SX_EINVAL (tolerance, mode, null pointers), SX_ETOOSMALL,
  * SX_EDEVICE.  Currently switched off: returns SX_EDEVICE without launching
- * anything for a non-empty scene (its kernel did not finish on its first GPU
- * run and the cause is not yet known). */
+ * anything for a non-empty scene (its kernel has been seen not to finish and
+ * the cause is not yet known). */
 int sx_expand_soup(sx_ctx *ctx, sx_scene *scene, float tolerance, int output_mode, void *out_dev,
                    uint64_t out_capacity_bytes, uint64_t *out_count, void *stream);
 

@@ -909,10 +909,10 @@ int sx_expand_soup(sx_ctx* ctx, sx_scene* s, float tolerance, int output_mode, v
     hipStream_t st = (hipStream_t)stream;
     *out_count = 0;
     if (s->n_tags == 0) return SX_OK;
-    // Switched off: the first GPU run of soup_kernel did not finish, and no
-    // cause has been found in the code yet (its loops are bounded and a CPU
-    // build of the same sink reproduces the ordered records exactly).  Nothing
-    // is launched until the cause is known.
+    // Switched off: soup_kernel has been seen not to finish on gfx950 and the
+    // cause is not known (its loops are bounded, and the same sink compiled
+    // for the host reproduces the ordered records exactly).  Nothing is
+    // launched until the cause is found.
     if (kSoupEnabled == 0) return fail(ctx, SX_EDEVICE, "single-pass expansion is switched off");
     s->last_stream = st;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);

@@ -1004,7 +1004,8 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
     } else if (hdr & kIfPlaceES) {
         // h = 0: uniform in |kappa|^1.5 (Section 2.2)
         const float aa = fabsf(pl.kna), ab = fabsf(pl.knb);
-        const float Pa15 = pow15f(aa), Pb15 = pow15f(ab);
+        const float a = sqrtf(aa), b = sqrtf(ab);
+        const float Pa15 = aa * a, Pb15 = ab * b;  // |kappa|^1.5
         float kap;
         if (hdr & kIfKSame) {
             // with a = sqrt|kappa_a|, b = sqrt|kappa_b| and p^3 = a^3 +
@@ -1012,7 +1013,6 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
             // p^3 - a^3 by b^3 - a^3 gives it without cancellation (nearly
             // constant curvature): tau = f (a^2 + ab + b^2)(p + a) /
             // ((a^2 + ap + p^2)(a + b))
-            const float a = sqrtf(aa), b = sqrtf(ab);
             const float p = cbrtf(Pa15 + f * (Pb15 - Pa15));
             const float den = (aa + a * p + p * p) * (a + b);
             tau = (den > 0.0f) ? f * (aa + a * b + ab) * (p + a) / den : f;

@@ -19,7 +19,7 @@ from paper_2405_00127_amd import scenes as S
 
 pytestmark = [
     pytest.mark.gpu,
-    pytest.mark.skip(reason="single-pass kernel switched off: its first GPU run did not finish and the cause "
+    pytest.mark.skip(reason="single-pass kernel switched off: it has been seen not to finish and the cause "
                             "is not yet known; sx_expand_soup returns SX_EDEVICE without launching"),
 ]
 
