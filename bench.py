@@ -110,6 +110,54 @@ def cpu_baseline(sc, mode, budget_s=12.0):
 
 
 # ------------------------------------------------------------------ plain
+def roofline_of(phase_ms, stats, n_tags, n_rec, mode, names):
+    """Roofline entry of the dominant phase and the achieved rate of every
+    phase: algorithmic work per launch (per-unit figures times the unit
+    counts of the instrumented run) over the average launch time."""
+    n_slots = stats["pieces"] + n_tags
+    curve_pieces = stats["pieces"] - stats["lines"]
+    work = {
+        # algorithmic FP64 flops per launch of each kernel
+        "bisect_count": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
+        "pieces": (curve_pieces * FLOPS["piece"] + stats["lines"] * FLOPS["line"] + stats["ranges"] * FLOPS["range"]
+                   + stats["evolutes"] * FLOPS["evolute"]),
+        "tails": stats["joins"] * FLOPS["join"],
+        # algorithmic FP32 flops
+        "records": n_rec * FLOPS_PER_RECORD[mode],
+        # algorithmic bytes
+        "scan_tags": n_tags * 17.0,
+        "scan_slots": n_tags * 12.0,
+        "scan_records": n_slots * 12.0,
+        # the write pass copies the kept piece codes into the canonical slot
+        # array (a tag with more pieces than are kept re-runs its bisection)
+        "bisect_write": n_slots * 8.0 + (n_slots - n_tags) * 4.0 + n_tags * 12.0,
+    }
+    dom = max(phase_ms, key=phase_ms.get)
+    t_dom = phase_ms[dom] * 1e-3
+    if dom in ("bisect_count", "pieces", "tails"):
+        achieved = work[dom] / t_dom / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "precision": "fp64 (decisions)"}
+    elif dom == "records":
+        achieved = work[dom] / t_dom / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
+    else:
+        gbs = work[dom] / t_dom / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": gbs / PEAK_HBM_GBS, "traffic": None}
+    roof["algorithmic_work_per_launch"] = work[dom]
+    roof["phase_ms"] = phase_ms
+    roof["work_counts"] = stats
+    roof["flops_per_unit"] = FLOPS
+    roof["flops_per_record"] = FLOPS_PER_RECORD[mode]
+    roof["per_kernel"] = {
+        n: ({"TFLOP/s": work[n] / (phase_ms[n] * 1e-3) / 1e12} if n in ("bisect_count", "pieces", "tails",
+                                                                         "records")
+            else {"GB/s": work[n] / (phase_ms[n] * 1e-3) / 1e9}) for n in names}
+    return roof
+
+
 def plain(args, ctx, B, S, torch, np):
     mode = S.OUT_LINES if args.mode == "lines" else S.OUT_ARCS
     dev = torch.device("cuda:0")
@@ -174,47 +222,7 @@ def plain(args, ctx, B, S, torch, np):
     log(f"bench: work {stats}")
 
     n_tags = scene.n_tags
-    n_slots = stats["pieces"] + n_tags
-    curve_pieces = stats["pieces"] - stats["lines"]
-    work = {
-        # algorithmic FP64 flops per launch of each kernel
-        "bisect_count": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
-        "pieces": (curve_pieces * FLOPS["piece"] + stats["lines"] * FLOPS["line"] + stats["ranges"] * FLOPS["range"]
-                   + stats["evolutes"] * FLOPS["evolute"]),
-        "tails": stats["joins"] * FLOPS["join"],
-        # algorithmic FP32 flops
-        "records": n_rec * FLOPS_PER_RECORD[mode],
-        # algorithmic bytes
-        "scan_tags": n_tags * 17.0,
-        "scan_slots": n_tags * 12.0,
-        "scan_records": n_slots * 12.0,
-        # the write pass copies the kept piece codes into the canonical slot
-        # array (a tag with more pieces than are kept re-runs its bisection)
-        "bisect_write": n_slots * 8.0 + (n_slots - n_tags) * 4.0 + n_tags * 12.0,
-    }
-    dom = max(phase_ms, key=phase_ms.get)
-    t_dom = phase_ms[dom] * 1e-3
-    if dom in ("bisect_count", "pieces", "tails"):
-        achieved = work[dom] / t_dom / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "precision": "fp64 (decisions)"}
-    elif dom == "records":
-        achieved = work[dom] / t_dom / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
-    else:
-        gbs = work[dom] / t_dom / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": gbs / PEAK_HBM_GBS, "traffic": None}
-    roof["algorithmic_work_per_launch"] = work[dom]
-    roof["phase_ms"] = phase_ms
-    roof["work_counts"] = stats
-    roof["flops_per_unit"] = FLOPS
-    roof["flops_per_record"] = FLOPS_PER_RECORD[mode]
-    roof["per_kernel"] = {
-        n: ({"TFLOP/s": work[n] / (phase_ms[n] * 1e-3) / 1e12} if n in ("bisect_count", "pieces", "tails",
-                                                                         "records")
-            else {"GB/s": work[n] / (phase_ms[n] * 1e-3) / 1e9}) for n in names}
+    roof = roofline_of(phase_ms, stats, n_tags, n_rec, mode, names)
     out = {
         "metric": "path segs/s expanded at 0.25px tol (batched vs plain); p50/p99 request latency",
         "value": n_seg / (ms * 1e-3),
@@ -281,12 +289,16 @@ def fill(args, ctx, B, S, torch, np):
     torch.cuda.synchronize()
     phase_ms = {names[p]: sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
                 for p in range(len(names))}
+    stats = ctx.piece_stats(scene, tol, mode, stream=stream)
+    roof = roofline_of(phase_ms, stats, scene.n_tags, n_rec, mode, names)
     res = {
         "workload": f"map/CAD scene, {args.paths} paths, {n_seg} segments, every path filled, {args.mode}, "
                     f"tol 0.25 px",
         "segments": n_seg, "tags": scene.n_tags, "records": n_rec,
         "ms_per_step": ms, "segs_per_s": n_seg / (ms * 1e-3), "records_per_s": n_rec / (ms * 1e-3),
         "phase_ms": phase_ms,
+        "roofline": {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                                          "algorithmic_work_per_launch", "per_kernel", "work_counts")},
     }
     log(f"bench: fill {ms:.3f} ms/step, {n_rec} records; phases "
         + ", ".join(f"{n} {phase_ms[n]:.3f}" for n in names))
