@@ -374,6 +374,7 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // their canonical positions: copied from the kept codes, or, for the few
 // segments with more pieces, from a second run of the bisection.
 constexpr int kBisectBlock = 64;
+constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (8 beat 4, 12, 16 and 32 on the map scene)
 
 template <bool Write, bool Stats, int MinWaves>
 __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
@@ -393,11 +394,11 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
     Bisect bs;
     uint32_t n_trials = 0, n_lines = 0;
     for (;;) {
-        // refill idle lanes with the next tags of the range, once a quarter
-        // of the wave is idle (a refill fetches segments: its latency is
-        // shared by the lanes it serves) or the wave has nothing left to run
+        // refill idle lanes with the next tags of the range, once kRefillLanes
+        // lanes are idle (a refill fetches segments: its latency is shared by
+        // the lanes it serves) or the wave has nothing left to run
         const uint64_t idle = __ballot(!busy);
-        if (idle && cursor < b && (__popcll(idle) >= 16 || __ballot(busy) == 0ull)) {
+        if (idle && cursor < b && (__popcll(idle) >= kRefillLanes || __ballot(busy) == 0ull)) {
             const uint32_t ni = cursor + (uint32_t)__popcll(idle & below);
             cursor += (uint32_t)__popcll(idle);
             if (!busy && ni < b) {
