@@ -374,7 +374,7 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // their canonical positions: copied from the kept codes, or, for the few
 // segments with more pieces, from a second run of the bisection.
 constexpr int kBisectBlock = 64;
-constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (8 beat 4, 12, 16 and 32 on the map scene)
+constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (on the map scene 8 and 12 beat 4, 16 and 32)
 
 template <bool Write, bool Stats, int MinWaves>
 __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
