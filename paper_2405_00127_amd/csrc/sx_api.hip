@@ -22,6 +22,12 @@ struct sx_ctx {
     uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, status
 };
 
+// Per-tag terms of the single-pass output estimate (see soup_terms).
+struct SoupTerm {
+    float a = 0.0f, b = 1.0f, w = 0.0f;
+    uint32_t flags = 0;
+};
+
 struct sx_scene {
     sx_ctx* ctx = nullptr;
     uint32_t n_tags = 0, n_pts = 0, n_paths = 0, n_styles = 0, n_xforms = 0;
@@ -60,7 +66,7 @@ struct sx_scene {
     // single-pass variant: record counter and the per-tag terms of the
     // output estimate (host)
     unsigned long long* d_soup_n = nullptr;
-    std::vector<float> est;  // 4 per tag: a, b, w, flags (see soup_terms)
+    std::vector<SoupTerm> est;  // one per tag (see soup_terms)
 };
 
 struct sx_batch {
@@ -430,15 +436,15 @@ const char* sx_last_error(const sx_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 // 8 fill, 16 round join or cap.
 enum { kEstCurve = 1, kEstLine = 2, kEstMarker = 4, kEstFill = 8, kEstRound = 16 };
 static void soup_terms(const sx::HostEncoding& enc, const sx_style* styles, const sx_affine* xforms,
-                std::vector<float>& est) {
+                       std::vector<SoupTerm>& est) {
     const size_t n = enc.tags.size();
-    est.assign(4 * n, 0.0f);
+    est.assign(n, SoupTerm{});
     uint32_t off = 0;
     int sty = -1, xfi = -1;
     for (size_t i = 0; i < n; i++) {
         const uint32_t t = enc.tags[i];
-        if (t & 0x40u) sty++;
-        if (t & 0x20u) xfi++;
+        if (t & sx::kTagStyle) sty++;
+        if (t & sx::kTagXform) xfi++;
         const sx_style& st = styles[enc.style_stream[sty]];
         const sx_affine& X = xforms[enc.xform_stream[xfi]];
         const bool fill = (st.flags & SX_STYLE_FILL) != 0;
@@ -447,9 +453,9 @@ static void soup_terms(const sx::HostEncoding& enc, const sx_style* styles, cons
         uint32_t fl = fill ? kEstFill : 0u;
         if (!fill && (st.join == SX_JOIN_ROUND || st.start_cap == SX_CAP_ROUND || st.end_cap == SX_CAP_ROUND))
             fl |= kEstRound;
-        const uint32_t c = t & 3u;
+        const uint32_t c = t & sx::kTagCount;
         double a = 0.0, b = 1.0;
-        if (t & 0x04u) {
+        if (t & sx::kTagEnd) {
             fl |= kEstMarker;
         } else if (c == 1u) {
             fl |= kEstLine;
@@ -469,11 +475,8 @@ static void soup_terms(const sx::HostEncoding& enc, const sx_style* styles, cons
             a = std::sqrt(dd * M / 8.0);
             b = std::sqrt(1.0 + (ch > 0.0 ? w * dd * M / (ch * ch) : 0.0));
         }
-        est[4 * i] = (float)a;
-        est[4 * i + 1] = (float)b;
-        est[4 * i + 2] = (float)w;
-        est[4 * i + 3] = (float)fl;
-        off += c + ((t & 0x04u) ? 1u : 0u);
+        est[i] = SoupTerm{(float)a, (float)b, (float)w, fl};
+        off += c + ((t & sx::kTagEnd) ? 1u : 0u);
     }
 }
 
@@ -878,12 +881,12 @@ int sx_scene_estimate(const sx_scene* s, float tolerance, int output_mode, uint6
     if (!make_cfg(tolerance, output_mode, cfg)) return SX_EINVAL;
     const double tf = cfg.tau_flat, rtf = 1.0 / std::sqrt(tf);
     uint64_t total = 0;
-    for (size_t i = 0; i < s->est.size() / 4; i++) {
-        const double a = s->est[4 * i], b = s->est[4 * i + 1], w = s->est[4 * i + 2];
-        const uint32_t fl = (uint32_t)s->est[4 * i + 3];
+    for (const SoupTerm& e : s->est) {
+        const double a = e.a, b = e.b, w = e.w;
+        const uint32_t fl = e.flags;
         const bool fill = (fl & kEstFill) != 0;
         uint64_t tail = 0;
-        if (!fill) tail = (fl & kEstRound) ? (w > tf ? (uint64_t)std::ceil(M_PI / (2.0 * std::acos(1.0 - tf / w))) : 2u) + 4u
+        if (!fill) tail = (fl & kEstRound) ? (w > tf ? (uint64_t)std::ceil(sx::kHalfPi / std::acos(1.0 - tf / w)) : 2u) + 4u
                                            : 6u;
         uint64_t n = tail;
         if (fl & kEstLine) {
