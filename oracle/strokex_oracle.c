@@ -321,6 +321,8 @@ ox_enc *ox_encode(const uint8_t *verbs, const uint32_t *verb_off, const float *p
             pi += c;
             sub_nseg++;
         }
+        /* a path's verbs consume exactly the points it owns */
+        if (pi != np) { e->status = -1; return e; }
         if (fill && in_sub && sub_nseg > 0 && !closed) {
             if (enc_closing_line(e, sx, sy, &cx, &cy)) { e->status = -2; return e; }
             closed = 1;
