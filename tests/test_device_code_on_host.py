@@ -1,0 +1,89 @@
+"""The expansion's device code (sx_device.h) compiled for the host with hipcc
+and driven through the GPU pipeline's steps serially (tests/host/
+device_on_host.hip), against the FP64 oracle at the GPU parity bars: counts
+identical except at oracle decisions within the margin thresholds, endpoints
+within 1e-3 px, arc bulge within 1e-3 px, path ids equal, outlines closed
+per path.  It checks the kernels' arithmetic (decisions, counts, placement)
+in the CPU suite; the GPU's own code generation is covered by the -m gpu
+tests.  CPU only."""
+import ctypes as C
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle as O
+import parity as P
+from paper_2405_00127_amd import scenes as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2405_00127_amd", "csrc")
+HIPCC = "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else shutil.which("hipcc")
+
+LINE_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("path", "<u4")])
+ARC_DTYPE = np.dtype([("x0", "<f4"), ("y0", "<f4"), ("x1", "<f4"), ("y1", "<f4"), ("curv", "<f4"), ("path", "<u4")])
+
+
+class _Paths(C.Structure):
+    _fields_ = [("verbs", C.c_void_p), ("verb_off", C.c_void_p), ("pts", C.c_void_p), ("pt_off", C.c_void_p),
+                ("style_ix", C.c_void_p), ("xform_ix", C.c_void_p), ("n_paths", C.c_uint32)]
+
+
+@pytest.fixture(scope="module")
+def dev(tmp_path_factory):
+    if not HIPCC:
+        pytest.skip("hipcc not available")
+    out = str(tmp_path_factory.mktemp("devhost") / "libdevhost.so")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-O2", "-std=c++17", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-Wno-unused-command-line-argument",
+                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", out,
+                           os.path.join(os.path.dirname(__file__), "host", "device_on_host.hip"),
+                           os.path.join(CSRC, "sx_encode.cpp")],
+                          stderr=subprocess.DEVNULL)
+    L = C.CDLL(out)
+    L.dh_expand.argtypes = [C.POINTER(_Paths), C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint32, C.c_float, C.c_int,
+                            C.c_void_p, C.c_uint32, C.c_void_p, C.c_uint64, C.POINTER(C.c_uint32),
+                            C.POINTER(C.c_uint64), C.c_int]
+    return L
+
+
+def _run(L, sc):
+    mode = sc.output_mode
+    keep = [np.ascontiguousarray(sc.verbs, np.uint8), np.ascontiguousarray(sc.verb_off, np.uint32),
+            np.ascontiguousarray(sc.pts, np.float32), np.ascontiguousarray(sc.pt_off, np.uint32),
+            np.ascontiguousarray(sc.style_ix, np.uint32), np.ascontiguousarray(sc.xform_ix, np.uint32)]
+    p = _Paths(*[k.ctypes.data for k in keep], sc.n_paths)
+    st = np.ascontiguousarray(sc.styles)
+    xf = np.ascontiguousarray(sc.xforms, np.float32)
+    cap = len(sc.verbs) + 4 * sc.n_paths + 16
+    counts = np.zeros(cap, np.uint32)
+    nt, nr = C.c_uint32(), C.c_uint64()
+    args = (C.byref(p), st.ctypes.data, len(st), xf.ctypes.data, len(xf), sc.tolerance, mode, counts.ctypes.data,
+            cap)
+    assert L.dh_expand(*args, None, 0, C.byref(nt), C.byref(nr), 0) == 0
+    w = 6 if mode else 5
+    recs = np.zeros(nr.value * w + 1, np.float32)
+    assert L.dh_expand(*args, recs.ctypes.data, nr.value, C.byref(nt), C.byref(nr), 0) == 0
+    return counts[: nt.value].copy(), recs[: nr.value * w].view(ARC_DTYPE if mode else LINE_DTYPE).copy()
+
+
+@pytest.mark.parametrize("name", ["c1_lines", "c1_arcs", "c2_lines", "c3_arcs", "c1_fills_shear"])
+def test_device_code_on_host_matches_the_oracle(dev, name):
+    sc = {"c1_lines": lambda: S.scene_c1(1),
+          "c1_arcs": lambda: S.scene_c1(1, output_mode=S.OUT_ARCS),
+          "c2_lines": lambda: S.scene_c2(2, n_segments=10000, n_paths=100),
+          "c3_arcs": lambda: S.scene_c3(3, n_cubics=300),
+          "c1_fills_shear": lambda: S.with_fills(S.scene_c1(1), 0.5, seed=3,
+                                                 xform=[1.0, 0.2, 0.5, 0.9, 10.0, -5.0])}[name]()
+    counts, recs = _run(dev, sc)
+    ref = O.expand(sc)
+    assert ref.status == 0
+    rep = P.compare(counts, recs, ref, sc.output_mode)
+    assert rep.n_unexplained == 0, rep
+    assert rep.worst_endpoint <= P.ENDPOINT_TOL, rep
+    assert rep.worst_sweep <= P.SWEEP_TOL, rep
+    assert rep.bad_path_ids == 0
+    assert P.closed_per_path(recs) == 0
