@@ -375,3 +375,18 @@ def test_invalid_inputs_are_rejected(ctx, bad):
     scene = ctx.encode(bad_tol)
     with pytest.raises(B.StrokexError):
         ctx.expand(scene, tolerance=0.0)
+
+
+@pytest.mark.parametrize("name,factor", [("c1", 1.5), ("c2", 1.1)])
+def test_host_estimate_of_records(ctx, name, factor):
+    """sx_scene_estimate (host only: Wang's formula per curve, inflated per
+    stroke side, plus join / cap bounds) covers these scenes' exact need with
+    room to spare; on cusp-heavy scenes it is a heuristic and may fall short."""
+    sc = {"c1": lambda: S.scene_c1(1), "c2": lambda: S.scene_c2(2, n_segments=40000, n_paths=400)}[name]()
+    scene = ctx.encode(sc)
+    need = int(O.expand(sc, emit=False).counts.sum())
+    est = ctx.estimate(scene, sc.tolerance, sc.output_mode)
+    _say("estimate", name, est, "need", need)
+    assert est >= factor * need
+    assert est == ctx.estimate(scene, sc.tolerance, sc.output_mode)  # deterministic
+    assert ctx.estimate(scene, 2 * sc.tolerance, sc.output_mode) < est  # coarser tolerance, fewer records
