@@ -19,6 +19,8 @@ SRC = os.path.join(HERE, "strokex_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 FIT_OFFSET, FIT_PAPER = 0, 1
+# fit-mode bit: Algorithm 2 without the hodograph test of reading G29
+FIT_NO_HODO = 2
 KIND_OFFSET, KIND_EVOLUTE, KIND_CONNECT, KIND_JOIN_OUTER, KIND_JOIN_INNER, KIND_CAP = range(6)
 
 OUT_DTYPE = np.dtype(
@@ -91,6 +93,10 @@ def lib():
                 f.restype = d
                 f.argtypes = [d] * nargs
             L.ox_es_integral.argtypes = [d, d, d, C.POINTER(d), C.POINTER(d)]
+            L.ox_line_integral_es.restype = d
+            L.ox_line_integral_es.argtypes = [d] * 6
+            L.ox_es_side.restype = vp
+            L.ox_es_side.argtypes = [d, d, d, d, d, C.c_int]
             L.ox_gl_nodes.argtypes = [vp, vp]
             L.ox_xform_ok.restype = C.c_int
             L.ox_xform_ok.argtypes = [vp]
@@ -151,6 +157,25 @@ def es_integral(k0, k1, u):
     re, im = C.c_double(), C.c_double()
     lib().ox_es_integral(float(k0), float(k1), float(u), C.byref(re), C.byref(im))
     return complex(re.value, im.value)
+
+
+def line_integral_es(k0, k1, L, h, ua, ub):
+    """Section 4.2 subdivision integral of side h over [ua, ub] of an Euler
+    spiral of arc length L (before the sqrt(1/(8 tau_flat)) factor)."""
+    return lib().ox_line_integral_es(float(k0), float(k1), float(L), float(h), float(ua), float(ub))
+
+
+def es_side(k0, k1, L, h, tol, mode):
+    """Records (OUT_DTYPE) of side h of an Euler spiral placed at the origin
+    with base angle 0: p(u) = L Z(u), tangent angle phi(u)."""
+    L_ = lib()
+    hv = C.c_void_p(L_.ox_es_side(float(k0), float(k1), float(L), float(h), float(tol), int(mode)))
+    if not hv.value:
+        raise MemoryError("oracle es_side failed")
+    try:
+        return _copy(L_.ox_res_out(hv), OUT_DTYPE, L_.ox_res_nout(hv))
+    finally:
+        L_.ox_res_free(hv)
 
 
 def gl_nodes():

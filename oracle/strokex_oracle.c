@@ -61,6 +61,9 @@ enum { OX_CAP_BUTT = 0, OX_CAP_SQUARE = 1, OX_CAP_ROUND = 2 };
 #define OX_STYLE_FILL 0x01u
 enum { OX_OUT_LINES = 0, OX_OUT_ARCS = 1 };
 enum { OX_FIT_OFFSET = 0, OX_FIT_PAPER = 1 };
+/* fit-mode bit: leave out the hodograph test of reading G29 (Algorithm 2 as
+ * printed; kept only so the tests can show what the reading prevents) */
+#define OX_FIT_NO_HODO 2
 
 /* kinds recorded per output (for the tests' geometric checks only) */
 enum { OX_K_OFFSET = 0, OX_K_EVOLUTE = 1, OX_K_CONNECT = 2, OX_K_JOIN_OUTER = 3,
@@ -903,6 +906,53 @@ static void emit_side(ox_sink *k, const ox_cfg *cfg, const ox_es *es, double h, 
     }
 }
 
+/* ---- test exports: one Euler spiral on its own ------------------------- */
+
+/* An ES of arc length L with curvature parameters k0, k1 placed at the
+ * origin with tangent angle phi(u) (base angle 0): p(u) = L Z(u). */
+static ox_es es_at_origin(double k0, double k1, double L) {
+    ox_es es;
+    es.pivot = 0;
+    es.k0 = k0; es.k1 = k1; es.L = L;
+    es.rot = v2m(L, 0.0);
+    es.base = 0.0;
+    es.p0 = v2m(0.0, 0.0);
+    es.p1 = cmul(es.rot, es_integral(k0, k1, 1.0));
+    double a0 = es_phi(k0, k1, 0.0), a1 = es_phi(k0, k1, 1.0);
+    es.n0 = v2m(sin(a0), -cos(a0));
+    es.n1 = v2m(sin(a1), -cos(a1));
+    return es;
+}
+
+/* Section 4.2 subdivision integral of side h over [ua, ub] of that ES, as the
+ * line count uses it (before the sqrt(1 / (8 tau_flat)) factor). */
+double ox_line_integral_es(double k0, double k1, double L, double h, double ua, double ub) {
+    ox_es es = es_at_origin(k0, k1, L);
+    return line_integral(&es, h, ua, ub);
+}
+
+/* The records of side h of that ES (Sections 4-6: the range split at the
+ * parallel-curve cusp, offsets, evolutes and connecting lines) at tolerance
+ * tol in output mode `mode`; tag and path 0. */
+ox_res *ox_es_side(double k0, double k1, double L, double h, double tol, int mode) {
+    ox_res *r = (ox_res *)calloc(1, sizeof(ox_res));
+    if (!r) return NULL;
+    ox_cfg cfg;
+    cfg.tau = tol;
+    cfg.tau_fit = OX_FIT_FRAC * tol;
+    cfg.tau_flat = OX_FLAT_FRAC * tol;
+    cfg.mode = mode;
+    cfg.fit_mode = OX_FIT_OFFSET;
+    ox_es es = es_at_origin(k0, k1, L);
+    ox_sink sk;
+    sk.r = r; sk.path = 0; sk.tag = 0; sk.emit = 1; sk.count = 0; sk.mode = mode;
+    ox_margin m;
+    m.fit = m.count = m.rho = m.q = m.len = m.join = INFINITY;
+    m.n_pieces = 0; m.max_depth_hits = 0;
+    emit_side(&sk, &cfg, &es, h, &m);
+    return r;
+}
+
 /* ---- joins and caps (Algorithm 1, SVG styles) --------------------------- */
 
 static double round_step(double w, double tau_flat) {
@@ -1041,7 +1091,7 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
         double th1 = atan2(vcross(chord, next_q.dir), vdot(chord, next_q.dir));
         double d0 = last_q.mag * dt / cl, d1 = next_q.mag * dt / cl;
         double est = ox_fit_estimate(th0, th1, d0, d1);
-                double err = (cfg->fit_mode == OX_FIT_PAPER) ? est * cl : est * (cl + OX_FIT_K * hw) * OX_FIT_S;
+                double err = ((cfg->fit_mode & OX_FIT_PAPER) != 0) ? est * cl : est * (cl + OX_FIT_K * hw) * OX_FIT_S;
         /* reading G11: only a chord of exactly zero leaves the end angles
          * undefined; such a piece is subdivided */
         int len_ok = cl > 0.0;
@@ -1058,7 +1108,7 @@ static void process_segment(ox_sink *k, const ox_cfg *cfg, const ox_seg *s, ox_m
             v2 b = vsub(vsub(chord, a), c);
             /* a middle vector that is zero up to rounding leaves only the
              * turn from a to c, which is below pi: no test */
-            if (ma > 0.0 && mc > 0.0 && vlen(b) > 1e-9 * (ma + mc)) {
+            if (!(cfg->fit_mode & OX_FIT_NO_HODO) && ma > 0.0 && mc > 0.0 && vlen(b) > 1e-9 * (ma + mc)) {
                 double hv = vdot(a, b) * mc + vdot(b, c) * ma;
                 double scale = vlen(b) * ma * mc;
                 if (scale > 0.0) margin_min(&m->len, fabs(hv) / scale);

@@ -139,7 +139,9 @@ def sample_outputs(x0, y0, x1, y1, curv=None, spacing=0.05):
         b = np.array([x1[j], y1[j]], np.float64)
         k = 0.0 if curv is None else float(curv[j])
         c = np.hypot(*(b - a))
-        if k == 0.0 or c == 0.0:
+        if k == 0.0 or c == 0.0 or abs(k) * c * c < 1e-12:
+            # (a bulge c^2 |k| / 8 far below any tolerance: drawn as its chord,
+            # which keeps the circle's centre from cancelling catastrophically)
             q = line_pts(a, b, spacing)
         else:
             # arc with chord a->b and signed curvature k (ccw positive)
