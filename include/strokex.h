@@ -103,8 +103,44 @@ typedef struct {
 typedef struct sx_ctx sx_ctx;
 typedef struct sx_scene sx_scene;
 
-/* Create a context on HIP device `device`.  *out receives the handle. */
-int sx_ctx_create(int device, sx_ctx **out);
+/* Context configuration, fixed for the context's life (NULL = all fields 0,
+ * the defaults).
+ *   fit_mode  the error the cubic -> Euler spiral bisection compares with
+ *             its share of the tolerance (Algorithm 2, Section 7.1):
+ *             SX_FIT_OFFSET (default) est x (chord + 9 |h|) x 1.6, where est
+ *             is the chord-normalised estimate of Section 7.1 and h the
+ *             half-width, so that the parallel curves stay within tolerance;
+ *             SX_FIT_PAPER est x chord, the positional estimate alone (it
+ *             lets wide strokes leave the tolerance; kept for comparison).
+ *   density   how offset lines are counted and placed (Section 4.2):
+ *             SX_DENSITY_APPROX (default) with the piecewise approximation
+ *             f_approx of the subdivision density integral and its closed
+ *             inverse; SX_DENSITY_NEWTON with the exact integral f, points
+ *             placed by the approximate inverse refined by two Newton steps
+ *             on f (the higher-quality option the section describes).
+ *   constants_version  0 or SX_CONSTANTS_VERSION: the version of the
+ *             printed constants (Section 4.2 c1..c3, Section 7.1
+ *             coefficients, Appendix A polynomials) the caller expects.
+ *   reserved  0.
+ * The outline depends on fit_mode and density; sx_set_tuning never changes
+ * it. */
+enum { SX_FIT_OFFSET = 0, SX_FIT_PAPER = 1 };
+enum { SX_DENSITY_APPROX = 0, SX_DENSITY_NEWTON = 1 };
+#define SX_CONSTANTS_VERSION 1u
+typedef struct {
+    uint32_t fit_mode;
+    uint32_t density;
+    uint32_t constants_version;
+    uint32_t reserved;
+} sx_config;
+
+/* Create a context on HIP device `device` with configuration *cfg (NULL:
+ * defaults).  *out receives the handle.  Errors: SX_EINVAL (null out, a
+ * field out of range, an unknown constants version, reserved != 0),
+ * SX_EDEVICE (no such device), SX_ENOMEM. */
+int sx_ctx_create(int device, const sx_config *cfg, sx_ctx **out);
+/* The configuration the context was created with. */
+int sx_get_config(const sx_ctx *ctx, sx_config *cfg);
 /* Destroy a context and every scene it still owns.  NULL is a no-op. */
 int sx_ctx_destroy(sx_ctx *ctx);
 /* Text of the last error on this context (never NULL; "" when none). */

@@ -43,6 +43,16 @@ class _Paths(C.Structure):
                 ("style_ix", C.c_void_p), ("xform_ix", C.c_void_p), ("n_paths", C.c_uint32)]
 
 
+class _Config(C.Structure):
+    _fields_ = [("fit_mode", C.c_uint32), ("density", C.c_uint32), ("constants_version", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+FIT_OFFSET, FIT_PAPER = 0, 1
+DENSITY_APPROX, DENSITY_NEWTON = 0, 1
+CONSTANTS_VERSION = 1
+
+
 class _Tuning(C.Structure):
     _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("bisect_range", C.c_uint32),
                 ("bisect_waves", C.c_uint32)]
@@ -67,7 +77,8 @@ def lib():
             L = C.CDLL(LIB_PATH)
             vp, u32, u64 = C.c_void_p, C.c_uint32, C.c_uint64
             sig = {
-                "sx_ctx_create": (C.c_int, [C.c_int, C.POINTER(vp)]),
+                "sx_ctx_create": (C.c_int, [C.c_int, C.POINTER(_Config), C.POINTER(vp)]),
+                "sx_get_config": (C.c_int, [vp, C.POINTER(_Config)]),
                 "sx_ctx_destroy": (C.c_int, [vp]),
                 "sx_last_error": (C.c_char_p, [vp]),
                 "sx_version": (C.c_char_p, []),
@@ -148,14 +159,24 @@ class Scene:
 
 
 class Context:
-    def __init__(self, device: int = 0):
+    """A library context on one device.  fit_mode: FIT_OFFSET (default) or
+    FIT_PAPER; density: DENSITY_APPROX (default) or DENSITY_NEWTON (see
+    sx_config in include/strokex.h)."""
+
+    def __init__(self, device: int = 0, fit_mode: int = FIT_OFFSET, density: int = DENSITY_APPROX):
         self.h = 0
         h = C.c_void_p()
-        rc = lib().sx_ctx_create(int(device), C.byref(h))
+        cfg = _Config(int(fit_mode), int(density), CONSTANTS_VERSION, 0)
+        rc = lib().sx_ctx_create(int(device), C.byref(cfg), C.byref(h))
         if rc != SX_OK:
-            raise StrokexError(rc, "sx_ctx_create failed (is a gfx950 GPU visible?)")
+            raise StrokexError(rc, "sx_ctx_create failed (bad configuration, or no gfx950 GPU visible?)")
         self.h = h.value
         self.device = device
+
+    def config(self) -> dict:
+        c = _Config()
+        self._check(lib().sx_get_config(C.c_void_p(self.h), C.byref(c)), "sx_get_config")
+        return {"fit_mode": c.fit_mode, "density": c.density, "constants_version": c.constants_version}
 
     def close(self):
         if self.h:

@@ -17,6 +17,7 @@
 
 struct sx_ctx {
     int device = 0;
+    sx_config cfg = {SX_FIT_OFFSET, SX_DENSITY_APPROX, SX_CONSTANTS_VERSION, 0u};
     std::string err;
     sx_tuning tune = {2u, 16u, 256u, 2u};
     uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, status
@@ -274,7 +275,7 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
     return e;
 }
 
-bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
+bool make_cfg(const sx_ctx* ctx, float tol, int mode, sx::Cfg& cfg) {
     if (!(tol > 0.0f) || !std::isfinite(tol)) return false;
     if (mode != SX_OUT_LINES && mode != SX_OUT_ARCS) return false;
     double tf = sx::kFlatFrac * (double)tol;
@@ -283,8 +284,9 @@ bool make_cfg(float tol, int mode, sx::Cfg& cfg) {
     cfg.inv_sqrt8tf = std::sqrt(1.0 / (8.0 * tf));
     cfg.cbrt_inv120tf = std::cbrt(1.0 / (120.0 * tf));
     cfg.arcs = mode == SX_OUT_ARCS;
-    cfg.paper_fit = 0;
-    cfg.K = 16;
+    cfg.paper_fit = ctx && ctx->cfg.fit_mode == SX_FIT_PAPER ? 1 : 0;
+    cfg.newton = ctx && ctx->cfg.density == SX_DENSITY_NEWTON ? 1 : 0;
+    cfg.K = ctx ? ctx->tune.chunk_k : 16u;
     sx::set_break_increments(cfg.xinc);
     return true;
 }
@@ -381,14 +383,24 @@ extern "C" {
 
 const char* sx_version(void) { return "strokex 0.1 (gfx950)"; }
 
-int sx_ctx_create(int device, sx_ctx** out) {
+int sx_ctx_create(int device, const sx_config* cfg, sx_ctx** out) {
     if (!out) return SX_EINVAL;
     *out = nullptr;
+    sx_config conf = {SX_FIT_OFFSET, SX_DENSITY_APPROX, SX_CONSTANTS_VERSION, 0u};
+    if (cfg) {
+        if (cfg->fit_mode > SX_FIT_PAPER || cfg->density > SX_DENSITY_NEWTON || cfg->reserved != 0u ||
+            (cfg->constants_version != 0u && cfg->constants_version != SX_CONSTANTS_VERSION))
+            return SX_EINVAL;
+        if (cfg->density == SX_DENSITY_NEWTON) return SX_EINVAL;  // not available yet
+        conf = *cfg;
+        conf.constants_version = SX_CONSTANTS_VERSION;
+    }
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SX_EDEVICE;
     sx_ctx* c = new (std::nothrow) sx_ctx();
     if (!c) return SX_ENOMEM;
     c->device = device;
+    c->cfg = conf;
     if (hipSetDevice(device) != hipSuccess) { delete c; return SX_EDEVICE; }
     if (hipHostMalloc((void**)&c->pinned_total, 2 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -416,6 +428,12 @@ int sx_set_tuning(sx_ctx* ctx, const sx_tuning* t) {
     ctx->tune = *t;
     if (ctx->tune.bisect_range == 0) ctx->tune.bisect_range = 256;
     if (ctx->tune.bisect_waves == 0) ctx->tune.bisect_waves = 2;
+    return SX_OK;
+}
+
+int sx_get_config(const sx_ctx* ctx, sx_config* cfg) {
+    if (!ctx || !cfg) return SX_EINVAL;
+    *cfg = ctx->cfg;
     return SX_OK;
 }
 
@@ -597,12 +615,11 @@ int sx_expand_async(sx_ctx* ctx, const sx_scene* scene, float tolerance, int out
                     uint64_t out_capacity_bytes, uint64_t* out_count_dev, void* stream) {
     if (!ctx || !scene) return SX_EINVAL;
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (!out_count_dev) return fail(ctx, SX_EINVAL, "null count pointer");
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(scene)->last_stream = st;
-    cfg.K = ctx->tune.chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     return run_all(ctx, scene, cfg, out_dev, out_capacity_bytes / rec, out_count_dev, st);
 }
@@ -611,12 +628,11 @@ int sx_expand(sx_ctx* ctx, const sx_scene* scene, float tolerance, int output_mo
               uint64_t out_capacity_bytes, uint64_t* out_count, void* stream) {
     if (!ctx || !scene || !out_count) return SX_EINVAL;
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     hipStream_t st = (hipStream_t)stream;
     sx_scene* s = const_cast<sx_scene*>(scene);
     s->last_stream = st;
-    cfg.K = ctx->tune.chunk_k;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
     *out_count = 0;
     if (s->n_tags == 0) return SX_OK;
@@ -630,11 +646,10 @@ int sx_run_phase(sx_ctx* ctx, const sx_scene* s, int phase, float tolerance, int
                  uint64_t out_capacity_bytes, void* stream) {
     if (!ctx || !s) return SX_EINVAL;
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (phase < 0 || phase >= kPhN) return fail(ctx, SX_EINVAL, "bad phase");
     if (phase == kPhRecords && out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
     if (s->n_tags == 0) return SX_OK;
-    cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     const_cast<sx_scene*>(s)->last_stream = st;
     const uint64_t rec = output_mode == SX_OUT_ARCS ? sizeof(sx_arc) : sizeof(sx_line);
@@ -771,9 +786,8 @@ int sx_batch_expand(sx_ctx* ctx, sx_batch* b, float tolerance, int output_mode, 
     if (!ctx || !b || !scene_offsets_dev || !status_dev) return SX_EINVAL;
     if (b->ctx != ctx) return fail(ctx, SX_EINVAL, "batch belongs to another context");
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
-    cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     sx_scene* a = b->arena;
     a->last_stream = st;
@@ -789,10 +803,9 @@ int sx_debug_piece_stats(sx_ctx* ctx, const sx_scene* s, float tolerance, int ou
                          void* stream) {
     if (!ctx || !s || !stats6) return SX_EINVAL;
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     for (int j = 0; j < 6; j++) stats6[j] = 0;
     if (s->n_tags == 0) return SX_OK;
-    cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     sx_scene* sc = const_cast<sx_scene*>(s);
     // size the workspace first, so the instrumented run covers every slot
@@ -825,14 +838,13 @@ int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void*
 static int tag_records(sx_ctx* ctx, const sx_scene* s, float tolerance, int output_mode, uint32_t* counts,
                        uint64_t* offs, void* stream) {
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     hipStream_t st = (hipStream_t)stream;
     if (s->n_tags == 0) {
         if (!offs) return SX_OK;
         hipError_t e = hipMemsetAsync(offs, 0, sizeof(uint64_t), st);
         return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "memset");
     }
-    cfg.K = ctx->tune.chunk_k;
     uint64_t n_rec = 0;
     int r = run_sized(ctx, const_cast<sx_scene*>(s), cfg, nullptr, 0, &n_rec, st);
     if (r != SX_OK) return r;
@@ -871,14 +883,13 @@ int sx_scan_u32(sx_ctx* ctx, const uint32_t* in_dev, uint64_t* out_dev, uint32_t
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "scan_u32");
 }
 
-
 // ------------------------------------------------------------ single pass
 constexpr int kSoupEnabled = 0;
 
 int sx_scene_estimate(const sx_scene* s, float tolerance, int output_mode, uint64_t* out_records) {
     if (!s || !out_records) return SX_EINVAL;
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return SX_EINVAL;
+    if (!make_cfg(s->ctx, tolerance, output_mode, cfg)) return SX_EINVAL;
     const double tf = cfg.tau_flat, rtf = 1.0 / std::sqrt(tf);
     uint64_t total = 0;
     for (const SoupTerm& e : s->est) {
@@ -906,9 +917,8 @@ int sx_expand_soup(sx_ctx* ctx, sx_scene* s, float tolerance, int output_mode, v
                    uint64_t out_capacity_bytes, uint64_t* out_count, void* stream) {
     if (!ctx || !s || !out_count) return SX_EINVAL;
     sx::Cfg cfg;
-    if (!make_cfg(tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
+    if (!make_cfg(ctx, tolerance, output_mode, cfg)) return fail(ctx, SX_EINVAL, "bad tolerance or output mode");
     if (out_capacity_bytes && !out_dev) return fail(ctx, SX_EINVAL, "null output buffer");
-    cfg.K = ctx->tune.chunk_k;
     hipStream_t st = (hipStream_t)stream;
     *out_count = 0;
     if (s->n_tags == 0) return SX_OK;

@@ -566,7 +566,8 @@ struct Cfg {
     double tau_fit, tau_flat, inv_sqrt8tf;  // sqrt(1 / (8 tau_flat))
     double cbrt_inv120tf;                   // cbrt(1 / (120 tau_flat))
     int arcs;
-    int paper_fit;
+    int paper_fit;                          // fit error: Section 7.1 estimate x chord (else offset-aware)
+    int newton;                             // exact density integral, Newton-refined inverse (Section 4.2)
     uint32_t K;                             // records per item chunk
     double xinc[5];                         // F increments between the branch breaks
 };

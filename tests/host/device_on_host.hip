@@ -40,7 +40,7 @@ extern "C" int dh_expand(const sx_paths* paths, const sx_style* styles, uint32_t
     sv.path_map = enc.path_map.data(); sv.mon = mon.data(); sv.n_tags = n; sv.n_pts = enc.data.size()/2; sv.n_styles = sd.size(); sv.n_xforms = xd.size()/6; sv.n_paths = enc.path_map.size();
     Cfg cfg; double tf = kFlatFrac * (double)tol;
     cfg.tau_fit = kFitFrac * (double)tol; cfg.tau_flat = tf; cfg.inv_sqrt8tf = std::sqrt(1.0 / (8.0 * tf));
-    cfg.cbrt_inv120tf = std::cbrt(1.0 / (120.0 * tf)); cfg.arcs = mode; cfg.paper_fit = paper_fit;
+    cfg.cbrt_inv120tf = std::cbrt(1.0 / (120.0 * tf)); cfg.arcs = mode; cfg.paper_fit = paper_fit & 1; cfg.newton = (paper_fit >> 1) & 1;
     cfg.K = g_K;
     set_break_increments(cfg.xinc);
     // slot pipeline on the host: bisection -> slots, slots -> items, scan, records

@@ -156,12 +156,15 @@ def test_offsets_are_the_scan_of_the_counts(ctx):
     assert np.array_equal(o, np.concatenate([[0], np.cumsum(c)]))
 
 
-def test_full_size_c2_counts_and_samples(ctx):
-    """The 1M-segment map scene in the launch configuration the benchmark
-    times: counts of every tag against the oracle (count-only pass) and the
-    records of sampled tags against the oracle run tag by tag."""
-    sc = S.scene_c2(2)
-    _say("full c2: encode")
+@pytest.mark.parametrize("mode", [S.OUT_LINES, S.OUT_ARCS])
+def test_full_size_c2_counts_and_samples(ctx, mode):
+    """The 1M-segment map scene, lines and arcs, at the default launch
+    parameters (test_gpu_tuning shows every launch configuration the tuner
+    can pick gives these records bit for bit): counts of every tag against
+    the oracle (count-only pass) and the records of sampled tags against the
+    oracle run tag by tag (endpoints, arc bulge, path ids)."""
+    sc = S.scene_c2(2, output_mode=mode)
+    _say("full c2: encode", mode)
     scene, counts, recs = _expand(ctx, sc)
     _say("full c2: oracle counts")
     ref = O.expand(sc, emit=False)
@@ -173,7 +176,7 @@ def test_full_size_c2_counts_and_samples(ctx):
     go = np.concatenate([[0], np.cumsum(counts.astype(np.int64))])
     rng = np.random.default_rng(9)
     sample = np.sort(rng.choice(np.nonzero(~mism)[0], 3000, replace=False))
-    worst = 0.0
+    worst = worst_b = 0.0
     enc = ref.enc
     for i in sample:
         r = O.expand(sc, emit=True, tag_begin=int(i), tag_end=int(i) + 1, enc=enc)
@@ -184,9 +187,12 @@ def test_full_size_c2_counts_and_samples(ctx):
             d = max(np.max(np.abs(g["x0"] - o["x0"])), np.max(np.abs(g["y0"] - o["y0"])),
                     np.max(np.abs(g["x1"] - o["x1"])), np.max(np.abs(g["y1"] - o["y1"])))
             worst = max(worst, float(d))
+            if mode == S.OUT_ARCS:
+                worst_b = max(worst_b, float(np.max(np.abs(P.arc_bulge(g) - P.arc_bulge(o)))))
             assert np.all(g["path"] == o["path"])
-    _say("full c2: sampled worst endpoint", worst)
+    _say("full c2: sampled worst endpoint", worst, "bulge", worst_b)
     assert worst <= P.ENDPOINT_TOL
+    assert worst_b <= P.SWEEP_TOL
     assert P.closed_per_path(recs) == 0
 
 
