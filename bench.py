@@ -32,31 +32,30 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3
-PEAK_FP64_TFLOPS = 78.6
+# vector ALU, unpacked (the library is built without packed FP32): 256 CUs x
+# 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, the same for FP32 and FP64
+PEAK_VALU_TFLOPS = 78.6
+# VALU issue: one wave instruction per SIMD per clock, 256 CUs x 4 SIMDs x 2.4 GHz
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9
 
-# Algorithmic FP64 work per unit, counted from the definitions
-# (transcendentals at the FMA count of their polynomial evaluation: sin/cos
-# 25, sincos 40, atan2 40, acos 40, cbrt 30, sqrt 10, divide 10):
-#   fit trial (Algorithm 2): sub-cubic end point, tangent and chord 70, two
-#     end angles 92, arms 24, the Section 7.1 estimate 180, hodograph 91 = 460
-#   line step: chord length and acceptance                               = 15
-#   accepted cubic piece: the trial again 460, end normals 66, Appendix A
-#     polynomials 50, Z(1) by 8-node quadrature (paired nodes) 226,
-#     rotation and base angle 66, L 10                                  = 880
-#   line piece: normal 33, length 13, angle 40                           = 90
-#   parallel-curve range: curvatures, density split and its F increment
-#     (Section 4.2 branches) or the arc count (Section 5), count           = 130
-#   evolute bundle: Section 6 count and exact end points                  = 90
-#   join or cap: tangents, normals, offsets, round-join angles            = 150
-FLOPS = {"trial": 460.0, "line_step": 15.0, "piece": 880.0, "line": 90.0, "range": 130.0, "evolute": 90.0,
-         "join": 150.0}
-# Algorithmic FP32 work of the record kernel per output record (one new
-# outline point per record): spiral position by 4-node quadrature 118,
-# normal 24, offset 4, point placement (inverse of the density integral) 54
-# for lines; arcs replace placement by the sweep and curvature 32.
-FLOPS_PER_RECORD = {0: 200.0, 1: 178.0}
+# Algorithmic work per unit, in flop equivalents: an FMA counts 2, a
+# transcendental (sin, cos, atan2, sqrt, cbrt, asin, pow, a division) 1.
+#   fit trial (Algorithm 2, Section 7.1): 60 FMA + 7 transcendentals        = 127
+#   output point (record kernel, one new outline point per record): inverse
+#     of the density integral, map to u, Euler spiral position by a 4-node
+#     quadrature, tangent, offset: 100 FMA + 10 transcendentals             = 210
+#   accepted curve piece (piece kernel): its trial's chord and end angles
+#     127, Appendix A polynomials 20 FMA (40), Z(1) by 4 nodes (4 sincos +
+#     16 FMA: 40), end normals 10, L = chord / c 1                          = 218
+#   line piece: chord length and normal, 8 FMA + 2 transcendentals           = 18
+#   parallel-curve range (count of Section 4.2 or 5): 12 FMA + 4 trans.      = 28
+#   evolute bundle (count of Section 6): 4 FMA + 4 transcendentals           = 12
+#   join or cap (Algorithm 1): unit tangents, cross and dot, offsets, round
+#     count: 10 FMA + 7 transcendentals                                     = 27
+WORK = {"trial": 127.0, "point": 210.0, "piece": 218.0, "line": 18.0, "range": 28.0, "evolute": 12.0,
+        "join": 27.0}
 RECORD_BYTES = {0: 20, 1: 24}
+ALU_PHASES = ("bisect_count", "pieces", "tails", "records")
 
 
 def log(*a):
@@ -73,75 +72,116 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(sc, mode, budget_s=12.0):
-    """The FP64 oracle (single thread, as it stands) on a bounded prefix of the
-    same scene: whole tag ranges, grown until ~budget_s of CPU time."""
+def _oracle_run(sc, mode, enc, a, b):
+    """The oracle on tags [a, b): (segments, records)."""
     import numpy as np
 
     import oracle as O
 
+    status, n = O.expand_run(sc, mode=mode, tag_begin=a, tag_end=b, enc=enc)
+    assert status == 0
+    return int(np.count_nonzero((enc.tags[a:b] & 4) == 0)), n
+
+
+def cpu_baseline(sc, mode, budget_s=10.0):
+    """The FP64 oracle as it stands on a bounded prefix of the same scene:
+    once on one thread, then on every host core (one thread per core over
+    consecutive tag ranges, the oracle's C code releasing the interpreter
+    lock; the ranges' records concatenate in canonical order).  Each run
+    takes whole chunks of tags until about budget_s of wall time."""
+    import concurrent.futures as F
+
+    import oracle as O
+
     enc = O.encode(sc)
+    O.es_integral(0.0, 0.0, 0.5)  # quadrature nodes initialised before threads start
     n_tags = len(enc.tags)
-    t0 = time.process_time()
-    w0 = time.time()
-    done_tags = 0
-    segs = 0
-    recs = 0
     step = 20000
-    while done_tags < n_tags and time.process_time() - t0 < budget_s:
-        end = min(n_tags, done_tags + step)
-        r = O.expand(sc, mode=mode, tag_begin=done_tags, tag_end=end, enc=enc)
-        recs += len(r.out)
-        segs += int(np.count_nonzero((enc.tags[done_tags:end] & 4) == 0))
-        done_tags = end
-    cpu = time.process_time() - t0
-    wall = time.time() - w0
+
+    def single():
+        w0, c0 = time.time(), time.process_time()
+        done = segs = recs = 0
+        while done < n_tags and time.time() - w0 < budget_s:
+            end = min(n_tags, done + step)
+            s_, r_ = _oracle_run(sc, mode, enc, done, end)
+            segs += s_
+            recs += r_
+            done = end
+        return done, segs, recs, time.time() - w0, time.process_time() - c0
+
+    def multi(threads):
+        w0, c0 = time.time(), time.process_time()
+        done = segs = recs = 0
+        with F.ThreadPoolExecutor(threads) as ex:
+            while done < n_tags and time.time() - w0 < budget_s:
+                chunks = [(a, min(n_tags, a + step)) for a in range(done, min(n_tags, done + threads * step), step)]
+                for s_, r_ in ex.map(lambda ab: _oracle_run(sc, mode, enc, *ab), chunks):
+                    segs += s_
+                    recs += r_
+                done = chunks[-1][1]
+        return done, segs, recs, time.time() - w0, time.process_time() - c0
+
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    d1, s1, r1, w1, c1 = single()
+    dn, sn, rn, wn, cn = multi(cores)
     return {
-        "value": segs / wall,
+        "value": sn / wn,
         "unit": "input segs/s",
-        "cores": 1,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"first {done_tags} of {n_tags} tags ({segs} segments, {recs} records) of the same scene, "
-                  f"{wall:.1f} s wall / {cpu:.1f} s CPU, FP64, single thread",
-        "records_per_s": recs / wall,
+        "sample": f"first {dn} of {n_tags} tags ({sn} segments, {rn} records) of the same scene, "
+                  f"{wn:.1f} s wall / {cn:.1f} s CPU on {cores} threads (one per core, consecutive tag "
+                  f"ranges of {step}), FP64",
+        "records_per_s": rn / wn,
+        "single_thread": {"value": s1 / w1, "unit": "input segs/s", "cores": 1, "records_per_s": r1 / w1,
+                          "sample": f"first {d1} tags ({s1} segments, {r1} records), {w1:.1f} s wall / "
+                                    f"{c1:.1f} s CPU"},
         "cpu_model": _cpu_model(),
         "nproc": os.cpu_count(),
     }
 
 
 # ------------------------------------------------------------------ plain
-def roofline_of(phase_ms, stats, n_tags, n_rec, mode, names):
-    """Roofline entry of the dominant phase and the achieved rate of every
-    phase: algorithmic work per launch (per-unit figures times the unit
-    counts of the instrumented run) over the average launch time."""
+def work_of(stats, n_tags, n_rec):
+    """Algorithmic work of one launch of each phase: flop equivalents
+    (WORK x the unit counts of the instrumented run) for the ALU phases,
+    bytes for the memory phases."""
     n_slots = stats["pieces"] + n_tags
     curve_pieces = stats["pieces"] - stats["lines"]
-    work = {
-        # algorithmic FP64 flops per launch of each kernel
-        "bisect_count": stats["trials"] * FLOPS["trial"] + stats["lines"] * FLOPS["line_step"],
-        "pieces": (curve_pieces * FLOPS["piece"] + stats["lines"] * FLOPS["line"] + stats["ranges"] * FLOPS["range"]
-                   + stats["evolutes"] * FLOPS["evolute"]),
-        "tails": stats["joins"] * FLOPS["join"],
-        # algorithmic FP32 flops
-        "records": n_rec * FLOPS_PER_RECORD[mode],
-        # algorithmic bytes
+    return {
+        "bisect_count": stats["trials"] * WORK["trial"],
+        "pieces": (curve_pieces * WORK["piece"] + stats["lines"] * WORK["line"] + stats["ranges"] * WORK["range"]
+                   + stats["evolutes"] * WORK["evolute"]),
+        "tails": stats["joins"] * WORK["join"],
+        "records": n_rec * WORK["point"],
+        # bytes: tag read + four monoid words written
         "scan_tags": n_tags * 17.0,
+        # count read, u64 base written
         "scan_slots": n_tags * 12.0,
         "scan_records": n_slots * 12.0,
-        # the write pass copies the kept piece codes into the canonical slot
-        # array (a tag with more pieces than are kept re-runs its bisection)
+        # the write pass writes every slot (8 B), reads the kept code of each
+        # piece (4 B) and each tag's slot count and base (12 B)
         "bisect_write": n_slots * 8.0 + (n_slots - n_tags) * 4.0 + n_tags * 12.0,
     }
+
+
+def roofline_of(phase_ms, stats, n_tags, n_rec, mode, names, valu=None):
+    """Roofline entry of the dominant phase and the achieved rate of every
+    phase: algorithmic work per launch over the average launch time measured
+    live.  With VALU counters of the same sources and launch parameters
+    (valu: phase -> wave instructions per dispatch), each ALU phase also gets
+    its VALU issue rate against one wave instruction per SIMD per clock."""
+    work = work_of(stats, n_tags, n_rec)
     dom = max(phase_ms, key=phase_ms.get)
     t_dom = phase_ms[dom] * 1e-3
-    if dom in ("bisect_count", "pieces", "tails"):
+    if dom in ALU_PHASES:
         achieved = work[dom] / t_dom / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "precision": "fp64 (decisions)"}
-    elif dom == "records":
-        achieved = work[dom] / t_dom / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                "precision": "fp32 points" if dom == "records" else "fp64 decisions"}
     else:
         gbs = work[dom] / t_dom / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -149,13 +189,59 @@ def roofline_of(phase_ms, stats, n_tags, n_rec, mode, names):
     roof["algorithmic_work_per_launch"] = work[dom]
     roof["phase_ms"] = phase_ms
     roof["work_counts"] = stats
-    roof["flops_per_unit"] = FLOPS
-    roof["flops_per_record"] = FLOPS_PER_RECORD[mode]
-    roof["per_kernel"] = {
-        n: ({"TFLOP/s": work[n] / (phase_ms[n] * 1e-3) / 1e12} if n in ("bisect_count", "pieces", "tails",
-                                                                         "records")
-            else {"GB/s": work[n] / (phase_ms[n] * 1e-3) / 1e9}) for n in names}
+    roof["work_per_unit"] = WORK
+    per = {}
+    for n in names:
+        t = phase_ms[n] * 1e-3
+        if n in ALU_PHASES:
+            e = {"TFLOP/s": work[n] / t / 1e12, "frac": work[n] / t / 1e12 / PEAK_VALU_TFLOPS}
+            if valu and n in valu:
+                rate = valu[n] / t
+                e["valu_wave_insts_per_launch"] = valu[n]
+                e["valu_issue_frac"] = rate / PEAK_VALU_WAVE_INSTS
+        else:
+            e = {"GB/s": work[n] / t / 1e9, "frac": work[n] / t / 1e9 / PEAK_HBM_GBS}
+        per[n] = e
+    roof["per_kernel"] = per
+    if valu and dom in valu:
+        roof["valu_issue"] = {"achieved": valu[dom] / t_dom, "peak": PEAK_VALU_WAVE_INSTS, "unit": "wave-insts/s",
+                              "frac": valu[dom] / t_dom / PEAK_VALU_WAVE_INSTS}
     return roof
+
+
+TUNE_CACHE = os.path.join(ROOT, "paper_2405_00127_amd", "tuning.json")
+
+
+def time_steps(ctx, scene, tol, mode, buf, cnt, stream, steps, warmup, torch):
+    """Average ms of one whole-pipeline step (sx_expand_async, inputs resident
+    in HBM), host clock around `steps` launches bracketed by device syncs."""
+    def step():
+        ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def phase_times(ctx, scene, tol, mode, buf, stream, steps, B, torch):
+    """Average ms of each pipeline phase: HIP events recorded on the stream the
+    phase kernels are launched on, around each phase launch."""
+    names = B.PHASE_NAMES
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in names]
+           for _ in range(steps)]
+    for k in range(steps):
+        for p in range(len(names)):
+            evs[k][p][0].record(stream)
+            ctx.run_phase(scene, p, tol, mode, buf.data_ptr(), buf.numel(), stream=stream)
+            evs[k][p][1].record(stream)
+    torch.cuda.synchronize()
+    return {names[p]: sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(steps)) / steps
+            for p in range(len(names))}
 
 
 def plain(args, ctx, B, S, torch, np):
@@ -179,50 +265,34 @@ def plain(args, ctx, B, S, torch, np):
                                 ("bisect_range", args.bisect_range), ("bisect_waves", args.bisect_waves)) if v}
     if manual:
         ctx.set_tuning(**manual)
+        tune_info["source"] = "command line"
     elif not args.no_tune:
         from paper_2405_00127_amd import autotune as AT
 
-        log("bench: autotuning launch parameters")
+        log("bench: launch parameters from the autotuner" + (" (retuning)" if args.retune else " (cache)"))
         _, times = AT.tune(ctx, scene, tol, mode, buf.data_ptr(), buf.numel(), cnt.data_ptr(), stream,
-                           use_cache=False)
-        tune_info = {"candidates_ms": times}
+                           cache_path=args.tune_cache, use_cache=not args.retune)
+        tune_info = {"source": "autotuner, timed now" if times else f"autotuner cache {os.path.relpath(args.tune_cache, ROOT)}",
+                     "candidates_ms": times}
     tune_info["chosen"] = ctx.get_tuning()
     log(f"bench: tuning {tune_info['chosen']}")
 
-    def step():
-        ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = time_steps(ctx, scene, tol, mode, buf, cnt, stream, args.steps, args.warmup, torch)
     assert int(cnt[0].item()) == n_rec and int(cnt[1].item()) == 0
-    ms = (t1 - t0) * 1e3 / args.steps
     log(f"bench: plain {ms:.3f} ms/step")
-
-    # per-kernel times: HIP events on the launching stream around each phase
     names = B.PHASE_NAMES
-    nph = len(names)
-    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nph)]
-           for _ in range(args.steps)]
-    for k in range(args.steps):
-        for p in range(nph):
-            evs[k][p][0].record(stream)
-            ctx.run_phase(scene, p, tol, mode, buf.data_ptr(), buf.numel(), stream=stream)
-            evs[k][p][1].record(stream)
-    torch.cuda.synchronize()
-    phase_ms = {names[p]: sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
-                for p in range(nph)}
+    phase_ms = phase_times(ctx, scene, tol, mode, buf, stream, args.steps, B, torch)
     log("bench: phases " + ", ".join(f"{n} {phase_ms[n]:.3f} ms" for n in names))
     stats = ctx.piece_stats(scene, tol, mode, stream=stream)
     log(f"bench: work {stats}")
 
     n_tags = scene.n_tags
-    roof = roofline_of(phase_ms, stats, n_tags, n_rec, mode, names)
+    counters = None if args.fill_scene else measured_counters(args.mode, tune_info["chosen"])
+    roof = roofline_of(phase_ms, stats, n_tags, n_rec, mode, names,
+                       valu=counters["valu"] if counters else None)
+    if counters and roof["kernel"] in counters["traffic"]:
+        roof["traffic"] = counters["traffic"][roof["kernel"]]
+        roof["traffic_source"] = counters["source"]
     out = {
         "metric": "path segs/s expanded at 0.25px tol (batched vs plain); p50/p99 request latency",
         "value": n_seg / (ms * 1e-3),
@@ -246,7 +316,65 @@ def plain(args, ctx, B, S, torch, np):
         "roofline": roof,
         "tuning": tune_info,
     }
+    del buf
     return out, sc, mode
+
+
+def legs(args, ctx, B, S, torch, np):
+    """The other single-scene configurations, with the plain leg's launch
+    parameters: the 1k-cubic scene (lines; also replayed as a captured HIP
+    graph, since a scene this small is bound by launch overhead), the map
+    scene with arc output, and the 100k-cubic stress scene (arcs, 0.1 px)."""
+    stream = torch.cuda.current_stream()
+    dev = torch.device("cuda:0")
+    res = {}
+    for name, make in (("c1_lines", lambda: S.scene_c1(1)),
+                       ("map1M_arcs", lambda: S.scene_map(2, args.segments, args.paths, 0.25, S.OUT_ARCS)),
+                       ("stress100k_arcs", lambda: S.scene_c3(3))):
+        sc = make()
+        mode = sc.output_mode
+        scene = ctx.encode(sc, stream=stream)
+        tol = sc.tolerance
+        _, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)
+        cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+        steps = args.steps * (10 if name == "c1_lines" else 1)
+        ms = time_steps(ctx, scene, tol, mode, buf, cnt, stream, steps, args.warmup, torch)
+        assert int(cnt[0].item()) == n_rec and int(cnt[1].item()) == 0
+        phase_ms = phase_times(ctx, scene, tol, mode, buf, stream, args.steps, B, torch)
+        stats = ctx.piece_stats(scene, tol, mode, stream=stream)
+        roof = roofline_of(phase_ms, stats, scene.n_tags, n_rec, mode, B.PHASE_NAMES)
+        n_seg = sc.n_segments()
+        r = {"workload": sc.name, "segments": n_seg, "tags": scene.n_tags, "records": n_rec,
+             "output": "arcs" if mode == S.OUT_ARCS else "lines", "tolerance": tol,
+             "ms_per_step": ms, "segs_per_s": n_seg / (ms * 1e-3), "records_per_s": n_rec / (ms * 1e-3),
+             "phase_ms": phase_ms,
+             "roofline": {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}}
+        if name == "c1_lines":
+            s2 = torch.cuda.Stream()
+            with torch.cuda.stream(s2):
+                ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=s2)
+            s2.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=s2):
+                ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=s2)
+            s2.synchronize()
+            for _ in range(3):
+                g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g.replay()
+            torch.cuda.synchronize()
+            gms = (time.perf_counter() - t0) * 1e3 / steps
+            assert int(cnt[0].item()) == n_rec
+            r["graph_ms_per_step"] = gms
+            r["graph_segs_per_s"] = n_seg / (gms * 1e-3)
+            del g
+        log(f"bench: leg {name}: {ms:.3f} ms/step, {n_rec} records")
+        res[name] = r
+        scene.release()
+        del buf
+    return res
 
 
 # ------------------------------------------------------------------- fill
@@ -264,31 +392,10 @@ def fill(args, ctx, B, S, torch, np):
     recs, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)
     cnt = torch.zeros(2, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-
-    def step():
-        ctx.expand_async(scene, buf.data_ptr(), buf.numel(), cnt.data_ptr(), tol, mode, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = time_steps(ctx, scene, tol, mode, buf, cnt, stream, args.steps, args.warmup, torch)
     assert int(cnt[0].item()) == n_rec and int(cnt[1].item()) == 0
-    ms = (t1 - t0) * 1e3 / args.steps
     names = B.PHASE_NAMES
-    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in names]
-           for _ in range(args.steps)]
-    for k in range(args.steps):
-        for p in range(len(names)):
-            evs[k][p][0].record(stream)
-            ctx.run_phase(scene, p, tol, mode, buf.data_ptr(), buf.numel(), stream=stream)
-            evs[k][p][1].record(stream)
-    torch.cuda.synchronize()
-    phase_ms = {names[p]: sum(evs[k][p][0].elapsed_time(evs[k][p][1]) for k in range(args.steps)) / args.steps
-                for p in range(len(names))}
+    phase_ms = phase_times(ctx, scene, tol, mode, buf, stream, args.steps, B, torch)
     stats = ctx.piece_stats(scene, tol, mode, stream=stream)
     roof = roofline_of(phase_ms, stats, scene.n_tags, n_rec, mode, names)
     res = {
@@ -459,11 +566,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, mode: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading), or
-    None when the summary is missing or was taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_map1M_{mode}.json")
+def measured_counters(mode: str, tuning: dict):
+    """HBM bytes and VALU wave instructions per launch of each phase from the
+    committed rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy's reading; SQ_INSTS_VALU), or None when the summary is missing
+    or was taken on other kernel sources or launch parameters."""
+    path = os.path.join(ROOT, "profiles", f"counters_map1M_{mode}.json")
     try:
         with open(path, "r", encoding="utf-8") as f:
             data = json.load(f)
@@ -471,8 +579,11 @@ def measured_traffic(kernel: str, mode: str):
         return None
     if data.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = data.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    if {k: int(v) for k, v in data.get("tuning", {}).items()} != {k: int(v) for k, v in tuning.items()}:
+        return None
+    return {"traffic": {k: v["bytes_per_launch"] for k, v in data.get("kernels", {}).items()},
+            "valu": {k: v["valu_insts"] for k, v in data.get("valu", {}).items()},
+            "source": os.path.relpath(path, ROOT)}
 
 
 def phase_of_kernel(name: str):
@@ -497,16 +608,18 @@ def phase_of_kernel(name: str):
     return None
 
 
-def summarize_counters(fetch_db: str, write_db: str, probe_mb: int, mode: str, commands) -> dict:
+def summarize_counters(fetch_db: str, write_db: str, valu_db: str, probe_mb: int, mode: str, tuning: dict,
+                       commands) -> dict:
     """Per-launch HBM bytes of each phase from two rocprofv3 --pmc databases
     (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the same
     counter reads for the plain copy of probe_mb MiB that --copy-probe runs
-    (the largest runtime copy kernel of the run)."""
+    (the largest runtime copy kernel of the run), and the VALU counters of a
+    third database (summarize_valu)."""
     import sqlite3
 
     probe = float(probe_mb << 20)
-    out = {"kernel_source_hash": kernel_source_hash(), "workload": f"map1M_{mode}", "commands": list(commands),
-           "calibration": {"probe_bytes": probe}, "kernels": {}}
+    out = {"kernel_source_hash": kernel_source_hash(), "workload": f"map1M_{mode}", "tuning": tuning,
+           "commands": list(commands), "calibration": {"probe_bytes": probe}, "kernels": {}}
     per = {}
     for counter, db in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
         con = sqlite3.connect(db)
@@ -528,6 +641,7 @@ def summarize_counters(fetch_db: str, write_db: str, probe_mb: int, mode: str, c
             w = sum(c["WRITE_SIZE"].values()) / len(c["WRITE_SIZE"])
             out["kernels"][ph] = {"fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,
                                   "dispatches": [len(c["FETCH_SIZE"]), len(c["WRITE_SIZE"])]}
+    out["valu"] = summarize_valu(valu_db)
     return out
 
 
@@ -570,13 +684,13 @@ def main():
         print(json.dumps(summarize_valu(sys.argv[2]), indent=1))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-counters":
-        # offline: bench.py --summarize-counters FETCH_DB WRITE_DB PROBE_MB MODE [COMMAND ...]
-        fetch_db, write_db, probe_mb, mode = sys.argv[2:6]
-        res = summarize_counters(fetch_db, write_db, int(probe_mb), mode, sys.argv[6:])
-        path = os.path.join(ROOT, "profiles", f"traffic_map1M_{mode}.json")
+        # offline: bench.py --summarize-counters FETCH_DB WRITE_DB VALU_DB PROBE_MB MODE TUNING_JSON [COMMAND ...]
+        fetch_db, write_db, valu_db, probe_mb, mode, tuning = sys.argv[2:8]
+        res = summarize_counters(fetch_db, write_db, valu_db, int(probe_mb), mode, json.loads(tuning), sys.argv[8:])
+        path = os.path.join(ROOT, "profiles", f"counters_map1M_{mode}.json")
         with open(path, "w", encoding="utf-8") as f:
             json.dump(res, f, indent=1)
-        print(json.dumps(res["kernels"], indent=1))
+        print(json.dumps({"kernels": res["kernels"], "valu": res["valu"]}, indent=1))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -586,8 +700,11 @@ def main():
     ap.add_argument("--segments", type=int, default=1_000_000)
     ap.add_argument("--paths", type=int, default=10_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-parameter autotuner")
+    ap.add_argument("--retune", action="store_true", help="time the autotuner's candidates instead of its cache")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE, help="autotuner cache file")
+    ap.add_argument("--no-legs", action="store_true", help="skip the 1k-cubic, map-arcs and stress legs")
     ap.add_argument("--piece-waves", type=int, default=None)
     ap.add_argument("--chunk-k", type=int, default=None)
     ap.add_argument("--bisect-range", type=int, default=None)
@@ -600,8 +717,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--pool", type=int, default=64)
-    ap.add_argument("--qps", type=float, nargs="*", default=[100.0, 1000.0, 5000.0])
-    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--qps", type=float, nargs="*", default=[100.0, 200.0, 500.0, 1000.0, 2000.0, 5000.0])
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one plain device copy of this many MB (a known-size reference for "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counter calibration)")
@@ -631,10 +748,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     out, sc, mode = plain(args, ctx, B, S, torch, np)
-    # the stored counters are those of the stroked map scene
-    traffic = None if args.fill_scene else measured_traffic(out["roofline"]["kernel"], args.mode)
-    if traffic is not None:
-        out["roofline"]["traffic"] = traffic
+    if not args.no_legs:
+        out["legs"] = legs(args, ctx, B, S, torch, np)
     fill_sc = None
     if not args.no_fill:
         out["fill"], fill_sc = fill(args, ctx, B, S, torch, np)
@@ -647,7 +762,7 @@ def main():
         log("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(sc, mode, args.cpu_budget)
         if fill_sc is not None:
-            out["fill"]["cpu_baseline"] = cpu_baseline(fill_sc, mode, min(args.cpu_budget, 6.0))
+            out["fill"]["cpu_baseline"] = cpu_baseline(fill_sc, mode, min(args.cpu_budget, 4.0))
     print(json.dumps(out), flush=True)
 
 

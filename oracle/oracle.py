@@ -270,8 +270,34 @@ class Result:
         return o
 
 
+def expand_run(scene, tolerance=None, mode=None, tag_begin=0, tag_end=None, enc: Encoded | None = None):
+    """Run the full expansion (records emitted) of tags [tag_begin, tag_end)
+    and return (status, number of records) without copying anything back:
+    the oracle's own work, for timing it."""
+    L = lib()
+    if enc is None:
+        enc = encode(scene)
+    tol = scene.tolerance if tolerance is None else tolerance
+    mode = scene.output_mode if mode is None else mode
+    styles = np.ascontiguousarray(scene.styles)
+    xforms = np.ascontiguousarray(scene.xforms, np.float32)
+    nt = len(enc.tags)
+    h = L.ox_expand(C.c_void_p(enc._h), _ptr(styles), len(styles), _ptr(xforms), len(xforms), float(tol),
+                    int(mode), FIT_OFFSET, 1, int(tag_begin), int(nt if tag_end is None else tag_end))
+    if not h:
+        raise MemoryError("oracle expand failed")
+    hv = C.c_void_p(h)
+    try:
+        return L.ox_res_status(hv), int(L.ox_res_nout(hv))
+    finally:
+        L.ox_res_free(hv)
+
+
 def expand(scene, tolerance=None, mode=None, fit_mode=FIT_OFFSET, emit=True,
-           tag_begin=0, tag_end=None, enc: Encoded | None = None) -> Result:
+           tag_begin=0, tag_end=None, enc: Encoded | None = None, margins: bool = True) -> Result:
+    """Expand with the oracle (tags [tag_begin, tag_end) of the scene).
+    margins=False leaves the per-tag decision margins out of the result
+    (they are copied for the whole scene otherwise)."""
     L = lib()
     if enc is None:
         enc = encode(scene)
@@ -295,7 +321,7 @@ def expand(scene, tolerance=None, mode=None, fit_mode=FIT_OFFSET, emit=True,
             status=L.ox_res_status(hv),
             counts=_copy(L.ox_res_counts(hv), np.uint32, nt),
             out=_copy(L.ox_res_out(hv), OUT_DTYPE, L.ox_res_nout(hv)),
-            margins=_copy(L.ox_res_margins(hv), MARGIN_DTYPE, nt),
+            margins=_copy(L.ox_res_margins(hv), MARGIN_DTYPE, nt) if margins else np.zeros(0, MARGIN_DTYPE),
             pieces=_copy(L.ox_res_pieces(hv), PIECE_DTYPE, L.ox_res_npieces(hv)),
             enc=enc,
         )

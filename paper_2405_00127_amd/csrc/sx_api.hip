@@ -161,6 +161,7 @@ sx::SceneView view(const sx_scene* s) {
     v.n_styles = s->n_styles;
     v.n_xforms = s->n_xforms;
     v.n_paths = s->n_paths;
+    v.mon_stride = sx::mon_stride_of(s->n_tags);
     return v;
 }
 
@@ -231,9 +232,9 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         const uint32_t c = n_tags;
         const size_t ntag_pad = ((size_t)c + 16 + 15) & ~(size_t)15;
         regrow(s->d_tags, ntag_pad);
-        regrow(s->d_mon, 4 * (size_t)c * sizeof(uint32_t));
+        regrow(s->d_mon, 4 * (size_t)sx::mon_stride_of(c) * sizeof(uint32_t));
         regrow(s->d_nslots, ((size_t)c + 16) * sizeof(uint32_t));
-        regrow(s->d_codes, ((size_t)c + 1) * sx::kKeepCodes * sizeof(uint32_t));
+        regrow(s->d_codes, (size_t)sx::mon_stride_of(c) * sx::kKeepCodes * sizeof(uint32_t));
         regrow(s->d_base, ((size_t)c + 1) * sizeof(uint64_t));
         regrow(s->d_status_tags, sx::scan_status_bytes(c));
         regrow(s->d_status_nslots, sx::scan_status_bytes(c));
@@ -829,8 +830,10 @@ int sx_debug_monoids(sx_ctx* ctx, const sx_scene* s, uint32_t* out4xn_dev, void*
     if (!ctx || !s || (!out4xn_dev && s->n_tags)) return SX_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl_block(s, 0), s->d_status_tags, nullptr, st);
-    if (e == hipSuccess && s->n_tags)
-        e = hipMemcpyAsync(out4xn_dev, s->d_mon, 4 * (size_t)s->n_tags * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    const size_t stride = sx::mon_stride_of(s->n_tags);
+    for (int k = 0; k < 4 && e == hipSuccess && s->n_tags; k++)
+        e = hipMemcpyAsync(out4xn_dev + k * (size_t)s->n_tags, s->d_mon + k * stride, (size_t)s->n_tags * sizeof(uint32_t),
+                           hipMemcpyDeviceToDevice, st);
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "monoids");
 }
 

@@ -1231,9 +1231,12 @@ struct SceneView {
     const StyleD* styles;
     const float* xforms;  // 6 floats each
     const uint32_t* path_map;
-    const uint32_t* mon;  // 4 x n SoA
+    const uint32_t* mon;  // 4 x mon_stride SoA (point offset, path, style, transform)
     uint32_t n_tags, n_pts, n_styles, n_xforms, n_paths;
+    uint32_t mon_stride;  // n_tags rounded up to a multiple of 4 (16-byte aligned rows)
 };
+// row stride of the monoid SoA for n tags
+SX_FN uint32_t mon_stride_of(uint32_t n) { return (n + 3u) & ~3u; }
 
 enum { kTagInvalid = 0, kTagSegment = 1, kTagMarker = 2 };
 
@@ -1250,7 +1253,7 @@ struct TagInfo {
 
 // Input path id of tag i (all ones for a tag outside every path).
 SX_FN uint32_t path_of(const SceneView& sv, uint32_t i) {
-    const uint32_t pi = sv.mon[(size_t)sv.n_tags + i];
+    const uint32_t pi = sv.mon[(size_t)sv.mon_stride + i];
     return pi < sv.n_paths ? sv.path_map[pi] : 0xffffffffu;
 }
 
@@ -1263,8 +1266,8 @@ SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s
     ti.fill = false;
     const uint32_t tag = sv.tags[i];
     const uint32_t off = sv.mon[i];
-    const uint32_t sty = sv.mon[2 * (size_t)n + i];
-    const uint32_t xfi = sv.mon[3 * (size_t)n + i];
+    const uint32_t sty = sv.mon[2 * (size_t)sv.mon_stride + i];
+    const uint32_t xfi = sv.mon[3 * (size_t)sv.mon_stride + i];
     const uint32_t need = (tag & kTagEnd) ? 3u : (tag & kTagCount) + 1u;
     if (sty >= sv.n_styles || xfi >= sv.n_xforms || (size_t)off + need > sv.n_pts) return;
     if (!(tag & kTagEnd)) {

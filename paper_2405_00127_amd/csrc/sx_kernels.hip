@@ -290,11 +290,14 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
             o_sty[j] = (uint32_t)in.b - 1u;
             o_xf[j] = (uint32_t)(in.b >> 32) - 1u;
         }
+        // rows of mon_stride_of(n) words: 16-byte aligned, so a full run of
+        // 16 tags (base a multiple of 16) stores as four uint4 per row
+        const size_t stride = mon_stride_of(n);
         uint32_t* m0 = mon;
-        uint32_t* m1 = mon + n;
-        uint32_t* m2 = mon + 2 * (size_t)n;
-        uint32_t* m3 = mon + 3 * (size_t)n;
-        if (base + kTagItems <= n && (n & 3u) == 0u) {
+        uint32_t* m1 = mon + stride;
+        uint32_t* m2 = mon + 2 * stride;
+        uint32_t* m3 = mon + 3 * stride;
+        if (base + kTagItems <= n) {
 #pragma unroll
             for (int j = 0; j < kTagItems; j += 4) {
                 *reinterpret_cast<uint4*>(m0 + base + j) = make_uint4(o_off[j], o_off[j + 1], o_off[j + 2], o_off[j + 3]);
@@ -369,7 +372,9 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // a lane whose segment is done takes the wave's next tag (lane refill), so
 // the wave is busy until its range is exhausted instead of waiting for its
 // longest segment.  The count pass writes, per tag, its slot count (accepted
-// pieces + 1 tail) and keeps the codes of its first kKeepCodes pieces; the
+// pieces + 1 tail) and keeps the codes of its first kKeepCodes pieces (code
+// q of tag i at codes[q * stride + i], so the lanes of a wave, holding
+// consecutive tags, read and write consecutive words); the
 // write pass, after the scan of those counts, writes each tag's slots at
 // their canonical positions: copied from the kept codes, or, for the few
 // segments with more pieces, from a second run of the bisection.
@@ -383,6 +388,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
     unsigned long long* __restrict__ stats) {
     const uint32_t lane = threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const size_t cstride = mon_stride_of(sv.n_tags);  // row stride of the kept codes
     const uint32_t a = blockIdx.x * range;
     const uint32_t b = min(sv.n_tags, a + range);
     uint32_t cursor = a;  // next unassigned tag (wave-uniform)
@@ -410,9 +416,8 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                     const uint32_t np = nslots[i] - 1u;
                     if (np <= (uint32_t)kKeepCodes) {
                         // pieces known from the count pass: copy them and the tail
-                        const uint32_t* c = codes + (size_t)i * kKeepCodes;
                         for (uint32_t q = 0; q < np; q++)
-                            if (bi + q < slot_cap) slots[bi + q] = Slot{i, c[q]};
+                            if (bi + q < slot_cap) slots[bi + q] = Slot{i, codes[q * cstride + i]};
                         if (bi + np < slot_cap) slots[bi + np] = Slot{i, kSlotTail};
                         copied = true;
                     }
@@ -423,7 +428,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 } else if (!Write && ti.kind == kTagSegment && ti.line) {
                     // a line is one straight piece (reading G32): no bisection
                     nslots[i] = 2u;
-                    codes[(size_t)i * kKeepCodes] = slot_code(0u, 0u, false);
+                    codes[i] = slot_code(0u, 0u, false);
                     if (Stats) n_lines++;
                 } else if (ti.kind == kTagSegment) {
                     bisect_init(bs, s);
@@ -452,7 +457,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                     const uint64_t at = bi + seq;
                     if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth, pivot)};
                 } else if (seq < (uint32_t)kKeepCodes) {
-                    codes[(size_t)i * kKeepCodes + seq] = slot_code(t0u, depth, pivot);
+                    codes[seq * cstride + i] = slot_code(t0u, depth, pivot);
                 }
                 seq++;
                 if (done) {

@@ -21,13 +21,14 @@ extern "C" int dh_expand(const sx_paths* paths, const sx_style* styles, uint32_t
     uint32_t n = enc.tags.size();
     *n_tags_out = n;
     if (n > cap_tags) return -4;
-    std::vector<uint32_t> mon(4 * (size_t)n + 4);
+    const uint32_t ms = mon_stride_of(n);
+    std::vector<uint32_t> mon(4 * (size_t)ms + 4);
     uint32_t off = 0, pth = 0, sty = 0, xfi = 0;
     for (uint32_t i = 0; i < n; i++) {
         uint32_t t = enc.tags[i];
-        mon[i] = off; mon[n + i] = pth;
+        mon[i] = off; mon[ms + i] = pth;
         sty += (t & kTagStyle) ? 1 : 0; xfi += (t & kTagXform) ? 1 : 0;
-        mon[2 * n + i] = sty - 1; mon[3 * n + i] = xfi - 1;
+        mon[2 * ms + i] = sty - 1; mon[3 * ms + i] = xfi - 1;
         off += (t & kTagCount) + ((t & kTagEnd) ? 1 : 0);
         pth += (t & kTagPath) ? 1 : 0;
     }
@@ -37,7 +38,7 @@ extern "C" int dh_expand(const sx_paths* paths, const sx_style* styles, uint32_t
     for (auto k : enc.xform_stream) { const sx_affine& X = xf[k]; float v[6] = {X.a, X.b, X.c, X.d, X.e, X.f}; xd.insert(xd.end(), v, v + 6); }
     SceneView sv;
     sv.tags = enc.tags.data(); sv.pts = (const float2*)enc.data.data(); sv.styles = sd.data(); sv.xforms = xd.data();
-    sv.path_map = enc.path_map.data(); sv.mon = mon.data(); sv.n_tags = n; sv.n_pts = enc.data.size()/2; sv.n_styles = sd.size(); sv.n_xforms = xd.size()/6; sv.n_paths = enc.path_map.size();
+    sv.path_map = enc.path_map.data(); sv.mon = mon.data(); sv.n_tags = n; sv.n_pts = enc.data.size()/2; sv.n_styles = sd.size(); sv.n_xforms = xd.size()/6; sv.n_paths = enc.path_map.size(); sv.mon_stride = ms;
     Cfg cfg; double tf = kFlatFrac * (double)tol;
     cfg.tau_fit = kFitFrac * (double)tol; cfg.tau_flat = tf; cfg.inv_sqrt8tf = std::sqrt(1.0 / (8.0 * tf));
     cfg.cbrt_inv120tf = std::cbrt(1.0 / (120.0 * tf)); cfg.arcs = mode; cfg.paper_fit = paper_fit & 1; cfg.newton = (paper_fit >> 1) & 1;
@@ -73,7 +74,7 @@ extern "C" int dh_expand(const sx_paths* paths, const sx_style* styles, uint32_t
     for (size_t j = 0; j < slots.size(); j++) {
         const Slot sl = slots[j];
         for (;;) {
-            ItemSink<Fix> kw{st.data(), es_tab.data(), Fix{0, st.size()}, enc.path_map[mon[n + sl.tag]], (uint32_t)j, 0};
+            ItemSink<Fix> kw{st.data(), es_tab.data(), Fix{0, st.size()}, enc.path_map[mon[ms + sl.tag]], (uint32_t)j, 0};
             TagInfo ti; Seg sg;
             fetch_tag(sv, sl.tag, ti, sg);
             if (sl.code == kSlotTail) emit_tail(kw, cfg, sv, sl.tag, ti, sg);
