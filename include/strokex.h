@@ -347,6 +347,21 @@ int sx_get_tuning(const sx_ctx *ctx, sx_tuning *tuning);
  * n + 1 uint64 (device pointers), single-pass decoupled look-back. */
 int sx_scan_u32(sx_ctx *ctx, const uint32_t *in_dev, uint64_t *out_dev, uint32_t n, void *stream);
 
+/* The same scan for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * allocation and no host synchronisation.  The scan's control block and
+ * per-tile status words live in a static device array of the library
+ * (SX_SCAN_NOALLOC_BYTES bytes per GPU, held until the process ends; its
+ * device address is looked up once per device when a context is created).
+ * n <= SX_SCAN_NOALLOC_MAX, else SX_EINVAL and nothing is launched.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one device
+ * (other streams, other contexts, other host threads) race and give wrong
+ * sums; serialise them.  Ordered on `stream`; in_dev, out_dev as for
+ * sx_scan_u32.  Errors: SX_EINVAL, SX_EDEVICE. */
+#define SX_SCAN_NOALLOC_MAX (1u << 24)
+#define SX_SCAN_NOALLOC_BYTES (256u + 262144u)
+int sx_scan_u32_noalloc(sx_ctx *ctx, const uint32_t *in_dev, uint64_t *out_dev, uint32_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

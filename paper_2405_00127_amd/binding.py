@@ -92,6 +92,7 @@ def lib():
                 "sx_debug_counts": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
                 "sx_debug_offsets": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, vp]),
                 "sx_scan_u32": (C.c_int, [vp, vp, vp, u32, vp]),
+                "sx_scan_u32_noalloc": (C.c_int, [vp, vp, vp, u32, vp]),
                 "sx_run_phase": (C.c_int, [vp, vp, C.c_int, C.c_float, C.c_int, vp, u64, vp]),
                 "sx_set_tuning": (C.c_int, [vp, C.POINTER(_Tuning)]),
                 "sx_batch_create": (C.c_int, [vp, C.POINTER(vp)]),
@@ -366,6 +367,20 @@ class Context:
         out = torch.empty(n + 1, dtype=torch.int64, device=values.device)
         self._check(lib().sx_scan_u32(C.c_void_p(self.h), C.c_void_p(values.data_ptr()), C.c_void_p(out.data_ptr()),
                                       n, _stream_ptr(stream)), "sx_scan_u32")
+        return out
+
+
+    def scan_u32_noalloc(self, values, out=None, stream=None):
+        """sx_scan_u32_noalloc into `out` (int64, n + 1; allocated here when
+        None -- the library call itself allocates nothing)."""
+        import torch
+
+        n = int(values.numel())
+        if out is None:
+            out = torch.empty(n + 1, dtype=torch.int64, device=values.device)
+        self._check(lib().sx_scan_u32_noalloc(C.c_void_p(self.h), C.c_void_p(values.data_ptr()),
+                                              C.c_void_p(out.data_ptr()), n, _stream_ptr(stream)),
+                    "sx_scan_u32_noalloc")
         return out
 
 

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -21,6 +22,7 @@ struct sx_ctx {
     std::string err;
     sx_tuning tune = {2u, 16u, 256u, 2u};
     uint64_t* pinned_total = nullptr;  // host-pinned 2 x u64: record count, status
+    void* scratch = nullptr;           // device address of `scratch` on this device
 };
 
 // Per-tag terms of the single-pass output estimate (see soup_terms).
@@ -79,7 +81,30 @@ struct sx_batch {
     hipEvent_t staged = nullptr;       // recorded after the last staging upload
 };
 
+// Scratch of sx_scan_u32_noalloc: the scan's control block (first 256
+// bytes) and its tile status words, one copy per GPU, zero when the code
+// object is loaded.  Host code never passes `scratch` itself to a kernel:
+// its device address (per device) comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[SX_SCAN_NOALLOC_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up
+// once per device); nullptr if the lookup fails.
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
 
 constexpr uint32_t kMaxBatchScenes = 65535;
 constexpr uint32_t kSlotsPerTag = 4;        // initial slot capacity per tag
@@ -407,6 +432,8 @@ int sx_ctx_create(int device, const sx_config* cfg, sx_ctx** out) {
         delete c;
         return SX_ENOMEM;
     }
+    // the no-allocation scan's scratch on this device (device is current)
+    c->scratch = scratch_ptr(device);
     *out = c;
     return SX_OK;
 }
@@ -884,6 +911,20 @@ int sx_scan_u32(sx_ctx* ctx, const uint32_t* in_dev, uint64_t* out_dev, uint32_t
     if (ctl) (void)hipFree(ctl);
     if (status) (void)hipFree(status);
     return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "scan_u32");
+}
+
+int sx_scan_u32_noalloc(sx_ctx* ctx, const uint32_t* in_dev, uint64_t* out_dev, uint32_t n, void* stream) {
+    if (!ctx || !out_dev || (n && !in_dev)) return SX_EINVAL;
+    if (n > SX_SCAN_NOALLOC_MAX) return fail(ctx, SX_EINVAL, "n exceeds SX_SCAN_NOALLOC_MAX");
+    static_assert(SX_SCAN_NOALLOC_BYTES >= 256u, "control block");
+    if (sx::scan_ctl_bytes() > 256u || sx::scan_status_bytes(SX_SCAN_NOALLOC_MAX) > SX_SCAN_NOALLOC_BYTES - 256u)
+        return fail(ctx, SX_EDEVICE, "scan scratch layout");
+    if (!ctx->scratch) return fail(ctx, SX_EDEVICE, "scratch address lookup failed");
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ctx->scratch;
+    hipError_t e = n == 0 ? sx::launch_zero_u64(out_dev, st)
+                          : sx::launch_scan_counts(in_dev, n, out_dev, base, base + 256, st);
+    return e == hipSuccess ? SX_OK : hip_fail(ctx, e, "scan_u32_noalloc");
 }
 
 // ------------------------------------------------------------ single pass

@@ -48,6 +48,8 @@ size_t scan_ctl_bytes();
 hipError_t launch_scan_tags(const uint8_t* tags, uint32_t n, uint32_t* mon, void* ctl, void* st, WsCtl* ws_reset,
                             hipStream_t s);
 hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, void* ctl, void* st, hipStream_t s);
+// out[0] = 0 by a one-thread kernel (no memset node when captured in a graph)
+hipError_t launch_zero_u64(uint64_t* out, hipStream_t s);
 hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
                                   void* st, hipStream_t s);
 // piece codes kept per tag by the counting bisection pass

@@ -981,6 +981,13 @@ hipError_t launch_scan_counts(const uint32_t* in, uint32_t n, uint64_t* out, voi
     scan_counts_kernel<<<count_scan_tiles(n), kScanBlock, 0, s>>>(in, n, out, (ScanCtl*)ctl, (TileStatus*)st);
     return hipGetLastError();
 }
+__global__ void zero_u64_kernel(uint64_t* out) {
+    if (threadIdx.x == 0) out[0] = 0ull;
+}
+hipError_t launch_zero_u64(uint64_t* out, hipStream_t s) {
+    zero_u64_kernel<<<1, 64, 0, s>>>(out);
+    return hipGetLastError();
+}
 hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
                                   void* st, hipStream_t s) {
     scan_counts_dev_kernel<<<count_scan_tiles(cap > 0 ? cap : 1), kScanBlock, 0, s>>>(in, n_dev, cap, out, (ScanCtl*)ctl,
