@@ -21,6 +21,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 FIT_OFFSET, FIT_PAPER = 0, 1
 # fit-mode bit: Algorithm 2 without the hodograph test of reading G29
 FIT_NO_HODO = 2
+# mode bit: exact density integral for line counts, Newton-refined inverse
+# for their points (Section 4.2)
+DENSITY_NEWTON = 4
 KIND_OFFSET, KIND_EVOLUTE, KIND_CONNECT, KIND_JOIN_OUTER, KIND_JOIN_INNER, KIND_CAP = range(6)
 
 OUT_DTYPE = np.dtype(
@@ -94,9 +97,13 @@ def lib():
                 f.argtypes = [d] * nargs
             L.ox_es_integral.argtypes = [d, d, d, C.POINTER(d), C.POINTER(d)]
             L.ox_line_integral_es.restype = d
-            L.ox_line_integral_es.argtypes = [d] * 6
+            L.ox_line_integral_es.argtypes = [d] * 6 + [C.c_int]
             L.ox_es_side.restype = vp
-            L.ox_es_side.argtypes = [d, d, d, d, d, C.c_int]
+            L.ox_es_side.argtypes = [d, d, d, d, d, C.c_int, C.c_int]
+            L.ox_dens_integral.restype = d
+            L.ox_dens_integral.argtypes = [d, d]
+            L.ox_f_newton_inv.restype = d
+            L.ox_f_newton_inv.argtypes = [d, d, d]
             L.ox_gl_nodes.argtypes = [vp, vp]
             L.ox_xform_ok.restype = C.c_int
             L.ox_xform_ok.argtypes = [vp]
@@ -159,17 +166,29 @@ def es_integral(k0, k1, u):
     return complex(re.value, im.value)
 
 
-def line_integral_es(k0, k1, L, h, ua, ub):
+def line_integral_es(k0, k1, L, h, ua, ub, exact=False):
     """Section 4.2 subdivision integral of side h over [ua, ub] of an Euler
-    spiral of arc length L (before the sqrt(1/(8 tau_flat)) factor)."""
-    return lib().ox_line_integral_es(float(k0), float(k1), float(L), float(h), float(ua), float(ub))
+    spiral of arc length L (before the sqrt(1/(8 tau_flat)) factor), with
+    f_approx or (exact=True) the exact integral."""
+    return lib().ox_line_integral_es(float(k0), float(k1), float(L), float(h), float(ua), float(ub), int(bool(exact)))
 
 
-def es_side(k0, k1, L, h, tol, mode):
+def dens_integral(a, b):
+    """int_a^b sqrt|u^2 - 1| du (Section 4.1), integrated directly."""
+    return lib().ox_dens_integral(float(a), float(b))
+
+
+def f_newton_inv(y, lo=-1e300, hi=1e300):
+    """x with f(x) = y: the f_approx inverse refined by two Newton steps."""
+    return lib().ox_f_newton_inv(float(y), float(lo), float(hi))
+
+
+def es_side(k0, k1, L, h, tol, mode, flags=0):
     """Records (OUT_DTYPE) of side h of an Euler spiral placed at the origin
-    with base angle 0: p(u) = L Z(u), tangent angle phi(u)."""
+    with base angle 0: p(u) = L Z(u), tangent angle phi(u).  flags: 0 or
+    DENSITY_NEWTON."""
     L_ = lib()
-    hv = C.c_void_p(L_.ox_es_side(float(k0), float(k1), float(L), float(h), float(tol), int(mode)))
+    hv = C.c_void_p(L_.ox_es_side(float(k0), float(k1), float(L), float(h), float(tol), int(mode), int(flags)))
     if not hv.value:
         raise MemoryError("oracle es_side failed")
     try:

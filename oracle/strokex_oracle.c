@@ -64,6 +64,10 @@ enum { OX_FIT_OFFSET = 0, OX_FIT_PAPER = 1 };
 /* fit-mode bit: leave out the hodograph test of reading G29 (Algorithm 2 as
  * printed; kept only so the tests can show what the reading prevents) */
 #define OX_FIT_NO_HODO 2
+/* mode bit: count offset lines with the exact subdivision density integral f
+ * and place their points by the f_approx inverse refined by two Newton steps
+ * on f (the higher-quality option of Section 4.2) */
+#define OX_DENSITY_NEWTON 4
 
 /* kinds recorded per output (for the tests' geometric checks only) */
 enum { OX_K_OFFSET = 0, OX_K_EVOLUTE = 1, OX_K_CONNECT = 2, OX_K_JOIN_OUTER = 3,
@@ -546,6 +550,77 @@ double ox_f_approx_inv(double y) {
     return y < 0 ? -r : r;
 }
 
+/* Section 4.1: the exact subdivision density integral over [a, b] (signed),
+ * D(a, b) = int_a^b sqrt|u^2 - 1| du, integrated directly (not as a
+ * difference of f, which cancels on short ranges).  [a, b] is cut at -1, 0
+ * and 1; by the density's symmetry each part is a part of [0, 1] or of
+ * [1, inf), integrated after the substitution u = 1 - v^2 (integrand
+ * 2 v^2 sqrt(2 - v^2)) or u = 1 + v^2 (integrand 2 v^2 sqrt(2 + v^2)), both
+ * smooth in v, by 16-node Gauss-Legendre on panels of at most 1/4 in v. */
+static double gl_panels(double va, double dv, double sgn) {
+    gl_init();
+    if (!(dv > 0.0)) return 0.0;
+    int m = (int)ceil(dv / 0.25);
+    if (m < 1) m = 1;
+    double h = dv / m, sum = 0.0;
+    for (int j = 0; j < m; j++) {
+        double a = va + j * h;
+        for (int i = 0; i < OX_GL_N; i++) {
+            double v = a + 0.5 * h * (gl_x[i] + 1.0);
+            sum += gl_w[i] * 0.5 * h * 2.0 * v * v * sqrt(2.0 + sgn * v * v);
+        }
+    }
+    return sum;
+}
+/* int_p^q for 0 <= p <= q, with [p, q] inside [0, 1] or inside [1, inf); the
+ * v interval's length is taken without cancellation,
+ * |sqrt|q - 1| - sqrt|p - 1|| = (q - p) / (sqrt|q - 1| + sqrt|p - 1|) */
+static double dens_part(double p, double q) {
+    if (q <= 1.0) {
+        double vq = sqrt(1.0 - q), vp = sqrt(1.0 - p);
+        return gl_panels(vq, (q - p) / (vq + vp), -1.0);
+    }
+    double vp = sqrt(p - 1.0), vq = sqrt(q - 1.0);
+    return gl_panels(vp, (q - p) / (vp + vq), 1.0);
+}
+double ox_dens_integral(double a, double b) {
+    if (a == b) return 0.0;
+    if (a > b) return -ox_dens_integral(b, a);
+    const double cuts[3] = {-1.0, 0.0, 1.0};
+    double pts[5];
+    int n = 0;
+    pts[n++] = a;
+    for (int k = 0; k < 3; k++)
+        if (cuts[k] > a && cuts[k] < b) pts[n++] = cuts[k];
+    pts[n++] = b;
+    double sum = 0.0;
+    for (int k = 0; k + 1 < n; k++) {
+        double p = pts[k], q = pts[k + 1];
+        /* the density is even: a part at or below 0 is its mirror image */
+        if (q <= 0.0) sum += dens_part(-q, -p);
+        else sum += dens_part(p, q);
+    }
+    return sum;
+}
+
+/* Section 4.2's refinement: the point where f reaches y, from the f_approx
+ * inverse as the initial guess, by two Newton steps x <- x - (f(x) - y) /
+ * sqrt|x^2 - 1| on the exact f; each step kept inside [lo, hi] (the range
+ * being flattened) and skipped where the density vanishes. */
+double ox_f_newton_inv(double y, double lo, double hi) {
+    double x = ox_f_approx_inv(y);
+    if (x < lo) x = lo;
+    if (x > hi) x = hi;
+    for (int it = 0; it < 2; it++) {
+        double d = sqrt(fabs(x * x - 1.0));
+        if (!(d > 0.0)) break;
+        x -= (ox_f_exact(x) - y) / d;
+        if (x < lo) x = lo;
+        if (x > hi) x = hi;
+    }
+    return x;
+}
+
 /* ===================================================== 4. expansion ===== */
 
 typedef struct {
@@ -698,7 +773,7 @@ static v2 evolute_point(const ox_es *es, double u) {
  * When the x range is tiny (kappa' ~ 0) the density is constant and
  * I = F'(x_mid) L_r / (2 sqrt|h|).  For h = 0 (zero-width stroke) the ES's own
  * density sqrt|kappa| is used (Section 2.2). */
-static double line_integral(const ox_es *es, double h, double ua, double ub) {
+static double line_integral(const ox_es *es, double h, double ua, double ub, int exact) {
     if (es->k1 == 0.0) {
         /* constant curvature k0 / L: I = sqrt(|kappa| |1 + h kappa|) L_r, written
          * so that it stays finite for a pivot of zero length */
@@ -714,9 +789,13 @@ static double line_integral(const ox_es *es, double h, double ua, double ub) {
         return 2.0 / (3.0 * fabs(kp)) * (pow(fabs(ka), 1.5) + pow(fabs(kb), 1.5));
     }
     double xa = -1.0 - 2.0 * h * ka, xb = -1.0 - 2.0 * h * kb;
-    if (fabs(xb - xa) < 1e-9) return ox_f_approx_deriv(0.5 * (xa + xb)) * Lr / (2.0 * sqrt(fabs(h)));
+    if (fabs(xb - xa) < 1e-9) {
+        double xm = 0.5 * (xa + xb);
+        return (exact ? sqrt(fabs(xm * xm - 1.0)) : ox_f_approx_deriv(xm)) * Lr / (2.0 * sqrt(fabs(h)));
+    }
     double kp = es->k1 / (es->L * es->L);
-    return fabs(ox_f_approx(xb) - ox_f_approx(xa)) / (4.0 * fabs(kp) * pow(fabs(h), 1.5));
+    double dF = exact ? ox_dens_integral(xa, xb) : ox_f_approx(xb) - ox_f_approx(xa);
+    return fabs(dF) / (4.0 * fabs(kp) * pow(fabs(h), 1.5));
 }
 
 /* ---- emission helpers ---------------------------------------------------- */
@@ -758,7 +837,7 @@ static void emit_range(ox_sink *k, const ox_cfg *cfg, const ox_es *es, double h,
     uint32_t n;
     double *us = NULL;
     if (cfg->mode == OX_OUT_LINES) {
-        double I = line_integral(es, h, ua, ub);
+        double I = line_integral(es, h, ua, ub, (cfg->fit_mode & OX_DENSITY_NEWTON) != 0);
         double n_est = I * sqrt(1.0 / (8.0 * cfg->tau_flat));
         count_margin(m, n_est);
         n = ceil_count(n_est);
@@ -778,7 +857,17 @@ static void emit_range(ox_sink *k, const ox_cfg *cfg, const ox_es *es, double h,
     } else {
         us = (double *)malloc((n + 1) * sizeof(double));
         us[0] = ua; us[n] = ub;
-        if (cfg->mode == OX_OUT_LINES && h != 0.0 && es->k1 != 0.0) {
+        if (cfg->mode == OX_OUT_LINES && h != 0.0 && es->k1 != 0.0 && (cfg->fit_mode & OX_DENSITY_NEWTON)) {
+            /* exact density: points uniform in f between the range ends */
+            double xa = -1.0 - 2.0 * h * ka, xb = -1.0 - 2.0 * h * kb;
+            double Fa = ox_f_exact(xa), D = ox_dens_integral(xa, xb);
+            double lo = fmin(xa, xb), hi = fmax(xa, xb);
+            for (uint32_t i = 1; i < n; i++) {
+                if (fabs(xb - xa) < 1e-9) { us[i] = ua + (ub - ua) * ((double)i / n); continue; }
+                double x = ox_f_newton_inv(Fa + D * ((double)i / n), lo, hi);
+                us[i] = ua + (ub - ua) * ((x - xa) / (xb - xa));
+            }
+        } else if (cfg->mode == OX_OUT_LINES && h != 0.0 && es->k1 != 0.0) {
             double xa = -1.0 - 2.0 * h * ka, xb = -1.0 - 2.0 * h * kb;
             double Fa = ox_f_approx(xa), Fb = ox_f_approx(xb);
             for (uint32_t i = 1; i < n; i++) {
@@ -926,15 +1015,15 @@ static ox_es es_at_origin(double k0, double k1, double L) {
 
 /* Section 4.2 subdivision integral of side h over [ua, ub] of that ES, as the
  * line count uses it (before the sqrt(1 / (8 tau_flat)) factor). */
-double ox_line_integral_es(double k0, double k1, double L, double h, double ua, double ub) {
+double ox_line_integral_es(double k0, double k1, double L, double h, double ua, double ub, int exact) {
     ox_es es = es_at_origin(k0, k1, L);
-    return line_integral(&es, h, ua, ub);
+    return line_integral(&es, h, ua, ub, exact);
 }
 
 /* The records of side h of that ES (Sections 4-6: the range split at the
  * parallel-curve cusp, offsets, evolutes and connecting lines) at tolerance
  * tol in output mode `mode`; tag and path 0. */
-ox_res *ox_es_side(double k0, double k1, double L, double h, double tol, int mode) {
+ox_res *ox_es_side(double k0, double k1, double L, double h, double tol, int mode, int flags) {
     ox_res *r = (ox_res *)calloc(1, sizeof(ox_res));
     if (!r) return NULL;
     ox_cfg cfg;
@@ -942,7 +1031,7 @@ ox_res *ox_es_side(double k0, double k1, double L, double h, double tol, int mod
     cfg.tau_fit = OX_FIT_FRAC * tol;
     cfg.tau_flat = OX_FLAT_FRAC * tol;
     cfg.mode = mode;
-    cfg.fit_mode = OX_FIT_OFFSET;
+    cfg.fit_mode = flags;
     ox_es es = es_at_origin(k0, k1, L);
     ox_sink sk;
     sk.r = r; sk.path = 0; sk.tag = 0; sk.emit = 1; sk.count = 0; sk.mode = mode;

@@ -259,7 +259,10 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         regrow(s->d_tags, ntag_pad);
         regrow(s->d_mon, 4 * (size_t)sx::mon_stride_of(c) * sizeof(uint32_t));
         regrow(s->d_nslots, ((size_t)c + 16) * sizeof(uint32_t));
-        regrow(s->d_codes, (size_t)sx::mon_stride_of(c) * sx::kKeepCodes * sizeof(uint32_t));
+        // kept piece codes: keep_codes_of(n) x mon_stride_of(n) words for any
+        // n <= c (at most 2^23, or kKeepCodes rows of c)
+        regrow(s->d_codes, std::max<size_t>((size_t)1 << 23, (size_t)sx::mon_stride_of(c) * sx::kKeepCodes) *
+                               sizeof(uint32_t));
         regrow(s->d_base, ((size_t)c + 1) * sizeof(uint64_t));
         regrow(s->d_status_tags, sx::scan_status_bytes(c));
         regrow(s->d_status_nslots, sx::scan_status_bytes(c));
@@ -332,12 +335,14 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
             return sx::launch_scan_tags(s->d_tags, s->n_tags, s->d_mon, ctl_block(s, 0), s->d_status_tags, s->d_ws_ctl,
                                         st);
         case kPhBisectCount:
-            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, false, s->d_nslots,
+            return sx::launch_bisect(view(s), cfg, t.bisect_range, sx::keep_codes_of(s->n_tags), (int)t.bisect_waves,
+                                     false, s->d_nslots,
                                      s->d_codes, nullptr, nullptr, 0, stats, st);
         case kPhScanSlots:
             return sx::launch_scan_counts(s->d_nslots, s->n_tags, s->d_base, ctl_block(s, 1), s->d_status_nslots, st);
         case kPhBisectWrite:
-            return sx::launch_bisect(view(s), cfg, t.bisect_range, (int)t.bisect_waves, true, s->d_nslots,
+            return sx::launch_bisect(view(s), cfg, t.bisect_range, sx::keep_codes_of(s->n_tags), (int)t.bisect_waves,
+                                     true, s->d_nslots,
                                      s->d_codes, s->d_base, s->d_slots, s->slot_cap, nullptr, st);
         case kPhPieces:
             return sx::launch_slots(view(s), cfg, workspace(s), s->d_slots, n_slots_dev(s), s->slot_cap, s->d_rc,
@@ -417,7 +422,6 @@ int sx_ctx_create(int device, const sx_config* cfg, sx_ctx** out) {
         if (cfg->fit_mode > SX_FIT_PAPER || cfg->density > SX_DENSITY_NEWTON || cfg->reserved != 0u ||
             (cfg->constants_version != 0u && cfg->constants_version != SX_CONSTANTS_VERSION))
             return SX_EINVAL;
-        if (cfg->density == SX_DENSITY_NEWTON) return SX_EINVAL;  // not available yet
         conf = *cfg;
         conf.constants_version = SX_CONSTANTS_VERSION;
     }

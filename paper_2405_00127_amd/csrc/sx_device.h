@@ -20,6 +20,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
 
 // Every function is host+device so the same code can be unit-checked off the GPU.
 #define SX_HD __host__ __device__
@@ -473,6 +474,104 @@ SX_HD inline float branch_inv_frac(const XSegT<float>& s, float f) {
     return 2.0f * f * G / (B + sqrtf(fmaxf(B * B + 2.0f * dFa, 0.0f)));
 }
 
+// ------------------------------- exact density integral, refined inverse
+// The higher-quality option of Section 4.2: counts from the exact integral
+// f(x) = int_0^x sqrt|u^2 - 1| du, points where f reaches each target, found
+// from the f_approx inverse by two Newton steps on f.  FP64 throughout.
+
+// f in closed form (reading G5 for |x| > 1), odd
+SX_FN double f_exact_d(double x) {
+    const double a = fabs(x);
+    const double r = a <= 1.0 ? 0.5 * (a * sqrt(1.0 - a * a) + asin(a))
+                              : 0.5 * (a * sqrt(a * a - 1.0) - acosh(a)) + 0.25 * kPi;
+    return x < 0.0 ? -r : r;
+}
+// int of 2 v^2 sqrt(2 + s v^2) over [v0, v0 + dv] by 8-node Gauss-Legendre
+// (the density after the substitution u = 1 + s v^2, smooth in v)
+SX_HD inline double sub_gl8(double v0, double dv, double s) {
+    const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const double c = v0 + 0.5 * dv, hw = 0.5 * dv;
+    double sum = 0.0;
+    for (int i = 0; i < 4; i++) {
+        const double va = c - hw * gx[i], vb = c + hw * gx[i];
+        sum += gw[i] * (va * va * sqrt(2.0 + s * va * va) + vb * vb * sqrt(2.0 + s * vb * vb));
+    }
+    return sum * dv;  // (dv / 2) x weights x 2 v^2 sqrt(...)
+}
+// int_p^q sqrt|u^2 - 1| du, 0 <= p <= q on one side of 1, by the substitution
+// u = 1 -+ v^2 (v's interval length without cancellation)
+SX_HD inline double dens_side(double p, double q) {
+    if (q <= 1.0) {
+        const double vq = sqrt(1.0 - q), vp = sqrt(1.0 - p);
+        return (vp + vq > 0.0) ? sub_gl8(vq, (q - p) / (vp + vq), -1.0) : 0.0;
+    }
+    const double vp = sqrt(p - 1.0), vq = sqrt(q - 1.0);
+    return (vp + vq > 0.0) ? sub_gl8(vp, (q - p) / (vp + vq), 1.0) : 0.0;
+}
+// int_a^b sqrt|u^2 - 1| du (signed), relative-accurate: the closed-form
+// difference when it keeps at least 1e-4 of the larger |f| (rounding then
+// costs at most ~1e-12 of the result), else -- a short range -- the
+// substituted quadrature on each part between -1, 0 and 1
+SX_HD inline double dens_int_d(double a, double b) {
+    if (a == b) return 0.0;
+    const double fa = f_exact_d(a), fb = f_exact_d(b);
+    const double d = fb - fa;
+    if (fabs(d) >= 1e-4 * fmax(fabs(fa), fabs(fb))) return d;
+    const double lo = fmin(a, b), hi = fmax(a, b);
+    const double cut[3] = {-1.0, 0.0, 1.0};
+    double sum = 0.0, p = lo;
+    for (int k = 0; k <= 3; k++) {
+        const double q = (k < 3 && cut[k] > p && cut[k] < hi) ? cut[k] : (k == 3 ? hi : p);
+        if (q > p) {
+            sum += (q <= 0.0) ? dens_side(-q, -p) : dens_side(p, q);
+            p = q;
+        }
+    }
+    return b > a ? sum : -sum;
+}
+// inverse of f_approx, branch by branch (Section 4.2)
+SX_HD inline double f_approx_inv_d(double y) {
+    const double a = fabs(y);
+    const double b1 = sin(kC1 * 0.8) / kC1;
+    const double b2 = kA2 * 0.125 + 0.25 * kPi;  // sqrt(8)/3 (1/4)^1.5 + pi/4
+    const double b3 = 0.6406 * 2.1 * 2.1 - 0.81 * 2.1 + kC2;
+    double r;
+    if (a < b1) {
+        r = asin(kC1 * a) / kC1;
+    } else if (a < b2) {
+        const double u = (a - 0.25 * kPi) / kA2;
+        r = 1.0 + (u < 0.0 ? -cbrt(u * u) : cbrt(u * u));
+    } else if (a < b3) {
+        r = (0.81 + sqrt(0.81 * 0.81 - 4.0 * 0.6406 * (kC2 - a))) / (2.0 * 0.6406);
+    } else {
+        r = 0.156 + sqrt(0.156 * 0.156 - 2.0 * (kC3 - a));
+    }
+    return y < 0.0 ? -r : r;
+}
+// x in [lo, hi] where f(x) = y: the f_approx inverse, then two Newton steps
+// x <- x - (f(x) - y) / sqrt|x^2 - 1| (each kept in [lo, hi], skipped where
+// the density vanishes)
+SX_HD inline double f_newton_inv_d(double y, double lo, double hi) {
+    double x = fmin(fmax(f_approx_inv_d(y), lo), hi);
+    for (int it = 0; it < 2; it++) {
+        const double d = sqrt(fabs(x * x - 1.0));
+        if (!(d > 0.0)) break;
+        x = fmin(fmax(x - (f_exact_d(x) - y) / d, lo), hi);
+    }
+    return x;
+}
+SX_FN float bits_f(uint32_t v) {
+    float f;
+    memcpy(&f, &v, 4);
+    return f;
+}
+SX_FN uint32_t f_bits(float f) {
+    uint32_t v;
+    memcpy(&v, &f, 4);
+    return v;
+}
+
 SX_FN uint32_t ceil_count(double n_est) {
     if (!(n_est > 1.0)) return 1u;
     if (n_est > 1e7) return kMaxCount;
@@ -498,6 +597,7 @@ constexpr uint32_t kIfEndB = 1u << 10;      // evolute: connecting lines at ub
 constexpr uint32_t kIfDneg = 1u << 11;      // evolute: side traversed backwards
 constexpr uint32_t kIfInnerFirst = 1u << 12;  // join: inner part before the outer part
 constexpr uint32_t kIfKSame = 1u << 13;       // offset, h == 0: curvature keeps its sign over the range
+constexpr uint32_t kIfNewton = 1u << 14;      // offset: place points by the Newton-refined exact inverse
 constexpr uint32_t kXBitsShift = 16;          // offset: the split at the branch breaks (bits 16-22)
 // join outer part kind (bits 16..19), inner part kind (bits 20..21)
 enum { kOutLine1 = 0, kOutLine2 = 1, kOutLine3 = 2, kOutRound = 3 };
@@ -529,6 +629,8 @@ struct OffsetP {
     float ua, du, len0, fh;  // u range, x length of its first branch piece, side h
     float Pax, Pay, Pbx, Pby;
     float dF, dF0;  // F increment of the range and of its first branch piece
+    // (with kIfNewton: len0 and dF0 hold the low and high words of the FP64
+    // density coordinate x at ua, dF the x length of the range)
 };
 // evolute-item payload: the range, its density split alpha and evolute
 // count, the exact offset and evolute end points
@@ -628,6 +730,9 @@ struct RangeRes {
     float dF0, len0, alpha;  // increment and x length of its first branch piece; evolute point split
     uint32_t n, ne, place, xbits;  // xbits: the split at the branch breaks (split_x_sum)
 };
+// Newton: the build that can count with the exact integral (cfg.newton);
+// the default build leaves that code out.
+template <bool Newton = true>
 SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, double h, double ua, double ub,
                            bool reversed) {
     RangeRes r;
@@ -652,6 +757,19 @@ SX_FN RangeRes range_count(const Cfg& cfg, double k0, double k1, double L, doubl
             } else {
                 I = (2.0 / 3.0) * du * sqrt(L) * (pow15(aa) + pow15(ab)) / (aa + ab);
             }
+        } else if (Newton && cfg.newton) {
+            // the exact integral (counts) and the range's x in FP64 (placement)
+            r.place = kIfNewton;
+            const double hL = h / L;
+            const double xa = -1.0 - 2.0 * (hL * kna), xb = -1.0 - 2.0 * (hL * knb);
+            const double dx = -2.0 * hL * k1 * du;
+            const double D = dens_int_d(xa, xb);
+            uint64_t xw;
+            memcpy(&xw, &xa, 8);
+            r.len0 = bits_f((uint32_t)xw);
+            r.dF0 = bits_f((uint32_t)(xw >> 32));
+            r.dF = (float)dx;
+            I = (dx != 0.0) ? fabs(D) * L * L / (4.0 * fabs(h * k1) * sqrt(fabs(h))) : 0.0;
         } else {
             r.place = kIfPlaceF;
             const double hL = h / L;
@@ -960,6 +1078,33 @@ struct Place {
     float kna, knb;
     float inv_n;  // 1 / (records of the range)
 };
+// Exact-density placement of a range (kIfNewton): its x interval and the
+// exact integral over it, FP64.
+struct PlaceN {
+    double xa, dx, lo, hi, Fa, D;
+};
+SX_HD inline void place_newton_init(PlaceN& pn, const OffsetP& p) {
+    const uint64_t xw = (uint64_t)f_bits(p.len0) | ((uint64_t)f_bits(p.dF0) << 32);
+    memcpy(&pn.xa, &xw, 8);
+    pn.dx = (double)p.dF;
+    const double xb = pn.xa + pn.dx;
+    pn.lo = fmin(pn.xa, xb);
+    pn.hi = fmax(pn.xa, xb);
+    pn.Fa = f_exact_d(pn.xa);
+    pn.D = dens_int_d(pn.xa, xb);
+}
+// u of point i (0 < i < n): uniform in the exact integral, x from the
+// Newton-refined inverse (a range of x length below 1e-9 has constant
+// density: uniform in u)
+SX_HD inline float offset_u_newton(const OffsetP& p, const PlaceN& pn, uint32_t i, uint32_t n) {
+    const double f = (double)i / (double)n;
+    double tau = f;
+    if (fabs(pn.dx) >= 1e-9) {
+        const double x = f_newton_inv_d(pn.Fa + pn.D * f, pn.lo, pn.hi);
+        tau = fmin(fmax((x - pn.xa) / pn.dx, 0.0), 1.0);
+    }
+    return (float)((double)p.ua + (double)p.du * tau);
+}
 SX_HD inline void place_init(Place& pl, const ES& es, const OffsetP& p, uint32_t hdr, const XIncF& xi) {
     pl.kna = es.fk0 + es.fk1 * (p.ua - 0.5f);
     pl.knb = es.fk0 + es.fk1 * (p.ua + p.du - 0.5f);
@@ -1035,7 +1180,9 @@ SX_HD inline float offset_u(const OffsetP& p, uint32_t hdr, uint32_t i, uint32_t
 }
 
 // One item chunk (header + payload words) into records; es: the slot's
-// spiral (8 floats) for offset and evolute items.
+// spiral (8 floats) for offset and evolute items.  Newton: the build that
+// handles exact-density offset items (kIfNewton).
+template <bool Newton = false>
 SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, const XIncF& xi, RecOut& o) {
     const ItemHdr h = *reinterpret_cast<const ItemHdr*>(it);
     const uint32_t* pw = it + kHdrWords;
@@ -1047,7 +1194,10 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, const XIncF
         const OffsetP p = *reinterpret_cast<const OffsetP*>(pw);
         const ES es = es_from_f(es_rec, (hdr & kIfPivot) != 0);
         Place pl;
-        place_init(pl, es, p, hdr, xi);
+        PlaceN pn;
+        const bool newton = Newton && (hdr & kIfNewton) != 0;
+        if (newton) place_newton_init(pn, p);
+        else place_init(pl, es, p, hdr, xi);
         const uint32_t n = h.ntot;
         pl.inv_n = 1.0f / (float)n;
         const bool neg = (hdr & kIfDirNeg) != 0;
@@ -1058,7 +1208,7 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, const XIncF
             uprev = p.ua;
             prev = v2(p.Pax, p.Pay);
         } else {
-            uprev = offset_u(p, hdr, h.k0, n, pl, xi);
+            uprev = newton ? offset_u_newton(p, pn, h.k0, n) : offset_u(p, hdr, h.k0, n, pl, xi);
             prev = offset_point_f(es, p.fh, uprev);
         }
         for (uint32_t r = 0; r < nrec; r++) {
@@ -1069,7 +1219,7 @@ SX_HD inline void emit_item(const uint32_t* it, const float* es_rec, const XIncF
                 u = p.ua + p.du;
                 P = v2(p.Pbx, p.Pby);
             } else {
-                u = offset_u(p, hdr, i, n, pl, xi);
+                u = newton ? offset_u_newton(p, pn, i, n) : offset_u(p, hdr, i, n, pl, xi);
                 P = offset_point_f(es, p.fh, u);
             }
             if (!arcs) {

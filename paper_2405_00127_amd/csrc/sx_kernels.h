@@ -53,9 +53,17 @@ hipError_t launch_zero_u64(uint64_t* out, hipStream_t s);
 hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
                                   void* st, hipStream_t s);
 // piece codes kept per tag by the counting bisection pass
-constexpr int kKeepCodes = 32;
-hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
-                         uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
+constexpr int kKeepCodes = 32;  // fewest piece codes kept per tag by the count pass
+// Piece codes the count pass keeps per tag for n tags: a budget of 2^23 words
+// shared by the tags, at least kKeepCodes and at most 1024 per tag (small
+// scenes keep every code, so the write pass copies instead of re-running the
+// bisection of segments with many pieces).
+inline uint32_t keep_codes_of(uint32_t n) {
+    const uint64_t k = (1ull << 23) / ((uint64_t)mon_stride_of(n) + 1u);
+    return (uint32_t)(k < (uint64_t)kKeepCodes ? kKeepCodes : (k > 1024u ? 1024u : k));
+}
+hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,
+                         uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
                          unsigned long long* stats, hipStream_t s);
 // piece slots (one thread per slot)
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,

@@ -372,7 +372,7 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // a lane whose segment is done takes the wave's next tag (lane refill), so
 // the wave is busy until its range is exhausted instead of waiting for its
 // longest segment.  The count pass writes, per tag, its slot count (accepted
-// pieces + 1 tail) and keeps the codes of its first kKeepCodes pieces (code
+// pieces + 1 tail) and keeps the codes of its first `keep` pieces (code
 // q of tag i at codes[q * stride + i], so the lanes of a wave, holding
 // consecutive tags, read and write consecutive words); the
 // write pass, after the scan of those counts, writes each tag's slots at
@@ -383,7 +383,7 @@ constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (on the map
 
 template <bool Write, bool Stats, int MinWaves>
 __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
-    SceneView sv, Cfg cfg, uint32_t range, uint32_t* __restrict__ nslots, uint32_t* __restrict__ codes,
+    SceneView sv, Cfg cfg, uint32_t range, uint32_t keep, uint32_t* __restrict__ nslots, uint32_t* __restrict__ codes,
     const uint64_t* __restrict__ base, Slot* __restrict__ slots, uint64_t slot_cap,
     unsigned long long* __restrict__ stats) {
     const uint32_t lane = threadIdx.x;
@@ -414,7 +414,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 if (Write) {
                     bi = base[i];
                     const uint32_t np = nslots[i] - 1u;
-                    if (np <= (uint32_t)kKeepCodes) {
+                    if (np <= keep) {
                         // pieces known from the count pass: copy them and the tail
                         for (uint32_t q = 0; q < np; q++)
                             if (bi + q < slot_cap) slots[bi + q] = Slot{i, codes[q * cstride + i]};
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 if (Write) {
                     const uint64_t at = bi + seq;
                     if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth, pivot)};
-                } else if (seq < (uint32_t)kKeepCodes) {
+                } else if (seq < keep) {
                     codes[seq * cstride + i] = slot_code(t0u, depth, pivot);
                 }
                 seq++;
@@ -525,7 +525,7 @@ __device__ __forceinline__ uint32_t slot_class(const SceneView& sv, Slot sl) {
 // thread, the second ranges of the whole block are packed onto its first
 // threads (the piece's k0, k1, L, width and cusp go through LDS), and then
 // each thread writes its piece's items in canonical order.
-template <int MinWaves, bool Stats>
+template <int MinWaves, bool Stats, bool Newton>
 __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
                                                                     const Slot* __restrict__ slots,
                                                                     const uint64_t* __restrict__ n_slots_dev,
@@ -606,8 +606,8 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                 g0 = side_geo(es, sg.w, 0);
                 g1 = side_geo(es, sg.w, 1);
                 g1.split = g1.split && side1;
-                s_first[0][t] = range_count(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
-                if (side1) s_first[1][t] = range_count(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
+                s_first[0][t] = range_count<Newton>(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
+                if (side1) s_first[1][t] = range_count<Newton>(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
                 if (g0.split || g1.split) {
                     s_own[t][0] = es.k0;
                     s_own[t][1] = es.k1;
@@ -632,8 +632,8 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         for (uint32_t q = t; q < n_task; q += kSlotBlock) {
             const uint32_t task = s_task[q], own = task >> 2, side = (task >> 1) & 1u;
             const double w = s_own[own][3];
-            s_res[q] = range_count(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w, s_tc[own][side],
-                                   1.0, (task & 1u) != 0u);
+            s_res[q] = range_count<Newton>(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w,
+                                           s_tc[own][side], 1.0, (task & 1u) != 0u);
         }
         __syncthreads();
         // phase 3: the items of each piece in canonical order
@@ -753,6 +753,7 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
 
 // One item chunk starting at unit u: loads its one or two units and writes
 // its records.
+template <bool Newton>
 __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& ws, const Unit* u,
                                             const uint64_t* roff, uint64_t n_slots, float* out, uint64_t cap,
                                             int arcs, const XIncF& xi, float* stage = nullptr, uint64_t lo = 0,
@@ -771,11 +772,12 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
     if (slot >= n_slots) return;
     const uint64_t end = roff[slot + 1] < cap ? roff[slot + 1] : cap;
     RecOut o{out, roff[slot] + w[3], end, path, arcs, stage, lo, hi};
-    emit_item(w, ws.es_tab + 8 * (size_t)slot, xi, o);
+    emit_item<Newton>(w, ws.es_tab + 8 * (size_t)slot, xi, o);
 }
 
 // Per item chunk, the FP32 per-point work: records at
 // roff[slot] + the chunk's position within its slot.
+template <bool Newton>
 __global__ __launch_bounds__(kRecBlock, 6) void record_kernel(SceneView sv, ItemWs ws, int arcs,
                                                            const uint64_t* __restrict__ roff,
                                                            const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
@@ -805,7 +807,8 @@ __global__ __launch_bounds__(kRecBlock, 6) void record_kernel(SceneView sv, Item
             const uint64_t n_st = ws.tile_n[tile] > ws.region_cap ? 0u
                                   : (n_rec < kStageWords / words ? n_rec : kStageWords / words);
             for (uint32_t s2 = threadIdx.x; s2 < cnt; s2 += kRecBlock)
-                record_item(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs, xi, s_stage, lo, lo + n_st);
+                record_item<Newton>(sv, ws, base + s2, roff, n_slots, out, cap_records, arcs, xi, s_stage, lo,
+                                    lo + n_st);
             __syncthreads();
             uint32_t* dst = reinterpret_cast<uint32_t*>(out) + lo * words;
             const uint32_t* src = reinterpret_cast<const uint32_t*>(s_stage);
@@ -817,7 +820,7 @@ __global__ __launch_bounds__(kRecBlock, 6) void record_kernel(SceneView sv, Item
         const Unit* base = ws.units + ws.ovf_base;
         for (uint64_t s = (uint64_t)(b - kRecGrid) * kRecBlock + threadIdx.x; s < cnt;
              s += (uint64_t)kOvfBlocks * kRecBlock)
-            record_item(sv, ws, base + s, roff, n_slots, out, cap_records, arcs, xi);
+            record_item<Newton>(sv, ws, base + s, roff, n_slots, out, cap_records, arcs, xi);
     }
 }
 
@@ -834,7 +837,7 @@ struct SoupSink {
     unsigned long long* counter;
     float* es_tab;  // the current piece's FP32 spiral (8 floats, slot 0)
     XIncF xi;
-    uint32_t path, slot, n, arcs;
+    uint32_t path, slot, n, arcs, newton;
     uint32_t st[1];
     template <class P>
     __device__ void put(uint32_t hdr, uint32_t nrec, uint32_t K, const P& p) {
@@ -854,7 +857,8 @@ struct SoupSink {
             w[4] = c * K;
             w[5] = nrec;
             RecOut o{out, base + (uint64_t)c * K, base + nrec, path, (int)arcs, nullptr, 0, 0};
-            emit_item(w, es_tab, xi, o);
+            if (newton) emit_item<true>(w, es_tab, xi, o);
+            else emit_item<false>(w, es_tab, xi, o);
         }
     }
 };
@@ -864,7 +868,8 @@ __global__ __launch_bounds__(256) void soup_kernel(SceneView sv, Cfg cfg, XIncF 
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sv.n_tags; i += stride) {
         float es_loc[8];
-        SoupSink k{out, cap, counter, es_loc, xi, path_of(sv, i), 0u, 0u, (uint32_t)cfg.arcs, {0u}};
+        SoupSink k{out, cap, counter, es_loc, xi, path_of(sv, i), 0u, 0u, (uint32_t)cfg.arcs,
+                   (uint32_t)(cfg.newton && !cfg.arcs), {0u}};
         TagInfo ti;
         Seg sg;
         fetch_tag(sv, i, ti, sg);
@@ -997,40 +1002,59 @@ hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uin
 
 template <bool Write, bool Stats>
 static void bisect_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, uint32_t range,
-                          uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t cap,
-                          unsigned long long* stats) {
+                          uint32_t keep, uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots,
+                          uint64_t cap, unsigned long long* stats) {
     if (waves <= 2)
-        bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
+        bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+                                                                stats);
     else if (waves == 3)
-        bisect_kernel<Write, Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
+        bisect_kernel<Write, Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+                                                                stats);
     else
-        bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, nslots, codes, base, slots, cap, stats);
+        bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+                                                                stats);
 }
-hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, int waves, bool write, uint32_t* nslots,
-                         uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
+hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,
+                         uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
                          unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    if (range == 0 || range % 64u) return hipErrorInvalidValue;
+    if (range == 0 || range % 64u || keep < (uint32_t)kKeepCodes) return hipErrorInvalidValue;
+    // a scene too small to give every SIMD a wave at this range takes
+    // shorter ranges (down to one tag per lane)
+    const uint32_t fill = ((sv.n_tags / 4096u + 63u) / 64u) * 64u;
+    if (fill < range) range = fill < 64u ? 64u : fill;
     const uint32_t g = (sv.n_tags + range - 1) / range;
-    if (write) bisect_launch<true, false>(g, s, waves, sv, cfg, range, nslots, codes, base, slots, slot_cap, stats);
-    else if (stats) bisect_launch<false, true>(g, s, waves, sv, cfg, range, nslots, codes, base, slots, slot_cap, stats);
-    else bisect_launch<false, false>(g, s, waves, sv, cfg, range, nslots, codes, base, slots, slot_cap, stats);
+    if (write)
+        bisect_launch<true, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+    else if (stats)
+        bisect_launch<false, true>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+    else
+        bisect_launch<false, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
     return hipGetLastError();
+}
+template <bool Newton>
+static void slot_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, const ItemWs& ws,
+                        const Slot* slots, const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc,
+                        unsigned long long* stats) {
+    if (stats)
+        slot_kernel<1, true, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else if (waves <= 1)
+        slot_kernel<1, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else if (waves == 2)
+        slot_kernel<2, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else
+        slot_kernel<3, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
 }
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
                         const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
                         unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     const uint32_t g = std::min<uint32_t>(kSlotGrid, std::max<uint32_t>(1u, slot_tiles(slot_cap)));
-    if (stats) {
-        slot_kernel<1, true><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    } else if (waves <= 1) {
-        slot_kernel<1, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    } else if (waves == 2) {
-        slot_kernel<2, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    } else {
-        slot_kernel<3, false><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
-    }
+    // the exact-integral counts apply to line output only
+    if (cfg.newton && !cfg.arcs)
+        slot_launch<true>(g, s, waves, sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+    else
+        slot_launch<false>(g, s, waves, sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
     return hipGetLastError();
 }
 hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const uint64_t* base,
@@ -1046,8 +1070,13 @@ hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg,
     if (sv.n_tags == 0) return hipSuccess;
     XIncF xi;
     for (int k = 0; k < 5; k++) xi.v[k] = (float)cfg.xinc[k];
-    record_kernel<<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, n_slots_dev, slot_cap,
-                                                              (float*)out, cap, xi);
+    // exact-density items exist only with line output in the Newton mode
+    if (cfg.newton && !cfg.arcs)
+        record_kernel<true><<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, n_slots_dev, slot_cap,
+                                                                        (float*)out, cap, xi);
+    else
+        record_kernel<false><<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, n_slots_dev,
+                                                                         slot_cap, (float*)out, cap, xi);
     return hipGetLastError();
 }
 hipError_t launch_gather(const GatherDesc* descs, uint32_t n_scenes, uint8_t* tags, float2* pts, StyleD* styles,

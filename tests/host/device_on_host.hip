@@ -106,7 +106,8 @@ extern "C" int dh_expand(const sx_paths* paths, const sx_style* styles, uint32_t
         RecOut o{recs, roff[slot] + w[3], roff[slot + 1], path, cfg.arcs};
         XIncF xi;
         for (int q = 0; q < 5; q++) xi.v[q] = (float)cfg.xinc[q];
-        emit_item(buf, es_tab.data() + 8 * (size_t)slot, xi, o);
+        if (cfg.newton) emit_item<true>(buf, es_tab.data() + 8 * (size_t)slot, xi, o);
+        else emit_item<false>(buf, es_tab.data() + 8 * (size_t)slot, xi, o);
         if (o.idx != roff[slot] + w[3] + item_n(w[0])) return -10;
     }
     return 0;

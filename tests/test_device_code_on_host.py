@@ -50,7 +50,8 @@ def dev(tmp_path_factory):
     return L
 
 
-def _run(L, sc):
+def _run(L, sc, flags=0):
+    """flags: bit 0 the paper-literal fit, bit 1 the exact-density (Newton) mode."""
     mode = sc.output_mode
     keep = [np.ascontiguousarray(sc.verbs, np.uint8), np.ascontiguousarray(sc.verb_off, np.uint32),
             np.ascontiguousarray(sc.pts, np.float32), np.ascontiguousarray(sc.pt_off, np.uint32),
@@ -63,10 +64,10 @@ def _run(L, sc):
     nt, nr = C.c_uint32(), C.c_uint64()
     args = (C.byref(p), st.ctypes.data, len(st), xf.ctypes.data, len(xf), sc.tolerance, mode, counts.ctypes.data,
             cap)
-    assert L.dh_expand(*args, None, 0, C.byref(nt), C.byref(nr), 0) == 0
+    assert L.dh_expand(*args, None, 0, C.byref(nt), C.byref(nr), flags) == 0
     w = 6 if mode else 5
     recs = np.zeros(nr.value * w + 1, np.float32)
-    assert L.dh_expand(*args, recs.ctypes.data, nr.value, C.byref(nt), C.byref(nr), 0) == 0
+    assert L.dh_expand(*args, recs.ctypes.data, nr.value, C.byref(nt), C.byref(nr), flags) == 0
     return counts[: nt.value].copy(), recs[: nr.value * w].view(ARC_DTYPE if mode else LINE_DTYPE).copy()
 
 
@@ -87,3 +88,22 @@ def test_device_code_on_host_matches_the_oracle(dev, name):
     assert rep.worst_sweep <= P.SWEEP_TOL, rep
     assert rep.bad_path_ids == 0
     assert P.closed_per_path(recs) == 0
+
+
+@pytest.mark.parametrize("name", ["c1_lines", "c2_lines", "c3_lines"])
+def test_exact_density_mode_on_host_matches_the_oracle(dev, name):
+    """The exact-density mode (counts from the exact integral, points by the
+    Newton-refined inverse; Section 4.2) of the device code against the
+    oracle's, at the same bars."""
+    sc = {"c1_lines": lambda: S.scene_c1(1),
+          "c2_lines": lambda: S.scene_c2(2, n_segments=10000, n_paths=100),
+          "c3_lines": lambda: S.scene_c3(3, n_cubics=300, output_mode=S.OUT_LINES)}[name]()
+    counts, recs = _run(dev, sc, flags=2)
+    ref = O.expand(sc, fit_mode=O.DENSITY_NEWTON)
+    assert ref.status == 0
+    rep = P.compare(counts, recs, ref, sc.output_mode)
+    assert rep.n_unexplained == 0, rep
+    assert rep.worst_endpoint <= P.ENDPOINT_TOL, rep
+    assert rep.bad_path_ids == 0
+    assert P.closed_per_path(recs) == 0
+    assert counts.sum() != O.expand(sc, emit=False).counts.sum()  # the mode changes the counts

@@ -403,3 +403,119 @@ def test_evolute_outputs_follow_the_exact_evolutes_of_the_pieces():
         if checked == 12:
             break
     assert checked == 12
+
+
+# ------------------------------- Section 4.2: exact integral, Newton inverse
+def _f_mp(x):
+    """The closed form of f (reading G5) in 40-digit arithmetic."""
+    import mpmath as M
+
+    M.mp.dps = 40
+    x = M.mpf(x)
+    a = abs(x)
+    r = (a * M.sqrt(1 - a * a) + M.asin(a)) / 2 if a <= 1 else (a * M.sqrt(a * a - 1) - M.acosh(a)) / 2 + M.pi / 4
+    return r if x >= 0 else -r
+
+
+def test_exact_density_integral_against_high_precision():
+    """The oracle integrates sqrt|u^2 - 1| over [a, b] directly (substitutions
+    u = 1 -+ v^2, Gauss-Legendre); it must equal f(b) - f(a) of the closed
+    form evaluated in 40-digit arithmetic to a few ulps, on long and very
+    short ranges, across and next to the points +-1 where the density
+    vanishes."""
+    pytest.importorskip("mpmath")
+    rng = np.random.default_rng(21)
+    cases = [(0.3, 0.9), (-2.0, 3.0), (0.999, 1.001), (1.0, 1.0 + 1e-7), (5.0, 5.0001), (-0.5, -0.49),
+             (-7.0, -1.0), (100.0, 100.000001), (0.99999, 1.00001), (-1.0 - 1e-9, -1.0 + 1e-9)]
+    for _ in range(200):
+        a = rng.uniform(-40, 40)
+        cases.append((a, a + rng.choice([-1, 1]) * 10 ** rng.uniform(-8, 1.5)))
+    for a, b in cases:
+        want = float(_f_mp(b) - _f_mp(a))
+        got = O.dens_integral(a, b)
+        assert abs(got - want) <= 8e-16 * abs(want) + 1e-300, (a, b, got, want)
+
+
+def test_newton_refined_inverse_reaches_fp32_accuracy():
+    """Section 4.2: two Newton steps from the f_approx inverse bring the
+    inverse of the exact integral to 32-bit accuracy.  Checked against the
+    40-digit closed form over |x| <= 30 and within 1e-9 .. 0.1 of +-1, where
+    the density vanishes; the approximate inverse alone is off by up to
+    about 5%."""
+    pytest.importorskip("mpmath")
+    xs = np.concatenate([np.linspace(-30, 30, 3001), 1 + np.logspace(-9, -1, 100), 1 - np.logspace(-9, -1, 100),
+                         -1 + np.logspace(-9, -1, 50), -1 - np.logspace(-9, -1, 50)])
+    worst_n = worst_a = 0.0
+    for x in xs:
+        y = float(_f_mp(x))
+        s = max(abs(x), 1e-300)
+        worst_n = max(worst_n, abs(O.f_newton_inv(y) - x) / s)
+        worst_a = max(worst_a, abs(O.f_approx_inv(y) - x) / s)
+    assert worst_n <= 1e-7, worst_n
+    assert worst_a > 1e-3
+
+
+def test_exact_mode_line_integral_equals_quadrature():
+    """With the exact integral the Section 4.2 count integral is the
+    quadrature of sqrt(|kappa| |1 + h kappa|) ds to rounding, on any range."""
+    rng = np.random.default_rng(6)
+    for _ in range(200):
+        k0 = rng.uniform(-3, 3)
+        k1 = rng.choice([-1, 1]) * rng.uniform(0.05, 6.0)
+        L = math.exp(rng.uniform(math.log(2.0), math.log(500.0)))
+        h = rng.choice([-1, 1]) * math.exp(rng.uniform(math.log(0.1), math.log(60.0)))
+        ua, ub = np.sort(rng.uniform(0.0, 1.0, 2))
+        if ub - ua < 1e-3:
+            continue
+        got = O.line_integral_es(k0, k1, L, h, ua, ub, exact=True)
+        want = density_quad(k0, k1, L, h, ua, ub)
+        assert abs(got / want - 1.0) < 1e-9, (k0, k1, L, h, ua, ub, got, want)
+
+
+@pytest.mark.parametrize("tol", [0.25, 0.02])
+def test_newton_mode_flattening_error_is_tau_flat(tol):
+    """Lines counted with the exact integral and placed by the refined
+    inverse: the same bounds as with f_approx (at most 1.2 tau_flat from the
+    exact parallel curve; at least 0.6 tau_flat where n >= 8); the points of
+    each range are uniform in the exact integral."""
+    tf = 0.65 * tol
+    worst, least = 0.0, np.inf
+    for k0, k1, L, h in SIDE_CASES:
+        u, p, N = es_exact(k0, k1, L)
+        P = p + h * N
+        r = O.es_side(k0, k1, L, h, tol, S.OUT_LINES, O.DENSITY_NEWTON)
+        off = r[r["kind"] == O.KIND_OFFSET]
+        pts, _ = X.sample_outputs(off["x0"], off["y0"], off["x1"], off["y1"], None, 0.02)
+        e = max(dist_to_polyline(pts, P).max(), dist_to_polyline(P, pts).max())
+        worst = max(worst, e / tf)
+        if len(off) >= 8:
+            least = min(least, e / tf)
+    assert worst <= 1.2, worst
+    assert 0.6 <= least < 1.0, least
+
+
+def test_newton_mode_counts_follow_the_exact_integral():
+    """On a whole scene the exact integral changes counts only by the
+    approximation's few percent, and the outline stays within tolerance of
+    the exact parallel curves."""
+    sc = S.scene_c1(1).subset(range(4))
+    ra = O.expand(sc)
+    rn = O.expand(sc, fit_mode=O.DENSITY_NEWTON)
+    assert ra.status == 0 and rn.status == 0
+    na, nn = int(ra.counts.sum()), int(rn.counts.sum())
+    assert 0.9 < nn / na < 1.1 and nn != na
+    offs = rn.offsets()
+    enc = rn.enc
+    mon = O.monoids(enc.tags)
+    worst = 0.0
+    for i in np.nonzero((enc.tags & X.TAG_END) == 0)[0]:
+        o = rn.out[offs[i]: offs[i + 1]]
+        o = o[o["kind"] == O.KIND_OFFSET]
+        xf = sc.xforms[enc.xform_stream[mon[3][i]]]
+        w = float(sc.styles[enc.style_stream[mon[2][i]]]["half_width"])
+        P_, W = X.world_segment(enc.data, mon[0][i], enc.tags[i], xf)
+        A, B_, cusps = X.dense_offsets(P_, w, 0.02)
+        ref = np.concatenate([A, B_] + [X.circle_pts(c, w) for c in cusps])
+        pts, _ = X.sample_outputs(o["x0"], o["y0"], o["x1"], o["y1"], None, 0.05)
+        worst = max(worst, X.max_dist(pts, ref)[0])
+    assert worst <= sc.tolerance, worst
