@@ -1694,6 +1694,30 @@ SX_HD void emit_tail(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i, c
     emit_join(k, cfg, ti.join, (double)ti.miter, pend, s.te, tb, ti.w);
 }
 
+// The single pass of one tag (Section 8.1's organisation): its bisection,
+// each accepted piece's parallel curves as soon as it is accepted, then its
+// join or cap, all into one sink.  Shared by the single-pass kernel and its
+// host build.
+template <class Sink>
+SX_HD void soup_tag(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i) {
+    TagInfo ti;
+    Seg sg;
+    fetch_tag(sv, i, ti, sg);
+    if (ti.kind == kTagSegment) {
+        Bisect bs;
+        bisect_init(bs, sg);
+        for (;;) {
+            uint32_t t0u = 0, depth = 0;
+            bool done = false, pivot = false;
+            if (bisect_step(bs, sg, cfg, ti.line, t0u, depth, pivot, done)) {
+                emit_piece(k, cfg, sg, ti.line, t0u, depth, pivot);
+                if (done) break;
+            }
+        }
+    }
+    emit_tail(k, cfg, sv, i, ti, sg);
+}
+
 // ------------------------------------------------------------ slots
 // Every tag owns (pieces + 1) consecutive *slots* in canonical order: one
 // per accepted piece in t order, then its tail (join / cap).  A slot code is

@@ -870,22 +870,7 @@ __global__ __launch_bounds__(256) void soup_kernel(SceneView sv, Cfg cfg, XIncF 
         float es_loc[8];
         SoupSink k{out, cap, counter, es_loc, xi, path_of(sv, i), 0u, 0u, (uint32_t)cfg.arcs,
                    (uint32_t)(cfg.newton && !cfg.arcs), {0u}};
-        TagInfo ti;
-        Seg sg;
-        fetch_tag(sv, i, ti, sg);
-        if (ti.kind == kTagSegment) {
-            Bisect bs;
-            bisect_init(bs, sg);
-            for (;;) {
-                uint32_t t0u = 0, depth = 0;
-                bool done = false, pivot = false;
-                if (bisect_step(bs, sg, cfg, ti.line, t0u, depth, pivot, done)) {
-                    emit_piece(k, cfg, sg, ti.line, t0u, depth, pivot);
-                    if (done) break;
-                }
-            }
-        }
-        emit_tail(k, cfg, sv, i, ti, sg);
+        soup_tag(k, cfg, sv, i);
     }
 }
 
