@@ -78,6 +78,10 @@ def lib():
                 f.restype = rt
                 f.argtypes = [vp]
             L.ox_enc_free.argtypes = [vp]
+            L.ox_dash_seg_len.restype = C.c_double
+            L.ox_dash_seg_len.argtypes = [vp, C.c_int, vp]
+            L.ox_encode_dashed.restype = vp
+            L.ox_encode_dashed.argtypes = [vp, vp, vp, vp, vp, u32]
             L.ox_monoids.argtypes = [vp, u32, vp, vp, vp, vp]
             L.ox_expand.restype = vp
             L.ox_expand.argtypes = [vp, vp, u32, vp, u32, C.c_double, C.c_int, C.c_int, C.c_int, u32, u32]
@@ -262,6 +266,39 @@ def encode(scene) -> Encoded:
         _h=h,
     )
     return enc
+
+
+def dash_seg_len(points) -> float:
+    """Arc length of a degree-c Bezier (c + 1 points) by the dashing rule
+    (reading G35: 16 panels of 8-node Gauss-Legendre of |B'|)."""
+    P = np.ascontiguousarray(np.asarray(points, np.float64).reshape(-1, 2))
+    panel = np.zeros(16)
+    return lib().ox_dash_seg_len(_ptr(P), len(P) - 1, _ptr(panel))
+
+
+def encode_dashed(scene, enc: Encoded | None = None) -> Encoded:
+    """The dashed encoding of the scene (readings G34-G36): every stroke with
+    a dash pattern cut into dashes, each an open subpath."""
+    L = lib()
+    if enc is None:
+        enc = encode(scene)
+    vals, off, ph = scene.dash_tables()
+    vals = np.ascontiguousarray(vals if len(vals) else np.zeros(1, np.float32))
+    fill = np.ascontiguousarray((np.asarray(scene.styles["flags"], np.uint8) & STYLE_FILL).astype(np.uint8))
+    h = L.ox_encode_dashed(C.c_void_p(enc._h), _ptr(vals), _ptr(off), _ptr(ph), _ptr(fill), len(scene.styles))
+    if not h:
+        raise MemoryError("oracle dashed encode failed")
+    hv = C.c_void_p(h)
+    nt = L.ox_enc_ntags(hv)
+    return Encoded(
+        tags=_copy(L.ox_enc_tags(hv), np.uint8, nt),
+        data=_copy(L.ox_enc_data(hv), np.float32, 2 * L.ox_enc_npts(hv)).reshape(-1, 2),
+        style_stream=_copy(L.ox_enc_style_stream(hv), np.uint32, L.ox_enc_nstyles(hv)),
+        xform_stream=_copy(L.ox_enc_xform_stream(hv), np.uint32, L.ox_enc_nxforms(hv)),
+        path_map=_copy(L.ox_enc_path_map(hv), np.uint32, L.ox_enc_npaths(hv)),
+        status=L.ox_enc_status(hv),
+        _h=h,
+    )
 
 
 def monoids(tags: np.ndarray) -> np.ndarray:

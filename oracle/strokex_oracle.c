@@ -621,6 +621,262 @@ double ox_f_newton_inv(double y, double lo, double hi) {
     return x;
 }
 
+/* ============================================ dashing (Sections 1, 9.3) == */
+/* The dash pattern of a stroke (an SVG dash array and offset, in the path's
+ * own units) cuts each subpath into dashes; every dash is then stroked as an
+ * open subpath with the style's joins and caps.  The paper dashes on the CPU
+ * and expands the dashes as individual strokes; this is that definition, as
+ * an encoding of the dashed path.  Readings:
+ *   G34  the pattern restarts at every subpath; a closed subpath is dashed
+ *        along its closing line as well and no dash continues across its
+ *        start point (every dash is open); zero-length dashes draw nothing;
+ *        an odd-length array is repeated once; a pattern of total length 0
+ *        leaves the stroke solid.
+ *   G35  arc length of a segment: 16 equal parameter panels of 8-node
+ *        Gauss-Legendre of |B'(t)|; lengths and pattern positions on a grid
+ *        of 2^-24 units, so that sums along a subpath are exact; a dash
+ *        boundary inside a segment lies at the parameter where the rule's
+ *        partial integral reaches it; the dash's part of the segment is the
+ *        segment restricted to that parameter range (its control points
+ *        rounded to FP32).
+ *   G36  the dashed encoding: every path opens with an empty closed subpath
+ *        at its first point carrying its style and transform bits and ends
+ *        with an empty closed subpath at its last subpath's start point
+ *        carrying its path end bit (so that every path keeps its entries in
+ *        the style, transform and path streams even when no dash falls on
+ *        it); each dash is [start point][parts of segments][stroke cap
+ *        marker (start, first control point that differs from it, else the
+ *        start plus (1, 0))].
+ * Fills are not dashed. */
+#define OX_DASH_PANELS 16
+#define OX_DASH_GRID 16777216.0 /* 2^24 */
+
+static const double dash_gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+static const double dash_gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+
+/* |B'(t)| of the degree-c Bezier P[0..c] */
+static double bez_speed(const v2 *P, int c, double t) {
+    double mt = 1.0 - t;
+    v2 d;
+    if (c == 1) d = vsub(P[1], P[0]);
+    else if (c == 2) d = vscale(vadd(vscale(vsub(P[1], P[0]), mt), vscale(vsub(P[2], P[1]), t)), 2.0);
+    else d = vscale(vadd(vadd(vscale(vsub(P[1], P[0]), mt * mt), vscale(vsub(P[2], P[1]), 2.0 * t * mt)),
+                         vscale(vsub(P[3], P[2]), t * t)), 3.0);
+    return vlen(d);
+}
+/* 8-node Gauss-Legendre of |B'| over [a, b] */
+static double speed_gl8(const v2 *P, int c, double a, double b) {
+    double m = 0.5 * (a + b), h = 0.5 * (b - a), sum = 0.0;
+    for (int i = 0; i < 4; i++)
+        sum += dash_gw[i] * (bez_speed(P, c, m - h * dash_gx[i]) + bez_speed(P, c, m + h * dash_gx[i]));
+    return sum * h;
+}
+/* G35 arc length; panel[k] receives the integral over panel k */
+double ox_dash_seg_len(const v2 *P, int c, double *panel) {
+    double total = 0.0;
+    for (int k = 0; k < OX_DASH_PANELS; k++) {
+        panel[k] = speed_gl8(P, c, (double)k / OX_DASH_PANELS, (double)(k + 1) / OX_DASH_PANELS);
+        total += panel[k];
+    }
+    return total;
+}
+/* parameter where the rule's partial integral reaches s (bisection) */
+static double dash_t_at(const v2 *P, int c, const double *panel, double s) {
+    double acc = 0.0;
+    int k = 0;
+    while (k < OX_DASH_PANELS - 1 && acc + panel[k] <= s) acc += panel[k++];
+    double lo = (double)k / OX_DASH_PANELS, hi = (double)(k + 1) / OX_DASH_PANELS;
+    const double t0 = lo, rest = s - acc;
+    for (int it = 0; it < 200 && hi > lo; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (speed_gl8(P, c, t0, mid) < rest) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+/* blossom of the degree-c Bezier at (u[0..c-1]) */
+static v2 bez_blossom(const v2 *P, int c, const double *u) {
+    v2 q[4];
+    for (int j = 0; j <= c; j++) q[j] = P[j];
+    for (int l = 0; l < c; l++)
+        for (int j = 0; j < c - l; j++) q[j] = vadd(vscale(q[j], 1.0 - u[l]), vscale(q[j + 1], u[l]));
+    return q[0];
+}
+/* control points of the segment restricted to [ta, tb], rounded to FP32
+ * (the segment's own end points where ta = 0 or tb = 1) */
+static void bez_part(const v2 *P, int c, double ta, double tb, float *out) {
+    for (int j = 0; j <= c; j++) {
+        double u[3];
+        for (int l = 0; l < c; l++) u[l] = (l < c - j) ? ta : tb;
+        v2 q = bez_blossom(P, c, u);
+        if (j == 0 && ta == 0.0) q = P[0];
+        if (j == c && tb == 1.0) q = P[c];
+        out[2 * j] = (float)q.x;
+        out[2 * j + 1] = (float)q.y;
+    }
+}
+static int64_t dash_fix(double v) { return (int64_t)llround(v * OX_DASH_GRID); }
+static int64_t floor_div(int64_t a, int64_t b) { int64_t q = a / b; return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q; }
+
+static void enc_marker(ox_enc *e, uint8_t extra, float sx, float sy, float dx, float dy) {
+    e->tags[e->n_tags++] = (uint8_t)(2u | OX_TAG_SUBPATH_END | OX_TAG_F32 | extra);
+    enc_pt(e, sx, sy);
+    enc_pt(e, dx, dy);
+}
+/* an empty closed subpath at p (start point, then the marker's two points) */
+static int enc_empty(ox_enc *e, uint8_t extra, float px, float py) {
+    if (enc_reserve(e, 1, 3)) return -2;
+    enc_pt(e, px, py);
+    enc_marker(e, (uint8_t)(OX_TAG_CLOSED | extra), px, py, px + 1.0f, py);
+    return 0;
+}
+
+/* The dashed encoding of an encoded scene (G34-G36).  Per user style:
+ * dash values dash_arr[dash_off[k] .. dash_off[k+1]) and offset dash_phase[k];
+ * style_fill[k] marks fills.  Paths whose style has no pattern (or a pattern
+ * of total length 0) keep their tags and points unchanged. */
+ox_enc *ox_encode_dashed(const ox_enc *src, const float *dash_arr, const uint32_t *dash_off,
+                         const float *dash_phase, const uint8_t *style_fill, uint32_t n_user_styles) {
+    ox_enc *e = (ox_enc *)calloc(1, sizeof(ox_enc));
+    if (!e) return NULL;
+    e->status = src->status;
+    if (src->status) return e;
+    for (uint32_t i = 0; i < src->n_styles; i++)
+        if (enc_push_u32(&e->style_stream, &e->n_styles, &e->cap_styles, src->style_stream[i])) goto oom;
+    for (uint32_t i = 0; i < src->n_xforms; i++)
+        if (enc_push_u32(&e->xform_stream, &e->n_xforms, &e->cap_xforms, src->xform_stream[i])) goto oom;
+    for (uint32_t i = 0; i < src->n_paths; i++)
+        if (enc_push_u32(&e->path_map, &e->n_paths, &e->cap_paths, src->path_map[i])) goto oom;
+    {
+        uint32_t n = src->n_tags;
+        uint32_t off = 0;
+        int32_t sty = -1;
+        uint32_t t = 0;
+        while (t < n) {
+            /* one path: tags t .. pe (the tag carrying the path end bit) */
+            uint32_t pe = t;
+            while (pe < n && !(src->tags[pe] & OX_TAG_PATH)) pe++;
+            if (pe >= n) { e->status = -1; return e; }
+            if (src->tags[t] & OX_TAG_STYLE) sty++;
+            uint32_t us = src->style_stream[sty];
+            if (us >= n_user_styles) { e->status = -1; return e; }
+            const float *D0 = src->data + 2 * (size_t)off;
+            float p0x = D0[0], p0y = D0[1];
+            /* the pattern on the 2^-24 grid */
+            int64_t pat[64];
+            uint32_t np_ = dash_off[us + 1] - dash_off[us];
+            int64_t period = 0;
+            int solid = style_fill[us] != 0 || np_ == 0 || np_ > 32;
+            if (!solid) {
+                uint32_t m = (np_ & 1u) ? 2 * np_ : np_;
+                for (uint32_t j = 0; j < m; j++) {
+                    pat[j] = dash_fix((double)dash_arr[dash_off[us] + (j % np_)]);
+                    period += pat[j];
+                }
+                np_ = m;
+                solid = period <= 0;
+            }
+            if (enc_empty(e, (uint8_t)(src->tags[t] & (OX_TAG_STYLE | OX_TAG_XFORM)), p0x, p0y)) goto oom;
+            if (solid) {
+                /* copy the path's tags and points */
+                for (uint32_t i = t; i <= pe; i++) {
+                    uint32_t tg = src->tags[i];
+                    uint32_t inc = (tg & OX_TAG_COUNT) + ((tg & OX_TAG_SUBPATH_END) ? 1u : 0u);
+                    /* the first tag of each subpath brings its start point */
+                    int first = (i == t) || (src->tags[i - 1] & OX_TAG_SUBPATH_END);
+                    if (enc_reserve(e, 1, inc + 1)) goto oom;
+                    const float *D = src->data + 2 * (size_t)off;
+                    if (first) enc_pt(e, D[0], D[1]);
+                    for (uint32_t j = 1; j <= (tg & OX_TAG_COUNT); j++) enc_pt(e, D[2 * j], D[2 * j + 1]);
+                    e->tags[e->n_tags++] = (uint8_t)(tg & ~(OX_TAG_PATH | OX_TAG_STYLE | OX_TAG_XFORM));
+                    off += inc;
+                }
+            } else {
+                int64_t phase = dash_fix((double)dash_phase[us]) % period;
+                if (phase < 0) phase += period;
+                uint32_t i = t;
+                while (i <= pe) {
+                    /* one subpath: segments i .. me-1, marker me */
+                    uint32_t me = i;
+                    while (!(src->tags[me] & OX_TAG_SUBPATH_END)) me++;
+                    int64_t S = 0; /* subpath position of the current segment's start */
+                    /* total length first (for dashes running to the subpath end) */
+                    int64_t Stot = 0;
+                    {
+                        uint32_t o2 = off;
+                        for (uint32_t j = i; j < me; j++) {
+                            uint32_t c = src->tags[j] & OX_TAG_COUNT;
+                            v2 P[4];
+                            double panel[OX_DASH_PANELS];
+                            for (uint32_t q = 0; q <= c; q++) P[q] = v2m(src->data[2 * (o2 + q)], src->data[2 * (o2 + q) + 1]);
+                            Stot += dash_fix(ox_dash_seg_len(P, (int)c, panel));
+                            o2 += c;
+                        }
+                    }
+                    float ds_x = 0, ds_y = 0, dd_x = 0, dd_y = 0;
+                    int dash_open = 0;
+                    for (uint32_t j = i; j < me; j++) {
+                        uint32_t c = src->tags[j] & OX_TAG_COUNT;
+                        v2 P[4];
+                        double panel[OX_DASH_PANELS];
+                        for (uint32_t q = 0; q <= c; q++) P[q] = v2m(src->data[2 * (off + q)], src->data[2 * (off + q) + 1]);
+                        int64_t len = dash_fix(ox_dash_seg_len(P, (int)c, panel));
+                        int64_t S0 = S, S1 = S + len;
+                        int last = (j + 1 == me);
+                        /* dash intervals [a, b) meeting (S0, S1] */
+                        int64_t mlo = floor_div(S0 + phase, period) - 1, mhi = floor_div(S1 + phase, period) + 1;
+                        for (int64_t m = mlo; m <= mhi; m++) {
+                            int64_t cpos = 0;
+                            for (uint32_t k = 0; k < np_; k++) {
+                                int64_t a = m * period + cpos - phase, b = a + pat[k];
+                                cpos += pat[k];
+                                if (k & 1u) continue; /* a gap */
+                                if (a < 0) a = 0;
+                                if (b > Stot) b = Stot;
+                                int64_t lo = a > S0 ? a : S0, hi = b < S1 ? b : S1;
+                                if (!(lo < hi)) continue;
+                                double ta = lo == S0 ? 0.0 : dash_t_at(P, (int)c, panel, (double)(lo - S0) / OX_DASH_GRID);
+                                double tb = hi == S1 ? 1.0 : dash_t_at(P, (int)c, panel, (double)(hi - S0) / OX_DASH_GRID);
+                                if (tb < ta) tb = ta;
+                                float part[8];
+                                bez_part(P, (int)c, ta, tb, part);
+                                if (enc_reserve(e, 2, c + 3)) goto oom;
+                                if (a >= S0) {
+                                    /* the dash starts here: its start point, and its tangent point (G14) */
+                                    dash_open = 1;
+                                    ds_x = part[0]; ds_y = part[1];
+                                    dd_x = ds_x + 1.0f; dd_y = ds_y;
+                                    for (uint32_t q = 1; q <= c; q++)
+                                        if (!(part[2 * q] == ds_x && part[2 * q + 1] == ds_y)) { dd_x = part[2 * q]; dd_y = part[2 * q + 1]; break; }
+                                    enc_pt(e, ds_x, ds_y);
+                                }
+                                for (uint32_t q = 1; q <= c; q++) enc_pt(e, part[2 * q], part[2 * q + 1]);
+                                e->tags[e->n_tags++] = (uint8_t)(c | OX_TAG_F32);
+                                if (b <= S1 || last) {
+                                    if (dash_open) enc_marker(e, 0, ds_x, ds_y, dd_x, dd_y);
+                                    dash_open = 0;
+                                }
+                            }
+                        }
+                        S = S1;
+                        off += c;
+                    }
+                    off += 3; /* the subpath's marker: its two points and the next start point */
+                    i = me + 1;
+                }
+            }
+            /* (off is now past the path's last marker: its start point is 2 back) */
+            if (enc_empty(e, OX_TAG_PATH, src->data[2 * (size_t)(off - 2)], src->data[2 * (size_t)(off - 2) + 1]))
+                goto oom;
+            t = pe + 1;
+        }
+    }
+    return e;
+oom:
+    e->status = -2;
+    return e;
+}
+
 /* ===================================================== 4. expansion ===== */
 
 typedef struct {

@@ -260,8 +260,8 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         regrow(s->d_mon, 4 * (size_t)sx::mon_stride_of(c) * sizeof(uint32_t));
         regrow(s->d_nslots, ((size_t)c + 16) * sizeof(uint32_t));
         // kept piece codes: keep_codes_of(n) x mon_stride_of(n) words for any
-        // n <= c (at most 2^23, or kKeepCodes rows of c)
-        regrow(s->d_codes, std::max<size_t>((size_t)1 << 23, (size_t)sx::mon_stride_of(c) * sx::kKeepCodes) *
+        // n <= c (at most 2^25, or kKeepCodes rows of c)
+        regrow(s->d_codes, std::max<size_t>((size_t)1 << 25, (size_t)sx::mon_stride_of(c) * sx::kKeepCodes) *
                                sizeof(uint32_t));
         regrow(s->d_base, ((size_t)c + 1) * sizeof(uint64_t));
         regrow(s->d_status_tags, sx::scan_status_bytes(c));

@@ -54,12 +54,12 @@ hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uin
                                   void* st, hipStream_t s);
 // piece codes kept per tag by the counting bisection pass
 constexpr int kKeepCodes = 32;  // fewest piece codes kept per tag by the count pass
-// Piece codes the count pass keeps per tag for n tags: a budget of 2^23 words
+// Piece codes the count pass keeps per tag for n tags: a budget of 2^25 words
 // shared by the tags, at least kKeepCodes and at most 1024 per tag (small
 // scenes keep every code, so the write pass copies instead of re-running the
 // bisection of segments with many pieces).
 inline uint32_t keep_codes_of(uint32_t n) {
-    const uint64_t k = (1ull << 23) / ((uint64_t)mon_stride_of(n) + 1u);
+    const uint64_t k = (1ull << 25) / ((uint64_t)mon_stride_of(n) + 1u);
     return (uint32_t)(k < (uint64_t)kKeepCodes ? kKeepCodes : (k > 1024u ? 1024u : k));
 }
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,

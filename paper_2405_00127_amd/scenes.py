@@ -59,6 +59,8 @@ class Scene:
     xform_ix  u32 [n_paths]       index into ``xforms``
     styles    STYLE_DTYPE [n_styles]
     xforms    f32 [n_xforms, 6]   (a, b, c, d, e, f): x' = a x + c y + e, y' = b x + d y + f
+    dashes    optional, one entry per style: None (solid) or (dash lengths,
+              dash offset) in the path's own units (SVG dasharray/dashoffset)
     """
 
     verbs: np.ndarray
@@ -72,6 +74,7 @@ class Scene:
     name: str = ""
     tolerance: float = 0.25
     output_mode: int = OUT_LINES
+    dashes: Optional[list] = None
 
     @property
     def n_paths(self) -> int:
@@ -93,8 +96,24 @@ class Scene:
         for k in path_ids:
             v, p = self.path(int(k))
             b.add_path(v, p, int(self.style_ix[k]), int(self.xform_ix[k]))
-        return b.build(self.styles, self.xforms, name=self.name + "[subset]",
-                       tolerance=self.tolerance, output_mode=self.output_mode)
+        sc = b.build(self.styles, self.xforms, name=self.name + "[subset]",
+                     tolerance=self.tolerance, output_mode=self.output_mode)
+        sc.dashes = self.dashes
+        return sc
+
+    def dash_tables(self):
+        """The dash patterns as flat arrays: values (f32), per-style offsets
+        into them (u32, n_styles + 1) and dash offsets (f32, n_styles)."""
+        n = len(self.styles)
+        ds = self.dashes or [None] * n
+        vals, off, ph = [], [0], []
+        for k in range(n):
+            d = ds[k] if k < len(ds) else None
+            arr, o = (d if d is not None else ((), 0.0))
+            vals.extend(float(v) for v in arr)
+            off.append(len(vals))
+            ph.append(float(o))
+        return (np.asarray(vals, np.float32), np.asarray(off, np.uint32), np.asarray(ph, np.float32))
 
 
 class SceneBuilder:
@@ -579,4 +598,22 @@ def scene_batch(seed: int = 4, n_scenes: int = 256, lo: int = 100, hi: int = 200
     for i, s in enumerate(sizes):
         s = int(max(s, 4))
         out.append(scene_map(seed * 100_003 + i, s, max(1, s // 100), 0.25, output_mode))
+    return out
+
+
+def with_dashes(scene: Scene, seed: int = 0, lo: float = 1.0, hi: float = 24.0, max_len: int = 4) -> Scene:
+    """The scene with a seeded dash pattern on every stroke style: 1..max_len
+    (dash, gap) pairs of lengths log-uniform in [lo, hi] (in the path's own
+    units) and an offset uniform in one period; fills stay solid."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dashes = []
+    for st in scene.styles:
+        if int(st["flags"]) & STYLE_FILL:
+            dashes.append(None)
+            continue
+        m = 2 * int(rng.integers(1, max_len + 1))
+        arr = np.exp(rng.uniform(math.log(lo), math.log(hi), m)).astype(np.float32)
+        dashes.append((arr, float(rng.uniform(0.0, float(arr.sum())))))
+    out = dataclasses.replace(scene, name=scene.name + "-dashed")
+    out.dashes = dashes
     return out
