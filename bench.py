@@ -331,8 +331,10 @@ def legs(args, ctx, B, S, torch, np):
     """The other single-scene configurations, with the plain leg's launch
     parameters: the 1k-cubic scene (lines; also replayed as a captured HIP
     graph, since a scene this small is bound by launch overhead), the map
-    scene with arc output, the 100k-cubic stress scene (arcs, 0.1 px), and the
-    map scene with lines counted and placed by the exact density integral."""
+    scene with arc output, the 100k-cubic stress scene (arcs, 0.1 px), the
+    map scene with lines counted and placed by the exact density integral,
+    and the map scene with a dash pattern on every stroke (dash passes timed
+    at encoding, then the expansion of the dashed scene)."""
     stream = torch.cuda.current_stream()
     dev = torch.device("cuda:0")
     res = {}
@@ -344,7 +346,10 @@ def legs(args, ctx, B, S, torch, np):
                           ("map1M_arcs", lambda: S.scene_map(2, args.segments, args.paths, 0.25, S.OUT_ARCS), ctx),
                           ("stress100k_arcs", lambda: S.scene_c3(3), ctx),
                           ("map1M_lines_exact_density",
-                           lambda: S.scene_map(2, args.segments, args.paths, 0.25, S.OUT_LINES), ctx_n)):
+                           lambda: S.scene_map(2, args.segments, args.paths, 0.25, S.OUT_LINES), ctx_n),
+                          ("map1M_dashed_lines",
+                           lambda: S.with_dashes(S.scene_map(2, args.segments, args.paths, 0.25, S.OUT_LINES),
+                                                 seed=4, lo=0.5, hi=12.0), ctx)):
         ctx_saved, ctx = ctx, c
         sc = make()
         mode = sc.output_mode
@@ -364,6 +369,16 @@ def legs(args, ctx, B, S, torch, np):
              "ms_per_step": ms, "segs_per_s": n_seg / (ms * 1e-3), "records_per_s": n_rec / (ms * 1e-3),
              "phase_ms": phase_ms,
              "roofline": {k: roof[k] for k in ("kernel", "bound", "achieved", "peak", "unit", "frac")}}
+        if sc.dashes is not None:
+            # the dash passes run once, at encoding (device time measured there);
+            # the oracle's dashing of the same scene on one host core beside it
+            import oracle as O
+
+            t0 = time.perf_counter()
+            O.encode_dashed(sc)
+            r["dash_ms"] = scene.dash_ms()
+            r["dashed_tags"] = scene.n_tags
+            r["oracle_dash_ms_one_core"] = (time.perf_counter() - t0) * 1e3
         if name == "c1_lines":
             s2 = torch.cuda.Stream()
             with torch.cuda.stream(s2):

@@ -163,6 +163,38 @@ const char *sx_version(void);
  * SX_ENOMEM, SX_EDEVICE.  The scene is owned by ctx. */
 int sx_scene_encode(sx_ctx *ctx, const sx_paths *paths, const sx_style *styles, uint32_t n_styles,
                     const sx_affine *xforms, uint32_t n_xforms, void *stream, sx_scene **out);
+/* Dash pattern of a stroke style (SVG stroke-dasharray / stroke-dashoffset,
+ * in the path's own units): array[0 .. count) alternate dash and gap
+ * lengths (an odd count repeats once), offset shifts the pattern's start.
+ * count 0, or a pattern of total length 0, leaves the stroke solid. */
+typedef struct {
+    const float *array;
+    uint32_t count;  /* <= 32 */
+    float offset;
+} sx_dash;
+
+/* Encode paths with dash patterns (dashes[k] for styles[k]; fills are never
+ * dashed): as sx_scene_encode, then the GPU cuts every dashed subpath into
+ * dashes, each an open subpath stroked with the style's joins and caps
+ * (the dash patterns of Sections 1 and 9.3, done as prefix sums of segment
+ * arc lengths).  The pattern restarts at every subpath; a closed subpath is
+ * dashed along its closing line and no dash continues across its start
+ * point; zero-length dashes draw nothing.  Arc length: 16 parameter panels
+ * of 8-node Gauss-Legendre of |B'(t)| per segment, on a grid of 2^-24
+ * units; a dash ends inside a segment at the parameter where that integral
+ * reaches it, and its part of the segment is the segment restricted there
+ * (control points rounded to FP32).  Every path of the result opens and
+ * ends with an empty closed subpath (they draw nothing).  The returned
+ * scene expands like any other; sx_scene_dash_ms gives the device time of
+ * the dashing passes.  Synchronous.  Errors: those of sx_scene_encode, and
+ * SX_EINVAL for a null table, count > 32, a negative or non-finite value or
+ * a non-finite offset. */
+int sx_scene_encode_dashed(sx_ctx *ctx, const sx_paths *paths, const sx_style *styles, const sx_dash *dashes,
+                           uint32_t n_styles, const sx_affine *xforms, uint32_t n_xforms, void *stream,
+                           sx_scene **out);
+/* Device milliseconds of the dashing passes of a dashed scene (0 otherwise). */
+int sx_scene_dash_ms(const sx_scene *scene, float *ms);
+
 /* Release a scene (waits for work queued on the scene's last stream). */
 int sx_scene_release(sx_ctx *ctx, sx_scene *scene);
 /* Sizes of an encoded scene (any pointer may be NULL). */

@@ -53,6 +53,10 @@ DENSITY_APPROX, DENSITY_NEWTON = 0, 1
 CONSTANTS_VERSION = 1
 
 
+class _Dash(C.Structure):
+    _fields_ = [("array", C.c_void_p), ("count", C.c_uint32), ("offset", C.c_float)]
+
+
 class _Tuning(C.Structure):
     _fields_ = [("piece_waves", C.c_uint32), ("chunk_k", C.c_uint32), ("bisect_range", C.c_uint32),
                 ("bisect_waves", C.c_uint32)]
@@ -84,6 +88,9 @@ def lib():
                 "sx_version": (C.c_char_p, []),
                 "sx_scene_encode": (C.c_int, [vp, C.POINTER(_Paths), vp, u32, vp, u32, vp, C.POINTER(vp)]),
                 "sx_scene_release": (C.c_int, [vp, vp]),
+                "sx_scene_encode_dashed": (C.c_int, [vp, C.POINTER(_Paths), vp, vp, u32, vp, u32, vp,
+                                                     C.POINTER(vp)]),
+                "sx_scene_dash_ms": (C.c_int, [vp, C.POINTER(C.c_float)]),
                 "sx_scene_info": (C.c_int, [vp, vp, vp, vp, vp, vp]),
                 "sx_scene_download": (C.c_int, [vp, vp, vp, vp]),
                 "sx_expand": (C.c_int, [vp, vp, C.c_float, C.c_int, vp, u64, C.POINTER(u64), vp]),
@@ -136,6 +143,12 @@ class Scene:
         lib().sx_scene_info(C.c_void_p(handle), C.byref(nt), C.byref(npt), C.byref(np_), C.byref(ns), C.byref(nx))
         self.n_tags, self.n_pts, self.n_paths = nt.value, npt.value, np_.value
         self.n_styles, self.n_xforms = ns.value, nx.value
+
+    def dash_ms(self) -> float:
+        """Device milliseconds of the dashing passes (0 for an undashed scene)."""
+        v = C.c_float()
+        lib().sx_scene_dash_ms(C.c_void_p(self.h), C.byref(v))
+        return float(v.value)
 
     def release(self):
         if self.h:
@@ -206,9 +219,25 @@ class Context:
                    keep["pt_off"].ctypes.data, keep["style_ix"].ctypes.data, keep["xform_ix"].ctypes.data,
                    scene.n_paths)
         out = C.c_void_p()
-        rc = lib().sx_scene_encode(C.c_void_p(self.h), C.byref(p), keep["styles"].ctypes.data, len(keep["styles"]),
-                                   keep["xforms"].ctypes.data, len(keep["xforms"]), _stream_ptr(stream), C.byref(out))
-        self._check(rc, "sx_scene_encode")
+        if scene.dashes is not None:
+            # per style: its pattern (None: solid)
+            n = len(keep["styles"])
+            arrs = [np.ascontiguousarray((scene.dashes[k][0] if k < len(scene.dashes) and scene.dashes[k] is not None
+                                          else np.zeros(0)), np.float32) for k in range(n)]
+            tab = (_Dash * max(1, n))()
+            for k in range(n):
+                d = scene.dashes[k] if k < len(scene.dashes) else None
+                tab[k] = _Dash(arrs[k].ctypes.data if len(arrs[k]) else None, len(arrs[k]),
+                               float(d[1]) if d is not None else 0.0)
+            rc = lib().sx_scene_encode_dashed(C.c_void_p(self.h), C.byref(p), keep["styles"].ctypes.data, tab, n,
+                                              keep["xforms"].ctypes.data, len(keep["xforms"]), _stream_ptr(stream),
+                                              C.byref(out))
+            self._check(rc, "sx_scene_encode_dashed")
+        else:
+            rc = lib().sx_scene_encode(C.c_void_p(self.h), C.byref(p), keep["styles"].ctypes.data,
+                                       len(keep["styles"]), keep["xforms"].ctypes.data, len(keep["xforms"]),
+                                       _stream_ptr(stream), C.byref(out))
+            self._check(rc, "sx_scene_encode")
         return Scene(self, out.value, scene)
 
     def expand_into(self, scene: Scene, out_ptr: int, capacity_bytes: int, tolerance: float, mode: int,

@@ -70,6 +70,7 @@ struct sx_scene {
     // output estimate (host)
     unsigned long long* d_soup_n = nullptr;
     std::vector<SoupTerm> est;  // one per tag (see soup_terms)
+    float dash_ms = 0.0f;        // device time of the dashing passes (dashed scenes)
 };
 
 struct sx_batch {
@@ -530,8 +531,9 @@ static void soup_terms(const sx::HostEncoding& enc, const sx_style* styles, cons
     }
 }
 
-int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, uint32_t n_styles,
-                    const sx_affine* xforms, uint32_t n_xforms, void* stream, sx_scene** out) {
+static int encode_impl(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, uint32_t n_styles,
+                       const sx_affine* xforms, uint32_t n_xforms, void* stream, sx_scene** out,
+                       std::vector<uint32_t>* style_stream) {
     if (!ctx || !out) return SX_EINVAL;
     *out = nullptr;
     if (!paths || (paths->n_paths && (!paths->verbs || !paths->verb_off || !paths->pts || !paths->pt_off ||
@@ -607,8 +609,163 @@ int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, 
         return hip_fail(ctx, e, "scene upload");
     }
     soup_terms(enc, styles, xforms, s->est);
+    if (style_stream) *style_stream = enc.style_stream;
     s->last_stream = st;
     *out = s;
+    return SX_OK;
+}
+
+int sx_scene_encode(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, uint32_t n_styles,
+                    const sx_affine* xforms, uint32_t n_xforms, void* stream, sx_scene** out) {
+    return encode_impl(ctx, paths, styles, n_styles, xforms, n_xforms, stream, out, nullptr);
+}
+
+int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* styles, const sx_dash* dashes,
+                           uint32_t n_styles, const sx_affine* xforms, uint32_t n_xforms, void* stream,
+                           sx_scene** out) {
+    if (!ctx || !out) return SX_EINVAL;
+    *out = nullptr;
+    if (n_styles && !dashes) return fail(ctx, SX_EINVAL, "null dash table");
+    // the patterns on the 2^-24 grid, per user style (an odd array repeats once)
+    std::vector<std::vector<int64_t>> pats(n_styles);
+    std::vector<int64_t> phases(n_styles, 0), periods(n_styles, 0);
+    for (uint32_t k = 0; k < n_styles; k++) {
+        const sx_dash& d = dashes[k];
+        if (d.count > 32u || (d.count && !d.array) || !std::isfinite(d.offset))
+            return fail(ctx, SX_EINVAL, "bad dash pattern");
+        if (styles && (styles[k].flags & SX_STYLE_FILL)) continue;  // fills are not dashed
+        const uint32_t m = (d.count & 1u) ? 2u * d.count : d.count;
+        int64_t period = 0;
+        for (uint32_t j = 0; j < m; j++) {
+            const float v = d.array[j % d.count];
+            if (!(v >= 0.0f) || !std::isfinite(v)) return fail(ctx, SX_EINVAL, "bad dash pattern");
+            pats[k].push_back(sx::dash_fix((double)v));
+            period += pats[k].back();
+        }
+        if (period <= 0) {
+            pats[k].clear();  // nothing to dash: solid
+            continue;
+        }
+        int64_t ph = sx::dash_fix((double)d.offset) % period;
+        phases[k] = ph < 0 ? ph + period : ph;
+        periods[k] = period;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<uint32_t> sstream;
+    sx_scene* src = nullptr;
+    int r = encode_impl(ctx, paths, styles, n_styles, xforms, n_xforms, stream, &src, &sstream);
+    if (r != SX_OK) return r;
+    const uint32_t n = src->n_tags;
+    // per style entry of the scene: its user style's pattern
+    std::vector<sx::DashDesc> desc(sstream.size());
+    std::vector<int64_t> pat;
+    for (size_t e = 0; e < sstream.size(); e++) {
+        const uint32_t k = sstream[e];
+        desc[e] = sx::DashDesc{(uint32_t)pat.size(), (uint32_t)pats[k].size(), periods[k], phases[k]};
+        pat.insert(pat.end(), pats[k].begin(), pats[k].end());
+    }
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t x) {
+        if (e == hipSuccess) e = x;
+    };
+    sx::DashDesc* d_desc = nullptr;
+    int64_t* d_pat = nullptr;
+    uint64_t *d_len = nullptr, *d_cum = nullptr, *d_sub = nullptr, *d_otag = nullptr, *d_opt = nullptr;
+    uint32_t* d_subix = nullptr;
+    uint2* d_cnt = nullptr;
+    void *ctl = nullptr, *sts0 = nullptr, *sts1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    sx_scene* dst = nullptr;
+    uint64_t tot[2] = {0, 0}, tot_p[2] = {0, 0};
+    const size_t nn = (size_t)n + 2;
+    A(dalloc(&d_desc, std::max<size_t>(desc.size(), 1) * sizeof(sx::DashDesc)));
+    A(dalloc(&d_pat, std::max<size_t>(pat.size(), 1) * sizeof(int64_t)));
+    A(dalloc(&d_len, nn * sizeof(uint64_t)));
+    A(dalloc(&d_cum, nn * sizeof(uint64_t)));
+    A(dalloc(&d_sub, nn * sizeof(uint64_t)));
+    A(dalloc(&d_otag, nn * sizeof(uint64_t)));
+    A(dalloc(&d_opt, nn * sizeof(uint64_t)));
+    A(dalloc(&d_subix, nn * sizeof(uint32_t)));
+    A(dalloc(&d_cnt, nn * sizeof(uint2)));
+    A(dalloc(&ctl, 2 * sx::scan_ctl_bytes()));
+    A(dalloc(&sts0, sx::scan_status_bytes(n)));
+    A(dalloc(&sts1, sx::scan_status_bytes(n)));
+    A(hipEventCreate(&ev0));
+    A(hipEventCreate(&ev1));
+    if (e == hipSuccess && !desc.empty())
+        e = hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(sx::DashDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !pat.empty())
+        e = hipMemcpyAsync(d_pat, pat.data(), pat.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
+    A(hipMemsetAsync(ctl, 0, 2 * sx::scan_ctl_bytes(), st));
+    A(hipMemsetAsync(sts0, 0, sx::scan_status_bytes(n), st));
+    A(hipMemsetAsync(sts1, 0, sx::scan_status_bytes(n), st));
+    char* ctl1 = (char*)ctl + sx::scan_ctl_bytes();
+    if (e == hipSuccess && n)
+        e = sx::launch_scan_tags(src->d_tags, n, src->d_mon, ctl_block(src, 0), src->d_status_tags, nullptr, st);
+    A(hipEventRecord(ev0, st));
+    if (e == hipSuccess)
+        e = sx::launch_dash(view(src), d_desc, d_pat, d_len, d_cum, d_subix, d_sub, d_cnt, d_otag, d_opt, ctl, sts0,
+                            ctl1, sts1, 0, nullptr, nullptr, st);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(&tot[0], d_otag + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(&tot_p[0], d_opt + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    A(hipStreamSynchronize(st));
+    if (e == hipSuccess && (tot[0] > UINT32_MAX - 64 || tot_p[0] > UINT32_MAX)) {
+        r = fail(ctx, SX_EINVAL, "dashed scene exceeds 32-bit stream sizes");
+    } else if (e == hipSuccess) {
+        dst = new (std::nothrow) sx_scene();
+        if (!dst) e = hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess && r == SX_OK) {
+        dst->ctx = ctx;
+        dst->n_tags = (uint32_t)tot[0];
+        dst->n_pts = (uint32_t)tot_p[0];
+        dst->n_paths = src->n_paths;
+        dst->n_styles = src->n_styles;
+        dst->n_xforms = src->n_xforms;
+        e = reserve_scene(dst, dst->n_tags, dst->n_pts, dst->n_styles, dst->n_xforms, dst->n_paths, st);
+        if (e == hipSuccess && n)
+            e = sx::launch_dash(view(src), d_desc, d_pat, d_len, d_cum, d_subix, d_sub, d_cnt, d_otag, d_opt, ctl,
+                                sts0, ctl1, sts1, 1, dst->d_tags, dst->d_pts, st);
+        A(hipEventRecord(ev1, st));
+        if (src->n_styles)
+            A(hipMemcpyAsync(dst->d_styles, src->d_styles, src->n_styles * sizeof(sx::StyleD),
+                             hipMemcpyDeviceToDevice, st));
+        if (src->n_xforms)
+            A(hipMemcpyAsync(dst->d_xforms, src->d_xforms, src->n_xforms * 6 * sizeof(float), hipMemcpyDeviceToDevice,
+                             st));
+        if (src->n_paths)
+            A(hipMemcpyAsync(dst->d_path_map, src->d_path_map, src->n_paths * sizeof(uint32_t),
+                             hipMemcpyDeviceToDevice, st));
+        A(hipStreamSynchronize(st));
+        if (e == hipSuccess) (void)hipEventElapsedTime(&dst->dash_ms, ev0, ev1);
+    }
+    dfree(d_desc);
+    dfree(d_pat);
+    dfree(d_len);
+    dfree(d_cum);
+    dfree(d_sub);
+    dfree(d_otag);
+    dfree(d_opt);
+    dfree(d_subix);
+    dfree(d_cnt);
+    dfree(ctl);
+    dfree(sts0);
+    dfree(sts1);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    free_scene(src);
+    if (e != hipSuccess || r != SX_OK) {
+        free_scene(dst);
+        return r != SX_OK ? r : hip_fail(ctx, e, "dashed encoding");
+    }
+    dst->last_stream = st;
+    *out = dst;
+    return SX_OK;
+}
+
+int sx_scene_dash_ms(const sx_scene* s, float* ms) {
+    if (!s || !ms) return SX_EINVAL;
+    *ms = s->dash_ms;
     return SX_OK;
 }
 

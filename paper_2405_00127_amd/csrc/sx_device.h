@@ -1733,4 +1733,239 @@ SX_FN uint32_t code_t0u(uint32_t code) { return code >> 6; }
 SX_FN uint32_t code_depth(uint32_t code) { return code & 31u; }
 SX_FN bool code_pivot(uint32_t code) { return (code & 32u) != 0u; }
 
+
+// ------------------------------------------------------------- dashing
+// Dash patterns (Sections 1 and 9.3) cut a stroke's subpaths into dashes,
+// each then stroked as an open subpath.  Lengths are measured in the path's
+// own units by 16 panels of 8-node Gauss-Legendre of |B'(t)| and kept on a
+// grid of 2^-24 units (64-bit integers), so prefix sums over a subpath are
+// exact and order-free; a dash boundary inside a segment sits at the
+// parameter where the panels' partial integral reaches it (Newton steps kept
+// inside the panel), and the dash's part of the segment is the segment
+// restricted to that parameter range (blossom), rounded to FP32.
+constexpr int kDashPanels = 16;
+constexpr double kDashGrid = 16777216.0;  // 2^24
+// per style entry: pattern values pat[off .. off + n) (n even; 0 = solid),
+// their sum and the offset, on the grid
+struct DashDesc {
+    uint32_t off, n;
+    int64_t period, phase;
+};
+
+// |B'(t)| of the degree-c Bezier P[0..c]
+SX_FN double bez_speed_d(const D2* P, int c, double t) {
+    const double mt = 1.0 - t;
+    double dx, dy;
+    if (c == 1) {
+        dx = P[1].x - P[0].x;
+        dy = P[1].y - P[0].y;
+    } else if (c == 2) {
+        dx = 2.0 * (mt * (P[1].x - P[0].x) + t * (P[2].x - P[1].x));
+        dy = 2.0 * (mt * (P[1].y - P[0].y) + t * (P[2].y - P[1].y));
+    } else {
+        const double a = mt * mt, b = 2.0 * t * mt, e = t * t;
+        dx = 3.0 * (a * (P[1].x - P[0].x) + b * (P[2].x - P[1].x) + e * (P[3].x - P[2].x));
+        dy = 3.0 * (a * (P[1].y - P[0].y) + b * (P[2].y - P[1].y) + e * (P[3].y - P[2].y));
+    }
+    return hypot(dx, dy);
+}
+// 8-node Gauss-Legendre of |B'| over [a, b]
+SX_HD inline double speed_gl8_d(const D2* P, int c, double a, double b) {
+    const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
+    const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+    const double m = 0.5 * (a + b), h = 0.5 * (b - a);
+    double sum = 0.0;
+    for (int i = 0; i < 4; i++) sum += gw[i] * (bez_speed_d(P, c, m - h * gx[i]) + bez_speed_d(P, c, m + h * gx[i]));
+    return sum * h;
+}
+// arc length (sum of the panels' integrals, panel[k] each)
+SX_HD inline double dash_len_d(const D2* P, int c, double* panel) {
+    double total = 0.0;
+    for (int k = 0; k < kDashPanels; k++) {
+        panel[k] = speed_gl8_d(P, c, (double)k / kDashPanels, (double)(k + 1) / kDashPanels);
+        total += panel[k];
+    }
+    return total;
+}
+SX_FN int64_t dash_fix(double v) { return (int64_t)llround(v * kDashGrid); }
+SX_FN int64_t floor_div64(int64_t a, int64_t b) {
+    const int64_t q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+// parameter where the panels' partial integral reaches s
+SX_HD inline double dash_t_d(const D2* P, int c, const double* panel, double s) {
+    double acc = 0.0;
+    int k = 0;
+    while (k < kDashPanels - 1 && acc + panel[k] <= s) acc += panel[k++];
+    double lo = (double)k / kDashPanels, hi = (double)(k + 1) / kDashPanels;
+    const double t0 = lo, rest = s - acc;
+    double t = lo + (hi - lo) * fmin(fmax(panel[k] > 0.0 ? rest / panel[k] : 0.5, 0.0), 1.0);
+    for (int it = 0; it < 60; it++) {
+        const double g = speed_gl8_d(P, c, t0, t) - rest;
+        if (g < 0.0) lo = t;
+        else hi = t;
+        const double d = bez_speed_d(P, c, t);
+        double tn = d > 0.0 ? t - g / d : 0.5 * (lo + hi);
+        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (tn == t || !(hi > lo)) break;
+        t = tn;
+    }
+    return t;
+}
+// the segment restricted to [ta, tb], control points rounded to FP32 (its
+// own end points where ta = 0 or tb = 1)
+SX_HD inline void dash_part_d(const D2* P, int c, double ta, double tb, float* out) {
+    for (int j = 0; j <= c; j++) {
+        D2 q[4];
+        for (int l = 0; l <= c; l++) q[l] = P[l];
+        for (int l = 0; l < c; l++) {
+            const double u = (l < c - j) ? ta : tb;
+            for (int m = 0; m < c - l; m++) q[m] = q[m] * (1.0 - u) + q[m + 1] * u;
+        }
+        D2 r = q[0];
+        if (j == 0 && ta == 0.0) r = P[0];
+        if (j == c && tb == 1.0) r = P[c];
+        out[2 * j] = (float)r.x;
+        out[2 * j + 1] = (float)r.y;
+    }
+}
+// The dash intervals [a, b) (clipped to the subpath [0, Stot]) meeting the
+// segment (S0, S1], in order: f(lo, hi, a, b) for each, lo < hi.
+template <class F>
+SX_HD void dash_parts(int64_t S0, int64_t S1, int64_t Stot, const int64_t* pat, uint32_t n, int64_t period,
+                      int64_t phase, F f) {
+    const int64_t mlo = floor_div64(S0 + phase, period) - 1, mhi = floor_div64(S1 + phase, period) + 1;
+    for (int64_t m = mlo; m <= mhi; m++) {
+        int64_t cpos = 0;
+        for (uint32_t k = 0; k < n; k++) {
+            int64_t a = m * period + cpos - phase, b = a + pat[k];
+            cpos += pat[k];
+            if (k & 1u) continue;  // a gap
+            if (a < 0) a = 0;
+            if (b > Stot) b = Stot;
+            const int64_t lo = a > S0 ? a : S0, hi = b < S1 ? b : S1;
+            if (lo < hi) f(lo, hi, a, b);
+        }
+    }
+}
+
+
+struct DashIn {
+    SceneView sv;
+    const DashDesc* desc;       // per style entry
+    const int64_t* pat;         // pattern values on the grid
+    const uint64_t* len;        // per tag: grid length of a dashed segment, else 0
+    const uint64_t* cum;        // per tag: exclusive prefix of len
+    const uint32_t* subix;      // per tag: subpaths ended before it
+    const uint64_t* sub_start;  // per subpath: cum at its first tag
+};
+
+// The dashed encoding's tags and points of source tag i: counted (Write
+// false) or written at tags_out[t0 ..], pts_out[p0 ..] (Write true).
+template <bool Write>
+SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts_out,
+                         uint64_t t0, uint64_t p0, uint32_t& nt, uint32_t& np) {
+    const SceneView& sv = in.sv;
+    auto put_pt = [&](float x, float y) {
+        if (Write) pts_out[p0 + np] = make_float2(x, y);
+        np++;
+    };
+    auto put_tag = [&](uint32_t t) {
+        if (Write) tags_out[t0 + nt] = (uint8_t)t;
+        nt++;
+    };
+    auto put_empty = [&](uint32_t extra, float2 p) {
+        put_pt(p.x, p.y);
+        put_pt(p.x, p.y);
+        put_pt(p.x + 1.0f, p.y);
+        put_tag(2u | kTagEnd | kTagF32 | kTagClosed | extra);
+    };
+    const uint32_t tag = sv.tags[i];
+    const uint32_t off = sv.mon[i];
+    const uint32_t sty = sv.mon[2 * (size_t)sv.mon_stride + i];
+    const float2* D = sv.pts + off;
+    const bool first_of_path = i == 0 || (sv.tags[i - 1] & kTagPath);
+    const bool first_of_sub = i == 0 || (sv.tags[i - 1] & kTagEnd);
+    if (first_of_path) put_empty(tag & (kTagStyle | kTagXform), D[0]);
+    const DashDesc dd = sty < sv.n_styles ? in.desc[sty] : DashDesc{0, 0, 0, 0};
+    if (dd.n == 0) {
+        // a solid stroke or a fill: the tag and its points as they are
+        if (first_of_sub) put_pt(D[0].x, D[0].y);
+        const uint32_t cnt = tag & kTagCount;
+        for (uint32_t j = 1; j <= cnt; j++) put_pt(D[j].x, D[j].y);
+        put_tag(tag & ~(kTagPath | kTagStyle | kTagXform));
+    } else if (!(tag & kTagEnd)) {
+        const int c = (int)(tag & kTagCount);
+        D2 P[4];
+        for (int j = 0; j <= c; j++) P[j] = d2((double)D[j].x, (double)D[j].y);
+        double panel[kDashPanels];
+        (void)dash_len_d(P, c, panel);
+        const uint32_t k = in.subix[i];
+        const int64_t base = (int64_t)in.sub_start[k];
+        const int64_t S0 = (int64_t)in.cum[i] - base, S1 = S0 + (int64_t)in.len[i];
+        const int64_t Stot = (int64_t)in.sub_start[k + 1] - base;
+        const bool last = (sv.tags[i + 1] & kTagEnd) != 0;
+        const int64_t* pat = in.pat + dd.off;
+        // the first part of a dash in segment j (points rounded as its writer rounds them)
+        auto part_of = [&](const D2* Q, int cq, const double* pq, int64_t Q0, int64_t Q1, int64_t lo, int64_t hi,
+                           float* out) {
+            const double ta = lo == Q0 ? 0.0 : dash_t_d(Q, cq, pq, (double)(lo - Q0) / kDashGrid);
+            double tb = hi == Q1 ? 1.0 : dash_t_d(Q, cq, pq, (double)(hi - Q0) / kDashGrid);
+            if (tb < ta) tb = ta;
+            dash_part_d(Q, cq, ta, tb, out);
+        };
+        auto start_dir = [&](const float* part, int cq, float2& s, float2& d) {
+            s = make_float2(part[0], part[1]);
+            d = make_float2(s.x + 1.0f, s.y);
+            for (int q = 1; q <= cq; q++)
+                if (!(part[2 * q] == s.x && part[2 * q + 1] == s.y)) {
+                    d = make_float2(part[2 * q], part[2 * q + 1]);
+                    break;
+                }
+        };
+        dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
+            float part[8];
+            part_of(P, c, panel, S0, S1, lo, hi, part);
+            float2 ds, dv;
+            if (a >= S0) {
+                put_pt(part[0], part[1]);
+            }
+            for (int q = 1; q <= c; q++) put_pt(part[2 * q], part[2 * q + 1]);
+            put_tag((uint32_t)c | kTagF32);
+            if (b <= S1 || last) {
+                if (a >= S0) {
+                    start_dir(part, c, ds, dv);
+                } else if (Write) {
+                    // the dash started in an earlier segment of this subpath:
+                    // the last tag at or before its start position
+                    const uint64_t pos = (uint64_t)(base + a);
+                    uint32_t l = 0, h = i;  // cum[l] <= pos < ... ; search the last j <= i with cum[j] <= pos
+                    while (l < h) {
+                        const uint32_t mid = l + (h - l + 1) / 2;
+                        if (in.cum[mid] <= pos) l = mid;
+                        else h = mid - 1;
+                    }
+                    const uint32_t j = l;
+                    const uint32_t tj = sv.tags[j];
+                    const int cj = (int)(tj & kTagCount);
+                    const float2* Dj = sv.pts + sv.mon[j];
+                    D2 Q[4];
+                    for (int q = 0; q <= cj; q++) Q[q] = d2((double)Dj[q].x, (double)Dj[q].y);
+                    double pj[kDashPanels];
+                    (void)dash_len_d(Q, cj, pj);
+                    const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
+                    float pt2[8];
+                    part_of(Q, cj, pj, Q0, Q1, a, b < Q1 ? b : Q1, pt2);
+                    start_dir(pt2, cj, ds, dv);
+                }
+                put_pt(ds.x, ds.y);
+                put_pt(dv.x, dv.y);
+                put_tag(2u | kTagEnd | kTagF32);
+            }
+        });
+    }
+    // (a dashed stroke's own markers give way to its dashes' markers)
+    if (tag & kTagPath) put_empty(kTagPath, D[1]);
+}
+
 }  // namespace sx

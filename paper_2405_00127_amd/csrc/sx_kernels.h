@@ -88,4 +88,14 @@ hipError_t launch_finish(const uint64_t* roff, const uint64_t* n_slots_dev, uint
 hipError_t launch_tag_records(const uint64_t* base, const uint64_t* roff, uint64_t slot_cap, uint32_t n_tags,
                               uint32_t* counts, uint64_t* offs, hipStream_t s);
 
+// Dashing: phase 0 runs the measuring pass, the two scans and the count
+// pass (otag[n], opt[n] then hold the dashed encoding's tag and point
+// totals); phase 1 writes the dashed tags and points.  Scratch per source
+// tag: len, cum (n + 1), subix (n + 1), cnt; sub_start (n + 2); otag, opt
+// (n + 1); ctl / st: two look-back scan control and status blocks.
+hipError_t launch_dash(const SceneView& sv, const DashDesc* desc, const int64_t* pat, uint64_t* len, uint64_t* cum,
+                       uint32_t* subix, uint64_t* sub_start, uint2* cnt, uint64_t* otag, uint64_t* opt, void* ctl0,
+                       void* st0, void* ctl1, void* st1, int phase, uint8_t* tags_out, float2* pts_out,
+                       hipStream_t s);
+
 }  // namespace sx

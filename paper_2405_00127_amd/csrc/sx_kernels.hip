@@ -1090,4 +1090,142 @@ hipError_t launch_tag_records(const uint64_t* base, const uint64_t* roff, uint64
 size_t scan_status_bytes(uint32_t n) { return (size_t)scan_tiles(n > 0 ? n : 1) * sizeof(TileStatus); }
 size_t scan_ctl_bytes() { return sizeof(ScanCtl); }
 
+
+// ------------------------------------------------------------- dashing
+// The dashed encoding of a scene (dash patterns of Sections 1 and 9.3), in
+// five passes over the source tags: the grid length of every dashed segment;
+// an exclusive scan of (length, subpath ends) giving each tag its position
+// along the scene and its subpath; each subpath's start position; per tag
+// the tags and points it contributes to the dashed encoding; a scan of
+// those counts; and the write pass.  Every path of the result opens with an
+// empty closed subpath carrying its style and transform bits and ends with
+// one carrying its path end bit; each dash is an open subpath ([start point]
+// [parts of segments][stroke cap marker]); solid strokes and fills are
+// copied.
+__global__ __launch_bounds__(256) void dash_measure_kernel(SceneView sv, const DashDesc* __restrict__ desc,
+                                                           uint64_t* __restrict__ len) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sv.n_tags) return;
+    const uint32_t tag = sv.tags[i];
+    uint64_t q = 0;
+    if (!(tag & kTagEnd)) {
+        const uint32_t sty = sv.mon[2 * (size_t)sv.mon_stride + i];
+        if (sty < sv.n_styles && desc[sty].n) {
+            const int c = (int)(tag & kTagCount);
+            const float2* D = sv.pts + sv.mon[i];
+            D2 P[4];
+            for (int j = 0; j <= c; j++) P[j] = d2((double)D[j].x, (double)D[j].y);
+            double panel[kDashPanels];
+            q = (uint64_t)dash_fix(dash_len_d(P, c, panel));
+        }
+    }
+    len[i] = q;
+}
+
+// exclusive scan of (len, subpath end) over the tags; cum[n], subix[n] = totals
+__global__ __launch_bounds__(kScanBlock) void dash_scan_kernel(const uint8_t* __restrict__ tags,
+                                                               const uint64_t* __restrict__ len, uint32_t n,
+                                                               uint64_t* __restrict__ cum,
+                                                               uint32_t* __restrict__ subix, ScanCtl* ctl,
+                                                               TileStatus* st) {
+    auto load = [&](uint64_t base, Pair* item) {
+#pragma unroll
+        for (int j = 0; j < kTagItems; j++)
+            item[j] = (base + j < n) ? Pair{len[base + j], (tags[base + j] & kTagEnd) ? 1ull : 0ull} : Pair{0, 0};
+    };
+    auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
+#pragma unroll
+        for (int j = 0; j < kTagItems; j++) {
+            const Pair ex = j > 0 ? pre + incl[j - 1] : pre;
+            if (base + j < n) {
+                cum[base + j] = ex.a;
+                subix[base + j] = (uint32_t)ex.b;
+            }
+            if (base + j == (uint64_t)n - 1u) {
+                cum[n] = pre.a + incl[j].a;
+                subix[n] = (uint32_t)(pre.b + incl[j].b);
+            }
+        }
+    };
+    scan_tile<kTagItems>(load, store, n, ctl, st);
+}
+
+__global__ __launch_bounds__(256) void dash_sub_start_kernel(const uint8_t* __restrict__ tags,
+                                                             const uint64_t* __restrict__ cum,
+                                                             const uint32_t* __restrict__ subix, uint32_t n,
+                                                             uint64_t* __restrict__ sub_start) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0) sub_start[0] = 0;
+    if (tags[i] & kTagEnd) sub_start[subix[i] + 1u] = cum[i];
+}
+
+__global__ __launch_bounds__(256) void dash_count_kernel(DashIn in, uint2* __restrict__ cnt) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= in.sv.n_tags) return;
+    uint32_t nt = 0, np = 0;
+    dash_tag<false>(in, i, nullptr, nullptr, 0, 0, nt, np);
+    cnt[i] = make_uint2(nt, np);
+}
+
+// exclusive scan of (tags, points) counts; otag[n], opt[n] = totals
+__global__ __launch_bounds__(kScanBlock) void dash_off_scan_kernel(const uint2* __restrict__ cnt, uint32_t n,
+                                                                   uint64_t* __restrict__ otag,
+                                                                   uint64_t* __restrict__ opt, ScanCtl* ctl,
+                                                                   TileStatus* st) {
+    auto load = [&](uint64_t base, Pair* item) {
+#pragma unroll
+        for (int j = 0; j < kTagItems; j++) {
+            const uint2 v = (base + j < n) ? cnt[base + j] : make_uint2(0u, 0u);
+            item[j] = Pair{v.x, v.y};
+        }
+    };
+    auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
+#pragma unroll
+        for (int j = 0; j < kTagItems; j++) {
+            const Pair ex = j > 0 ? pre + incl[j - 1] : pre;
+            if (base + j < n) {
+                otag[base + j] = ex.a;
+                opt[base + j] = ex.b;
+            }
+            if (base + j == (uint64_t)n - 1u) {
+                otag[n] = pre.a + incl[j].a;
+                opt[n] = pre.b + incl[j].b;
+            }
+        }
+    };
+    scan_tile<kTagItems>(load, store, n, ctl, st);
+}
+
+__global__ __launch_bounds__(256) void dash_write_kernel(DashIn in, const uint64_t* __restrict__ otag,
+                                                         const uint64_t* __restrict__ opt,
+                                                         uint8_t* __restrict__ tags_out, float2* __restrict__ pts_out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= in.sv.n_tags) return;
+    uint32_t nt = 0, np = 0;
+    dash_tag<true>(in, i, tags_out, pts_out, otag[i], opt[i], nt, np);
+}
+
+hipError_t launch_dash(const SceneView& sv, const DashDesc* desc, const int64_t* pat, uint64_t* len, uint64_t* cum,
+                       uint32_t* subix, uint64_t* sub_start, uint2* cnt, uint64_t* otag, uint64_t* opt, void* ctl0,
+                       void* st0, void* ctl1, void* st1, int phase, uint8_t* tags_out, float2* pts_out,
+                       hipStream_t s) {
+    const uint32_t n = sv.n_tags;
+    if (n == 0) return hipSuccess;
+    const uint32_t g = (n + 255u) / 256u;
+    DashIn in{sv, desc, pat, len, cum, subix, sub_start};
+    if (phase == 0) {
+        dash_measure_kernel<<<g, 256, 0, s>>>(sv, desc, len);
+        dash_scan_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(sv.tags, len, n, cum, subix, (ScanCtl*)ctl0,
+                                                               (TileStatus*)st0);
+        dash_sub_start_kernel<<<g, 256, 0, s>>>(sv.tags, cum, subix, n, sub_start);
+        dash_count_kernel<<<g, 256, 0, s>>>(in, cnt);
+        dash_off_scan_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(cnt, n, otag, opt, (ScanCtl*)ctl1,
+                                                                   (TileStatus*)st1);
+    } else {
+        dash_write_kernel<<<g, 256, 0, s>>>(in, otag, opt, tags_out, pts_out);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace sx
