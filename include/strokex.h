@@ -187,8 +187,9 @@ typedef struct {
  * ends with an empty closed subpath (they draw nothing).  The returned
  * scene expands like any other; sx_scene_dash_ms gives the device time of
  * the dashing passes.  Synchronous.  Errors: those of sx_scene_encode, and
- * SX_EINVAL for a null table, count > 32, a negative or non-finite value or
- * a non-finite offset. */
+ * SX_EINVAL for a null table, count > 32, a negative or non-finite value, a
+ * non-finite offset, or a pattern whose total length is positive but below
+ * 2^-10 units. */
 int sx_scene_encode_dashed(sx_ctx *ctx, const sx_paths *paths, const sx_style *styles, const sx_dash *dashes,
                            uint32_t n_styles, const sx_affine *xforms, uint32_t n_xforms, void *stream,
                            sx_scene **out);

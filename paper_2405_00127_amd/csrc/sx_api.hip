@@ -646,6 +646,9 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
             pats[k].clear();  // nothing to dash: solid
             continue;
         }
+        // a period below 2^-10 units would cut every unit of length into
+        // thousands of dashes (and as many loop turns per segment)
+        if (period < ((int64_t)1 << 14)) return fail(ctx, SX_EINVAL, "dash pattern period below 2^-10 units");
         int64_t ph = sx::dash_fix((double)d.offset) % period;
         phases[k] = ph < 0 ? ph + period : ph;
         periods[k] = period;
