@@ -183,7 +183,9 @@ typedef struct {
  * of 8-node Gauss-Legendre of |B'(t)| per segment, on a grid of 2^-24
  * units; a dash ends inside a segment at the parameter where that integral
  * reaches it, and its part of the segment is the segment restricted there
- * (control points rounded to FP32).  Every path of the result opens and
+ * (control points rounded to FP32); a part whose rounded control points all
+ * coincide is left out, like a zero-length input segment, and a dash left
+ * without parts draws nothing.  Every path of the result opens and
  * ends with an empty closed subpath (they draw nothing).  The returned
  * scene expands like any other; sx_scene_dash_ms gives the device time of
  * the dashing passes.  Synchronous.  Errors: those of sx_scene_encode, and

@@ -645,8 +645,11 @@ double ox_f_newton_inv(double y, double lo, double hi) {
  *        carrying its path end bit (so that every path keeps its entries in
  *        the style, transform and path streams even when no dash falls on
  *        it); each dash is [start point][parts of segments][stroke cap
- *        marker (start, first control point that differs from it, else the
- *        start plus (1, 0))].
+ *        marker (start, first control point that differs from it)].  A part
+ *        whose rounded control points all equal its first point has no
+ *        extent and is left out, as the encoding leaves out zero-length
+ *        segments (G22); the dash starts at its first part with extent, and
+ *        a dash without one draws nothing.
  * Fills are not dashed. */
 #define OX_DASH_PANELS 16
 #define OX_DASH_GRID 16777216.0 /* 2^24 */
@@ -814,7 +817,7 @@ ox_enc *ox_encode_dashed(const ox_enc *src, const float *dash_arr, const uint32_
                         }
                     }
                     float ds_x = 0, ds_y = 0, dd_x = 0, dd_y = 0;
-                    int dash_open = 0;
+                    int dash_written = 0; /* the current dash has a part with extent */
                     for (uint32_t j = i; j < me; j++) {
                         uint32_t c = src->tags[j] & OX_TAG_COUNT;
                         v2 P[4];
@@ -841,20 +844,25 @@ ox_enc *ox_encode_dashed(const ox_enc *src, const float *dash_arr, const uint32_
                                 float part[8];
                                 bez_part(P, (int)c, ta, tb, part);
                                 if (enc_reserve(e, 2, c + 3)) goto oom;
-                                if (a >= S0) {
-                                    /* the dash starts here: its start point, and its tangent point (G14) */
-                                    dash_open = 1;
-                                    ds_x = part[0]; ds_y = part[1];
-                                    dd_x = ds_x + 1.0f; dd_y = ds_y;
-                                    for (uint32_t q = 1; q <= c; q++)
-                                        if (!(part[2 * q] == ds_x && part[2 * q + 1] == ds_y)) { dd_x = part[2 * q]; dd_y = part[2 * q + 1]; break; }
-                                    enc_pt(e, ds_x, ds_y);
+                                if (a >= S0) dash_written = 0; /* a new dash */
+                                /* the first control point that differs from the part's start */
+                                int qd = 0;
+                                for (uint32_t q = 1; q <= c && !qd; q++)
+                                    if (!(part[2 * q] == part[0] && part[2 * q + 1] == part[1])) qd = (int)q;
+                                if (qd) {
+                                    if (!dash_written) {
+                                        /* the dash's first part with extent: its start point, and its tangent point (G14) */
+                                        dash_written = 1;
+                                        ds_x = part[0]; ds_y = part[1];
+                                        dd_x = part[2 * qd]; dd_y = part[2 * qd + 1];
+                                        enc_pt(e, ds_x, ds_y);
+                                    }
+                                    for (uint32_t q = 1; q <= c; q++) enc_pt(e, part[2 * q], part[2 * q + 1]);
+                                    e->tags[e->n_tags++] = (uint8_t)(c | OX_TAG_F32);
                                 }
-                                for (uint32_t q = 1; q <= c; q++) enc_pt(e, part[2 * q], part[2 * q + 1]);
-                                e->tags[e->n_tags++] = (uint8_t)(c | OX_TAG_F32);
                                 if (b <= S1 || last) {
-                                    if (dash_open) enc_marker(e, 0, ds_x, ds_y, dd_x, dd_y);
-                                    dash_open = 0;
+                                    if (dash_written) enc_marker(e, 0, ds_x, ds_y, dd_x, dd_y);
+                                    dash_written = 0;
                                 }
                             }
                         }

@@ -677,7 +677,9 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
     uint32_t* d_subix = nullptr;
     uint2* d_cnt = nullptr;
     void *ctl = nullptr, *sts0 = nullptr, *sts1 = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // device time of the two dashing phases (the host reads the totals and
+    // allocates the result between them)
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     sx_scene* dst = nullptr;
     uint64_t tot[2] = {0, 0}, tot_p[2] = {0, 0};
     const size_t nn = (size_t)n + 2;
@@ -695,6 +697,8 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
     A(dalloc(&sts1, sx::scan_status_bytes(n)));
     A(hipEventCreate(&ev0));
     A(hipEventCreate(&ev1));
+    A(hipEventCreate(&ev2));
+    A(hipEventCreate(&ev3));
     if (e == hipSuccess && !desc.empty())
         e = hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(sx::DashDesc), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !pat.empty())
@@ -709,6 +713,7 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
     if (e == hipSuccess)
         e = sx::launch_dash(view(src), d_desc, d_pat, d_len, d_cum, d_subix, d_sub, d_cnt, d_otag, d_opt, ctl, sts0,
                             ctl1, sts1, 0, nullptr, nullptr, st);
+    A(hipEventRecord(ev1, st));
     if (e == hipSuccess && n) e = hipMemcpyAsync(&tot[0], d_otag + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess && n) e = hipMemcpyAsync(&tot_p[0], d_opt + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
     A(hipStreamSynchronize(st));
@@ -726,10 +731,11 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
         dst->n_styles = src->n_styles;
         dst->n_xforms = src->n_xforms;
         e = reserve_scene(dst, dst->n_tags, dst->n_pts, dst->n_styles, dst->n_xforms, dst->n_paths, st);
+        A(hipEventRecord(ev2, st));
         if (e == hipSuccess && n)
             e = sx::launch_dash(view(src), d_desc, d_pat, d_len, d_cum, d_subix, d_sub, d_cnt, d_otag, d_opt, ctl,
                                 sts0, ctl1, sts1, 1, dst->d_tags, dst->d_pts, st);
-        A(hipEventRecord(ev1, st));
+        A(hipEventRecord(ev3, st));
         if (src->n_styles)
             A(hipMemcpyAsync(dst->d_styles, src->d_styles, src->n_styles * sizeof(sx::StyleD),
                              hipMemcpyDeviceToDevice, st));
@@ -740,7 +746,10 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
             A(hipMemcpyAsync(dst->d_path_map, src->d_path_map, src->n_paths * sizeof(uint32_t),
                              hipMemcpyDeviceToDevice, st));
         A(hipStreamSynchronize(st));
-        if (e == hipSuccess) (void)hipEventElapsedTime(&dst->dash_ms, ev0, ev1);
+        float ms0 = 0.0f, ms1 = 0.0f;
+        if (e == hipSuccess && hipEventElapsedTime(&ms0, ev0, ev1) == hipSuccess &&
+            hipEventElapsedTime(&ms1, ev2, ev3) == hipSuccess)
+            dst->dash_ms = ms0 + ms1;
     }
     dfree(d_desc);
     dfree(d_pat);
@@ -756,6 +765,8 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
     dfree(sts1);
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    if (ev2) (void)hipEventDestroy(ev2);
+    if (ev3) (void)hipEventDestroy(ev3);
     free_scene(src);
     if (e != hipSuccess || r != SX_OK) {
         free_scene(dst);

@@ -533,7 +533,7 @@ SX_HD inline double dens_int_d(double a, double b) {
 // inverse of f_approx, branch by branch (Section 4.2)
 SX_HD inline double f_approx_inv_d(double y) {
     const double a = fabs(y);
-    const double b1 = sin(kC1 * 0.8) / kC1;
+    const double b1 = 0.7010707591262915;  // sin(0.8 c1) / c1: f_approx at 0.8
     const double b2 = kA2 * 0.125 + 0.25 * kPi;  // sqrt(8)/3 (1/4)^1.5 + pi/4
     const double b3 = 0.6406 * 2.1 * 2.1 - 0.81 * 2.1 + kC2;
     double r;
@@ -1914,50 +1914,86 @@ SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts
             if (tb < ta) tb = ta;
             dash_part_d(Q, cq, ta, tb, out);
         };
-        auto start_dir = [&](const float* part, int cq, float2& s, float2& d) {
-            s = make_float2(part[0], part[1]);
-            d = make_float2(s.x + 1.0f, s.y);
+        // the first control point of a part that differs from its start (0:
+        // the part has no extent and is left out, as the encoding leaves out
+        // zero-length segments)
+        auto extent_of = [](const float* part, int cq) {
             for (int q = 1; q <= cq; q++)
-                if (!(part[2 * q] == s.x && part[2 * q + 1] == s.y)) {
-                    d = make_float2(part[2 * q], part[2 * q + 1]);
+                if (!(part[2 * q] == part[0] && part[2 * q + 1] == part[1])) return q;
+            return 0;
+        };
+        // A dash that started in an earlier segment (at subpath position a <
+        // S0): whether one of its parts before this tag has extent and, when
+        // want_pt, the start and tangent points of the first such part.  Its
+        // start tag j is the last tag at or before position a; the tags
+        // between j and this one hold full parts (with extent) exactly when
+        // they have length.
+        auto earlier_extent = [&](int64_t a, int64_t b, bool want_pt, float2& ds, float2& dv) {
+            const uint64_t pos = (uint64_t)(base + a);
+            uint32_t l = 0, h = i;  // the last j < i with cum[j] <= pos (cum[i] > pos)
+            while (l < h) {
+                const uint32_t mid = l + (h - l + 1) / 2;
+                if (in.cum[mid] <= pos) l = mid;
+                else h = mid - 1;
+            }
+            const uint32_t j = l;
+            const uint64_t xj = in.cum[j] + in.len[j];  // where j's part ends
+            const bool between = xj < in.cum[i];
+            if (between && !want_pt) return true;
+            const uint32_t tj = sv.tags[j];
+            const int cj = (int)(tj & kTagCount);
+            const float2* Dj = sv.pts + sv.mon[j];
+            D2 Q[4];
+            for (int q = 0; q <= cj; q++) Q[q] = d2((double)Dj[q].x, (double)Dj[q].y);
+            double pj[kDashPanels];
+            (void)dash_len_d(Q, cj, pj);
+            const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
+            float pt2[8];
+            part_of(Q, cj, pj, Q0, Q1, a, b < Q1 ? b : Q1, pt2);
+            const int qj = extent_of(pt2, cj);
+            if (qj) {
+                ds = make_float2(pt2[0], pt2[1]);
+                dv = make_float2(pt2[2 * qj], pt2[2 * qj + 1]);
+                return true;
+            }
+            if (!between) return false;
+            // the first tag after j with length: the last k < i with cum[k] <= xj
+            uint32_t lk = j + 1, hk = i - 1;
+            while (lk < hk) {
+                const uint32_t mid = lk + (hk - lk + 1) / 2;
+                if (in.cum[mid] <= xj) lk = mid;
+                else hk = mid - 1;
+            }
+            const float2* Dk = sv.pts + sv.mon[lk];
+            const int ck = (int)(sv.tags[lk] & kTagCount);
+            ds = Dk[0];
+            dv = make_float2(Dk[0].x + 1.0f, Dk[0].y);  // (a full part always has extent)
+            for (int q = 1; q <= ck; q++)
+                if (!(Dk[q].x == Dk[0].x && Dk[q].y == Dk[0].y)) {
+                    dv = Dk[q];
                     break;
                 }
+            return true;
         };
         dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
             float part[8];
             part_of(P, c, panel, S0, S1, lo, hi, part);
-            float2 ds, dv;
-            if (a >= S0) {
-                put_pt(part[0], part[1]);
-            }
-            for (int q = 1; q <= c; q++) put_pt(part[2 * q], part[2 * q + 1]);
-            put_tag((uint32_t)c | kTagF32);
-            if (b <= S1 || last) {
-                if (a >= S0) {
-                    start_dir(part, c, ds, dv);
-                } else if (Write) {
-                    // the dash started in an earlier segment of this subpath:
-                    // the last tag at or before its start position
-                    const uint64_t pos = (uint64_t)(base + a);
-                    uint32_t l = 0, h = i;  // cum[l] <= pos < ... ; search the last j <= i with cum[j] <= pos
-                    while (l < h) {
-                        const uint32_t mid = l + (h - l + 1) / 2;
-                        if (in.cum[mid] <= pos) l = mid;
-                        else h = mid - 1;
-                    }
-                    const uint32_t j = l;
-                    const uint32_t tj = sv.tags[j];
-                    const int cj = (int)(tj & kTagCount);
-                    const float2* Dj = sv.pts + sv.mon[j];
-                    D2 Q[4];
-                    for (int q = 0; q <= cj; q++) Q[q] = d2((double)Dj[q].x, (double)Dj[q].y);
-                    double pj[kDashPanels];
-                    (void)dash_len_d(Q, cj, pj);
-                    const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
-                    float pt2[8];
-                    part_of(Q, cj, pj, Q0, Q1, a, b < Q1 ? b : Q1, pt2);
-                    start_dir(pt2, cj, ds, dv);
+            const int qd = extent_of(part, c);
+            const bool ends = b <= S1 || last;
+            float2 ds = make_float2(0.0f, 0.0f), dv = ds;
+            // an earlier part of this dash (in an earlier tag) had extent; its
+            // start and tangent points are needed only to write the marker here
+            const bool written = a < S0 && earlier_extent(a, b, Write && ends, ds, dv);
+            if (qd) {
+                if (!written) {
+                    put_pt(part[0], part[1]);
+                    ds = make_float2(part[0], part[1]);
+                    dv = make_float2(part[2 * qd], part[2 * qd + 1]);
                 }
+                for (int q = 1; q <= c; q++) put_pt(part[2 * q], part[2 * q + 1]);
+                put_tag((uint32_t)c | kTagF32);
+            }
+            if (ends && (written || qd)) {
                 put_pt(ds.x, ds.y);
                 put_pt(dv.x, dv.y);
                 put_tag(2u | kTagEnd | kTagF32);

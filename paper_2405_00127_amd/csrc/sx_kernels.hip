@@ -778,7 +778,7 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
 // Per item chunk, the FP32 per-point work: records at
 // roff[slot] + the chunk's position within its slot.
 template <bool Newton>
-__global__ __launch_bounds__(kRecBlock, 6) void record_kernel(SceneView sv, ItemWs ws, int arcs,
+__global__ __launch_bounds__(kRecBlock, Newton ? 3 : 6) void record_kernel(SceneView sv, ItemWs ws, int arcs,
                                                            const uint64_t* __restrict__ roff,
                                                            const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
                                                            float* __restrict__ out, uint64_t cap_records, XIncF xi) {

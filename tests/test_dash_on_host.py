@@ -64,9 +64,20 @@ def scenes():
     sq = S.single_path_scene([S.MOVE, S.LINE, S.LINE, S.LINE, S.CLOSE], [[0, 0], [40, 0], [40, 40], [0, 40]], 1.0,
                              join=S.JOIN_MITER, cap=S.CAP_BUTT)
     sq.dashes = [(np.array([50, 30], np.float32), 20.0)]
+    # a dash boundary 2^-20 before a corner at x ~ 1000 (a part without
+    # extent), and dashes shorter than the FP32 spacing there
+    corner = S.single_path_scene([S.MOVE, S.LINE, S.LINE], [[1000, 0], [1010, 0], [1010, 10]], 2.0,
+                                 join=S.JOIN_MITER, cap=S.CAP_BUTT)
+    corner.dashes = [(np.array([5, 5], np.float32), 2.0 ** -20)]
+    tiny = S.single_path_scene([S.MOVE, S.LINE], [[1000, 0], [1010, 0]], 2.0, join=S.JOIN_MITER, cap=S.CAP_BUTT)
+    tiny.dashes = [(np.array([2.0 ** -20, 1.0], np.float32), 0.0)]
     return {
         "line": line,
         "square": sq,
+        "ulp_corner": corner,
+        "ulp_dashes": tiny,
+        # holds dash boundaries within an ulp of segment ends
+        "map100k": S.with_dashes(S.scene_c2(2, n_segments=100000, n_paths=1000), seed=4, lo=0.5, hi=12.0),
         "c1": S.with_dashes(S.scene_c1(1), seed=1),
         "c1_fills": S.with_dashes(S.with_fills(S.scene_c1(1), 0.5, seed=3), seed=2),
         "map": S.with_dashes(S.scene_c2(2, n_segments=20000, n_paths=200), seed=4, lo=0.5, hi=12.0),
@@ -74,7 +85,8 @@ def scenes():
     }
 
 
-@pytest.mark.parametrize("name", ["line", "square", "c1", "c1_fills", "map", "stress"])
+@pytest.mark.parametrize("name", ["line", "square", "ulp_corner", "ulp_dashes", "c1", "c1_fills", "map", "map100k",
+                                  "stress"])
 def test_dashing_device_code_matches_the_oracle(lib, name):
     sc = scenes()[name]
     tags, pts = dash_host(lib, sc)

@@ -41,6 +41,17 @@ def _scene(name):
                                  1.0, join=S.JOIN_MITER, cap=S.CAP_SQUARE)
         sc.dashes = [(np.array([50, 30], np.float32), 20.0)]
         return sc
+    if name == "ulp_corner":
+        # a dash boundary 2^-20 before the corner at x = 1010: its part of
+        # the first segment has no extent in FP32 and is left out
+        sc = S.single_path_scene([S.MOVE, S.LINE, S.LINE], [[1000, 0], [1010, 0], [1010, 10]], 2.0,
+                                 join=S.JOIN_MITER, cap=S.CAP_SQUARE)
+        sc.dashes = [(np.array([5, 5], np.float32), 2.0 ** -20)]
+        return sc
+    if name == "ulp_dashes":
+        sc = S.single_path_scene([S.MOVE, S.LINE], [[1000, 0], [1010, 0]], 2.0, join=S.JOIN_MITER, cap=S.CAP_ROUND)
+        sc.dashes = [(np.array([2.0 ** -20, 1.0], np.float32), 0.0)]
+        return sc
     if name == "c1_lines":
         return S.with_dashes(S.scene_c1(1), seed=1)
     if name == "c1_arcs":
@@ -62,7 +73,8 @@ def _check_encoding(scene, ref):
     assert ulp.max() <= 1 and np.count_nonzero(ulp) <= max(4, 1e-4 * ulp.size), int(np.count_nonzero(ulp))
 
 
-@pytest.mark.parametrize("name", ["line", "square", "c1_lines", "c1_arcs", "c1_fills", "map_lines", "stress_arcs"])
+@pytest.mark.parametrize("name", ["line", "square", "ulp_corner", "ulp_dashes", "c1_lines", "c1_arcs", "c1_fills",
+                                  "map_lines", "stress_arcs"])
 def test_dashed_scene_parity(ctx, name):
     import torch
 
@@ -79,6 +91,7 @@ def test_dashed_scene_parity(ctx, name):
     counts = ctx.counts(scene, sc.tolerance, mode).cpu().numpy().astype(np.uint32)
     torch.cuda.synchronize()
     got = B.records_to_numpy(recs, mode)
+    assert all(np.all(np.isfinite(got[f])) for f in ("x0", "y0", "x1", "y1"))
     ref = O.expand(sc, enc=ref_enc)
     assert ref.status == 0
     rep = P.compare(counts, got, ref, mode)
@@ -107,6 +120,7 @@ def test_full_size_dashed_map_scene(ctx):
     counts = ctx.counts(scene).cpu().numpy().astype(np.uint32)
     torch.cuda.synchronize()
     got = B.records_to_numpy(recs, sc.output_mode)
+    assert all(np.all(np.isfinite(got[f])) for f in ("x0", "y0", "x1", "y1"))
     ref = O.expand(sc, enc=ref_enc, emit=False)
     near = P.near_threshold(ref.margins)
     mism = counts != ref.counts
@@ -133,7 +147,7 @@ def test_full_size_dashed_map_scene(ctx):
 def test_bad_dash_patterns_are_rejected(ctx):
     from paper_2405_00127_amd import binding as B
 
-    for pat in ([-1.0, 2.0], [float("nan"), 1.0]):
+    for pat in ([-1.0, 2.0], [float("nan"), 1.0], [2.0 ** -12, 2.0 ** -12]):
         sc = _scene("line")
         sc.dashes = [(np.array(pat, np.float32), 0.0)]
         with pytest.raises(B.StrokexError) as ei:

@@ -214,3 +214,80 @@ def test_solid_and_filled_paths_are_copied():
     assert np.array_equal(body, src)
     assert np.array_equal(de.style_stream, enc.style_stream)
     assert np.array_equal(de.path_map, enc.path_map)
+
+
+def _dash_structure(enc):
+    """(segments without extent, open subpaths without segments) of an
+    encoding: a segment has extent when one of its points differs from its
+    start point."""
+    mon = O.monoids(enc.tags)
+    flat, empty_open = 0, 0
+    for i, t in enumerate(enc.tags):
+        if t & TAG_END:
+            if not (t & TAG_CLOSED) and (i == 0 or (enc.tags[i - 1] & TAG_END)):
+                empty_open += 1
+            continue
+        c = int(t & 3)
+        D = enc.data[mon[0][i] : mon[0][i] + c + 1]
+        if np.all(D[1:] == D[0]):
+            flat += 1
+    return flat, empty_open
+
+
+def test_dash_starting_a_fraction_of_an_ulp_before_a_segment_end():
+    """Reading G36's rule for parts without extent.  The polyline
+    (1000,0)-(1010,0)-(1010,10) with dashes of 5 every 10 and offset 2^-20:
+    the second dash starts 2^-20 before the corner, where x = 1010 - 2^-20
+    rounds to 1010 in FP32, so its part of the first segment has no extent.
+    That part is left out: the dash is the vertical stretch from (1010, 0)
+    to (1010, 5 - 2^-20), its cap marker points along +y, and with butt caps
+    its outline is exactly the rectangle [1008, 1012] x [0, 5 - 2^-20] (no
+    join at the corner, no undefined tangents)."""
+    sc = _line_scene([5, 5], 2.0 ** -20, pts=((1000, 0), (1010, 0), (1010, 10)))
+    enc = O.encode_dashed(sc)
+    assert _dash_structure(enc) == (0, 0)
+    mon = O.monoids(enc.tags)
+    markers = [i for i, t in enumerate(enc.tags) if (t & TAG_END) and not (t & TAG_CLOSED)]
+    # dashes: [0, 5 - 2^-20), [10 - 2^-20, 15 - 2^-20), [20 - 2^-20, 20)
+    assert len(markers) == 3
+    m2 = enc.data[mon[0][markers[1]] + 1 : mon[0][markers[1]] + 3]  # (the point before is the last point)
+    assert m2[0].tolist() == [1010.0, 0.0]
+    assert m2[1][0] == 1010.0 and m2[1][1] > 4.9
+    r = O.expand(sc, enc=enc)
+    assert r.status == 0
+    o = r.out
+    xy = np.stack([o["x0"], o["y0"], o["x1"], o["y1"]], 1)
+    assert np.all(np.isfinite(xy))
+    second = o[(np.minimum(o["x0"], o["x1"]) >= 1007.9) & (np.maximum(o["y0"], o["y1"]) <= 5.5)]
+    assert len(second) == 4 and len(r.out[(r.out["kind"] == O.KIND_JOIN_OUTER)]) == 0
+    ys = np.concatenate([second["y0"], second["y1"]])
+    xs = np.concatenate([second["x0"], second["x1"]])
+    assert abs(ys.min() - 0.0) < 1e-9 and abs(ys.max() - (5 - 2.0 ** -20)) < 1e-5
+    assert abs(xs.min() - 1008.0) < 1e-9 and abs(xs.max() - 1012.0) < 1e-9
+
+
+def test_dashes_shorter_than_an_ulp_draw_nothing():
+    """Dashes of 2^-20 units every 1 + 2^-20 along a segment at x ~ 1000,
+    where the FP32 spacing is 2^-16: most dashes round to a single point and
+    draw nothing; those that straddle a rounding boundary remain as tiny
+    dashes with extent.  No segment of the encoding lacks extent and no dash
+    is empty."""
+    sc = _line_scene([2.0 ** -20, 1.0], 0.0, pts=((1000, 0), (1010, 0)))
+    enc = O.encode_dashed(sc)
+    assert _dash_structure(enc) == (0, 0)
+    n_dash = int(np.count_nonzero(((enc.tags & TAG_END) != 0) & ((enc.tags & TAG_CLOSED) == 0)))
+    assert n_dash <= 3
+    r = O.expand(sc, enc=enc)
+    assert r.status == 0 and np.all(np.isfinite(r.out["x0"]))
+
+
+@pytest.mark.parametrize("name", ["c1", "map", "stress"])
+def test_dashed_encodings_have_no_parts_without_extent(name):
+    """Every segment of a dashed encoding has extent and every dash has a
+    segment, on seeded scenes whose dash boundaries fall anywhere."""
+    sc = {"c1": lambda: S.with_dashes(S.scene_c1(1), seed=1),
+          "map": lambda: S.with_dashes(S.scene_c2(2, n_segments=20000, n_paths=200), seed=4, lo=0.5, hi=12.0),
+          "stress": lambda: S.with_dashes(S.scene_c3(3, n_cubics=500), seed=6, lo=2.0, hi=30.0)}[name]()
+    enc = O.encode_dashed(sc)
+    assert enc.status == 0
+    assert _dash_structure(enc) == (0, 0)
