@@ -1802,12 +1802,17 @@ SX_HD inline double dash_t_d(const D2* P, int c, const double* panel, double s) 
     double t = lo + (hi - lo) * fmin(fmax(panel[k] > 0.0 ? rest / panel[k] : 0.5, 0.0), 1.0);
     for (int it = 0; it < 60; it++) {
         const double g = speed_gl8_d(P, c, t0, t) - rest;
+        if (g == 0.0) break;
         if (g < 0.0) lo = t;
         else hi = t;
         const double d = bez_speed_d(P, c, t);
         double tn = d > 0.0 ? t - g / d : 0.5 * (lo + hi);
-        if (!(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-        if (tn == t || !(hi > lo)) break;
+        if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
+        // converged: the step is down to a few ulps of t <= 1
+        if (fabs(tn - t) <= 4.0e-16 || !(hi > lo)) {
+            t = tn;
+            break;
+        }
         t = tn;
     }
     return t;
