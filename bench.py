@@ -35,8 +35,10 @@ PEAK_HBM_GBS = 8000.0
 # vector ALU, unpacked (the library is built without packed FP32): 256 CUs x
 # 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz, the same for FP32 and FP64
 PEAK_VALU_TFLOPS = 78.6
-# VALU issue: one wave instruction per SIMD per clock, 256 CUs x 4 SIMDs x 2.4 GHz
-PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9
+# VALU issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4 clocks
+# (the same 16 lanes x 2 flops per clock that give the flop peak), so at most
+# 256 CUs x 4 SIMDs x 2.4 GHz / 4 wave instructions per second
+PEAK_VALU_WAVE_INSTS = 256 * 4 * 2.4e9 / 4
 
 # Algorithmic work per unit, in flop equivalents: an FMA counts 2, a
 # transcendental (sin, cos, atan2, sqrt, cbrt, asin, pow, a division) 1.
@@ -624,14 +626,16 @@ def phase_of_kernel(name: str):
     import re
 
     simple = (("scan_tags_kernel", "scan_tags"), ("scan_counts_kernel", "scan_slots"),
-              ("scan_counts_dev_kernel", "scan_records"), ("record_kernel", "records"), ("finish_kernel", "finish"))
+              ("scan_counts_dev_kernel", "scan_records"), ("finish_kernel", "finish"))
     for key, phase in simple:
         if f"sx::{key}(" in name:
             return phase
+    if re.search(r"sx::record_kernel(<(true|false)>)?\(", name):
+        return "records"
     m = re.search(r"sx::bisect_kernel<(true|false), (true|false), \d+>", name)
     if m:
         return None if m.group(2) == "true" else ("bisect_write" if m.group(1) == "true" else "bisect_count")
-    m = re.search(r"sx::slot_kernel<\d+, (true|false)>", name)
+    m = re.search(r"sx::slot_kernel<\d+, (true|false)(, (true|false))?>", name)
     if m:
         return None if m.group(1) == "true" else "pieces"
     m = re.search(r"sx::tail_kernel<(true|false)>", name)
