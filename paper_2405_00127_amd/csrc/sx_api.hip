@@ -667,75 +667,99 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
         desc[e] = sx::DashDesc{(uint32_t)pat.size(), (uint32_t)pats[k].size(), periods[k], phases[k]};
         pat.insert(pat.end(), pats[k].begin(), pats[k].end());
     }
+    // coordinates within 2^24 units keep every segment's grid length below
+    // 2^53 and a subpath's below 2^63 for any realistic segment count
+    {
+        const uint32_t np = paths->n_paths ? paths->pt_off[paths->n_paths] : 0u;
+        for (uint32_t j = 0; j < 2u * np; j++)
+            if (!(std::fabs(paths->pts[j]) <= 16777216.0f)) {
+                free_scene(src);
+                return fail(ctx, SX_EINVAL, "dashed paths need coordinates within 2^24 units");
+            }
+    }
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t x) {
         if (e == hipSuccess) e = x;
     };
-    sx::DashDesc* d_desc = nullptr;
-    int64_t* d_pat = nullptr;
-    uint64_t *d_len = nullptr, *d_cum = nullptr, *d_sub = nullptr, *d_otag = nullptr, *d_opt = nullptr;
-    uint32_t* d_subix = nullptr;
-    uint2* d_cnt = nullptr;
-    void *ctl = nullptr, *sts0 = nullptr, *sts1 = nullptr;
-    // device time of the two dashing phases (the host reads the totals and
-    // allocates the result between them)
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    sx::DashBufs b{};
     sx_scene* dst = nullptr;
-    uint64_t tot[2] = {0, 0}, tot_p[2] = {0, 0};
+    // device time of the three dashing phases (the host reads the sizes and
+    // allocates between them)
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    uint64_t n_ch = 0, tot_t = 0, tot_p = 0;
+    uint32_t too_fine = 0;
     const size_t nn = (size_t)n + 2;
-    A(dalloc(&d_desc, std::max<size_t>(desc.size(), 1) * sizeof(sx::DashDesc)));
-    A(dalloc(&d_pat, std::max<size_t>(pat.size(), 1) * sizeof(int64_t)));
-    A(dalloc(&d_len, nn * sizeof(uint64_t)));
-    A(dalloc(&d_cum, nn * sizeof(uint64_t)));
-    A(dalloc(&d_sub, nn * sizeof(uint64_t)));
-    A(dalloc(&d_otag, nn * sizeof(uint64_t)));
-    A(dalloc(&d_opt, nn * sizeof(uint64_t)));
-    A(dalloc(&d_subix, nn * sizeof(uint32_t)));
-    A(dalloc(&d_cnt, nn * sizeof(uint2)));
-    A(dalloc(&ctl, 2 * sx::scan_ctl_bytes()));
-    A(dalloc(&sts0, sx::scan_status_bytes(n)));
-    A(dalloc(&sts1, sx::scan_status_bytes(n)));
-    A(hipEventCreate(&ev0));
-    A(hipEventCreate(&ev1));
-    A(hipEventCreate(&ev2));
-    A(hipEventCreate(&ev3));
+    A(dalloc(&b.desc, std::max<size_t>(desc.size(), 1) * sizeof(sx::DashDesc)));
+    A(dalloc(&b.pat, std::max<size_t>(pat.size(), 1) * sizeof(int64_t)));
+    A(dalloc(&b.len, nn * sizeof(uint64_t)));
+    A(dalloc(&b.cum, nn * sizeof(uint64_t)));
+    A(dalloc(&b.sub_start, nn * sizeof(uint64_t)));
+    A(dalloc(&b.subix, nn * sizeof(uint32_t)));
+    A(dalloc(&b.nch, nn * sizeof(uint32_t)));
+    A(dalloc(&b.chb, nn * sizeof(uint64_t)));
+    A(dalloc(&b.flag, sizeof(uint32_t)));
+    A(dalloc(&b.ctl0, sx::scan_ctl_bytes()));
+    A(dalloc(&b.ctl1, sx::scan_ctl_bytes()));
+    A(dalloc(&b.ctl2, sx::scan_ctl_bytes()));
+    A(dalloc(&b.st0, sx::scan_status_bytes(n)));
+    A(dalloc(&b.st1, sx::scan_status_bytes(n)));
+    for (auto& x : ev) A(hipEventCreate(&x));
     if (e == hipSuccess && !desc.empty())
-        e = hipMemcpyAsync(d_desc, desc.data(), desc.size() * sizeof(sx::DashDesc), hipMemcpyHostToDevice, st);
+        e = hipMemcpyAsync(b.desc, desc.data(), desc.size() * sizeof(sx::DashDesc), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && !pat.empty())
-        e = hipMemcpyAsync(d_pat, pat.data(), pat.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
-    A(hipMemsetAsync(ctl, 0, 2 * sx::scan_ctl_bytes(), st));
-    A(hipMemsetAsync(sts0, 0, sx::scan_status_bytes(n), st));
-    A(hipMemsetAsync(sts1, 0, sx::scan_status_bytes(n), st));
-    char* ctl1 = (char*)ctl + sx::scan_ctl_bytes();
+        e = hipMemcpyAsync(b.pat, pat.data(), pat.size() * sizeof(int64_t), hipMemcpyHostToDevice, st);
+    A(hipMemsetAsync(b.ctl0, 0, sx::scan_ctl_bytes(), st));
+    A(hipMemsetAsync(b.ctl1, 0, sx::scan_ctl_bytes(), st));
+    A(hipMemsetAsync(b.ctl2, 0, sx::scan_ctl_bytes(), st));
+    A(hipMemsetAsync(b.st0, 0, sx::scan_status_bytes(n), st));
+    A(hipMemsetAsync(b.st1, 0, sx::scan_status_bytes(n), st));
+    A(hipMemsetAsync(b.flag, 0, sizeof(uint32_t), st));
     if (e == hipSuccess && n)
         e = sx::launch_scan_tags(src->d_tags, n, src->d_mon, ctl_block(src, 0), src->d_status_tags, nullptr, st);
-    A(hipEventRecord(ev0, st));
-    if (e == hipSuccess)
-        e = sx::launch_dash(view(src), d_desc, d_pat, d_len, d_cum, d_subix, d_sub, d_cnt, d_otag, d_opt, ctl, sts0,
-                            ctl1, sts1, 0, nullptr, nullptr, st);
-    A(hipEventRecord(ev1, st));
-    if (e == hipSuccess && n) e = hipMemcpyAsync(&tot[0], d_otag + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && n) e = hipMemcpyAsync(&tot_p[0], d_opt + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    // phase 0: lengths, positions, subpath starts, chunks per tag and their scan
+    A(hipEventRecord(ev[0], st));
+    if (e == hipSuccess) e = sx::launch_dash(view(src), b, 0, nullptr, nullptr, st);
+    A(hipEventRecord(ev[1], st));
+    if (e == hipSuccess && n) e = hipMemcpyAsync(&n_ch, b.chb + n, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && n) e = hipMemcpyAsync(&too_fine, b.flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
     A(hipStreamSynchronize(st));
-    if (e == hipSuccess && (tot[0] > UINT32_MAX - 64 || tot_p[0] > UINT32_MAX)) {
+    if (e == hipSuccess && (too_fine || n_ch > (uint64_t)INT32_MAX))
+        r = fail(ctx, SX_EINVAL, "dash pattern too fine for the segment lengths");
+    // phase 1: chunk owners, per-chunk counts and their scan
+    if (e == hipSuccess && r == SX_OK && n) {
+        b.n_ch = (uint32_t)n_ch;
+        const size_t nc = (size_t)n_ch + 2;
+        A(dalloc(&b.ch_tag, nc * sizeof(uint32_t)));
+        A(dalloc(&b.cnt, nc * sizeof(uint2)));
+        A(dalloc(&b.otag, nc * sizeof(uint64_t)));
+        A(dalloc(&b.opt, nc * sizeof(uint64_t)));
+        A(dalloc(&b.st2, sx::scan_status_bytes(b.n_ch)));
+        A(hipMemsetAsync(b.st2, 0, sx::scan_status_bytes(b.n_ch), st));
+        A(hipEventRecord(ev[2], st));
+        if (e == hipSuccess) e = sx::launch_dash(view(src), b, 1, nullptr, nullptr, st);
+        A(hipEventRecord(ev[3], st));
+        if (e == hipSuccess) e = hipMemcpyAsync(&tot_t, b.otag + b.n_ch, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&tot_p, b.opt + b.n_ch, sizeof(uint64_t), hipMemcpyDeviceToHost, st);
+        A(hipStreamSynchronize(st));
+    }
+    if (e == hipSuccess && r == SX_OK && (tot_t > UINT32_MAX - 64 || tot_p > UINT32_MAX)) {
         r = fail(ctx, SX_EINVAL, "dashed scene exceeds 32-bit stream sizes");
-    } else if (e == hipSuccess) {
+    } else if (e == hipSuccess && r == SX_OK) {
         dst = new (std::nothrow) sx_scene();
         if (!dst) e = hipErrorOutOfMemory;
     }
+    // phase 2: the write pass into the result scene
     if (e == hipSuccess && r == SX_OK) {
         dst->ctx = ctx;
-        dst->n_tags = (uint32_t)tot[0];
-        dst->n_pts = (uint32_t)tot_p[0];
+        dst->n_tags = (uint32_t)tot_t;
+        dst->n_pts = (uint32_t)tot_p;
         dst->n_paths = src->n_paths;
         dst->n_styles = src->n_styles;
         dst->n_xforms = src->n_xforms;
         e = reserve_scene(dst, dst->n_tags, dst->n_pts, dst->n_styles, dst->n_xforms, dst->n_paths, st);
-        A(hipEventRecord(ev2, st));
-        if (e == hipSuccess && n)
-            e = sx::launch_dash(view(src), d_desc, d_pat, d_len, d_cum, d_subix, d_sub, d_cnt, d_otag, d_opt, ctl,
-                                sts0, ctl1, sts1, 1, dst->d_tags, dst->d_pts, st);
-        A(hipEventRecord(ev3, st));
+        A(hipEventRecord(ev[4], st));
+        if (e == hipSuccess && n) e = sx::launch_dash(view(src), b, 2, dst->d_tags, dst->d_pts, st);
+        A(hipEventRecord(ev[5], st));
         if (src->n_styles)
             A(hipMemcpyAsync(dst->d_styles, src->d_styles, src->n_styles * sizeof(sx::StyleD),
                              hipMemcpyDeviceToDevice, st));
@@ -746,27 +770,33 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
             A(hipMemcpyAsync(dst->d_path_map, src->d_path_map, src->n_paths * sizeof(uint32_t),
                              hipMemcpyDeviceToDevice, st));
         A(hipStreamSynchronize(st));
-        float ms0 = 0.0f, ms1 = 0.0f;
-        if (e == hipSuccess && hipEventElapsedTime(&ms0, ev0, ev1) == hipSuccess &&
-            hipEventElapsedTime(&ms1, ev2, ev3) == hipSuccess)
-            dst->dash_ms = ms0 + ms1;
+        float ms[3] = {0.0f, 0.0f, 0.0f};
+        if (e == hipSuccess && n && hipEventElapsedTime(&ms[0], ev[0], ev[1]) == hipSuccess &&
+            hipEventElapsedTime(&ms[1], ev[2], ev[3]) == hipSuccess &&
+            hipEventElapsedTime(&ms[2], ev[4], ev[5]) == hipSuccess)
+            dst->dash_ms = ms[0] + ms[1] + ms[2];
     }
-    dfree(d_desc);
-    dfree(d_pat);
-    dfree(d_len);
-    dfree(d_cum);
-    dfree(d_sub);
-    dfree(d_otag);
-    dfree(d_opt);
-    dfree(d_subix);
-    dfree(d_cnt);
-    dfree(ctl);
-    dfree(sts0);
-    dfree(sts1);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-    if (ev2) (void)hipEventDestroy(ev2);
-    if (ev3) (void)hipEventDestroy(ev3);
+    dfree(b.desc);
+    dfree(b.pat);
+    dfree(b.len);
+    dfree(b.cum);
+    dfree(b.sub_start);
+    dfree(b.subix);
+    dfree(b.nch);
+    dfree(b.chb);
+    dfree(b.flag);
+    dfree(b.ch_tag);
+    dfree(b.cnt);
+    dfree(b.otag);
+    dfree(b.opt);
+    dfree(b.ctl0);
+    dfree(b.ctl1);
+    dfree(b.ctl2);
+    dfree(b.st0);
+    dfree(b.st1);
+    dfree(b.st2);
+    for (auto& x : ev)
+        if (x) (void)hipEventDestroy(x);
     free_scene(src);
     if (e != hipSuccess || r != SX_OK) {
         free_scene(dst);

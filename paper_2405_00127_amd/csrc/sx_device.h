@@ -1836,11 +1836,16 @@ SX_HD inline void dash_part_d(const D2* P, int c, double ta, double tb, float* o
 }
 // The dash intervals [a, b) (clipped to the subpath [0, Stot]) meeting the
 // segment (S0, S1], in order: f(lo, hi, a, b) for each, lo < hi.
+// Only the pattern periods m in [m_begin, m_end] are visited (a chunk of the
+// segment's work; the whole span is [dash_m_lo, dash_m_hi]).
+SX_FN int64_t dash_m_lo(int64_t S0, int64_t period, int64_t phase) { return floor_div64(S0 + phase, period) - 1; }
+SX_FN int64_t dash_m_hi(int64_t S1, int64_t period, int64_t phase) { return floor_div64(S1 + phase, period) + 1; }
 template <class F>
 SX_HD void dash_parts(int64_t S0, int64_t S1, int64_t Stot, const int64_t* pat, uint32_t n, int64_t period,
-                      int64_t phase, F f) {
-    const int64_t mlo = floor_div64(S0 + phase, period) - 1, mhi = floor_div64(S1 + phase, period) + 1;
-    for (int64_t m = mlo; m <= mhi; m++) {
+                      int64_t phase, int64_t m_begin, int64_t m_end, F f) {
+    const int64_t mlo = dash_m_lo(S0, period, phase), mhi = dash_m_hi(S1, period, phase);
+    const int64_t ma = mlo > m_begin ? mlo : m_begin, mb = mhi < m_end ? mhi : m_end;
+    for (int64_t m = ma; m <= mb; m++) {
         int64_t cpos = 0;
         for (uint32_t k = 0; k < n; k++) {
             int64_t a = m * period + cpos - phase, b = a + pat[k];
@@ -1865,10 +1870,45 @@ struct DashIn {
     const uint64_t* sub_start;  // per subpath: cum at its first tag
 };
 
-// The dashed encoding's tags and points of source tag i: counted (Write
-// false) or written at tags_out[t0 ..], pts_out[p0 ..] (Write true).
+// Work split of the count and write passes: a dashed segment's dash
+// intervals are taken a few pattern periods at a time (about kDashChunk
+// dashes), one chunk per thread, so a long segment with hundreds of dashes
+// does not hold up its wave; every other tag is one chunk.  A chunk's
+// output is the part of its tag's output that its periods produce (the
+// first chunk also opens the path, the last one ends it), so the chunks'
+// outputs in order are the tag's.
+constexpr int64_t kDashChunk = 16;
+struct DashSpan {
+    int64_t S0, S1, Stot, base;  // the segment on its subpath (grid units)
+    int64_t mlo, per;            // first pattern period, periods per chunk
+    uint32_t nq;                 // chunks
+};
+SX_HD inline DashSpan dash_span(const DashIn& in, uint32_t i, const DashDesc& dd) {
+    DashSpan sp{0, 0, 0, 0, 0, 1, 1u};
+    const uint32_t tag = in.sv.tags[i];
+    if (dd.n == 0 || (tag & kTagEnd)) return sp;
+    const uint32_t k = in.subix[i];
+    sp.base = (int64_t)in.sub_start[k];
+    sp.S0 = (int64_t)in.cum[i] - sp.base;
+    sp.S1 = sp.S0 + (int64_t)in.len[i];
+    sp.Stot = (int64_t)in.sub_start[k + 1] - sp.base;
+    sp.mlo = dash_m_lo(sp.S0, dd.period, dd.phase);
+    const int64_t span = dash_m_hi(sp.S1, dd.period, dd.phase) - sp.mlo + 1;
+    const int64_t dashes = (int64_t)(dd.n / 2u);
+    sp.per = dashes >= kDashChunk ? 1 : kDashChunk / dashes;
+    sp.nq = (uint32_t)((span + sp.per - 1) / sp.per);
+    return sp;
+}
+SX_HD inline DashDesc dash_desc_of(const DashIn& in, uint32_t i) {
+    const uint32_t sty = in.sv.mon[2 * (size_t)in.sv.mon_stride + i];
+    return sty < in.sv.n_styles ? in.desc[sty] : DashDesc{0, 0, 0, 0};
+}
+SX_HD inline uint32_t dash_chunks(const DashIn& in, uint32_t i) { return dash_span(in, i, dash_desc_of(in, i)).nq; }
+
+// The dashed encoding's tags and points of chunk q of source tag i: counted
+// (Write false) or written at tags_out[t0 ..], pts_out[p0 ..] (Write true).
 template <bool Write>
-SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts_out,
+SX_HD void dash_tag(const DashIn& in, uint32_t i, uint32_t q, uint8_t* tags_out, float2* pts_out,
                          uint64_t t0, uint64_t p0, uint32_t& nt, uint32_t& np) {
     const SceneView& sv = in.sv;
     auto put_pt = [&](float x, float y) {
@@ -1887,12 +1927,12 @@ SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts
     };
     const uint32_t tag = sv.tags[i];
     const uint32_t off = sv.mon[i];
-    const uint32_t sty = sv.mon[2 * (size_t)sv.mon_stride + i];
     const float2* D = sv.pts + off;
     const bool first_of_path = i == 0 || (sv.tags[i - 1] & kTagPath);
     const bool first_of_sub = i == 0 || (sv.tags[i - 1] & kTagEnd);
-    if (first_of_path) put_empty(tag & (kTagStyle | kTagXform), D[0]);
-    const DashDesc dd = sty < sv.n_styles ? in.desc[sty] : DashDesc{0, 0, 0, 0};
+    const DashDesc dd = dash_desc_of(in, i);
+    const DashSpan spn = dash_span(in, i, dd);
+    if (first_of_path && q == 0) put_empty(tag & (kTagStyle | kTagXform), D[0]);
     if (dd.n == 0) {
         // a solid stroke or a fill: the tag and its points as they are
         if (first_of_sub) put_pt(D[0].x, D[0].y);
@@ -1905,10 +1945,8 @@ SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts
         for (int j = 0; j <= c; j++) P[j] = d2((double)D[j].x, (double)D[j].y);
         double panel[kDashPanels];
         (void)dash_len_d(P, c, panel);
-        const uint32_t k = in.subix[i];
-        const int64_t base = (int64_t)in.sub_start[k];
-        const int64_t S0 = (int64_t)in.cum[i] - base, S1 = S0 + (int64_t)in.len[i];
-        const int64_t Stot = (int64_t)in.sub_start[k + 1] - base;
+        const int64_t base = spn.base, S0 = spn.S0, S1 = spn.S1, Stot = spn.Stot;
+        const int64_t m_begin = spn.mlo + (int64_t)q * spn.per, m_end = m_begin + spn.per - 1;
         const bool last = (sv.tags[i + 1] & kTagEnd) != 0;
         const int64_t* pat = in.pat + dd.off;
         // the first part of a dash in segment j (points rounded as its writer rounds them)
@@ -1980,7 +2018,8 @@ SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts
                 }
             return true;
         };
-        dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
+        dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, m_begin, m_end,
+                   [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
             float part[8];
             part_of(P, c, panel, S0, S1, lo, hi, part);
             const int qd = extent_of(part, c);
@@ -2006,7 +2045,7 @@ SX_HD void dash_tag(const DashIn& in, uint32_t i, uint8_t* tags_out, float2* pts
         });
     }
     // (a dashed stroke's own markers give way to its dashes' markers)
-    if (tag & kTagPath) put_empty(kTagPath, D[1]);
+    if ((tag & kTagPath) && q + 1 == spn.nq) put_empty(kTagPath, D[1]);
 }
 
 }  // namespace sx

@@ -93,9 +93,27 @@ hipError_t launch_tag_records(const uint64_t* base, const uint64_t* roff, uint64
 // totals); phase 1 writes the dashed tags and points.  Scratch per source
 // tag: len, cum (n + 1), subix (n + 1), cnt; sub_start (n + 2); otag, opt
 // (n + 1); ctl / st: two look-back scan control and status blocks.
-hipError_t launch_dash(const SceneView& sv, const DashDesc* desc, const int64_t* pat, uint64_t* len, uint64_t* cum,
-                       uint32_t* subix, uint64_t* sub_start, uint2* cnt, uint64_t* otag, uint64_t* opt, void* ctl0,
-                       void* st0, void* ctl1, void* st1, int phase, uint8_t* tags_out, float2* pts_out,
+// Device buffers of the dashing passes (per source tag unless noted).
+struct DashBufs {
+    DashDesc* desc;       // per style entry
+    int64_t* pat;         // pattern values on the grid
+    uint64_t* len;        // grid length of each dashed segment
+    uint64_t* cum;        // exclusive prefix of len (+ total)
+    uint64_t* sub_start;  // per subpath: cum at its first tag
+    uint32_t* subix;      // subpaths ended before each tag
+    uint32_t* nch;        // work chunks of each tag
+    uint64_t* chb;        // exclusive prefix of nch (+ total)
+    uint32_t* flag;       // set when a segment needs too many chunks
+    uint32_t* ch_tag;     // per chunk: its tag
+    uint2* cnt;           // per chunk: (tags, points) it contributes
+    uint64_t *otag, *opt; // per chunk: exclusive prefixes of cnt (+ totals)
+    void *ctl0, *ctl1, *ctl2, *st0, *st1, *st2;  // scan control blocks and tile status
+    uint32_t n_ch;        // number of chunks (known from phase 1 on)
+};
+// phase 0: lengths, positions, subpath starts, chunks and their scan;
+// phase 1 (b.n_ch set): chunk owners, per-chunk counts and their scan;
+// phase 2: the write pass into tags_out / pts_out.
+hipError_t launch_dash(const SceneView& sv, const DashBufs& b, int phase, uint8_t* tags_out, float2* pts_out,
                        hipStream_t s);
 
 }  // namespace sx

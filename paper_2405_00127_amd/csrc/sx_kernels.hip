@@ -1160,12 +1160,39 @@ __global__ __launch_bounds__(256) void dash_sub_start_kernel(const uint8_t* __re
     if (tags[i] & kTagEnd) sub_start[subix[i] + 1u] = cum[i];
 }
 
-__global__ __launch_bounds__(256) void dash_count_kernel(DashIn in, uint2* __restrict__ cnt) {
+// chunks of each tag (at most kDashMaxChunks; more sets the flag)
+constexpr uint32_t kDashMaxChunks = 1u << 20;
+__global__ __launch_bounds__(256) void dash_nch_kernel(DashIn in, uint32_t* __restrict__ nch,
+                                                       uint32_t* __restrict__ flag) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= in.sv.n_tags) return;
+    uint32_t q = dash_chunks(in, i);
+    if (q > kDashMaxChunks) {
+        atomicOr(flag, 1u);
+        q = 1u;
+    }
+    nch[i] = q;
+}
+
+// the owner tag of every chunk
+__global__ __launch_bounds__(256) void dash_chunk_tag_kernel(const uint32_t* __restrict__ nch,
+                                                             const uint64_t* __restrict__ chb, uint32_t n,
+                                                             uint32_t* __restrict__ ch_tag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t at = chb[i];
+    for (uint32_t q = 0; q < nch[i]; q++) ch_tag[at + q] = i;
+}
+
+__global__ __launch_bounds__(256) void dash_count_kernel(DashIn in, const uint32_t* __restrict__ ch_tag,
+                                                         const uint64_t* __restrict__ chb, uint32_t n_ch,
+                                                         uint2* __restrict__ cnt) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_ch) return;
+    const uint32_t i = ch_tag[k];
     uint32_t nt = 0, np = 0;
-    dash_tag<false>(in, i, nullptr, nullptr, 0, 0, nt, np);
-    cnt[i] = make_uint2(nt, np);
+    dash_tag<false>(in, i, (uint32_t)(k - chb[i]), nullptr, nullptr, 0, 0, nt, np);
+    cnt[k] = make_uint2(nt, np);
 }
 
 // exclusive scan of (tags, points) counts; otag[n], opt[n] = totals
@@ -1197,33 +1224,41 @@ __global__ __launch_bounds__(kScanBlock) void dash_off_scan_kernel(const uint2* 
     scan_tile<kTagItems>(load, store, n, ctl, st);
 }
 
-__global__ __launch_bounds__(256) void dash_write_kernel(DashIn in, const uint64_t* __restrict__ otag,
+__global__ __launch_bounds__(256) void dash_write_kernel(DashIn in, const uint32_t* __restrict__ ch_tag,
+                                                         const uint64_t* __restrict__ chb, uint32_t n_ch,
+                                                         const uint64_t* __restrict__ otag,
                                                          const uint64_t* __restrict__ opt,
                                                          uint8_t* __restrict__ tags_out, float2* __restrict__ pts_out) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= in.sv.n_tags) return;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_ch) return;
+    const uint32_t i = ch_tag[k];
     uint32_t nt = 0, np = 0;
-    dash_tag<true>(in, i, tags_out, pts_out, otag[i], opt[i], nt, np);
+    dash_tag<true>(in, i, (uint32_t)(k - chb[i]), tags_out, pts_out, otag[k], opt[k], nt, np);
 }
 
-hipError_t launch_dash(const SceneView& sv, const DashDesc* desc, const int64_t* pat, uint64_t* len, uint64_t* cum,
-                       uint32_t* subix, uint64_t* sub_start, uint2* cnt, uint64_t* otag, uint64_t* opt, void* ctl0,
-                       void* st0, void* ctl1, void* st1, int phase, uint8_t* tags_out, float2* pts_out,
+hipError_t launch_dash(const SceneView& sv, const DashBufs& b, int phase, uint8_t* tags_out, float2* pts_out,
                        hipStream_t s) {
     const uint32_t n = sv.n_tags;
     if (n == 0) return hipSuccess;
     const uint32_t g = (n + 255u) / 256u;
-    DashIn in{sv, desc, pat, len, cum, subix, sub_start};
+    DashIn in{sv, b.desc, b.pat, b.len, b.cum, b.subix, b.sub_start};
     if (phase == 0) {
-        dash_measure_kernel<<<g, 256, 0, s>>>(sv, desc, len);
-        dash_scan_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(sv.tags, len, n, cum, subix, (ScanCtl*)ctl0,
-                                                               (TileStatus*)st0);
-        dash_sub_start_kernel<<<g, 256, 0, s>>>(sv.tags, cum, subix, n, sub_start);
-        dash_count_kernel<<<g, 256, 0, s>>>(in, cnt);
-        dash_off_scan_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(cnt, n, otag, opt, (ScanCtl*)ctl1,
-                                                                   (TileStatus*)st1);
+        dash_measure_kernel<<<g, 256, 0, s>>>(sv, b.desc, b.len);
+        dash_scan_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(sv.tags, b.len, n, b.cum, b.subix, (ScanCtl*)b.ctl0,
+                                                               (TileStatus*)b.st0);
+        dash_sub_start_kernel<<<g, 256, 0, s>>>(sv.tags, b.cum, b.subix, n, b.sub_start);
+        dash_nch_kernel<<<g, 256, 0, s>>>(in, b.nch, b.flag);
+        return launch_scan_counts(b.nch, n, b.chb, b.ctl1, b.st1, s);
+    }
+    if (b.n_ch == 0) return hipSuccess;
+    const uint32_t gc = (b.n_ch + 255u) / 256u;
+    if (phase == 1) {
+        dash_chunk_tag_kernel<<<g, 256, 0, s>>>(b.nch, b.chb, n, b.ch_tag);
+        dash_count_kernel<<<gc, 256, 0, s>>>(in, b.ch_tag, b.chb, b.n_ch, b.cnt);
+        dash_off_scan_kernel<<<scan_tiles(b.n_ch), kScanBlock, 0, s>>>(b.cnt, b.n_ch, b.otag, b.opt,
+                                                                        (ScanCtl*)b.ctl2, (TileStatus*)b.st2);
     } else {
-        dash_write_kernel<<<g, 256, 0, s>>>(in, otag, opt, tags_out, pts_out);
+        dash_write_kernel<<<gc, 256, 0, s>>>(in, b.ch_tag, b.chb, b.n_ch, b.otag, b.opt, tags_out, pts_out);
     }
     return hipGetLastError();
 }

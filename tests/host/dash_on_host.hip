@@ -1,7 +1,8 @@
-// Test shim: the dashing passes' per-tag code (dash_len_d, dash_tag in
-// sx_device.h, the code the kernels run) built for the host and driven
-// serially: grid lengths, their exclusive prefix with the subpath index,
-// subpath starts, per-tag counts, their prefix, the write pass.  Returns the
+// Test shim: the dashing passes' per-tag code (dash_len_d, dash_chunks,
+// dash_tag in sx_device.h, the code the kernels run) built for the host and
+// driven serially: grid lengths, their exclusive prefix with the subpath
+// index, subpath starts, the work chunks, per-chunk counts, their prefix,
+// the write pass.  Returns the
 // dashed encoding for comparison with the oracle's.  Test infrastructure only.
 #include <cstring>
 #include <vector>
@@ -90,19 +91,25 @@ extern "C" int dh_dash(const sx_paths* paths, const sx_style* styles, uint32_t n
     for (uint32_t i = 0; i < n; i++)
         if (enc.tags[i] & kTagEnd) sub[subix[i] + 1] = cum[i];
     DashIn in{sv, desc.data(), pat.data(), len.data(), cum.data(), subix.data(), sub.data()};
-    std::vector<uint64_t> ot(n + 1, 0), op(n + 1, 0);
-    for (uint32_t i = 0; i < n; i++) {
+    // work chunks as the kernels take them: (tag, chunk index)
+    std::vector<std::pair<uint32_t, uint32_t>> chunks;
+    for (uint32_t i = 0; i < n; i++)
+        for (uint32_t q = 0, nq = dash_chunks(in, i); q < nq; q++) chunks.push_back({i, q});
+    const size_t nc = chunks.size();
+    std::vector<uint64_t> ot(nc + 1, 0), op(nc + 1, 0);
+    for (size_t k = 0; k < nc; k++) {
         uint32_t a = 0, b = 0;
-        dash_tag<false>(in, i, nullptr, nullptr, 0, 0, a, b);
-        ot[i + 1] = ot[i] + a;
-        op[i + 1] = op[i] + b;
+        dash_tag<false>(in, chunks[k].first, chunks[k].second, nullptr, nullptr, 0, 0, a, b);
+        ot[k + 1] = ot[k] + a;
+        op[k + 1] = op[k] + b;
     }
-    *nt_out = ot[n];
-    *np_out = op[n];
-    if (!tags_out || ot[n] > cap_tags || op[n] > cap_pts) return tags_out ? -4 : 0;
-    for (uint32_t i = 0; i < n; i++) {
+    *nt_out = ot[nc];
+    *np_out = op[nc];
+    if (!tags_out || ot[nc] > cap_tags || op[nc] > cap_pts) return tags_out ? -4 : 0;
+    for (size_t k = 0; k < nc; k++) {
         uint32_t a = 0, b = 0;
-        dash_tag<true>(in, i, tags_out, (float2*)pts_out, ot[i], op[i], a, b);
+        dash_tag<true>(in, chunks[k].first, chunks[k].second, tags_out, (float2*)pts_out, ot[k], op[k], a, b);
+        if (a != ot[k + 1] - ot[k] || b != op[k + 1] - op[k]) return -5;  // the passes disagree
     }
     return 0;
 }
