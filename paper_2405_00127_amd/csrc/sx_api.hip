@@ -691,6 +691,7 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
     const size_t nn = (size_t)n + 2;
     A(dalloc(&b.desc, std::max<size_t>(desc.size(), 1) * sizeof(sx::DashDesc)));
     A(dalloc(&b.pat, std::max<size_t>(pat.size(), 1) * sizeof(int64_t)));
+    A(dalloc(&b.panels, (size_t)std::max<uint32_t>(n, 1u) * sx::kDashPanels * sizeof(double)));
     A(dalloc(&b.len, nn * sizeof(uint64_t)));
     A(dalloc(&b.cum, nn * sizeof(uint64_t)));
     A(dalloc(&b.sub_start, nn * sizeof(uint64_t)));
@@ -778,6 +779,7 @@ int sx_scene_encode_dashed(sx_ctx* ctx, const sx_paths* paths, const sx_style* s
     }
     dfree(b.desc);
     dfree(b.pat);
+    dfree(b.panels);
     dfree(b.len);
     dfree(b.cum);
     dfree(b.sub_start);

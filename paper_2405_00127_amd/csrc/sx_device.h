@@ -1752,14 +1752,16 @@ struct DashDesc {
     int64_t period, phase;
 };
 
-// |B'(t)| of the degree-c Bezier P[0..c]
-SX_FN double bez_speed_d(const D2* P, int c, double t) {
+// |B'(t)| of the degree-C Bezier P[0..C] (the degree a template parameter,
+// so that every array of the dashing code is indexed statically)
+template <int C>
+SX_FN double bez_speed_c(const D2* P, double t) {
     const double mt = 1.0 - t;
     double dx, dy;
-    if (c == 1) {
+    if (C == 1) {
         dx = P[1].x - P[0].x;
         dy = P[1].y - P[0].y;
-    } else if (c == 2) {
+    } else if (C == 2) {
         dx = 2.0 * (mt * (P[1].x - P[0].x) + t * (P[2].x - P[1].x));
         dy = 2.0 * (mt * (P[1].y - P[0].y) + t * (P[2].y - P[1].y));
     } else {
@@ -1770,22 +1772,32 @@ SX_FN double bez_speed_d(const D2* P, int c, double t) {
     return hypot(dx, dy);
 }
 // 8-node Gauss-Legendre of |B'| over [a, b]
-SX_HD inline double speed_gl8_d(const D2* P, int c, double a, double b) {
+template <int C>
+SX_FN double speed_gl8_c(const D2* P, double a, double b) {
     const double gx[4] = {0.1834346424956498, 0.5255324099163290, 0.7966664774136267, 0.9602898564975363};
     const double gw[4] = {0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
     const double m = 0.5 * (a + b), h = 0.5 * (b - a);
     double sum = 0.0;
-    for (int i = 0; i < 4; i++) sum += gw[i] * (bez_speed_d(P, c, m - h * gx[i]) + bez_speed_d(P, c, m + h * gx[i]));
+#pragma unroll
+    for (int i = 0; i < 4; i++) sum += gw[i] * (bez_speed_c<C>(P, m - h * gx[i]) + bez_speed_c<C>(P, m + h * gx[i]));
     return sum * h;
 }
 // arc length (sum of the panels' integrals, panel[k] each)
-SX_HD inline double dash_len_d(const D2* P, int c, double* panel) {
+template <int C>
+SX_FN double dash_len_c(const D2* P, double* panel) {
     double total = 0.0;
+#pragma unroll
     for (int k = 0; k < kDashPanels; k++) {
-        panel[k] = speed_gl8_d(P, c, (double)k / kDashPanels, (double)(k + 1) / kDashPanels);
+        panel[k] = speed_gl8_c<C>(P, (double)k / kDashPanels, (double)(k + 1) / kDashPanels);
         total += panel[k];
     }
     return total;
+}
+// the same for the degree c of a tag (1, 2 or 3; P[0..c])
+SX_HD inline double dash_len_d(const D2* P, int c, double* panel) {
+    if (c == 1) return dash_len_c<1>(P, panel);
+    if (c == 2) return dash_len_c<2>(P, panel);
+    return dash_len_c<3>(P, panel);
 }
 SX_FN int64_t dash_fix(double v) { return (int64_t)llround(v * kDashGrid); }
 SX_FN int64_t floor_div64(int64_t a, int64_t b) {
@@ -1793,19 +1805,34 @@ SX_FN int64_t floor_div64(int64_t a, int64_t b) {
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 // parameter where the panels' partial integral reaches s
-SX_HD inline double dash_t_d(const D2* P, int c, const double* panel, double s) {
-    double acc = 0.0;
-    int k = 0;
-    while (k < kDashPanels - 1 && acc + panel[k] <= s) acc += panel[k++];
+template <int C>
+SX_FN double dash_t_c(const D2* P, const double* panel, double s) {
+    // the panel holding s: the first k (< 15) with acc + panel[k] > s, where
+    // acc sums the panels before it (unrolled: the panels stay in registers)
+    double acc = 0.0, pk = panel[kDashPanels - 1];
+    int k = kDashPanels - 1;
+    bool found = false;
+#pragma unroll
+    for (int q = 0; q < kDashPanels - 1; q++) {
+        if (!found) {
+            if (acc + panel[q] <= s) {
+                acc += panel[q];
+            } else {
+                found = true;
+                k = q;
+                pk = panel[q];
+            }
+        }
+    }
     double lo = (double)k / kDashPanels, hi = (double)(k + 1) / kDashPanels;
     const double t0 = lo, rest = s - acc;
-    double t = lo + (hi - lo) * fmin(fmax(panel[k] > 0.0 ? rest / panel[k] : 0.5, 0.0), 1.0);
+    double t = lo + (hi - lo) * fmin(fmax(pk > 0.0 ? rest / pk : 0.5, 0.0), 1.0);
     for (int it = 0; it < 60; it++) {
-        const double g = speed_gl8_d(P, c, t0, t) - rest;
+        const double g = speed_gl8_c<C>(P, t0, t) - rest;
         if (g == 0.0) break;
         if (g < 0.0) lo = t;
         else hi = t;
-        const double d = bez_speed_d(P, c, t);
+        const double d = bez_speed_c<C>(P, t);
         double tn = d > 0.0 ? t - g / d : 0.5 * (lo + hi);
         if (!(tn >= lo && tn <= hi)) tn = 0.5 * (lo + hi);
         // converged: the step is down to a few ulps of t <= 1
@@ -1817,22 +1844,57 @@ SX_HD inline double dash_t_d(const D2* P, int c, const double* panel, double s) 
     }
     return t;
 }
-// the segment restricted to [ta, tb], control points rounded to FP32 (its
-// own end points where ta = 0 or tb = 1)
-SX_HD inline void dash_part_d(const D2* P, int c, double ta, double tb, float* out) {
-    for (int j = 0; j <= c; j++) {
-        D2 q[4];
-        for (int l = 0; l <= c; l++) q[l] = P[l];
-        for (int l = 0; l < c; l++) {
-            const double u = (l < c - j) ? ta : tb;
-            for (int m = 0; m < c - l; m++) q[m] = q[m] * (1.0 - u) + q[m + 1] * u;
+// A dash's part of one segment: its control points (the segment restricted
+// to [ta, tb] by blossoming, rounded to FP32; the segment's own end points
+// where ta = 0 or tb = 1), whether it has extent (a control point differs
+// from its start; a part without extent is left out, as the encoding
+// leaves out zero-length segments) and the first such point.
+struct DashPart {
+    float2 p[4];
+    bool extent;
+    float2 dv;
+};
+template <int C>
+SX_FN DashPart dash_part_c(const float2* Dq, const double* pan, int64_t Q0, int64_t Q1, int64_t lo, int64_t hi) {
+    D2 P[C + 1];
+#pragma unroll
+    for (int j = 0; j <= C; j++) P[j] = d2((double)Dq[j].x, (double)Dq[j].y);
+    const double ta = lo == Q0 ? 0.0 : dash_t_c<C>(P, pan, (double)(lo - Q0) / kDashGrid);
+    double tb = hi == Q1 ? 1.0 : dash_t_c<C>(P, pan, (double)(hi - Q0) / kDashGrid);
+    if (tb < ta) tb = ta;
+    DashPart r;
+#pragma unroll
+    for (int j = 0; j <= C; j++) {
+        D2 q[C + 1];
+#pragma unroll
+        for (int l = 0; l <= C; l++) q[l] = P[l];
+#pragma unroll
+        for (int l = 0; l < C; l++) {
+            const double u = (l < C - j) ? ta : tb;
+#pragma unroll
+            for (int m = 0; m < C - l; m++) q[m] = q[m] * (1.0 - u) + q[m + 1] * u;
         }
-        D2 r = q[0];
-        if (j == 0 && ta == 0.0) r = P[0];
-        if (j == c && tb == 1.0) r = P[c];
-        out[2 * j] = (float)r.x;
-        out[2 * j + 1] = (float)r.y;
+        D2 v = q[0];
+        if (j == 0 && ta == 0.0) v = P[0];
+        if (j == C && tb == 1.0) v = P[C];
+        r.p[j] = make_float2((float)v.x, (float)v.y);
     }
+    r.extent = false;
+    r.dv = r.p[0];
+#pragma unroll
+    for (int j = 1; j <= C; j++)
+        if (!r.extent && !(r.p[j].x == r.p[0].x && r.p[j].y == r.p[0].y)) {
+            r.extent = true;
+            r.dv = r.p[j];
+        }
+    return r;
+}
+// the same for the degree c of a tag
+SX_HD inline DashPart dash_part_d(int c, const float2* Dq, const double* pan, int64_t Q0, int64_t Q1, int64_t lo,
+                                  int64_t hi) {
+    if (c == 1) return dash_part_c<1>(Dq, pan, Q0, Q1, lo, hi);
+    if (c == 2) return dash_part_c<2>(Dq, pan, Q0, Q1, lo, hi);
+    return dash_part_c<3>(Dq, pan, Q0, Q1, lo, hi);
 }
 // The dash intervals [a, b) (clipped to the subpath [0, Stot]) meeting the
 // segment (S0, S1], in order: f(lo, hi, a, b) for each, lo < hi.
@@ -1864,6 +1926,7 @@ struct DashIn {
     SceneView sv;
     const DashDesc* desc;       // per style entry
     const int64_t* pat;         // pattern values on the grid
+    const double* panels;       // per dashed segment tag i: panel k's integral at [k * n_tags + i]
     const uint64_t* len;        // per tag: grid length of a dashed segment, else 0
     const uint64_t* cum;        // per tag: exclusive prefix of len
     const uint32_t* subix;      // per tag: subpaths ended before it
@@ -1905,6 +1968,90 @@ SX_HD inline DashDesc dash_desc_of(const DashIn& in, uint32_t i) {
 }
 SX_HD inline uint32_t dash_chunks(const DashIn& in, uint32_t i) { return dash_span(in, i, dash_desc_of(in, i)).nq; }
 
+// Chunk q of dashed segment i (degree C): its dashes' parts and markers.
+template <bool Write, int C, class PutPt, class PutTag>
+SX_HD void dash_segment(const DashIn& in, uint32_t i, uint32_t q, const DashDesc& dd, const DashSpan& spn,
+                        PutPt& put_pt, PutTag& put_tag) {
+    const SceneView& sv = in.sv;
+    const float2* D = sv.pts + sv.mon[i];
+    double panel[kDashPanels];
+#pragma unroll
+    for (int k = 0; k < kDashPanels; k++) panel[k] = in.panels[(size_t)k * sv.n_tags + i];
+    const int64_t base = spn.base, S0 = spn.S0, S1 = spn.S1, Stot = spn.Stot;
+    const int64_t m_begin = spn.mlo + (int64_t)q * spn.per, m_end = m_begin + spn.per - 1;
+    const bool last = (sv.tags[i + 1] & kTagEnd) != 0;
+    const int64_t* pat = in.pat + dd.off;
+    // A dash that started in an earlier segment (at subpath position a <
+    // S0): whether one of its parts before this tag has extent and, when
+    // want_pt, the start and tangent points of the first such part.  Its
+    // start tag j is the last tag at or before position a; the tags between
+    // j and this one hold full parts (with extent) exactly when they have
+    // length.
+    auto earlier_extent = [&](int64_t a, int64_t b, bool want_pt, float2& ds, float2& dv) {
+        const uint64_t pos = (uint64_t)(base + a);
+        uint32_t l = 0, h = i;  // the last j < i with cum[j] <= pos (cum[i] > pos)
+        while (l < h) {
+            const uint32_t mid = l + (h - l + 1) / 2;
+            if (in.cum[mid] <= pos) l = mid;
+            else h = mid - 1;
+        }
+        const uint32_t j = l;
+        const uint64_t xj = in.cum[j] + in.len[j];  // where j's part ends
+        const bool between = xj < in.cum[i];
+        if (between && !want_pt) return true;
+        double pj[kDashPanels];
+#pragma unroll
+        for (int k = 0; k < kDashPanels; k++) pj[k] = in.panels[(size_t)k * sv.n_tags + j];
+        const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
+        const DashPart pt2 = dash_part_d((int)(sv.tags[j] & kTagCount), sv.pts + sv.mon[j], pj, Q0, Q1, a,
+                                         b < Q1 ? b : Q1);
+        if (pt2.extent) {
+            ds = pt2.p[0];
+            dv = pt2.dv;
+            return true;
+        }
+        if (!between) return false;
+        // the first tag after j with length: the last k < i with cum[k] <= xj
+        uint32_t lk = j + 1, hk = i - 1;
+        while (lk < hk) {
+            const uint32_t mid = lk + (hk - lk + 1) / 2;
+            if (in.cum[mid] <= xj) lk = mid;
+            else hk = mid - 1;
+        }
+        const float2* Dk = sv.pts + sv.mon[lk];
+        const int ck = (int)(sv.tags[lk] & kTagCount);
+        ds = Dk[0];
+        dv = make_float2(Dk[0].x + 1.0f, Dk[0].y);  // (a full part always has extent)
+        for (int m = ck; m >= 1; m--)
+            if (!(Dk[m].x == Dk[0].x && Dk[m].y == Dk[0].y)) dv = Dk[m];
+        return true;
+    };
+    dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, m_begin, m_end,
+               [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
+        const DashPart pa = dash_part_c<C>(D, panel, S0, S1, lo, hi);
+        const bool ends = b <= S1 || last;
+        float2 ds = make_float2(0.0f, 0.0f), dv = ds;
+        // an earlier part of this dash (in an earlier tag) had extent; its
+        // start and tangent points are needed only to write the marker here
+        const bool written = a < S0 && earlier_extent(a, b, Write && ends, ds, dv);
+        if (pa.extent) {
+            if (!written) {
+                put_pt(pa.p[0].x, pa.p[0].y);
+                ds = pa.p[0];
+                dv = pa.dv;
+            }
+#pragma unroll
+            for (int m = 1; m <= C; m++) put_pt(pa.p[m].x, pa.p[m].y);
+            put_tag((uint32_t)C | kTagF32);
+        }
+        if (ends && (written || pa.extent)) {
+            put_pt(ds.x, ds.y);
+            put_pt(dv.x, dv.y);
+            put_tag(2u | kTagEnd | kTagF32);
+        }
+    });
+}
+
 // The dashed encoding's tags and points of chunk q of source tag i: counted
 // (Write false) or written at tags_out[t0 ..], pts_out[p0 ..] (Write true).
 template <bool Write>
@@ -1941,108 +2088,9 @@ SX_HD void dash_tag(const DashIn& in, uint32_t i, uint32_t q, uint8_t* tags_out,
         put_tag(tag & ~(kTagPath | kTagStyle | kTagXform));
     } else if (!(tag & kTagEnd)) {
         const int c = (int)(tag & kTagCount);
-        D2 P[4];
-        for (int j = 0; j <= c; j++) P[j] = d2((double)D[j].x, (double)D[j].y);
-        double panel[kDashPanels];
-        (void)dash_len_d(P, c, panel);
-        const int64_t base = spn.base, S0 = spn.S0, S1 = spn.S1, Stot = spn.Stot;
-        const int64_t m_begin = spn.mlo + (int64_t)q * spn.per, m_end = m_begin + spn.per - 1;
-        const bool last = (sv.tags[i + 1] & kTagEnd) != 0;
-        const int64_t* pat = in.pat + dd.off;
-        // the first part of a dash in segment j (points rounded as its writer rounds them)
-        auto part_of = [&](const D2* Q, int cq, const double* pq, int64_t Q0, int64_t Q1, int64_t lo, int64_t hi,
-                           float* out) {
-            const double ta = lo == Q0 ? 0.0 : dash_t_d(Q, cq, pq, (double)(lo - Q0) / kDashGrid);
-            double tb = hi == Q1 ? 1.0 : dash_t_d(Q, cq, pq, (double)(hi - Q0) / kDashGrid);
-            if (tb < ta) tb = ta;
-            dash_part_d(Q, cq, ta, tb, out);
-        };
-        // the first control point of a part that differs from its start (0:
-        // the part has no extent and is left out, as the encoding leaves out
-        // zero-length segments)
-        auto extent_of = [](const float* part, int cq) {
-            for (int q = 1; q <= cq; q++)
-                if (!(part[2 * q] == part[0] && part[2 * q + 1] == part[1])) return q;
-            return 0;
-        };
-        // A dash that started in an earlier segment (at subpath position a <
-        // S0): whether one of its parts before this tag has extent and, when
-        // want_pt, the start and tangent points of the first such part.  Its
-        // start tag j is the last tag at or before position a; the tags
-        // between j and this one hold full parts (with extent) exactly when
-        // they have length.
-        auto earlier_extent = [&](int64_t a, int64_t b, bool want_pt, float2& ds, float2& dv) {
-            const uint64_t pos = (uint64_t)(base + a);
-            uint32_t l = 0, h = i;  // the last j < i with cum[j] <= pos (cum[i] > pos)
-            while (l < h) {
-                const uint32_t mid = l + (h - l + 1) / 2;
-                if (in.cum[mid] <= pos) l = mid;
-                else h = mid - 1;
-            }
-            const uint32_t j = l;
-            const uint64_t xj = in.cum[j] + in.len[j];  // where j's part ends
-            const bool between = xj < in.cum[i];
-            if (between && !want_pt) return true;
-            const uint32_t tj = sv.tags[j];
-            const int cj = (int)(tj & kTagCount);
-            const float2* Dj = sv.pts + sv.mon[j];
-            D2 Q[4];
-            for (int q = 0; q <= cj; q++) Q[q] = d2((double)Dj[q].x, (double)Dj[q].y);
-            double pj[kDashPanels];
-            (void)dash_len_d(Q, cj, pj);
-            const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
-            float pt2[8];
-            part_of(Q, cj, pj, Q0, Q1, a, b < Q1 ? b : Q1, pt2);
-            const int qj = extent_of(pt2, cj);
-            if (qj) {
-                ds = make_float2(pt2[0], pt2[1]);
-                dv = make_float2(pt2[2 * qj], pt2[2 * qj + 1]);
-                return true;
-            }
-            if (!between) return false;
-            // the first tag after j with length: the last k < i with cum[k] <= xj
-            uint32_t lk = j + 1, hk = i - 1;
-            while (lk < hk) {
-                const uint32_t mid = lk + (hk - lk + 1) / 2;
-                if (in.cum[mid] <= xj) lk = mid;
-                else hk = mid - 1;
-            }
-            const float2* Dk = sv.pts + sv.mon[lk];
-            const int ck = (int)(sv.tags[lk] & kTagCount);
-            ds = Dk[0];
-            dv = make_float2(Dk[0].x + 1.0f, Dk[0].y);  // (a full part always has extent)
-            for (int q = 1; q <= ck; q++)
-                if (!(Dk[q].x == Dk[0].x && Dk[q].y == Dk[0].y)) {
-                    dv = Dk[q];
-                    break;
-                }
-            return true;
-        };
-        dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, m_begin, m_end,
-                   [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
-            float part[8];
-            part_of(P, c, panel, S0, S1, lo, hi, part);
-            const int qd = extent_of(part, c);
-            const bool ends = b <= S1 || last;
-            float2 ds = make_float2(0.0f, 0.0f), dv = ds;
-            // an earlier part of this dash (in an earlier tag) had extent; its
-            // start and tangent points are needed only to write the marker here
-            const bool written = a < S0 && earlier_extent(a, b, Write && ends, ds, dv);
-            if (qd) {
-                if (!written) {
-                    put_pt(part[0], part[1]);
-                    ds = make_float2(part[0], part[1]);
-                    dv = make_float2(part[2 * qd], part[2 * qd + 1]);
-                }
-                for (int q = 1; q <= c; q++) put_pt(part[2 * q], part[2 * q + 1]);
-                put_tag((uint32_t)c | kTagF32);
-            }
-            if (ends && (written || qd)) {
-                put_pt(ds.x, ds.y);
-                put_pt(dv.x, dv.y);
-                put_tag(2u | kTagEnd | kTagF32);
-            }
-        });
+        if (c == 1) dash_segment<Write, 1>(in, i, q, dd, spn, put_pt, put_tag);
+        else if (c == 2) dash_segment<Write, 2>(in, i, q, dd, spn, put_pt, put_tag);
+        else dash_segment<Write, 3>(in, i, q, dd, spn, put_pt, put_tag);
     }
     // (a dashed stroke's own markers give way to its dashes' markers)
     if ((tag & kTagPath) && q + 1 == spn.nq) put_empty(kTagPath, D[1]);

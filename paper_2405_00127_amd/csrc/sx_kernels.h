@@ -97,6 +97,7 @@ hipError_t launch_tag_records(const uint64_t* base, const uint64_t* roff, uint64
 struct DashBufs {
     DashDesc* desc;       // per style entry
     int64_t* pat;         // pattern values on the grid
+    double* panels;       // 16 panel integrals of each dashed segment (panel-major)
     uint64_t* len;        // grid length of each dashed segment
     uint64_t* cum;        // exclusive prefix of len (+ total)
     uint64_t* sub_start;  // per subpath: cum at its first tag

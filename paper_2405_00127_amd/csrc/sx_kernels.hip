@@ -1103,7 +1103,7 @@ size_t scan_ctl_bytes() { return sizeof(ScanCtl); }
 // [parts of segments][stroke cap marker]); solid strokes and fills are
 // copied.
 __global__ __launch_bounds__(256) void dash_measure_kernel(SceneView sv, const DashDesc* __restrict__ desc,
-                                                           uint64_t* __restrict__ len) {
+                                                           uint64_t* __restrict__ len, double* __restrict__ panels) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= sv.n_tags) return;
     const uint32_t tag = sv.tags[i];
@@ -1117,6 +1117,8 @@ __global__ __launch_bounds__(256) void dash_measure_kernel(SceneView sv, const D
             for (int j = 0; j <= c; j++) P[j] = d2((double)D[j].x, (double)D[j].y);
             double panel[kDashPanels];
             q = (uint64_t)dash_fix(dash_len_d(P, c, panel));
+            // kept for the count and write passes (panel k of every tag together)
+            for (int k = 0; k < kDashPanels; k++) panels[(size_t)k * sv.n_tags + i] = panel[k];
         }
     }
     len[i] = q;
@@ -1241,9 +1243,9 @@ hipError_t launch_dash(const SceneView& sv, const DashBufs& b, int phase, uint8_
     const uint32_t n = sv.n_tags;
     if (n == 0) return hipSuccess;
     const uint32_t g = (n + 255u) / 256u;
-    DashIn in{sv, b.desc, b.pat, b.len, b.cum, b.subix, b.sub_start};
+    DashIn in{sv, b.desc, b.pat, b.panels, b.len, b.cum, b.subix, b.sub_start};
     if (phase == 0) {
-        dash_measure_kernel<<<g, 256, 0, s>>>(sv, b.desc, b.len);
+        dash_measure_kernel<<<g, 256, 0, s>>>(sv, b.desc, b.len, b.panels);
         dash_scan_kernel<<<scan_tiles(n), kScanBlock, 0, s>>>(sv.tags, b.len, n, b.cum, b.subix, (ScanCtl*)b.ctl0,
                                                                (TileStatus*)b.st0);
         dash_sub_start_kernel<<<g, 256, 0, s>>>(sv.tags, b.cum, b.subix, n, b.sub_start);

@@ -71,6 +71,7 @@ extern "C" int dh_dash(const sx_paths* paths, const sx_style* styles, uint32_t n
     sv.n_paths = (uint32_t)enc.path_map.size();
     sv.mon_stride = ms;
     std::vector<uint64_t> len(n + 1, 0), cum(n + 1, 0), sub(n + 2, 0);
+    std::vector<double> panels((size_t)n * kDashPanels + 1, 0.0);
     std::vector<uint32_t> subix(n + 1, 0);
     for (uint32_t i = 0; i < n; i++) {
         const uint32_t tag = enc.tags[i];
@@ -82,6 +83,7 @@ extern "C" int dh_dash(const sx_paths* paths, const sx_style* styles, uint32_t n
             for (int j = 0; j <= c; j++) P[j] = d2((double)D[j].x, (double)D[j].y);
             double panel[kDashPanels];
             len[i] = (uint64_t)dash_fix(dash_len_d(P, c, panel));
+            for (int k = 0; k < kDashPanels; k++) panels[(size_t)k * n + i] = panel[k];
         }
     }
     for (uint32_t i = 0; i < n; i++) {
@@ -90,7 +92,7 @@ extern "C" int dh_dash(const sx_paths* paths, const sx_style* styles, uint32_t n
     }
     for (uint32_t i = 0; i < n; i++)
         if (enc.tags[i] & kTagEnd) sub[subix[i] + 1] = cum[i];
-    DashIn in{sv, desc.data(), pat.data(), len.data(), cum.data(), subix.data(), sub.data()};
+    DashIn in{sv, desc.data(), pat.data(), panels.data(), len.data(), cum.data(), subix.data(), sub.data()};
     // work chunks as the kernels take them: (tag, chunk index)
     std::vector<std::pair<uint32_t, uint32_t>> chunks;
     for (uint32_t i = 0; i < n; i++)
