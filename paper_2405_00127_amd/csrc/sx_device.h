@@ -1989,7 +1989,15 @@ SX_HD void dash_segment(const DashIn& in, uint32_t i, uint32_t q, const DashDesc
     // length.
     auto earlier_extent = [&](int64_t a, int64_t b, bool want_pt, float2& ds, float2& dv) {
         const uint64_t pos = (uint64_t)(base + a);
-        uint32_t l = 0, h = i;  // the last j < i with cum[j] <= pos (cum[i] > pos)
+        // the last j < i with cum[j] <= pos (cum[i] > pos; the subpath's
+        // first tag qualifies): usually i - 1, so gallop back from there,
+        // then bisect the last step
+        uint32_t h = i - 1, l = h, step = 1;
+        while (in.cum[l] > pos) {
+            h = l - 1;
+            l = l >= step ? l - step : 0u;
+            step *= 2u;
+        }
         while (l < h) {
             const uint32_t mid = l + (h - l + 1) / 2;
             if (in.cum[mid] <= pos) l = mid;
@@ -2011,8 +2019,14 @@ SX_HD void dash_segment(const DashIn& in, uint32_t i, uint32_t q, const DashDesc
             return true;
         }
         if (!between) return false;
-        // the first tag after j with length: the last k < i with cum[k] <= xj
-        uint32_t lk = j + 1, hk = i - 1;
+        // the first tag after j with length: the last k < i with cum[k] <=
+        // xj (cum[j + 1] = xj), usually j + 1: gallop forward, then bisect
+        uint32_t lk = j + 1, hk = lk, stp = 1;
+        while (hk < i - 1 && in.cum[hk + 1] <= xj) {
+            lk = hk + 1;
+            hk = (i - 1 - hk > stp) ? hk + stp : i - 1;
+            stp *= 2u;
+        }
         while (lk < hk) {
             const uint32_t mid = lk + (hk - lk + 1) / 2;
             if (in.cum[mid] <= xj) lk = mid;
