@@ -1186,11 +1186,47 @@ __global__ __launch_bounds__(256) void dash_chunk_tag_kernel(const uint32_t* __r
     for (uint32_t q = 0; q < nch[i]; q++) ch_tag[at + q] = i;
 }
 
+// The chunk a thread of a 256-thread block takes: the block's chunks
+// ordered by kind (dashed lines, quadratics, cubics, the rest), so that a
+// wave mostly runs one degree's code (the per-degree dash code would
+// otherwise run three times over in a mixed wave).  ~0u: none.
+__device__ uint32_t dash_chunk_of_thread(const DashIn& in, const uint32_t* __restrict__ ch_tag, uint32_t n_ch,
+                                         uint32_t* s_ord, uint32_t (*s_hist)[4]) {
+    const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
+    const uint32_t k = blockIdx.x * 256u + t;
+    uint32_t cls = 4u;
+    if (k < n_ch) {
+        const uint32_t i = ch_tag[k];
+        const uint32_t tag = in.sv.tags[i];
+        cls = (!(tag & kTagEnd) && dash_desc_of(in, i).n) ? (tag & kTagCount) - 1u : 3u;
+    }
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < 4; c++) {
+        const uint64_t m = __ballot(cls == c);
+        if (cls == c) rank = (uint32_t)__popcll(m & below);
+        if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    uint32_t pos = rank, n_valid = 0;
+    for (uint32_t c = 0; c < 4; c++)
+        for (uint32_t w = 0; w < 4; w++) {
+            if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
+            n_valid += s_hist[w][c];
+        }
+    if (cls < 4u) s_ord[pos] = t;
+    __syncthreads();
+    return t < n_valid ? blockIdx.x * 256u + s_ord[t] : ~0u;
+}
+
 __global__ __launch_bounds__(256) void dash_count_kernel(DashIn in, const uint32_t* __restrict__ ch_tag,
                                                          const uint64_t* __restrict__ chb, uint32_t n_ch,
                                                          uint2* __restrict__ cnt) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_ch) return;
+    __shared__ uint32_t s_ord[256];
+    __shared__ uint32_t s_hist[4][4];
+    const uint32_t k = dash_chunk_of_thread(in, ch_tag, n_ch, s_ord, s_hist);
+    if (k == ~0u) return;
     const uint32_t i = ch_tag[k];
     uint32_t nt = 0, np = 0;
     dash_tag<false>(in, i, (uint32_t)(k - chb[i]), nullptr, nullptr, 0, 0, nt, np);
@@ -1231,8 +1267,10 @@ __global__ __launch_bounds__(256) void dash_write_kernel(DashIn in, const uint32
                                                          const uint64_t* __restrict__ otag,
                                                          const uint64_t* __restrict__ opt,
                                                          uint8_t* __restrict__ tags_out, float2* __restrict__ pts_out) {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_ch) return;
+    __shared__ uint32_t s_ord[256];
+    __shared__ uint32_t s_hist[4][4];
+    const uint32_t k = dash_chunk_of_thread(in, ch_tag, n_ch, s_ord, s_hist);
+    if (k == ~0u) return;
     const uint32_t i = ch_tag[k];
     uint32_t nt = 0, np = 0;
     dash_tag<true>(in, i, (uint32_t)(k - chb[i]), tags_out, pts_out, otag[k], opt[k], nt, np);
