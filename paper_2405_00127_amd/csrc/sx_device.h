@@ -1721,15 +1721,18 @@ SX_HD void soup_tag(Sink& k, const Cfg& cfg, const SceneView& sv, uint32_t i) {
 // ------------------------------------------------------------ slots
 // Every tag owns (pieces + 1) consecutive *slots* in canonical order: one
 // per accepted piece in t order, then its tail (join / cap).  A slot code is
-// (t0_u << 6) | pivot << 5 | depth for a piece, kSlotTail for the tail.
+// (t0_u << 6) | pivot << 5 | depth for a piece (bit 31 marks the single
+// piece of a line segment, reading G32), kSlotTail for the tail.
 constexpr uint32_t kSlotTail = 0xffffffffu;
+constexpr uint32_t kCodeLine = 0x80000000u;
 struct Slot {
     uint32_t tag, code;
 };
 SX_FN uint32_t slot_code(uint32_t t0_u, uint32_t depth, bool pivot) {
     return (t0_u << 6) | (pivot ? 32u : 0u) | depth;
 }
-SX_FN uint32_t code_t0u(uint32_t code) { return code >> 6; }
+SX_FN uint32_t code_t0u(uint32_t code) { return (code & ~kCodeLine) >> 6; }
+SX_FN bool code_line(uint32_t code) { return code != kSlotTail && (code & kCodeLine) != 0u; }
 SX_FN uint32_t code_depth(uint32_t code) { return code & 31u; }
 SX_FN bool code_pivot(uint32_t code) { return (code & 32u) != 0u; }
 

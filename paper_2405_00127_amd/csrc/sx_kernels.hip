@@ -428,7 +428,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 } else if (!Write && ti.kind == kTagSegment && ti.line) {
                     // a line is one straight piece (reading G32): no bisection
                     nslots[i] = 2u;
-                    codes[i] = slot_code(0u, 0u, false);
+                    codes[i] = slot_code(0u, 0u, false) | kCodeLine;
                     if (Stats) n_lines++;
                 } else if (ti.kind == kTagSegment) {
                     bisect_init(bs, s);
@@ -511,9 +511,9 @@ struct TileAlloc {
 
 // Work class of a slot for the in-tile ordering: curve pieces, line
 // pieces, tails (joins and caps).
-__device__ __forceinline__ uint32_t slot_class(const SceneView& sv, Slot sl) {
+__device__ __forceinline__ uint32_t slot_class(Slot sl) {
     if (sl.code == kSlotTail) return 2u;
-    return (sl.tag < sv.n_tags && (sv.tags[sl.tag] & kTagCount) == 1u) ? 1u : 0u;
+    return code_line(sl.code) ? 1u : 0u;
 }
 
 // One thread per piece slot: the piece's Euler spiral and parallel curves
@@ -533,6 +533,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                                                                     unsigned long long* __restrict__ stats) {
     __shared__ uint32_t s_n, s_ntask;
     __shared__ uint32_t s_order[kSlotBlock];
+    __shared__ Slot s_slot[kSlotBlock];
     __shared__ uint32_t s_hist[kSlotBlock / 64][3];
     __shared__ uint32_t s_task[2 * kSlotBlock];     // owner thread << 2 | side << 1 | reversed
     __shared__ double s_own[kSlotBlock][4];        // k0, k1, L, w of the owner's piece
@@ -553,7 +554,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         }
         const uint64_t j0 = first + t;
         const Slot mine = j0 < n_slots ? slots[j0] : Slot{0u, kSlotTail};
-        const uint32_t cls = j0 < n_slots ? slot_class(sv, mine) : 3u;
+        const uint32_t cls = j0 < n_slots ? slot_class(mine) : 3u;
         uint32_t rank = 0;
 #pragma unroll
         for (uint32_t c = 0; c < 3; c++) {
@@ -566,7 +567,10 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         for (uint32_t c = 0; c < 3; c++)
             for (uint32_t w = 0; w < kSlotBlock / 64; w++)
                 if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
-        if (cls < 3u) s_order[pos] = t;
+        if (cls < 3u) {
+            s_order[pos] = t;
+            s_slot[pos] = mine;
+        }
         uint32_t n_valid = 0;  // slots of this tile (the rest of s_order is unused)
         for (uint32_t w = 0; w < kSlotBlock / 64; w++) n_valid += s_hist[w][0] + s_hist[w][1] + s_hist[w][2];
         __syncthreads();
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         Slot sl{0u, kSlotTail};
         if (t < n_valid) {
             j = first + s_order[t];
-            sl = slots[j];
+            sl = s_slot[t];
         }
         const bool act = t < n_valid && sl.code != kSlotTail;
         TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
