@@ -280,7 +280,7 @@ def plain(args, ctx, B, S, torch, np):
 
         log("bench: launch parameters from the autotuner" + (" (retuning)" if args.retune else " (cache)"))
         _, times = AT.tune(ctx, scene, tol, mode, buf.data_ptr(), buf.numel(), cnt.data_ptr(), stream,
-                           cache_path=args.tune_cache, use_cache=not args.retune)
+                           cache_path=args.tune_cache, use_cache=not args.retune, counts=cnt)
         tune_info = {"source": "autotuner, timed now" if times else f"autotuner cache {os.path.relpath(args.tune_cache, ROOT)}",
                      "candidates_ms": times}
     tune_info["chosen"] = ctx.get_tuning()
@@ -485,6 +485,19 @@ def batched(args, ctx, B, S, torch, np):
     batch = B.Batch(ctx)
     batch.set(scenes, stream=stream)
     bout, boffs, bstatus = batch.prepare(tol, mode, stream=stream)
+    # the batch's own launch parameters: the autotuner on the arena (cached
+    # per size bucket); the per-scene loop runs with the same ones
+    from paper_2405_00127_amd import autotune as AT
+
+    plain_tuning = ctx.get_tuning()
+    bcnt = torch.zeros(2, dtype=torch.int64, device=dev)
+    _, btimes = AT.tune(ctx, batch.arena(), tol, mode, bout.data_ptr(), bout.numel(), bcnt.data_ptr(), stream,
+                        cache_path=args.tune_cache, use_cache=not args.retune, counts=bcnt)
+    batch_tuning = ctx.get_tuning()
+    log(f"bench: batch tuning {batch_tuning}" + (" (timed now)" if btimes else " (cache)"))
+    with torch.cuda.stream(stream):  # the workspaces of the loop's scenes, for the batch's chunk size
+        for i, s in enumerate(scenes):
+            ctx.expand_into(s, buf.data_ptr() + int(starts[i]) * rec, int(counts[i]) * rec, tol, mode, stream)
 
     def batch_step():
         batch.expand_async(tol, mode, bout.data_ptr(), bout.numel(), boffs.data_ptr(), bstatus.data_ptr(),
@@ -523,6 +536,7 @@ def batched(args, ctx, B, S, torch, np):
                 and torch.equal(bout[: total_rec * rec], buf[: total_rec * rec]))
     del g
     batch.destroy()
+    ctx.set_tuning(**plain_tuning)
     return {
         "workload": f"{len(scs)} map/CAD scenes, log-uniform 100..200k segments, {total_seg} segments, "
                     f"{args.mode}, tol 0.25 px",
@@ -537,6 +551,7 @@ def batched(args, ctx, B, S, torch, np):
         "speedup": loop_ms / graph_ms,
         "device_ms": {"batched": graph_dev, "plain_loop": loop_dev},
         "outputs_identical": same,
+        "tuning": {"chosen": batch_tuning, "candidates_ms": btimes},
     }
 
 

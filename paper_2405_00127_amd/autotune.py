@@ -63,12 +63,22 @@ def _store(path: str, data: Dict[str, dict]) -> None:
 
 
 def time_config(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, count_ptr: int,
-                stream, reps: int = 5) -> float:
+                stream, reps: int = 5, counts=None) -> float:
     """Average ms of one asynchronous expansion with the context's current
-    tuning, timed with HIP events on ``stream`` (after one untimed run)."""
+    tuning, timed with HIP events on ``stream`` (after one untimed run).
+    ``counts``: the device tensor behind count_ptr; when given, the untimed
+    run's status is read and an item workspace too short for these launch
+    parameters (smaller record chunks need more item units) is grown by one
+    synchronous expansion before the timed runs, so that no candidate is
+    timed on a run that stopped short."""
     import torch
 
     ctx.expand_async(scene, out_ptr, capacity, count_ptr, tolerance, mode, stream=stream)
+    if counts is not None:
+        stream.synchronize()
+        if int(counts[1].item()) != 0:
+            ctx.expand_into(scene, out_ptr, capacity, tolerance, mode, stream)
+            ctx.expand_async(scene, out_ptr, capacity, count_ptr, tolerance, mode, stream=stream)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
@@ -80,10 +90,12 @@ def time_config(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity:
 
 
 def tune(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, count_ptr: int, stream=None,
-         reps: int = 5, cache_path: Optional[str] = None, use_cache: bool = True) -> Tuple[dict, Dict[str, float]]:
+         reps: int = 5, cache_path: Optional[str] = None, use_cache: bool = True,
+         counts=None) -> Tuple[dict, Dict[str, float]]:
     """Pick the fastest launch parameters for this scene and set them on
     ``ctx``.  The output buffer must already be large enough (size it with
-    one ``ctx.expand``).  Coordinate search: the slot kernel's waves, then the
+    one ``ctx.expand``); pass the device tensor behind count_ptr as
+    ``counts`` so that each candidate's item workspace is checked.  Coordinate search: the slot kernel's waves, then the
     bisection range and waves, then the chunk size.  Returns (chosen tuning,
     {"w{W}r{R}b{B}k{K}": ms} of every candidate timed; empty when the cache
     answered)."""
@@ -109,7 +121,8 @@ def tune(ctx, scene, tolerance: float, mode: int, out_ptr: int, capacity: int, c
         name = f"w{t['piece_waves']}r{t['bisect_range']}b{t['bisect_waves']}k{t['chunk_k']}"
         if name not in times:
             ctx.set_tuning(**t)
-            times[name] = time_config(ctx, scene, tolerance, mode, out_ptr, capacity, count_ptr, stream, reps)
+            times[name] = time_config(ctx, scene, tolerance, mode, out_ptr, capacity, count_ptr, stream, reps,
+                                      counts=counts)
         return times[name]
 
     for group in ({"piece_waves": PIECE_WAVES}, {"bisect_range": BISECT_RANGE, "bisect_waves": BISECT_WAVES},
