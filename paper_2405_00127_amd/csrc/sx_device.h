@@ -1883,7 +1883,7 @@ SX_FN DashPart dash_part_c(const float2* Dq, const double* pan, int64_t Q0, int6
         r.p[j] = make_float2((float)v.x, (float)v.y);
     }
     r.extent = false;
-    r.dv = r.p[0];
+    r.dv = make_float2(r.p[0].x + 1.0f, r.p[0].y);
 #pragma unroll
     for (int j = 1; j <= C; j++)
         if (!r.extent && !(r.p[j].x == r.p[0].x && r.p[j].y == r.p[0].y)) {
@@ -1891,6 +1891,28 @@ SX_FN DashPart dash_part_c(const float2* Dq, const double* pan, int64_t Q0, int6
             r.dv = r.p[j];
         }
     return r;
+}
+// A part of grid length lp of a segment of grid length ls whose control
+// points lie within +-M cannot have rounded control points that all
+// coincide when lp is longer than their control polygon could then be
+// (3 legs of at most a diagonal of the 2^-23 M rounding box: under 8 x
+// 2^-22 M), plus the arc-length rule's own error (below 2e-3 ls even
+// beside a cusp) and 2^-20: such a part has extent without computing it.
+// Both dashing passes take the same decision, so their counts agree.
+SX_FN bool dash_surely_extent(int64_t lp, int64_t ls, double M) {
+    return (double)lp / kDashGrid > 8.0 * M * 0x1p-22 + 2e-3 * ((double)ls / kDashGrid) + 0x1p-20;
+}
+template <int C>
+SX_FN double dash_max_coord(const float2* D) {
+    double m = 0.0;
+#pragma unroll
+    for (int j = 0; j <= C; j++) m = fmax(m, fmax(fabs((double)D[j].x), fabs((double)D[j].y)));
+    return m;
+}
+SX_HD inline double dash_max_coord_d(int c, const float2* D) {
+    if (c == 1) return dash_max_coord<1>(D);
+    if (c == 2) return dash_max_coord<2>(D);
+    return dash_max_coord<3>(D);
 }
 // the same for the degree c of a tag
 SX_HD inline DashPart dash_part_d(int c, const float2* Dq, const double* pan, int64_t Q0, int64_t Q1, int64_t lo,
@@ -2010,13 +2032,17 @@ SX_HD void dash_segment(const DashIn& in, uint32_t i, uint32_t q, const DashDesc
         const uint64_t xj = in.cum[j] + in.len[j];  // where j's part ends
         const bool between = xj < in.cum[i];
         if (between && !want_pt) return true;
+        const int cj = (int)(sv.tags[j] & kTagCount);
+        const float2* Dj = sv.pts + sv.mon[j];
+        const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
+        const int64_t hj = b < Q1 ? b : Q1;
+        const bool sure = dash_surely_extent(hj - a, Q1 - Q0, dash_max_coord_d(cj, Dj));
+        if (sure && !want_pt) return true;
         double pj[kDashPanels];
 #pragma unroll
         for (int k = 0; k < kDashPanels; k++) pj[k] = in.panels[(size_t)k * sv.n_tags + j];
-        const int64_t Q0 = (int64_t)in.cum[j] - base, Q1 = Q0 + (int64_t)in.len[j];
-        const DashPart pt2 = dash_part_d((int)(sv.tags[j] & kTagCount), sv.pts + sv.mon[j], pj, Q0, Q1, a,
-                                         b < Q1 ? b : Q1);
-        if (pt2.extent) {
+        const DashPart pt2 = dash_part_d(cj, Dj, pj, Q0, Q1, a, hj);
+        if (sure || pt2.extent) {
             ds = pt2.p[0];
             dv = pt2.dv;
             return true;
@@ -2043,15 +2069,20 @@ SX_HD void dash_segment(const DashIn& in, uint32_t i, uint32_t q, const DashDesc
             if (!(Dk[m].x == Dk[0].x && Dk[m].y == Dk[0].y)) dv = Dk[m];
         return true;
     };
+    const double M = dash_max_coord<C>(D);
     dash_parts(S0, S1, Stot, pat, dd.n, dd.period, dd.phase, m_begin, m_end,
                [&](int64_t lo, int64_t hi, int64_t a, int64_t b) {
-        const DashPart pa = dash_part_c<C>(D, panel, S0, S1, lo, hi);
+        // (the count pass needs the part's points only when its extent is in doubt)
+        const bool sure = dash_surely_extent(hi - lo, S1 - S0, M);
+        DashPart pa{};
+        if (Write || !sure) pa = dash_part_c<C>(D, panel, S0, S1, lo, hi);
+        const bool extent = sure || pa.extent;
         const bool ends = b <= S1 || last;
         float2 ds = make_float2(0.0f, 0.0f), dv = ds;
         // an earlier part of this dash (in an earlier tag) had extent; its
         // start and tangent points are needed only to write the marker here
         const bool written = a < S0 && earlier_extent(a, b, Write && ends, ds, dv);
-        if (pa.extent) {
+        if (extent) {
             if (!written) {
                 put_pt(pa.p[0].x, pa.p[0].y);
                 ds = pa.p[0];
@@ -2061,7 +2092,7 @@ SX_HD void dash_segment(const DashIn& in, uint32_t i, uint32_t q, const DashDesc
             for (int m = 1; m <= C; m++) put_pt(pa.p[m].x, pa.p[m].y);
             put_tag((uint32_t)C | kTagF32);
         }
-        if (ends && (written || pa.extent)) {
+        if (ends && (written || extent)) {
             put_pt(ds.x, ds.y);
             put_pt(dv.x, dv.y);
             put_tag(2u | kTagEnd | kTagF32);
