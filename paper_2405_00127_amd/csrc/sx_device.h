@@ -1966,6 +1966,7 @@ struct DashIn {
 // first chunk also opens the path, the last one ends it), so the chunks'
 // outputs in order are the tag's.
 constexpr int64_t kDashChunk = 16;
+constexpr uint32_t kDashMaxChunks = 1u << 20;  // per segment; more is refused
 struct DashSpan {
     int64_t S0, S1, Stot, base;  // the segment on its subpath (grid units)
     int64_t mlo, per;            // first pattern period, periods per chunk
@@ -1984,7 +1985,8 @@ SX_HD inline DashSpan dash_span(const DashIn& in, uint32_t i, const DashDesc& dd
     const int64_t span = dash_m_hi(sp.S1, dd.period, dd.phase) - sp.mlo + 1;
     const int64_t dashes = (int64_t)(dd.n / 2u);
     sp.per = dashes >= kDashChunk ? 1 : kDashChunk / dashes;
-    sp.nq = (uint32_t)((span + sp.per - 1) / sp.per);
+    const int64_t nq = (span + sp.per - 1) / sp.per;
+    sp.nq = nq > (int64_t)kDashMaxChunks ? kDashMaxChunks + 1u : (uint32_t)nq;
     return sp;
 }
 SX_HD inline DashDesc dash_desc_of(const DashIn& in, uint32_t i) {

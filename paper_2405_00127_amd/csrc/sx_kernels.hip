@@ -1167,7 +1167,6 @@ __global__ __launch_bounds__(256) void dash_sub_start_kernel(const uint8_t* __re
 }
 
 // chunks of each tag (at most kDashMaxChunks; more sets the flag)
-constexpr uint32_t kDashMaxChunks = 1u << 20;
 __global__ __launch_bounds__(256) void dash_nch_kernel(DashIn in, uint32_t* __restrict__ nch,
                                                        uint32_t* __restrict__ flag) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -153,6 +153,14 @@ def test_bad_dash_patterns_are_rejected(ctx):
         with pytest.raises(B.StrokexError) as ei:
             ctx.encode(sc)
         assert ei.value.code == B.SX_EINVAL
+    # coordinates beyond 2^24 units, and a segment that would need more than
+    # 2^20 chunks of dashes (a pattern of 2^-10 units along 1.6e7 units)
+    for pts, pat in (([[0, 0], [3.0e7, 0]], [1.0, 1.0]), ([[0, 0], [1.6e7, 0]], [2.0 ** -11, 2.0 ** -11])):
+        sc = S.single_path_scene([S.MOVE, S.LINE], pts, 1.0, join=S.JOIN_ROUND, cap=S.CAP_BUTT)
+        sc.dashes = [(np.array(pat, np.float32), 0.0)]
+        with pytest.raises(B.StrokexError) as ei:
+            ctx.encode(sc)
+        assert ei.value.code == B.SX_EINVAL
     sc = _scene("line")
     sc.dashes = [(np.array([0.0, 0.0], np.float32), 0.0)]  # total length 0: solid
     scene = ctx.encode(sc)
