@@ -261,8 +261,19 @@ def plain(args, ctx, B, S, torch, np):
     sc = S.scene_map(2, args.segments, args.paths, 0.25, mode)
     if args.fill_scene:
         sc = S.with_fills(sc)
+    if args.dashed_scene:
+        sc = S.with_dashes(sc, seed=4, lo=0.5, hi=12.0)
     n_seg = sc.n_segments()
     scene = ctx.encode(sc, stream=stream)
+    dash_ms = []
+    if args.dashed_scene:
+        # the dash passes run at encoding: encode twice more for their timings
+        dash_ms.append(scene.dash_ms())
+        for _ in range(2):
+            scene.release()
+            scene = ctx.encode(sc, stream=stream)
+            dash_ms.append(scene.dash_ms())
+        log(f"bench: dash passes {dash_ms} ms, {scene.n_tags} dashed tags")
     tol = sc.tolerance
     recs, n_rec, buf = ctx.expand(scene, tol, mode, stream=stream)  # sizes output and workspace
     cnt = torch.zeros(2, dtype=torch.int64, device=dev)
@@ -296,7 +307,8 @@ def plain(args, ctx, B, S, torch, np):
     log(f"bench: work {stats}")
 
     n_tags = scene.n_tags
-    counters = None if args.fill_scene else measured_counters(args.mode, tune_info["chosen"])
+    counters = (None if (args.fill_scene or args.dashed_scene or args.density != "approx")
+                else measured_counters(args.mode, tune_info["chosen"]))
     roof = roofline_of(phase_ms, stats, n_tags, n_rec, mode, names,
                        valu=counters["valu"] if counters else None)
     if counters and roof["kernel"] in counters["traffic"]:
@@ -318,6 +330,8 @@ def plain(args, ctx, B, S, torch, np):
         "config": {
             "workload": f"map/CAD scene, {args.paths} paths, {n_seg} segments (60% lines, 15% quads, 25% cubics), "
                         + ("every path filled, " if args.fill_scene else "")
+                        + ("dash pattern on every stroke, " if args.dashed_scene else "")
+                        + ("exact density with Newton-refined inverse, " if args.density != "approx" else "")
                         + f"plain per-scene expansion, {args.mode}, tol 0.25 px",
             "segments": n_seg, "tags": n_tags, "records": n_rec, "output": args.mode, "tolerance": tol,
         },
@@ -325,6 +339,8 @@ def plain(args, ctx, B, S, torch, np):
         "roofline": roof,
         "tuning": tune_info,
     }
+    if dash_ms:
+        out["dash_ms"] = dash_ms
     del buf
     return out, sc, mode
 
@@ -764,6 +780,10 @@ def main():
     ap.add_argument("--no-fill", action="store_true", help="skip the fill leg (the map scene filled)")
     ap.add_argument("--fill-scene", action="store_true",
                     help="time the map scene with every path filled in the main leg (for profiling the fill)")
+    ap.add_argument("--dashed-scene", action="store_true",
+                    help="time the map scene with a dash pattern on every stroke in the main leg (for profiling)")
+    ap.add_argument("--density", choices=["approx", "newton"], default="approx",
+                    help="main leg's density mode (newton: exact integral, Newton-refined inverse; for profiling)")
     ap.add_argument("--batch-scenes", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true")
@@ -789,7 +809,7 @@ def main():
     if not os.path.exists(B.LIB_PATH):
         PB.build()
     torch.cuda.set_device(0)
-    ctx = B.Context(0)
+    ctx = B.Context(0, density=B.DENSITY_NEWTON if args.density == "newton" else B.DENSITY_APPROX)
     if args.copy_probe:
         n = args.copy_probe << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
