@@ -104,6 +104,7 @@ def lib():
             L.ox_line_integral_es.argtypes = [d] * 6 + [C.c_int]
             L.ox_es_side.restype = vp
             L.ox_es_side.argtypes = [d, d, d, d, d, C.c_int, C.c_int]
+            L.ox_cubic_chord.argtypes = [vp, d, d, vp]
             L.ox_dens_integral.restype = d
             L.ox_dens_integral.argtypes = [d, d]
             L.ox_f_newton_inv.restype = d
@@ -175,6 +176,15 @@ def line_integral_es(k0, k1, L, h, ua, ub, exact=False):
     spiral of arc length L (before the sqrt(1/(8 tau_flat)) factor), with
     f_approx or (exact=True) the exact integral."""
     return lib().ox_line_integral_es(float(k0), float(k1), float(L), float(h), float(ua), float(ub), int(bool(exact)))
+
+
+def cubic_chord(P, t0: float, dt: float) -> np.ndarray:
+    """B(t0 + dt) - B(t0) of the cubic P (4 x 2), as the expansion computes
+    its sub-cubic chords (test export)."""
+    p8 = np.ascontiguousarray(np.asarray(P, np.float64).reshape(8))
+    out = np.zeros(2, np.float64)
+    lib().ox_cubic_chord(_ptr(p8), float(t0), float(dt), _ptr(out))
+    return out
 
 
 def dens_integral(a, b):

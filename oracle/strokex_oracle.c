@@ -962,6 +962,14 @@ static v2 cubic_chord(const v2 *P, double t0, double dt) {
     return v2m(3.0 * dt * q0.x + 3.0 * dt * dt * s2.x + dt * dt * dt * s3.x,
                3.0 * dt * q0.y + 3.0 * dt * dt * s2.y + dt * dt * dt * s3.y);
 }
+/* test export: the chord B(t0 + dt) - B(t0) of the cubic P8 = (x0 y0 .. x3 y3) */
+void ox_cubic_chord(const double *P8, double t0, double dt, double *out2) {
+    v2 P[4];
+    for (int j = 0; j < 4; j++) P[j] = v2m(P8[2 * j], P8[2 * j + 1]);
+    v2 c = cubic_chord(P, t0, dt);
+    out2[0] = c.x;
+    out2[1] = c.y;
+}
 static v2 cubic_q(const v2 *P, double t) {
     double mt = 1.0 - t;
     v2 a = vsub(P[1], P[0]), b = vsub(P[2], P[1]), c = vsub(P[3], P[2]);

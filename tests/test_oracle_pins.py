@@ -519,3 +519,63 @@ def test_newton_mode_counts_follow_the_exact_integral():
         pts, _ = X.sample_outputs(o["x0"], o["y0"], o["x1"], o["y1"], None, 0.05)
         worst = max(worst, X.max_dist(pts, ref)[0])
     assert worst <= sc.tolerance, worst
+
+
+# ------------------------------------------ sub-cubic chords, smooth joins
+def test_cubic_chord_against_high_precision():
+    """The bisection's chord B(t0 + dt) - B(t0) is taken from the cubic's
+    terminating Taylor expansion at t0 (so that short chords far from the
+    origin keep their digits).  Against a 50-digit evaluation of the
+    definition, on cubics placed up to 1e4 from the origin and pieces down
+    to 2^-16 of the parameter: relative error within 1e-13 of the chord
+    (a dropped or mis-scaled derivative term fails at every dt)."""
+    import mpmath as mp
+
+    mp.mp.dps = 50
+    rng = np.random.default_rng(5)
+
+    def bez(P, t):
+        t = mp.mpf(t)
+        u = 1 - t
+        return [u ** 3 * P[0][k] + 3 * u * u * t * P[1][k] + 3 * u * t * t * P[2][k] + t ** 3 * P[3][k]
+                for k in range(2)]
+
+    worst = 0.0
+    for trial in range(60):
+        off = rng.uniform(-1e4, 1e4, 2)
+        P = off + rng.uniform(-200, 200, (4, 2))
+        Pm = [[mp.mpf(float(v)) for v in row] for row in P]
+        for dt in (0.5, 2.0 ** -8, 2.0 ** -16):
+            t0 = float(np.floor(rng.uniform(0, 1 - dt) / dt) * dt)
+            a, b = bez(Pm, t0), bez(Pm, t0 + dt)
+            ref = np.array([float(b[0] - a[0]), float(b[1] - a[1])])
+            got = O.cubic_chord(P, t0, dt)
+            worst = max(worst, float(np.hypot(*(got - ref)) / max(np.hypot(*ref), 1e-300)))
+    assert worst <= 1e-13, worst
+
+
+@pytest.mark.parametrize("bend", [1e-6, 1e-3])
+def test_near_smooth_joins(bend):
+    """Reading G31.  Two lines meeting at an angle below 1e-5 rad close each
+    side of the join with one straight line from one offset end point to the
+    other (length w x angle) and draw no pivot lines: the wedge left out is
+    thinner than w x 1e-5.  At 1e-3 rad the ordinary round join is drawn: an
+    outer arc and the inner side's two lines through the pivot."""
+    w = 5.0
+    d = np.array([math.cos(bend), math.sin(bend)])
+    pts = [[0.0, 0.0], [100.0, 0.0], list(np.array([100.0, 0.0]) + 100.0 * d)]
+    sc = S.single_path_scene([S.MOVE, S.LINE, S.LINE], pts, w, join=S.JOIN_ROUND, cap=S.CAP_BUTT)
+    r = O.expand(sc)
+    assert r.status == 0
+    outer = r.out[r.out["kind"] == O.KIND_JOIN_OUTER]
+    inner = r.out[r.out["kind"] == O.KIND_JOIN_INNER]
+    if bend < 1e-5:
+        assert len(outer) == 2 and len(inner) == 0
+        na, nb = np.array([0.0, -1.0]), np.array([d[1], -d[0]])  # side A's normals (right-hand)
+        want = {(tuple(np.round(100 * np.array([1, 0]) + w * na, 9)), tuple(np.round(100 * np.array([1, 0]) + w * nb, 9))),
+                (tuple(np.round(100 * np.array([1, 0]) - w * nb, 9)), tuple(np.round(100 * np.array([1, 0]) - w * na, 9)))}
+        got = {(tuple(np.round([o["x0"], o["y0"]], 9)), tuple(np.round([o["x1"], o["y1"]], 9))) for o in outer}
+        assert got == want, got
+        assert np.all(np.hypot(outer["x1"] - outer["x0"], outer["y1"] - outer["y0"]) <= w * 1.01 * bend)
+    else:
+        assert len(inner) == 2 and len(outer) >= 1
