@@ -365,7 +365,7 @@ int sx_batch_expand(sx_ctx *ctx, sx_batch *batch, float tolerance, int output_mo
  *                 allocation allows (more waves hide more latency but spill);
  *   chunk_k       1..255: records per emission item chunk (work per thread
  *                 of the record kernel);
- *   bisect_range  tags per bisection wave, a multiple of 64 up to 8192
+ *   bisect_range  tags per bisection wave, a multiple of 64 up to 1024
  *                 (0 = 256): longer ranges keep lanes refilled longer;
  *   bisect_waves  2, 3 or 4 (0 = 2): waves per SIMD of the bisection kernels.
  * Defaults {2, 16, 256, 2}.  Errors: SX_EINVAL (out of range). */

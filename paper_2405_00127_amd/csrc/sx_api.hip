@@ -454,8 +454,8 @@ int sx_set_tuning(sx_ctx* ctx, const sx_tuning* t) {
     if (!ctx || !t) return SX_EINVAL;
     if (t->piece_waves < 1 || t->piece_waves > 3) return fail(ctx, SX_EINVAL, "piece_waves must be 1, 2 or 3");
     if (t->chunk_k < 1 || t->chunk_k > 255) return fail(ctx, SX_EINVAL, "chunk_k must be in [1, 255]");
-    if (t->bisect_range != 0 && (t->bisect_range % 64 || t->bisect_range > 8192))
-        return fail(ctx, SX_EINVAL, "bisect_range must be a multiple of 64 up to 8192 (0: 256)");
+    if (t->bisect_range != 0 && (t->bisect_range % 64 || t->bisect_range > 1024))
+        return fail(ctx, SX_EINVAL, "bisect_range must be a multiple of 64 up to 1024 (0: 256)");
     if (t->bisect_waves != 0 && (t->bisect_waves < 2 || t->bisect_waves > 4))
         return fail(ctx, SX_EINVAL, "bisect_waves must be 2, 3 or 4 (0: 2)");
     ctx->tune = *t;

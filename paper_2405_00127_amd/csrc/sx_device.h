@@ -1409,23 +1409,34 @@ SX_FN uint32_t path_of(const SceneView& sv, uint32_t i) {
 
 // Segment fetch and degree elevation (Section 8.1) of tag i; bounds derived
 // from the monoids are checked (a consistent scan never trips them).
-SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s) {
-    const uint32_t n = sv.n_tags;
-    ti.kind = kTagInvalid;
-    ti.line = false;
-    ti.fill = false;
+// The kind of tag i (kTagInvalid when its indices or its points, or for a
+// segment the next tag's points, fall outside the scene), and whether a
+// segment is a line: what fetch_tag decides, without loading the segment.
+SX_HD inline int tag_kind(const SceneView& sv, uint32_t i, bool& line) {
+    line = false;
     const uint32_t tag = sv.tags[i];
     const uint32_t off = sv.mon[i];
     const uint32_t sty = sv.mon[2 * (size_t)sv.mon_stride + i];
     const uint32_t xfi = sv.mon[3 * (size_t)sv.mon_stride + i];
     const uint32_t need = (tag & kTagEnd) ? 3u : (tag & kTagCount) + 1u;
-    if (sty >= sv.n_styles || xfi >= sv.n_xforms || (size_t)off + need > sv.n_pts) return;
-    if (!(tag & kTagEnd)) {
-        if (i + 1 >= n) return;
-        const uint32_t t1 = sv.tags[i + 1];
-        const uint32_t need1 = (t1 & kTagEnd) ? 3u : (t1 & kTagCount) + 1u;
-        if ((size_t)sv.mon[i + 1] + need1 > sv.n_pts) return;
-    }
+    if (sty >= sv.n_styles || xfi >= sv.n_xforms || (size_t)off + need > sv.n_pts) return kTagInvalid;
+    if (tag & kTagEnd) return kTagMarker;
+    if (i + 1 >= sv.n_tags) return kTagInvalid;
+    const uint32_t t1 = sv.tags[i + 1];
+    const uint32_t need1 = (t1 & kTagEnd) ? 3u : (t1 & kTagCount) + 1u;
+    if ((size_t)sv.mon[i + 1] + need1 > sv.n_pts) return kTagInvalid;
+    line = (tag & kTagCount) == 1u;
+    return kTagSegment;
+}
+
+SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s) {
+    ti.fill = false;
+    ti.kind = tag_kind(sv, i, ti.line);
+    if (ti.kind == kTagInvalid) return;
+    const uint32_t tag = sv.tags[i];
+    const uint32_t off = sv.mon[i];
+    const uint32_t sty = sv.mon[2 * (size_t)sv.mon_stride + i];
+    const uint32_t xfi = sv.mon[3 * (size_t)sv.mon_stride + i];
     const StyleD st = sv.styles[sty];
     const float* X = sv.xforms + 6 * (size_t)xfi;
     const double scale = sqrt(fabs((double)X[0] * X[3] - (double)X[1] * X[2]));
@@ -1438,14 +1449,9 @@ SX_HD inline void fetch_tag(const SceneView& sv, uint32_t i, TagInfo& ti, Seg& s
     ti.scap = (st.packed >> 8) & 0xff;
     ti.ecap = (st.packed >> 16) & 0xff;
     ti.fill = (st.packed & kStyleFill) != 0u;
-    if (tag & kTagEnd) {
-        ti.kind = kTagMarker;
-        return;
-    }
-    ti.kind = kTagSegment;
+    if (ti.kind == kTagMarker) return;
     const float2* D = sv.pts + off;
     const int c = tag & kTagCount;
-    ti.line = c == 1;
     // the segment's c + 1 points, loaded without a runtime-indexed array
     // (indices clamped to the segment, so every load stays in it)
     const float2 r0 = D[0], r1 = D[1], r2 = D[c >= 2 ? 2 : 1], r3 = D[c >= 3 ? 3 : c];

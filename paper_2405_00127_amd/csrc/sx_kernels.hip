@@ -379,6 +379,7 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // their canonical positions: copied from the kept codes, or, for the few
 // segments with more pieces, from a second run of the bisection.
 constexpr int kBisectBlock = 64;
+constexpr uint32_t kBisectMaxRange = 1024;  // tags per wave (the autotuner's largest range)
 constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (on the map scene 8 and 12 beat 4, 16 and 32)
 
 template <bool Write, bool Stats, int MinWaves>
@@ -391,24 +392,58 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
     const size_t cstride = mon_stride_of(sv.n_tags);  // row stride of the kept codes
     const uint32_t a = blockIdx.x * range;
     const uint32_t b = min(sv.n_tags, a + range);
-    uint32_t cursor = a;  // next unassigned tag (wave-uniform)
+    uint32_t n_trials = 0, n_lines = 0;
+    // Count pass: lines (one straight piece each, reading G32), markers and
+    // invalid tags need no bisection.  They are settled for the whole range
+    // first, 64 consecutive tags at a time, and only the curves are listed
+    // (in LDS) for the refill loop, so that a refill does not spend rounds
+    // of scattered loads on tags that take no trial.
+    __shared__ uint32_t s_curve[kBisectMaxRange];
+    uint32_t n_curve = 0;
+    if (!Write) {
+        for (uint32_t t0 = a; t0 < b; t0 += 64u) {
+            const uint32_t it = t0 + lane;
+            bool curve = false;
+            if (it < b) {
+                bool line;
+                const int kind = tag_kind(sv, it, line);
+                if (kind == kTagSegment && !line) {
+                    curve = true;
+                } else if (kind == kTagSegment) {
+                    nslots[it] = 2u;
+                    codes[it] = slot_code(0u, 0u, false) | kCodeLine;
+                    if (Stats) n_lines++;
+                } else {
+                    nslots[it] = 1u;  // markers and invalid tags own only their tail slot
+                }
+            }
+            const uint64_t m = __ballot(curve);
+            if (curve) s_curve[n_curve + (uint32_t)__popcll(m & below)] = it;
+            n_curve += (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the refill loop's work list: the range's curves (count pass) or its tags
+    uint32_t cursor = Write ? a : 0u;  // next unassigned entry (wave-uniform)
+    const uint32_t cend = Write ? b : n_curve;
     bool busy = false;
     uint32_t i = 0, seq = 0;
     uint64_t bi = 0;  // slot base of the lane's tag (write pass)
     TagInfo ti;
     Seg s;
     Bisect bs;
-    uint32_t n_trials = 0, n_lines = 0;
     for (;;) {
         // refill idle lanes with the next tags of the range, once kRefillLanes
         // lanes are idle (a refill fetches segments: its latency is shared by
         // the lanes it serves) or the wave has nothing left to run
         const uint64_t idle = __ballot(!busy);
-        if (idle && cursor < b && (__popcll(idle) >= kRefillLanes || __ballot(busy) == 0ull)) {
+        if (idle && cursor < cend && (__popcll(idle) >= kRefillLanes || __ballot(busy) == 0ull)) {
             const uint32_t ni = cursor + (uint32_t)__popcll(idle & below);
             cursor += (uint32_t)__popcll(idle);
-            if (!busy && ni < b) {
-                i = ni;
+            if (!busy && ni < cend) {
+                i = Write ? ni : s_curve[ni];
                 seq = 0;
                 bool copied = false;
                 if (Write) {
@@ -1007,7 +1042,8 @@ hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, ui
                          uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
                          unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
-    if (range == 0 || range % 64u || keep < (uint32_t)kKeepCodes) return hipErrorInvalidValue;
+    if (range == 0 || range % 64u || range > kBisectMaxRange || keep < (uint32_t)kKeepCodes)
+        return hipErrorInvalidValue;
     // a scene too small to give every SIMD a wave at this range takes
     // shorter ranges (down to one tag per lane)
     const uint32_t fill = ((sv.n_tags / 4096u + 63u) / 64u) * 64u;
