@@ -663,11 +663,9 @@ def phase_of_kernel(name: str):
             return phase
     if re.search(r"sx::record_kernel(<(true|false)>)?\(", name):
         return "records"
-    m = re.search(r"sx::bisect_(classify|curves)_kernel<(true|false)", name)
+    m = re.search(r"sx::bisect_kernel<(true|false), (true|false), \d+>", name)
     if m:
-        return None if m.group(2) == "true" else "bisect_count"
-    if re.search(r"sx::bisect_write_kernel<\d+>", name):
-        return "bisect_write"
+        return None if m.group(2) == "true" else ("bisect_write" if m.group(1) == "true" else "bisect_count")
     m = re.search(r"sx::slot_kernel<\d+, (true|false)(, (true|false))?>", name)
     if m:
         return None if m.group(1) == "true" else "pieces"
@@ -703,16 +701,13 @@ def summarize_counters(fetch_db: str, write_db: str, valu_db: str, probe_mb: int
         for k, d, v in rows:
             ph = phase_of_kernel(k)
             if ph is not None:
-                # per phase and kernel (a phase may run more than one kernel)
-                per.setdefault(ph, {}).setdefault(counter, {}).setdefault(k, {})[d] = v * 1024.0 * factor
+                per.setdefault(ph, {}).setdefault(counter, {})[d] = v * 1024.0 * factor
     for ph, c in per.items():
         if "FETCH_SIZE" in c and "WRITE_SIZE" in c:
-            # bytes of one launch of the phase: each kernel's average per dispatch, summed
-            f = sum(sum(x.values()) / len(x) for x in c["FETCH_SIZE"].values())
-            w = sum(sum(x.values()) / len(x) for x in c["WRITE_SIZE"].values())
+            f = sum(c["FETCH_SIZE"].values()) / len(c["FETCH_SIZE"])
+            w = sum(c["WRITE_SIZE"].values()) / len(c["WRITE_SIZE"])
             out["kernels"][ph] = {"fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w,
-                                  "dispatches": [sum(len(x) for x in c["FETCH_SIZE"].values()),
-                                                 sum(len(x) for x in c["WRITE_SIZE"].values())]}
+                                  "dispatches": [len(c["FETCH_SIZE"]), len(c["WRITE_SIZE"])]}
     out["valu"] = summarize_valu(valu_db)
     return out
 
@@ -734,17 +729,15 @@ def summarize_valu(db: str, n_cu: int = 256, n_xcd: int = 8):
     for k, d, c, v in rows:
         ph = phase_of_kernel(k)
         if ph is not None:
-            ks = per.setdefault(ph, {}).setdefault(k, {})
-            ks.setdefault(d, {})[c] = ks.get(d, {}).get(c, 0.0) + v
+            per.setdefault(ph, {}).setdefault(d, {})[c] = per.get(ph, {}).get(d, {}).get(c, 0.0) + v
     out = {}
-    for ph, kernels in per.items():
+    for ph, ds in per.items():
         def avg(c):
-            # one launch of the phase: each kernel's average per dispatch, summed
-            return sum(sum(x.get(c, 0.0) for x in ds.values()) / len(ds) for ds in kernels.values())
+            return sum(x.get(c, 0.0) for x in ds.values()) / len(ds)
 
         gui = avg("GRBM_GUI_ACTIVE") / n_xcd
         act = avg("SQ_ACTIVE_INST_VALU")
-        out[ph] = {"dispatches": sum(len(ds) for ds in kernels.values()), "gui_cycles": gui,
+        out[ph] = {"dispatches": len(ds), "gui_cycles": gui,
                    "valu_busy_pct": 100.0 * act / (n_cu * gui) if gui else None,
                    "valu_lane_util_pct": 100.0 * avg("SQ_THREAD_CYCLES_VALU") / (64.0 * act) if act else None,
                    "valu_insts": avg("SQ_INSTS_VALU"), "salu_insts": avg("SQ_INSTS_SALU"),

@@ -44,7 +44,6 @@ struct sx_scene {
     uint32_t* d_mon = nullptr;
     uint32_t* d_nslots = nullptr;
     uint32_t* d_codes = nullptr;  // the first piece codes of each tag (count pass)
-    uint32_t* d_curves = nullptr; // the curve tags the count pass bisects
     uint64_t* d_base = nullptr;
     // per slot: the slot, its record count and record offset
     sx::Slot* d_slots = nullptr;
@@ -144,7 +143,6 @@ void free_scene(sx_scene* s) {
     dfree(s->d_mon);
     dfree(s->d_nslots);
     dfree(s->d_codes);
-    dfree(s->d_curves);
     dfree(s->d_base);
     dfree(s->d_slots);
     dfree(s->d_rc);
@@ -266,7 +264,6 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         // n <= c (at most 2^25, or kKeepCodes rows of c)
         regrow(s->d_codes, std::max<size_t>((size_t)1 << 25, (size_t)sx::mon_stride_of(c) * sx::kKeepCodes) *
                                sizeof(uint32_t));
-        regrow(s->d_curves, ((size_t)c + 1) * sizeof(uint32_t));
         regrow(s->d_base, ((size_t)c + 1) * sizeof(uint64_t));
         regrow(s->d_status_tags, sx::scan_status_bytes(c));
         regrow(s->d_status_nslots, sx::scan_status_bytes(c));
@@ -340,14 +337,14 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
                                         st);
         case kPhBisectCount:
             return sx::launch_bisect(view(s), cfg, t.bisect_range, sx::keep_codes_of(s->n_tags), (int)t.bisect_waves,
-                                     false, s->d_nslots, s->d_codes, nullptr, nullptr, 0, s->d_curves, s->d_ws_ctl,
-                                     stats, st);
+                                     false, s->d_nslots,
+                                     s->d_codes, nullptr, nullptr, 0, stats, st);
         case kPhScanSlots:
             return sx::launch_scan_counts(s->d_nslots, s->n_tags, s->d_base, ctl_block(s, 1), s->d_status_nslots, st);
         case kPhBisectWrite:
             return sx::launch_bisect(view(s), cfg, t.bisect_range, sx::keep_codes_of(s->n_tags), (int)t.bisect_waves,
-                                     true, s->d_nslots, s->d_codes, s->d_base, s->d_slots, s->slot_cap, nullptr,
-                                     nullptr, nullptr, st);
+                                     true, s->d_nslots,
+                                     s->d_codes, s->d_base, s->d_slots, s->slot_cap, nullptr, st);
         case kPhPieces:
             return sx::launch_slots(view(s), cfg, workspace(s), s->d_slots, n_slots_dev(s), s->slot_cap, s->d_rc,
                                     (int)t.piece_waves, stats, st);

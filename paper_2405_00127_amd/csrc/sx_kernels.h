@@ -15,8 +15,6 @@ struct WsCtl {
     unsigned long long items_total;  // units requested by all tiles
     unsigned long long slots_total;  // slots of the last expansion
     unsigned long long result[2];    // records and status, for synchronous readback
-    unsigned long long curve_n;      // curve tags listed for the bisection count pass
-    unsigned long long curve_next;   // next list entry a count-pass wave takes
 };
 struct ItemWs {
     Unit* units;
@@ -64,14 +62,9 @@ inline uint32_t keep_codes_of(uint32_t n) {
     const uint64_t k = (1ull << 25) / ((uint64_t)mon_stride_of(n) + 1u);
     return (uint32_t)(k < (uint64_t)kKeepCodes ? kKeepCodes : (k > 1024u ? 1024u : k));
 }
-// Algorithm 2 over every tag.  Count pass (write false): slots per tag and
-// the first `keep` piece codes, the curves taken from a scene-wide list by
-// persistent waves (curves: n_tags words; ctl: the list's counters, zeroed
-// at the start of the pass).  Write pass: every slot at its base, `range`
-// tags per wave.
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,
                          uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
-                         uint32_t* curves, WsCtl* ctl, unsigned long long* stats, hipStream_t s);
+                         unsigned long long* stats, hipStream_t s);
 // piece slots (one thread per slot)
 hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
                         const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,

@@ -3,15 +3,11 @@
 //  scan_tags_kernel       tag-monoid prefix scan (Section 8.2): single pass,
 //                         wave64 shuffle scan + LDS block scan + decoupled
 //                         look-back over dynamically numbered tiles.
-//  bisect_classify_kernel count pass of Algorithm 2, part 1: lines, markers
-//                         and invalid tags settled, curves listed.
-//  bisect_curves_kernel   count pass, part 2: persistent waves run Algorithm 2
-//                         in FP64 on the listed curves with lane refill from
-//                         the scene-wide list: slots per tag (pieces + 1
-//                         tail) and the codes of the first pieces.
-//  bisect_write_kernel    write pass: every slot {tag, code} at its canonical
-//                         position (a wave owns a range of tags; kept codes
-//                         copied, long segments bisected again).
+//  bisect_kernel          Algorithm 2 in FP64 with lane refill (a wave owns a
+//                         range of tags; a lane whose tag is done takes the
+//                         next).  Count pass: slots per tag (pieces + 1 tail)
+//                         and the codes of the first pieces; write pass: every
+//                         slot {tag, code} at its canonical position.
 //  scan_counts_kernel     exclusive scan of u32 counts into u64 offsets (slot
 //  scan_counts_dev_kernel bases; record offsets, with the count read on the
 //                         device).  Replaces the paper's atomic bump
@@ -371,34 +367,70 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 }
 
 // --------------------------------------------------------- bisection
-// Algorithm 2 in two passes.  The count pass (the two kernels below) writes,
-// per tag, its slot count (accepted pieces + 1 tail) and keeps the codes of
-// its first `keep` pieces (code q of tag i at codes[q * stride + i]).  The
+// One wave per workgroup owns `range` consecutive tags.  Every lane runs the
+// bisection of one segment at a time (Algorithm 2, one trial per loop turn);
+// a lane whose segment is done takes the wave's next tag (lane refill), so
+// the wave is busy until its range is exhausted instead of waiting for its
+// longest segment.  The count pass writes, per tag, its slot count (accepted
+// pieces + 1 tail) and keeps the codes of its first `keep` pieces (code
+// q of tag i at codes[q * stride + i], so the lanes of a wave, holding
+// consecutive tags, read and write consecutive words); the
 // write pass, after the scan of those counts, writes each tag's slots at
 // their canonical positions: copied from the kept codes, or, for the few
-// segments with more pieces, from a second run of the bisection.  In both,
-// every lane runs the bisection of one segment at a time (one trial per
-// loop turn) and a lane whose segment is done takes the next one (lane
-// refill), so a wave is not held by its longest segment.
+// segments with more pieces, from a second run of the bisection.
 constexpr int kBisectBlock = 64;
-constexpr uint32_t kBisectMaxRange = 1024;  // tags per write-pass wave (the autotuner's largest range)
+constexpr uint32_t kBisectMaxRange = 1024;  // tags per wave (the autotuner's largest range)
 constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (on the map scene 8 and 12 beat 4, 16 and 32)
 
-// Write pass: one wave per workgroup owns `range` consecutive tags.
-template <int MinWaves>
-__global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_write_kernel(
-    SceneView sv, Cfg cfg, uint32_t range, uint32_t keep, const uint32_t* __restrict__ nslots,
-    const uint32_t* __restrict__ codes, const uint64_t* __restrict__ base, Slot* __restrict__ slots,
-    uint64_t slot_cap) {
+template <bool Write, bool Stats, int MinWaves>
+__global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
+    SceneView sv, Cfg cfg, uint32_t range, uint32_t keep, uint32_t* __restrict__ nslots, uint32_t* __restrict__ codes,
+    const uint64_t* __restrict__ base, Slot* __restrict__ slots, uint64_t slot_cap,
+    unsigned long long* __restrict__ stats) {
     const uint32_t lane = threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const size_t cstride = mon_stride_of(sv.n_tags);  // row stride of the kept codes
     const uint32_t a = blockIdx.x * range;
     const uint32_t b = min(sv.n_tags, a + range);
-    uint32_t cursor = a;  // next unassigned tag (wave-uniform)
+    uint32_t n_trials = 0, n_lines = 0;
+    // Count pass: lines (one straight piece each, reading G32), markers and
+    // invalid tags need no bisection.  They are settled for the whole range
+    // first, 64 consecutive tags at a time, and only the curves are listed
+    // (in LDS) for the refill loop, so that a refill does not spend rounds
+    // of scattered loads on tags that take no trial.
+    __shared__ uint32_t s_curve[kBisectMaxRange];
+    uint32_t n_curve = 0;
+    if (!Write) {
+        for (uint32_t t0 = a; t0 < b; t0 += 64u) {
+            const uint32_t it = t0 + lane;
+            bool curve = false;
+            if (it < b) {
+                bool line;
+                const int kind = tag_kind(sv, it, line);
+                if (kind == kTagSegment && !line) {
+                    curve = true;
+                } else if (kind == kTagSegment) {
+                    nslots[it] = 2u;
+                    codes[it] = slot_code(0u, 0u, false) | kCodeLine;
+                    if (Stats) n_lines++;
+                } else {
+                    nslots[it] = 1u;  // markers and invalid tags own only their tail slot
+                }
+            }
+            const uint64_t m = __ballot(curve);
+            if (curve) s_curve[n_curve + (uint32_t)__popcll(m & below)] = it;
+            n_curve += (uint32_t)__popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // the refill loop's work list: the range's curves (count pass) or its tags
+    uint32_t cursor = Write ? a : 0u;  // next unassigned entry (wave-uniform)
+    const uint32_t cend = Write ? b : n_curve;
     bool busy = false;
     uint32_t i = 0, seq = 0;
-    uint64_t bi = 0;  // slot base of the lane's tag
+    uint64_t bi = 0;  // slot base of the lane's tag (write pass)
     TagInfo ti;
     Seg s;
     Bisect bs;
@@ -407,26 +439,41 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_write_kernel(
         // lanes are idle (a refill fetches segments: its latency is shared by
         // the lanes it serves) or the wave has nothing left to run
         const uint64_t idle = __ballot(!busy);
-        if (idle && cursor < b && (__popcll(idle) >= kRefillLanes || __ballot(busy) == 0ull)) {
+        if (idle && cursor < cend && (__popcll(idle) >= kRefillLanes || __ballot(busy) == 0ull)) {
             const uint32_t ni = cursor + (uint32_t)__popcll(idle & below);
             cursor += (uint32_t)__popcll(idle);
-            if (!busy && ni < b) {
-                i = ni;
+            if (!busy && ni < cend) {
+                i = Write ? ni : s_curve[ni];
                 seq = 0;
-                bi = base[i];
-                const uint32_t np = nslots[i] - 1u;
-                if (np <= keep) {
-                    // pieces known from the count pass: copy them and the tail
-                    for (uint32_t q = 0; q < np; q++)
-                        if (bi + q < slot_cap) slots[bi + q] = Slot{i, codes[q * cstride + i]};
-                    if (bi + np < slot_cap) slots[bi + np] = Slot{i, kSlotTail};
+                bool copied = false;
+                if (Write) {
+                    bi = base[i];
+                    const uint32_t np = nslots[i] - 1u;
+                    if (np <= keep) {
+                        // pieces known from the count pass: copy them and the tail
+                        for (uint32_t q = 0; q < np; q++)
+                            if (bi + q < slot_cap) slots[bi + q] = Slot{i, codes[q * cstride + i]};
+                        if (bi + np < slot_cap) slots[bi + np] = Slot{i, kSlotTail};
+                        copied = true;
+                    }
+                }
+                if (!copied) fetch_tag(sv, i, ti, s);
+                if (copied) {
+                    // done with this tag
+                } else if (!Write && ti.kind == kTagSegment && ti.line) {
+                    // a line is one straight piece (reading G32): no bisection
+                    nslots[i] = 2u;
+                    codes[i] = slot_code(0u, 0u, false) | kCodeLine;
+                    if (Stats) n_lines++;
+                } else if (ti.kind == kTagSegment) {
+                    bisect_init(bs, s);
+                    busy = true;
                 } else {
-                    fetch_tag(sv, i, ti, s);
-                    if (ti.kind == kTagSegment) {
-                        bisect_init(bs, s);
-                        busy = true;
-                    } else if (bi < slot_cap) {
-                        slots[bi] = Slot{i, kSlotTail};  // (never reached: such tags have no pieces)
+                    // markers and invalid tags own only their tail slot
+                    if (Write) {
+                        if (bi < slot_cap) slots[bi] = Slot{i, kSlotTail};
+                    } else {
+                        nslots[i] = 1u;
                     }
                 }
             }
@@ -436,119 +483,34 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_write_kernel(
         if (busy) {
             uint32_t t0u = 0, depth = 0;
             bool done = false, pivot = false;
+            if (Stats) {
+                if (ti.line) n_lines++;
+                else n_trials++;
+            }
             if (bisect_step(bs, s, cfg, ti.line, t0u, depth, pivot, done)) {
-                const uint64_t at = bi + seq;
-                if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth, pivot)};
+                if (Write) {
+                    const uint64_t at = bi + seq;
+                    if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth, pivot)};
+                } else if (seq < keep) {
+                    codes[seq * cstride + i] = slot_code(t0u, depth, pivot);
+                }
                 seq++;
                 if (done) {
-                    if (bi + seq < slot_cap) slots[bi + seq] = Slot{i, kSlotTail};
+                    if (Write) {
+                        const uint64_t at = bi + seq;
+                        if (at < slot_cap) slots[at] = Slot{i, kSlotTail};
+                    } else {
+                        nslots[i] = seq + 1u;
+                    }
                     busy = false;
                 }
             }
         }
     }
-}
-
-// the count pass's list counters start at zero (a kernel, so that the
-// pass stays graph-capturable and does not depend on the tag scan)
-__global__ void bisect_list_reset_kernel(WsCtl* ctl) {
-    if (threadIdx.x == 0) {
-        ctl->curve_n = 0;
-        ctl->curve_next = 0;
-    }
-}
-
-// Count pass, part 1 (one thread per tag): lines take their one straight
-// piece (reading G32), markers and invalid tags only their tail slot; the
-// curves are listed for part 2, one atomic per wave reserving the wave's
-// entries (the list's order is free: the count pass writes by tag).
-template <bool Stats>
-__global__ __launch_bounds__(256) void bisect_classify_kernel(SceneView sv, uint32_t* __restrict__ nslots,
-                                                              uint32_t* __restrict__ codes,
-                                                              uint32_t* __restrict__ curves, WsCtl* ctl,
-                                                              unsigned long long* __restrict__ stats) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, lane = threadIdx.x & 63u;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    bool curve = false, line_seg = false;
-    if (i < sv.n_tags) {
-        bool line;
-        const int kind = tag_kind(sv, i, line);
-        if (kind == kTagSegment && !line) {
-            curve = true;
-        } else if (kind == kTagSegment) {
-            nslots[i] = 2u;
-            codes[i] = slot_code(0u, 0u, false) | kCodeLine;
-            line_seg = true;
-        } else {
-            nslots[i] = 1u;
-        }
-    }
-    const uint64_t m = __ballot(curve);
-    uint64_t at = 0;
-    if (lane == 0 && m) at = atomicAdd(&ctl->curve_n, (unsigned long long)__popcll(m));
-    at = __shfl(at, 0);
-    const uint64_t e = at + (uint64_t)__popcll(m & below);
-    if (curve && e < sv.n_tags) curves[e] = i;  // (the list holds at most one entry per tag)
     if (Stats) {
-        const uint64_t ml = __ballot(line_seg);
-        if (lane == 0 && ml) atomicAdd(&stats[kStLines], (unsigned long long)__popcll(ml));
+        atomicAdd(&stats[kStTrials], (unsigned long long)n_trials);
+        atomicAdd(&stats[kStLines], (unsigned long long)n_lines);
     }
-}
-
-// Count pass, part 2: persistent waves run Algorithm 2 on the listed curves
-// with lane refill, taking the next entries of the scene-wide list with one
-// atomic per refill, so no wave idles while curves remain anywhere (a range
-// of tags per wave holds fewer curves than lanes and spends most of its time
-// draining).  Every wave exits once the list is taken and its lanes are done.
-template <bool Stats, int MinWaves>
-__global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_curves_kernel(
-    SceneView sv, Cfg cfg, uint32_t keep, uint32_t* __restrict__ nslots, uint32_t* __restrict__ codes,
-    const uint32_t* __restrict__ curves, WsCtl* ctl, unsigned long long* __restrict__ stats) {
-    const uint32_t lane = threadIdx.x;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const size_t cstride = mon_stride_of(sv.n_tags);  // row stride of the kept codes
-    const uint64_t listed = ctl->curve_n;            // written by part 1 (an earlier launch)
-    const uint64_t total = listed < sv.n_tags ? listed : sv.n_tags;
-    bool more = true;                                // entries may remain (wave-uniform)
-    bool busy = false;
-    uint32_t i = 0, seq = 0, n_trials = 0;
-    TagInfo ti;
-    Seg s;
-    Bisect bs;
-    for (;;) {
-        const uint64_t idle = __ballot(!busy);
-        if (idle && more && (__popcll(idle) >= kRefillLanes || __ballot(busy) == 0ull)) {
-            const uint32_t k = (uint32_t)__popcll(idle);
-            uint64_t start = 0;
-            if (lane == 0) start = atomicAdd(&ctl->curve_next, (unsigned long long)k);
-            start = __shfl(start, 0);
-            if (start + k >= total) more = false;
-            const uint64_t e = start + (uint64_t)__popcll(idle & below);
-            if (!busy && e < total) {
-                i = curves[e];
-                seq = 0;
-                fetch_tag(sv, i, ti, s);
-                bisect_init(bs, s);
-                busy = true;
-            }
-            continue;
-        }
-        if (__ballot(busy) == 0ull) break;
-        if (busy) {
-            uint32_t t0u = 0, depth = 0;
-            bool done = false, pivot = false;
-            if (Stats) n_trials++;
-            if (bisect_step(bs, s, cfg, false, t0u, depth, pivot, done)) {
-                if (seq < keep) codes[seq * cstride + i] = slot_code(t0u, depth, pivot);
-                seq++;
-                if (done) {
-                    nslots[i] = seq + 1u;
-                    busy = false;
-                }
-            }
-        }
-    }
-    if (Stats && n_trials) atomicAdd(&stats[kStTrials], (unsigned long long)n_trials);
 }
 
 // ------------------------------------------------------------- slots
@@ -1062,57 +1024,37 @@ hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uin
     return hipGetLastError();
 }
 
-static void bisect_write_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg,
-                                uint32_t range, uint32_t keep, const uint32_t* nslots, const uint32_t* codes,
-                                const uint64_t* base, Slot* slots, uint64_t cap) {
+template <bool Write, bool Stats>
+static void bisect_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, uint32_t range,
+                          uint32_t keep, uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots,
+                          uint64_t cap, unsigned long long* stats) {
     if (waves <= 2)
-        bisect_write_kernel<2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap);
+        bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+                                                                stats);
     else if (waves == 3)
-        bisect_write_kernel<3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap);
+        bisect_kernel<Write, Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+                                                                stats);
     else
-        bisect_write_kernel<4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap);
-}
-template <bool Stats>
-static void bisect_count_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg,
-                                uint32_t keep, uint32_t* nslots, uint32_t* codes, const uint32_t* curves, WsCtl* ctl,
-                                unsigned long long* stats) {
-    if (waves <= 2)
-        bisect_curves_kernel<Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, keep, nslots, codes, curves, ctl, stats);
-    else if (waves == 3)
-        bisect_curves_kernel<Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, keep, nslots, codes, curves, ctl, stats);
-    else
-        bisect_curves_kernel<Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, keep, nslots, codes, curves, ctl, stats);
+        bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+                                                                stats);
 }
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,
                          uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
-                         uint32_t* curves, WsCtl* ctl, unsigned long long* stats, hipStream_t s) {
+                         unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     if (range == 0 || range % 64u || range > kBisectMaxRange || keep < (uint32_t)kKeepCodes)
         return hipErrorInvalidValue;
-    if (!write) {
-        // part 1 over every tag, then persistent waves: as many as the chip
-        // holds (256 CUs x 4 SIMDs x 4), fewer for a small scene (one per
-        // 64 tags)
-        const uint32_t g1 = (sv.n_tags + 255u) / 256u;
-        const uint32_t resident = 256u * 4u * 4u;  // every bisection variant fits four waves per SIMD
-        const uint32_t need = (sv.n_tags + 63u) / 64u;
-        const uint32_t g2 = need < resident ? need : resident;
-        bisect_list_reset_kernel<<<1, 64, 0, s>>>(ctl);
-        if (stats) {
-            bisect_classify_kernel<true><<<g1, 256, 0, s>>>(sv, nslots, codes, curves, ctl, stats);
-            bisect_count_launch<true>(g2, s, waves, sv, cfg, keep, nslots, codes, curves, ctl, stats);
-        } else {
-            bisect_classify_kernel<false><<<g1, 256, 0, s>>>(sv, nslots, codes, curves, ctl, stats);
-            bisect_count_launch<false>(g2, s, waves, sv, cfg, keep, nslots, codes, curves, ctl, stats);
-        }
-        return hipGetLastError();
-    }
     // a scene too small to give every SIMD a wave at this range takes
     // shorter ranges (down to one tag per lane)
     const uint32_t fill = ((sv.n_tags / 4096u + 63u) / 64u) * 64u;
     if (fill < range) range = fill < 64u ? 64u : fill;
     const uint32_t g = (sv.n_tags + range - 1) / range;
-    bisect_write_launch(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap);
+    if (write)
+        bisect_launch<true, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+    else if (stats)
+        bisect_launch<false, true>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+    else
+        bisect_launch<false, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
     return hipGetLastError();
 }
 template <bool Newton>
