@@ -49,6 +49,9 @@ def _mixed_scenes(mode):
         S.with_fills(S.scene_map(15, 4000, 30, 0.25, mode)),
         S.with_fills(S.scene_c1(1, output_mode=mode).subset(range(5)), 0.5, seed=2,
                      xform=[1.0, 0.2, 0.5, 0.9, 10.0, -5.0]),
+        # dashed scenes are ordinary scenes once encoded
+        S.with_dashes(S.scene_map(16, 3000, 20, 0.25, mode), seed=5, lo=0.5, hi=12.0),
+        S.with_dashes(S.scene_c1(1, output_mode=mode).subset(range(4)), seed=6),
     ]
 
 
