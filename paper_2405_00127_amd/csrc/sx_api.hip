@@ -58,7 +58,7 @@ struct sx_scene {
     float* d_es = nullptr;  // per-slot spiral records
     uint32_t* d_tile_n = nullptr;
     sx::WsCtl* d_ws_ctl = nullptr;
-    uint32_t region_per_slot = 0;  // item units per slot in the per-tile regions
+    uint32_t region_per_piece = 0;  // item units per piece in the per-tile regions
     uint64_t ovf_cap = 0;          // shared overflow units
     uint64_t slot_cap = 0;         // slots the slot buffers hold
     // allocated capacities (a batch arena is reused for smaller contents)
@@ -109,7 +109,7 @@ void* scratch_ptr(int device) {
 
 constexpr uint32_t kMaxBatchScenes = 65535;
 constexpr uint32_t kSlotsPerTag = 4;        // initial slot capacity per tag
-constexpr uint32_t kRegionPerSlot = 3;      // initial item units per slot in the tile regions
+constexpr uint32_t kRegionPerPiece = 4;     // initial item units per piece in the tile regions
 constexpr uint64_t kMinSlots = 4096;
 constexpr uint64_t kMinOverflow = 65536;    // initial shared overflow units (minimum)
 constexpr uint32_t kMaxSlotCap = 0xfffff000u;  // slots are indexed by u32
@@ -198,7 +198,7 @@ sx::ItemWs workspace(const sx_scene* s) {
     w.tile_n = s->d_tile_n;
     w.ctl = s->d_ws_ctl;
     w.tile = sx::slot_block();
-    w.region_cap = s->region_per_slot * w.tile;
+    w.region_cap = s->region_per_piece * w.tile;
     w.ovf_base = (uint64_t)sx::slot_tiles(s->slot_cap) * w.region_cap;
     w.ovf_cap = s->ovf_cap;
     return w;
@@ -207,11 +207,12 @@ sx::ItemWs workspace(const sx_scene* s) {
 char* ctl_block(const sx_scene* s, int k) { return (char*)s->d_scan_ctl + k * sx::scan_ctl_bytes(); }
 
 // (Re)allocate the slot buffers for slot_cap slots and the item workspace
-// (region_per_slot 64-byte units per slot in the tile regions, ovf shared
-// units).
+// (region_per_piece 64-byte units per piece in the tile regions, one region
+// per slot_block() slots of capacity, since pieces never outnumber slots; ovf
+// shared units).
 // Scan status words are zeroed when allocated.  Ordered on st; allocation is
 // synchronous.
-hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_slot, uint64_t ovf, hipStream_t st) {
+hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_piece, uint64_t ovf, hipStream_t st) {
     hipError_t e = hipSuccess;
     auto A = [&](hipError_t r) {
         if (e == hipSuccess) e = r;
@@ -234,9 +235,9 @@ hipError_t size_slots(sx_scene* s, uint64_t slot_cap, uint32_t region_per_slot, 
         s->slot_cap = slot_cap;
     }
     dfree(s->d_items);
-    s->region_per_slot = region_per_slot;
+    s->region_per_piece = region_per_piece;
     s->ovf_cap = ovf;
-    const uint64_t items = (uint64_t)sx::slot_tiles(slot_cap) * sx::slot_block() * region_per_slot + ovf;
+    const uint64_t items = (uint64_t)sx::slot_tiles(slot_cap) * sx::slot_block() * region_per_piece + ovf;
     return dalloc(&s->d_items, items * sizeof(sx::Unit));
 }
 
@@ -274,7 +275,7 @@ hipError_t reserve_scene(sx_scene* s, uint32_t n_tags, uint32_t n_pts, uint32_t 
         A(hipMemsetAsync(s->d_status_nslots, 0, sx::scan_status_bytes(c), st));
         const uint64_t want = std::max<uint64_t>((uint64_t)c * kSlotsPerTag, kMinSlots);
         if (want > s->slot_cap) {
-            const uint32_t region = s->region_per_slot ? s->region_per_slot : kRegionPerSlot;
+            const uint32_t region = s->region_per_piece ? s->region_per_piece : kRegionPerPiece;
             A(size_slots(s, std::min<uint64_t>(want, kMaxSlotCap), region,
                          std::max<uint64_t>(std::max<uint64_t>(want, s->ovf_cap), kMinOverflow), st));
         }
@@ -354,8 +355,8 @@ hipError_t run_one(const sx_ctx* ctx, const sx_scene* s, const sx::Cfg& cfg, int
             return sx::launch_scan_counts_dev(s->d_rc, n_slots_dev(s), (uint32_t)s->slot_cap, s->d_roff,
                                               ctl_block(s, 2), s->d_status_rc, st);
         case kPhRecords:
-            return sx::launch_records(view(s), workspace(s), cfg, s->d_roff, n_slots_dev(s), s->slot_cap, out,
-                                      cap_records, st);
+            return sx::launch_records(view(s), workspace(s), cfg, s->d_roff, s->d_slots, n_slots_dev(s), s->slot_cap,
+                                      out, cap_records, st);
     }
     return hipErrorInvalidValue;
 }
@@ -398,10 +399,11 @@ int run_sized(sx_ctx* ctx, sx_scene* s, const sx::Cfg& cfg, void* out, uint64_t 
         if (w.slots_total > s->slot_cap) {
             if (w.slots_total > kMaxSlotCap) return fail(ctx, SX_ENOMEM, "scene needs more than 2^32 slots");
             const uint64_t cap = std::min<uint64_t>(w.slots_total + w.slots_total / 4 + 64, kMaxSlotCap);
-            e = size_slots(s, cap, s->region_per_slot, std::max<uint64_t>(s->ovf_cap, cap), st);
+            e = size_slots(s, cap, s->region_per_piece, std::max<uint64_t>(s->ovf_cap, cap), st);
         } else {
-            const uint64_t per = (w.items_total * 5 / 4 + w.slots_total - 1) / std::max<uint64_t>(w.slots_total, 1);
-            const uint32_t region = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per, kRegionPerSlot), 64);
+            const uint64_t pieces = std::max<uint64_t>(w.slots_total - std::min<uint64_t>(w.slots_total, s->n_tags), 1);
+            const uint64_t per = (w.items_total * 5 / 4 + pieces - 1) / pieces;
+            const uint32_t region = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(per, kRegionPerPiece), 64);
             e = size_slots(s, s->slot_cap, region, std::max<uint64_t>(w.items_total, kMinOverflow), st);
         }
         if (e != hipSuccess) return hip_fail(ctx, e, "workspace allocation");

@@ -8,8 +8,9 @@
 namespace sx {
 
 // Item workspace of the slot / record kernels: one region of region_cap
-// 64-byte units per slot tile, then ovf_cap shared overflow units at
-// ovf_base; and the per-slot spiral records (8 floats per slot).
+// 64-byte units per piece tile (the slots from its first piece to the next
+// tile's), then ovf_cap shared overflow units at ovf_base; and the per-slot
+// spiral records (8 floats per slot).
 struct WsCtl {
     unsigned long long ovf_n;        // overflow units requested
     unsigned long long items_total;  // units requested by all tiles
@@ -21,7 +22,7 @@ struct ItemWs {
     float* es_tab;
     uint32_t* tile_n;  // per slot tile: units requested (clamp to region_cap)
     WsCtl* ctl;
-    uint32_t tile;        // slots per tile
+    uint32_t tile;        // pieces per tile
     uint32_t region_cap;  // units per tile
     uint64_t ovf_base, ovf_cap;
 };
@@ -62,17 +63,19 @@ inline uint32_t keep_codes_of(uint32_t n) {
     const uint64_t k = (1ull << 25) / ((uint64_t)mon_stride_of(n) + 1u);
     return (uint32_t)(k < (uint64_t)kKeepCodes ? kKeepCodes : (k > 1024u ? 1024u : k));
 }
+// The write pass fills pcs, the piece list: piece p of the scene (canonical
+// order) as {tag, code}, its slot being p + tag.
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,
-                         uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
+                         uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* pcs, uint64_t slot_cap,
                          unsigned long long* stats, hipStream_t s);
-// piece slots (one thread per slot)
-hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
+// pieces (one thread per piece, tiles of slot_block() pieces)
+hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* pcs,
                         const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
                         unsigned long long* stats, hipStream_t s);
 // tail slots (one thread per tag), after launch_slots
 hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const uint64_t* base,
                         uint64_t slot_cap, uint32_t* rc, unsigned long long* stats, hipStream_t s);
-hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff,
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff, const Slot* pcs,
                           const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s);
 // Single-pass expansion into an unordered line soup (one thread per tag;
 // records reserved with atomic adds on *counter, which ends at the total the

@@ -7,15 +7,17 @@
 //                         range of tags; a lane whose tag is done takes the
 //                         next).  Count pass: slots per tag (pieces + 1 tail)
 //                         and the codes of the first pieces; write pass: every
-//                         slot {tag, code} at its canonical position.
+//                         piece {tag, code} at its canonical position in the
+//                         piece list.
 //  scan_counts_kernel     exclusive scan of u32 counts into u64 offsets (slot
 //  scan_counts_dev_kernel bases; record offsets, with the count read on the
 //                         device).  Replaces the paper's atomic bump
 //                         allocation: the output order is canonical.
-//  slot_kernel            per piece slot, the Euler spiral, parallel curves,
-//                         cusp split, evolutes and counts (Sections 4-6).
-//                         Writes emission items into per-tile workspace
-//                         regions and the slot's record count.
+//  slot_kernel            per piece, the Euler spiral, parallel curves,
+//                         cusp split, evolutes and counts (Sections 4-6),
+//                         over tiles of 256 pieces.  Writes emission items
+//                         into per-tile workspace regions and the slot's
+//                         record count.
 //  tail_kernel            per tag, its tail slot: the join or cap
 //                         (Algorithm 1), items into the same regions.
 //  record_kernel          per item chunk, the FP32 per-point work: records
@@ -375,9 +377,11 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
 // pieces + 1 tail) and keeps the codes of its first `keep` pieces (code
 // q of tag i at codes[q * stride + i], so the lanes of a wave, holding
 // consecutive tags, read and write consecutive words); the
-// write pass, after the scan of those counts, writes each tag's slots at
-// their canonical positions: copied from the kept codes, or, for the few
-// segments with more pieces, from a second run of the bisection.
+// write pass, after the scan of those counts, writes each tag's pieces into
+// the scene's piece list (canonical order; the piece of ordinal p of tag i
+// has slot p + i, since every tag before it owns one tail slot besides its
+// pieces): copied from the kept codes, or, for the few segments with more
+// pieces, from a second run of the bisection.
 constexpr int kBisectBlock = 64;
 constexpr uint32_t kBisectMaxRange = 1024;  // tags per wave (the autotuner's largest range)
 constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (on the map scene 8 and 12 beat 4, 16 and 32)
@@ -385,7 +389,7 @@ constexpr int kRefillLanes = 8;  // idle lanes that trigger a refill (on the map
 template <bool Write, bool Stats, int MinWaves>
 __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
     SceneView sv, Cfg cfg, uint32_t range, uint32_t keep, uint32_t* __restrict__ nslots, uint32_t* __restrict__ codes,
-    const uint64_t* __restrict__ base, Slot* __restrict__ slots, uint64_t slot_cap,
+    const uint64_t* __restrict__ base, Slot* __restrict__ pcs, uint64_t slot_cap,
     unsigned long long* __restrict__ stats) {
     const uint32_t lane = threadIdx.x;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
     const uint32_t cend = Write ? b : n_curve;
     bool busy = false;
     uint32_t i = 0, seq = 0;
-    uint64_t bi = 0;  // slot base of the lane's tag (write pass)
+    uint64_t bi = 0;  // piece ordinal of the lane's tag's first piece (write pass)
     TagInfo ti;
     Seg s;
     Bisect bs;
@@ -447,13 +451,12 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 seq = 0;
                 bool copied = false;
                 if (Write) {
-                    bi = base[i];
+                    bi = base[i] - i;  // pieces of the tags before this one
                     const uint32_t np = nslots[i] - 1u;
                     if (np <= keep) {
-                        // pieces known from the count pass: copy them and the tail
+                        // pieces known from the count pass: copy them
                         for (uint32_t q = 0; q < np; q++)
-                            if (bi + q < slot_cap) slots[bi + q] = Slot{i, codes[q * cstride + i]};
-                        if (bi + np < slot_cap) slots[bi + np] = Slot{i, kSlotTail};
+                            if (bi + q < slot_cap) pcs[bi + q] = Slot{i, codes[q * cstride + i]};
                         copied = true;
                     }
                 }
@@ -468,13 +471,8 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
                 } else if (ti.kind == kTagSegment) {
                     bisect_init(bs, s);
                     busy = true;
-                } else {
-                    // markers and invalid tags own only their tail slot
-                    if (Write) {
-                        if (bi < slot_cap) slots[bi] = Slot{i, kSlotTail};
-                    } else {
-                        nslots[i] = 1u;
-                    }
+                } else if (!Write) {
+                    nslots[i] = 1u;  // markers and invalid tags own only their tail slot
                 }
             }
             continue;  // refill again until no idle lane can take a tag
@@ -490,18 +488,13 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
             if (bisect_step(bs, s, cfg, ti.line, t0u, depth, pivot, done)) {
                 if (Write) {
                     const uint64_t at = bi + seq;
-                    if (at < slot_cap) slots[at] = Slot{i, slot_code(t0u, depth, pivot)};
+                    if (at < slot_cap) pcs[at] = Slot{i, slot_code(t0u, depth, pivot)};
                 } else if (seq < keep) {
                     codes[seq * cstride + i] = slot_code(t0u, depth, pivot);
                 }
                 seq++;
                 if (done) {
-                    if (Write) {
-                        const uint64_t at = bi + seq;
-                        if (at < slot_cap) slots[at] = Slot{i, kSlotTail};
-                    } else {
-                        nslots[i] = seq + 1u;
-                    }
+                    if (!Write) nslots[i] = seq + 1u;
                     busy = false;
                 }
             }
@@ -514,7 +507,7 @@ __global__ __launch_bounds__(kBisectBlock, MinWaves) void bisect_kernel(
 }
 
 // ------------------------------------------------------------- slots
-constexpr int kSlotBlock = 256;   // slots per workgroup and per workspace tile
+constexpr int kSlotBlock = 256;   // pieces per workgroup and per workspace tile
 constexpr int kSlotGrid = 8192;   // persistent grid of the slot kernel (tiles stride by it)
 constexpr int kTailBlock = 256;   // tags per tail-kernel workgroup
 constexpr int kTailGrid = 8192;   // grid cap of the tail kernel (tags stride by it)
@@ -544,32 +537,46 @@ struct TileAlloc {
     }
 };
 
-// Work class of a slot for the in-tile ordering: curve pieces, line
-// pieces, tails (joins and caps).
-__device__ __forceinline__ uint32_t slot_class(Slot sl) {
-    if (sl.code == kSlotTail) return 2u;
-    return code_line(sl.code) ? 1u : 0u;
+// Piece tiles: tile T holds the pieces of ordinals [T, T + 1) x kSlotBlock
+// and owns the slots from the first of them up to the first slot of tile
+// T + 1 (so also the tails of the tags whose last piece it holds; tile 0
+// starts at slot 0, and there is always at least one tile).  Its item
+// region and its contiguous range of output records follow from that.
+__device__ __forceinline__ uint32_t piece_tile_count(uint64_t n_pieces) {
+    return n_pieces ? (uint32_t)((n_pieces + kSlotBlock - 1) / kSlotBlock) : 1u;
+}
+__device__ __forceinline__ uint64_t tile_first_slot(const Slot* pcs, uint32_t tile, uint32_t n_tiles,
+                                                    uint64_t n_slots) {
+    if (tile == 0u) return 0u;
+    if (tile >= n_tiles) return n_slots;
+    const uint64_t p = (uint64_t)tile * kSlotBlock;
+    return p + pcs[p].tag;
+}
+// The tile of tag i's tail slot: the tile of the last piece of tags 0..i.
+__device__ __forceinline__ uint64_t tail_tile(const uint64_t* base, uint32_t i) {
+    const uint64_t p = base[i + 1] - (uint64_t)(i + 1);  // pieces of tags 0..i
+    return p ? (p - 1u) / kSlotBlock : 0u;
 }
 
-// One thread per piece slot: the piece's Euler spiral and parallel curves
-// as emission items (records relative to the slot) and the slot's record
-// count.  Tiles of kSlotBlock slots are ordered by work class first (curve
-// pieces, line pieces), so a wave runs slots of one kind; tail slots are left
-// to tail_kernel.  Every side has one range, a few have a second one past a
+// One thread per piece: its Euler spiral and parallel curves as emission
+// items (records relative to the slot) and the slot's record count.  A tile
+// of kSlotBlock pieces is ordered by work class first (curve pieces, then
+// line pieces), so a wave runs pieces of one kind; the tails are done by
+// tail_kernel.  Every side has one range, a few have a second one past a
 // parallel-curve cusp: the counts of the first ranges run on the slot's own
 // thread, the second ranges of the whole block are packed onto its first
 // threads (the piece's k0, k1, L, width and cusp go through LDS), and then
 // each thread writes its piece's items in canonical order.
 template <int MinWaves, bool Stats, bool Newton>
 __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
-                                                                    const Slot* __restrict__ slots,
+                                                                    const Slot* __restrict__ pcs,
                                                                     const uint64_t* __restrict__ n_slots_dev,
                                                                     uint64_t slot_cap, uint32_t* __restrict__ rc,
                                                                     unsigned long long* __restrict__ stats) {
     __shared__ uint32_t s_n, s_ntask;
     __shared__ uint32_t s_order[kSlotBlock];
     __shared__ Slot s_slot[kSlotBlock];
-    __shared__ uint32_t s_hist[kSlotBlock / 64][3];
+    __shared__ uint32_t s_hist[kSlotBlock / 64][2];
     __shared__ uint32_t s_task[2 * kSlotBlock];     // owner thread << 2 | side << 1 | reversed
     __shared__ double s_own[kSlotBlock][4];        // k0, k1, L, w of the owner's piece
     __shared__ double s_tc[kSlotBlock][2];         // cusp u of each side
@@ -577,7 +584,8 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     __shared__ RangeRes s_first[2][kSlotBlock];    // each side's first range
     const uint64_t n_slots = *n_slots_dev;
     if (n_slots > slot_cap) return;  // reported by the finish kernel
-    const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
+    const uint64_t n_pieces = n_slots - sv.n_tags;
+    const uint32_t n_tiles = piece_tile_count(n_pieces);
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
@@ -587,36 +595,36 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
             s_n = 0u;
             s_ntask = 0u;
         }
-        const uint64_t j0 = first + t;
-        const Slot mine = j0 < n_slots ? slots[j0] : Slot{0u, kSlotTail};
-        const uint32_t cls = j0 < n_slots ? slot_class(mine) : 3u;
+        const uint64_t p0 = first + t;
+        const Slot mine = p0 < n_pieces ? pcs[p0] : Slot{0u, kSlotTail};
+        const uint32_t cls = p0 < n_pieces ? (code_line(mine.code) ? 1u : 0u) : 2u;
         uint32_t rank = 0;
 #pragma unroll
-        for (uint32_t c = 0; c < 3; c++) {
+        for (uint32_t c = 0; c < 2; c++) {
             const uint64_t m = __ballot(cls == c);
             if (cls == c) rank = (uint32_t)__popcll(m & below);
             if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
         }
         __syncthreads();
         uint32_t pos = rank;
-        for (uint32_t c = 0; c < 3; c++)
+        for (uint32_t c = 0; c < 2; c++)
             for (uint32_t w = 0; w < kSlotBlock / 64; w++)
                 if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
-        if (cls < 3u) {
+        if (cls < 2u) {
             s_order[pos] = t;
             s_slot[pos] = mine;
         }
-        uint32_t n_valid = 0;  // slots of this tile (the rest of s_order is unused)
-        for (uint32_t w = 0; w < kSlotBlock / 64; w++) n_valid += s_hist[w][0] + s_hist[w][1] + s_hist[w][2];
+        uint32_t n_valid = 0;  // pieces of this tile (the rest of s_order is unused)
+        for (uint32_t w = 0; w < kSlotBlock / 64; w++) n_valid += s_hist[w][0] + s_hist[w][1];
         __syncthreads();
         // phase 1: the piece's spiral, its sides and the first range of each
-        uint64_t j = 0;
+        uint64_t j = 0;  // the piece's slot
         Slot sl{0u, kSlotTail};
         if (t < n_valid) {
-            j = first + s_order[t];
             sl = s_slot[t];
+            j = first + s_order[t] + sl.tag;
         }
-        const bool act = t < n_valid && sl.code != kSlotTail;
+        const bool act = t < n_valid;
         TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
                      ws.ovf_cap};
         ItemSink<TileAlloc, Stats> k;
@@ -721,9 +729,9 @@ struct TailSink {
 
 // One thread per tag: its tail slot (the last of its slots, at
 // base[tag + 1] - 1) holds the join with the next segment or the cap
-// (Algorithm 1).  The items continue the regions of the tails' slot tiles
+// (Algorithm 1).  The items continue the regions of the tails' piece tiles
 // after the piece launch's items: a block's consecutive tags have increasing
-// tail slots spanning a few tiles, so it counts its units per tile in LDS and
+// tail tiles spanning a few tiles, so it counts its units per tile in LDS and
 // takes them from each tile's counter with one global atomic (per lane only
 // when the block spans more than kTailWin tiles).
 template <bool Stats>
@@ -742,8 +750,8 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
     for (uint32_t i0 = blockIdx.x * kTailBlock; i0 < n; i0 += gridDim.x * kTailBlock) {
         const uint32_t i = i0 + t;
         const uint32_t ilast = min(n, i0 + kTailBlock) - 1u;
-        const uint64_t tile_lo = (base[i0 + 1] - 1u) / kSlotBlock;
-        const uint64_t span = (base[ilast + 1] - 1u) / kSlotBlock - tile_lo + 1u;
+        const uint64_t tile_lo = tail_tile(base, i0);
+        const uint64_t span = tail_tile(base, ilast) - tile_lo + 1u;
         const bool win = span <= (uint64_t)kTailWin;
         if (t < kTailWin) s_cnt[t] = 0u;
         __syncthreads();
@@ -755,7 +763,7 @@ __global__ __launch_bounds__(kTailBlock, 3) void tail_kernel(SceneView sv, Cfg c
         uint32_t need = 0, local = 0;
         if (i < n) {
             slot = base[i + 1] - 1u;
-            tile = slot / kSlotBlock;
+            tile = tail_tile(base, i);
             TagInfo ti;
             Seg sg;
             fetch_tag(sv, i, ti, sg);
@@ -819,12 +827,13 @@ __device__ __forceinline__ void record_item(const SceneView& sv, const ItemWs& w
 template <bool Newton>
 __global__ __launch_bounds__(kRecBlock, Newton ? 3 : 6) void record_kernel(SceneView sv, ItemWs ws, int arcs,
                                                            const uint64_t* __restrict__ roff,
+                                                           const Slot* __restrict__ pcs,
                                                            const uint64_t* __restrict__ n_slots_dev, uint64_t slot_cap,
                                                            float* __restrict__ out, uint64_t cap_records, XIncF xi) {
     const uint64_t n_slots = *n_slots_dev;
     // nothing is written when the records exceed the capacity, or slots or items were dropped
     if (n_slots > slot_cap || roff[n_slots] > cap_records || ws.ctl->ovf_n > ws.ovf_cap) return;
-    const uint32_t n_tiles = (uint32_t)((n_slots + kSlotBlock - 1) / kSlotBlock);
+    const uint32_t n_tiles = piece_tile_count(n_slots - sv.n_tags);
     const uint32_t b = blockIdx.x;
     if (b < kRecGrid) {
         // a tile's units, one per thread (units in any order: every record's
@@ -837,8 +846,8 @@ __global__ __launch_bounds__(kRecBlock, Newton ? 3 : 6) void record_kernel(Scene
         for (uint32_t tile = b; tile < n_tiles; tile += kRecGrid) {
             const uint32_t cnt = ws.tile_n[tile] < ws.region_cap ? ws.tile_n[tile] : ws.region_cap;
             const Unit* base = ws.units + (uint64_t)tile * ws.region_cap;
-            const uint64_t s_lo = (uint64_t)tile * kSlotBlock;
-            const uint64_t s_hi = s_lo + kSlotBlock < n_slots ? s_lo + kSlotBlock : n_slots;
+            const uint64_t s_lo = tile_first_slot(pcs, tile, n_tiles, n_slots);
+            const uint64_t s_hi = tile_first_slot(pcs, tile + 1u, n_tiles, n_slots);
             const uint64_t lo = roff[s_lo];
             const uint64_t n_rec = roff[s_hi] - lo;
             // (a tile whose items spilled into the overflow area is not
@@ -1026,20 +1035,20 @@ hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uin
 
 template <bool Write, bool Stats>
 static void bisect_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, uint32_t range,
-                          uint32_t keep, uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots,
+                          uint32_t keep, uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* pcs,
                           uint64_t cap, unsigned long long* stats) {
     if (waves <= 2)
-        bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+        bisect_kernel<Write, Stats, 2><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, pcs, cap,
                                                                 stats);
     else if (waves == 3)
-        bisect_kernel<Write, Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+        bisect_kernel<Write, Stats, 3><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, pcs, cap,
                                                                 stats);
     else
-        bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, slots, cap,
+        bisect_kernel<Write, Stats, 4><<<g, kBisectBlock, 0, s>>>(sv, cfg, range, keep, nslots, codes, base, pcs, cap,
                                                                 stats);
 }
 hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, uint32_t keep, int waves, bool write,
-                         uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* slots, uint64_t slot_cap,
+                         uint32_t* nslots, uint32_t* codes, const uint64_t* base, Slot* pcs, uint64_t slot_cap,
                          unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     if (range == 0 || range % 64u || range > kBisectMaxRange || keep < (uint32_t)kKeepCodes)
@@ -1050,36 +1059,36 @@ hipError_t launch_bisect(const SceneView& sv, const Cfg& cfg, uint32_t range, ui
     if (fill < range) range = fill < 64u ? 64u : fill;
     const uint32_t g = (sv.n_tags + range - 1) / range;
     if (write)
-        bisect_launch<true, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+        bisect_launch<true, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, pcs, slot_cap, stats);
     else if (stats)
-        bisect_launch<false, true>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+        bisect_launch<false, true>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, pcs, slot_cap, stats);
     else
-        bisect_launch<false, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, slots, slot_cap, stats);
+        bisect_launch<false, false>(g, s, waves, sv, cfg, range, keep, nslots, codes, base, pcs, slot_cap, stats);
     return hipGetLastError();
 }
 template <bool Newton>
 static void slot_launch(uint32_t g, hipStream_t s, int waves, const SceneView& sv, const Cfg& cfg, const ItemWs& ws,
-                        const Slot* slots, const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc,
+                        const Slot* pcs, const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc,
                         unsigned long long* stats) {
     if (stats)
-        slot_kernel<1, true, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<1, true, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, pcs, n_slots_dev, slot_cap, rc, stats);
     else if (waves <= 1)
-        slot_kernel<1, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<1, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, pcs, n_slots_dev, slot_cap, rc, stats);
     else if (waves == 2)
-        slot_kernel<2, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<2, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, pcs, n_slots_dev, slot_cap, rc, stats);
     else
-        slot_kernel<3, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_kernel<3, false, Newton><<<g, kSlotBlock, 0, s>>>(sv, cfg, ws, pcs, n_slots_dev, slot_cap, rc, stats);
 }
-hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* slots,
+hipError_t launch_slots(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const Slot* pcs,
                         const uint64_t* n_slots_dev, uint64_t slot_cap, uint32_t* rc, int waves,
                         unsigned long long* stats, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     const uint32_t g = std::min<uint32_t>(kSlotGrid, std::max<uint32_t>(1u, slot_tiles(slot_cap)));
     // the exact-integral counts apply to line output only
     if (cfg.newton && !cfg.arcs)
-        slot_launch<true>(g, s, waves, sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_launch<true>(g, s, waves, sv, cfg, ws, pcs, n_slots_dev, slot_cap, rc, stats);
     else
-        slot_launch<false>(g, s, waves, sv, cfg, ws, slots, n_slots_dev, slot_cap, rc, stats);
+        slot_launch<false>(g, s, waves, sv, cfg, ws, pcs, n_slots_dev, slot_cap, rc, stats);
     return hipGetLastError();
 }
 hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, const uint64_t* base,
@@ -1090,17 +1099,17 @@ hipError_t launch_tails(const SceneView& sv, const Cfg& cfg, const ItemWs& ws, c
     else tail_kernel<false><<<g, kTailBlock, 0, s>>>(sv, cfg, ws, base, slot_cap, rc, stats);
     return hipGetLastError();
 }
-hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff,
+hipError_t launch_records(const SceneView& sv, const ItemWs& ws, const Cfg& cfg, const uint64_t* roff, const Slot* pcs,
                           const uint64_t* n_slots_dev, uint64_t slot_cap, void* out, uint64_t cap, hipStream_t s) {
     if (sv.n_tags == 0) return hipSuccess;
     XIncF xi;
     for (int k = 0; k < 5; k++) xi.v[k] = (float)cfg.xinc[k];
     // exact-density items exist only with line output in the Newton mode
     if (cfg.newton && !cfg.arcs)
-        record_kernel<true><<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, n_slots_dev, slot_cap,
-                                                                        (float*)out, cap, xi);
+        record_kernel<true><<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, pcs, n_slots_dev,
+                                                                        slot_cap, (float*)out, cap, xi);
     else
-        record_kernel<false><<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, n_slots_dev,
+        record_kernel<false><<<kRecGrid + kOvfBlocks, kRecBlock, 0, s>>>(sv, ws, cfg.arcs, roff, pcs, n_slots_dev,
                                                                          slot_cap, (float*)out, cap, xi);
     return hipGetLastError();
 }

@@ -148,6 +148,58 @@ def test_outline_parity(ctx, name):
     assert P.closed_per_path(recs) == 0
 
 
+def _tile_edge_scene(name, mode):
+    """Scenes whose piece counts fall on and around the 256-piece tiles of the
+    piece launch (lines are one piece each; open subpaths end in a cap marker,
+    a tag without pieces whose tail joins the tile of the piece before it)."""
+    rng = np.random.default_rng({"exact256": 1, "exact512": 2, "mixed": 3}[name])
+    b = S.SceneBuilder()
+
+    def poly(n, closed=False):
+        pts = np.cumsum(rng.uniform(-4, 4, (n + 1, 2)), 0) + 300
+        b.add_path([S.MOVE] + [S.LINE] * n + ([S.CLOSE] if closed else []), pts, int(rng.integers(0, 3)))
+
+    if name == "exact256":
+        poly(256)
+    elif name == "exact512":
+        poly(200)
+        poly(312)
+    else:
+        for n in [255, 1, 256, 257, 511, 1, 512]:
+            poly(n, closed=bool(rng.integers(0, 2)))
+        for _ in range(600):  # one piece and one marker each
+            poly(1)
+        for _ in range(40):  # wide cubics: several pieces per tag, straddling tiles
+            p = rng.uniform(0, 200, (4, 2))
+            b.add_path([S.MOVE, S.CUBIC], p, 2)
+        poly(300)
+    styles = S.make_styles([0.5, 2.0, 12.0], S.JOIN_ROUND, S.CAP_ROUND)
+    return b.build(styles, name=name, output_mode=mode)
+
+
+@pytest.mark.parametrize("mode", [S.OUT_LINES, S.OUT_ARCS])
+@pytest.mark.parametrize("name", ["exact256", "exact512", "mixed"])
+def test_piece_tile_edges(ctx, name, mode):
+    """A tile of the piece launch holds 256 pieces and owns the slots from its
+    first piece to the next tile's first (with the tails between them):
+    scenes of exactly one and two full tiles, and polylines of 255, 256,
+    257, 511 and 512 lines, single-line subpaths and multi-piece cubics whose
+    pieces straddle tile boundaries, against the oracle."""
+    sc = _tile_edge_scene(name, mode)
+    scene, counts, recs = _expand(ctx, sc)
+    ref = O.expand(sc)
+    assert ref.status == 0
+    n_pieces = len(ref.pieces)
+    _say("tile edges", name, mode, "tags", len(counts), "pieces", n_pieces)
+    assert n_pieces == {"exact256": 256, "exact512": 512}.get(name, n_pieces)
+    rep = P.compare(counts, recs, ref, sc.output_mode)
+    assert rep.n_unexplained == 0, rep
+    assert rep.worst_endpoint <= P.ENDPOINT_TOL, rep
+    assert rep.worst_sweep <= P.SWEEP_TOL, rep
+    assert rep.bad_path_ids == 0
+    assert P.closed_per_path(recs) == 0
+
+
 def test_offsets_are_the_scan_of_the_counts(ctx):
     sc = _scene("c2_lines")
     scene = ctx.encode(sc)
