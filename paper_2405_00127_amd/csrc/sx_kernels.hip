@@ -563,17 +563,18 @@ __device__ __forceinline__ uint64_t tail_tile(const uint64_t* base, uint32_t i) 
 // of kSlotBlock pieces is ordered by work class first (curve pieces, then
 // line pieces), so a wave runs pieces of one kind; the tails are done by
 // tail_kernel.  Every side has one range, a few have a second one past a
-// parallel-curve cusp: the counts of the first ranges run on the slot's own
-// thread, the second ranges of the whole block are packed onto its first
-// threads (the piece's k0, k1, L, width and cusp go through LDS), and then
-// each thread writes its piece's items in canonical order.
+// parallel-curve cusp: the counts of the first ranges run on the piece's own
+// thread, the second ranges of each wave are packed onto its first lanes
+// (the piece's k0, k1, L, width and cusp go through the wave's part of LDS,
+// so no block barrier is needed), and then each thread writes its piece's
+// items in canonical order.
 template <int MinWaves, bool Stats, bool Newton>
 __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv, Cfg cfg, ItemWs ws,
                                                                     const Slot* __restrict__ pcs,
                                                                     const uint64_t* __restrict__ n_slots_dev,
                                                                     uint64_t slot_cap, uint32_t* __restrict__ rc,
                                                                     unsigned long long* __restrict__ stats) {
-    __shared__ uint32_t s_n, s_ntask;
+    __shared__ uint32_t s_n;
     __shared__ uint32_t s_order[kSlotBlock];
     __shared__ Slot s_slot[kSlotBlock];
     __shared__ uint32_t s_hist[kSlotBlock / 64][2];
@@ -591,10 +592,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
     for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const uint64_t first = (uint64_t)tile * kSlotBlock;
-        if (t == 0) {
-            s_n = 0u;
-            s_ntask = 0u;
-        }
+        if (t == 0) s_n = 0u;
         const uint64_t p0 = first + t;
         const Slot mine = p0 < n_pieces ? pcs[p0] : Slot{0u, kSlotTail};
         const uint32_t cls = p0 < n_pieces ? (code_line(mine.code) ? 1u : 0u) : 2u;
@@ -663,33 +661,42 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                     s_tc[t][0] = g0.tc;
                     s_tc[t][1] = g1.tc;
                 }
-                if (g0.split) {
-                    qa = atomicAdd(&s_ntask, 1u);
-                    s_task[qa] = (t << 2) | (g0.rev2 ? 1u : 0u);
-                }
-                if (g1.split) {
-                    qb = atomicAdd(&s_ntask, 1u);
-                    s_task[qb] = (t << 2) | 2u | (g1.rev2 ? 1u : 0u);
-                }
             }
         }
-        __syncthreads();
-        // phase 2: the second ranges of the block, packed
-        const uint32_t n_task = s_ntask;
-        for (uint32_t q = t; q < n_task; q += kSlotBlock) {
-            const uint32_t task = s_task[q], own = task >> 2, side = (task >> 1) & 1u;
+        // phase 2: the second ranges of the wave, packed onto its first lanes
+        // (wave-private LDS: no block barrier)
+        const bool sp0 = have && g0.split, sp1 = have && g1.split;
+        const uint64_t m0 = __ballot(sp0), m1 = __ballot(sp1);
+        const uint32_t n0 = (uint32_t)__popcll(m0), n_task = n0 + (uint32_t)__popcll(m1);
+        uint32_t* w_task = s_task + wv * 128u;
+        RangeRes* w_res = s_res + wv * 128u;
+        if (sp0) {
+            qa = (uint32_t)__popcll(m0 & below);
+            w_task[qa] = (t << 2) | (g0.rev2 ? 1u : 0u);
+        }
+        if (sp1) {
+            qb = n0 + (uint32_t)__popcll(m1 & below);
+            w_task[qb] = (t << 2) | 2u | (g1.rev2 ? 1u : 0u);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (uint32_t q = lane; q < n_task; q += 64u) {
+            const uint32_t task = w_task[q], own = task >> 2, side = (task >> 1) & 1u;
             const double w = s_own[own][3];
-            s_res[q] = range_count<Newton>(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w,
+            w_res[q] = range_count<Newton>(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w,
                                            s_tc[own][side], 1.0, (task & 1u) != 0u);
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         // phase 3: the items of each piece in canonical order
         if (have) {
             range_put(k, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
-            if (g0.split) range_put(k, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, s_res[qa]);
+            if (g0.split) range_put(k, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, w_res[qa]);
             if (side1) {
                 range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
-                if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, s_res[qb]);
+                if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, w_res[qb]);
             }
         }
         if (act) {
