@@ -590,20 +590,33 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t first = (uint64_t)tile * kSlotBlock;
-        if (t == 0) s_n = 0u;
-        const uint64_t p0 = first + t;
-        const Slot mine = p0 < n_pieces ? pcs[p0] : Slot{0u, kSlotTail};
-        const uint32_t cls = p0 < n_pieces ? (code_line(mine.code) ? 1u : 0u) : 2u;
-        uint32_t rank = 0;
+    // A tile's work-class order: each thread's piece class, its rank among
+    // the wave's pieces of that class, and the wave's class counts in s_hist.
+    // The next tile's pieces are loaded early in the current one and ranked
+    // at its end, so the order costs no load latency and shares the tile-end
+    // barrier.
+    auto classify = [&](uint32_t tl, Slot& mine, uint32_t& cls, uint32_t& rank) {
+        const uint64_t p = (uint64_t)tl * kSlotBlock + t;
+        cls = (tl < n_tiles && p < n_pieces) ? (code_line(mine.code) ? 1u : 0u) : 2u;
+        rank = 0;
 #pragma unroll
         for (uint32_t c = 0; c < 2; c++) {
             const uint64_t m = __ballot(cls == c);
             if (cls == c) rank = (uint32_t)__popcll(m & below);
             if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
         }
-        __syncthreads();
+    };
+    auto load_piece = [&](uint32_t tl) {
+        const uint64_t p = (uint64_t)tl * kSlotBlock + t;
+        return (tl < n_tiles && p < n_pieces) ? pcs[p] : Slot{0u, kSlotTail};
+    };
+    Slot mine = load_piece(blockIdx.x);
+    uint32_t cls, rank;
+    classify(blockIdx.x, mine, cls, rank);
+    if (t == 0) s_n = 0u;
+    __syncthreads();
+    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const uint64_t first = (uint64_t)tile * kSlotBlock;
         uint32_t pos = rank;
         for (uint32_t c = 0; c < 2; c++)
             for (uint32_t w = 0; w < kSlotBlock / 64; w++)
@@ -623,6 +636,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
             j = first + s_order[t] + sl.tag;
         }
         const bool act = t < n_valid;
+        mine = load_piece(tile + gridDim.x);  // the next tile's, used at this tile's end
         TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
                      ws.ovf_cap};
         ItemSink<TileAlloc, Stats> k;
@@ -704,12 +718,16 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
             if (Stats)
                 for (int q = 0; q < kStN; q++) st[q] += k.st[q];
         }
+        // s_hist is free again (read before the barrier above): rank the
+        // next tile's pieces; the barrier then also ends this tile's items
+        classify(tile + gridDim.x, mine, cls, rank);
         __syncthreads();
         if (t == 0) {
+            // nobody allocates again before the next tile's first barrier
             ws.tile_n[tile] = s_n;
             atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
+            s_n = 0u;
         }
-        __syncthreads();
     }
     if (Stats) {
         for (int q = kStPieces; q <= kStEvolutes; q++)
