@@ -517,23 +517,26 @@ constexpr int kRecGrid = 8192;    // persistent grid of the record kernel
 constexpr uint32_t kStageWords = 6400;  // LDS words staging a tile's records (25 KB)
 constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the overflow slots
 
-// Slot allocator of one slot tile: the tile's own region first (LDS
-// counter), then the shared overflow region (global counter).
-struct TileAlloc {
-    Unit* units;
-    uint32_t* lds_n;
-    uint64_t region;
-    uint32_t region_cap;
-    unsigned long long* ovf_n;
-    uint64_t ovf_base, ovf_cap;
+// Unit allocation of the piece launch.  A piece's items are first counted
+// by a dry run of its puts (CountAlloc: nothing is written); the wave then
+// reserves the units of all its lanes with one LDS atomic on the tile's
+// counter, and each lane hands out its own reservation in order
+// (LaneAlloc).  A reservation that does not fit in the tile's region moves
+// as a whole to the shared overflow area (the part inside the region is
+// left empty).
+struct CountAlloc {
+    uint32_t n;
     __device__ uint64_t alloc(uint32_t nc) {
-        uint32_t s = atomicAdd(lds_n, nc);
-        if (s + nc <= region_cap) return region + s;
-        // the part of the request inside the region is left empty
-        for (uint32_t j = s; j < region_cap; j++) units[region + j].w[0] = 0u;
-        unsigned long long o = atomicAdd(ovf_n, (unsigned long long)nc);
-        if (o + nc <= ovf_cap) return ovf_base + o;
+        n += nc;
         return ~0ull;
+    }
+};
+struct LaneAlloc {
+    uint64_t next;  // next unit of the reservation, or ~0ull (dropped)
+    __device__ uint64_t alloc(uint32_t nc) {
+        const uint64_t u = next;
+        if (u != ~0ull) next = u + nc;
+        return u;
     }
 };
 
@@ -637,12 +640,10 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         }
         const bool act = t < n_valid;
         mine = load_piece(tile + gridDim.x);  // the next tile's, used at this tile's end
-        TileAlloc al{ws.units, &s_n, (uint64_t)tile * ws.region_cap, ws.region_cap, &ws.ctl->ovf_n, ws.ovf_base,
-                     ws.ovf_cap};
-        ItemSink<TileAlloc, Stats> k;
+        ItemSink<LaneAlloc, Stats> k;
         k.units = ws.units;
         k.es_tab = ws.es_tab;
-        k.al = al;
+        k.al.next = ~0ull;
         k.path = 0xffffffffu;
         k.slot = (uint32_t)j;
         k.n = 0;
@@ -704,15 +705,51 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // phase 3: the items of each piece in canonical order
-        if (have) {
-            range_put(k, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
-            if (g0.split) range_put(k, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, w_res[qa]);
+        // phase 3: the items of each piece in canonical order, into units
+        // reserved for the whole wave at once
+        auto put_all = [&](auto& sink) {
+            range_put(sink, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
+            if (g0.split) range_put(sink, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, w_res[qa]);
             if (side1) {
-                range_put(k, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
-                if (g1.split) range_put(k, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, w_res[qb]);
+                range_put(sink, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
+                if (g1.split)
+                    range_put(sink, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, w_res[qb]);
+            }
+        };
+        uint32_t need = 0;
+        if (have) {
+            ItemSink<CountAlloc, false> dry;
+            dry.units = ws.units;
+            dry.es_tab = ws.es_tab;
+            dry.al.n = 0;
+            dry.path = 0;
+            dry.slot = 0;
+            dry.n = 0;
+            put_all(dry);
+            need = dry.al.n;
+        }
+        uint32_t incl = need;
+#pragma unroll
+        for (uint32_t d = 1; d < 64; d *= 2) {
+            const uint32_t v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        const uint32_t wave_need = __shfl(incl, 63);
+        uint32_t wave_at = 0;
+        if (lane == 0 && wave_need) wave_at = atomicAdd(&s_n, wave_need);
+        wave_at = __shfl(wave_at, 0);
+        if (need) {
+            const uint32_t at = wave_at + incl - need;
+            const uint64_t region = (uint64_t)tile * ws.region_cap;
+            if (at + need <= ws.region_cap) {
+                k.al.next = region + at;
+            } else {
+                for (uint32_t u = at; u < ws.region_cap; u++) ws.units[region + u].w[0] = 0u;
+                const unsigned long long o = atomicAdd(&ws.ctl->ovf_n, (unsigned long long)need);
+                k.al.next = (o + need <= ws.ovf_cap) ? ws.ovf_base + o : ~0ull;
             }
         }
+        if (have) put_all(k);
         if (act) {
             rc[j] = k.n;
             if (Stats)
