@@ -171,9 +171,9 @@ def work_of(stats, n_tags, n_rec):
         # count read, u64 base written
         "scan_slots": n_tags * 12.0,
         "scan_records": n_slots * 12.0,
-        # the write pass writes every slot (8 B), reads the kept code of each
-        # piece (4 B) and each tag's slot count and base (12 B)
-        "bisect_write": n_slots * 8.0 + (n_slots - n_tags) * 4.0 + n_tags * 12.0,
+        # the write pass writes every piece into the piece list (8 B), reads
+        # its kept code (4 B) and each tag's slot count and base (12 B)
+        "bisect_write": stats["pieces"] * 12.0 + n_tags * 12.0,
     }
 
 
