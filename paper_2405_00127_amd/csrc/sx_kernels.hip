@@ -518,12 +518,12 @@ constexpr uint32_t kStageWords = 6400;  // LDS words staging a tile's records (2
 constexpr int kOvfBlocks = 512;   // record-kernel blocks striding over the overflow slots
 
 // Unit allocation of the piece launch.  A piece's items are first counted
-// by a dry run of its puts (CountAlloc: nothing is written); the wave then
-// reserves the units of all its lanes with one LDS atomic on the tile's
-// counter, and each lane hands out its own reservation in order
-// (LaneAlloc).  A reservation that does not fit in the tile's region moves
-// as a whole to the shared overflow area (the part inside the region is
-// left empty).
+// by a dry run of its puts (CountAlloc: nothing is written); the lane then
+// reserves them with one LDS atomic on its tile's counter (the address
+// differs between lanes, so this is a plain per-lane atomic, not a scalar
+// loop over the lanes) and hands its reservation out in order (LaneAlloc).
+// A reservation that does not fit in the tile's region moves as a whole to
+// the shared overflow area (the part inside the region is left empty).
 struct CountAlloc {
     uint32_t n;
     __device__ uint64_t alloc(uint32_t nc) {
@@ -531,6 +531,7 @@ struct CountAlloc {
         return ~0ull;
     }
 };
+constexpr uint32_t kPieceGroup = 4;  // piece tiles a piece-launch workgroup orders together
 struct LaneAlloc {
     uint64_t next;  // next unit of the reservation, or ~0ull (dropped)
     __device__ uint64_t alloc(uint32_t nc) {
@@ -562,10 +563,13 @@ __device__ __forceinline__ uint64_t tail_tile(const uint64_t* base, uint32_t i) 
 }
 
 // One thread per piece: its Euler spiral and parallel curves as emission
-// items (records relative to the slot) and the slot's record count.  A tile
-// of kSlotBlock pieces is ordered by work class first (curve pieces, then
-// line pieces), so a wave runs pieces of one kind; the tails are done by
-// tail_kernel.  Every side has one range, a few have a second one past a
+// items (records relative to the slot) and the slot's record count.  A
+// workgroup takes kPieceGroup consecutive piece tiles at a time and orders
+// their pieces by work class (curve pieces, then line pieces), so a wave runs
+// pieces of one kind and only one wave of the group mixes the two; it then
+// runs the order in passes of kSlotBlock pieces, each piece's items going to
+// its own tile's region.  The tails are done by tail_kernel.  Every side has
+// one range, a few have a second one past a
 // parallel-curve cusp: the counts of the first ranges run on the piece's own
 // thread, the second ranges of each wave are packed onto its first lanes
 // (the piece's k0, k1, L, width and cusp go through the wave's part of LDS,
@@ -577,10 +581,9 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                                                                     const uint64_t* __restrict__ n_slots_dev,
                                                                     uint64_t slot_cap, uint32_t* __restrict__ rc,
                                                                     unsigned long long* __restrict__ stats) {
-    __shared__ uint32_t s_n;
-    __shared__ uint32_t s_order[kSlotBlock];
-    __shared__ Slot s_slot[kSlotBlock];
-    __shared__ uint32_t s_hist[kSlotBlock / 64][2];
+    __shared__ uint32_t s_n[kPieceGroup];  // units taken in each tile of the group
+    __shared__ uint32_t s_order[kPieceGroup * kSlotBlock];  // group ordinal at each position of the class order
+    __shared__ uint32_t s_hist[kPieceGroup][kSlotBlock / 64][2];
     __shared__ uint32_t s_task[2 * kSlotBlock];     // owner thread << 2 | side << 1 | reversed
     __shared__ double s_own[kSlotBlock][4];        // k0, k1, L, w of the owner's piece
     __shared__ double s_tc[kSlotBlock][2];         // cusp u of each side
@@ -590,180 +593,172 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     if (n_slots > slot_cap) return;  // reported by the finish kernel
     const uint64_t n_pieces = n_slots - sv.n_tags;
     const uint32_t n_tiles = piece_tile_count(n_pieces);
+    const uint32_t n_groups = (n_tiles + kPieceGroup - 1) / kPieceGroup;
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
-    // A tile's work-class order: each thread's piece class, its rank among
-    // the wave's pieces of that class, and the wave's class counts in s_hist.
-    // The next tile's pieces are loaded early in the current one and ranked
-    // at its end, so the order costs no load latency and shares the tile-end
-    // barrier.
-    auto classify = [&](uint32_t tl, Slot& mine, uint32_t& cls, uint32_t& rank) {
-        const uint64_t p = (uint64_t)tl * kSlotBlock + t;
-        cls = (tl < n_tiles && p < n_pieces) ? (code_line(mine.code) ? 1u : 0u) : 2u;
-        rank = 0;
+    for (uint32_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
+        const uint64_t gfirst = (uint64_t)grp * kPieceGroup * kSlotBlock;
+        if (t < kPieceGroup) s_n[t] = 0u;
+        // the group's work-class order (curve pieces, then line pieces): each
+        // thread ranks its piece of every tile among its wave's pieces of that
+        // class, and the waves' class counts go to s_hist
+        uint32_t cls[kPieceGroup], rank[kPieceGroup];
 #pragma unroll
-        for (uint32_t c = 0; c < 2; c++) {
-            const uint64_t m = __ballot(cls == c);
-            if (cls == c) rank = (uint32_t)__popcll(m & below);
-            if (lane == 0) s_hist[wv][c] = (uint32_t)__popcll(m);
+        for (uint32_t g = 0; g < kPieceGroup; g++) {
+            const uint64_t p = gfirst + g * kSlotBlock + t;
+            cls[g] = p < n_pieces ? (code_line(pcs[p].code) ? 1u : 0u) : 2u;
+            rank[g] = 0u;
+#pragma unroll
+            for (uint32_t c = 0; c < 2; c++) {
+                const uint64_t m = __ballot(cls[g] == c);
+                if (cls[g] == c) rank[g] = (uint32_t)__popcll(m & below);
+                if (lane == 0) s_hist[g][wv][c] = (uint32_t)__popcll(m);
+            }
         }
-    };
-    auto load_piece = [&](uint32_t tl) {
-        const uint64_t p = (uint64_t)tl * kSlotBlock + t;
-        return (tl < n_tiles && p < n_pieces) ? pcs[p] : Slot{0u, kSlotTail};
-    };
-    Slot mine = load_piece(blockIdx.x);
-    uint32_t cls, rank;
-    classify(blockIdx.x, mine, cls, rank);
-    if (t == 0) s_n = 0u;
-    __syncthreads();
-    for (uint32_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-        const uint64_t first = (uint64_t)tile * kSlotBlock;
-        uint32_t pos = rank;
-        for (uint32_t c = 0; c < 2; c++)
-            for (uint32_t w = 0; w < kSlotBlock / 64; w++)
-                if (c < cls || (c == cls && w < wv)) pos += s_hist[w][c];
-        if (cls < 2u) {
-            s_order[pos] = t;
-            s_slot[pos] = mine;
-        }
-        uint32_t n_valid = 0;  // pieces of this tile (the rest of s_order is unused)
-        for (uint32_t w = 0; w < kSlotBlock / 64; w++) n_valid += s_hist[w][0] + s_hist[w][1];
         __syncthreads();
-        // phase 1: the piece's spiral, its sides and the first range of each
-        uint64_t j = 0;  // the piece's slot
-        Slot sl{0u, kSlotTail};
-        if (t < n_valid) {
-            sl = s_slot[t];
-            j = first + s_order[t] + sl.tag;
+        uint32_t n_curve = 0, n_valid = 0;
+        for (uint32_t g = 0; g < kPieceGroup; g++)
+            for (uint32_t w = 0; w < kSlotBlock / 64; w++) {
+                n_curve += s_hist[g][w][0];
+                n_valid += s_hist[g][w][0] + s_hist[g][w][1];
+            }
+#pragma unroll
+        for (uint32_t g = 0; g < kPieceGroup; g++) {
+            if (cls[g] < 2u) {
+                uint32_t pos = rank[g] + (cls[g] ? n_curve : 0u);
+                for (uint32_t g2 = 0; g2 < kPieceGroup; g2++)
+                    for (uint32_t w = 0; w < kSlotBlock / 64; w++)
+                        if (g2 < g || (g2 == g && w < wv)) pos += s_hist[g2][w][cls[g]];
+                s_order[pos] = g * kSlotBlock + t;
+            }
         }
-        const bool act = t < n_valid;
-        mine = load_piece(tile + gridDim.x);  // the next tile's, used at this tile's end
-        ItemSink<LaneAlloc, Stats> k;
-        k.units = ws.units;
-        k.es_tab = ws.es_tab;
-        k.al.next = ~0ull;
-        k.path = 0xffffffffu;
-        k.slot = (uint32_t)j;
-        k.n = 0;
-        if (Stats)
-            for (int q = 0; q < kStN; q++) k.st[q] = 0;
-        bool have = false;
-        ES es;
-        SideGeo g0, g1;
-        uint32_t qa = 0, qb = 0;
-        bool side1 = false;  // a stroke's second side (a fill has one)
-        if (act && sl.tag < sv.n_tags) {
-            k.path = path_of(sv, sl.tag);
-            TagInfo ti;
-            Seg sg;
-            fetch_tag(sv, sl.tag, ti, sg);
-            if (ti.kind == kTagSegment) {
-                have = true;
-                piece_es(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code), es);
-                side1 = !sg.fill;
-                g0 = side_geo(es, sg.w, 0);
-                g1 = side_geo(es, sg.w, 1);
-                g1.split = g1.split && side1;
-                s_first[0][t] = range_count<Newton>(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
-                if (side1) s_first[1][t] = range_count<Newton>(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
-                if (g0.split || g1.split) {
-                    s_own[t][0] = es.k0;
-                    s_own[t][1] = es.k1;
-                    s_own[t][2] = es.L;
-                    s_own[t][3] = sg.w;
-                    s_tc[t][0] = g0.tc;
-                    s_tc[t][1] = g1.tc;
+        __syncthreads();
+        for (uint32_t pass = 0; pass < kPieceGroup && pass * kSlotBlock < n_valid; pass++) {
+            const uint32_t qo = pass * kSlotBlock + t;  // this thread's position in the class order
+            // phase 1: the piece's spiral, its sides and the first range of each
+            const bool act = qo < n_valid;
+            uint64_t j = 0;  // the piece's slot
+            uint32_t kt = 0;  // its tile within the group
+            Slot sl{0u, kSlotTail};
+            if (act) {
+                const uint32_t o = s_order[qo];
+                kt = o / kSlotBlock;
+                sl = pcs[gfirst + o];
+                j = gfirst + o + sl.tag;
+            }
+            ItemSink<LaneAlloc, Stats> k;
+            k.units = ws.units;
+            k.es_tab = ws.es_tab;
+            k.al.next = ~0ull;
+            k.path = 0xffffffffu;
+            k.slot = (uint32_t)j;
+            k.n = 0;
+            if (Stats)
+                for (int q = 0; q < kStN; q++) k.st[q] = 0;
+            bool have = false;
+            ES es;
+            SideGeo g0, g1;
+            uint32_t qa = 0, qb = 0;
+            bool side1 = false;  // a stroke's second side (a fill has one)
+            if (act && sl.tag < sv.n_tags) {
+                k.path = path_of(sv, sl.tag);
+                TagInfo ti;
+                Seg sg;
+                fetch_tag(sv, sl.tag, ti, sg);
+                if (ti.kind == kTagSegment) {
+                    have = true;
+                    piece_es(k, cfg, sg, ti.line, code_t0u(sl.code), code_depth(sl.code), code_pivot(sl.code), es);
+                    side1 = !sg.fill;
+                    g0 = side_geo(es, sg.w, 0);
+                    g1 = side_geo(es, sg.w, 1);
+                    g1.split = g1.split && side1;
+                    s_first[0][t] = range_count<Newton>(cfg, es.k0, es.k1, es.L, g0.h, 0.0, g0.tc, g0.rev1);
+                    if (side1) s_first[1][t] = range_count<Newton>(cfg, es.k0, es.k1, es.L, g1.h, 0.0, g1.tc, g1.rev1);
+                    if (g0.split || g1.split) {
+                        s_own[t][0] = es.k0;
+                        s_own[t][1] = es.k1;
+                        s_own[t][2] = es.L;
+                        s_own[t][3] = sg.w;
+                        s_tc[t][0] = g0.tc;
+                        s_tc[t][1] = g1.tc;
+                    }
                 }
             }
-        }
-        // phase 2: the second ranges of the wave, packed onto its first lanes
-        // (wave-private LDS: no block barrier)
-        const bool sp0 = have && g0.split, sp1 = have && g1.split;
-        const uint64_t m0 = __ballot(sp0), m1 = __ballot(sp1);
-        const uint32_t n0 = (uint32_t)__popcll(m0), n_task = n0 + (uint32_t)__popcll(m1);
-        uint32_t* w_task = s_task + wv * 128u;
-        RangeRes* w_res = s_res + wv * 128u;
-        if (sp0) {
-            qa = (uint32_t)__popcll(m0 & below);
-            w_task[qa] = (t << 2) | (g0.rev2 ? 1u : 0u);
-        }
-        if (sp1) {
-            qb = n0 + (uint32_t)__popcll(m1 & below);
-            w_task[qb] = (t << 2) | 2u | (g1.rev2 ? 1u : 0u);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        for (uint32_t q = lane; q < n_task; q += 64u) {
-            const uint32_t task = w_task[q], own = task >> 2, side = (task >> 1) & 1u;
-            const double w = s_own[own][3];
-            w_res[q] = range_count<Newton>(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w,
-                                           s_tc[own][side], 1.0, (task & 1u) != 0u);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // phase 3: the items of each piece in canonical order, into units
-        // reserved for the whole wave at once
-        auto put_all = [&](auto& sink) {
-            range_put(sink, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
-            if (g0.split) range_put(sink, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, w_res[qa]);
-            if (side1) {
-                range_put(sink, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
-                if (g1.split)
-                    range_put(sink, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, w_res[qb]);
+            // phase 2: the second ranges of the wave, packed onto its first lanes
+            // (wave-private LDS: no block barrier)
+            const bool sp0 = have && g0.split, sp1 = have && g1.split;
+            const uint64_t m0 = __ballot(sp0), m1 = __ballot(sp1);
+            const uint32_t n0 = (uint32_t)__popcll(m0), n_task = n0 + (uint32_t)__popcll(m1);
+            uint32_t* w_task = s_task + wv * 128u;
+            RangeRes* w_res = s_res + wv * 128u;
+            if (sp0) {
+                qa = (uint32_t)__popcll(m0 & below);
+                w_task[qa] = (t << 2) | (g0.rev2 ? 1u : 0u);
             }
-        };
-        uint32_t need = 0;
-        if (have) {
-            ItemSink<CountAlloc, false> dry;
-            dry.units = ws.units;
-            dry.es_tab = ws.es_tab;
-            dry.al.n = 0;
-            dry.path = 0;
-            dry.slot = 0;
-            dry.n = 0;
-            put_all(dry);
-            need = dry.al.n;
-        }
-        uint32_t incl = need;
-#pragma unroll
-        for (uint32_t d = 1; d < 64; d *= 2) {
-            const uint32_t v = __shfl_up(incl, d);
-            if (lane >= d) incl += v;
-        }
-        const uint32_t wave_need = __shfl(incl, 63);
-        uint32_t wave_at = 0;
-        if (lane == 0 && wave_need) wave_at = atomicAdd(&s_n, wave_need);
-        wave_at = __shfl(wave_at, 0);
-        if (need) {
-            const uint32_t at = wave_at + incl - need;
-            const uint64_t region = (uint64_t)tile * ws.region_cap;
-            if (at + need <= ws.region_cap) {
-                k.al.next = region + at;
-            } else {
-                for (uint32_t u = at; u < ws.region_cap; u++) ws.units[region + u].w[0] = 0u;
-                const unsigned long long o = atomicAdd(&ws.ctl->ovf_n, (unsigned long long)need);
-                k.al.next = (o + need <= ws.ovf_cap) ? ws.ovf_base + o : ~0ull;
+            if (sp1) {
+                qb = n0 + (uint32_t)__popcll(m1 & below);
+                w_task[qb] = (t << 2) | 2u | (g1.rev2 ? 1u : 0u);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (uint32_t q = lane; q < n_task; q += 64u) {
+                const uint32_t task = w_task[q], own = task >> 2, side = (task >> 1) & 1u;
+                const double w = s_own[own][3];
+                w_res[q] = range_count<Newton>(cfg, s_own[own][0], s_own[own][1], s_own[own][2], side ? -w : w,
+                                               s_tc[own][side], 1.0, (task & 1u) != 0u);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // phase 3: the items of each piece in canonical order, into units
+            // reserved for the whole wave at once
+            auto put_all = [&](auto& sink) {
+                range_put(sink, cfg, es, g0.h, 0.0, g0.tc, g0.rev1, true, !g0.split, g0.P0, g0.Pc, s_first[0][t]);
+                if (g0.split) range_put(sink, cfg, es, g0.h, g0.tc, 1.0, g0.rev2, false, true, g0.Pc, g0.P1, w_res[qa]);
+                if (side1) {
+                    range_put(sink, cfg, es, g1.h, 0.0, g1.tc, g1.rev1, true, !g1.split, g1.P0, g1.Pc, s_first[1][t]);
+                    if (g1.split)
+                        range_put(sink, cfg, es, g1.h, g1.tc, 1.0, g1.rev2, false, true, g1.Pc, g1.P1, w_res[qb]);
+                }
+            };
+            uint32_t need = 0;
+            if (have) {
+                ItemSink<CountAlloc, false> dry;
+                dry.units = ws.units;
+                dry.es_tab = ws.es_tab;
+                dry.al.n = 0;
+                dry.path = 0;
+                dry.slot = 0;
+                dry.n = 0;
+                put_all(dry);
+                need = dry.al.n;
+            }
+            if (need) {
+                // one LDS atomic per lane on its tile's counter (lanes of a wave
+                // can belong to different tiles of the group)
+                const uint32_t at = atomicAdd(&s_n[kt], need);
+                const uint64_t region = ((uint64_t)grp * kPieceGroup + kt) * ws.region_cap;
+                if (at + need <= ws.region_cap) {
+                    k.al.next = region + at;
+                } else {
+                    for (uint32_t u = at; u < ws.region_cap; u++) ws.units[region + u].w[0] = 0u;
+                    const unsigned long long o = atomicAdd(&ws.ctl->ovf_n, (unsigned long long)need);
+                    k.al.next = (o + need <= ws.ovf_cap) ? ws.ovf_base + o : ~0ull;
+                }
+            }
+            if (have) put_all(k);
+            if (act) {
+                rc[j] = k.n;
+                if (Stats)
+                    for (int q = 0; q < kStN; q++) st[q] += k.st[q];
             }
         }
-        if (have) put_all(k);
-        if (act) {
-            rc[j] = k.n;
-            if (Stats)
-                for (int q = 0; q < kStN; q++) st[q] += k.st[q];
-        }
-        // s_hist is free again (read before the barrier above): rank the
-        // next tile's pieces; the barrier then also ends this tile's items
-        classify(tile + gridDim.x, mine, cls, rank);
         __syncthreads();
-        if (t == 0) {
-            // nobody allocates again before the next tile's first barrier
-            ws.tile_n[tile] = s_n;
-            atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n);
-            s_n = 0u;
+        if (t < kPieceGroup && grp * kPieceGroup + t < n_tiles) {
+            ws.tile_n[grp * kPieceGroup + t] = s_n[t];
+            atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n[t]);
         }
     }
     if (Stats) {
