@@ -531,7 +531,8 @@ struct CountAlloc {
         return ~0ull;
     }
 };
-constexpr uint32_t kPieceGroup = 4;  // piece tiles a piece-launch workgroup orders together
+constexpr uint32_t kPieceGroup = 4;     // piece tiles a piece-launch workgroup orders together
+constexpr uint32_t kSingleTiles = 1024;  // the last piece tiles, taken one per workgroup
 struct LaneAlloc {
     uint64_t next;  // next unit of the reservation, or ~0ull (dropped)
     __device__ uint64_t alloc(uint32_t nc) {
@@ -593,12 +594,17 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
     if (n_slots > slot_cap) return;  // reported by the finish kernel
     const uint64_t n_pieces = n_slots - sv.n_tags;
     const uint32_t n_tiles = piece_tile_count(n_pieces);
-    const uint32_t n_groups = (n_tiles + kPieceGroup - 1) / kPieceGroup;
+    // groups of kPieceGroup tiles, then the last kSingleTiles tiles one at a
+    // time, so that the launch's last round is short
+    const uint32_t n_multi = n_tiles > kSingleTiles ? (n_tiles - kSingleTiles) / kPieceGroup : 0u;
+    const uint32_t n_groups = n_multi + (n_tiles - n_multi * kPieceGroup);
     const uint32_t t = threadIdx.x, lane = t & 63u, wv = t >> 6;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint32_t st[kStN] = {0, 0, 0, 0, 0, 0};
     for (uint32_t grp = blockIdx.x; grp < n_groups; grp += gridDim.x) {
-        const uint64_t gfirst = (uint64_t)grp * kPieceGroup * kSlotBlock;
+        const uint32_t tile0 = grp < n_multi ? grp * kPieceGroup : n_multi * kPieceGroup + (grp - n_multi);
+        const uint32_t n_gt = grp < n_multi ? kPieceGroup : 1u;  // tiles of this group
+        const uint64_t gfirst = (uint64_t)tile0 * kSlotBlock;
         if (t < kPieceGroup) s_n[t] = 0u;
         // the group's work-class order (curve pieces, then line pieces): each
         // thread ranks its piece of every tile among its wave's pieces of that
@@ -607,7 +613,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
 #pragma unroll
         for (uint32_t g = 0; g < kPieceGroup; g++) {
             const uint64_t p = gfirst + g * kSlotBlock + t;
-            cls[g] = p < n_pieces ? (code_line(pcs[p].code) ? 1u : 0u) : 2u;
+            cls[g] = (g < n_gt && p < n_pieces) ? (code_line(pcs[p].code) ? 1u : 0u) : 2u;
             rank[g] = 0u;
 #pragma unroll
             for (uint32_t c = 0; c < 2; c++) {
@@ -739,7 +745,7 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
                 // one LDS atomic per lane on its tile's counter (lanes of a wave
                 // can belong to different tiles of the group)
                 const uint32_t at = atomicAdd(&s_n[kt], need);
-                const uint64_t region = ((uint64_t)grp * kPieceGroup + kt) * ws.region_cap;
+                const uint64_t region = ((uint64_t)tile0 + kt) * ws.region_cap;
                 if (at + need <= ws.region_cap) {
                     k.al.next = region + at;
                 } else {
@@ -756,8 +762,8 @@ __global__ __launch_bounds__(kSlotBlock, MinWaves) void slot_kernel(SceneView sv
             }
         }
         __syncthreads();
-        if (t < kPieceGroup && grp * kPieceGroup + t < n_tiles) {
-            ws.tile_n[grp * kPieceGroup + t] = s_n[t];
+        if (t < n_gt) {
+            ws.tile_n[tile0 + t] = s_n[t];
             atomicAdd(&ws.ctl->items_total, (unsigned long long)s_n[t]);
         }
     }
