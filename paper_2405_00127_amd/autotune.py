@@ -20,7 +20,7 @@ import threading
 from typing import Dict, Iterable, Optional, Tuple
 
 PIECE_WAVES = (1, 2, 3)
-BISECT_RANGE = (128, 256, 512, 1024)
+BISECT_RANGE = (128, 192, 256, 384, 512, 1024)
 BISECT_WAVES = (2, 3, 4)
 CHUNK_K = (4, 8, 16, 32, 64)
 KEYS = ("piece_waves", "chunk_k", "bisect_range", "bisect_waves")
