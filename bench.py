@@ -613,12 +613,16 @@ def served(args, ctx, B, S, torch, np):
 
 
 def kernel_source_hash() -> str:
-    """Hash of the HIP sources without comments and blank space: counter
-    readings are tied to the code they were taken on."""
+    """Hash of the HIP sources without comments and blank space, and of the
+    compiler flags they are built with: counter readings are tied to the
+    code they were taken on."""
     import hashlib
     import re
 
+    from paper_2405_00127_amd import build as PB
+
     h = hashlib.sha256()
+    h.update(" ".join(PB.FLAGS).encode() + b"\0")
     csrc = os.path.join(ROOT, "paper_2405_00127_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".h", ".cpp")):

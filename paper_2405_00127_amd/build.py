@@ -26,6 +26,10 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed-FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep constant materialisations where they are used: hoisted out of the
+    # kernels' loops, the FP64 polynomial coefficients of the math library
+    # held dozens of VGPRs for the whole loop and were spilled to scratch
+    "-mllvm", "-disable-machine-licm",
     "-Wno-unused-command-line-argument",
 ]
 
