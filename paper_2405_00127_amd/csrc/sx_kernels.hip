@@ -178,6 +178,7 @@ __device__ Pair look_back(TileStatus* st, uint32_t tile, uint32_t epoch, int lan
 constexpr int kScanBlock = 256;
 constexpr int kTagItems = 16;    // tags per thread of the tag-monoid scan
 constexpr int kCountItems = 32;  // counts per thread of the count scans
+constexpr int kRecCountItems = 64;  // counts per thread of the record-count scan (one round of tiles)
 
 __device__ __forceinline__ Pair tag_inc(uint32_t t) {
     uint64_t pts = (t & kTagCount) + ((t & kTagEnd) ? 1u : 0u);
@@ -323,12 +324,13 @@ __global__ __launch_bounds__(kScanBlock) void scan_tags_kernel(const uint8_t* __
 }
 
 // exclusive scan of u32 counts into u64 offsets; out[n] = total
+template <int Items>
 __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
                                               ScanCtl* ctl, TileStatus* st);
 __global__ __launch_bounds__(kScanBlock) void scan_counts_kernel(const uint32_t* __restrict__ in, uint32_t n,
                                                                  uint64_t* __restrict__ out, ScanCtl* ctl,
                                                                  TileStatus* st) {
-    scan_u32_body(in, n, out, ctl, st);
+    scan_u32_body<kCountItems>(in, n, out, ctl, st);
 }
 // the same with n read from device memory (clamped to the buffers' capacity);
 // the grid covers the capacity
@@ -338,14 +340,15 @@ __global__ __launch_bounds__(kScanBlock) void scan_counts_dev_kernel(const uint3
                                                                      TileStatus* st) {
     const uint64_t nd = *n_dev;
     if (nd == 0 && blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0;
-    scan_u32_body(in, nd < cap ? (uint32_t)nd : cap, out, ctl, st);
+    scan_u32_body<kRecCountItems>(in, nd < cap ? (uint32_t)nd : cap, out, ctl, st);
 }
+template <int Items>
 __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, uint32_t n, uint64_t* __restrict__ out,
                                               ScanCtl* ctl, TileStatus* st) {
     auto load = [&](uint64_t base, Pair* item) {
-        if (base + kCountItems <= n) {
+        if (base + Items <= n) {
 #pragma unroll
-            for (int j = 0; j < kCountItems; j += 4) {
+            for (int j = 0; j < Items; j += 4) {
                 uint4 v = *reinterpret_cast<const uint4*>(in + base + j);
                 item[j] = Pair{v.x, 0};
                 item[j + 1] = Pair{v.y, 0};
@@ -354,18 +357,18 @@ __device__ __forceinline__ void scan_u32_body(const uint32_t* __restrict__ in, u
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < kCountItems; j++) item[j] = Pair{(base + j < n) ? (uint64_t)in[base + j] : 0ull, 0};
+            for (int j = 0; j < Items; j++) item[j] = Pair{(base + j < n) ? (uint64_t)in[base + j] : 0ull, 0};
         }
     };
     auto store = [&](uint64_t base, const Pair* incl, Pair pre) {
 #pragma unroll
-        for (int j = 0; j < kCountItems; j++) {
+        for (int j = 0; j < Items; j++) {
             const uint64_t ex = pre.a + (j > 0 ? incl[j - 1].a : 0ull);
             if (base + j < n) out[base + j] = ex;
             if (base + j == (uint64_t)n - 1u) out[n] = pre.a + incl[j].a;
         }
     };
-    scan_tile<kCountItems>(load, store, n, ctl, st);
+    scan_tile<Items>(load, store, n, ctl, st);
 }
 
 // --------------------------------------------------------- bisection
@@ -1063,8 +1066,8 @@ __global__ void scene_offsets_kernel(const uint64_t* __restrict__ base, const ui
 
 // ------------------------------------------------------------- launches
 int scan_tiles(uint32_t n) { return (int)((n + kScanBlock * kTagItems - 1) / (kScanBlock * kTagItems)); }
-static int count_scan_tiles(uint32_t n) {
-    return (int)((n + kScanBlock * kCountItems - 1) / (kScanBlock * kCountItems));
+static int count_scan_tiles(uint32_t n, int items = kCountItems) {
+    return (int)((n + (uint32_t)(kScanBlock * items) - 1) / (uint32_t)(kScanBlock * items));
 }
 
 uint32_t piece_tiles(uint32_t n, uint32_t tile) { return (n + tile - 1) / tile; }
@@ -1091,8 +1094,8 @@ hipError_t launch_zero_u64(uint64_t* out, hipStream_t s) {
 }
 hipError_t launch_scan_counts_dev(const uint32_t* in, const uint64_t* n_dev, uint32_t cap, uint64_t* out, void* ctl,
                                   void* st, hipStream_t s) {
-    scan_counts_dev_kernel<<<count_scan_tiles(cap > 0 ? cap : 1), kScanBlock, 0, s>>>(in, n_dev, cap, out, (ScanCtl*)ctl,
-                                                                              (TileStatus*)st);
+    const int g = count_scan_tiles(cap > 0 ? cap : 1, kRecCountItems);
+    scan_counts_dev_kernel<<<g, kScanBlock, 0, s>>>(in, n_dev, cap, out, (ScanCtl*)ctl, (TileStatus*)st);
     return hipGetLastError();
 }
 
